@@ -1,0 +1,81 @@
+"""Dense-block assembly of the Jacobian J = S + sum_blocks u v^T.
+
+Section 4 ("Overall Structure"): every non-zero m x m block of J is an
+r1-sparse matrix, the sum of a sparse block and rank-one updates (the
+definition of r1-sparsity in section 4.1).  Here each existing block (c, d)
+carries exactly one pair:
+
+    D_{c,d} = S_{c,d} + u_{c,d} v_{c,d}^T.
+
+S_{c,C} (the diagonal block) has a full diagonal, a tridiagonal band coupling
+neighbouring levels k, k+1 (k < L) and a dense 3 x 3 corner for the flow
+unknowns L, L+1, L+2.  S_{c,d} for d != C is diagonal.
+
+The result is stored in the paper's BSR format (section 5.1): block_indptr,
+block_indices (ascending block columns within a block row) and a 3-D data
+array [n_blocks][m][m].
+"""
+import numpy as np
+
+from . import mesh
+
+FLOW_PAIRS = ((0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1))
+
+
+def diagonal_sparse_block(p, c: int, L: int) -> np.ndarray:
+    """S_{c,C} as a dense m x m array (sparse pattern, zeros elsewhere)."""
+    m = L + 3
+    A = np.zeros((m, m))
+    A[np.arange(m), np.arange(m)] = p["s_diag"][c]
+    for k in range(L - 1):
+        A[k + 1, k] = p["s_sub"][c, k]
+        A[k, k + 1] = p["s_sup"][c, k]
+    for t, (i, j) in enumerate(FLOW_PAIRS):
+        A[L + i, L + j] = p["s_flow"][c, t]
+    return A
+
+
+def sparse_block(p, c: int, d: int, L: int) -> np.ndarray:
+    """S_{c,d} as a dense m x m array."""
+    if d == mesh.C:
+        return diagonal_sparse_block(p, c, L)
+    return np.diag(p["s_nbr"][c, mesh.NBR_SLOT[d]])
+
+
+def dense_block(p, c: int, d: int, L: int) -> np.ndarray:
+    """D_{c,d} = S_{c,d} + u_{c,d} v_{c,d}^T."""
+    return sparse_block(p, c, d, L) + np.outer(p["u"][c, d], p["v"][c, d])
+
+
+def assemble_bsr(p, nx: int, ny: int, L: int, cells=None):
+    """Assemble the block rows of `cells` (default: all) in BSR format.
+
+    Returns (block_indptr, block_indices, data, rows): `rows` are the block-row
+    cell numbers in order, block_indptr indexes into block_indices/data
+    relative to that list of rows.
+    """
+    if cells is None:
+        cells = range(nx * ny)
+    cells = list(cells)
+    indptr = [0]
+    indices = []
+    blocks = []
+    for c in cells:
+        for d in (mesh.S, mesh.W, mesh.C, mesh.E, mesh.N):
+            nb = mesh.neighbour(nx, ny, c, d)
+            if nb < 0:
+                continue
+            indices.append(nb)
+            blocks.append(dense_block(p, c, d, L))
+        indptr.append(len(indices))
+    m = L + 3
+    data = np.array(blocks).reshape(len(blocks), m, m)
+    return (np.array(indptr, dtype=np.int64), np.array(indices, dtype=np.int64),
+            data, np.array(cells, dtype=np.int64))
+
+
+def diagonal_blocks(p, nx: int, ny: int, L: int, cells=None) -> np.ndarray:
+    """[len(cells)][m][m] diagonal blocks D_{c,C} (the block-Jacobi blocks)."""
+    if cells is None:
+        cells = range(nx * ny)
+    return np.array([dense_block(p, c, mesh.C, L) for c in cells])

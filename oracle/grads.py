@@ -1,0 +1,54 @@
+"""Gradients of the linear loss  Loss = sum_r w_r . x_r  with  J x_r = b_r.
+
+Reverse-mode differentiation of a linear solve: with lambda_r = J^{-T} w_r,
+dLoss/db_r = lambda_r and dLoss/dJ = -sum_r lambda_r x_r^T.  Restricting the
+matrix cotangent to one dense block gives G_{c,d} = -sum_r lambda_r[c] x_r[nb]^T
+(nb = the block's column cell); the chain rule through
+D_{c,d} = S_{c,d} + u_{c,d} v_{c,d}^T then gives
+
+    dS_{c,d}  = G_{c,d} at the stored pattern positions of S_{c,d}
+    du_{c,d}  = G_{c,d} v_{c,d}
+    dv_{c,d}  = G_{c,d}^T u_{c,d}
+
+This works through the dense blocks (section 3's standard representation),
+independent of any rank-one shortcut.
+"""
+import numpy as np
+
+from . import assemble, mesh
+
+
+def structured_grads(p, nx, ny, L, lam, x):
+    """Gradients w.r.t. every stored structured array, summed over the batch.
+
+    lam, x: [nrhs][N][m].  Returns a dict with the keys of the input arrays.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    if lam.ndim == 2:
+        lam, x = lam[None], x[None]
+    N, m = nx * ny, L + 3
+    g = {k: np.zeros_like(p[k]) for k in ("s_diag", "s_sub", "s_sup", "s_flow",
+                                          "s_nbr", "u", "v")}
+    for c in range(N):
+        for d in (mesh.S, mesh.W, mesh.C, mesh.E, mesh.N):
+            nb = mesh.neighbour(nx, ny, c, d)
+            if nb < 0:
+                continue
+            G = -np.einsum("ri,rj->ij", lam[:, c, :], x[:, nb, :])
+            g["u"][c, d] = G @ p["v"][c, d]
+            g["v"][c, d] = G.T @ p["u"][c, d]
+            if d == mesh.C:
+                g["s_diag"][c] = np.diag(G)
+                for k in range(L - 1):
+                    g["s_sub"][c, k] = G[k + 1, k]
+                    g["s_sup"][c, k] = G[k, k + 1]
+                for t, (i, j) in enumerate(assemble.FLOW_PAIRS):
+                    g["s_flow"][c, t] = G[L + i, L + j]
+            else:
+                g["s_nbr"][c, mesh.NBR_SLOT[d]] = np.diag(G)
+    return g
+
+
+def loss(x, w):
+    return float(np.sum(np.asarray(w) * np.asarray(x)))

@@ -1,0 +1,46 @@
+"""Structured-mesh adjacency for the first-order finite-volume stencil.
+
+Section 3 ("Jacobian Complexity"): the block row of element kappa holds the
+diagonal block plus one block per interior edge of kappa.  On a structured
+nx x ny quadrilateral mesh without periodicity an element has up to four
+interior edges (section 4, "Overall Structure").
+
+Cell numbering: c = iy*nx + ix.  Direction numbering: 0 = S (iy-1),
+1 = W (ix-1), 2 = C (the cell itself), 3 = E (ix+1), 4 = N (iy+1); for a given
+cell these are in ascending order of the neighbour's cell number.
+"""
+import numpy as np
+
+S, W, C, E, N = 0, 1, 2, 3, 4
+# slot of each off-diagonal direction in the [N][4][m] neighbour-diagonal array
+NBR_SLOT = {S: 0, W: 1, E: 2, N: 3}
+
+
+def neighbour(nx: int, ny: int, c: int, d: int) -> int:
+    """Cell number of the neighbour of c in direction d, or -1 if none."""
+    iy, ix = divmod(c, nx)
+    if d == S:
+        return c - nx if iy > 0 else -1
+    if d == W:
+        return c - 1 if ix > 0 else -1
+    if d == C:
+        return c
+    if d == E:
+        return c + 1 if ix < nx - 1 else -1
+    if d == N:
+        return c + nx if iy < ny - 1 else -1
+    raise ValueError(d)
+
+
+def neighbour_table(nx: int, ny: int) -> np.ndarray:
+    """[N][5] int array of neighbour cell numbers (-1 where no block)."""
+    tab = np.full((nx * ny, 5), -1, dtype=np.int64)
+    for c in range(nx * ny):
+        for d in range(5):
+            tab[c, d] = neighbour(nx, ny, c, d)
+    return tab
+
+
+def opposite(d: int) -> int:
+    """The direction pointing back: the neighbour's block towards c."""
+    return {S: N, W: E, C: C, E: W, N: S}[d]

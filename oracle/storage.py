@@ -1,0 +1,34 @@
+"""Stored-value counts of the two Jacobian representations.
+
+Standard (BSR) representation, section 3: N_A = sum over elements of
+m^2 (N_{kappa,e} + 1), where N_{kappa,e} is the element's number of interior
+edges.  On a non-periodic nx x ny mesh the number of stored blocks is
+B = 5N - 2nx - 2ny, so N_A = B m^2.
+
+Block r1-sparse representation, sections 4-5: the fully sparse part stores,
+per cell, the diagonal block pattern (m diagonal entries, 2(L-1) level-band
+entries and 6 flow-corner entries: 3m - 2 in total since L = m - 3) and one
+diagonal of m entries for each of the B - N neighbour blocks; the rank-one
+part stores 2m values (u and v) per block and per pair.
+"""
+
+
+def n_blocks(nx: int, ny: int) -> int:
+    """Count the stored blocks by walking the mesh (diagonal + interior edges)."""
+    B = 0
+    for iy in range(ny):
+        for ix in range(nx):
+            B += 1 + (iy > 0) + (ix > 0) + (ix < nx - 1) + (iy < ny - 1)
+    return B
+
+
+def bsr_values(nx: int, ny: int, m: int) -> int:
+    return n_blocks(nx, ny) * m * m
+
+
+def structured_values(nx: int, ny: int, m: int, pairs_per_block: int = 1) -> int:
+    N = nx * ny
+    B = n_blocks(nx, ny)
+    L = m - 3
+    diag_block = m + 2 * (L - 1) + 6
+    return N * diag_block + (B - N) * m + B * pairs_per_block * 2 * m

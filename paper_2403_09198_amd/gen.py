@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs for the r1-sparse block Jacobian.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic (no matvec, no factorisation, no solve).  Both the HIP
+library and the CPU oracle consume exactly the arrays produced here.
+
+Problem family (the first-order finite-volume Jacobian of section 3 with the
+block structure of section 4, "Overall Structure"): a structured nx x ny mesh,
+5-point block stencil, block size m = L + 3 (L level densities, two momenta,
+energy).  Every existing block (c, d) is  S_{c,d} + u_{c,d} v_{c,d}^T  with one
+rank-one pair (the block-wise rank-one representation of section 4).
+
+Array layout (all float64, C-contiguous; N = nx*ny, cell c = iy*nx + ix):
+
+  s_diag [N][m]      diagonal of S_cc
+  s_sub  [N][L-1]    S_cc[k+1][k], level band (k = 0..L-2)
+  s_sup  [N][L-1]    S_cc[k][k+1], level band
+  s_flow [N][6]      flow-corner off-diagonals (rows/cols L..L+2) in the order
+                     (0,1) (0,2) (1,0) (1,2) (2,0) (2,1)
+  s_nbr  [N][4][m]   diagonals of the neighbour blocks S_{c,d}, d in S,W,E,N
+  u, v   [N][5][m]   rank-one pairs, d in S,W,C,E,N
+
+Directions: 0 = S (iy-1), 1 = W (ix-1), 2 = C, 3 = E (ix+1), 4 = N (iy+1).
+The mesh is not periodic: a boundary cell simply has no block towards the
+missing neighbour, and the slots for such blocks are zero.
+
+Value distributions (one fixed draw order from numpy's PCG64):
+  s_diag = inv_dt + 10*|N(0,1)|, s_sub, s_sup, s_flow ~ N(0,1),
+  s_nbr ~ U(-1,0), u, v ~ N(0, 0.1^2).  Right-hand sides from seed+1, loss
+  weights from seed+2, both N(0,1).  inv_dt = 20 makes S strictly row
+  diagonally dominant with overwhelming probability; inv_dt = 1 is a stress
+  case that forces GMRES restarts.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict
+
+import numpy as np
+
+DIR_S, DIR_W, DIR_C, DIR_E, DIR_N = 0, 1, 2, 3, 4
+# s_nbr slot j holds direction NBR_DIRS[j]
+NBR_DIRS = (DIR_S, DIR_W, DIR_E, DIR_N)
+
+FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
+
+
+@dataclass(frozen=True)
+class Workload:
+    """A named problem size: mesh, levels, and solver settings."""
+    name: str
+    nx: int
+    ny: int
+    L: int
+    restart: int = 50
+    rtol: float = 1e-10
+    nrhs: int = 1
+    inv_dt: float = 20.0
+    seed: int = 0
+
+    @property
+    def m(self) -> int:
+        return self.L + 3
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny
+
+
+# The five workloads of the benchmark plan: the small CPU-checkable case, the
+# 256x128 L=61 single-GPU case, the 512x256 level sweep, the mixed-precision
+# case and the batched adjoint case.
+WORKLOADS: Dict[str, Workload] = {
+    "small_16x16_L8": Workload("small_16x16_L8", 16, 16, 8, restart=30),
+    "mesh256x128_L61": Workload("mesh256x128_L61", 256, 128, 61, restart=50),
+    "mesh512x256_L32": Workload("mesh512x256_L32", 512, 256, 32),
+    "mesh512x256_L61": Workload("mesh512x256_L61", 512, 256, 61),
+    "mesh512x256_L120": Workload("mesh512x256_L120", 512, 256, 120),
+    "mesh512x256_L200": Workload("mesh512x256_L200", 512, 256, 200),
+    "adjoint256x128_L61_b8": Workload("adjoint256x128_L61_b8", 256, 128, 61,
+                                      nrhs=8),
+}
+
+
+def block_exists(nx: int, ny: int) -> np.ndarray:
+    """[N][5] bool: does cell c have a block in direction d (non-periodic)."""
+    iy, ix = np.divmod(np.arange(nx * ny), nx)
+    ex = np.ones((nx * ny, 5), dtype=bool)
+    ex[:, DIR_S] = iy > 0
+    ex[:, DIR_W] = ix > 0
+    ex[:, DIR_E] = ix < nx - 1
+    ex[:, DIR_N] = iy < ny - 1
+    return ex
+
+
+def make_problem(nx: int, ny: int, L: int, seed: int = 0,
+                 inv_dt: float = 20.0) -> Dict[str, np.ndarray]:
+    """Draw the structured values of one Jacobian (float64 arrays)."""
+    if nx < 1 or ny < 1 or L < 1:
+        raise ValueError("nx, ny, L must be >= 1")
+    N, m = nx * ny, L + 3
+    rng = np.random.default_rng(seed)
+    p = {}
+    p["s_diag"] = inv_dt + 10.0 * np.abs(rng.standard_normal((N, m)))
+    p["s_sub"] = rng.standard_normal((N, L - 1))
+    p["s_sup"] = rng.standard_normal((N, L - 1))
+    p["s_flow"] = rng.standard_normal((N, 6))
+    p["s_nbr"] = rng.uniform(-1.0, 0.0, size=(N, 4, m))
+    p["u"] = 0.1 * rng.standard_normal((N, 5, m))
+    p["v"] = 0.1 * rng.standard_normal((N, 5, m))
+    ex = block_exists(nx, ny)
+    for j, d in enumerate(NBR_DIRS):
+        p["s_nbr"][~ex[:, d], j, :] = 0.0
+    p["u"][~ex] = 0.0
+    p["v"][~ex] = 0.0
+    for k in FIELDS:
+        p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
+    return p
+
+
+def make_rhs(nx: int, ny: int, L: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
+    """Right-hand sides b ~ N(0,1), shape [nrhs][N][m], from seed+1."""
+    rng = np.random.default_rng(seed + 1)
+    return rng.standard_normal((nrhs, nx * ny, L + 3))
+
+
+def make_loss_weights(nx: int, ny: int, L: int, nrhs: int = 1,
+                      seed: int = 0) -> np.ndarray:
+    """Loss weights w ~ N(0,1), shape [nrhs][N][m], from seed+2."""
+    rng = np.random.default_rng(seed + 2)
+    return rng.standard_normal((nrhs, nx * ny, L + 3))
+
+
+def make_vector(nx: int, ny: int, L: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
+    """A generic N(0,1) test vector [nrhs][N][m] from its own stream."""
+    rng = np.random.default_rng(1_000_003 + seed)
+    return rng.standard_normal((nrhs, nx * ny, L + 3))
+
+
+def workload_problem(w: Workload) -> Dict[str, np.ndarray]:
+    return make_problem(w.nx, w.ny, w.L, seed=w.seed, inv_dt=w.inv_dt)
