@@ -1,0 +1,250 @@
+/*
+ * r1s -- block r1-sparse Jacobians on MI355X (gfx950).
+ *
+ * C ABI of libr1s.so.  The Jacobian of a first-order finite-volume
+ * discretisation on a structured nx x ny mesh (5-point block stencil, blocks
+ * of size m = L + 3: L level densities, two momenta, energy) is held as a
+ * fully sparse matrix S plus one rank-one pair per block, the "block
+ * r1-sparse" representation of section 4 (Overall Structure) and section 5.1
+ * (BR1-BSR format):
+ *
+ *     J = S + sum over blocks (c, d) of  u_{c,d} v_{c,d}^T .
+ *
+ * The library multiplies by J and J^T (section 5.2), applies the block-Jacobi
+ * preconditioner through the Sherman-Morrison-Woodbury identity (section 6,
+ * eq. SMW, with the sign of the correction term corrected to minus), and
+ * solves J x = b by restarted right-preconditioned GMRES (section 6, eq.
+ * right_precond_system).  A dense-block BSR representation of the same J
+ * (section 3, Jacobian Complexity; section 5.1, BSR format) with dense-LU
+ * block-Jacobi is provided as the baseline.
+ *
+ * Conventions
+ * -----------
+ * - Every call returns an int status (R1S_OK = 0, negative on error) and
+ *   never throws.  r1s_last_error() returns a thread-local message for the
+ *   last failing call on the calling thread.
+ * - Arguments are validated on the host before any device work is issued; a
+ *   call that fails validation has no side effect.
+ * - All device memory is owned by the caller.  *_size calls report how many
+ *   bytes a buffer must have; the caller passes a device buffer of at least
+ *   that size (256-byte aligned) to the matching *_init / *_setup call and
+ *   keeps it alive while the handle is in use.  Handles are small host
+ *   objects created by *_init / *_setup and released by *_destroy; they do
+ *   not own the device buffer.  The library never keeps a pointer to a
+ *   user input buffer after the call that received it returns.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Matvec, apply and
+ *   grad calls are asynchronous on that stream.  *_init, *_setup and
+ *   r1s_gmres synchronise the stream before returning.
+ * - Handles are not thread-safe; calls that use one handle must be ordered.
+ * - Vectors are float64, C-contiguous, shape [nrhs][N][m] (N = nx*ny cells,
+ *   cell c = iy*nx + ix, unknown g = c*m + k), device pointers, 8-byte
+ *   aligned.  Input and output vectors must not overlap.
+ *
+ * Structured input layout (device pointers, float64, C-contiguous)
+ * ----------------------------------------------------------------
+ *   s_diag [N][m]     diagonal of S_{c,C}
+ *   s_sub  [N][L-1]   S_{c,C}[k+1][k], the level band below the diagonal
+ *   s_sup  [N][L-1]   S_{c,C}[k][k+1], the level band above the diagonal
+ *   s_flow [N][6]     flow-corner off-diagonals of S_{c,C} (rows/columns
+ *                     L..L+2) in the order (0,1) (0,2) (1,0) (1,2) (2,0) (2,1)
+ *   s_nbr  [N][4][m]  diagonals of the neighbour blocks S_{c,d}, d = S,W,E,N
+ *   u, v   [N][5][m]  rank-one pair of block (c, d), d = S,W,C,E,N
+ * Directions: S = (ix, iy-1), W = (ix-1, iy), C = the cell, E = (ix+1, iy),
+ * N = (ix, iy+1).  The mesh is not periodic: slots of blocks that do not
+ * exist must hold finite values and are treated as zero.  s_sub / s_sup may
+ * be NULL when L = 1.
+ */
+#ifndef R1S_H
+#define R1S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status --- */
+#define R1S_OK 0
+#define R1S_ERR_ARG (-1)         /* invalid argument (dims, pointer, size)  */
+#define R1S_ERR_ALLOC (-2)       /* host allocation failed                   */
+#define R1S_ERR_HIP (-3)         /* a HIP runtime call failed                */
+#define R1S_ERR_SINGULAR (-4)    /* zero pivot or singular SMW capacitance   */
+#define R1S_ERR_NOCONV (-5)      /* GMRES did not reach the tolerance        */
+#define R1S_ERR_NONFINITE (-6)   /* NaN or Inf met in a residual             */
+#define R1S_ERR_UNSUPPORTED (-7) /* valid but unsupported (e.g. m > 256)     */
+
+/* ------------------------------------------------------------- flags --- */
+#define R1S_F64 0 /* precision argument: float64 values, float64 arithmetic */
+#define R1S_F32 1 /* float32 values and accumulation, float64 vectors       */
+
+#define R1S_KEEP_F32 1   /* also keep float32 copies (mixed precision)      */
+#define R1S_WITH_TRANS 2 /* preconditioner: also set up the transposed apply */
+
+#define R1S_MAX_M 256 /* largest supported block size m = L + 3 */
+
+typedef struct r1s_mat_s* r1s_mat;   /* structured r1-sparse Jacobian      */
+typedef struct r1s_prec_s* r1s_prec; /* block-Jacobi preconditioner        */
+typedef struct r1s_bsr_s* r1s_bsr;   /* dense-block BSR copy of a Jacobian */
+
+typedef struct {
+  const double* s_diag;
+  const double* s_sub;
+  const double* s_sup;
+  const double* s_flow;
+  const double* s_nbr;
+  const double* u;
+  const double* v;
+} r1s_inputs;
+
+/* Gradient outputs, same shapes as r1s_inputs (device pointers, written). */
+typedef struct {
+  double* s_diag;
+  double* s_sub;
+  double* s_sup;
+  double* s_flow;
+  double* s_nbr;
+  double* u;
+  double* v;
+} r1s_grads;
+
+typedef struct {
+  int64_t n_cells, n_blocks, m;
+  int64_t structured_values;  /* algorithmic stored values of S + u/v      */
+  int64_t structured_padded;  /* values actually held (64-byte row padding) */
+  int64_t bsr_values;         /* B * m^2 of the dense-block representation */
+  int64_t index_bytes;        /* explicit index data: 0 (mesh-implicit)    */
+  int64_t matvec_bytes;       /* algorithmic HBM bytes of one F64 matvec   */
+  int64_t smw_apply_bytes;    /* algorithmic HBM bytes of one F64 apply    */
+} r1s_storage;
+
+/* GMRES operator / mode selectors. */
+#define R1S_OP_STRUCTURED 0
+#define R1S_OP_BSR 1
+#define R1S_MODE_F64 0      /* float64 operator and preconditioner          */
+#define R1S_MODE_MIXED_IR 1 /* float32 inner GMRES operator + preconditioner,
+                               float64 Arnoldi, residual and refinement     */
+
+typedef struct {
+  int restart;      /* Krylov space size per cycle (k of GMRES(k)), >= 1   */
+  int max_cycles;   /* restart cycles per (inner) solve                     */
+  double rtol;      /* stop when |b - J x|_2 <= rtol |b|_2 (per right-hand side) */
+  int trans;        /* 1: solve J^T x = b (needs R1S_WITH_TRANS)            */
+  int x0_given;     /* 1: x holds the initial guess; 0: start from zero     */
+  int op;           /* R1S_OP_STRUCTURED or R1S_OP_BSR                      */
+  int mode;         /* R1S_MODE_F64 or R1S_MODE_MIXED_IR                    */
+  double inner_rtol;/* mixed mode: relative tolerance of each inner solve   */
+  int max_outer;    /* mixed mode: iterative-refinement steps               */
+} r1s_gmres_opts;
+
+typedef struct {
+  int iters;            /* Arnoldi steps (summed over inner solves)         */
+  int cycles;           /* restart cycles                                   */
+  int outer;            /* refinement steps (mixed mode)                    */
+  int converged;        /* 1 if |b - J x| <= rtol |b|                       */
+  double rel_residual;  /* true float64 relative residual at exit           */
+} r1s_gmres_stats;
+
+/* ---------------------------------------------------------------- API --- */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* r1s_last_error(void);
+
+/* Device bytes of the packed matrix for an nx x ny mesh with L levels.
+ * flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG for
+ * nx, ny, L < 1 or a NULL `bytes`; R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M. */
+int r1s_mat_size(int nx, int ny, int L, int flags, size_t* bytes);
+
+/* Pack the structured arrays (see the layout above) into `mem` and create a
+ * handle.  Section 5.1: the index structure is fixed by the mesh adjacency
+ * and the block size by m; here it is implicit in (nx, ny, L).
+ * Errors: R1S_ERR_ARG (dims, NULL or misaligned pointer, mem_bytes too
+ * small), R1S_ERR_HIP. */
+int r1s_mat_init(int nx, int ny, int L, int flags, const r1s_inputs* in,
+                 void* mem, size_t mem_bytes, void* stream, r1s_mat* out);
+
+/* New values, same structure (the next Newton iterate).  Preconditioners
+ * and BSR copies made from A must be set up again. */
+int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream);
+
+int r1s_mat_destroy(r1s_mat A);
+
+/* Stored-value counts of the structured and dense-block representations
+ * (section 3, Jacobian Complexity: N_A = sum m^2 (N_e + 1)). */
+int r1s_mat_storage(r1s_mat A, r1s_storage* out);
+
+/* y = J x (trans = 0) or y = J^T x (trans = 1) for nrhs vectors, section 5.2:
+ * the sparse part plus, for every block, u times the coefficient v . x_col.
+ * precision R1S_F32 needs R1S_KEEP_F32.  Asynchronous. */
+int r1s_matvec(r1s_mat A, int precision, int trans, int nrhs, const double* x,
+               double* y, void* stream);
+
+/* r = b - J x in float64 (the residual of the refinement loop). */
+int r1s_residual(r1s_mat A, int nrhs, const double* b, const double* x,
+                 double* r, void* stream);
+
+/* Device bytes for the SMW block-Jacobi factors of A (flags: R1S_KEEP_F32,
+ * R1S_WITH_TRANS). */
+int r1s_prec_size(r1s_mat A, int flags, size_t* bytes);
+
+/* Section 6: block-Jacobi with D_c = A0_c + u_cC v_cC^T.  Factors the sparse
+ * diagonal block A0_c (tridiagonal level band by LU without pivoting, 3 x 3
+ * flow corner by its inverse), solves A0_c w_c = u_cC (SMW-1) and forms the
+ * capacitance C_c = 1 + v_cC . w_c (SMW-2).  Synchronises; returns
+ * R1S_ERR_SINGULAR naming the first cell with a zero pivot or
+ * |C_c| <= 1e-12 (1 + |v_cC| |w_c|). */
+int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
+                   void* stream, r1s_prec* out);
+
+/* z = M r (trans = 0) or M^T r: per cell x0 = A0^{-1} r_c, then
+ * z_c = x0 - w_c (v_cC . x0) / C_c (section 6, SMW steps, sign corrected).
+ * Also applies a BSR dense-LU preconditioner (r1s_bsr_prec_setup; trans = 0,
+ * precision R1S_F64 only).  Asynchronous. */
+int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs,
+                   const double* r, double* z, void* stream);
+
+int r1s_prec_destroy(r1s_prec M);
+
+/* Dense-block BSR copy of A: every existing block D = S_{c,d} + u v^T stored
+ * as a dense m x m block (section 5.1, BSR format; column-major inside a
+ * block), plus block_indptr / block_indices (int32). */
+int r1s_bsr_size(r1s_mat A, size_t* bytes);
+int r1s_bsr_init(r1s_mat A, void* mem, size_t mem_bytes, void* stream,
+                 r1s_bsr* out);
+/* y = J x through the dense blocks.  Asynchronous. */
+int r1s_bsr_matvec(r1s_bsr B, int nrhs, const double* x, double* y,
+                   void* stream);
+/* Classical block-Jacobi (section 6): LU with partial pivoting of every
+ * diagonal dense block.  Synchronises; R1S_ERR_SINGULAR on a zero pivot. */
+int r1s_bsr_prec_size(r1s_bsr B, size_t* bytes);
+int r1s_bsr_prec_setup(r1s_bsr B, void* mem, size_t mem_bytes, void* stream,
+                       r1s_prec* out);
+int r1s_bsr_destroy(r1s_bsr B);
+
+/* Workspace bytes for r1s_gmres with these options and nrhs. */
+int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
+                        size_t* bytes);
+
+/* Restarted right-preconditioned GMRES (section 6): solves (J M) y = b and
+ * returns x = M y, for nrhs independent right-hand sides advanced together.
+ * Classical Gram-Schmidt with one reorthogonalisation, float64.  Mixed mode
+ * wraps float32-operator inner solves in float64 iterative refinement.
+ * `B` is used when opts->op == R1S_OP_BSR (may be NULL otherwise).
+ * On R1S_ERR_NOCONV, x holds the last iterate and stats are filled (one
+ * r1s_gmres_stats per right-hand side, stats may be NULL). Synchronises. */
+int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
+              int nrhs, const double* b, double* x, void* work,
+              size_t work_bytes, r1s_gmres_stats* stats, void* stream);
+
+/* Gradients of Loss with  J x_r = b_r  given lambda_r = J^{-T} dLoss/dx_r:
+ * dLoss/dS = -sum_r lambda_r x_r^T on the stored pattern,
+ * dLoss/du_{c,d} = -sum_r lambda_r[c] (v_{c,d} . x_r[nb]),
+ * dLoss/dv_{c,d} = -sum_r x_r[nb] (u_{c,d} . lambda_r[c]); zero in the slots
+ * of blocks that do not exist.  Asynchronous. */
+int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
+             const r1s_grads* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* R1S_H */

@@ -41,6 +41,11 @@ def neighbour_table(nx: int, ny: int) -> np.ndarray:
     return tab
 
 
+def neighbour_table_row(nx: int, ny: int, c: int):
+    """Neighbours of c in the order S, W, C, E, N (-1 where none)."""
+    return [neighbour(nx, ny, c, d) for d in range(5)]
+
+
 def opposite(d: int) -> int:
     """The direction pointing back: the neighbour's block towards c."""
     return {S: N, W: E, C: C, E: W, N: S}[d]

@@ -9,7 +9,7 @@ Vectors have shape [nrhs][N][m] (or [N][m] for a single right-hand side).
 """
 import numpy as np
 
-from . import assemble
+from . import assemble, mesh
 
 
 def _as3(x):
@@ -65,6 +65,25 @@ def matvec_T(p, nx, ny, L, x, chunk=4096):
             for b in range(indptr[r], indptr[r + 1]):
                 y[:, indices[b], :] += x3[:, c, :] @ data[b]
     return y if np.ndim(x) == 3 else y[0]
+
+
+def matvec_T_rows(p, nx, ny, L, x, cells):
+    """(J^T x) restricted to the block rows `cells`: [nrhs][len(cells)][m].
+
+    Block column j of J holds the blocks (c, d) whose column cell is j, i.e.
+    the diagonal block of j and one block of each neighbour of j; row j of
+    J^T is the sum of their transposes applied to x_c.
+    """
+    x3 = _as3(x)
+    out = np.zeros((x3.shape[0], len(cells), L + 3))
+    for t, j in enumerate(cells):
+        rows = sorted({j} | {nb for nb in mesh.neighbour_table_row(nx, ny, j) if nb >= 0})
+        indptr, indices, data, rws = assemble.assemble_bsr(p, nx, ny, L, rows)
+        for r, c in enumerate(rws):
+            for b in range(indptr[r], indptr[r + 1]):
+                if indices[b] == j:
+                    out[:, t, :] += x3[:, c, :] @ data[b]
+    return out
 
 
 def dense_matrix(p, nx, ny, L):

@@ -1,0 +1,49 @@
+"""Differentiable linear solve x = J^{-1} b through the r1s C ABI.
+
+Forward: pack the structured values, set up the SMW block-Jacobi (with its
+transposed factors) and solve by GMRES.  Only x is saved: backward solves
+the adjoint system J^T lambda = dLoss/dx with a fresh Krylov basis (nothing
+of the forward basis is stored), then forms the gradients w.r.t. b
+(= lambda) and w.r.t. the structured arrays with the hand-written gradient
+kernel.
+"""
+import torch
+
+from . import r1s
+
+FIELDS = r1s.FIELDS
+
+
+class R1SolveFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, b, s_diag, s_sub, s_sup, s_flow, s_nbr, u, v, cfg):
+        nx, ny, L = cfg["nx"], cfg["ny"], cfg["L"]
+        vals = dict(zip(FIELDS, (s_diag, s_sub, s_sup, s_flow, s_nbr, u, v)))
+        vals = {k: t.detach().contiguous() for k, t in vals.items()}
+        A = r1s.R1Matrix(nx, ny, L, vals)
+        M = r1s.SMWPreconditioner(A, with_trans=True)
+        bb = b.detach().contiguous()
+        res = r1s.gmres(A, M, bb, restart=cfg.get("restart", 50), rtol=cfg.get("rtol", 1e-12),
+                        max_cycles=cfg.get("max_cycles", 200))
+        ctx.A, ctx.M, ctx.cfg = A, M, cfg
+        ctx.stats = res.stats
+        ctx.save_for_backward(res.x)
+        return res.x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        cfg = ctx.cfg
+        gx = gx.contiguous()
+        lam = r1s.gmres(ctx.A, ctx.M, gx, trans=True, restart=cfg.get("restart", 50),
+                        rtol=cfg.get("adj_rtol", cfg.get("rtol", 1e-12)),
+                        max_cycles=cfg.get("max_cycles", 200)).x
+        g = r1s.grad(ctx.A, lam, x)
+        return (lam, g["s_diag"], g["s_sub"], g["s_sup"], g["s_flow"], g["s_nbr"], g["u"],
+                g["v"], None)
+
+
+def solve(b, values, nx, ny, L, **cfg):
+    """x = J^{-1} b, differentiable w.r.t. b and every structured array."""
+    c = dict(cfg, nx=nx, ny=ny, L=L)
+    return R1SolveFn.apply(b, *(values[k] for k in FIELDS), c)

@@ -1,0 +1,812 @@
+// C ABI of libr1s (declared in include/r1s.h): argument validation, layout of
+// the caller-provided device buffers, handles and the GMRES driver loop.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "r1s.h"
+#include "r1s_kernels.hpp"
+
+using namespace r1s;
+
+// ------------------------------------------------------------ errors -----
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(R1S_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                            \
+  } while (0)
+
+extern "C" const char* r1s_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------ helpers ----
+static inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+static inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Carves 256-byte aligned sub-buffers out of one caller buffer.  With a null
+// base it only counts bytes, so size queries and init share one layout.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+static int check_dims(int nx, int ny, int L) {
+  if (nx < 1 || ny < 1 || L < 1)
+    return fail(R1S_ERR_ARG, "nx, ny, L must be >= 1 (got %d, %d, %d)", nx, ny, L);
+  if ((long long)nx * ny > (1LL << 30)) return fail(R1S_ERR_ARG, "mesh too large");
+  if (L + 3 > R1S_MAX_M)
+    return fail(R1S_ERR_UNSUPPORTED, "block size m = L + 3 = %d exceeds %d", L + 3, R1S_MAX_M);
+  return R1S_OK;
+}
+
+static Mesh make_mesh(int nx, int ny, int L) {
+  Mesh g;
+  g.nx = nx; g.ny = ny; g.L = L; g.m = L + 3; g.mp = pad_m(L + 3);
+  g.N = nx * ny;
+  g.n = (long long)g.N * g.m;
+  return g;
+}
+
+static long long n_blocks(int nx, int ny) { return 5LL * nx * ny - 2LL * nx - 2LL * ny; }
+
+// ------------------------------------------------------------- matrix ----
+struct r1s_mat_s {
+  Mesh g;
+  int flags;
+  double* rec64;
+  float* rec32;
+};
+
+static void mat_layout(Carver& cv, const Mesh& g, int flags, double** r64, float** r32) {
+  const size_t cnt = (size_t)g.N * F_REC * g.mp;
+  *r64 = cv.take<double>(cnt);
+  *r32 = (flags & R1S_KEEP_F32) ? cv.take<float>(cnt) : nullptr;
+}
+
+extern "C" int r1s_mat_size(int nx, int ny, int L, int flags, size_t* bytes) {
+  if (int e = check_dims(nx, ny, L)) return e;
+  if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
+  if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
+  Carver cv(nullptr);
+  double* a;
+  float* b;
+  mat_layout(cv, make_mesh(nx, ny, L), flags, &a, &b);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+static int check_inputs(const r1s_inputs* in, int L) {
+  if (!in) return fail(R1S_ERR_ARG, "inputs is NULL");
+  const void* ps[7] = {in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr, in->u, in->v};
+  const char* names[7] = {"s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"};
+  for (int i = 0; i < 7; ++i) {
+    if ((i == 1 || i == 2) && L == 1) continue;
+    if (!ps[i]) return fail(R1S_ERR_ARG, "input %s is NULL", names[i]);
+    if (!aligned(ps[i], 8)) return fail(R1S_ERR_ARG, "input %s is not 8-byte aligned", names[i]);
+  }
+  return R1S_OK;
+}
+
+static int do_pack(r1s_mat A, const r1s_inputs* in, hipStream_t s) {
+  PackIn p{in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr, in->u, in->v};
+  HIP_TRY(launch_pack(A->g, p, A->rec64, A->rec32, s));
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_init(int nx, int ny, int L, int flags, const r1s_inputs* in, void* mem,
+                            size_t mem_bytes, void* stream, r1s_mat* out) {
+  size_t need;
+  if (int e = r1s_mat_size(nx, ny, L, flags, &need)) return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  if (int e = check_inputs(in, L)) return e;
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need)
+    return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  r1s_mat A = (r1s_mat)calloc(1, sizeof(r1s_mat_s));
+  if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  A->g = make_mesh(nx, ny, L);
+  A->flags = flags;
+  Carver cv(mem);
+  mat_layout(cv, A->g, flags, &A->rec64, &A->rec32);
+  if (int e = do_pack(A, in, as_stream(stream))) {
+    free(A);
+    return e;
+  }
+  hipError_t he = hipStreamSynchronize(as_stream(stream));
+  if (he != hipSuccess) {
+    free(A);
+    return fail(R1S_ERR_HIP, "pack: %s", hipGetErrorString(he));
+  }
+  *out = A;
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (int e = check_inputs(in, A->g.L)) return e;
+  if (int e = do_pack(A, in, as_stream(stream))) return e;
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_destroy(r1s_mat A) {
+  free(A);
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
+  if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
+  const Mesh& g = A->g;
+  const long long B = n_blocks(g.nx, g.ny), N = g.N, m = g.m;
+  out->n_cells = N;
+  out->n_blocks = B;
+  out->m = m;
+  out->structured_values = N * (3 * m - 2) + (B - N) * m + 2 * B * m;
+  out->structured_padded = N * (long long)F_REC * g.mp;
+  out->bsr_values = B * m * m;
+  out->index_bytes = 0;
+  out->matvec_bytes = 8 * out->structured_values + 8 * 2 * N * m;
+  out->smw_apply_bytes = 8 * N * (5 * m - 1) + 8 * 2 * N * m;
+  return R1S_OK;
+}
+
+static int check_vec(const void* p, const char* name) {
+  if (!p) return fail(R1S_ERR_ARG, "%s is NULL", name);
+  if (!aligned(p, 8)) return fail(R1S_ERR_ARG, "%s is not 8-byte aligned", name);
+  return R1S_OK;
+}
+
+extern "C" int r1s_matvec(r1s_mat A, int precision, int trans, int nrhs, const double* x,
+                          double* y, void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (precision != R1S_F64 && precision != R1S_F32)
+    return fail(R1S_ERR_ARG, "unknown precision %d", precision);
+  if (precision == R1S_F32 && !A->rec32)
+    return fail(R1S_ERR_ARG, "float32 matvec needs a matrix made with R1S_KEEP_F32");
+  if (int e = check_vec(x, "x")) return e;
+  if (int e = check_vec(y, "y")) return e;
+  if (x == y) return fail(R1S_ERR_ARG, "x and y must not alias");
+  const bool f32 = precision == R1S_F32;
+  HIP_TRY(launch_matvec(A->g, f32 ? (const void*)A->rec32 : (const void*)A->rec64, f32, trans != 0,
+                        x, y, nrhs, as_stream(stream)));
+  return R1S_OK;
+}
+
+extern "C" int r1s_residual(r1s_mat A, int nrhs, const double* b, const double* x, double* r,
+                            void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (int e = check_vec(b, "b")) return e;
+  if (int e = check_vec(x, "x")) return e;
+  if (int e = check_vec(r, "r")) return e;
+  if (x == r) return fail(R1S_ERR_ARG, "x and r must not alias");
+  HIP_TRY(launch_residual(A->g, A->rec64, false, b, x, r, nrhs, as_stream(stream)));
+  return R1S_OK;
+}
+
+// -------------------------------------------------------- preconditioner --
+enum { PREC_SMW = 0, PREC_BSR_LU = 1 };
+
+struct r1s_prec_s {
+  int kind;
+  int flags;
+  Mesh g;
+  // SMW
+  double *facF, *facT, *invC;
+  float *facF32, *facT32, *invC32;
+  int* status;
+  // BSR dense LU
+  double* lu;
+  int* piv;
+};
+
+static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
+  const size_t f = (size_t)g.N * F_SMW * g.mp;
+  P->facF = cv.take<double>(f);
+  P->facT = (flags & R1S_WITH_TRANS) ? cv.take<double>(f) : nullptr;
+  P->invC = cv.take<double>(g.N);
+  P->status = cv.take<int>(64);
+  P->facF32 = (flags & R1S_KEEP_F32) ? cv.take<float>(f) : nullptr;
+  P->facT32 = ((flags & R1S_KEEP_F32) && (flags & R1S_WITH_TRANS)) ? cv.take<float>(f) : nullptr;
+  P->invC32 = (flags & R1S_KEEP_F32) ? cv.take<float>(g.N) : nullptr;
+}
+
+extern "C" int r1s_prec_size(r1s_mat A, int flags, size_t* bytes) {
+  if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
+  if (flags & ~(R1S_KEEP_F32 | R1S_WITH_TRANS)) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
+  Carver cv(nullptr);
+  r1s_prec_s tmp;
+  prec_layout(cv, A->g, flags, &tmp);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+static int read_status(int* dstatus, hipStream_t s, int* host) {
+  HIP_TRY(hipMemcpyAsync(host, dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return R1S_OK;
+}
+
+extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes, void* stream,
+                              r1s_prec* out) {
+  size_t need;
+  if (int e = r1s_prec_size(A, flags, &need)) return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need) return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  r1s_prec P = (r1s_prec)calloc(1, sizeof(r1s_prec_s));
+  if (!P) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  P->kind = PREC_SMW;
+  P->flags = flags;
+  P->g = A->g;
+  Carver cv(mem);
+  prec_layout(cv, A->g, flags, P);
+  hipStream_t s = as_stream(stream);
+  int st = 0x7fffffff;
+  int rc = R1S_OK;
+  do {
+    hipError_t e;
+    if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
+    if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
+    if (P->facF32) {
+      const long long f = (long long)A->g.N * F_SMW * A->g.mp;
+      if ((e = launch_cast_f32(P->facF, P->facF32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+      if (P->facT32 && (e = launch_cast_f32(P->facT, P->facT32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+      if ((e = launch_cast_f32(P->invC, P->invC32, A->g.N, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+    }
+    if ((rc = read_status(P->status, s, &st))) break;
+    if (st != 0x7fffffff) {
+      rc = fail(R1S_ERR_SINGULAR, "SMW setup: singular diagonal block (zero pivot or capacitance) at cell %d", st);
+      break;
+    }
+  } while (0);
+  if (rc) {
+    free(P);
+    return rc;
+  }
+  *out = P;
+  return R1S_OK;
+}
+
+extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, const double* r,
+                              double* z, void* stream) {
+  if (!M) return fail(R1S_ERR_ARG, "preconditioner handle is NULL");
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (int e = check_vec(r, "r")) return e;
+  if (int e = check_vec(z, "z")) return e;
+  if (r == z) return fail(R1S_ERR_ARG, "r and z must not alias");
+  if (precision != R1S_F64 && precision != R1S_F32)
+    return fail(R1S_ERR_ARG, "unknown precision %d", precision);
+  hipStream_t s = as_stream(stream);
+  if (M->kind == PREC_BSR_LU) {
+    if (trans || precision != R1S_F64)
+      return fail(R1S_ERR_UNSUPPORTED, "the dense-LU preconditioner applies M r in float64 only");
+    HIP_TRY(launch_bsr_lu_apply(M->g, M->lu, M->piv, r, z, nrhs, s));
+    return R1S_OK;
+  }
+  if (trans && !M->facT) return fail(R1S_ERR_ARG, "transposed apply needs R1S_WITH_TRANS at setup");
+  if (precision == R1S_F32) {
+    if (!M->facF32) return fail(R1S_ERR_ARG, "float32 apply needs R1S_KEEP_F32 at setup");
+    HIP_TRY(launch_smw_apply(M->g, trans ? (const void*)M->facT32 : (const void*)M->facF32, M->invC32,
+                             true, trans != 0, r, z, nrhs, s));
+  } else {
+    HIP_TRY(launch_smw_apply(M->g, trans ? (const void*)M->facT : (const void*)M->facF, M->invC,
+                             false, trans != 0, r, z, nrhs, s));
+  }
+  return R1S_OK;
+}
+
+extern "C" int r1s_prec_destroy(r1s_prec M) {
+  free(M);
+  return R1S_OK;
+}
+
+// ------------------------------------------------------------------ BSR ---
+struct r1s_bsr_s {
+  Mesh g;
+  long long nblocks;
+  int *indptr, *indices, *blk_row, *blk_dir, *diag_block;
+  double* data;
+};
+
+static void bsr_layout(Carver& cv, const Mesh& g, r1s_bsr_s* B) {
+  B->nblocks = n_blocks(g.nx, g.ny);
+  B->data = cv.take<double>((size_t)B->nblocks * g.m * g.m);
+  B->indptr = cv.take<int>(g.N + 1);
+  B->indices = cv.take<int>(B->nblocks);
+  B->blk_row = cv.take<int>(B->nblocks);
+  B->blk_dir = cv.take<int>(B->nblocks);
+  B->diag_block = cv.take<int>(g.N);
+}
+
+extern "C" int r1s_bsr_size(r1s_mat A, size_t* bytes) {
+  if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
+  Carver cv(nullptr);
+  r1s_bsr_s tmp;
+  bsr_layout(cv, A->g, &tmp);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+extern "C" int r1s_bsr_init(r1s_mat A, void* mem, size_t mem_bytes, void* stream, r1s_bsr* out) {
+  size_t need;
+  if (int e = r1s_bsr_size(A, &need)) return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need) return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  const Mesh& g = A->g;
+  if ((long long)n_blocks(g.nx, g.ny) * g.m * g.m > (1LL << 62))
+    return fail(R1S_ERR_UNSUPPORTED, "BSR too large");
+  r1s_bsr B = (r1s_bsr)calloc(1, sizeof(r1s_bsr_s));
+  if (!B) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  B->g = g;
+  Carver cv(mem);
+  bsr_layout(cv, g, B);
+  // block structure in BSR order: block rows by cell, columns ascending
+  std::vector<int> indptr(g.N + 1), indices, row, dir, diag(g.N);
+  indices.reserve(B->nblocks);
+  for (int c = 0; c < g.N; ++c) {
+    indptr[c] = (int)indices.size();
+    const int iy = c / g.nx, ix = c % g.nx;
+    const int nbs[5] = {iy > 0 ? c - g.nx : -1, ix > 0 ? c - 1 : -1, c,
+                        ix < g.nx - 1 ? c + 1 : -1, iy < g.ny - 1 ? c + g.nx : -1};
+    for (int d = 0; d < 5; ++d) {
+      if (nbs[d] < 0) continue;
+      if (d == D_C) diag[c] = (int)indices.size();
+      indices.push_back(nbs[d]);
+      row.push_back(c);
+      dir.push_back(d);
+    }
+  }
+  indptr[g.N] = (int)indices.size();
+  hipStream_t s = as_stream(stream);
+  int rc = R1S_OK;
+  do {
+    hipError_t e;
+#define TRY_(x) if ((e = (x)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "%s: %s", #x, hipGetErrorString(e)); break; }
+    TRY_(hipMemcpyAsync(B->indptr, indptr.data(), indptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TRY_(hipMemcpyAsync(B->indices, indices.data(), indices.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TRY_(hipMemcpyAsync(B->blk_row, row.data(), row.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TRY_(hipMemcpyAsync(B->blk_dir, dir.data(), dir.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TRY_(hipMemcpyAsync(B->diag_block, diag.data(), diag.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    TRY_(launch_bsr_assemble(g, A->rec64, B->blk_row, B->blk_dir, B->nblocks, B->data, s));
+    TRY_(hipStreamSynchronize(s));
+#undef TRY_
+  } while (0);
+  if (rc) {
+    free(B);
+    return rc;
+  }
+  *out = B;
+  return R1S_OK;
+}
+
+extern "C" int r1s_bsr_matvec(r1s_bsr B, int nrhs, const double* x, double* y, void* stream) {
+  if (!B) return fail(R1S_ERR_ARG, "BSR handle is NULL");
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (int e = check_vec(x, "x")) return e;
+  if (int e = check_vec(y, "y")) return e;
+  if (x == y) return fail(R1S_ERR_ARG, "x and y must not alias");
+  HIP_TRY(launch_bsr_matvec(B->g, B->indptr, B->indices, B->data, x, y, nrhs, as_stream(stream)));
+  return R1S_OK;
+}
+
+static void bsr_prec_layout(Carver& cv, const Mesh& g, r1s_prec_s* P) {
+  P->lu = cv.take<double>((size_t)g.N * g.m * g.m);
+  P->piv = cv.take<int>((size_t)g.N * g.m);
+  P->status = cv.take<int>(64);
+}
+
+extern "C" int r1s_bsr_prec_size(r1s_bsr B, size_t* bytes) {
+  if (!B || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
+  Carver cv(nullptr);
+  r1s_prec_s tmp;
+  bsr_prec_layout(cv, B->g, &tmp);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+extern "C" int r1s_bsr_prec_setup(r1s_bsr B, void* mem, size_t mem_bytes, void* stream,
+                                  r1s_prec* out) {
+  size_t need;
+  if (int e = r1s_bsr_prec_size(B, &need)) return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need) return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  r1s_prec P = (r1s_prec)calloc(1, sizeof(r1s_prec_s));
+  if (!P) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  P->kind = PREC_BSR_LU;
+  P->g = B->g;
+  Carver cv(mem);
+  bsr_prec_layout(cv, B->g, P);
+  hipStream_t s = as_stream(stream);
+  int st = 0x7fffffff, rc = R1S_OK;
+  do {
+    hipError_t e;
+    if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
+    if ((e = launch_bsr_lu_setup(B->g, B->diag_block, B->data, P->lu, P->piv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "bsr lu: %s", hipGetErrorString(e)); break; }
+    if ((rc = read_status(P->status, s, &st))) break;
+    if (st != 0x7fffffff) { rc = fail(R1S_ERR_SINGULAR, "dense LU: zero pivot in the diagonal block of cell %d", st); break; }
+  } while (0);
+  if (rc) {
+    free(P);
+    return rc;
+  }
+  *out = P;
+  return R1S_OK;
+}
+
+extern "C" int r1s_bsr_destroy(r1s_bsr B) {
+  free(B);
+  return R1S_OK;
+}
+
+// ---------------------------------------------------------------- GMRES ---
+struct GmresWork {
+  double *V, *w, *z, *t, *part, *hdev, *ydev, *scal, *r64, *d;
+  int nblk;
+};
+
+static void gmres_layout(Carver& cv, const Mesh& g, int k, int nrhs, bool mixed, GmresWork* W) {
+  const size_t n = (size_t)g.n;
+  W->nblk = dot_blocks(g.n);
+  W->V = cv.take<double>((size_t)nrhs * (k + 1) * n);
+  W->w = cv.take<double>((size_t)nrhs * n);
+  W->z = cv.take<double>((size_t)nrhs * n);
+  W->t = cv.take<double>((size_t)nrhs * n);
+  W->part = cv.take<double>((size_t)nrhs * (k + 2) * W->nblk);
+  W->hdev = cv.take<double>((size_t)nrhs * (k + 2) * 2);
+  W->ydev = cv.take<double>((size_t)nrhs * (k + 1));
+  W->scal = cv.take<double>((size_t)nrhs * 4);
+  W->r64 = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
+  W->d = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
+}
+
+static int check_opts(const r1s_gmres_opts* o) {
+  if (!o) return fail(R1S_ERR_ARG, "opts is NULL");
+  if (o->restart < 1 || o->restart > 1000) return fail(R1S_ERR_ARG, "restart must be in [1, 1000]");
+  if (o->max_cycles < 1) return fail(R1S_ERR_ARG, "max_cycles must be >= 1");
+  if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(R1S_ERR_ARG, "rtol must be in (0, 1)");
+  if (o->op != R1S_OP_STRUCTURED && o->op != R1S_OP_BSR) return fail(R1S_ERR_ARG, "unknown op");
+  if (o->mode != R1S_MODE_F64 && o->mode != R1S_MODE_MIXED_IR) return fail(R1S_ERR_ARG, "unknown mode");
+  if (o->mode == R1S_MODE_MIXED_IR) {
+    if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) return fail(R1S_ERR_ARG, "inner_rtol must be in (0, 1)");
+    if (o->max_outer < 1) return fail(R1S_ERR_ARG, "max_outer must be >= 1");
+    if (o->op != R1S_OP_STRUCTURED) return fail(R1S_ERR_ARG, "mixed mode needs the structured operator");
+  }
+  return R1S_OK;
+}
+
+extern "C" int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs, size_t* bytes) {
+  if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
+  if (int e = check_opts(opts)) return e;
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  Carver cv(nullptr);
+  GmresWork W;
+  gmres_layout(cv, A->g, opts->restart, nrhs, opts->mode == R1S_MODE_MIXED_IR, &W);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+// The operator pair one GMRES solve works with.
+struct OpCtx {
+  r1s_mat A;
+  r1s_bsr B;
+  r1s_prec M;
+  bool f32;   // float32 operator + preconditioner (inner solves)
+  bool trans;
+  bool bsr;
+  hipStream_t s;
+};
+
+static int op_apply(const OpCtx& c, const double* in, double* out, int nrhs) {
+  if (c.bsr) {
+    HIP_TRY(launch_bsr_matvec(c.B->g, c.B->indptr, c.B->indices, c.B->data, in, out, nrhs, c.s));
+  } else {
+    HIP_TRY(launch_matvec(c.A->g, c.f32 ? (const void*)c.A->rec32 : (const void*)c.A->rec64, c.f32,
+                          c.trans, in, out, nrhs, c.s));
+  }
+  return R1S_OK;
+}
+
+static int prec_apply(const OpCtx& c, const double* in, double* out, int nrhs) {
+  if (int e = r1s_prec_apply(c.M, c.f32 ? R1S_F32 : R1S_F64, c.trans ? 1 : 0, nrhs, in, out, c.s))
+    return e;
+  return R1S_OK;
+}
+
+// out = b - op(x), float64 for the structured operator in f64 mode, else via op
+static int op_residual(const OpCtx& c, const double* b, const double* x, double* out, int nrhs) {
+  if (!c.bsr && !c.f32) {
+    HIP_TRY(launch_residual(c.A->g, c.A->rec64, c.trans, b, x, out, nrhs, c.s));
+    return R1S_OK;
+  }
+  if (int e = op_apply(c, x, out, nrhs)) return e;
+  HIP_TRY(launch_rsub(b, out, c.A->g.n, nrhs, c.s));
+  return R1S_OK;
+}
+
+// Norms of nrhs contiguous vectors of length n (deterministic, float64).
+static int norms(const Mesh& g, GmresWork& W, const double* v, int nrhs, hipStream_t s,
+                 std::vector<double>& out) {
+  Basis none{W.V, 0, 0};
+  HIP_TRY(launch_multidot(none, 0, v, g.n, g.n, nrhs, W.part, W.nblk, true, s));
+  HIP_TRY(launch_reduce(W.part, nrhs, W.nblk, W.scal, s));
+  out.assign(nrhs, 0.0);
+  HIP_TRY(hipMemcpyAsync(out.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (auto& x : out) x = sqrt(x);
+  return R1S_OK;
+}
+
+struct SolveStat {
+  int iters = 0, cycles = 0;
+  bool converged = false;
+  double rel = 0.0;
+};
+
+// Restarted right-preconditioned GMRES on nrhs systems op(x) = b, starting
+// from x (x0_given) or zero.  rtol is relative to |b| per right-hand side.
+static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
+                      double rtol, int nrhs, const double* b, double* x, bool x0_given,
+                      std::vector<SolveStat>& st) {
+  hipStream_t s = c.s;
+  const long long n = g.n;
+  const int HS = k + 2;  // stride of the per-rhs h arrays
+  std::vector<double> bnorm;
+  if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;
+  st.assign(nrhs, SolveStat());
+  if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
+  for (int r = 0; r < nrhs; ++r)
+    if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
+  Basis Vb{W.V, n, (long long)(k + 1) * n};
+  std::vector<double> H((size_t)nrhs * (k + 1) * k), cs((size_t)nrhs * k), sn((size_t)nrhs * k),
+      gv((size_t)nrhs * (k + 1)), y((size_t)nrhs * (k + 1)), hbuf((size_t)nrhs * HS * 2),
+      beta, w0(nrhs);
+  std::vector<int> jend(nrhs), done(nrhs);
+  auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
+
+  for (int cycle = 0;; ++cycle) {
+    // true residual of the current iterate
+    if (cycle == 0 && !x0_given) {
+      HIP_TRY(hipMemcpyAsync(W.w, b, (size_t)nrhs * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      if (int e = op_residual(c, b, x, W.w, nrhs)) return e;
+    }
+    if (int e = norms(g, W, W.w, nrhs, s, beta)) return e;
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!(beta[r] == beta[r]) || isinf(beta[r])) return fail(R1S_ERR_NONFINITE, "residual of right-hand side %d is not finite", r);
+      st[r].rel = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
+      st[r].converged = beta[r] <= rtol * bnorm[r];
+      done[r] = st[r].converged;
+      all = all && done[r];
+    }
+    if (all || cycle == max_cycles) break;
+    for (int r = 0; r < nrhs; ++r) {
+      st[r].cycles += done[r] ? 0 : 1;
+      y[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;  // scale factors for v_0
+      jend[r] = 0;
+      for (int i = 0; i <= k; ++i) gv[(size_t)r * (k + 1) + i] = 0.0;
+      gv[(size_t)r * (k + 1)] = beta[r];
+    }
+    HIP_TRY(hipMemcpyAsync(W.scal, y.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_scale(W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
+
+    for (int j = 0; j < k; ++j) {
+      double* Vj = W.V + (long long)j * n;
+      // z = M v_j ; w = op(z)   (v_j of every rhs: strided copy into t)
+      if (nrhs == 1) {
+        if (int e = prec_apply(c, Vj, W.z, 1)) return e;
+      } else {
+        HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
+                                 n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+        if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
+      }
+      if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
+      const int nv = j + 1;
+      // CGS pass 1: h1 = V^T w, |w|^2 ; w -= V h1
+      HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, W.hdev, s));
+      HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
+      // CGS pass 2: h2 = V^T w, |w|^2
+      double* h2 = W.hdev + (size_t)nrhs * HS;
+      HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
+      // v_{j+1} = (w - V h2) / |w - V h2|
+      HIP_TRY(launch_update_normalize(Vb, nv, h2, nv + 1, h2 + nv, nv + 1, W.w, n,
+                                      W.V + (long long)(j + 1) * n, n, nrhs, s));
+      HIP_TRY(hipMemcpyAsync(hbuf.data(), W.hdev, (size_t)nrhs * (nv + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)nrhs * HS, h2,
+                             (size_t)nrhs * (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      bool all_done = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (done[r]) continue;
+        const double* h1r = hbuf.data() + (size_t)r * (nv + 1);
+        const double* h2r = hbuf.data() + (size_t)nrhs * HS + (size_t)r * (nv + 1);
+        double hh = 0.0;
+        for (int i = 0; i < nv; ++i) {
+          Hat(r, i, j) = h1r[i] + h2r[i];
+          hh += h2r[i] * h2r[i];
+        }
+        const double q = h2r[nv] - hh;
+        const double hn = q > 0.0 ? sqrt(q) : 0.0;
+        const double wnorm0 = sqrt(h1r[nv]);
+        Hat(r, j + 1, j) = hn;
+        st[r].iters += 1;
+        // previous rotations, then a new one eliminating H[j+1][j]
+        for (int i = 0; i < j; ++i) {
+          const double a = Hat(r, i, j), bb = Hat(r, i + 1, j);
+          Hat(r, i, j) = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
+          Hat(r, i + 1, j) = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
+        }
+        const double a = Hat(r, j, j), bb = Hat(r, j + 1, j);
+        const double rho = hypot(a, bb);
+        const bool breakdown = hn <= 1e-14 * wnorm0;
+        const double cj = rho > 0 ? a / rho : 1.0, sj = rho > 0 ? bb / rho : 0.0;
+        cs[(size_t)r * k + j] = cj;
+        sn[(size_t)r * k + j] = sj;
+        Hat(r, j, j) = rho;
+        Hat(r, j + 1, j) = 0.0;
+        double* gr = gv.data() + (size_t)r * (k + 1);
+        gr[j + 1] = -sj * gr[j];
+        gr[j] = cj * gr[j];
+        jend[r] = j + 1;
+        if (breakdown || fabs(gr[j + 1]) <= rtol * bnorm[r]) done[r] = 1;
+        all_done = all_done && done[r];
+      }
+      if (all_done) break;
+    }
+    // y = R^{-1} g per rhs; x += M (V y)
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+      const int je = jend[r];
+      double* yr = y.data() + (size_t)r * (k + 1);
+      const double* gr = gv.data() + (size_t)r * (k + 1);
+      for (int i = je - 1; i >= 0; --i) {
+        double acc = gr[i];
+        for (int l = i + 1; l < je; ++l) acc -= Hat(r, i, l) * yr[l];
+        yr[i] = Hat(r, i, i) != 0.0 ? acc / Hat(r, i, i) : 0.0;
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(W.ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    int kmax = 0;
+    for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, jend[r]);
+    HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
+    if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
+    HIP_TRY(launch_axpy(nullptr, W.z, x, n, nrhs, s));
+  }
+  return R1S_OK;
+}
+
+extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts, int nrhs,
+                         const double* b, double* x, void* work, size_t work_bytes,
+                         r1s_gmres_stats* stats, void* stream) {
+  if (!A || !M) return fail(R1S_ERR_ARG, "matrix or preconditioner handle is NULL");
+  if (int e = check_opts(opts)) return e;
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (int e = check_vec(b, "b")) return e;
+  if (int e = check_vec(x, "x")) return e;
+  if (b == x) return fail(R1S_ERR_ARG, "b and x must not alias");
+  if (opts->op == R1S_OP_BSR && !B) return fail(R1S_ERR_ARG, "BSR operator requested but B is NULL");
+  if (opts->op == R1S_OP_BSR && opts->trans) return fail(R1S_ERR_UNSUPPORTED, "BSR operator: no transposed solve");
+  if (B && (B->g.nx != A->g.nx || B->g.ny != A->g.ny || B->g.L != A->g.L))
+    return fail(R1S_ERR_ARG, "BSR handle does not match the matrix");
+  if (M->g.nx != A->g.nx || M->g.ny != A->g.ny || M->g.L != A->g.L)
+    return fail(R1S_ERR_ARG, "preconditioner does not match the matrix");
+  if (opts->trans && M->kind == PREC_SMW && !M->facT)
+    return fail(R1S_ERR_ARG, "transposed solve needs a preconditioner set up with R1S_WITH_TRANS");
+  if (opts->trans && M->kind == PREC_BSR_LU)
+    return fail(R1S_ERR_UNSUPPORTED, "dense-LU preconditioner: no transposed apply");
+  const bool mixed = opts->mode == R1S_MODE_MIXED_IR;
+  if (mixed && (!A->rec32 || M->kind != PREC_SMW || !M->facF32))
+    return fail(R1S_ERR_ARG, "mixed mode needs R1S_KEEP_F32 on the matrix and the preconditioner");
+  if (!work || !aligned(work, 256)) return fail(R1S_ERR_ARG, "work is NULL or not 256-byte aligned");
+  size_t need;
+  if (int e = r1s_gmres_work_size(A, opts, nrhs, &need)) return e;
+  if (work_bytes < need) return fail(R1S_ERR_ARG, "work_bytes %zu < required %zu", work_bytes, need);
+
+  const Mesh& g = A->g;
+  GmresWork W;
+  Carver cv(work);
+  gmres_layout(cv, g, opts->restart, nrhs, mixed, &W);
+  hipStream_t s = as_stream(stream);
+  OpCtx c{A, B, M, false, opts->trans != 0, opts->op == R1S_OP_BSR, s};
+  std::vector<SolveStat> st;
+  int outer = 0;
+  int rc;
+  if (!mixed) {
+    rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
+                    opts->x0_given != 0, st);
+    if (rc) return rc;
+  } else {
+    // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
+    std::vector<double> bnorm, rn;
+    if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;
+    if (!opts->x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * g.n * sizeof(double), s));
+    OpCtx ci = c;
+    ci.f32 = true;
+    std::vector<SolveStat> tot(nrhs);
+    for (;; ++outer) {
+      if (int e = op_residual(c, b, x, W.r64, nrhs)) return e;
+      if (int e = norms(g, W, W.r64, nrhs, s, rn)) return e;
+      bool all = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!(rn[r] == rn[r]) || isinf(rn[r])) return fail(R1S_ERR_NONFINITE, "refinement residual %d is not finite", r);
+        tot[r].rel = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+        tot[r].converged = rn[r] <= opts->rtol * bnorm[r];
+        all = all && tot[r].converged;
+      }
+      if (all || outer == opts->max_outer) break;
+      std::vector<SolveStat> in;
+      rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs, W.r64,
+                      W.d, false, in);
+      if (rc) return rc;
+      for (int r = 0; r < nrhs; ++r) {
+        tot[r].iters += in[r].iters;
+        tot[r].cycles += in[r].cycles;
+      }
+      HIP_TRY(launch_axpy(nullptr, W.d, x, g.n, nrhs, s));
+    }
+    st = tot;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  bool ok = true;
+  for (int r = 0; r < nrhs; ++r) {
+    ok = ok && st[r].converged;
+    if (stats) {
+      stats[r].iters = st[r].iters;
+      stats[r].cycles = st[r].cycles;
+      stats[r].outer = outer;
+      stats[r].converged = st[r].converged ? 1 : 0;
+      stats[r].rel_residual = st[r].rel;
+    }
+  }
+  if (!ok) return fail(R1S_ERR_NOCONV, "GMRES did not reach rtol %g", opts->rtol);
+  return R1S_OK;
+}
+
+// ------------------------------------------------------------ gradients ---
+extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
+                        const r1s_grads* out, void* stream) {
+  if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
+  if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
+  if (int e = check_vec(lambda, "lambda")) return e;
+  if (int e = check_vec(x, "x")) return e;
+  const void* ps[7] = {out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v};
+  for (int i = 0; i < 7; ++i) {
+    if ((i == 1 || i == 2) && A->g.L == 1) continue;
+    if (int e = check_vec(ps[i], "gradient output")) return e;
+  }
+  GradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v};
+  HIP_TRY(launch_grad(A->g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
+  return R1S_OK;
+}

@@ -1,0 +1,284 @@
+// Dense-block BSR baseline: the standard representation of section 3
+// (Jacobian Complexity, N_A = sum m^2 (N_e + 1) stored values) in the BSR
+// format of section 5.1, and the classical block-Jacobi of section 6 (LU of
+// every dense diagonal block).
+//
+// Blocks are stored column-major (element (i, j) of block b at b*m*m + j*m + i)
+// so that the lanes of a wavefront, one per block row i, read contiguous
+// memory for every column j.
+#include <math.h>
+
+#include "r1s_device.hpp"
+#include "r1s_kernels.hpp"
+
+namespace r1s {
+
+// D_{c,d} = S_{c,d} + u v^T, one workgroup per block.
+__global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __restrict__ rec,
+                                                      const int* __restrict__ blk_row,
+                                                      const int* __restrict__ blk_dir,
+                                                      double* __restrict__ data) {
+  const long long b = blockIdx.x;
+  const int c = blk_row[b], d = blk_dir[b];
+  const int m = g.m, mp = g.mp, L = g.L;
+  const double* rc = rec + (long long)c * F_REC * mp;
+  const double* u = rc + (long long)(F_U + d) * mp;
+  const double* v = rc + (long long)(F_V + d) * mp;
+  double* out = data + b * m * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int j = e / m, i = e - j * m;
+    double s = 0.0;
+    if (d == D_C) {
+      if (i == j) {
+        s = rc[F_DIAG * mp + i];
+      } else if (i < L && j < L) {
+        if (j == i - 1) s = rc[F_LO * mp + i];
+        if (j == i + 1) s = rc[F_HI * mp + i];
+      } else if (i >= L && j >= L) {
+        const int a = i - L, bb = j - L;
+        if (bb == (a + 2) % 3) s = rc[F_LO * mp + i];
+        if (bb == (a + 1) % 3) s = rc[F_HI * mp + i];
+      }
+    } else if (i == j) {
+      s = rc[(F_NBR + nbr_slot(d)) * mp + i];
+    }
+    out[e] = s + u[i] * v[j];
+  }
+}
+
+hipError_t launch_bsr_assemble(const Mesh& g, const double* rec, const int* blk_row,
+                               const int* blk_dir, long long nblocks, double* data,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_bsr_assemble, dim3((unsigned)nblocks), dim3(256), 0, s, g, rec, blk_row,
+                     blk_dir, data);
+  return hipGetLastError();
+}
+
+// y_c = sum_b D_b x_{col(b)}.  One wavefront per (cell, 64-row chunk); the
+// column blocks of x are read as wave-uniform values.
+__global__ __launch_bounds__(256) void k_bsr_matvec(Mesh g, const int* __restrict__ indptr,
+                                                    const int* __restrict__ indices,
+                                                    const double* __restrict__ data,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ y, int nrhs) {
+  const int nch = (g.m + WAVE - 1) / WAVE;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int unit = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
+  if (unit >= g.N * nch) return;
+  const int c = unit / nch, ch = unit - c * nch;
+  const int m = g.m;
+  const int i = ch * WAVE + lane_id();
+  const bool act = i < m;
+  const int b0 = indptr[c], b1 = indptr[c + 1];
+  for (int r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) {
+      const double* D = data + (long long)b * m * m + i;
+      const double* xc = x + (long long)r * g.n + (long long)indices[b] * m;
+      int j = 0;
+      for (; j + 4 <= m; j += 4) {
+        const double d0 = act ? D[(long long)(j + 0) * m] : 0.0;
+        const double d1 = act ? D[(long long)(j + 1) * m] : 0.0;
+        const double d2 = act ? D[(long long)(j + 2) * m] : 0.0;
+        const double d3 = act ? D[(long long)(j + 3) * m] : 0.0;
+        acc += d0 * xc[j] + d1 * xc[j + 1] + d2 * xc[j + 2] + d3 * xc[j + 3];
+      }
+      for (; j < m; ++j) acc += (act ? D[(long long)j * m] : 0.0) * xc[j];
+    }
+    if (act) y[(long long)r * g.n + (long long)c * m + i] = acc;
+  }
+}
+
+hipError_t launch_bsr_matvec(const Mesh& g, const int* indptr, const int* indices,
+                             const double* data, const double* x, double* y, int nrhs,
+                             hipStream_t s) {
+  const int nch = (g.m + WAVE - 1) / WAVE;
+  const long long units = (long long)g.N * nch;
+  hipLaunchKernelGGL(k_bsr_matvec, dim3((unsigned)((units + 3) / 4)), dim3(256), 0, s, g, indptr,
+                     indices, data, x, y, nrhs);
+  return hipGetLastError();
+}
+
+// LU with partial pivoting of the diagonal block of every cell, one
+// workgroup per cell, right-looking elimination on a column-major copy.  The
+// copy lives in LDS when it fits (m*m*8 <= 64 KiB), otherwise in the output
+// buffer itself.
+template <bool IN_LDS>
+__global__ __launch_bounds__(256) void k_bsr_lu(Mesh g, const int* __restrict__ diag_block,
+                                                const double* __restrict__ data,
+                                                double* __restrict__ lu, int* __restrict__ piv,
+                                                int* status) {
+  extern __shared__ double smem[];
+  __shared__ double red_v[4];
+  __shared__ int red_i[4];
+  __shared__ int s_p;
+  const int c = blockIdx.x;
+  const int m = g.m;
+  const long long mm = (long long)m * m;
+  const double* src = data + (long long)diag_block[c] * mm;
+  double* out = lu + (long long)c * mm;
+  double* A = IN_LDS ? smem : out;
+  for (int e = threadIdx.x; e < mm; e += blockDim.x) A[e] = src[e];
+  __syncthreads();
+  bool bad = false;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  for (int k = 0; k < m; ++k) {
+    // pivot: argmax |A[i][k]|, i >= k (lowest index on ties)
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < m; i += blockDim.x) {
+      const double a = fabs(A[(long long)k * m + i]);
+      if (a > best) { best = a; bi = i; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, WAVE);
+      const int oi = __shfl_xor(bi, off, WAVE);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { red_v[wave] = best; red_i[wave] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double bv = red_v[0];
+      int bidx = red_i[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bidx)) { bv = red_v[w]; bidx = red_i[w]; }
+      s_p = bidx;
+      piv[(long long)c * m + k] = bidx;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != k)
+      for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const double t = A[(long long)j * m + k];
+        A[(long long)j * m + k] = A[(long long)j * m + p];
+        A[(long long)j * m + p] = t;
+      }
+    __syncthreads();
+    const double pv = A[(long long)k * m + k];
+    if (pv == 0.0) bad = true;
+    const double pinv = 1.0 / pv;
+    for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) A[(long long)k * m + i] *= pinv;
+    __syncthreads();
+    const int nt = m - k - 1;
+    for (int e = threadIdx.x; e < nt * nt; e += blockDim.x) {
+      const int jj = e / nt, ii = e - jj * nt;
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      A[(long long)j * m + i] -= A[(long long)k * m + i] * A[(long long)j * m + k];
+    }
+    __syncthreads();
+  }
+  if (IN_LDS)
+    for (int e = threadIdx.x; e < mm; e += blockDim.x) out[e] = A[e];
+  if (bad && threadIdx.x == 0) atomicMin(status, c);
+}
+
+hipError_t launch_bsr_lu_setup(const Mesh& g, const int* diag_block, const double* data,
+                               double* lu, int* piv, int* status, hipStream_t s) {
+  const size_t lds = (size_t)g.m * g.m * sizeof(double);
+  if (lds <= 65536)
+    hipLaunchKernelGGL(k_bsr_lu<true>, dim3(g.N), dim3(256), lds, s, g, diag_block, data, lu, piv,
+                       status);
+  else
+    hipLaunchKernelGGL(k_bsr_lu<false>, dim3(g.N), dim3(256), 0, s, g, diag_block, data, lu, piv,
+                       status);
+  return hipGetLastError();
+}
+
+// z_c = D_cc^{-1} r_c from the packed LU: row swaps, unit-lower forward
+// substitution, upper back substitution.  One wavefront per cell; the m
+// unknowns sit in NCH registers per lane and every step broadcasts the newly
+// final unknown with a cross-lane read.
+template <int NCH>
+__global__ __launch_bounds__(256) void k_bsr_lu_apply(Mesh g, const double* __restrict__ lu,
+                                                      const int* __restrict__ piv,
+                                                      const double* __restrict__ rin,
+                                                      double* __restrict__ zout, int nrhs) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
+  if (c >= g.N) return;
+  const int lane = lane_id();
+  const int m = g.m;
+  const double* LU = lu + (long long)c * m * m;
+  const int* P = piv + (long long)c * m;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* rv = rin + (long long)r * g.n + (long long)c * m;
+    double y[NCH];
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const int i = t * WAVE + lane;
+      y[t] = i < m ? rv[i] : 0.0;
+    }
+    // row swaps in order
+    for (int k = 0; k < m; ++k) {
+      const int p = P[k];
+      if (p == k) continue;
+      const int tk = k / WAVE, lk = k % WAVE, tp = p / WAVE, lp = p % WAVE;
+      double vk = 0.0, vp = 0.0;
+#pragma unroll
+      for (int t = 0; t < NCH; ++t) {
+        const double a = __shfl(y[t], lk, WAVE);
+        const double b = __shfl(y[t], lp, WAVE);
+        if (t == tk) vk = a;
+        if (t == tp) vp = b;
+      }
+#pragma unroll
+      for (int t = 0; t < NCH; ++t) {
+        if (t == tk && lane == lk) y[t] = vp;
+        if (t == tp && lane == lp) y[t] = vk;
+      }
+    }
+    // forward: L unit lower
+#pragma unroll
+    for (int tj = 0; tj < NCH; ++tj) {
+      for (int lj = 0; lj < WAVE; ++lj) {
+        const int j = tj * WAVE + lj;
+        if (j >= m) break;
+        const double yj = __shfl(y[tj], lj, WAVE);
+        const double* col = LU + (long long)j * m;
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+          const int i = t * WAVE + lane;
+          if (t >= tj && i > j && i < m) y[t] -= col[i] * yj;
+        }
+      }
+    }
+    // backward: U upper
+#pragma unroll
+    for (int tj = NCH - 1; tj >= 0; --tj) {
+      for (int lj = WAVE - 1; lj >= 0; --lj) {
+        const int j = tj * WAVE + lj;
+        if (j >= m) continue;
+        const double* col = LU + (long long)j * m;
+        if (lane == lj) y[tj] /= col[j];
+        const double xj = __shfl(y[tj], lj, WAVE);
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+          const int i = t * WAVE + lane;
+          if (t <= tj && i < j) y[t] -= col[i] * xj;
+        }
+      }
+    }
+    double* zv = zout + (long long)r * g.n + (long long)c * m;
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const int i = t * WAVE + lane;
+      if (i < m) zv[i] = y[t];
+    }
+  }
+}
+
+hipError_t launch_bsr_lu_apply(const Mesh& g, const double* lu, const int* piv, const double* r,
+                               double* z, int nrhs, hipStream_t s) {
+  const int grid = (g.N + 3) / 4;
+  switch ((g.m + WAVE - 1) / WAVE) {
+    case 1: hipLaunchKernelGGL(k_bsr_lu_apply<1>, dim3(grid), dim3(256), 0, s, g, lu, piv, r, z, nrhs); break;
+    case 2: hipLaunchKernelGGL(k_bsr_lu_apply<2>, dim3(grid), dim3(256), 0, s, g, lu, piv, r, z, nrhs); break;
+    case 3: hipLaunchKernelGGL(k_bsr_lu_apply<3>, dim3(grid), dim3(256), 0, s, g, lu, piv, r, z, nrhs); break;
+    case 4: hipLaunchKernelGGL(k_bsr_lu_apply<4>, dim3(grid), dim3(256), 0, s, g, lu, piv, r, z, nrhs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace r1s

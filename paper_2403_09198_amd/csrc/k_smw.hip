@@ -1,0 +1,289 @@
+// Block-Jacobi preconditioner through the Sherman-Morrison-Woodbury identity.
+//
+// Section 6: the diagonal block of cell c is D_c = A0_c + u_cC v_cC^T with A0_c
+// the sparse diagonal block of S.  With w = A0^{-1} u and C = 1 + v . w
+// (SMW-1, SMW-2), D_c^{-1} r = x0 - w (v . x0) / C where x0 = A0^{-1} r.  The
+// printed identity adds the correction; the correct Woodbury identity
+// subtracts it, which is what is computed here.
+//
+// A0_c is the tridiagonal level band (no level/flow coupling) plus a dense
+// 3 x 3 flow corner.  The band is factored once (LU without pivoting, the
+// Thomas algorithm); each apply then runs the two bidiagonal sweeps as
+// affine-map scans across the 64 lanes of one wavefront (a serial recurrence
+// y_k = a_k y_{k-1} + b_k is a prefix composition of affine maps), carrying
+// the last value from one 64-level chunk to the next.
+#include <math.h>
+
+#include "r1s_device.hpp"
+#include "r1s_kernels.hpp"
+
+namespace r1s {
+
+__global__ void k_fill_int(int* p, int value, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- setup ----
+// One thread per cell; runs once per matrix.  Factor records (see
+// r1s_device.hpp): forward a = -l_k, dinv = 1/d_k, b = -s_k/d_k, w, v_cC;
+// transpose a = -s_{k-1}/d_k, dinv, b = -l_{k+1}, wt = A0^{-T} v_cC, u_cC.
+__global__ __launch_bounds__(256) void k_smw_setup(Mesh g, const double* __restrict__ rec,
+                                                   double* __restrict__ facF,
+                                                   double* __restrict__ facT,
+                                                   double* __restrict__ invC, int* status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const int L = g.L, m = g.m, mp = g.mp;
+  const double* rc = rec + (long long)c * F_REC * mp;
+  const double* dg = rc + (long long)F_DIAG * mp;
+  const double* lo = rc + (long long)F_LO * mp;
+  const double* hi = rc + (long long)F_HI * mp;
+  const double* uC = rc + (long long)(F_U + D_C) * mp;
+  const double* vC = rc + (long long)(F_V + D_C) * mp;
+  double* fA = facF + (long long)c * F_SMW * mp;
+  double* fT = facT ? facT + (long long)c * F_SMW * mp : nullptr;
+  bool bad = false;
+
+  for (int k = m; k < mp; ++k)
+    for (int f = 0; f < F_SMW; ++f) {
+      fA[f * mp + k] = 0.0;
+      if (fT) fT[f * mp + k] = 0.0;
+    }
+
+  // LU of the level band: d_0 = a_0, l_k = sub_{k-1}/d_{k-1},
+  // d_k = a_k - l_k sup_{k-1}.
+  double dprev = 1.0;
+  for (int k = 0; k < L; ++k) {
+    const double l = k == 0 ? 0.0 : lo[k] / dprev;
+    const double t = k == 0 ? 0.0 : l * hi[k - 1];
+    const double d = dg[k] - t;
+    if (!(fabs(d) > 1e-14 * (fabs(dg[k]) + fabs(t)))) bad = true;
+    fA[P_A * mp + k] = -l;
+    fA[P_DINV * mp + k] = 1.0 / d;
+    dprev = d;
+  }
+  for (int k = 0; k < L; ++k) {
+    const double di = fA[P_DINV * mp + k];
+    fA[P_B * mp + k] = k <= L - 2 ? -hi[k] * di : 0.0;
+    if (fT) {
+      fT[P_A * mp + k] = k >= 1 ? -hi[k - 1] * di : 0.0;
+      fT[P_DINV * mp + k] = di;
+      fT[P_B * mp + k] = k <= L - 2 ? fA[P_A * mp + k + 1] : 0.0;
+    }
+  }
+
+  // 3 x 3 flow corner, inverse by cofactors.
+  double F[3][3], Fi[3][3];
+  for (int i = 0; i < 3; ++i) {
+    F[i][i] = dg[L + i];
+    F[i][(i + 2) % 3] = lo[L + i];
+    F[i][(i + 1) % 3] = hi[L + i];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int r1 = (j + 1) % 3, r2 = (j + 2) % 3, c1 = (i + 1) % 3, c2 = (i + 2) % 3;
+      Fi[i][j] = F[r1][c1] * F[r2][c2] - F[r1][c2] * F[r2][c1];  // adjugate
+    }
+  const double det = F[0][0] * Fi[0][0] + F[0][1] * Fi[1][0] + F[0][2] * Fi[2][0];
+  double rn = 1.0;
+  for (int i = 0; i < 3; ++i) rn *= fabs(F[i][0]) + fabs(F[i][1]) + fabs(F[i][2]);
+  if (!(fabs(det) > 1e-14 * rn)) bad = true;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Fi[i][j] /= det;
+  for (int i = 0; i < 3; ++i) {
+    fA[P_A * mp + L + i] = Fi[i][0];
+    fA[P_DINV * mp + L + i] = Fi[i][1];
+    fA[P_B * mp + L + i] = Fi[i][2];
+    if (fT) {
+      fT[P_A * mp + L + i] = Fi[0][i];
+      fT[P_DINV * mp + L + i] = Fi[1][i];
+      fT[P_B * mp + L + i] = Fi[2][i];
+    }
+  }
+
+  // SMW-1: w = A0^{-1} u_cC (forward then backward sweep, then the corner).
+  double* w = fA + P_W * mp;
+  double prev = 0.0;
+  for (int k = 0; k < L; ++k) {
+    prev = uC[k] + fA[P_A * mp + k] * prev;
+    w[k] = prev;
+  }
+  prev = 0.0;
+  for (int k = L - 1; k >= 0; --k) {
+    prev = fA[P_DINV * mp + k] * w[k] + fA[P_B * mp + k] * prev;
+    w[k] = prev;
+  }
+  for (int i = 0; i < 3; ++i)
+    w[L + i] = Fi[i][0] * uC[L] + Fi[i][1] * uC[L + 1] + Fi[i][2] * uC[L + 2];
+  // SMW-2: capacitance C = 1 + v . w
+  double vw = 0.0, vv = 0.0, ww = 0.0;
+  for (int k = 0; k < m; ++k) {
+    vw += vC[k] * w[k];
+    vv += vC[k] * vC[k];
+    ww += w[k] * w[k];
+    fA[P_V * mp + k] = vC[k];
+  }
+  const double C = 1.0 + vw;
+  if (!(fabs(C) > 1e-12 * (1.0 + sqrt(vv * ww)))) bad = true;
+  invC[c] = 1.0 / C;
+
+  if (fT) {  // wt = A0^{-T} v_cC, used by the transposed apply
+    double* wt = fT + P_W * mp;
+    prev = 0.0;
+    for (int k = 0; k < L; ++k) {
+      prev = fT[P_DINV * mp + k] * vC[k] + fT[P_A * mp + k] * prev;
+      wt[k] = prev;
+    }
+    prev = 0.0;
+    for (int k = L - 1; k >= 0; --k) {
+      prev = wt[k] + fT[P_B * mp + k] * prev;
+      wt[k] = prev;
+    }
+    for (int i = 0; i < 3; ++i)
+      wt[L + i] = Fi[0][i] * vC[L] + Fi[1][i] * vC[L + 1] + Fi[2][i] * vC[L + 2];
+    for (int k = 0; k < m; ++k) fT[P_V * mp + k] = uC[k];
+  }
+  if (bad) atomicMin(status, c);
+}
+
+hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
+                            double* invC, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_smw_setup, dim3((g.N + 255) / 256), dim3(256), 0, s, g, rec, facF, facT,
+                     invC, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- apply ----
+// One wavefront per cell, NCH = ceil(m / 64) chunks of 64 unknowns held in
+// registers; NR right-hand sides per launch starting at r0.
+template <typename TV, int NCH, int NR, bool TRANS>
+__global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
+                                                   const TV* __restrict__ invC,
+                                                   const double* __restrict__ rin,
+                                                   double* __restrict__ zout, int r0) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
+  if (c >= g.N) return;
+  const int lane = lane_id();
+  const int L = g.L, m = g.m, mp = g.mp;
+  const TV* fc = fac + (long long)c * F_SMW * mp;
+  TV A[NCH], DI[NCH], B[NCH], W[NCH], V[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const bool in = k < m;
+    A[ch] = in ? fc[P_A * mp + k] : TV(0);
+    DI[ch] = in ? fc[P_DINV * mp + k] : TV(0);
+    B[ch] = in ? fc[P_B * mp + k] : TV(0);
+    W[ch] = in ? fc[P_W * mp + k] : TV(0);
+    V[ch] = in ? fc[P_V * mp + k] : TV(0);
+  }
+  const TV ic = invC[c];
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double* rv = rin + (long long)(r0 + r) * g.n + (long long)c * m;
+    TV R[NCH], Y[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      R[ch] = k < m ? (TV)rv[k] : TV(0);
+    }
+    const TV rf0 = (TV)rv[L], rf1 = (TV)rv[L + 1], rf2 = (TV)rv[L + 2];
+    // forward sweep over the levels: y_k = a_k y_{k-1} + s1_k r_k
+    TV carry = TV(0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      const bool lev = k < L;
+      TV a = lev ? A[ch] : TV(0);
+      TV bb = lev ? (TRANS ? DI[ch] * R[ch] : R[ch]) : TV(0);
+      if (ch * WAVE < L) {
+        scan_affine_up(a, bb);
+        Y[ch] = bb + a * carry;
+        carry = __shfl(Y[ch], WAVE - 1, WAVE);
+      } else {
+        Y[ch] = TV(0);
+      }
+    }
+    // backward sweep: x_k = b_k x_{k+1} + s2_k y_k ; flow lanes: corner inverse
+    carry = TV(0);
+    TV s = TV(0);
+#pragma unroll
+    for (int ch = NCH - 1; ch >= 0; --ch) {
+      const int k = ch * WAVE + lane;
+      const bool lev = k < L;
+      TV a = lev ? B[ch] : TV(0);
+      TV bb = lev ? (TRANS ? Y[ch] : DI[ch] * Y[ch]) : TV(0);
+      TV x0;
+      if (ch * WAVE < L) {
+        scan_affine_down(a, bb);
+        x0 = bb + a * carry;
+        carry = __shfl(x0, 0, WAVE);
+      } else {
+        x0 = TV(0);
+      }
+      if (!lev && k < m) x0 = A[ch] * rf0 + DI[ch] * rf1 + B[ch] * rf2;
+      R[ch] = x0;
+      s += V[ch] * x0;
+    }
+    s = wave_sum(s) * ic;
+    double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      if (k < m) zv[k] = (double)(R[ch] - s * W[ch]);
+    }
+  }
+}
+
+template <typename TV, int NCH, bool TRANS>
+static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, const double* r,
+                                 double* z, int nrhs, hipStream_t s) {
+  const int grid = (g.N + 3) / 4;
+  int r0 = 0;
+  while (r0 < nrhs) {
+    const int rem = nrhs - r0;
+    if (rem >= 4) {
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 4, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      r0 += 4;
+    } else if (rem >= 2) {
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      r0 += 2;
+    } else {
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      r0 += 1;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename TV, bool TRANS>
+static hipError_t launch_apply_nch(const Mesh& g, const TV* fac, const TV* invC, const double* r,
+                                   double* z, int nrhs, hipStream_t s) {
+  const int nch = (g.m + WAVE - 1) / WAVE;
+  switch (nch) {
+    case 1: return launch_apply_t<TV, 1, TRANS>(g, fac, invC, r, z, nrhs, s);
+    case 2: return launch_apply_t<TV, 2, TRANS>(g, fac, invC, r, z, nrhs, s);
+    case 3: return launch_apply_t<TV, 3, TRANS>(g, fac, invC, r, z, nrhs, s);
+    case 4: return launch_apply_t<TV, 4, TRANS>(g, fac, invC, r, z, nrhs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
+                            const double* r, double* z, int nrhs, hipStream_t s) {
+  if (f32)
+    return trans ? launch_apply_nch<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
+                 : launch_apply_nch<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);
+  return trans ? launch_apply_nch<double, true>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s)
+               : launch_apply_nch<double, false>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s);
+}
+
+}  // namespace r1s

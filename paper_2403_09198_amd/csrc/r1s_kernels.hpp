@@ -1,0 +1,74 @@
+// Host-callable kernel launchers of libr1s (all asynchronous on `s`).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "r1s_device.hpp"
+
+namespace r1s {
+
+struct PackIn {
+  const double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
+};
+
+struct GradOut {
+  double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
+};
+
+// packing / casting
+hipError_t launch_pack(const Mesh& g, const PackIn& in, double* rec64, float* rec32, hipStream_t s);
+hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipStream_t s);
+
+// structured matvec (rec: packed record, float when f32)
+hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,
+                         double* y, int nrhs, hipStream_t s);
+hipError_t launch_residual(const Mesh& g, const double* rec, bool trans, const double* b,
+                           const double* x, double* r, int nrhs, hipStream_t s);
+
+// SMW block-Jacobi
+hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
+                            double* invC, int* status, hipStream_t s);
+hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
+                            const double* r, double* z, int nrhs, hipStream_t s);
+hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
+
+// dense-block BSR baseline
+hipError_t launch_bsr_assemble(const Mesh& g, const double* rec, const int* blk_row,
+                               const int* blk_dir, long long nblocks, double* data, hipStream_t s);
+hipError_t launch_bsr_matvec(const Mesh& g, const int* indptr, const int* indices,
+                             const double* data, const double* x, double* y, int nrhs,
+                             hipStream_t s);
+hipError_t launch_bsr_lu_setup(const Mesh& g, const int* diag_block, const double* data,
+                               double* lu, int* piv, int* status, hipStream_t s);
+hipError_t launch_bsr_lu_apply(const Mesh& g, const double* lu, const int* piv, const double* r,
+                               double* z, int nrhs, hipStream_t s);
+
+// Krylov vector kernels (float64).  Vectors of length n per right-hand
+// side; V holds nv basis vectors per right-hand side with stride vstride
+// between vectors and rstride between right-hand sides.
+struct Basis {
+  double* V;
+  long long vstride, rstride;
+};
+int dot_blocks(long long n);
+hipError_t launch_multidot(Basis B, int nv, const double* w, long long wstride, long long n,
+                           int nrhs, double* part, int nblk, bool with_norm, hipStream_t s);
+hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hipStream_t s);
+hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* w,
+                         long long wstride, long long n, int nrhs, hipStream_t s);
+hipError_t launch_update_normalize(Basis B, int nv, const double* h, int hstride,
+                                   const double* nrm2, int nstride, const double* w,
+                                   long long wstride, double* vout, long long n, int nrhs,
+                                   hipStream_t s);
+hipError_t launch_scale(const double* w, long long wstride, const double* inv, double* out,
+                        long long ostride, long long n, int nrhs, hipStream_t s);
+hipError_t launch_combine(Basis B, int nv, const double* y, int ystride, double* out,
+                          long long ostride, long long n, int nrhs, hipStream_t s);
+hipError_t launch_rsub(const double* bv, double* yv, long long n, int nrhs, hipStream_t s);
+hipError_t launch_axpy(const double* alpha, const double* xv, double* yv, long long n, int nrhs,
+                       hipStream_t s);
+
+// gradients
+hipError_t launch_grad(const Mesh& g, const double* rec, const double* lam, const double* x,
+                       int nrhs, const GradOut& out, hipStream_t s);
+
+}  // namespace r1s

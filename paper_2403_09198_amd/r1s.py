@@ -1,0 +1,316 @@
+"""Python binding of the r1s C ABI.
+
+Functions named like the C calls (r1s_mat_size, r1s_matvec, ...) marshal
+torch tensors into pointers and sizes and nothing else: every step runs in
+the HIP kernels of libr1s.so.  torch supplies device memory and the stream.
+The classes below (R1Matrix, SMWPreconditioner, BSRMatrix) keep the
+caller-owned device buffers alive next to the handles.
+
+Vectors are float64 CUDA tensors of shape [nrhs, N, m] or [N, m].
+"""
+import ctypes as C
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import torch
+
+from . import _lib as L
+from ._lib import R1SError, check, lib
+
+FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _need_vec(t, name, n):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() % n != 0 or t.numel() == 0:
+        raise ValueError(f"{name} has {t.numel()} elements, not a multiple of N*m = {n}")
+    return t.numel() // n
+
+
+def _buffer(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv):
+    N, m = nx * ny, Lv + 3
+    shapes = {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
+              "s_nbr": (N, 4, m), "u": (N, 5, m), "v": (N, 5, m)}
+    ins = L.Inputs()
+    for k in FIELDS:
+        t = values[k]
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+            raise TypeError(f"{k} must be a float64 CUDA tensor")
+        if tuple(t.shape) != shapes[k] or not t.is_contiguous():
+            raise ValueError(f"{k} must be contiguous with shape {shapes[k]}")
+        setattr(ins, k, _ptr(t).value)
+    return ins
+
+
+# ----------------------------------------------------- C-named functions ---
+def r1s_last_error() -> str:
+    return lib().r1s_last_error().decode()
+
+
+def r1s_mat_size(nx, ny, Lv, flags=0) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_mat_size(nx, ny, Lv, flags, C.byref(b)))
+    return b.value
+
+
+def r1s_mat_init(nx, ny, Lv, flags, values, mem, stream=None):
+    h = C.c_void_p()
+    ins = _inputs(values, nx, ny, Lv)
+    check(lib().r1s_mat_init(nx, ny, Lv, flags, C.byref(ins), _ptr(mem), mem.numel(),
+                             _stream(stream), C.byref(h)))
+    return h
+
+
+def r1s_mat_update(h, values, nx, ny, Lv, stream=None):
+    ins = _inputs(values, nx, ny, Lv)
+    check(lib().r1s_mat_update(h, C.byref(ins), _stream(stream)))
+
+
+def r1s_mat_storage(h) -> dict:
+    s = L.Storage()
+    check(lib().r1s_mat_storage(h, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in L.Storage._fields_}
+
+
+def r1s_matvec(h, precision, trans, nrhs, x, y, stream=None):
+    check(lib().r1s_matvec(h, precision, int(trans), nrhs, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def r1s_residual(h, nrhs, b, x, r, stream=None):
+    check(lib().r1s_residual(h, nrhs, _ptr(b), _ptr(x), _ptr(r), _stream(stream)))
+
+
+def r1s_prec_size(h, flags=0) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_prec_size(h, flags, C.byref(b)))
+    return b.value
+
+
+def r1s_prec_setup(h, flags, mem, stream=None):
+    p = C.c_void_p()
+    check(lib().r1s_prec_setup(h, flags, _ptr(mem), mem.numel(), _stream(stream), C.byref(p)))
+    return p
+
+
+def r1s_prec_apply(p, precision, trans, nrhs, r, z, stream=None):
+    check(lib().r1s_prec_apply(p, precision, int(trans), nrhs, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def r1s_bsr_size(h) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_bsr_size(h, C.byref(b)))
+    return b.value
+
+
+def r1s_bsr_init(h, mem, stream=None):
+    p = C.c_void_p()
+    check(lib().r1s_bsr_init(h, _ptr(mem), mem.numel(), _stream(stream), C.byref(p)))
+    return p
+
+
+def r1s_bsr_matvec(bh, nrhs, x, y, stream=None):
+    check(lib().r1s_bsr_matvec(bh, nrhs, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def r1s_bsr_prec_size(bh) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_bsr_prec_size(bh, C.byref(b)))
+    return b.value
+
+
+def r1s_bsr_prec_setup(bh, mem, stream=None):
+    p = C.c_void_p()
+    check(lib().r1s_bsr_prec_setup(bh, _ptr(mem), mem.numel(), _stream(stream), C.byref(p)))
+    return p
+
+
+def r1s_gmres_work_size(h, opts: "L.GmresOpts", nrhs) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_gmres_work_size(h, C.byref(opts), nrhs, C.byref(b)))
+    return b.value
+
+
+def r1s_gmres(h, bh, p, opts, nrhs, b, x, work, stream=None):
+    stats = (L.GmresStats * nrhs)()
+    rc = lib().r1s_gmres(h, bh, p, C.byref(opts), nrhs, _ptr(b), _ptr(x), _ptr(work),
+                         work.numel(), stats, _stream(stream))
+    return rc, [{k: getattr(s, k) for k, _ in L.GmresStats._fields_} for s in stats]
+
+
+def r1s_grad(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
+    g = L.Grads()
+    for k in FIELDS:
+        setattr(g, k, _ptr(out[k]).value)
+    check(lib().r1s_grad(h, nrhs, _ptr(lam), _ptr(x), C.byref(g), _stream(stream)))
+
+
+# -------------------------------------------------------------- classes ---
+class R1Matrix:
+    """Structured block r1-sparse Jacobian on one GPU (packed, caller memory)."""
+
+    def __init__(self, nx, ny, L_levels, values: Dict[str, torch.Tensor], keep_f32=False,
+                 stream=None):
+        self.nx, self.ny, self.L = nx, ny, L_levels
+        self.m = L_levels + 3
+        self.N = nx * ny
+        self.n = self.N * self.m
+        self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
+        dev = values["s_diag"].device
+        self.device = dev
+        self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.flags), dev)
+        self.h = r1s_mat_init(nx, ny, L_levels, self.flags, values, self.mem, stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().r1s_mat_destroy(h)
+            self.h = None
+
+    def update(self, values, stream=None):
+        r1s_mat_update(self.h, values, self.nx, self.ny, self.L, stream)
+
+    def storage(self):
+        return r1s_mat_storage(self.h)
+
+    def matvec(self, x, trans=False, precision="f64", out=None, stream=None):
+        nrhs = _need_vec(x, "x", self.n)
+        y = torch.empty_like(x) if out is None else out
+        _need_vec(y, "out", self.n)
+        prec = L.R1S_F32 if precision == "f32" else L.R1S_F64
+        r1s_matvec(self.h, prec, trans, nrhs, x, y, stream)
+        return y
+
+    def residual(self, b, x, out=None, stream=None):
+        nrhs = _need_vec(b, "b", self.n)
+        _need_vec(x, "x", self.n)
+        r = torch.empty_like(b) if out is None else out
+        r1s_residual(self.h, nrhs, b, x, r, stream)
+        return r
+
+
+class SMWPreconditioner:
+    """Block-Jacobi through the Sherman-Morrison-Woodbury identity."""
+
+    def __init__(self, A: R1Matrix, keep_f32=False, with_trans=False, stream=None):
+        self.A = A
+        self.flags = (L.R1S_KEEP_F32 if keep_f32 else 0) | (L.R1S_WITH_TRANS if with_trans else 0)
+        self.mem = _buffer(r1s_prec_size(A.h, self.flags), A.device)
+        self.h = r1s_prec_setup(A.h, self.flags, self.mem, stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().r1s_prec_destroy(h)
+            self.h = None
+
+    def apply(self, r, trans=False, precision="f64", out=None, stream=None):
+        nrhs = _need_vec(r, "r", self.A.n)
+        z = torch.empty_like(r) if out is None else out
+        prec = L.R1S_F32 if precision == "f32" else L.R1S_F64
+        r1s_prec_apply(self.h, prec, trans, nrhs, r, z, stream)
+        return z
+
+
+class BSRMatrix:
+    """Dense-block BSR copy of an R1Matrix (the quadratic-in-m baseline)."""
+
+    def __init__(self, A: R1Matrix, stream=None):
+        self.A = A
+        self.mem = _buffer(r1s_bsr_size(A.h), A.device)
+        self.h = r1s_bsr_init(A.h, self.mem, stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().r1s_bsr_destroy(h)
+            self.h = None
+
+    def matvec(self, x, out=None, stream=None):
+        nrhs = _need_vec(x, "x", self.A.n)
+        y = torch.empty_like(x) if out is None else out
+        r1s_bsr_matvec(self.h, nrhs, x, y, stream)
+        return y
+
+
+class DenseLUPreconditioner:
+    """Classical block-Jacobi: LU with partial pivoting of each dense block."""
+
+    def __init__(self, B: BSRMatrix, stream=None):
+        self.B = B
+        self.A = B.A
+        self.mem = _buffer(r1s_bsr_prec_size(B.h), B.A.device)
+        self.h = r1s_bsr_prec_setup(B.h, self.mem, stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().r1s_prec_destroy(h)
+            self.h = None
+
+    def apply(self, r, out=None, stream=None):
+        nrhs = _need_vec(r, "r", self.A.n)
+        z = torch.empty_like(r) if out is None else out
+        r1s_prec_apply(self.h, L.R1S_F64, False, nrhs, r, z, stream)
+        return z
+
+
+@dataclass
+class GmresResult:
+    x: torch.Tensor
+    stats: List[dict]
+    status: int
+
+    @property
+    def converged(self):
+        return self.status == L.R1S_OK
+
+
+def gmres(A: R1Matrix, M, b, x0=None, restart=50, rtol=1e-10, max_cycles=200, trans=False,
+          op="structured", B: Optional[BSRMatrix] = None, mode="f64", inner_rtol=1e-6,
+          max_outer=10, raise_on_noconv=True, work=None, stream=None) -> GmresResult:
+    """Restarted right-preconditioned GMRES through r1s_gmres."""
+    nrhs = _need_vec(b, "b", A.n)
+    opts = L.GmresOpts(restart=restart, max_cycles=max_cycles, rtol=rtol, trans=int(trans),
+                       x0_given=int(x0 is not None),
+                       op=L.R1S_OP_BSR if op == "bsr" else L.R1S_OP_STRUCTURED,
+                       mode=L.R1S_MODE_MIXED_IR if mode == "mixed" else L.R1S_MODE_F64,
+                       inner_rtol=inner_rtol, max_outer=max_outer)
+    x = torch.empty_like(b) if x0 is None else x0.clone()
+    need = r1s_gmres_work_size(A.h, opts, nrhs)
+    if work is None or work.numel() < need:
+        work = _buffer(need, A.device)
+    rc, stats = r1s_gmres(A.h, B.h if B is not None else C.c_void_p(0), M.h, opts, nrhs, b, x,
+                          work, stream)
+    if rc != L.R1S_OK and (raise_on_noconv or rc != L.R1S_ERR_NOCONV):
+        raise R1SError(rc, r1s_last_error())
+    return GmresResult(x, stats, rc)
+
+
+def grad(A: R1Matrix, lam, x, stream=None) -> Dict[str, torch.Tensor]:
+    """Gradients w.r.t. the structured arrays given lambda = J^{-T} dLoss/dx."""
+    nrhs = _need_vec(lam, "lambda", A.n)
+    _need_vec(x, "x", A.n)
+    N, m, Lv = A.N, A.m, A.L
+    shapes = {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
+              "s_nbr": (N, 4, m), "u": (N, 5, m), "v": (N, 5, m)}
+    out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device) for k in FIELDS}
+    r1s_grad(A.h, nrhs, lam, x, out, stream)
+    return out

@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_2403_09198_amd import _lib as L
+
+HEADER = os.path.join(ROOT, "include", "r1s.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(r1s_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_bound_calls():
+    assert _declared() == sorted(L.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _rc(code_call):
+    rc = code_call
+    msg = L.lib().r1s_last_error().decode()
+    return rc, msg
+
+
+def test_size_validation():
+    lib = L.lib()
+    b = C.c_size_t()
+    assert lib.r1s_mat_size(0, 4, 4, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert "must be >= 1" in lib.r1s_last_error().decode()
+    assert lib.r1s_mat_size(4, 4, 0, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 254, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, 0, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, 0x10, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 253, 1, C.byref(b)) == L.R1S_OK
+    # packed rows are padded to 8 values: 17 rows of 256 doubles + floats
+    assert b.value >= 16 * 17 * 256 * 12
+
+
+def test_size_is_linear_in_cells():
+    lib = L.lib()
+    a, b = C.c_size_t(), C.c_size_t()
+    lib.r1s_mat_size(64, 32, 61, 0, C.byref(a))
+    lib.r1s_mat_size(128, 32, 61, 0, C.byref(b))
+    assert abs(b.value - 2 * a.value) <= 512
+
+
+def test_init_rejects_bad_arguments_before_device_work():
+    lib = L.lib()
+    ins = L.Inputs()
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert lib.r1s_mat_init(4, 4, 4, 0, None, fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert "is NULL" in lib.r1s_last_error().decode()
+    for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"):
+        setattr(ins, k, 1 << 21)
+    ins.u = (1 << 21) + 4  # misaligned
+    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert "aligned" in lib.r1s_last_error().decode()
+    ins.u = 1 << 21
+    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 16, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert "mem_bytes" in lib.r1s_last_error().decode()
+    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), C.c_void_p((1 << 20) + 8), 1 << 30, None,
+                            C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, None) == L.R1S_ERR_ARG
+
+
+def test_null_handles_rejected():
+    lib = L.lib()
+    fake = C.c_void_p(1 << 20)
+    assert lib.r1s_matvec(None, 0, 0, 1, fake, fake, None) == L.R1S_ERR_ARG
+    assert lib.r1s_prec_apply(None, 0, 0, 1, fake, fake, None) == L.R1S_ERR_ARG
+    assert lib.r1s_bsr_matvec(None, 1, fake, fake, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_storage(None, None) == L.R1S_ERR_ARG
+    assert lib.r1s_grad(None, 1, fake, fake, None, None) == L.R1S_ERR_ARG
+    opts = L.GmresOpts(restart=10, max_cycles=5, rtol=1e-8)
+    assert lib.r1s_gmres(None, None, None, C.byref(opts), 1, fake, fake, fake, 1 << 30, None,
+                         None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_destroy(None) == L.R1S_OK
+
+
+def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        L.lib()

@@ -132,3 +132,13 @@ def test_generator_distributions_and_dominance():
     # determinism
     q = gen.make_problem(nx, ny, L, seed=0)
     assert all(np.array_equal(p[k], q[k]) for k in gen.FIELDS)
+
+
+def test_transpose_rows_match_full_transpose():
+    nx, ny, L = 6, 5, 3
+    p = gen.make_problem(nx, ny, L, seed=12)
+    x = gen.make_vector(nx, ny, L, nrhs=2, seed=3)
+    full = ops.matvec_T(p, nx, ny, L, x)
+    cells = [0, 5, 7, 14, 29, 24]
+    assert np.allclose(ops.matvec_T_rows(p, nx, ny, L, x, cells), full[:, cells], rtol=1e-14,
+                       atol=1e-14)
