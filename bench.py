@@ -1,0 +1,261 @@
+"""Benchmark of the r1-sparse hot path on one MI355X.
+
+A step is one application of the operator pair the metric names, on the
+256 x 128 mesh with L = 61 levels (m = 64), float64:
+
+    y = J x        (structured matvec kernel)
+    z = M y        (SMW block-Jacobi apply kernel)
+
+`value` is the algorithmic HBM bytes of the pair (stored structural values
+plus input and output vectors, section-3 counts) per second over the timed
+steps.  Per-kernel times come from HIP events on the launch stream.  The
+same JSON line carries the float32-preconditioner pair, the adjoint pair
+(J^T x, M^T y), the dense-block BSR baseline pair on the same matrix, a
+cold-cache variant, a full GMRES solve, a device copy ceiling and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "J*x + SMW precond apply GB/s (%HBM peak); FP32-precond & adjoint vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pair_bytes(N, B, m, nrhs=1, value_bytes=8):
+    """Algorithmic bytes of one matvec and one SMW apply (values + vectors)."""
+    struct_vals = N * (3 * m - 2) + (B - N) * m + 2 * B * m
+    mv = value_bytes * struct_vals + 8 * 2 * nrhs * N * m
+    ap = value_bytes * N * (5 * m - 1) + 8 * 2 * nrhs * N * m
+    return mv, ap
+
+
+def bsr_pair_bytes(N, B, m):
+    return 8 * B * m * m + 8 * 2 * N * m, 8 * N * m * m + 8 * 2 * N * m
+
+
+def time_pair(torch, f1, f2, steps, warmup, flush=None):
+    """Run f1; f2 `steps` times after `warmup`; returns (wall s, ev1 ms list, ev2 ms list)."""
+    for _ in range(warmup):
+        f1()
+        f2()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1, e2 in evs:
+        if flush is not None:
+            flush()
+        e0.record()
+        f1()
+        e1.record()
+        f2()
+        e2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t1 = [a.elapsed_time(b) for a, b, _ in evs]
+    t2 = [b.elapsed_time(c) for _, b, c in evs]
+    return wall, t1, t2
+
+
+def cpu_baseline(p, nx, ny, L, budget_s=12.0):
+    """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
+    sample of block rows (blocks assembled and factored beforehand), repeated
+    for about `budget_s` seconds; GB/s of the same algorithmic bytes."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import assemble, blockjacobi, ops
+
+    N, m = nx * ny, L + 3
+    ncell = min(N, 1024)
+    cells = list(range(ncell))
+    x = np.random.default_rng(5).standard_normal((1, N, m))
+    indptr, indices, data, rows = assemble.assemble_bsr(p, nx, ny, L, cells)
+    D = assemble.diagonal_blocks(p, nx, ny, L, cells)
+    LU, piv = blockjacobi.lu_factor(D)
+    B_s = len(indices)
+    mv, ap = pair_bytes(ncell, B_s, m)
+    reps = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while True:
+            y = ops.bsr_matvec(indptr, indices, data, rows, x, N)
+            blockjacobi.lu_solve(LU, piv, y[0])
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    return {
+        "value": round((mv + ap) * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{ncell} of {N} block rows ({B_s} dense blocks, m={m}) of the same "
+                   f"workload, dense-block matvec + dense-LU block-Jacobi apply, blocks "
+                   f"assembled and factored beforehand, {reps} passes in {el:.1f} s, "
+                   f"1 BLAS thread"),
+        "seconds": round(el, 2),
+        "host": platform.processor() or platform.machine(),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="mesh256x128_L61")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the FP64 pair (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2403_09198_amd import gen, r1s
+
+    w = gen.WORKLOADS[args.workload]
+    nx, ny, L, m, N = w.nx, w.ny, w.L, w.m, w.N
+    B = 5 * N - 2 * nx - 2 * ny
+    dev = "cuda:0"
+    log(f"workload {w.name}: mesh {nx}x{ny}, L={L}, m={m}, blocks={B}")
+    p = gen.make_problem(nx, ny, L, seed=w.seed, inv_dt=w.inv_dt)
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
+    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True)
+    M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
+    del vals
+    x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+
+    mv_b, ap_b = pair_bytes(N, B, m)
+    steps, warm = args.steps, args.warmup
+    wall, t_mv, t_ap = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
+                                 steps, warm)
+    ms_step = wall / steps * 1e3
+    value = (mv_b + ap_b) / (wall / steps) / 1e9
+    mv_ms = float(np.mean(t_mv))
+    ap_ms = float(np.mean(t_ap))
+    log(f"fp64 pair: {ms_step * 1e3:.1f} us/step, matvec {mv_ms * 1e3:.1f} us, "
+        f"apply {ap_ms * 1e3:.1f} us, {value:.0f} GB/s")
+    ach = mv_b / (mv_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": steps, "warmup": warm, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": nx, "ny": ny, "L": L, "m": m, "nrhs": 1,
+                   "step": "y = J x then z = M y (SMW block-Jacobi), float64",
+                   "bytes_per_step": mv_b + ap_b},
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "cell_updates_per_s": round(N / (wall / steps), 1),
+        "roofline": {"bound": "hbm", "kernel": "k_matvec (float64, J x)",
+                     "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(mv_ms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": mv_b},
+        "kernels_us": {"matvec_f64": round(mv_ms * 1e3, 2), "smw_apply_f64": round(ap_ms * 1e3, 2)},
+        "kernel_gbs": {"matvec_f64": round(ach, 1),
+                       "smw_apply_f64": round(ap_b / (ap_ms / 1e3) / 1e9, 1)},
+    }
+
+    if not args.no_extras:
+        # float32 values + accumulation (vectors stay float64)
+        mv32, ap32 = pair_bytes(N, B, m, value_bytes=4)
+        wall32, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y, precision="f32"),
+                                   lambda: M.apply(y, out=z, precision="f32"), steps, warm)
+        out["fp32_pair"] = {
+            "gbs": round((mv32 + ap32) / (wall32 / steps) / 1e9, 1),
+            "us_per_step": round(wall32 / steps * 1e6, 2),
+            "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
+            "apply_us": round(float(np.mean(t2)) * 1e3, 2),
+            "speedup_vs_fp64": round(wall / wall32, 3)}
+        # adjoint pair J^T x, M^T y (same bytes as forward)
+        wallT, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y, trans=True),
+                                  lambda: M.apply(y, out=z, trans=True), steps, warm)
+        out["adjoint_pair"] = {
+            "gbs": round((mv_b + ap_b) / (wallT / steps) / 1e9, 1),
+            "us_per_step": round(wallT / steps * 1e6, 2),
+            "matvec_T_us": round(float(np.mean(t1)) * 1e3, 2),
+            "apply_T_us": round(float(np.mean(t2)) * 1e3, 2),
+            "ratio_vs_fp64": round(wallT / wall, 3)}
+        # cold: a 1 GiB buffer is read before every step (a read leaves clean
+        # lines, so no write-back of the flush competes with the timed kernels)
+        scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        sink = torch.empty((), dtype=torch.float64, device=dev)
+        _, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
+                              min(steps, 50), 5, flush=lambda: torch.sum(scratch, out=sink))
+        cold = (float(np.mean(t1)) + float(np.mean(t2))) / 1e3
+        out["cold_fp64_pair"] = {"gbs": round((mv_b + ap_b) / cold / 1e9, 1),
+                                 "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
+                                 "apply_us": round(float(np.mean(t2)) * 1e3, 2)}
+        # device copy ceiling (read + write bytes)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        cp = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        out["copy_ceiling_gbs"] = round(cp, 1)
+        out["pct_of_copy_ceiling"] = round(100 * value / cp, 2)
+        del scratch, src, dst
+        # dense-block BSR baseline on the same matrix
+        try:
+            Bm = r1s.BSRMatrix(A)
+            P = r1s.DenseLUPreconditioner(Bm)
+            bmv, bap = bsr_pair_bytes(N, B, m)
+            wallB, t1, t2 = time_pair(torch, lambda: Bm.matvec(x, out=y), lambda: P.apply(y, out=z),
+                                      max(10, steps // 10), 3)
+            out["bsr_pair"] = {
+                "gbs": round((bmv + bap) / (wallB / max(10, steps // 10)) / 1e9, 1),
+                "us_per_step": round(wallB / max(10, steps // 10) * 1e6, 2),
+                "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
+                "lu_apply_us": round(float(np.mean(t2)) * 1e3, 2),
+                "stored_values": B * m * m,
+                "speedup_structured_vs_bsr": round((wallB / max(10, steps // 10)) / (wall / steps), 2)}
+            del Bm, P
+        except Exception as e:  # report, never hide
+            out["bsr_pair"] = {"error": str(e)}
+        # full GMRES(50) solve to 1e-10 (float64) and the mixed-precision solve
+        b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
+        for mode in ("f64", "mixed"):
+            r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol, mode=mode)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol, mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[f"solve_{mode}"] = {"ms": round(el * 1e3, 2), "iters": res.stats[0]["iters"],
+                                    "outer": res.stats[0]["outer"],
+                                    "rel_residual": res.stats[0]["rel_residual"]}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(p, nx, ny, L)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
