@@ -201,7 +201,7 @@ def main():
         scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         sink = torch.empty((), dtype=torch.float64, device=dev)
         _, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
-                              min(steps, 50), 5, flush=lambda: torch.sum(scratch, out=sink))
+                              min(steps, 50), 5, flush=lambda: torch.sum(scratch, dim=0, out=sink))
         cold = (float(np.mean(t1)) + float(np.mean(t2))) / 1e3
         out["cold_fp64_pair"] = {"gbs": round((mv_b + ap_b) / cold / 1e9, 1),
                                  "matvec_us": round(float(np.mean(t1)) * 1e3, 2),

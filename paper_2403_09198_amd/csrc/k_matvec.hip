@@ -65,104 +65,145 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
 }
 
 // --------------------------------------------------------------- matvec ----
-// TV: value / accumulation type.  NR right-hand sides per launch, starting
-// at rhs r0.  RESID: write b - J x instead of J x.
-template <typename TV, int NR, bool TRANS, bool RESID>
+// TV: value / accumulation type.  NCH = ceil(m / 64) chunks of 64 unknowns,
+// NR right-hand sides per launch starting at rhs r0.  RESID: write b - J x.
+//
+// Every load of a wave is independent of the reductions, so all of them are
+// issued before the first wait: missing neighbours (mesh boundary) read the
+// cell's own, valid addresses and are masked out of the sums instead of
+// being skipped by a branch.  Lanes past m read element m-1 and are masked.
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID>
 __global__ __launch_bounds__(256) void k_matvec(Mesh g, const TV* __restrict__ rec,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ y, int r0) {
+  constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
   if (c >= g.N) return;
   const int lane = lane_id();
   const int m = g.m, mp = g.mp, L = g.L;
   const long long RS = (long long)F_REC * mp;
-  int nb[5];
+  int nb[5], nbc[5];
+  bool ex[5];
   neighbours(g, c, nb);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    ex[d] = nb[d] >= 0;
+    nbc[d] = ex[d] ? nb[d] : c;
+  }
   const TV* rc = rec + (long long)c * RS;
+  // coefficient row of phase 1, output row of phase 2, neighbour diagonal
+  const TV* prow[5];
+  const TV* urow[5];
+  const TV* nrow[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    if (!TRANS) {
+      prow[d] = rc + (long long)(F_V + d) * mp;
+      urow[d] = rc + (long long)(F_U + d) * mp;
+      nrow[d] = rc + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : d)) * mp;
+    } else {
+      const TV* rn = rec + (long long)nbc[d] * RS;
+      prow[d] = rn + (long long)(F_U + opposite(d)) * mp;
+      urow[d] = rn + (long long)(F_V + opposite(d)) * mp;
+      nrow[d] = rn + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : opposite(d))) * mp;
+    }
+  }
   const double* xr = x + (long long)r0 * g.n;
 
-  // Phase 1: one coefficient per block of the row (forward: v_{c,d} . x_nb;
-  // transpose: u_{nb,opp d} . x_nb).
+  TV pv[5][NCH], xv[NR][5][NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const int kk = k < m ? k : m - 1;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      pv[d][ch] = prow[d][kk];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        xv[r][d][ch] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
+    }
+  }
+
+  // sparse part of the row: diagonal, level band / flow corner partners,
+  // neighbour diagonals, and the u rows
+  TV dg[NCH], ca[NCH], cb[NCH], nv[5][NCH], uv[5][NCH], xa[NR][NCH], xb[NR][NCH];
+  auto load_sparse = [&](int ch) {
+    const int k = ch * WAVE + lane;
+    const int kk = k < m ? k : m - 1;
+    int pa, pb;
+    bool va, vb;
+    if (kk < L) {
+      va = kk >= 1; pa = va ? kk - 1 : kk;
+      vb = kk <= L - 2; pb = vb ? kk + 1 : kk;
+    } else {
+      const int i = kk - L;
+      pa = L + (i + 2) % 3; va = true;
+      pb = L + (i + 1) % 3; vb = true;
+    }
+    dg[ch] = rc[(long long)F_DIAG * mp + kk];
+    if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
+      ca[ch] = rc[(long long)F_LO * mp + kk];
+      cb[ch] = rc[(long long)F_HI * mp + kk];
+    } else {       // column k of S_cc: hi of row pa, lo of row pb
+      const TV ta = rc[(long long)F_HI * mp + pa];
+      const TV tb = rc[(long long)F_LO * mp + pb];
+      ca[ch] = va ? ta : TV(0);
+      cb[ch] = vb ? tb : TV(0);
+    }
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      if (d != D_C) nv[d][ch] = nrow[d][kk];
+      uv[d][ch] = urow[d][kk];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
+      xa[r][ch] = (TV)xv_c[pa];
+      xb[r][ch] = (TV)xv_c[pb];
+    }
+  };
+  if (PRELOAD) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) load_sparse(ch);
+    // keep these loads in flight during the reductions (one memory round
+    // trip per wave instead of two)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // pair coefficients: forward v_{c,d} . x_nb, transpose u_{nb,opp d} . x_nb
   TV acc[NR][5];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int d = 0; d < 5; ++d) acc[r][d] = TV(0);
-  for (int k0 = 0; k0 < m; k0 += WAVE) {
-    const int k = k0 + lane;
-    if (k < m) {
+    for (int d = 0; d < 5; ++d) {
+      TV s = TV(0);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (ch * WAVE + lane < m) s += pv[d][ch] * xv[r][d][ch];
+      s = wave_sum_u(s);
+      acc[r][d] = ex[d] ? s : TV(0);
+    }
+
+  // Lanes past m computed exactly what lane m-1 computes (all their indices
+  // are clamped), so every lane stores to its clamped index: duplicate lanes
+  // write identical values and no branch is needed around the stores.
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (!PRELOAD) load_sparse(ch);
+    const int k = ch * WAVE + lane;
+    const int kk = k < m ? k : m - 1;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      TV t = dg[ch] * xv[r][D_C][ch] + ca[ch] * xa[r][ch] + cb[ch] * xb[r][ch];
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
-        if (nb[d] < 0) continue;
-        const TV* src = TRANS ? rec + (long long)nb[d] * RS + (long long)(F_U + opposite(d)) * mp
-                              : rc + (long long)(F_V + d) * mp;
-        const TV vv = src[k];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-          acc[r][d] += vv * (TV)xr[(long long)r * g.n + (long long)nb[d] * m + k];
+        if (d != D_C && ex[d]) t += nv[d][ch] * xv[r][d][ch];
+        t += uv[d][ch] * acc[r][d];
       }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int d = 0; d < 5; ++d) acc[r][d] = wave_sum(acc[r][d]);
-
-  // Phase 2: sparse part + rank-one accumulation, one pass over the row.
-  for (int k0 = 0; k0 < m; k0 += WAVE) {
-    const int k = k0 + lane;
-    if (k >= m) continue;
-    // partner columns of the diagonal block: level band k-1 / k+1, or the
-    // two other flow unknowns
-    int pa, pb;
-    bool va, vb;
-    if (k < L) {
-      pa = k - 1; va = k >= 1;
-      pb = k + 1; vb = k <= L - 2;
-    } else {
-      const int i = k - L;
-      pa = L + (i + 2) % 3; va = true;
-      pb = L + (i + 1) % 3; vb = true;
-    }
-    const TV dg = rc[(long long)F_DIAG * mp + k];
-    TV ca, cb;
-    if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
-      ca = rc[(long long)F_LO * mp + k];
-      cb = rc[(long long)F_HI * mp + k];
-    } else {       // column k of S_cc: hi of row pa, lo of row pb
-      ca = va ? rc[(long long)F_HI * mp + pa] : TV(0);
-      cb = vb ? rc[(long long)F_LO * mp + pb] : TV(0);
-    }
-    if (!va) pa = k;
-    if (!vb) pb = k;
-    TV t[NR];
-    const long long xc = (long long)c * m;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double* xv = xr + (long long)r * g.n + xc;
-      t[r] = dg * (TV)xv[k] + ca * (TV)xv[pa] + cb * (TV)xv[pb];
-    }
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      if (nb[d] < 0) continue;
-      if (d != D_C) {
-        const TV cn = TRANS ? rec[(long long)nb[d] * RS + (long long)(F_NBR + nbr_slot(opposite(d))) * mp + k]
-                            : rc[(long long)(F_NBR + nbr_slot(d)) * mp + k];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-          t[r] += cn * (TV)xr[(long long)r * g.n + (long long)nb[d] * m + k];
-      }
-      const TV uu = TRANS ? rec[(long long)nb[d] * RS + (long long)(F_V + opposite(d)) * mp + k]
-                          : rc[(long long)(F_U + d) * mp + k];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) t[r] += uu * acc[r][d];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const long long o = (long long)(r0 + r) * g.n + xc + k;
-      y[o] = RESID ? b[o] - (double)t[r] : (double)t[r];
+      const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
+      y[o] = RESID ? b[o] - (double)t : (double)t;
     }
   }
 }
@@ -192,26 +233,44 @@ hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipSt
   return hipGetLastError();
 }
 
-template <typename TV, bool TRANS, bool RESID>
-static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
-                              double* y, int nrhs, hipStream_t s) {
+template <typename TV, int NCH, bool TRANS, bool RESID>
+static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
+                          double* y, int nrhs, hipStream_t s) {
   const int grid = (g.N + 3) / 4;
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
-    if (rem >= 8) {
-      hipLaunchKernelGGL((k_matvec<TV, 8, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
-      r0 += 8;
-    } else if (rem >= 4) {
-      hipLaunchKernelGGL((k_matvec<TV, 4, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
-      r0 += 4;
-    } else if (rem >= 2) {
-      hipLaunchKernelGGL((k_matvec<TV, 2, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+    if constexpr (NCH <= 2) {
+      if (rem >= 8) {
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+        r0 += 8;
+        continue;
+      }
+      if (rem >= 4) {
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+        r0 += 4;
+        continue;
+      }
+    }
+    if (rem >= 2) {
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_matvec<TV, 1, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
       r0 += 1;
     }
+  }
+}
+
+template <typename TV, bool TRANS, bool RESID>
+static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
+                              double* y, int nrhs, hipStream_t s) {
+  switch ((g.m + WAVE - 1) / WAVE) {
+    case 1: launch_mv_nch<TV, 1, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
+    case 2: launch_mv_nch<TV, 2, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
+    case 3: launch_mv_nch<TV, 3, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
+    case 4: launch_mv_nch<TV, 4, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

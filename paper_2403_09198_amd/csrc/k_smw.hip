@@ -161,7 +161,9 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 
 // ---------------------------------------------------------------- apply ----
 // One wavefront per cell, NCH = ceil(m / 64) chunks of 64 unknowns held in
-// registers; NR right-hand sides per launch starting at r0.
+// registers; NR right-hand sides per launch starting at r0.  Scans and the
+// reduction run on DPP lane moves; all loads are issued before the first
+// scan (lanes past m read element m-1 and are masked).
 template <typename TV, int NCH, int NR, bool TRANS>
 __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
                                                    const TV* __restrict__ invC,
@@ -174,28 +176,30 @@ __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict_
   const int L = g.L, m = g.m, mp = g.mp;
   const TV* fc = fac + (long long)c * F_SMW * mp;
   TV A[NCH], DI[NCH], B[NCH], W[NCH], V[NCH];
+  TV R[NR][NCH], RF[NR][3];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int k = ch * WAVE + lane;
-    const bool in = k < m;
-    A[ch] = in ? fc[P_A * mp + k] : TV(0);
-    DI[ch] = in ? fc[P_DINV * mp + k] : TV(0);
-    B[ch] = in ? fc[P_B * mp + k] : TV(0);
-    W[ch] = in ? fc[P_W * mp + k] : TV(0);
-    V[ch] = in ? fc[P_V * mp + k] : TV(0);
+    const int kk = k < m ? k : m - 1;
+    A[ch] = fc[P_A * mp + kk];
+    DI[ch] = fc[P_DINV * mp + kk];
+    B[ch] = fc[P_B * mp + kk];
+    W[ch] = fc[P_W * mp + kk];
+    V[ch] = fc[P_V * mp + kk];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      R[r][ch] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + kk];
   }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      RF[r][i] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + L + i];
   const TV ic = invC[c];
 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const double* rv = rin + (long long)(r0 + r) * g.n + (long long)c * m;
-    TV R[NCH], Y[NCH];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      const int k = ch * WAVE + lane;
-      R[ch] = k < m ? (TV)rv[k] : TV(0);
-    }
-    const TV rf0 = (TV)rv[L], rf1 = (TV)rv[L + 1], rf2 = (TV)rv[L + 2];
+    TV Y[NCH];
     // forward sweep over the levels: y_k = a_k y_{k-1} + s1_k r_k
     TV carry = TV(0);
 #pragma unroll
@@ -203,11 +207,11 @@ __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict_
       const int k = ch * WAVE + lane;
       const bool lev = k < L;
       TV a = lev ? A[ch] : TV(0);
-      TV bb = lev ? (TRANS ? DI[ch] * R[ch] : R[ch]) : TV(0);
+      TV bb = lev ? (TRANS ? DI[ch] * R[r][ch] : R[r][ch]) : TV(0);
       if (ch * WAVE < L) {
-        scan_affine_up(a, bb);
+        scan_affine_up_dpp(a, bb);
         Y[ch] = bb + a * carry;
-        carry = __shfl(Y[ch], WAVE - 1, WAVE);
+        carry = readlane(Y[ch], WAVE - 1);
       } else {
         Y[ch] = TV(0);
       }
@@ -215,6 +219,7 @@ __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict_
     // backward sweep: x_k = b_k x_{k+1} + s2_k y_k ; flow lanes: corner inverse
     carry = TV(0);
     TV s = TV(0);
+    TV X0[NCH];
 #pragma unroll
     for (int ch = NCH - 1; ch >= 0; --ch) {
       const int k = ch * WAVE + lane;
@@ -223,22 +228,23 @@ __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict_
       TV bb = lev ? (TRANS ? Y[ch] : DI[ch] * Y[ch]) : TV(0);
       TV x0;
       if (ch * WAVE < L) {
-        scan_affine_down(a, bb);
+        scan_affine_down_dpp(a, bb);
         x0 = bb + a * carry;
-        carry = __shfl(x0, 0, WAVE);
+        carry = readlane(x0, 0);
       } else {
         x0 = TV(0);
       }
-      if (!lev && k < m) x0 = A[ch] * rf0 + DI[ch] * rf1 + B[ch] * rf2;
-      R[ch] = x0;
+      const TV xf = A[ch] * RF[r][0] + DI[ch] * RF[r][1] + B[ch] * RF[r][2];
+      x0 = lev ? x0 : (k < m ? xf : TV(0));
+      X0[ch] = x0;
       s += V[ch] * x0;
     }
-    s = wave_sum(s) * ic;
+    s = wave_sum_u(s) * ic;
     double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int k = ch * WAVE + lane;
-      if (k < m) zv[k] = (double)(R[ch] - s * W[ch]);
+      if (k < m) zv[k] = (double)(X0[ch] - s * W[ch]);
     }
   }
 }

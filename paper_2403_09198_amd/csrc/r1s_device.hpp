@@ -104,4 +104,105 @@ __device__ inline void scan_affine_down(T& a, T& b) {
   }
 }
 
+// ------------------------------------------------ DPP wave primitives ----
+// Cross-lane moves in the VALU (data-parallel primitives) instead of LDS
+// permutes.  A 64-bit value moves as two 32-bit halves with the same control.
+// Rows are groups of 16 lanes; combining the four row results goes through
+// v_readlane (wave-uniform values), so no row-broadcast control is needed.
+constexpr int DPP_ROW_SHL = 0x100;   // + n: lane l reads lane l + n of its row
+constexpr int DPP_ROW_SHR = 0x110;   // + n: lane l reads lane l - n of its row
+constexpr int DPP_QP_1032 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int DPP_QP_2301 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ inline float dpp(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp(double old, double v) {
+  const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double readlane(double v, int l) {
+  const long long s = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)s, l);
+  const int hi = __builtin_amdgcn_readlane((int)(s >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, returned wave-uniform.  Fixed association order,
+// so the result is bitwise reproducible.
+template <typename T>
+__device__ inline T wave_sum_u(T v) {
+  v += dpp<DPP_QP_1032>(T(0), v);
+  v += dpp<DPP_QP_2301>(T(0), v);
+  v += dpp<DPP_HALF_MIRROR>(T(0), v);
+  v += dpp<DPP_MIRROR>(T(0), v);  // every lane holds its row's sum
+  return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
+// Inclusive scan of affine maps y -> a*y + b along increasing lane index
+// (lane l ends with the composition of lanes 0..l).  Within rows by DPP
+// shifts with the identity map (1, 0) shifted in; then every row is prefixed
+// with the composition of the rows below it.
+template <typename T>
+__device__ inline void scan_affine_up_dpp(T& a, T& b) {
+#define R1S_SCAN_STEP(N)                        \
+  {                                             \
+    const T ap = dpp<DPP_ROW_SHR + N>(T(1), a); \
+    const T bp = dpp<DPP_ROW_SHR + N>(T(0), b); \
+    b = a * bp + b;                             \
+    a = a * ap;                                 \
+  }
+  R1S_SCAN_STEP(1) R1S_SCAN_STEP(2) R1S_SCAN_STEP(4) R1S_SCAN_STEP(8)
+#undef R1S_SCAN_STEP
+  const T a0 = readlane(a, 15), b0 = readlane(b, 15);
+  const T a1 = readlane(a, 31), b1 = readlane(b, 31);
+  const T a2 = readlane(a, 47), b2 = readlane(b, 47);
+  // prefixes entering rows 1, 2, 3
+  const T pa1 = a0, pb1 = b0;
+  const T pa2 = a1 * pa1, pb2 = a1 * pb1 + b1;
+  const T pa3 = a2 * pa2, pb3 = a2 * pb2 + b2;
+  const int row = lane_id() >> 4;
+  const T pa = row == 0 ? T(1) : row == 1 ? pa1 : row == 2 ? pa2 : pa3;
+  const T pb = row == 0 ? T(0) : row == 1 ? pb1 : row == 2 ? pb2 : pb3;
+  b = a * pb + b;
+  a = a * pa;
+}
+
+// Same along decreasing lane index (lane l composes lanes 63..l).
+template <typename T>
+__device__ inline void scan_affine_down_dpp(T& a, T& b) {
+#define R1S_SCAN_STEP(N)                        \
+  {                                             \
+    const T ap = dpp<DPP_ROW_SHL + N>(T(1), a); \
+    const T bp = dpp<DPP_ROW_SHL + N>(T(0), b); \
+    b = a * bp + b;                             \
+    a = a * ap;                                 \
+  }
+  R1S_SCAN_STEP(1) R1S_SCAN_STEP(2) R1S_SCAN_STEP(4) R1S_SCAN_STEP(8)
+#undef R1S_SCAN_STEP
+  const T a3 = readlane(a, 48), b3 = readlane(b, 48);
+  const T a2 = readlane(a, 32), b2 = readlane(b, 32);
+  const T a1 = readlane(a, 16), b1 = readlane(b, 16);
+  // suffixes entering rows 2, 1, 0
+  const T sa2 = a3, sb2 = b3;
+  const T sa1 = a2 * sa2, sb1 = a2 * sb2 + b2;
+  const T sa0 = a1 * sa1, sb0 = a1 * sb1 + b1;
+  const int row = lane_id() >> 4;
+  const T sa = row == 3 ? T(1) : row == 2 ? sa2 : row == 1 ? sa1 : sa0;
+  const T sb = row == 3 ? T(0) : row == 2 ? sb2 : row == 1 ? sb1 : sb0;
+  b = a * sb + b;
+  a = a * sa;
+}
+
 }  // namespace r1s
