@@ -72,6 +72,69 @@ def time_pair(torch, f1, f2, steps, warmup, flush=None):
     return wall, t1, t2
 
 
+def capture(torch, fn):
+    """Capture fn's launches (on torch's current stream) into a HIP graph."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def kernel_ms(torch, fn, reps=100):
+    """Average duration of fn's single kernel: HIP events around `reps`
+    back-to-back launches on the current stream."""
+    for _ in range(5):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_pair(torch, f1, f2, steps, warmup):
+    """Graph-replayed (f1; f2) steps: wall seconds for `steps` replays, and
+    the per-kernel average durations of f1 and f2 in ms (events around each
+    launch of the alternating sequence)."""
+    g = capture(torch, lambda: (f1(), f2()))
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, t1, t2 = time_pair(torch, f1, f2, steps, warmup)
+    return wall, float(np.mean(t1)), float(np.mean(t2))
+
+
+def profile_pass(torch, A, M, x, y, z):
+    """Kernels for a counter run: 20 matvecs, 20 applies, and 5 copies of a
+    256 MiB buffer (the calibration kernel of known size)."""
+    for _ in range(20):
+        A.matvec(x, out=y)
+    for _ in range(20):
+        M.apply(y, out=z)
+    src = torch.ones(1 << 25, dtype=torch.float64, device=x.device)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile pass done: copy kernel moves %d bytes read + %d written" % (src.numel() * 8,
+                                                                          src.numel() * 8))
+
+
 def cpu_baseline(p, nx, ny, L, budget_s=12.0):
     """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
     sample of block rows (blocks assembled and factored beforehand), repeated
@@ -121,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 pair (for profiling runs)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="run the fixed kernel sequence used for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -147,12 +212,29 @@ def main():
 
     mv_b, ap_b = pair_bytes(N, B, m)
     steps, warm = args.steps, args.warmup
-    wall, t_mv, t_ap = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
-                                 steps, warm)
+    if args.profile_pass:
+        profile_pass(torch, A, M, x, y, z)
+        return
+
+    # one step = matvec + apply, captured once as a HIP graph and replayed
+    step_graph = capture(torch, lambda: (A.matvec(x, out=y), M.apply(y, out=z)))
+    for _ in range(warm):
+        step_graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_graph.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     ms_step = wall / steps * 1e3
     value = (mv_b + ap_b) / (wall / steps) / 1e9
-    mv_ms = float(np.mean(t_mv))
-    ap_ms = float(np.mean(t_ap))
+    # per-kernel durations: HIP events around every launch of the same
+    # alternating sequence, on the stream the library launches on (timing a
+    # kernel back-to-back with itself would let the 256 MB Infinity Cache
+    # hold most of its working set)
+    _, t_mv, t_ap = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
+                              steps, warm)
+    mv_ms, ap_ms = float(np.mean(t_mv)), float(np.mean(t_ap))
     log(f"fp64 pair: {ms_step * 1e3:.1f} us/step, matvec {mv_ms * 1e3:.1f} us, "
         f"apply {ap_ms * 1e3:.1f} us, {value:.0f} GB/s")
     ach = mv_b / (mv_ms / 1e3) / 1e9
@@ -162,11 +244,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "nx": nx, "ny": ny, "L": L, "m": m, "nrhs": 1,
-                   "step": "y = J x then z = M y (SMW block-Jacobi), float64",
+                   "step": "y = J x then z = M y (SMW block-Jacobi), float64, replayed as a HIP graph",
                    "bytes_per_step": mv_b + ap_b},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "cell_updates_per_s": round(N / (wall / steps), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_matvec (float64, J x)",
+        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false> (J x)",
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_us": round(mv_ms * 1e3, 2),
@@ -179,22 +261,20 @@ def main():
     if not args.no_extras:
         # float32 values + accumulation (vectors stay float64)
         mv32, ap32 = pair_bytes(N, B, m, value_bytes=4)
-        wall32, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y, precision="f32"),
-                                   lambda: M.apply(y, out=z, precision="f32"), steps, warm)
+        wall32, k1, k2 = measure_pair(torch, lambda: A.matvec(x, out=y, precision="f32"),
+                                      lambda: M.apply(y, out=z, precision="f32"), steps, warm)
         out["fp32_pair"] = {
             "gbs": round((mv32 + ap32) / (wall32 / steps) / 1e9, 1),
             "us_per_step": round(wall32 / steps * 1e6, 2),
-            "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
-            "apply_us": round(float(np.mean(t2)) * 1e3, 2),
+            "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
             "speedup_vs_fp64": round(wall / wall32, 3)}
         # adjoint pair J^T x, M^T y (same bytes as forward)
-        wallT, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y, trans=True),
-                                  lambda: M.apply(y, out=z, trans=True), steps, warm)
+        wallT, k1, k2 = measure_pair(torch, lambda: A.matvec(x, out=y, trans=True),
+                                     lambda: M.apply(y, out=z, trans=True), steps, warm)
         out["adjoint_pair"] = {
             "gbs": round((mv_b + ap_b) / (wallT / steps) / 1e9, 1),
             "us_per_step": round(wallT / steps * 1e6, 2),
-            "matvec_T_us": round(float(np.mean(t1)) * 1e3, 2),
-            "apply_T_us": round(float(np.mean(t2)) * 1e3, 2),
+            "matvec_T_us": round(k1 * 1e3, 2), "apply_T_us": round(k2 * 1e3, 2),
             "ratio_vs_fp64": round(wallT / wall, 3)}
         # cold: a 1 GiB buffer is read before every step (a read leaves clean
         # lines, so no write-back of the flush competes with the timed kernels)
@@ -206,36 +286,26 @@ def main():
         out["cold_fp64_pair"] = {"gbs": round((mv_b + ap_b) / cold / 1e9, 1),
                                  "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
                                  "apply_us": round(float(np.mean(t2)) * 1e3, 2)}
-        # device copy ceiling (read + write bytes)
+        # device copy ceiling (torch copy kernel, read + write bytes)
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        cp = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
-        out["copy_ceiling_gbs"] = round(cp, 1)
-        out["pct_of_copy_ceiling"] = round(100 * value / cp, 2)
+        cp_ms = kernel_ms(torch, lambda: dst.copy_(src), reps=10)
+        out["torch_copy_gbs"] = round(2 * src.numel() * 8 / (cp_ms / 1e3) / 1e9, 1)
         del scratch, src, dst
         # dense-block BSR baseline on the same matrix
         try:
             Bm = r1s.BSRMatrix(A)
             P = r1s.DenseLUPreconditioner(Bm)
             bmv, bap = bsr_pair_bytes(N, B, m)
-            wallB, t1, t2 = time_pair(torch, lambda: Bm.matvec(x, out=y), lambda: P.apply(y, out=z),
-                                      max(10, steps // 10), 3)
+            nb = max(10, steps // 10)
+            wallB, k1, k2 = measure_pair(torch, lambda: Bm.matvec(x, out=y),
+                                         lambda: P.apply(y, out=z), nb, 3)
             out["bsr_pair"] = {
-                "gbs": round((bmv + bap) / (wallB / max(10, steps // 10)) / 1e9, 1),
-                "us_per_step": round(wallB / max(10, steps // 10) * 1e6, 2),
-                "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
-                "lu_apply_us": round(float(np.mean(t2)) * 1e3, 2),
+                "gbs": round((bmv + bap) / (wallB / nb) / 1e9, 1),
+                "us_per_step": round(wallB / nb * 1e6, 2),
+                "matvec_us": round(k1 * 1e3, 2), "lu_apply_us": round(k2 * 1e3, 2),
                 "stored_values": B * m * m,
-                "speedup_structured_vs_bsr": round((wallB / max(10, steps // 10)) / (wall / steps), 2)}
+                "speedup_structured_vs_bsr": round((wallB / nb) / (wall / steps), 2)}
             del Bm, P
         except Exception as e:  # report, never hide
             out["bsr_pair"] = {"error": str(e)}

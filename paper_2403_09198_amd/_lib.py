@@ -6,7 +6,9 @@ no CPU fallback anywhere in the package.
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libr1s.so")
+# the in-tree build; R1S_LIB may name another build of the same library
+LIB_PATH = os.environ.get("R1S_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libr1s.so")
 
 R1S_OK = 0
 R1S_ERR_ARG = -1

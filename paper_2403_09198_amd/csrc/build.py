@@ -30,31 +30,35 @@ CFLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+def _compile(src, objdir, defines):
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{p.stdout}\n{p.stderr}")
     return obj
 
 
-def build(verbose=False):
+def build(verbose=False, defines=(), out=None):
+    """Compile and link; `defines` are extra preprocessor macros (tuning
+    knobs such as R1S_WPB=2), `out` another output path for such builds."""
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(OBJDIR, exist_ok=True)
+    lib = out or LIB
+    objdir = OBJDIR if not defines else os.path.join(OBJDIR, "_".join(defines).replace("=", ""))
+    os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(HERE, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s_: _compile(s_, objdir, list(defines)), srcs))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"link failed:\n{p.stdout}\n{p.stderr}")
-    shutil.move(tmp, LIB)
+    shutil.move(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

@@ -73,13 +73,13 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
 // cell's own, valid addresses and are masked out of the sums instead of
 // being skipped by a branch.  Lanes past m read element m-1 and are masked.
 template <typename TV, int NCH, int NR, bool TRANS, bool RESID>
-__global__ __launch_bounds__(256) void k_matvec(Mesh g, const TV* __restrict__ rec,
+__global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restrict__ rec,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ y, int r0) {
   constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
+  const int c = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
   if (c >= g.N) return;
   const int lane = lane_id();
   const int m = g.m, mp = g.mp, L = g.L;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_matvec(Mesh g, const TV* __restrict__ r
     const int kk = k < m ? k : m - 1;
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      pv[d][ch] = prow[d][kk];
+      pv[d][ch] = ld_stream(prow[d] + kk);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         xv[r][d][ch] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
@@ -142,10 +142,10 @@ __global__ __launch_bounds__(256) void k_matvec(Mesh g, const TV* __restrict__ r
       pa = L + (i + 2) % 3; va = true;
       pb = L + (i + 1) % 3; vb = true;
     }
-    dg[ch] = rc[(long long)F_DIAG * mp + kk];
+    dg[ch] = ld_stream(rc + (long long)F_DIAG * mp + kk);
     if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
-      ca[ch] = rc[(long long)F_LO * mp + kk];
-      cb[ch] = rc[(long long)F_HI * mp + kk];
+      ca[ch] = ld_stream(rc + (long long)F_LO * mp + kk);
+      cb[ch] = ld_stream(rc + (long long)F_HI * mp + kk);
     } else {       // column k of S_cc: hi of row pa, lo of row pb
       const TV ta = rc[(long long)F_HI * mp + pa];
       const TV tb = rc[(long long)F_LO * mp + pb];
@@ -154,8 +154,8 @@ __global__ __launch_bounds__(256) void k_matvec(Mesh g, const TV* __restrict__ r
     }
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      if (d != D_C) nv[d][ch] = nrow[d][kk];
-      uv[d][ch] = urow[d][kk];
+      if (d != D_C) nv[d][ch] = ld_stream(nrow[d] + kk);
+      uv[d][ch] = ld_stream(urow[d] + kk);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -236,27 +236,27 @@ hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipSt
 template <typename TV, int NCH, bool TRANS, bool RESID>
 static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
                           double* y, int nrhs, hipStream_t s) {
-  const int grid = (g.N + 3) / 4;
+  const int grid = (g.N + WPB - 1) / WPB;
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
     if constexpr (NCH <= 2) {
       if (rem >= 8) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 8;
         continue;
       }
       if (rem >= 4) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 4;
         continue;
       }
     }
     if (rem >= 2) {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID>), dim3(grid), dim3(256), 0, s, g, rec, x, b, y, r0);
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 1;
     }
   }

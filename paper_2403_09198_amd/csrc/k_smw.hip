@@ -160,91 +160,106 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 }
 
 // ---------------------------------------------------------------- apply ----
-// One wavefront per cell, NCH = ceil(m / 64) chunks of 64 unknowns held in
-// registers; NR right-hand sides per launch starting at r0.  Scans and the
-// reduction run on DPP lane moves; all loads are issued before the first
-// scan (lanes past m read element m-1 and are masked).
+// One wavefront per CPW cells (the loads of all of them are issued before
+// the first scan), NCH = ceil(m / 64) chunks of 64 unknowns held in
+// registers, NR right-hand sides per launch starting at r0.  Scans and the
+// reduction run on DPP lane moves; lanes past m read element m-1 and are
+// masked.
+#ifndef R1S_APPLY_CPW
+#define R1S_APPLY_CPW 1
+#endif
 template <typename TV, int NCH, int NR, bool TRANS>
-__global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
-                                                   const TV* __restrict__ invC,
-                                                   const double* __restrict__ rin,
-                                                   double* __restrict__ zout, int r0) {
+__global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
+                                                       const TV* __restrict__ invC,
+                                                       const double* __restrict__ rin,
+                                                       double* __restrict__ zout, int r0) {
+  constexpr int CPW = NCH == 1 ? R1S_APPLY_CPW : 1;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
-  if (c >= g.N) return;
+  const int c0 = __builtin_amdgcn_readfirstlane((tile * WPB + (int)(threadIdx.x >> 6)) * CPW);
+  if (c0 >= g.N) return;
   const int lane = lane_id();
   const int L = g.L, m = g.m, mp = g.mp;
-  const TV* fc = fac + (long long)c * F_SMW * mp;
-  TV A[NCH], DI[NCH], B[NCH], W[NCH], V[NCH];
-  TV R[NR][NCH], RF[NR][3];
+  TV A[CPW][NCH], DI[CPW][NCH], B[CPW][NCH], W[CPW][NCH], V[CPW][NCH];
+  TV R[CPW][NR][NCH], RF[CPW][NR][3], IC[CPW];
 #pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    const int k = ch * WAVE + lane;
-    const int kk = k < m ? k : m - 1;
-    A[ch] = fc[P_A * mp + kk];
-    DI[ch] = fc[P_DINV * mp + kk];
-    B[ch] = fc[P_B * mp + kk];
-    W[ch] = fc[P_W * mp + kk];
-    V[ch] = fc[P_V * mp + kk];
+  for (int j = 0; j < CPW; ++j) {
+    const int c = c0 + j < g.N ? c0 + j : g.N - 1;
+    const TV* fc = fac + (long long)c * F_SMW * mp;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      const int kk = k < m ? k : m - 1;
+      A[j][ch] = ld_stream(fc + P_A * mp + kk);
+      DI[j][ch] = ld_stream(fc + P_DINV * mp + kk);
+      B[j][ch] = ld_stream(fc + P_B * mp + kk);
+      W[j][ch] = ld_stream(fc + P_W * mp + kk);
+      V[j][ch] = ld_stream(fc + P_V * mp + kk);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        R[j][r][ch] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + kk];
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-      R[r][ch] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + kk];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        RF[j][r][i] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + L + i];
+    IC[j] = invC[c];
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      RF[r][i] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + L + i];
-  const TV ic = invC[c];
 
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    TV Y[NCH];
-    // forward sweep over the levels: y_k = a_k y_{k-1} + s1_k r_k
-    TV carry = TV(0);
+  for (int j = 0; j < CPW; ++j) {
+    const int c = c0 + j;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      const int k = ch * WAVE + lane;
-      const bool lev = k < L;
-      TV a = lev ? A[ch] : TV(0);
-      TV bb = lev ? (TRANS ? DI[ch] * R[r][ch] : R[r][ch]) : TV(0);
-      if (ch * WAVE < L) {
-        scan_affine_up_dpp(a, bb);
-        Y[ch] = bb + a * carry;
-        carry = readlane(Y[ch], WAVE - 1);
-      } else {
-        Y[ch] = TV(0);
+    for (int r = 0; r < NR; ++r) {
+      TV Y[NCH];
+      // forward sweep over the levels: y_k = a_k y_{k-1} + s1_k r_k
+      TV carry = TV(0);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int k = ch * WAVE + lane;
+        const bool lev = k < L;
+        TV a = lev ? A[j][ch] : TV(0);
+        TV bb = lev ? (TRANS ? DI[j][ch] * R[j][r][ch] : R[j][r][ch]) : TV(0);
+        if (ch * WAVE < L) {
+          scan_affine_up_dpp(a, bb);
+          Y[ch] = bb + a * carry;
+          carry = readlane(Y[ch], WAVE - 1);
+        } else {
+          Y[ch] = TV(0);
+        }
       }
-    }
-    // backward sweep: x_k = b_k x_{k+1} + s2_k y_k ; flow lanes: corner inverse
-    carry = TV(0);
-    TV s = TV(0);
-    TV X0[NCH];
+      // backward sweep: x_k = b_k x_{k+1} + s2_k y_k ; flow lanes: corner inverse
+      carry = TV(0);
+      TV s = TV(0);
+      TV X0[NCH];
 #pragma unroll
-    for (int ch = NCH - 1; ch >= 0; --ch) {
-      const int k = ch * WAVE + lane;
-      const bool lev = k < L;
-      TV a = lev ? B[ch] : TV(0);
-      TV bb = lev ? (TRANS ? Y[ch] : DI[ch] * Y[ch]) : TV(0);
-      TV x0;
-      if (ch * WAVE < L) {
-        scan_affine_down_dpp(a, bb);
-        x0 = bb + a * carry;
-        carry = readlane(x0, 0);
-      } else {
-        x0 = TV(0);
+      for (int ch = NCH - 1; ch >= 0; --ch) {
+        const int k = ch * WAVE + lane;
+        const bool lev = k < L;
+        TV a = lev ? B[j][ch] : TV(0);
+        TV bb = lev ? (TRANS ? Y[ch] : DI[j][ch] * Y[ch]) : TV(0);
+        TV x0;
+        if (ch * WAVE < L) {
+          scan_affine_down_dpp(a, bb);
+          x0 = bb + a * carry;
+          carry = readlane(x0, 0);
+        } else {
+          x0 = TV(0);
+        }
+        const TV xf = A[j][ch] * RF[j][r][0] + DI[j][ch] * RF[j][r][1] + B[j][ch] * RF[j][r][2];
+        x0 = lev ? x0 : (k < m ? xf : TV(0));
+        X0[ch] = x0;
+        s += V[j][ch] * x0;
       }
-      const TV xf = A[ch] * RF[r][0] + DI[ch] * RF[r][1] + B[ch] * RF[r][2];
-      x0 = lev ? x0 : (k < m ? xf : TV(0));
-      X0[ch] = x0;
-      s += V[ch] * x0;
-    }
-    s = wave_sum_u(s) * ic;
-    double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;
+      s = wave_sum_u(s) * IC[j];
+      if (c < g.N) {
+        double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      const int k = ch * WAVE + lane;
-      if (k < m) zv[k] = (double)(X0[ch] - s * W[ch]);
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int k = ch * WAVE + lane;
+          if (k < m) zv[k] = (double)(X0[ch] - s * W[j][ch]);
+        }
+      }
     }
   }
 }
@@ -252,18 +267,19 @@ __global__ __launch_bounds__(256) void k_smw_apply(Mesh g, const TV* __restrict_
 template <typename TV, int NCH, bool TRANS>
 static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                  double* z, int nrhs, hipStream_t s) {
-  const int grid = (g.N + 3) / 4;
+  constexpr int CPW = NCH == 1 ? R1S_APPLY_CPW : 1;
+  const int grid = (g.N + WPB * CPW - 1) / (WPB * CPW);
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
     if (rem >= 4) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 4, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 4, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 4;
     } else if (rem >= 2) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS>), dim3(grid), dim3(256), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 1;
     }
   }

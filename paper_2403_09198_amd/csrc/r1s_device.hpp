@@ -21,6 +21,10 @@
 namespace r1s {
 
 constexpr int WAVE = 64;
+#ifndef R1S_WPB
+#define R1S_WPB 4
+#endif
+constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
 constexpr int F_REC = 17;    // field rows per cell record
 constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_U = 7, F_V = 12;
@@ -45,16 +49,33 @@ struct Mesh {
   long long n;     // N*m, stride between right-hand sides
 };
 
-// Workgroup id -> logical tile, so that each XCD (which receives every
-// NXCD-th workgroup) works on one contiguous range of tiles and keeps the
-// neighbouring x blocks in its own L2.
+// Workgroup id -> logical tile.  With R1S_XCD_REMAP each XCD (which
+// receives every NXCD-th workgroup) works on one contiguous range of tiles;
+// measured on MI355X this is slower for the cell kernels than the hardware's
+// round-robin order (all XCDs streaming neighbouring memory), so the default
+// keeps the identity map.
 __device__ inline int xcd_tile(int bid, int grid) {
+#ifndef R1S_XCD_REMAP
+  return bid;
+#endif
   const int xcd = bid % NXCD, local = bid / NXCD;
   const int per = grid / NXCD, rem = grid % NXCD;
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// Load of streamed matrix data (read once per kernel), marked non-temporal
+// so that it does not evict the reused x blocks from L2 (R1S_TEMPORAL builds
+// use ordinary loads).
+template <typename T>
+__device__ inline T ld_stream(const T* p) {
+#ifdef R1S_TEMPORAL
+  return *p;
+#else
+  return __builtin_nontemporal_load(p);
+#endif
+}
 
 // Neighbour cells of c in the order S, W, C, E, N (-1 where no block).
 __device__ inline void neighbours(const Mesh& g, int c, int nb[5]) {
