@@ -208,6 +208,123 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
   }
 }
 
+// Workgroup-per-cell form for m > 64: wave w of the workgroup owns unknowns
+// 64w .. 64w+63 of one cell, issues all of its loads at once (like the
+// single-chunk kernel), and the five pair coefficients are summed over the
+// waves through LDS in a fixed order.
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID>
+__global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g, const TV* __restrict__ rec,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ y, int r0) {
+  __shared__ TV part[NR][5][NCH];
+  const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = lane_id();
+  const int m = g.m, mp = g.mp, L = g.L;
+  const long long RS = (long long)F_REC * mp;
+  int nb[5], nbc[5];
+  bool ex[5];
+  neighbours(g, c, nb);
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    ex[d] = nb[d] >= 0;
+    nbc[d] = ex[d] ? nb[d] : c;
+  }
+  const TV* rc = rec + (long long)c * RS;
+  const TV* prow[5];
+  const TV* urow[5];
+  const TV* nrow[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    if (!TRANS) {
+      prow[d] = rc + (long long)(F_V + d) * mp;
+      urow[d] = rc + (long long)(F_U + d) * mp;
+      nrow[d] = rc + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : d)) * mp;
+    } else {
+      const TV* rn = rec + (long long)nbc[d] * RS;
+      prow[d] = rn + (long long)(F_U + opposite(d)) * mp;
+      urow[d] = rn + (long long)(F_V + opposite(d)) * mp;
+      nrow[d] = rn + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : opposite(d))) * mp;
+    }
+  }
+  const double* xr = x + (long long)r0 * g.n;
+  const int k = wv * WAVE + lane;
+  const int kk = k < m ? k : m - 1;
+
+  TV pv[5], xv[NR][5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    pv[d] = ld_stream(prow[d] + kk);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) xv[r][d] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
+  }
+  int pa, pb;
+  bool va, vb;
+  if (kk < L) {
+    va = kk >= 1; pa = va ? kk - 1 : kk;
+    vb = kk <= L - 2; pb = vb ? kk + 1 : kk;
+  } else {
+    const int i = kk - L;
+    pa = L + (i + 2) % 3; va = true;
+    pb = L + (i + 1) % 3; vb = true;
+  }
+  const TV dg = ld_stream(rc + (long long)F_DIAG * mp + kk);
+  TV ca, cb;
+  if (!TRANS) {
+    ca = ld_stream(rc + (long long)F_LO * mp + kk);
+    cb = ld_stream(rc + (long long)F_HI * mp + kk);
+  } else {
+    const TV ta = rc[(long long)F_HI * mp + pa];
+    const TV tb = rc[(long long)F_LO * mp + pb];
+    ca = va ? ta : TV(0);
+    cb = vb ? tb : TV(0);
+  }
+  TV nv[5], uv[5], xa[NR], xb[NR];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    if (d != D_C) nv[d] = ld_stream(nrow[d] + kk);
+    uv[d] = ld_stream(urow[d] + kk);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
+    xa[r] = (TV)xv_c[pa];
+    xb[r] = (TV)xv_c[pb];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      const TV s = wave_sum_u(k < m ? pv[d] * xv[r][d] : TV(0));
+      if (lane == 0) part[r][d][wv] = s;
+    }
+  __syncthreads();
+  TV acc[NR][5];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      TV s = part[r][d][0];
+#pragma unroll
+      for (int w = 1; w < NCH; ++w) s += part[r][d][w];
+      acc[r][d] = ex[d] ? s : TV(0);
+    }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    TV t = dg * xv[r][D_C] + ca * xa[r] + cb * xb[r];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      if (d != D_C && ex[d]) t += nv[d] * xv[r][d];
+      t += uv[d] * acc[r][d];
+    }
+    const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
+    y[o] = RESID ? b[o] - (double)t : (double)t;
+  }
+}
+
 // ------------------------------------------------------------ launchers ----
 static inline int grid_for(long long work, int per_block, int cap = 1 << 20) {
   long long g = (work + per_block - 1) / per_block;
@@ -236,6 +353,25 @@ hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipSt
 template <typename TV, int NCH, bool TRANS, bool RESID>
 static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
                           double* y, int nrhs, hipStream_t s) {
+#ifndef R1S_NO_WG_CELL
+  if constexpr (NCH > 1) {
+    int r0 = 0;
+    while (r0 < nrhs) {
+      const int rem = nrhs - r0;
+      if (rem >= 4) {
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+        r0 += 4;
+      } else if (rem >= 2) {
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+        r0 += 2;
+      } else {
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+        r0 += 1;
+      }
+    }
+    return;
+  }
+#endif
   const int grid = (g.N + WPB - 1) / WPB;
   int r0 = 0;
   while (r0 < nrhs) {

@@ -264,9 +264,112 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
   }
 }
 
+// Workgroup-per-cell form for m > 64: wave w owns unknowns 64w .. 64w+63.
+// Each wave scans its chunk; the chunk compositions go through LDS and every
+// wave folds in the compositions of the chunks before it (forward sweep) or
+// after it (backward sweep), in a fixed order.
+template <typename TV, int NCH, int NR, bool TRANS>
+__global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __restrict__ fac,
+                                                           const TV* __restrict__ invC,
+                                                           const double* __restrict__ rin,
+                                                           double* __restrict__ zout, int r0) {
+  __shared__ TV fa[NR][NCH], fb[NR][NCH], ga[NR][NCH], gb[NR][NCH], ss[NR][NCH];
+  const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = lane_id();
+  const int L = g.L, m = g.m, mp = g.mp;
+  const int k = wv * WAVE + lane;
+  const int kk = k < m ? k : m - 1;
+  const bool lev = k < L;
+  const bool has_lev = wv * WAVE < L;  // wave-uniform
+  const TV* fc = fac + (long long)c * F_SMW * mp;
+  const TV A = ld_stream(fc + P_A * mp + kk);
+  const TV DI = ld_stream(fc + P_DINV * mp + kk);
+  const TV B = ld_stream(fc + P_B * mp + kk);
+  const TV W = ld_stream(fc + P_W * mp + kk);
+  const TV V = ld_stream(fc + P_V * mp + kk);
+  TV R[NR], RF[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double* rv = rin + (long long)(r0 + r) * g.n + (long long)c * m;
+    R[r] = (TV)rv[kk];
+    RF[r][0] = (TV)rv[L];
+    RF[r][1] = (TV)rv[L + 1];
+    RF[r][2] = (TV)rv[L + 2];
+  }
+  const TV ic = invC[c];
+
+  TV a[NR], bb[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {  // forward sweep, local to the chunk
+    a[r] = lev ? A : TV(0);
+    bb[r] = lev ? (TRANS ? DI * R[r] : R[r]) : TV(0);
+    if (has_lev) scan_affine_up_dpp(a[r], bb[r]);
+    if (lane == WAVE - 1) {
+      fa[r][wv] = a[r];
+      fb[r][wv] = bb[r];
+    }
+  }
+  __syncthreads();
+  TV a2[NR], b2[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {  // carry in, then the backward sweep
+    TV carry = TV(0);
+    for (int w = 0; w < wv; ++w) carry = fb[r][w] + fa[r][w] * carry;
+    const TV Y = bb[r] + a[r] * carry;
+    a2[r] = lev ? B : TV(0);
+    b2[r] = lev ? (TRANS ? Y : DI * Y) : TV(0);
+    if (has_lev) scan_affine_down_dpp(a2[r], b2[r]);
+    if (lane == 0) {
+      ga[r][wv] = a2[r];
+      gb[r][wv] = b2[r];
+    }
+  }
+  __syncthreads();
+  TV X0[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    TV carry = TV(0);
+    for (int w = NCH - 1; w > wv; --w) carry = gb[r][w] + ga[r][w] * carry;
+    const TV x0 = b2[r] + a2[r] * carry;
+    const TV xf = A * RF[r][0] + DI * RF[r][1] + B * RF[r][2];
+    X0[r] = lev ? x0 : (k < m ? xf : TV(0));
+    const TV sp = wave_sum_u(V * X0[r]);
+    if (lane == 0) ss[r][wv] = sp;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    TV st = ss[r][0];
+#pragma unroll
+    for (int w = 1; w < NCH; ++w) st += ss[r][w];
+    st *= ic;
+    if (k < m) zout[(long long)(r0 + r) * g.n + (long long)c * m + k] = (double)(X0[r] - st * W);
+  }
+}
+
 template <typename TV, int NCH, bool TRANS>
 static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                  double* z, int nrhs, hipStream_t s) {
+#ifndef R1S_NO_WG_CELL
+  if constexpr (NCH > 1) {
+    int r0 = 0;
+    while (r0 < nrhs) {
+      const int rem = nrhs - r0;
+      if (rem >= 4) {
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 4, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        r0 += 4;
+      } else if (rem >= 2) {
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 2, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        r0 += 2;
+      } else {
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 1, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        r0 += 1;
+      }
+    }
+    return hipGetLastError();
+  }
+#endif
   constexpr int CPW = NCH == 1 ? R1S_APPLY_CPW : 1;
   const int grid = (g.N + WPB * CPW - 1) / (WPB * CPW);
   int r0 = 0;
