@@ -135,6 +135,82 @@ def profile_pass(torch, A, M, x, y, z):
                                                                           src.numel() * 8))
 
 
+def sweep(torch, levels=(32, 61, 120, 200), steps=50, warm=5):
+    """Level sweep on the 512 x 256 mesh: structured pairs (float64, float32,
+    adjoint) against the dense-block BSR pair.  BSR storage grows as m^2, so
+    for L = 200 the BSR pair runs on the 512 x 128 half mesh (130 GB) and the
+    structured pair is measured there as well."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    rows = []
+    for L in levels:
+        for nx, ny, with_bsr in ((512, 256, L <= 120), (512, 128, L > 120)):
+            if (nx, ny) == (512, 128) and L <= 120:
+                continue
+            m, N = L + 3, nx * ny
+            B = 5 * N - 2 * nx - 2 * ny
+            log(f"sweep: mesh {nx}x{ny} L={L}")
+            p = gen.make_problem(nx, ny, L, seed=0)
+            vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
+            del p
+            A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True)
+            del vals
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
+            t_setup = time.perf_counter() - t0
+            x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
+            y, z = torch.empty_like(x), torch.empty_like(x)
+            mv, ap = pair_bytes(N, B, m)
+            mv32, ap32 = pair_bytes(N, B, m, value_bytes=4)
+            row = {"nx": nx, "ny": ny, "L": L, "m": m, "cells": N,
+                   "structured_bytes": 8 * (N * (3 * m - 2) + (B - N) * m + 2 * B * m),
+                   "bsr_bytes": 8 * B * m * m, "smw_setup_ms": round(t_setup * 1e3, 2)}
+            for tag, f1, f2, nbytes in (
+                    ("f64", lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z), mv + ap),
+                    ("f32", lambda: A.matvec(x, out=y, precision="f32"),
+                     lambda: M.apply(y, out=z, precision="f32"), mv32 + ap32),
+                    ("adjoint", lambda: A.matvec(x, out=y, trans=True),
+                     lambda: M.apply(y, out=z, trans=True), mv + ap)):
+                wall, k1, k2 = measure_pair(torch, f1, f2, steps, warm)
+                row[tag] = {"us_per_step": round(wall / steps * 1e6, 2),
+                            "gbs": round(nbytes / (wall / steps) / 1e9, 1),
+                            "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
+                            "cell_updates_per_s": round(N / (wall / steps), 1)}
+            if with_bsr:
+                try:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    Bm = r1s.BSRMatrix(A)
+                    t_asm = time.perf_counter() - t0
+                    t0 = time.perf_counter()
+                    P = r1s.DenseLUPreconditioner(Bm)
+                    t_lu = time.perf_counter() - t0
+                    bmv, bap = bsr_pair_bytes(N, B, m)
+                    nb = 5
+                    wall, k1, k2 = measure_pair(torch, lambda: Bm.matvec(x, out=y),
+                                                lambda: P.apply(y, out=z), nb, 1)
+                    row["bsr"] = {"us_per_step": round(wall / nb * 1e6, 2),
+                                  "gbs": round((bmv + bap) / (wall / nb) / 1e9, 1),
+                                  "matvec_us": round(k1 * 1e3, 2), "lu_apply_us": round(k2 * 1e3, 2),
+                                  "assemble_ms": round(t_asm * 1e3, 1),
+                                  "lu_setup_ms": round(t_lu * 1e3, 1)}
+                    row["speedup_structured_vs_bsr"] = round(
+                        row["bsr"]["us_per_step"] / row["f64"]["us_per_step"], 2)
+                    row["matvec_speedup"] = round(k1 * 1e3 / row["f64"]["matvec_us"], 2)
+                    row["apply_speedup"] = round(k2 * 1e3 / row["f64"]["apply_us"], 2)
+                    del Bm, P
+                except Exception as e:  # report, never hide
+                    row["bsr"] = {"error": str(e)}
+            print(json.dumps(row), flush=True)
+            rows.append(row)
+            del A, M, x, y, z
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(p, nx, ny, L, budget_s=12.0):
     """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
     sample of block rows (blocks assembled and factored beforehand), repeated
@@ -184,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 pair (for profiling runs)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="512x256 level sweep against the BSR baseline (one JSON line per case)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the fixed kernel sequence used for hardware-counter runs")
     args = ap.parse_args()
@@ -196,6 +274,9 @@ def main():
 
     from paper_2403_09198_amd import gen, r1s
 
+    if args.sweep:
+        sweep(torch)
+        return
     w = gen.WORKLOADS[args.workload]
     nx, ny, L, m, N = w.nx, w.ny, w.L, w.m, w.N
     B = 5 * N - 2 * nx - 2 * ny

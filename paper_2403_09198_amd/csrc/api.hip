@@ -10,6 +10,9 @@
 #include <algorithm>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "r1s.h"
 #include "r1s_kernels.hpp"
 
@@ -417,17 +420,37 @@ extern "C" int r1s_bsr_matvec(r1s_bsr B, int nrhs, const double* x, double* y, v
   return R1S_OK;
 }
 
-static void bsr_prec_layout(Carver& cv, const Mesh& g, r1s_prec_s* P) {
+static void bsr_prec_layout(Carver& cv, const Mesh& g, r1s_prec_s* P, int** info) {
   P->lu = cv.take<double>((size_t)g.N * g.m * g.m);
   P->piv = cv.take<int>((size_t)g.N * g.m);
   P->status = cv.take<int>(64);
+  *info = cv.take<int>(g.N);
+}
+
+// Dense LU of blocks too large for LDS: rocSOLVER's batched getrf (baseline
+// setup only; it allocates its own workspace through rocBLAS).
+static int library_lu(const r1s_bsr_s* B, r1s_prec_s* P, int* info, hipStream_t s) {
+  HIP_TRY(launch_bsr_gather_diag(B->g, B->diag_block, B->data, P->lu, s));
+  rocblas_handle h;
+  if (rocblas_create_handle(&h) != rocblas_status_success)
+    return fail(R1S_ERR_HIP, "rocblas_create_handle failed");
+  rocblas_set_stream(h, s);
+  const int m = B->g.m;
+  const rocblas_status st = rocsolver_dgetrf_strided_batched(
+      h, m, m, P->lu, m, (rocblas_stride)m * m, P->piv, (rocblas_stride)m, info, B->g.N);
+  rocblas_destroy_handle(h);
+  if (st != rocblas_status_success)
+    return fail(R1S_ERR_HIP, "rocsolver_dgetrf_strided_batched failed (%d)", (int)st);
+  HIP_TRY(launch_bsr_piv_convert(B->g, P->piv, info, P->status, s));
+  return R1S_OK;
 }
 
 extern "C" int r1s_bsr_prec_size(r1s_bsr B, size_t* bytes) {
   if (!B || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
   Carver cv(nullptr);
   r1s_prec_s tmp;
-  bsr_prec_layout(cv, B->g, &tmp);
+  int* info;
+  bsr_prec_layout(cv, B->g, &tmp, &info);
   *bytes = cv.off;
   return R1S_OK;
 }
@@ -444,13 +467,18 @@ extern "C" int r1s_bsr_prec_setup(r1s_bsr B, void* mem, size_t mem_bytes, void* 
   P->kind = PREC_BSR_LU;
   P->g = B->g;
   Carver cv(mem);
-  bsr_prec_layout(cv, B->g, P);
+  int* info;
+  bsr_prec_layout(cv, B->g, P, &info);
   hipStream_t s = as_stream(stream);
   int st = 0x7fffffff, rc = R1S_OK;
   do {
     hipError_t e;
     if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
-    if ((e = launch_bsr_lu_setup(B->g, B->diag_block, B->data, P->lu, P->piv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "bsr lu: %s", hipGetErrorString(e)); break; }
+    if (bsr_lu_fits_lds(B->g)) {
+      if ((e = launch_bsr_lu_setup(B->g, B->diag_block, B->data, P->lu, P->piv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "bsr lu: %s", hipGetErrorString(e)); break; }
+    } else if ((rc = library_lu(B, P, info, s))) {
+      break;
+    }
     if ((rc = read_status(P->status, s, &st))) break;
     if (st != 0x7fffffff) { rc = fail(R1S_ERR_SINGULAR, "dense LU: zero pivot in the diagonal block of cell %d", st); break; }
   } while (0);

@@ -100,9 +100,9 @@ hipError_t launch_bsr_matvec(const Mesh& g, const int* indptr, const int* indice
 }
 
 // LU with partial pivoting of the diagonal block of every cell, one
-// workgroup per cell, right-looking elimination on a column-major copy.  The
-// copy lives in LDS when it fits (m*m*8 <= 64 KiB), otherwise in the output
-// buffer itself.
+// workgroup per cell, right-looking elimination on a column-major copy in
+// LDS (m*m*8 <= 64 KiB, i.e. m <= 90).  Larger blocks go to the batched
+// library LU (see the BSR preconditioner setup).
 template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_bsr_lu(Mesh g, const int* __restrict__ diag_block,
                                                 const double* __restrict__ data,
@@ -173,97 +173,161 @@ __global__ __launch_bounds__(256) void k_bsr_lu(Mesh g, const int* __restrict__ 
   if (bad && threadIdx.x == 0) atomicMin(status, c);
 }
 
+bool bsr_lu_fits_lds(const Mesh& g) { return (size_t)g.m * g.m * sizeof(double) <= 65536; }
+
 hipError_t launch_bsr_lu_setup(const Mesh& g, const int* diag_block, const double* data,
                                double* lu, int* piv, int* status, hipStream_t s) {
+  if (!bsr_lu_fits_lds(g)) return hipErrorInvalidValue;
   const size_t lds = (size_t)g.m * g.m * sizeof(double);
-  if (lds <= 65536)
-    hipLaunchKernelGGL(k_bsr_lu<true>, dim3(g.N), dim3(256), lds, s, g, diag_block, data, lu, piv,
-                       status);
-  else
-    hipLaunchKernelGGL(k_bsr_lu<false>, dim3(g.N), dim3(256), 0, s, g, diag_block, data, lu, piv,
-                       status);
+  hipLaunchKernelGGL(k_bsr_lu<true>, dim3(g.N), dim3(256), lds, s, g, diag_block, data, lu, piv,
+                     status);
+  return hipGetLastError();
+}
+
+// Copies the diagonal block of every cell into lu[c] (the in-place input of
+// the batched library LU used for blocks that do not fit in LDS).
+__global__ __launch_bounds__(256) void k_bsr_gather_diag(Mesh g, const int* __restrict__ diag_block,
+                                                         const double* __restrict__ data,
+                                                         double* __restrict__ lu) {
+  const long long mm = (long long)g.m * g.m;
+  const double* src = data + (long long)diag_block[blockIdx.x] * mm;
+  double* dst = lu + (long long)blockIdx.x * mm;
+  for (long long e = threadIdx.x; e < mm; e += blockDim.x) dst[e] = src[e];
+}
+
+// 1-based LAPACK pivots -> 0-based; info > 0 (exact zero pivot) -> status.
+__global__ __launch_bounds__(256) void k_bsr_piv_convert(Mesh g, int* __restrict__ piv,
+                                                         const int* __restrict__ info,
+                                                         int* status) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (long long)g.N * g.m) piv[i] -= 1;
+  if (i < g.N && info[i] != 0) atomicMin(status, (int)i);
+}
+
+hipError_t launch_bsr_gather_diag(const Mesh& g, const int* diag_block, const double* data,
+                                  double* lu, hipStream_t s) {
+  hipLaunchKernelGGL(k_bsr_gather_diag, dim3(g.N), dim3(256), 0, s, g, diag_block, data, lu);
+  return hipGetLastError();
+}
+
+hipError_t launch_bsr_piv_convert(const Mesh& g, int* piv, const int* info, int* status,
+                                  hipStream_t s) {
+  const long long n = (long long)g.N * g.m;
+  hipLaunchKernelGGL(k_bsr_piv_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, piv,
+                     info, status);
   return hipGetLastError();
 }
 
 // z_c = D_cc^{-1} r_c from the packed LU: row swaps, unit-lower forward
 // substitution, upper back substitution.  One wavefront per cell; the m
-// unknowns sit in NCH registers per lane and every step broadcasts the newly
-// final unknown with a cross-lane read.
+// unknowns sit in NCH registers per lane.  Columns of the factors are loaded
+// JB at a time ahead of the dependent substitution steps, and each newly
+// final unknown is broadcast with v_readlane.
+template <int NCH>
+__device__ inline double bcast(const double (&y)[NCH], int j) {
+  double v = 0.0;
+#pragma unroll
+  for (int s = 0; s < NCH; ++s)
+    if (s == (j >> 6)) v = readlane(y[s], j & 63);
+  return v;
+}
+
 template <int NCH>
 __global__ __launch_bounds__(256) void k_bsr_lu_apply(Mesh g, const double* __restrict__ lu,
                                                       const int* __restrict__ piv,
                                                       const double* __restrict__ rin,
                                                       double* __restrict__ zout, int nrhs) {
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + (int)(threadIdx.x >> 6));
+  constexpr int JB = 16;
+  const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   if (c >= g.N) return;
   const int lane = lane_id();
   const int m = g.m;
   const double* LU = lu + (long long)c * m * m;
   const int* P = piv + (long long)c * m;
+  int pv[NCH];
+#pragma unroll
+  for (int s = 0; s < NCH; ++s) {
+    const int i = s * WAVE + lane;
+    pv[s] = P[i < m ? i : m - 1];
+  }
   for (int r = 0; r < nrhs; ++r) {
     const double* rv = rin + (long long)r * g.n + (long long)c * m;
     double y[NCH];
 #pragma unroll
-    for (int t = 0; t < NCH; ++t) {
-      const int i = t * WAVE + lane;
-      y[t] = i < m ? rv[i] : 0.0;
+    for (int s = 0; s < NCH; ++s) {
+      const int i = s * WAVE + lane;
+      y[s] = rv[i < m ? i : m - 1];
     }
     // row swaps in order
     for (int k = 0; k < m; ++k) {
-      const int p = P[k];
+      int p = 0;
+#pragma unroll
+      for (int s = 0; s < NCH; ++s)
+        if (s == (k >> 6)) p = __builtin_amdgcn_readlane(pv[s], k & 63);
       if (p == k) continue;
-      const int tk = k / WAVE, lk = k % WAVE, tp = p / WAVE, lp = p % WAVE;
-      double vk = 0.0, vp = 0.0;
+      const double vk = bcast(y, k), vp = bcast(y, p);
 #pragma unroll
-      for (int t = 0; t < NCH; ++t) {
-        const double a = __shfl(y[t], lk, WAVE);
-        const double b = __shfl(y[t], lp, WAVE);
-        if (t == tk) vk = a;
-        if (t == tp) vp = b;
-      }
-#pragma unroll
-      for (int t = 0; t < NCH; ++t) {
-        if (t == tk && lane == lk) y[t] = vp;
-        if (t == tp && lane == lp) y[t] = vk;
+      for (int s = 0; s < NCH; ++s) {
+        const int i = s * WAVE + lane;
+        if (i == k) y[s] = vp;
+        if (i == p) y[s] = vk;
       }
     }
-    // forward: L unit lower
+    // forward: unit lower triangle
+    for (int j0 = 0; j0 < m; j0 += JB) {
+      double col[JB][NCH];
 #pragma unroll
-    for (int tj = 0; tj < NCH; ++tj) {
-      for (int lj = 0; lj < WAVE; ++lj) {
-        const int j = tj * WAVE + lj;
+      for (int t = 0; t < JB; ++t) {
+        const int j = j0 + t < m ? j0 + t : m - 1;
+#pragma unroll
+        for (int s = 0; s < NCH; ++s) {
+          const int i = s * WAVE + lane;
+          col[t][s] = LU[(long long)j * m + (i < m ? i : m - 1)];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const int j = j0 + t;
         if (j >= m) break;
-        const double yj = __shfl(y[tj], lj, WAVE);
-        const double* col = LU + (long long)j * m;
+        const double yj = bcast(y, j);
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const int i = t * WAVE + lane;
-          if (t >= tj && i > j && i < m) y[t] -= col[i] * yj;
+        for (int s = 0; s < NCH; ++s) {
+          const int i = s * WAVE + lane;
+          if (i > j && i < m) y[s] -= col[t][s] * yj;
         }
       }
     }
-    // backward: U upper
+    // backward: upper triangle
+    for (int j1 = m - 1; j1 >= 0; j1 -= JB) {
+      double col[JB][NCH];
 #pragma unroll
-    for (int tj = NCH - 1; tj >= 0; --tj) {
-      for (int lj = WAVE - 1; lj >= 0; --lj) {
-        const int j = tj * WAVE + lj;
-        if (j >= m) continue;
-        const double* col = LU + (long long)j * m;
-        if (lane == lj) y[tj] /= col[j];
-        const double xj = __shfl(y[tj], lj, WAVE);
+      for (int t = 0; t < JB; ++t) {
+        const int j = j1 - t >= 0 ? j1 - t : 0;
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const int i = t * WAVE + lane;
-          if (t <= tj && i < j) y[t] -= col[i] * xj;
+        for (int s = 0; s < NCH; ++s) {
+          const int i = s * WAVE + lane;
+          col[t][s] = LU[(long long)j * m + (i < m ? i : m - 1)];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const int j = j1 - t;
+        if (j < 0) break;
+        const double dj = LU[(long long)j * m + j];
+        const double xj = bcast(y, j) / dj;
+#pragma unroll
+        for (int s = 0; s < NCH; ++s) {
+          const int i = s * WAVE + lane;
+          if (i == j) y[s] = xj;
+          if (i < j) y[s] -= col[t][s] * xj;
         }
       }
     }
     double* zv = zout + (long long)r * g.n + (long long)c * m;
 #pragma unroll
-    for (int t = 0; t < NCH; ++t) {
-      const int i = t * WAVE + lane;
-      if (i < m) zv[i] = y[t];
+    for (int s = 0; s < NCH; ++s) {
+      const int i = s * WAVE + lane;
+      if (i < m) zv[i] = y[s];
     }
   }
 }

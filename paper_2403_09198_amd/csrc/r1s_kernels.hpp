@@ -39,6 +39,11 @@ hipError_t launch_bsr_matvec(const Mesh& g, const int* indptr, const int* indice
                              hipStream_t s);
 hipError_t launch_bsr_lu_setup(const Mesh& g, const int* diag_block, const double* data,
                                double* lu, int* piv, int* status, hipStream_t s);
+bool bsr_lu_fits_lds(const Mesh& g);
+hipError_t launch_bsr_gather_diag(const Mesh& g, const int* diag_block, const double* data,
+                                  double* lu, hipStream_t s);
+hipError_t launch_bsr_piv_convert(const Mesh& g, int* piv, const int* info, int* status,
+                                  hipStream_t s);
 hipError_t launch_bsr_lu_apply(const Mesh& g, const double* lu, const int* piv, const double* r,
                                double* z, int nrhs, hipStream_t s);
 
