@@ -30,15 +30,27 @@ hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- setup ----
-// One thread per cell; runs once per matrix.  Factor records (see
-// r1s_device.hpp): forward a = -l_k, dinv = 1/d_k, b = -s_k/d_k, w, v_cC;
-// transpose a = -s_{k-1}/d_k, dinv, b = -l_{k+1}, wt = A0^{-T} v_cC, u_cC.
-__global__ __launch_bounds__(256) void k_smw_setup(Mesh g, const double* __restrict__ rec,
-                                                   double* __restrict__ facF,
-                                                   double* __restrict__ facT,
-                                                   double* __restrict__ invC, int* status) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per cell, NCH chunks of 64 unknowns, runs once per matrix.
+//
+// Band LU (Thomas algorithm, no pivoting): d_0 = a_0, d_k = a_k - e_k / d_{k-1}
+// with e_k = sub_{k-1} sup_{k-1}.  The pivots are a continued fraction: with
+// d_k = p_k / q_k, [p_k; q_k] = [[a_k, -e_k], [1, 0]] [p_{k-1}; q_{k-1}], so
+// every chunk runs one inclusive scan of 2 x 2 matrix products (each factor
+// scaled by 1 / max(|a_k|, |e_k|, 1), which leaves the ratio unchanged and
+// keeps 64-factor products far from overflow) applied to the carried
+// [d_{prev}; 1].  Then l_k = sub_{k-1} / d_{k-1}, and the factor rows:
+//   forward  a = -l_k, dinv = 1/d_k, b = -sup_k / d_k, w = A0^{-1} u, v
+//   transpose a = -sup_{k-1} / d_k, dinv, b = -l_{k+1}, wt = A0^{-T} v, u
+// Flow lanes L + i hold row i of the 3 x 3 corner inverse (transpose: of its
+// transpose).  w and wt use the same affine-scan sweeps as the apply.
+template <int NCH>
+__global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __restrict__ rec,
+                                                       double* __restrict__ facF,
+                                                       double* __restrict__ facT,
+                                                       double* __restrict__ invC, int* status) {
+  const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + (threadIdx.x >> 6)));
   if (c >= g.N) return;
+  const int lane = lane_id();
   const int L = g.L, m = g.m, mp = g.mp;
   const double* rc = rec + (long long)c * F_REC * mp;
   const double* dg = rc + (long long)F_DIAG * mp;
@@ -46,39 +58,21 @@ __global__ __launch_bounds__(256) void k_smw_setup(Mesh g, const double* __restr
   const double* hi = rc + (long long)F_HI * mp;
   const double* uC = rc + (long long)(F_U + D_C) * mp;
   const double* vC = rc + (long long)(F_V + D_C) * mp;
-  double* fA = facF + (long long)c * F_SMW * mp;
-  double* fT = facT ? facT + (long long)c * F_SMW * mp : nullptr;
-  bool bad = false;
 
-  for (int k = m; k < mp; ++k)
-    for (int f = 0; f < F_SMW; ++f) {
-      fA[f * mp + k] = 0.0;
-      if (fT) fT[f * mp + k] = 0.0;
-    }
-
-  // LU of the level band: d_0 = a_0, l_k = sub_{k-1}/d_{k-1},
-  // d_k = a_k - l_k sup_{k-1}.
-  double dprev = 1.0;
-  for (int k = 0; k < L; ++k) {
-    const double l = k == 0 ? 0.0 : lo[k] / dprev;
-    const double t = k == 0 ? 0.0 : l * hi[k - 1];
-    const double d = dg[k] - t;
-    if (!(fabs(d) > 1e-14 * (fabs(dg[k]) + fabs(t)))) bad = true;
-    fA[P_A * mp + k] = -l;
-    fA[P_DINV * mp + k] = 1.0 / d;
-    dprev = d;
+  double AD[NCH], LO[NCH], HI[NCH], HM1[NCH], LP1[NCH], U[NCH], V[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const int kk = k < m ? k : m - 1;
+    AD[ch] = dg[kk];
+    LO[ch] = lo[kk];
+    HI[ch] = hi[kk];
+    HM1[ch] = kk >= 1 ? hi[kk - 1] : 0.0;
+    LP1[ch] = kk + 1 < m ? lo[kk + 1] : 0.0;
+    U[ch] = uC[kk];
+    V[ch] = vC[kk];
   }
-  for (int k = 0; k < L; ++k) {
-    const double di = fA[P_DINV * mp + k];
-    fA[P_B * mp + k] = k <= L - 2 ? -hi[k] * di : 0.0;
-    if (fT) {
-      fT[P_A * mp + k] = k >= 1 ? -hi[k - 1] * di : 0.0;
-      fT[P_DINV * mp + k] = di;
-      fT[P_B * mp + k] = k <= L - 2 ? fA[P_A * mp + k + 1] : 0.0;
-    }
-  }
-
-  // 3 x 3 flow corner, inverse by cofactors.
+  // 3 x 3 flow corner (wave-uniform values), inverse by cofactors
   double F[3][3], Fi[3][3];
   for (int i = 0; i < 3; ++i) {
     F[i][i] = dg[L + i];
@@ -93,69 +87,128 @@ __global__ __launch_bounds__(256) void k_smw_setup(Mesh g, const double* __restr
   const double det = F[0][0] * Fi[0][0] + F[0][1] * Fi[1][0] + F[0][2] * Fi[2][0];
   double rn = 1.0;
   for (int i = 0; i < 3; ++i) rn *= fabs(F[i][0]) + fabs(F[i][1]) + fabs(F[i][2]);
-  if (!(fabs(det) > 1e-14 * rn)) bad = true;
+  bool bad = !(fabs(det) > 1e-14 * rn);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Fi[i][j] /= det;
-  for (int i = 0; i < 3; ++i) {
-    fA[P_A * mp + L + i] = Fi[i][0];
-    fA[P_DINV * mp + L + i] = Fi[i][1];
-    fA[P_B * mp + L + i] = Fi[i][2];
-    if (fT) {
-      fT[P_A * mp + L + i] = Fi[0][i];
-      fT[P_DINV * mp + L + i] = Fi[1][i];
-      fT[P_B * mp + L + i] = Fi[2][i];
+
+  // pivots d_k by the matrix-product scan, chunk by chunk
+  double D[NCH], DP[NCH];  // d_k and d_{k-1}
+  double dprev = 1.0, qprev = 0.0;  // [p_{-1}; q_{-1}] = [1; 0]
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const bool lev = k < L;
+    const double e = k >= 1 ? LO[ch] * HM1[ch] : 0.0;
+    const double sc = 1.0 / fmax(fmax(fabs(AD[ch]), fabs(e)), 1.0);
+    double ma = lev ? AD[ch] * sc : 1.0, mb = lev ? -e * sc : 0.0;
+    double mc = lev ? sc : 0.0, md = lev ? 0.0 : 1.0;
+    if (ch * WAVE < L) {
+      scan_mat2_up_dpp(ma, mb, mc, md);
+      const double p = ma * dprev + mb * qprev;
+      const double q = mc * dprev + md * qprev;
+      D[ch] = p / q;
+      // d_{k-1}: one lane up; lane 0 takes the previous chunk's last pivot
+      const double up = __shfl_up(D[ch], 1, WAVE);
+      DP[ch] = lane == 0 ? dprev / qprev : up;
+      if (ch == 0 && lane == 0) DP[ch] = 1.0;
+      dprev = readlane(D[ch], WAVE - 1);
+      qprev = 1.0;
+    } else {
+      D[ch] = 1.0;
+      DP[ch] = 1.0;
     }
   }
-
-  // SMW-1: w = A0^{-1} u_cC (forward then backward sweep, then the corner).
-  double* w = fA + P_W * mp;
-  double prev = 0.0;
-  for (int k = 0; k < L; ++k) {
-    prev = uC[k] + fA[P_A * mp + k] * prev;
-    w[k] = prev;
+  // factor rows
+  double FA[NCH], FDI[NCH], FB[NCH], TA[NCH], TDI[NCH], TB[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    if (k < L) {
+      const double l = k >= 1 ? LO[ch] / DP[ch] : 0.0;
+      const double t = k >= 1 ? l * HM1[ch] : 0.0;
+      if (!(fabs(D[ch]) > 1e-14 * (fabs(AD[ch]) + fabs(t)))) bad = true;
+      const double di = 1.0 / D[ch];
+      FA[ch] = -l;
+      FDI[ch] = di;
+      FB[ch] = k <= L - 2 ? -HI[ch] * di : 0.0;
+      TA[ch] = k >= 1 ? -HM1[ch] * di : 0.0;
+      TDI[ch] = di;
+      TB[ch] = k <= L - 2 ? -LP1[ch] * di : 0.0;
+    } else {
+      const int i = k - L < 3 ? k - L : 0;
+      FA[ch] = Fi[i][0];
+      FDI[ch] = Fi[i][1];
+      FB[ch] = Fi[i][2];
+      TA[ch] = Fi[0][i];
+      TDI[ch] = Fi[1][i];
+      TB[ch] = Fi[2][i];
+    }
   }
-  prev = 0.0;
-  for (int k = L - 1; k >= 0; --k) {
-    prev = fA[P_DINV * mp + k] * w[k] + fA[P_B * mp + k] * prev;
-    w[k] = prev;
-  }
-  for (int i = 0; i < 3; ++i)
-    w[L + i] = Fi[i][0] * uC[L] + Fi[i][1] * uC[L + 1] + Fi[i][2] * uC[L + 2];
-  // SMW-2: capacitance C = 1 + v . w
+  // SMW-1: w = A0^{-1} u_cC ; SMW-2: C = 1 + v . w
+  const double uf0 = uC[L], uf1 = uC[L + 1], uf2 = uC[L + 2];
+  double W[NCH];
+  smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, uf0, uf1, uf2, W);
   double vw = 0.0, vv = 0.0, ww = 0.0;
-  for (int k = 0; k < m; ++k) {
-    vw += vC[k] * w[k];
-    vv += vC[k] * vC[k];
-    ww += w[k] * w[k];
-    fA[P_V * mp + k] = vC[k];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const bool in = ch * WAVE + lane < m;
+    vw += in ? V[ch] * W[ch] : 0.0;
+    vv += in ? V[ch] * V[ch] : 0.0;
+    ww += in ? W[ch] * W[ch] : 0.0;
   }
+  vw = wave_sum_u(vw);
+  vv = wave_sum_u(vv);
+  ww = wave_sum_u(ww);
   const double C = 1.0 + vw;
   if (!(fabs(C) > 1e-12 * (1.0 + sqrt(vv * ww)))) bad = true;
-  invC[c] = 1.0 / C;
 
-  if (fT) {  // wt = A0^{-T} v_cC, used by the transposed apply
-    double* wt = fT + P_W * mp;
-    prev = 0.0;
-    for (int k = 0; k < L; ++k) {
-      prev = fT[P_DINV * mp + k] * vC[k] + fT[P_A * mp + k] * prev;
-      wt[k] = prev;
+  double* fA = facF + (long long)c * F_SMW * mp;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    if (k < mp) {
+      const bool in = k < m;
+      fA[P_A * mp + k] = in ? FA[ch] : 0.0;
+      fA[P_DINV * mp + k] = in ? FDI[ch] : 0.0;
+      fA[P_B * mp + k] = in ? FB[ch] : 0.0;
+      fA[P_W * mp + k] = in ? W[ch] : 0.0;
+      fA[P_V * mp + k] = in ? V[ch] : 0.0;
     }
-    prev = 0.0;
-    for (int k = L - 1; k >= 0; --k) {
-      prev = wt[k] + fT[P_B * mp + k] * prev;
-      wt[k] = prev;
-    }
-    for (int i = 0; i < 3; ++i)
-      wt[L + i] = Fi[0][i] * vC[L] + Fi[1][i] * vC[L + 1] + Fi[2][i] * vC[L + 2];
-    for (int k = 0; k < m; ++k) fT[P_V * mp + k] = uC[k];
   }
-  if (bad) atomicMin(status, c);
+  if (facT) {  // wt = A0^{-T} v_cC, used by the transposed apply
+    const double vf0 = vC[L], vf1 = vC[L + 1], vf2 = vC[L + 2];
+    double WT[NCH];
+    smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V, vf0, vf1, vf2, WT);
+    // flow rows of the transposed record hold the transposed corner inverse
+    double* fT = facT + (long long)c * F_SMW * mp;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      if (k < mp) {
+        const bool in = k < m;
+        fT[P_A * mp + k] = in ? TA[ch] : 0.0;
+        fT[P_DINV * mp + k] = in ? TDI[ch] : 0.0;
+        fT[P_B * mp + k] = in ? TB[ch] : 0.0;
+        fT[P_W * mp + k] = in ? WT[ch] : 0.0;
+        fT[P_V * mp + k] = in ? U[ch] : 0.0;
+      }
+    }
+  }
+  if (lane == 0) invC[c] = 1.0 / C;
+  const unsigned long long anybad = __ballot(bad);
+  if (anybad && lane == 0) atomicMin(status, c);
 }
 
 hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
                             double* invC, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_smw_setup, dim3((g.N + 255) / 256), dim3(256), 0, s, g, rec, facF, facT,
-                     invC, status);
+  const int grid = (g.N + WPB - 1) / WPB;
+  switch ((g.m + WAVE - 1) / WAVE) {
+    case 1: hipLaunchKernelGGL(k_smw_setup<1>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 2: hipLaunchKernelGGL(k_smw_setup<2>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 3: hipLaunchKernelGGL(k_smw_setup<3>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 4: hipLaunchKernelGGL(k_smw_setup<4>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -211,46 +264,12 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
     const int c = c0 + j;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      TV Y[NCH];
-      // forward sweep over the levels: y_k = a_k y_{k-1} + s1_k r_k
-      TV carry = TV(0);
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
-        const int k = ch * WAVE + lane;
-        const bool lev = k < L;
-        TV a = lev ? A[j][ch] : TV(0);
-        TV bb = lev ? (TRANS ? DI[j][ch] * R[j][r][ch] : R[j][r][ch]) : TV(0);
-        if (ch * WAVE < L) {
-          scan_affine_up_dpp(a, bb);
-          Y[ch] = bb + a * carry;
-          carry = readlane(Y[ch], WAVE - 1);
-        } else {
-          Y[ch] = TV(0);
-        }
-      }
-      // backward sweep: x_k = b_k x_{k+1} + s2_k y_k ; flow lanes: corner inverse
-      carry = TV(0);
-      TV s = TV(0);
       TV X0[NCH];
+      smw_sweeps<TV, NCH, TRANS>(L, m, A[j], DI[j], B[j], R[j][r], RF[j][r][0], RF[j][r][1],
+                                 RF[j][r][2], X0);
+      TV s = TV(0);
 #pragma unroll
-      for (int ch = NCH - 1; ch >= 0; --ch) {
-        const int k = ch * WAVE + lane;
-        const bool lev = k < L;
-        TV a = lev ? B[j][ch] : TV(0);
-        TV bb = lev ? (TRANS ? Y[ch] : DI[j][ch] * Y[ch]) : TV(0);
-        TV x0;
-        if (ch * WAVE < L) {
-          scan_affine_down_dpp(a, bb);
-          x0 = bb + a * carry;
-          carry = readlane(x0, 0);
-        } else {
-          x0 = TV(0);
-        }
-        const TV xf = A[j][ch] * RF[j][r][0] + DI[j][ch] * RF[j][r][1] + B[j][ch] * RF[j][r][2];
-        x0 = lev ? x0 : (k < m ? xf : TV(0));
-        X0[ch] = x0;
-        s += V[j][ch] * x0;
-      }
+      for (int ch = 0; ch < NCH; ++ch) s += V[j][ch] * X0[ch];
       s = wave_sum_u(s) * IC[j];
       if (c < g.N) {
         double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;

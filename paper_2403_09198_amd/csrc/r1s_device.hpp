@@ -226,4 +226,87 @@ __device__ inline void scan_affine_down_dpp(T& a, T& b) {
   a = a * sa;
 }
 
+// Inclusive scan of 2x2 matrix products along increasing lane index: lane l
+// ends with P_l = M_l M_{l-1} ... M_0 (later factors on the left).  Rows of
+// 16 lanes by DPP shifts with the identity shifted in, then each row is
+// multiplied by the product of the rows below it.
+template <typename T>
+__device__ inline void mat2_mul(T& a, T& b, T& c, T& d, T e, T f, T g, T h) {
+  // [a b; c d] <- [a b; c d] * [e f; g h]
+  const T na = a * e + b * g, nb = a * f + b * h, nc = c * e + d * g, nd = c * f + d * h;
+  a = na; b = nb; c = nc; d = nd;
+}
+
+template <typename T>
+__device__ inline void scan_mat2_up_dpp(T& a, T& b, T& c, T& d) {
+#define R1S_MSTEP(N)                                \
+  {                                                 \
+    const T e = dpp<DPP_ROW_SHR + N>(T(1), a);      \
+    const T f = dpp<DPP_ROW_SHR + N>(T(0), b);      \
+    const T g_ = dpp<DPP_ROW_SHR + N>(T(0), c);     \
+    const T h = dpp<DPP_ROW_SHR + N>(T(1), d);      \
+    mat2_mul(a, b, c, d, e, f, g_, h);              \
+  }
+  R1S_MSTEP(1) R1S_MSTEP(2) R1S_MSTEP(4) R1S_MSTEP(8)
+#undef R1S_MSTEP
+  const T a0 = readlane(a, 15), b0 = readlane(b, 15), c0 = readlane(c, 15), d0 = readlane(d, 15);
+  T a1 = readlane(a, 31), b1 = readlane(b, 31), c1 = readlane(c, 31), d1 = readlane(d, 31);
+  T a2 = readlane(a, 47), b2 = readlane(b, 47), c2 = readlane(c, 47), d2 = readlane(d, 47);
+  // products entering rows 1, 2, 3
+  mat2_mul(a1, b1, c1, d1, a0, b0, c0, d0);  // R1 R0
+  mat2_mul(a2, b2, c2, d2, a1, b1, c1, d1);  // R2 R1 R0
+  const int row = lane_id() >> 4;
+  const T pa = row == 0 ? T(1) : row == 1 ? a0 : row == 2 ? a1 : a2;
+  const T pb = row == 0 ? T(0) : row == 1 ? b0 : row == 2 ? b1 : b2;
+  const T pc = row == 0 ? T(0) : row == 1 ? c0 : row == 2 ? c1 : c2;
+  const T pd = row == 0 ? T(1) : row == 1 ? d0 : row == 2 ? d1 : d2;
+  mat2_mul(a, b, c, d, pa, pb, pc, pd);
+}
+
+// The two bidiagonal sweeps of the SMW local solve over NCH chunks of 64
+// unknowns held by one wave, then the 3 x 3 flow corner.
+//   forward  y_k = A_k y_{k-1} + (TRANS ? DI_k R_k : R_k)
+//   backward x_k = B_k x_{k+1} + (TRANS ? y_k : DI_k y_k)
+//   flow lanes x_{L+i} = A rf0 + DI rf1 + B rf2 (the lane's corner-inverse row)
+template <typename T, int NCH, bool TRANS>
+__device__ inline void smw_sweeps(int L, int m, const T (&A)[NCH], const T (&DI)[NCH],
+                                  const T (&B)[NCH], const T (&R)[NCH], T rf0, T rf1, T rf2,
+                                  T (&X0)[NCH]) {
+  const int lane = lane_id();
+  T Y[NCH];
+  T carry = T(0);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const bool lev = k < L;
+    T a = lev ? A[ch] : T(0);
+    T bb = lev ? (TRANS ? DI[ch] * R[ch] : R[ch]) : T(0);
+    if (ch * WAVE < L) {
+      scan_affine_up_dpp(a, bb);
+      Y[ch] = bb + a * carry;
+      carry = readlane(Y[ch], WAVE - 1);
+    } else {
+      Y[ch] = T(0);
+    }
+  }
+  carry = T(0);
+#pragma unroll
+  for (int ch = NCH - 1; ch >= 0; --ch) {
+    const int k = ch * WAVE + lane;
+    const bool lev = k < L;
+    T a = lev ? B[ch] : T(0);
+    T bb = lev ? (TRANS ? Y[ch] : DI[ch] * Y[ch]) : T(0);
+    T x0;
+    if (ch * WAVE < L) {
+      scan_affine_down_dpp(a, bb);
+      x0 = bb + a * carry;
+      carry = readlane(x0, 0);
+    } else {
+      x0 = T(0);
+    }
+    const T xf = A[ch] * rf0 + DI[ch] * rf1 + B[ch] * rf2;
+    X0[ch] = lev ? x0 : (k < m ? xf : T(0));
+  }
+}
+
 }  // namespace r1s
