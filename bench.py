@@ -277,6 +277,74 @@ def sweep(torch, levels=(32, 61, 120, 200), steps=50, warm=5):
     return rows
 
 
+def solvers(torch):
+    """Time-to-solution of the mixed-precision and adjoint workloads."""
+    from paper_2403_09198_amd import autograd, gen, r1s
+
+    dev = "cuda:0"
+    # mixed precision: 512 x 256, L = 200, GMRES(50) to 1e-10
+    w = gen.WORKLOADS["mesh512x256_L200"]
+    log(f"solvers: {w.name}")
+    p = gen.make_problem(w.nx, w.ny, w.L, seed=w.seed)
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
+    del p
+    A = r1s.R1Matrix(w.nx, w.ny, w.L, vals, keep_f32=True)
+    del vals
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = r1s.SMWPreconditioner(A, keep_f32=True)
+    t_setup = time.perf_counter() - t0
+    b = torch.from_numpy(gen.make_rhs(w.nx, w.ny, w.L, seed=w.seed)).to(dev)
+    row = {"workload": w.name, "smw_setup_ms": round(t_setup * 1e3, 2)}
+    xs = {}
+    for tag, kw in (("f64", dict(mode="f64")),
+                    ("mixed_ir", dict(mode="mixed", inner_rtol=1e-6, max_outer=10)),
+                    ("f32_inner_only", dict(mode="mixed", inner_rtol=1e-6, max_outer=1))):
+        r1s.gmres(A, M, b, restart=50, rtol=1e-10, raise_on_noconv=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = r1s.gmres(A, M, b, restart=50, rtol=1e-10, raise_on_noconv=False, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        xs[tag] = res.x
+        st = res.stats[0]
+        row[tag] = {"ms": round(el * 1e3, 2), "iters": st["iters"], "outer": st["outer"],
+                    "rel_residual_f64": st["rel_residual"], "converged": bool(st["converged"])}
+    ref = xs["f64"]
+    for tag in ("mixed_ir", "f32_inner_only"):
+        row[tag]["rel_diff_vs_f64_solve"] = float(torch.linalg.norm(xs[tag] - ref) /
+                                                  torch.linalg.norm(ref))
+    row["mixed_speedup"] = round(row["f64"]["ms"] / row["mixed_ir"]["ms"], 3)
+    print(json.dumps(row), flush=True)
+    del A, M, b, xs, ref
+    torch.cuda.empty_cache()
+
+    # adjoint: 256 x 128, L = 61, batch of 8, loss = sum w . x
+    w = gen.WORKLOADS["adjoint256x128_L61_b8"]
+    log(f"solvers: {w.name}")
+    p = gen.make_problem(w.nx, w.ny, w.L, seed=w.seed)
+    params = {k: torch.from_numpy(p[k]).to(dev).requires_grad_(True) for k in gen.FIELDS}
+    b = torch.from_numpy(gen.make_rhs(w.nx, w.ny, w.L, nrhs=w.nrhs, seed=w.seed)).to(dev)
+    wt = torch.from_numpy(gen.make_loss_weights(w.nx, w.ny, w.L, nrhs=w.nrhs, seed=w.seed)).to(dev)
+    b.requires_grad_(True)
+    row = {"workload": w.name, "nrhs": w.nrhs}
+    for rep in range(2):  # the second repetition is timed
+        for t in list(params.values()) + [b]:
+            t.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = autograd.solve(b, params, w.nx, w.ny, w.L, restart=50, rtol=1e-10)
+        loss = (x * wt).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    row["forward_ms"] = round((t1 - t0) * 1e3, 2)
+    row["backward_ms"] = round((t2 - t1) * 1e3, 2)
+    print(json.dumps(row), flush=True)
+
+
 def cpu_baseline(p, nx, ny, L, budget_s=12.0):
     """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
     sample of block rows (blocks assembled and factored beforehand), repeated
@@ -328,6 +396,8 @@ def main():
                     help="only the FP64 pair (for profiling runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary from two --pmc runs of --profile-pass")
+    ap.add_argument("--solvers", action="store_true",
+                    help="mixed-precision and adjoint time-to-solution (one JSON line each)")
     ap.add_argument("--sweep", action="store_true",
                     help="512x256 level sweep against the BSR baseline (one JSON line per case)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -347,6 +417,9 @@ def main():
 
     if args.sweep:
         sweep(torch)
+        return
+    if args.solvers:
+        solvers(torch)
         return
     w = gen.WORKLOADS[args.workload]
     nx, ny, L, m, N = w.nx, w.ny, w.L, w.m, w.N

@@ -135,6 +135,8 @@ typedef struct {
   int mode;         /* R1S_MODE_F64 or R1S_MODE_MIXED_IR                    */
   double inner_rtol;/* mixed mode: relative tolerance of each inner solve   */
   int max_outer;    /* mixed mode: iterative-refinement steps               */
+  int always_reorth;/* 1: reorthogonalise every Arnoldi step (CGS2); 0: only
+                       when |w - V h| < |w| / sqrt(2) (selective CGS)       */
 } r1s_gmres_opts;
 
 typedef struct {
@@ -227,7 +229,8 @@ int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
 
 /* Restarted right-preconditioned GMRES (section 6): solves (J M) y = b and
  * returns x = M y, for nrhs independent right-hand sides advanced together.
- * Classical Gram-Schmidt with one reorthogonalisation, float64.  Mixed mode
+ * Classical Gram-Schmidt with selective (or, with always_reorth, unconditional)
+ * reorthogonalisation, float64.  Mixed mode
  * wraps float32-operator inner solves in float64 iterative refinement.
  * `B` is used when opts->op == R1S_OP_BSR (may be NULL otherwise).
  * On R1S_ERR_NOCONV, x holds the last iterate and stats are filled (one

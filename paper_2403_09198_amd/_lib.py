@@ -48,7 +48,7 @@ class Storage(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double),
                 ("trans", C.c_int), ("x0_given", C.c_int), ("op", C.c_int), ("mode", C.c_int),
-                ("inner_rtol", C.c_double), ("max_outer", C.c_int)]
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("always_reorth", C.c_int)]
 
 
 class GmresStats(C.Structure):

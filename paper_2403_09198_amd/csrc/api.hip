@@ -603,7 +603,7 @@ struct SolveStat {
 // from x (x0_given) or zero.  rtol is relative to |b| per right-hand side.
 static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
                       double rtol, int nrhs, const double* b, double* x, bool x0_given,
-                      std::vector<SolveStat>& st) {
+                      bool always_reorth, std::vector<SolveStat>& st) {
   hipStream_t s = c.s;
   const long long n = g.n;
   const int HS = k + 2;  // stride of the per-rhs h arrays
@@ -659,33 +659,49 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
       const int nv = j + 1;
-      // CGS pass 1: h1 = V^T w, |w|^2 ; w -= V h1
+      // Classical Gram-Schmidt: h1 = V^T w and |w|^2 in one pass.  The norm
+      // of w - V h1 follows from |w|^2 - |h1|^2 (V orthonormal); a second
+      // pass (reorthogonalisation) runs only when that norm drops below
+      // |w| / sqrt(2) for some right-hand side (Daniel-Gragg-Kaufman-Stewart
+      // criterion), where the subtraction would lose accuracy.
       HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
       HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, W.hdev, s));
-      HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
-      // CGS pass 2: h2 = V^T w, |w|^2
-      double* h2 = W.hdev + (size_t)nrhs * HS;
-      HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
-      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
-      // v_{j+1} = (w - V h2) / |w - V h2|
-      HIP_TRY(launch_update_normalize(Vb, nv, h2, nv + 1, h2 + nv, nv + 1, W.w, n,
-                                      W.V + (long long)(j + 1) * n, n, nrhs, s));
       HIP_TRY(hipMemcpyAsync(hbuf.data(), W.hdev, (size_t)nrhs * (nv + 1) * sizeof(double),
                              hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)nrhs * HS, h2,
-                             (size_t)nrhs * (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+      bool reorth = always_reorth;
+      for (int r = 0; r < nrhs; ++r) {
+        if (done[r]) continue;
+        const double* h1r = hbuf.data() + (size_t)r * (nv + 1);
+        double hh = 0.0;
+        for (int i = 0; i < nv; ++i) hh += h1r[i] * h1r[i];
+        if (!(h1r[nv] - hh > 0.5 * h1r[nv])) reorth = true;
+      }
+      double* h2 = W.hdev + (size_t)nrhs * HS;
+      if (reorth) {
+        HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
+        HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+        HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
+        HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)nrhs * HS, h2,
+                               (size_t)nrhs * (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+      // v_{j+1} = (w - V h) / |w - V h| with h the last pass's coefficients
+      const double* hlast = reorth ? h2 : W.hdev;
+      HIP_TRY(launch_update_normalize(Vb, nv, hlast, nv + 1, hlast + nv, nv + 1, W.w, n,
+                                      W.V + (long long)(j + 1) * n, n, nrhs, s));
+      if (reorth) HIP_TRY(hipStreamSynchronize(s));
       bool all_done = true;
       for (int r = 0; r < nrhs; ++r) {
         if (done[r]) continue;
         const double* h1r = hbuf.data() + (size_t)r * (nv + 1);
         const double* h2r = hbuf.data() + (size_t)nrhs * HS + (size_t)r * (nv + 1);
+        const double* hl = reorth ? h2r : h1r;  // the pass the new vector comes from
         double hh = 0.0;
         for (int i = 0; i < nv; ++i) {
-          Hat(r, i, j) = h1r[i] + h2r[i];
-          hh += h2r[i] * h2r[i];
+          Hat(r, i, j) = h1r[i] + (reorth ? h2r[i] : 0.0);
+          hh += hl[i] * hl[i];
         }
-        const double q = h2r[nv] - hh;
+        const double q = hl[nv] - hh;
         const double hn = q > 0.0 ? sqrt(q) : 0.0;
         const double wnorm0 = sqrt(h1r[nv]);
         Hat(r, j + 1, j) = hn;
@@ -773,7 +789,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
   int rc;
   if (!mixed) {
     rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
-                    opts->x0_given != 0, st);
+                    opts->x0_given != 0, opts->always_reorth != 0, st);
     if (rc) return rc;
   } else {
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
@@ -796,7 +812,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
       if (all || outer == opts->max_outer) break;
       std::vector<SolveStat> in;
       rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs, W.r64,
-                      W.d, false, in);
+                      W.d, false, opts->always_reorth != 0, in);
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r) {
         tot[r].iters += in[r].iters;
