@@ -679,8 +679,13 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       double* h2 = W.hdev + (size_t)nrhs * HS;
       if (reorth) {
-        HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
-        HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+        if (nv <= update_multidot_max()) {  // w -= V h1 and V^T w in one pass
+          HIP_TRY(launch_update_multidot(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, W.part,
+                                         W.nblk, s));
+        } else {
+          HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
+          HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+        }
         HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
         HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)nrhs * HS, h2,
                                (size_t)nrhs * (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));

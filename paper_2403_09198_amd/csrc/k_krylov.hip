@@ -109,6 +109,68 @@ static inline dim3 vec_grid(long long n, int nrhs) {
   return dim3((unsigned)b, nrhs);
 }
 
+// Fused reorthogonalisation pass for small bases (nv <= NVMAX): each thread
+// loads V_i[e] once into registers, forms w1[e] = w[e] - sum_i h_i V_i[e],
+// stores it, and accumulates V_i[e] w1[e] and w1[e]^2 for the next
+// coefficients (partials per block, reduced by k_reduce as for k_multidot).
+template <int NVMAX>
+__global__ __launch_bounds__(KB) void k_update_multidot(Basis B, int nv, const double* __restrict__ h,
+                                                        int hstride, double* __restrict__ w,
+                                                        long long wstride, long long n,
+                                                        double* __restrict__ part, int nblk) {
+  __shared__ double sh[KB / WAVE];
+  const int r = blockIdx.y;
+  const double* Vr = B.V + (long long)r * B.rstride;
+  const double* hr = h + (long long)r * hstride;
+  double* wr = w + (long long)r * wstride;
+  double hv[NVMAX], acc[NVMAX];
+#pragma unroll
+  for (int i = 0; i < NVMAX; ++i) {
+    hv[i] = i < nv ? hr[i] : 0.0;
+    acc[i] = 0.0;
+  }
+  double accn = 0.0;
+  const long long stride = (long long)nblk * KB;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n; e += stride) {
+    double v[NVMAX];
+    double a = wr[e];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) {
+      v[i] = i < nv ? Vr[(long long)i * B.vstride + e] : 0.0;
+      a -= hv[i] * v[i];
+    }
+    wr[e] = a;
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) acc[i] += v[i] * a;
+    accn += a * a;
+  }
+  double* pr = part + (long long)r * (nv + 1) * nblk;
+#pragma unroll
+  for (int i = 0; i < NVMAX; ++i) {
+    if (i >= nv) break;
+    const double t = block_sum(acc[i], sh);
+    if (threadIdx.x == 0) pr[(long long)i * nblk + blockIdx.x] = t;
+  }
+  const double t = block_sum(accn, sh);
+  if (threadIdx.x == 0) pr[(long long)nv * nblk + blockIdx.x] = t;
+}
+
+int update_multidot_max() { return 16; }
+
+hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride, double* w,
+                                  long long wstride, long long n, int nrhs, double* part, int nblk,
+                                  hipStream_t s) {
+  if (nv <= 8)
+    hipLaunchKernelGGL(k_update_multidot<8>, dim3(nblk, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
+                       w, wstride, n, part, nblk);
+  else if (nv <= 16)
+    hipLaunchKernelGGL(k_update_multidot<16>, dim3(nblk, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
+                       w, wstride, n, part, nblk);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 // w -= sum_i h[r*hstride + i] V_i
 __global__ __launch_bounds__(KB) void k_update(Basis B, int nv, const double* __restrict__ h,
                                                int hstride, double* __restrict__ w,
@@ -132,8 +194,10 @@ hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* 
 }
 
 // vout = (w - sum_i h_i V_i) / sqrt(max(0, nrm2 - sum_i h_i^2)); zero if that
-// norm is zero.  The norm of the reorthogonalised vector follows from the
-// norm before the second pass because V is orthonormal.
+// norm is zero.  The norm of the new vector follows from the norm before
+// this pass because V is orthonormal.  NVMAX > 0: the basis values of an
+// element are all loaded before use (nv <= NVMAX); NVMAX = 0: any nv.
+template <int NVMAX>
 __global__ __launch_bounds__(KB) void k_update_normalize(Basis B, int nv,
                                                          const double* __restrict__ h, int hstride,
                                                          const double* __restrict__ nrm2,
@@ -149,11 +213,27 @@ __global__ __launch_bounds__(KB) void k_update_normalize(Basis B, int nv,
   for (int i = 0; i < nv; ++i) hh += hr[i] * hr[i];
   const double q = nrm2[(long long)r * nstride] - hh;
   const double inv = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
-  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
-       e += (long long)gridDim.x * KB) {
-    double a = wr[e];
-    for (int i = 0; i < nv; ++i) a -= hr[i] * Vr[(long long)i * B.vstride + e];
-    vr[e] = a * inv;
+  if constexpr (NVMAX > 0) {
+    double hv[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) hv[i] = i < nv ? hr[i] : 0.0;
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
+         e += (long long)gridDim.x * KB) {
+      double v[NVMAX];
+#pragma unroll
+      for (int i = 0; i < NVMAX; ++i) v[i] = i < nv ? Vr[(long long)i * B.vstride + e] : 0.0;
+      double a = wr[e];
+#pragma unroll
+      for (int i = 0; i < NVMAX; ++i) a -= hv[i] * v[i];
+      vr[e] = a * inv;
+    }
+  } else {
+    for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
+         e += (long long)gridDim.x * KB) {
+      double a = wr[e];
+      for (int i = 0; i < nv; ++i) a -= hr[i] * Vr[(long long)i * B.vstride + e];
+      vr[e] = a * inv;
+    }
   }
 }
 
@@ -161,8 +241,15 @@ hipError_t launch_update_normalize(Basis B, int nv, const double* h, int hstride
                                    const double* nrm2, int nstride, const double* w,
                                    long long wstride, double* vout, long long n, int nrhs,
                                    hipStream_t s) {
-  hipLaunchKernelGGL(k_update_normalize, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
-                     nrm2, nstride, w, wstride, vout, n);
+  if (nv <= 8)
+    hipLaunchKernelGGL(k_update_normalize<8>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
+                       nrm2, nstride, w, wstride, vout, n);
+  else if (nv <= 16)
+    hipLaunchKernelGGL(k_update_normalize<16>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h,
+                       hstride, nrm2, nstride, w, wstride, vout, n);
+  else
+    hipLaunchKernelGGL(k_update_normalize<0>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
+                       nrm2, nstride, w, wstride, vout, n);
   return hipGetLastError();
 }
 

@@ -58,6 +58,10 @@ int dot_blocks(long long n);
 hipError_t launch_multidot(Basis B, int nv, const double* w, long long wstride, long long n,
                            int nrhs, double* part, int nblk, bool with_norm, hipStream_t s);
 hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hipStream_t s);
+int update_multidot_max();
+hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride, double* w,
+                                  long long wstride, long long n, int nrhs, double* part, int nblk,
+                                  hipStream_t s);
 hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* w,
                          long long wstride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_update_normalize(Basis B, int nv, const double* h, int hstride,

@@ -284,7 +284,7 @@ class GmresResult:
 
 
 def gmres(A: R1Matrix, M, b, x0=None, restart=50, rtol=1e-10, max_cycles=200, trans=False,
-          op="structured", B: Optional[BSRMatrix] = None, mode="f64", inner_rtol=1e-6,
+          op="structured", B: Optional[BSRMatrix] = None, mode="f64", inner_rtol=1e-5,
           max_outer=10, always_reorth=False, raise_on_noconv=True, work=None,
           stream=None) -> GmresResult:
     """Restarted right-preconditioned GMRES through r1s_gmres."""
