@@ -2,10 +2,9 @@
 
 Section 4 ("Overall Structure"): every non-zero m x m block of J is an
 r1-sparse matrix, the sum of a sparse block and rank-one updates (the
-definition of r1-sparsity in section 4.1).  Here each existing block (c, d)
-carries exactly one pair:
+definition of r1-sparsity in section 4.1):
 
-    D_{c,d} = S_{c,d} + u_{c,d} v_{c,d}^T.
+    D_{c,d} = S_{c,d} + sum over the block's pairs p of  u_p v_p^T.
 
 S_{c,C} (the diagonal block) has a full diagonal, a tridiagonal band coupling
 neighbouring levels k, k+1 (k < L) and a dense 3 x 3 corner for the flow
@@ -43,8 +42,12 @@ def sparse_block(p, c: int, d: int, L: int) -> np.ndarray:
 
 
 def dense_block(p, c: int, d: int, L: int) -> np.ndarray:
-    """D_{c,d} = S_{c,d} + u_{c,d} v_{c,d}^T."""
-    return sparse_block(p, c, d, L) + np.outer(p["u"][c, d], p["v"][c, d])
+    """D_{c,d} = S_{c,d} + sum_p u_p v_p^T over the pairs of block (c, d)."""
+    D = sparse_block(p, c, d, L)
+    a, cnt = mesh.pair_range(p, d)
+    for q in range(a, a + cnt):
+        D = D + np.outer(p["u"][c, q], p["v"][c, q])
+    return D
 
 
 def assemble_bsr(p, nx: int, ny: int, L: int, cells=None):

@@ -18,6 +18,8 @@ uses that sign; a test shows the printed sign fails to invert the block.
 """
 import numpy as np
 
+from . import mesh
+
 
 class SingularBlock(ArithmeticError):
     pass
@@ -129,17 +131,18 @@ def sparse_diag_solve(p, c, L, r):
 
 
 def smw_solve(p, c, L, r, sign=-1.0):
-    """Solve D_{c,C} x = r with D = A0 + u v^T by the three SMW steps of
-    section 6: (SMW-1) x0 = A0^{-1} r and w = A0^{-1} u; (SMW-2) C z = v . x0
-    with C = 1 + v . w; assemble x = x0 + sign * w z.  sign = -1 is the
-    correct identity; sign = +1 reproduces the printed one."""
-    u = p["u"][c, 2]
-    v = p["v"][c, 2]
+    """Solve D_{c,C} x = r with D = A0 + U V^T (eq. R1_Block_Jacobian) by the
+    three SMW steps of section 6: (SMW-1) x0 = A0^{-1} r and W = A0^{-1} U;
+    (SMW-2) C z = V^T x0 with C = I + V^T W; assemble x = x0 + sign * W z.
+    sign = -1 is the correct identity; sign = +1 reproduces the printed one."""
+    a, cnt = mesh.pair_range(p, 2)
+    U = p["u"][c, a:a + cnt].T  # m x r
+    V = p["v"][c, a:a + cnt].T
     x0 = sparse_diag_solve(p, c, L, r)
-    w = sparse_diag_solve(p, c, L, u)
-    Cs = 1.0 + float(np.dot(v, w))
-    z = float(np.dot(v, x0)) / Cs
-    return x0 + sign * w * z
+    W = np.column_stack([sparse_diag_solve(p, c, L, U[:, i]) for i in range(cnt)])
+    Cm = np.eye(cnt) + V.T @ W
+    z = np.linalg.solve(Cm, V.T @ x0)
+    return x0 + sign * (W @ z)
 
 
 def smw_inverse(p, c, L, sign=-1.0):

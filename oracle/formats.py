@@ -180,14 +180,15 @@ def structured_csr(p, nx, ny, L):
 
 
 def structured_br1(p, nx, ny):
-    """BR1-BSR arrays of the block rank-one part (one pair per block)."""
+    """BR1-BSR arrays of the block rank-one part (all pairs of every block)."""
     N = nx * ny
     blocks = []
     for c in range(N):
         for d in (mesh.S, mesh.W, mesh.C, mesh.E, mesh.N):
             nb = mesh.neighbour(nx, ny, c, d)
             if nb >= 0:
-                blocks.append((c, nb, [(p["u"][c, d], p["v"][c, d])]))
+                a, cnt = mesh.pair_range(p, d)
+                blocks.append((c, nb, [(p["u"][c, q], p["v"][c, q]) for q in range(a, a + cnt)]))
     return br1_bsr(blocks, N)
 
 

@@ -36,8 +36,10 @@ def structured_grads(p, nx, ny, L, lam, x):
             if nb < 0:
                 continue
             G = -np.einsum("ri,rj->ij", lam[:, c, :], x[:, nb, :])
-            g["u"][c, d] = G @ p["v"][c, d]
-            g["v"][c, d] = G.T @ p["u"][c, d]
+            a, cnt = mesh.pair_range(p, d)
+            for q in range(a, a + cnt):
+                g["u"][c, q] = G @ p["v"][c, q]
+                g["v"][c, q] = G.T @ p["u"][c, q]
             if d == mesh.C:
                 g["s_diag"][c] = np.diag(G)
                 for k in range(L - 1):

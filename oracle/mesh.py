@@ -46,6 +46,20 @@ def neighbour_table_row(nx: int, ny: int, c: int):
     return [neighbour(nx, ny, c, d) for d in range(5)]
 
 
+def pair_range(p, d: int):
+    """Slots (start, count) of the rank-one pairs of the block in direction d.
+
+    Section 4 ("Overall Structure"): a diagonal block carries the source
+    term's pair and two per face, an off-diagonal block the two trace-flux
+    pairs.  The arrays u, v hold the pairs of a cell's blocks one after the
+    other in the order S, W, C, E, N: r_off pairs for each neighbour block,
+    r_diag for the diagonal block (p["ranks"] = [r_diag, r_off], default one
+    pair each)."""
+    r_diag, r_off = (int(v) for v in p.get("ranks", (1, 1)))
+    counts = [r_off, r_off, r_diag, r_off, r_off]
+    return sum(counts[:d]), counts[d]
+
+
 def opposite(d: int) -> int:
     """The direction pointing back: the neighbour's block towards c."""
     return {S: N, W: E, C: C, E: W, N: S}[d]

@@ -26,9 +26,10 @@ def bsr_values(nx: int, ny: int, m: int) -> int:
     return n_blocks(nx, ny) * m * m
 
 
-def structured_values(nx: int, ny: int, m: int, pairs_per_block: int = 1) -> int:
+def structured_values(nx: int, ny: int, m: int, r_diag: int = 1, r_off: int = 1) -> int:
+    """r_diag pairs on every diagonal block, r_off on every neighbour block."""
     N = nx * ny
     B = n_blocks(nx, ny)
     L = m - 3
     diag_block = m + 2 * (L - 1) + 6
-    return N * diag_block + (B - N) * m + B * pairs_per_block * 2 * m
+    return N * diag_block + (B - N) * m + (N * r_diag + (B - N) * r_off) * 2 * m

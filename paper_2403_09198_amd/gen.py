@@ -7,8 +7,8 @@ library and the CPU oracle consume exactly the arrays produced here.
 Problem family (the first-order finite-volume Jacobian of section 3 with the
 block structure of section 4, "Overall Structure"): a structured nx x ny mesh,
 5-point block stencil, block size m = L + 3 (L level densities, two momenta,
-energy).  Every existing block (c, d) is  S_{c,d} + u_{c,d} v_{c,d}^T  with one
-rank-one pair (the block-wise rank-one representation of section 4).
+energy).  Every existing block (c, d) is  S_{c,d} + sum_p u_p v_p^T  over its
+rank-one pairs (the block-wise rank-one representation of section 4).
 
 Array layout (all float64, C-contiguous; N = nx*ny, cell c = iy*nx + ix):
 
@@ -18,9 +18,15 @@ Array layout (all float64, C-contiguous; N = nx*ny, cell c = iy*nx + ix):
   s_flow [N][6]      flow-corner off-diagonals (rows/cols L..L+2) in the order
                      (0,1) (0,2) (1,0) (1,2) (2,0) (2,1)
   s_nbr  [N][4][m]   diagonals of the neighbour blocks S_{c,d}, d in S,W,E,N
-  u, v   [N][5][m]   rank-one pairs, d in S,W,C,E,N
+  u, v   [N][P][m]   rank-one pairs grouped by block in the order S, W, C, E, N:
+                     r_off pairs for each neighbour block and r_diag for the
+                     diagonal block, P = r_diag + 4 r_off (P = 5 for one pair
+                     per block)
 
 Directions: 0 = S (iy-1), 1 = W (ix-1), 2 = C, 3 = E (ix+1), 4 = N (iy+1).
+The paper's structure (section 4, "Overall Structure") has r_diag = 9 (one
+source term and two per face) and r_off = 2 (two trace-flux terms); the
+synthetic workloads default to one pair per block.
 The mesh is not periodic: a boundary cell simply has no block towards the
 missing neighbour, and the slots for such blocks are zero.
 
@@ -80,6 +86,8 @@ WORKLOADS: Dict[str, Workload] = {
     "adjoint256x128_L61_b8": Workload("adjoint256x128_L61_b8", 256, 128, 61,
                                       nrhs=8),
 }
+# The paper's rank structure: 9 pairs on diagonal blocks, 2 on the others.
+PAPER_RANKS = (9, 2)
 
 
 def block_exists(nx: int, ny: int) -> np.ndarray:
@@ -93,12 +101,23 @@ def block_exists(nx: int, ny: int) -> np.ndarray:
     return ex
 
 
-def make_problem(nx: int, ny: int, L: int, seed: int = 0,
-                 inv_dt: float = 20.0) -> Dict[str, np.ndarray]:
-    """Draw the structured values of one Jacobian (float64 arrays)."""
+def pair_slots(r_diag: int = 1, r_off: int = 1):
+    """(first slot, count) of the pairs of each block direction S, W, C, E, N."""
+    counts = (r_off, r_off, r_diag, r_off, r_off)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    return [(int(a), int(b)) for a, b in zip(starts, counts)]
+
+
+def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
+                 r_diag: int = 1, r_off: int = 1) -> Dict[str, np.ndarray]:
+    """Draw the structured values of one Jacobian (float64 arrays).  The
+    returned dict also holds "ranks" = [r_diag, r_off]."""
     if nx < 1 or ny < 1 or L < 1:
         raise ValueError("nx, ny, L must be >= 1")
+    if r_diag < 1 or r_off < 0:
+        raise ValueError("need r_diag >= 1 and r_off >= 0")
     N, m = nx * ny, L + 3
+    P = r_diag + 4 * r_off
     rng = np.random.default_rng(seed)
     p = {}
     p["s_diag"] = inv_dt + 10.0 * np.abs(rng.standard_normal((N, m)))
@@ -106,15 +125,17 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0,
     p["s_sup"] = rng.standard_normal((N, L - 1))
     p["s_flow"] = rng.standard_normal((N, 6))
     p["s_nbr"] = rng.uniform(-1.0, 0.0, size=(N, 4, m))
-    p["u"] = 0.1 * rng.standard_normal((N, 5, m))
-    p["v"] = 0.1 * rng.standard_normal((N, 5, m))
+    p["u"] = 0.1 * rng.standard_normal((N, P, m))
+    p["v"] = 0.1 * rng.standard_normal((N, P, m))
     ex = block_exists(nx, ny)
     for j, d in enumerate(NBR_DIRS):
         p["s_nbr"][~ex[:, d], j, :] = 0.0
-    p["u"][~ex] = 0.0
-    p["v"][~ex] = 0.0
+    for d, (a, cnt) in enumerate(pair_slots(r_diag, r_off)):
+        p["u"][~ex[:, d], a:a + cnt, :] = 0.0
+        p["v"][~ex[:, d], a:a + cnt, :] = 0.0
     for k in FIELDS:
         p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
+    p["ranks"] = np.array([r_diag, r_off])
     return p
 
 
