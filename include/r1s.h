@@ -4,11 +4,17 @@
  * C ABI of libr1s.so.  The Jacobian of a first-order finite-volume
  * discretisation on a structured nx x ny mesh (5-point block stencil, blocks
  * of size m = L + 3: L level densities, two momenta, energy) is held as a
- * fully sparse matrix S plus one rank-one pair per block, the "block
- * r1-sparse" representation of section 4 (Overall Structure) and section 5.1
- * (BR1-BSR format):
+ * fully sparse matrix S plus rank-one pairs per block, the "block r1-sparse"
+ * representation of section 4 (Overall Structure) and section 5.1 (BR1-BSR
+ * format, where the pair count differs between diagonal and off-diagonal
+ * blocks):
  *
- *     J = S + sum over blocks (c, d) of  u_{c,d} v_{c,d}^T .
+ *     J = S + sum over blocks (c, d) of  sum_p u_{c,d,p} v_{c,d,p}^T .
+ *
+ * Every diagonal block carries r_diag pairs and every neighbour block r_off
+ * (section 4, Overall Structure: 9 and 2 for the state-to-state model, one
+ * temporal-source pair plus two per trace flux; 1 and 1 is the smallest
+ * layout).  Supported: 1 <= r_diag <= 9, 0 <= r_off <= 2.
  *
  * The library multiplies by J and J^T (section 5.2), applies the block-Jacobi
  * preconditioner through the Sherman-Morrison-Woodbury identity (section 6,
@@ -48,7 +54,9 @@
  *   s_flow [N][6]     flow-corner off-diagonals of S_{c,C} (rows/columns
  *                     L..L+2) in the order (0,1) (0,2) (1,0) (1,2) (2,0) (2,1)
  *   s_nbr  [N][4][m]  diagonals of the neighbour blocks S_{c,d}, d = S,W,E,N
- *   u, v   [N][5][m]  rank-one pair of block (c, d), d = S,W,C,E,N
+ *   u, v   [N][P][m]  rank-one pairs, P = r_diag + 4 r_off, in block order
+ *                     S (r_off slots), W (r_off), C (r_diag), E (r_off),
+ *                     N (r_off)
  * Directions: S = (ix, iy-1), W = (ix-1, iy), C = the cell, E = (ix+1, iy),
  * N = (ix, iy+1).  The mesh is not periodic: slots of blocks that do not
  * exist must hold finite values and are treated as zero.  s_sub / s_sup may
@@ -152,18 +160,22 @@ typedef struct {
 /* Message of the last failed call on this thread ("" if none). */
 const char* r1s_last_error(void);
 
-/* Device bytes of the packed matrix for an nx x ny mesh with L levels.
+/* Device bytes of the packed matrix for an nx x ny mesh with L levels and
+ * r_diag / r_off rank-one pairs per diagonal / neighbour block.
  * flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG for
- * nx, ny, L < 1 or a NULL `bytes`; R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M. */
-int r1s_mat_size(int nx, int ny, int L, int flags, size_t* bytes);
+ * nx, ny, L < 1, r_diag < 1, r_off < 0 or a NULL `bytes`;
+ * R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M or r_diag > 9 or r_off > 2. */
+int r1s_mat_size(int nx, int ny, int L, int r_diag, int r_off, int flags,
+                 size_t* bytes);
 
 /* Pack the structured arrays (see the layout above) into `mem` and create a
  * handle.  Section 5.1: the index structure is fixed by the mesh adjacency
  * and the block size by m; here it is implicit in (nx, ny, L).
  * Errors: R1S_ERR_ARG (dims, NULL or misaligned pointer, mem_bytes too
  * small), R1S_ERR_HIP. */
-int r1s_mat_init(int nx, int ny, int L, int flags, const r1s_inputs* in,
-                 void* mem, size_t mem_bytes, void* stream, r1s_mat* out);
+int r1s_mat_init(int nx, int ny, int L, int r_diag, int r_off, int flags,
+                 const r1s_inputs* in, void* mem, size_t mem_bytes,
+                 void* stream, r1s_mat* out);
 
 /* New values, same structure (the next Newton iterate).  Preconditioners
  * and BSR copies made from A must be set up again. */
@@ -189,17 +201,21 @@ int r1s_residual(r1s_mat A, int nrhs, const double* b, const double* x,
  * R1S_WITH_TRANS). */
 int r1s_prec_size(r1s_mat A, int flags, size_t* bytes);
 
-/* Section 6: block-Jacobi with D_c = A0_c + u_cC v_cC^T.  Factors the sparse
- * diagonal block A0_c (tridiagonal level band by LU without pivoting, 3 x 3
- * flow corner by its inverse), solves A0_c w_c = u_cC (SMW-1) and forms the
- * capacitance C_c = 1 + v_cC . w_c (SMW-2).  Synchronises; returns
- * R1S_ERR_SINGULAR naming the first cell with a zero pivot or
- * |C_c| <= 1e-12 (1 + |v_cC| |w_c|). */
+/* Section 6: block-Jacobi with D_c = A0_c + U_c V_c^T (eq. R1_Block_Jacobian;
+ * the r_diag columns of U_c, V_c are the pairs of the diagonal block).
+ * Factors the sparse diagonal block A0_c (tridiagonal level band by LU
+ * without pivoting, 3 x 3 flow corner by its inverse), solves
+ * A0_c W_c = U_c (SMW-1), forms the r_diag x r_diag capacitance
+ * C_c = I + V_c^T W_c (SMW-2) and inverts it (Gauss-Jordan, partial
+ * pivoting).  Synchronises; returns R1S_ERR_SINGULAR naming the first cell
+ * with a zero pivot of A0_c or of C_c (|pivot| <= 1e-12 (1 + |V_c| |W_c|),
+ * Frobenius norms). */
 int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
                    void* stream, r1s_prec* out);
 
 /* z = M r (trans = 0) or M^T r: per cell x0 = A0^{-1} r_c, then
- * z_c = x0 - w_c (v_cC . x0) / C_c (section 6, SMW steps, sign corrected).
+ * z_c = x0 - W_c C_c^{-1} (V_c^T x0) (section 6, SMW steps, sign corrected;
+ * the transpose uses A0^{-T} V_c, U_c and C_c^{-T}).
  * Also applies a BSR dense-LU preconditioner (r1s_bsr_prec_setup; trans = 0,
  * precision R1S_F64 only).  Asynchronous. */
 int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs,
@@ -207,7 +223,7 @@ int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs,
 
 int r1s_prec_destroy(r1s_prec M);
 
-/* Dense-block BSR copy of A: every existing block D = S_{c,d} + u v^T stored
+/* Dense-block BSR copy of A: every existing block D = S_{c,d} + sum u v^T stored
  * as a dense m x m block (section 5.1, BSR format; column-major inside a
  * block), plus block_indptr / block_indices (int32). */
 int r1s_bsr_size(r1s_mat A, size_t* bytes);
@@ -241,9 +257,9 @@ int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
 
 /* Gradients of Loss with  J x_r = b_r  given lambda_r = J^{-T} dLoss/dx_r:
  * dLoss/dS = -sum_r lambda_r x_r^T on the stored pattern,
- * dLoss/du_{c,d} = -sum_r lambda_r[c] (v_{c,d} . x_r[nb]),
- * dLoss/dv_{c,d} = -sum_r x_r[nb] (u_{c,d} . lambda_r[c]); zero in the slots
- * of blocks that do not exist.  Asynchronous. */
+ * dLoss/du_{c,d,p} = -sum_r lambda_r[c] (v_{c,d,p} . x_r[nb]),
+ * dLoss/dv_{c,d,p} = -sum_r x_r[nb] (u_{c,d,p} . lambda_r[c]); zero in the
+ * slots of blocks that do not exist.  nrhs <= 64.  Asynchronous. */
 int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
              const r1s_grads* out, void* stream);
 

@@ -64,8 +64,9 @@ _PSZ = C.POINTER(C.c_size_t)
 # name -> (restype, argtypes); every function declared in include/r1s.h
 SIGNATURES = {
     "r1s_last_error": (C.c_char_p, []),
-    "r1s_mat_size": (_I, [_I, _I, _I, _I, _PSZ]),
-    "r1s_mat_init": (_I, [_I, _I, _I, _I, C.POINTER(Inputs), _VP, _SZ, _VP, C.POINTER(_VP)]),
+    "r1s_mat_size": (_I, [_I, _I, _I, _I, _I, _I, _PSZ]),
+    "r1s_mat_init": (_I, [_I, _I, _I, _I, _I, _I, C.POINTER(Inputs), _VP, _SZ, _VP,
+                          C.POINTER(_VP)]),
     "r1s_mat_update": (_I, [_VP, C.POINTER(Inputs), _VP]),
     "r1s_mat_destroy": (_I, [_VP]),
     "r1s_mat_storage": (_I, [_VP, C.POINTER(Storage)]),

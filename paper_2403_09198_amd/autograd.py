@@ -20,7 +20,7 @@ class R1SolveFn(torch.autograd.Function):
         nx, ny, L = cfg["nx"], cfg["ny"], cfg["L"]
         vals = dict(zip(FIELDS, (s_diag, s_sub, s_sup, s_flow, s_nbr, u, v)))
         vals = {k: t.detach().contiguous() for k, t in vals.items()}
-        A = r1s.R1Matrix(nx, ny, L, vals)
+        A = r1s.R1Matrix(nx, ny, L, vals, ranks=cfg.get("ranks", (1, 1)))
         M = r1s.SMWPreconditioner(A, with_trans=True)
         bb = b.detach().contiguous()
         res = r1s.gmres(A, M, bb, restart=cfg.get("restart", 50), rtol=cfg.get("rtol", 1e-12),
@@ -44,6 +44,8 @@ class R1SolveFn(torch.autograd.Function):
 
 
 def solve(b, values, nx, ny, L, **cfg):
-    """x = J^{-1} b, differentiable w.r.t. b and every structured array."""
+    """x = J^{-1} b, differentiable w.r.t. b and every structured array.
+    cfg: ranks=(r_diag, r_off) (default (1, 1)), restart, rtol, adj_rtol,
+    max_cycles."""
     c = dict(cfg, nx=nx, ny=ny, L=L)
     return R1SolveFn.apply(b, *(values[k] for k in FIELDS), c)

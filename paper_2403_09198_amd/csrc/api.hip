@@ -67,11 +67,23 @@ static int check_dims(int nx, int ny, int L) {
   return R1S_OK;
 }
 
-static Mesh make_mesh(int nx, int ny, int L) {
+static int check_ranks(int r_diag, int r_off) {
+  if (r_diag < 1 || r_off < 0)
+    return fail(R1S_ERR_ARG, "need r_diag >= 1 and r_off >= 0 (got %d, %d)", r_diag, r_off);
+  if (!ranks_supported(r_diag, r_off))
+    return fail(R1S_ERR_UNSUPPORTED, "pair counts r_diag = %d, r_off = %d exceed %d, %d", r_diag,
+                r_off, RANK_DIAG_MAX, RANK_OFF_MAX);
+  return R1S_OK;
+}
+
+static Mesh make_mesh(int nx, int ny, int L, int r_diag, int r_off) {
   Mesh g;
   g.nx = nx; g.ny = ny; g.L = L; g.m = L + 3; g.mp = pad_m(L + 3);
   g.N = nx * ny;
   g.n = (long long)g.N * g.m;
+  g.rd = r_diag; g.ro = r_off;
+  g.P = r_diag + 4 * r_off;
+  g.F = F_U + 2 * g.P;
   return g;
 }
 
@@ -86,19 +98,21 @@ struct r1s_mat_s {
 };
 
 static void mat_layout(Carver& cv, const Mesh& g, int flags, double** r64, float** r32) {
-  const size_t cnt = (size_t)g.N * F_REC * g.mp;
+  const size_t cnt = (size_t)g.N * g.F * g.mp;
   *r64 = cv.take<double>(cnt);
   *r32 = (flags & R1S_KEEP_F32) ? cv.take<float>(cnt) : nullptr;
 }
 
-extern "C" int r1s_mat_size(int nx, int ny, int L, int flags, size_t* bytes) {
+extern "C" int r1s_mat_size(int nx, int ny, int L, int r_diag, int r_off, int flags,
+                            size_t* bytes) {
   if (int e = check_dims(nx, ny, L)) return e;
+  if (int e = check_ranks(r_diag, r_off)) return e;
   if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
   if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   Carver cv(nullptr);
   double* a;
   float* b;
-  mat_layout(cv, make_mesh(nx, ny, L), flags, &a, &b);
+  mat_layout(cv, make_mesh(nx, ny, L, r_diag, r_off), flags, &a, &b);
   *bytes = cv.off;
   return R1S_OK;
 }
@@ -121,10 +135,11 @@ static int do_pack(r1s_mat A, const r1s_inputs* in, hipStream_t s) {
   return R1S_OK;
 }
 
-extern "C" int r1s_mat_init(int nx, int ny, int L, int flags, const r1s_inputs* in, void* mem,
-                            size_t mem_bytes, void* stream, r1s_mat* out) {
+extern "C" int r1s_mat_init(int nx, int ny, int L, int r_diag, int r_off, int flags,
+                            const r1s_inputs* in, void* mem, size_t mem_bytes, void* stream,
+                            r1s_mat* out) {
   size_t need;
-  if (int e = r1s_mat_size(nx, ny, L, flags, &need)) return e;
+  if (int e = r1s_mat_size(nx, ny, L, r_diag, r_off, flags, &need)) return e;
   if (!out) return fail(R1S_ERR_ARG, "out is NULL");
   if (int e = check_inputs(in, L)) return e;
   if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
@@ -132,7 +147,7 @@ extern "C" int r1s_mat_init(int nx, int ny, int L, int flags, const r1s_inputs* 
     return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
   r1s_mat A = (r1s_mat)calloc(1, sizeof(r1s_mat_s));
   if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
-  A->g = make_mesh(nx, ny, L);
+  A->g = make_mesh(nx, ny, L, r_diag, r_off);
   A->flags = flags;
   Carver cv(mem);
   mat_layout(cv, A->g, flags, &A->rec64, &A->rec32);
@@ -169,12 +184,14 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   out->n_cells = N;
   out->n_blocks = B;
   out->m = m;
-  out->structured_values = N * (3 * m - 2) + (B - N) * m + 2 * B * m;
-  out->structured_padded = N * (long long)F_REC * g.mp;
+  const long long pairs = N * g.rd + (B - N) * g.ro;
+  out->structured_values = N * (3 * m - 2) + (B - N) * m + 2 * pairs * m;
+  out->structured_padded = N * (long long)g.F * g.mp;
   out->bsr_values = B * m * m;
   out->index_bytes = 0;
   out->matvec_bytes = 8 * out->structured_values + 8 * 2 * N * m;
-  out->smw_apply_bytes = 8 * N * (5 * m - 1) + 8 * 2 * N * m;
+  // A0 factors (as many values as S_cc), W and V, C^{-1}; r read, z written
+  out->smw_apply_bytes = 8 * N * ((3 * m - 2) + 2 * g.rd * m + (long long)g.rd * g.rd) + 8 * 2 * N * m;
   return R1S_OK;
 }
 
@@ -230,14 +247,15 @@ struct r1s_prec_s {
 };
 
 static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
-  const size_t f = (size_t)g.N * F_SMW * g.mp;
+  const size_t f = (size_t)g.N * smw_rows(g) * g.mp;
+  const size_t ic = (size_t)g.N * g.rd * g.rd;
   P->facF = cv.take<double>(f);
   P->facT = (flags & R1S_WITH_TRANS) ? cv.take<double>(f) : nullptr;
-  P->invC = cv.take<double>(g.N);
+  P->invC = cv.take<double>(ic);
   P->status = cv.take<int>(64);
   P->facF32 = (flags & R1S_KEEP_F32) ? cv.take<float>(f) : nullptr;
   P->facT32 = ((flags & R1S_KEEP_F32) && (flags & R1S_WITH_TRANS)) ? cv.take<float>(f) : nullptr;
-  P->invC32 = (flags & R1S_KEEP_F32) ? cv.take<float>(g.N) : nullptr;
+  P->invC32 = (flags & R1S_KEEP_F32) ? cv.take<float>(ic) : nullptr;
 }
 
 extern "C" int r1s_prec_size(r1s_mat A, int flags, size_t* bytes) {
@@ -278,10 +296,10 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
     if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
     if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
     if (P->facF32) {
-      const long long f = (long long)A->g.N * F_SMW * A->g.mp;
+      const long long f = (long long)A->g.N * smw_rows(A->g) * A->g.mp;
       if ((e = launch_cast_f32(P->facF, P->facF32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       if (P->facT32 && (e = launch_cast_f32(P->facT, P->facT32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
-      if ((e = launch_cast_f32(P->invC, P->invC32, A->g.N, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+      if ((e = launch_cast_f32(P->invC, P->invC32, (long long)A->g.N * A->g.rd * A->g.rd, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
     }
     if ((rc = read_status(P->status, s, &st))) break;
     if (st != 0x7fffffff) {

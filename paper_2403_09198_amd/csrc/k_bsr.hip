@@ -13,7 +13,7 @@
 
 namespace r1s {
 
-// D_{c,d} = S_{c,d} + u v^T, one workgroup per block.
+// D_{c,d} = S_{c,d} + sum_p u_p v_p^T, one workgroup per block.
 __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __restrict__ rec,
                                                       const int* __restrict__ blk_row,
                                                       const int* __restrict__ blk_dir,
@@ -21,9 +21,10 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
   const long long b = blockIdx.x;
   const int c = blk_row[b], d = blk_dir[b];
   const int m = g.m, mp = g.mp, L = g.L;
-  const double* rc = rec + (long long)c * F_REC * mp;
-  const double* u = rc + (long long)(F_U + d) * mp;
-  const double* v = rc + (long long)(F_V + d) * mp;
+  const double* rc = rec + (long long)c * g.F * mp;
+  const double* u = rc + (long long)(F_U + pair_start(g, d)) * mp;         // pair p at + p mp
+  const double* v = rc + (long long)(F_U + g.P + pair_start(g, d)) * mp;
+  const int cnt = pair_count(g, d);
   double* out = data + b * m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int j = e / m, i = e - j * m;
@@ -42,7 +43,8 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
     } else if (i == j) {
       s = rc[(F_NBR + nbr_slot(d)) * mp + i];
     }
-    out[e] = s + u[i] * v[j];
+    for (int p = 0; p < cnt; ++p) s += u[p * mp + i] * v[p * mp + j];
+    out[e] = s;
   }
 }
 

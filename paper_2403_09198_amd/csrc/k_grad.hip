@@ -1,48 +1,58 @@
 // Gradients of a loss through the linear solve J x_r = b_r.
 //
 // With lambda_r = J^{-T} dLoss/dx_r the matrix cotangent is -sum_r lambda_r x_r^T.
-// For block (c, d) = S_{c,d} + u v^T this gives, without forming any dense
-// block: the pattern entries of S, du = -sum_r lambda_r[c] (v . x_r[nb]) and
-// dv = -sum_r x_r[nb] (u . lambda_r[c]).  One wavefront per cell; the
-// coefficients v . x and u . lambda are wave reductions kept in LDS.
+// For block (c, d) = S_{c,d} + sum_p u_p v_p^T this gives, without forming
+// any dense block: the pattern entries of S, du_p = -sum_r lambda_r[c]
+// (v_p . x_r[nb]) and dv_p = -sum_r x_r[nb] (u_p . lambda_r[c]).  One
+// wavefront per cell; the coefficients v_p . x and u_p . lambda are wave
+// reductions kept in LDS ([wave][2][pair][rhs], sized at launch).
 #include "r1s_device.hpp"
 #include "r1s_kernels.hpp"
 
 namespace r1s {
 
 constexpr int GRAD_MAX_RHS = 64;
+constexpr int GRAD_LDS_MAX = 64 * 1024;
 
 __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__ rec,
                                               const double* __restrict__ lam,
                                               const double* __restrict__ x, int nrhs, GradOut o) {
-  __shared__ double coef[4][2][5][GRAD_MAX_RHS];
+  extern __shared__ double coef_all[];
+  const int wpg = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * 4 + wave);
+  const int c = __builtin_amdgcn_readfirstlane(tile * wpg + wave);
   if (c >= g.N) return;
   const int lane = lane_id();
-  const int m = g.m, mp = g.mp, L = g.L;
-  const double* rc = rec + (long long)c * F_REC * mp;
+  const int m = g.m, mp = g.mp, L = g.L, P = g.P;
+  double* alpha = coef_all + (long long)wave * 2 * P * nrhs;  // [P][nrhs]: v_q . x_r[nb]
+  double* beta = alpha + (long long)P * nrhs;                  // [P][nrhs]: u_q . lambda_r[c]
+  const double* rc = rec + (long long)c * g.F * mp;
   int nb[5];
   neighbours(g, c, nb);
 
-  // alpha[d][r] = v_{c,d} . x_r[nb_d],  beta[d][r] = u_{c,d} . lambda_r[c]
-  for (int r = 0; r < nrhs; ++r) {
-    const double* lr = lam + (long long)r * g.n + (long long)c * m;
-    for (int d = 0; d < 5; ++d) {
-      double a = 0.0, b = 0.0;
-      if (nb[d] >= 0) {
-        const double* xn = x + (long long)r * g.n + (long long)nb[d] * m;
-        for (int k = lane; k < m; k += WAVE) {
-          a += rc[(F_V + d) * mp + k] * xn[k];
-          b += rc[(F_U + d) * mp + k] * lr[k];
+  for (int d = 0; d < 5; ++d) {
+    const int q0 = pair_start(g, d), cnt = pair_count(g, d);
+    for (int p = 0; p < cnt; ++p) {
+      const int q = q0 + p;
+      const double* uq = rc + (long long)(F_U + q) * mp;
+      const double* vq = rc + (long long)(F_U + P + q) * mp;
+      for (int r = 0; r < nrhs; ++r) {
+        double a = 0.0, b = 0.0;
+        if (nb[d] >= 0) {
+          const double* xn = x + (long long)r * g.n + (long long)nb[d] * m;
+          const double* lr = lam + (long long)r * g.n + (long long)c * m;
+          for (int k = lane; k < m; k += WAVE) {
+            a += vq[k] * xn[k];
+            b += uq[k] * lr[k];
+          }
         }
-      }
-      a = wave_sum(a);
-      b = wave_sum(b);
-      if (lane == 0) {
-        coef[wave][0][d][r] = a;
-        coef[wave][1][d][r] = b;
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) {
+          alpha[q * nrhs + r] = a;
+          beta[q * nrhs + r] = b;
+        }
       }
     }
   }
@@ -50,9 +60,9 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+  // sparse part
   for (int k = lane; k < m; k += WAVE) {
     double gdiag = 0.0, glo = 0.0, ghi = 0.0, gnbr[5] = {0, 0, 0, 0, 0};
-    double gu[5] = {0, 0, 0, 0, 0}, gv[5] = {0, 0, 0, 0, 0};
     int pa, pb;
     bool va, vb;
     if (k < L) {
@@ -70,13 +80,10 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
       gdiag -= lk * xc[k];
       if (va) glo -= lk * xc[pa];
       if (vb) ghi -= lk * xc[pb];
+#pragma unroll
       for (int d = 0; d < 5; ++d) {
-        if (nb[d] < 0) continue;
-        const double* xn = x + (long long)r * g.n + (long long)nb[d] * m;
-        const double xk = xn[k];
-        if (d != D_C) gnbr[d] -= lk * xk;
-        gu[d] -= lk * coef[wave][0][d][r];
-        gv[d] -= xk * coef[wave][1][d][r];
+        if (d == D_C || nb[d] < 0) continue;
+        gnbr[d] -= lk * x[(long long)r * g.n + (long long)nb[d] * m + k];
       }
     }
     o.s_diag[(long long)c * m + k] = gdiag;
@@ -89,10 +96,27 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
       o.s_flow[(long long)c * 6 + i * 2 + (ja > i ? ja - 1 : ja)] = glo;
       o.s_flow[(long long)c * 6 + i * 2 + (jb > i ? jb - 1 : jb)] = ghi;
     }
-    for (int d = 0; d < 5; ++d) {
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
       if (d != D_C) o.s_nbr[((long long)c * 4 + nbr_slot(d)) * m + k] = gnbr[d];
-      o.u[((long long)c * 5 + d) * m + k] = gu[d];
-      o.v[((long long)c * 5 + d) * m + k] = gv[d];
+  }
+
+  // rank-one pairs (zero for the pairs of blocks outside the mesh)
+  for (int d = 0; d < 5; ++d) {
+    const int q0 = pair_start(g, d), cnt = pair_count(g, d);
+    for (int p = 0; p < cnt; ++p) {
+      const int q = q0 + p;
+      for (int k = lane; k < m; k += WAVE) {
+        double gu = 0.0, gv = 0.0;
+        if (nb[d] >= 0) {
+          for (int r = 0; r < nrhs; ++r) {
+            gu -= lam[(long long)r * g.n + (long long)c * m + k] * alpha[q * nrhs + r];
+            gv -= x[(long long)r * g.n + (long long)nb[d] * m + k] * beta[q * nrhs + r];
+          }
+        }
+        o.u[((long long)c * P + q) * m + k] = gu;
+        o.v[((long long)c * P + q) * m + k] = gv;
+      }
     }
   }
 }
@@ -100,7 +124,12 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
 hipError_t launch_grad(const Mesh& g, const double* rec, const double* lam, const double* x,
                        int nrhs, const GradOut& out, hipStream_t s) {
   if (nrhs > GRAD_MAX_RHS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_grad, dim3((g.N + 3) / 4), dim3(256), 0, s, g, rec, lam, x, nrhs, out);
+  const size_t per_wave = (size_t)2 * g.P * nrhs * sizeof(double);
+  int wpg = 4;
+  while (wpg > 1 && wpg * per_wave > GRAD_LDS_MAX) wpg >>= 1;
+  if (wpg * per_wave > GRAD_LDS_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_grad, dim3((g.N + wpg - 1) / wpg), dim3(64 * wpg), wpg * per_wave, s, g,
+                     rec, lam, x, nrhs, out);
   return hipGetLastError();
 }
 

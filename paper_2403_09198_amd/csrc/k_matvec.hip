@@ -4,24 +4,37 @@
 // coefficient v . x_J per rank-one pair, then coefficient * u accumulated
 // into the block row, on top of the CSR product of the sparse part.  Here one
 // wavefront owns one block row (cell) and does both parts: phase 1 forms the
-// five pair coefficients with wave reductions, phase 2 streams the sparse
-// rows and the u vectors once and writes y once.  The transpose gathers from
-// the neighbours' records (block (nb, opposite d) multiplies x_nb into row c),
-// so no atomics are needed and results are run-to-run deterministic.
+// coefficients of all pairs of the row with wave reductions, phase 2 streams
+// the sparse rows and the u vectors once and writes y once.  The transpose
+// gathers from the neighbours' records (block (nb, opposite d) multiplies x_nb
+// into row c), so no atomics are needed and results are run-to-run
+// deterministic.
+//
+// Pair counts: a diagonal block has g.rd pairs, a neighbour block g.ro.  The
+// kernels are compiled for maxima RDM / ROM: <1, 1> is the one-pair-per-block
+// layout (counts fixed at compile time), <9, 2> takes any rd <= 9, ro <= 2
+// with the counts as wave-uniform guards.
 #include "r1s_device.hpp"
 #include "r1s_kernels.hpp"
 
 namespace r1s {
 
 // ----------------------------------------------------------------- pack ----
+// Block direction of pair slot q (slots ordered S, W, C, E, N).
+__device__ inline int dir_of_slot(const Mesh& g, int q) {
+  return q < g.ro ? D_S : q < 2 * g.ro ? D_W : q < 2 * g.ro + g.rd ? D_C
+         : q < 3 * g.ro + g.rd ? D_E : D_N;
+}
+
 template <typename TV>
 __global__ __launch_bounds__(256) void k_pack(Mesh g, PackIn in, TV* __restrict__ rec) {
-  const long long total = (long long)g.N * F_REC * g.mp;
-  const int L = g.L, m = g.m;
+  const long long RS = (long long)g.F * g.mp;
+  const long long total = (long long)g.N * RS;
+  const int L = g.L, m = g.m, P = g.P;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(idx / (F_REC * g.mp));
-    const int rem = (int)(idx - (long long)c * F_REC * g.mp);
+    const int c = (int)(idx / RS);
+    const int rem = (int)(idx - (long long)c * RS);
     const int f = rem / g.mp, k = rem - f * g.mp;
     double val = 0.0;
     if (k < m) {
@@ -44,12 +57,12 @@ __global__ __launch_bounds__(256) void k_pack(Mesh g, PackIn in, TV* __restrict_
         const int slot = f - F_NBR;
         const int d = slot < 2 ? slot : slot + 1;
         if (nb[d]) val = in.s_nbr[((long long)c * 4 + slot) * m + k];
-      } else if (f < F_V) {
-        const int d = f - F_U;
-        if (nb[d]) val = in.u[((long long)c * 5 + d) * m + k];
+      } else if (f < F_U + P) {
+        const int q = f - F_U;
+        if (nb[dir_of_slot(g, q)]) val = in.u[((long long)c * P + q) * m + k];
       } else {
-        const int d = f - F_V;
-        if (nb[d]) val = in.v[((long long)c * 5 + d) * m + k];
+        const int q = f - F_U - P;
+        if (nb[dir_of_slot(g, q)]) val = in.v[((long long)c * P + q) * m + k];
       }
     }
     rec[idx] = (TV)val;
@@ -64,6 +77,42 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
     dst[i] = (TO)src[i];
 }
 
+// ------------------------------------------------ per-cell row pointers ----
+// The rows a cell's output depends on, per block direction d.  Forward: the
+// cell's own record (v rows give the coefficients, u rows the output).
+// Transpose: block (nb, opposite d) of the neighbour's record (its u rows give
+// the coefficients, its v rows the output; its diagonal is symmetric).
+template <typename TV, bool TRANS>
+struct CellRows {
+  const TV* rc;          // own record
+  const TV* base[5];     // record holding the block of direction d
+  int coef0[5], out0[5]; // first coefficient row, first output row
+  int nbr[5];            // neighbour-diagonal row
+
+  __device__ inline void init(const Mesh& g, const TV* rec, int c, const int (&nbc)[5]) {
+    const long long RS = (long long)g.F * g.mp;
+    rc = rec + (long long)c * RS;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      const int bd = TRANS ? opposite(d) : d;
+      base[d] = TRANS ? rec + (long long)nbc[d] * RS : rc;
+      coef0[d] = F_U + (TRANS ? 0 : g.P) + pair_start(g, bd);
+      out0[d] = F_U + (TRANS ? g.P : 0) + pair_start(g, bd);
+      nbr[d] = F_NBR + nbr_slot(bd == D_C ? 0 : bd);
+    }
+  }
+};
+
+// Kernel-side mesh: with one pair per block (EXACT) the pair counts become
+// compile-time constants and all row offsets fold.
+template <bool EXACT>
+__device__ inline Mesh kmesh(Mesh g) {
+  if (EXACT) {
+    g.rd = 1; g.ro = 1; g.P = 5; g.F = F_U + 10;
+  }
+  return g;
+}
+
 // --------------------------------------------------------------- matvec ----
 // TV: value / accumulation type.  NCH = ceil(m / 64) chunks of 64 unknowns,
 // NR right-hand sides per launch starting at rhs r0.  RESID: write b - J x.
@@ -72,54 +121,45 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
 // issued before the first wait: missing neighbours (mesh boundary) read the
 // cell's own, valid addresses and are masked out of the sums instead of
 // being skipped by a branch.  Lanes past m read element m-1 and are masked.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID>
-__global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restrict__ rec,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ b,
-                                                double* __restrict__ y, int r0) {
+// Pair slots past a block's count are skipped by wave-uniform guards.
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM>
+__global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ y, int r0) {
+  constexpr bool EXACT = RDM == 1 && ROM == 1;
+  constexpr int RM = RDM > ROM ? RDM : ROM;
   constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
+  const Mesh g = kmesh<EXACT>(g_);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int c = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
   if (c >= g.N) return;
   const int lane = lane_id();
-  const int m = g.m, mp = g.mp, L = g.L;
-  const long long RS = (long long)F_REC * mp;
-  int nb[5], nbc[5];
+  const int m = g.m, L = g.L;
+  const long long mp = g.mp;
+  int nb[5], nbc[5], cnt[5];
   bool ex[5];
   neighbours(g, c, nb);
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
     ex[d] = nb[d] >= 0;
     nbc[d] = ex[d] ? nb[d] : c;
+    cnt[d] = pair_count(g, d);
   }
-  const TV* rc = rec + (long long)c * RS;
-  // coefficient row of phase 1, output row of phase 2, neighbour diagonal
-  const TV* prow[5];
-  const TV* urow[5];
-  const TV* nrow[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    if (!TRANS) {
-      prow[d] = rc + (long long)(F_V + d) * mp;
-      urow[d] = rc + (long long)(F_U + d) * mp;
-      nrow[d] = rc + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : d)) * mp;
-    } else {
-      const TV* rn = rec + (long long)nbc[d] * RS;
-      prow[d] = rn + (long long)(F_U + opposite(d)) * mp;
-      urow[d] = rn + (long long)(F_V + opposite(d)) * mp;
-      nrow[d] = rn + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : opposite(d))) * mp;
-    }
-  }
+  CellRows<TV, TRANS> R;
+  R.init(g, rec, c, nbc);
   const double* xr = x + (long long)r0 * g.n;
 
-  TV pv[5][NCH], xv[NR][5][NCH];
+  TV pv[5][RM][NCH], xv[NR][5][NCH];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      pv[d][ch] = ld_stream(prow[d] + kk);
+#pragma unroll
+      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
+        pv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         xv[r][d][ch] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
@@ -127,8 +167,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
   }
 
   // sparse part of the row: diagonal, level band / flow corner partners,
-  // neighbour diagonals, and the u rows
-  TV dg[NCH], ca[NCH], cb[NCH], nv[5][NCH], uv[5][NCH], xa[NR][NCH], xb[NR][NCH];
+  // neighbour diagonals, and the output rows of the pairs
+  TV dg[NCH], ca[NCH], cb[NCH], nv[5][NCH], uv[5][RM][NCH], xa[NR][NCH], xb[NR][NCH];
   auto load_sparse = [&](int ch) {
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
@@ -142,20 +182,22 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
       pa = L + (i + 2) % 3; va = true;
       pb = L + (i + 1) % 3; vb = true;
     }
-    dg[ch] = ld_stream(rc + (long long)F_DIAG * mp + kk);
+    dg[ch] = ld_stream(R.rc + F_DIAG * mp + kk);
     if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
-      ca[ch] = ld_stream(rc + (long long)F_LO * mp + kk);
-      cb[ch] = ld_stream(rc + (long long)F_HI * mp + kk);
+      ca[ch] = ld_stream(R.rc + F_LO * mp + kk);
+      cb[ch] = ld_stream(R.rc + F_HI * mp + kk);
     } else {       // column k of S_cc: hi of row pa, lo of row pb
-      const TV ta = rc[(long long)F_HI * mp + pa];
-      const TV tb = rc[(long long)F_LO * mp + pb];
+      const TV ta = R.rc[F_HI * mp + pa];
+      const TV tb = R.rc[F_LO * mp + pb];
       ca[ch] = va ? ta : TV(0);
       cb[ch] = vb ? tb : TV(0);
     }
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      if (d != D_C) nv[d][ch] = ld_stream(nrow[d] + kk);
-      uv[d][ch] = ld_stream(urow[d] + kk);
+      if (d != D_C) nv[d][ch] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
+#pragma unroll
+      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
+        uv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -172,19 +214,21 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
     __builtin_amdgcn_sched_barrier(0);
   }
 
-  // pair coefficients: forward v_{c,d} . x_nb, transpose u_{nb,opp d} . x_nb
-  TV acc[NR][5];
+  // pair coefficients: forward v_p . x_nb, transpose u_p(nb, opp d) . x_nb
+  TV acc[NR][5][RM];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      TV s = TV(0);
+    for (int d = 0; d < 5; ++d)
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch)
-        if (ch * WAVE + lane < m) s += pv[d][ch] * xv[r][d][ch];
-      s = wave_sum_u(s);
-      acc[r][d] = ex[d] ? s : TV(0);
-    }
+      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
+        TV s = TV(0);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+          if (ch * WAVE + lane < m) s += pv[d][p][ch] * xv[r][d][ch];
+        s = wave_sum_u(s);
+        acc[r][d][p] = ex[d] ? s : TV(0);
+      }
 
   // Lanes past m computed exactly what lane m-1 computes (all their indices
   // are clamped), so every lane stores to its clamped index: duplicate lanes
@@ -200,7 +244,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
         if (d != D_C && ex[d]) t += nv[d][ch] * xv[r][d][ch];
-        t += uv[d][ch] * acc[r][d];
+#pragma unroll
+        for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) t += uv[d][p][ch] * acc[r][d][p];
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
       y[o] = RESID ? b[o] - (double)t : (double)t;
@@ -210,52 +255,43 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g, const TV* __restric
 
 // Workgroup-per-cell form for m > 64: wave w of the workgroup owns unknowns
 // 64w .. 64w+63 of one cell, issues all of its loads at once (like the
-// single-chunk kernel), and the five pair coefficients are summed over the
-// waves through LDS in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID>
-__global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g, const TV* __restrict__ rec,
+// single-chunk kernel), and the pair coefficients are summed over the waves
+// through LDS in a fixed order.
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM>
+__global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __restrict__ rec,
                                                         const double* __restrict__ x,
                                                         const double* __restrict__ b,
                                                         double* __restrict__ y, int r0) {
-  __shared__ TV part[NR][5][NCH];
+  constexpr bool EXACT = RDM == 1 && ROM == 1;
+  constexpr int RM = RDM > ROM ? RDM : ROM;
+  __shared__ TV part[NR][5][RM][NCH];
+  const Mesh g = kmesh<EXACT>(g_);
   const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
-  const int m = g.m, mp = g.mp, L = g.L;
-  const long long RS = (long long)F_REC * mp;
-  int nb[5], nbc[5];
+  const int m = g.m, L = g.L;
+  const long long mp = g.mp;
+  int nb[5], nbc[5], cnt[5];
   bool ex[5];
   neighbours(g, c, nb);
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
     ex[d] = nb[d] >= 0;
     nbc[d] = ex[d] ? nb[d] : c;
+    cnt[d] = pair_count(g, d);
   }
-  const TV* rc = rec + (long long)c * RS;
-  const TV* prow[5];
-  const TV* urow[5];
-  const TV* nrow[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    if (!TRANS) {
-      prow[d] = rc + (long long)(F_V + d) * mp;
-      urow[d] = rc + (long long)(F_U + d) * mp;
-      nrow[d] = rc + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : d)) * mp;
-    } else {
-      const TV* rn = rec + (long long)nbc[d] * RS;
-      prow[d] = rn + (long long)(F_U + opposite(d)) * mp;
-      urow[d] = rn + (long long)(F_V + opposite(d)) * mp;
-      nrow[d] = rn + (long long)(F_NBR + nbr_slot(d == D_C ? 0 : opposite(d))) * mp;
-    }
-  }
+  CellRows<TV, TRANS> R;
+  R.init(g, rec, c, nbc);
   const double* xr = x + (long long)r0 * g.n;
   const int k = wv * WAVE + lane;
   const int kk = k < m ? k : m - 1;
 
-  TV pv[5], xv[NR][5];
+  TV pv[5][RM], xv[NR][5];
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
-    pv[d] = ld_stream(prow[d] + kk);
+#pragma unroll
+    for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
+      pv[d][p] = p < cnt[d] ? ld_stream(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
 #pragma unroll
     for (int r = 0; r < NR; ++r) xv[r][d] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
   }
@@ -269,22 +305,24 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g, const TV* __rest
     pa = L + (i + 2) % 3; va = true;
     pb = L + (i + 1) % 3; vb = true;
   }
-  const TV dg = ld_stream(rc + (long long)F_DIAG * mp + kk);
+  const TV dg = ld_stream(R.rc + F_DIAG * mp + kk);
   TV ca, cb;
   if (!TRANS) {
-    ca = ld_stream(rc + (long long)F_LO * mp + kk);
-    cb = ld_stream(rc + (long long)F_HI * mp + kk);
+    ca = ld_stream(R.rc + F_LO * mp + kk);
+    cb = ld_stream(R.rc + F_HI * mp + kk);
   } else {
-    const TV ta = rc[(long long)F_HI * mp + pa];
-    const TV tb = rc[(long long)F_LO * mp + pb];
+    const TV ta = R.rc[F_HI * mp + pa];
+    const TV tb = R.rc[F_LO * mp + pb];
     ca = va ? ta : TV(0);
     cb = vb ? tb : TV(0);
   }
-  TV nv[5], uv[5], xa[NR], xb[NR];
+  TV nv[5], uv[5][RM], xa[NR], xb[NR];
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
-    if (d != D_C) nv[d] = ld_stream(nrow[d] + kk);
-    uv[d] = ld_stream(urow[d] + kk);
+    if (d != D_C) nv[d] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
+#pragma unroll
+    for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
+      uv[d][p] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -297,28 +335,26 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g, const TV* __rest
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      const TV s = wave_sum_u(k < m ? pv[d] * xv[r][d] : TV(0));
-      if (lane == 0) part[r][d][wv] = s;
-    }
+    for (int d = 0; d < 5; ++d)
+#pragma unroll
+      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
+        const TV s = wave_sum_u(k < m ? pv[d][p] * xv[r][d] : TV(0));
+        if (lane == 0) part[r][d][p][wv] = s;
+      }
   __syncthreads();
-  TV acc[NR][5];
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      TV s = part[r][d][0];
-#pragma unroll
-      for (int w = 1; w < NCH; ++w) s += part[r][d][w];
-      acc[r][d] = ex[d] ? s : TV(0);
-    }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     TV t = dg * xv[r][D_C] + ca * xa[r] + cb * xb[r];
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
       if (d != D_C && ex[d]) t += nv[d] * xv[r][d];
-      t += uv[d] * acc[r][d];
+#pragma unroll
+      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
+        TV s = part[r][d][p][0];
+#pragma unroll
+        for (int w = 1; w < NCH; ++w) s += part[r][d][p][w];
+        t += uv[d][p] * (ex[d] ? s : TV(0));
+      }
     }
     const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
     y[o] = RESID ? b[o] - (double)t : (double)t;
@@ -335,7 +371,7 @@ static inline int grid_for(long long work, int per_block, int cap = 1 << 20) {
 
 hipError_t launch_pack(const Mesh& g, const PackIn& in, double* rec64, float* rec32,
                        hipStream_t s) {
-  const long long total = (long long)g.N * F_REC * g.mp;
+  const long long total = (long long)g.N * g.F * g.mp;
   hipLaunchKernelGGL(k_pack<double>, dim3(grid_for(total, 256, 65536)), dim3(256), 0, s, g, in,
                      rec64);
   if (rec32)
@@ -350,22 +386,37 @@ hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipSt
   return hipGetLastError();
 }
 
-template <typename TV, int NCH, bool TRANS, bool RESID>
+bool ranks_supported(int rd, int ro) {
+  return rd >= 1 && rd <= RANK_DIAG_MAX && ro >= 0 && ro <= RANK_OFF_MAX;
+}
+
+// Right-hand sides per launch: 8 / 4 / 2 / 1 with one pair per block (4 / 2 / 1
+// in the workgroup form), 2 / 1 with several (their coefficient registers
+// grow with the pair count).
+template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM>
 static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
                           double* y, int nrhs, hipStream_t s) {
+  constexpr bool EXACT = RDM == 1 && ROM == 1;
 #ifndef R1S_NO_WG_CELL
   if constexpr (NCH > 1) {
     int r0 = 0;
     while (r0 < nrhs) {
       const int rem = nrhs - r0;
-      if (rem >= 4) {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
-        r0 += 4;
-      } else if (rem >= 2) {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+      if constexpr (EXACT) {
+        if (rem >= 4) {
+          hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID, RDM, ROM>), dim3(g.N),
+                             dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+          r0 += 4;
+          continue;
+        }
+      }
+      if (rem >= 2) {
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID, RDM, ROM>), dim3(g.N),
+                           dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
         r0 += 2;
       } else {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID>), dim3(g.N), dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID, RDM, ROM>), dim3(g.N),
+                           dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
         r0 += 1;
       }
     }
@@ -376,39 +427,51 @@ static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
-    if constexpr (NCH <= 2) {
+    if constexpr (NCH <= 2 && EXACT) {
       if (rem >= 8) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID, RDM, ROM>), dim3(grid),
+                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 8;
         continue;
       }
       if (rem >= 4) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM>), dim3(grid),
+                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 4;
         continue;
       }
     }
     if (rem >= 2) {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM>), dim3(grid),
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM>), dim3(grid),
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 1;
     }
   }
 }
 
-template <typename TV, bool TRANS, bool RESID>
-static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
+template <typename TV, bool TRANS, bool RESID, int RDM, int ROM>
+static hipError_t launch_mv_r(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   switch ((g.m + WAVE - 1) / WAVE) {
-    case 1: launch_mv_nch<TV, 1, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
-    case 2: launch_mv_nch<TV, 2, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
-    case 3: launch_mv_nch<TV, 3, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
-    case 4: launch_mv_nch<TV, 4, TRANS, RESID>(g, rec, x, b, y, nrhs, s); break;
+    case 1: launch_mv_nch<TV, 1, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
+    case 2: launch_mv_nch<TV, 2, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
+    case 3: launch_mv_nch<TV, 3, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
+    case 4: launch_mv_nch<TV, 4, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename TV, bool TRANS, bool RESID>
+static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
+                              double* y, int nrhs, hipStream_t s) {
+  if (g.rd == 1 && g.ro == 1) return launch_mv_r<TV, TRANS, RESID, 1, 1>(g, rec, x, b, y, nrhs, s);
+  if (!ranks_supported(g.rd, g.ro)) return hipErrorInvalidValue;
+  return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX>(g, rec, x, b, y, nrhs, s);
 }
 
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,

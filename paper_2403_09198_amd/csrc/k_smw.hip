@@ -1,10 +1,12 @@
 // Block-Jacobi preconditioner through the Sherman-Morrison-Woodbury identity.
 //
-// Section 6: the diagonal block of cell c is D_c = A0_c + u_cC v_cC^T with A0_c
-// the sparse diagonal block of S.  With w = A0^{-1} u and C = 1 + v . w
-// (SMW-1, SMW-2), D_c^{-1} r = x0 - w (v . x0) / C where x0 = A0^{-1} r.  The
-// printed identity adds the correction; the correct Woodbury identity
-// subtracts it, which is what is computed here.
+// Section 6: the diagonal block of cell c is D_c = A0_c + U V^T (eq.
+// R1_Block_Jacobian) with A0_c the sparse diagonal block of S and the rd
+// columns of U, V the block's rank-one pairs.  With W = A0^{-1} U and the rd x
+// rd capacitance C = I + V^T W (SMW-1, SMW-2), D_c^{-1} r = x0 - W C^{-1} V^T x0
+// where x0 = A0^{-1} r.  The printed identity adds the correction; the correct
+// Woodbury identity subtracts it, which is what is computed here.  With one
+// pair C is the scalar 1 + v . w.
 //
 // A0_c is the tridiagonal level band (no level/flow coupling) plus a dense
 // 3 x 3 flow corner.  The band is factored once (LU without pivoting, the
@@ -39,11 +41,16 @@ hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s) {
 // scaled by 1 / max(|a_k|, |e_k|, 1), which leaves the ratio unchanged and
 // keeps 64-factor products far from overflow) applied to the carried
 // [d_{prev}; 1].  Then l_k = sub_{k-1} / d_{k-1}, and the factor rows:
-//   forward  a = -l_k, dinv = 1/d_k, b = -sup_k / d_k, w = A0^{-1} u, v
-//   transpose a = -sup_{k-1} / d_k, dinv, b = -l_{k+1}, wt = A0^{-T} v, u
+//   forward  a = -l_k, dinv = 1/d_k, b = -sup_k / d_k, W_i = A0^{-1} u_i, v_i
+//   transpose a = -sup_{k-1} / d_k, dinv, b = -l_{k+1}, A0^{-T} v_i, u_i
 // Flow lanes L + i hold row i of the 3 x 3 corner inverse (transpose: of its
-// transpose).  w and wt use the same affine-scan sweeps as the apply.
-template <int NCH>
+// transpose).  W uses the same affine-scan sweeps as the apply.
+//
+// C^{-1} by Gauss-Jordan elimination with partial pivoting on [C | I]: lane t
+// holds column t of the augmented matrix (rows in registers), pivots are read
+// with v_readlane, so every step is wave-uniform.  The transposed apply uses
+// (C^{-1})^T, since I + U^T A0^{-T} V = C^T.
+template <int NCH, int RDM>
 __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __restrict__ rec,
                                                        double* __restrict__ facF,
                                                        double* __restrict__ facT,
@@ -52,14 +59,16 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   if (c >= g.N) return;
   const int lane = lane_id();
   const int L = g.L, m = g.m, mp = g.mp;
-  const double* rc = rec + (long long)c * F_REC * mp;
+  const int rd = RDM == 1 ? 1 : g.rd;
+  const int SR = 3 + 2 * rd;
+  const double* rc = rec + (long long)c * g.F * mp;
   const double* dg = rc + (long long)F_DIAG * mp;
   const double* lo = rc + (long long)F_LO * mp;
   const double* hi = rc + (long long)F_HI * mp;
-  const double* uC = rc + (long long)(F_U + D_C) * mp;
-  const double* vC = rc + (long long)(F_V + D_C) * mp;
+  const double* uC = rc + (long long)(F_U + pair_start(g, D_C)) * mp;         // pair i at + i mp
+  const double* vC = rc + (long long)(F_U + g.P + pair_start(g, D_C)) * mp;
 
-  double AD[NCH], LO[NCH], HI[NCH], HM1[NCH], LP1[NCH], U[NCH], V[NCH];
+  double AD[NCH], LO[NCH], HI[NCH], HM1[NCH], LP1[NCH];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int k = ch * WAVE + lane;
@@ -69,8 +78,6 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
     HI[ch] = hi[kk];
     HM1[ch] = kk >= 1 ? hi[kk - 1] : 0.0;
     LP1[ch] = kk + 1 < m ? lo[kk + 1] : 0.0;
-    U[ch] = uC[kk];
-    V[ch] = vC[kk];
   }
   // 3 x 3 flow corner (wave-uniform values), inverse by cofactors
   double F[3][3], Fi[3][3];
@@ -144,75 +151,196 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
       TB[ch] = Fi[2][i];
     }
   }
-  // SMW-1: w = A0^{-1} u_cC ; SMW-2: C = 1 + v . w
-  const double uf0 = uC[L], uf1 = uC[L + 1], uf2 = uC[L + 2];
-  double W[NCH];
-  smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, uf0, uf1, uf2, W);
-  double vw = 0.0, vv = 0.0, ww = 0.0;
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    const bool in = ch * WAVE + lane < m;
-    vw += in ? V[ch] * W[ch] : 0.0;
-    vv += in ? V[ch] * V[ch] : 0.0;
-    ww += in ? W[ch] * W[ch] : 0.0;
-  }
-  vw = wave_sum_u(vw);
-  vv = wave_sum_u(vv);
-  ww = wave_sum_u(ww);
-  const double C = 1.0 + vw;
-  if (!(fabs(C) > 1e-12 * (1.0 + sqrt(vv * ww)))) bad = true;
-
-  double* fA = facF + (long long)c * F_SMW * mp;
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    const int k = ch * WAVE + lane;
-    if (k < mp) {
-      const bool in = k < m;
-      fA[P_A * mp + k] = in ? FA[ch] : 0.0;
-      fA[P_DINV * mp + k] = in ? FDI[ch] : 0.0;
-      fA[P_B * mp + k] = in ? FB[ch] : 0.0;
-      fA[P_W * mp + k] = in ? W[ch] : 0.0;
-      fA[P_V * mp + k] = in ? V[ch] : 0.0;
-    }
-  }
-  if (facT) {  // wt = A0^{-T} v_cC, used by the transposed apply
-    const double vf0 = vC[L], vf1 = vC[L + 1], vf2 = vC[L + 2];
-    double WT[NCH];
-    smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V, vf0, vf1, vf2, WT);
-    // flow rows of the transposed record hold the transposed corner inverse
-    double* fT = facT + (long long)c * F_SMW * mp;
+  double* fA = facF + (long long)c * SR * mp;
+  double* fT = facT ? facT + (long long)c * SR * mp : nullptr;
+  auto put = [&](double* rec_row, const double (&val)[NCH]) {
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int k = ch * WAVE + lane;
-      if (k < mp) {
-        const bool in = k < m;
-        fT[P_A * mp + k] = in ? TA[ch] : 0.0;
-        fT[P_DINV * mp + k] = in ? TDI[ch] : 0.0;
-        fT[P_B * mp + k] = in ? TB[ch] : 0.0;
-        fT[P_W * mp + k] = in ? WT[ch] : 0.0;
-        fT[P_V * mp + k] = in ? U[ch] : 0.0;
-      }
+      if (k < mp) rec_row[k] = k < m ? val[ch] : 0.0;
+    }
+  };
+  put(fA + P_A * mp, FA);
+  put(fA + P_DINV * mp, FDI);
+  put(fA + P_B * mp, FB);
+  if (fT) {
+    put(fT + P_A * mp, TA);
+    put(fT + P_DINV * mp, TDI);
+    put(fT + P_B * mp, TB);
+  }
+
+  // SMW-1: W_j = A0^{-1} u_j
+  double W[RDM][NCH], V[RDM][NCH];
+  double vv = 0.0, ww = 0.0;
+#pragma unroll
+  for (int j = 0; j < RDM; ++j) {
+    if (j >= rd) break;
+    double U[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      const int kk = k < m ? k : m - 1;
+      U[ch] = uC[j * mp + kk];
+      V[j][ch] = vC[j * mp + kk];
+    }
+    const double* uf = uC + j * mp + L;
+    smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, uf[0], uf[1], uf[2], W[j]);
+    put(fA + (P_W + j) * mp, W[j]);
+    put(fA + (P_W + rd + j) * mp, V[j]);
+    double sv = 0.0, sw = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const bool in = ch * WAVE + lane < m;
+      sv += in ? V[j][ch] * V[j][ch] : 0.0;
+      sw += in ? W[j][ch] * W[j][ch] : 0.0;
+    }
+    vv += wave_sum_u(sv);
+    ww += wave_sum_u(sw);
+  }
+
+  // SMW-2: C = I + V^T W.  Mc[i] = row i of [C | I] at column `lane`.
+  double Mc[RDM];
+#pragma unroll
+  for (int i = 0; i < RDM; ++i) {
+    Mc[i] = lane == rd + i ? 1.0 : 0.0;
+    if (i >= rd) continue;
+#pragma unroll
+    for (int j = 0; j < RDM; ++j) {
+      if (j >= rd) break;
+      double s = 0.0;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        s += ch * WAVE + lane < m ? V[i][ch] * W[j][ch] : 0.0;
+      const double cij = (i == j ? 1.0 : 0.0) + wave_sum_u(s);
+      Mc[i] = lane == j ? cij : Mc[i];
     }
   }
-  if (lane == 0) invC[c] = 1.0 / C;
+  // the entries of V^T W carry rounding of order eps |V| |W|
+  const double tol = 1e-12 * (1.0 + sqrt(vv * ww));
+#pragma unroll
+  for (int k = 0; k < RDM; ++k) {
+    if (k >= rd) break;
+    int p = k;
+    double best = fabs(readlane(Mc[k], k));
+#pragma unroll
+    for (int i = k + 1; i < RDM; ++i) {
+      if (i >= rd) break;
+      const double a = fabs(readlane(Mc[i], k));
+      if (a > best) {
+        best = a;
+        p = i;
+      }
+    }
+    if (!(best > tol)) bad = true;
+    // swap rows k and p (p >= k, wave-uniform)
+    double rowp = Mc[k];
+#pragma unroll
+    for (int i = k + 1; i < RDM; ++i) rowp = i == p ? Mc[i] : rowp;
+#pragma unroll
+    for (int i = k + 1; i < RDM; ++i) Mc[i] = i == p ? Mc[k] : Mc[i];
+    Mc[k] = rowp;
+    Mc[k] *= 1.0 / readlane(Mc[k], k);
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) {
+      if (i == k || i >= rd) continue;
+      const double f = readlane(Mc[i], k);
+      Mc[i] -= f * Mc[k];
+    }
+  }
+  // lane rd + j holds column j of C^{-1}
+  if (lane >= rd && lane < 2 * rd) {
+    double* ic = invC + (long long)c * rd * rd + (lane - rd);
+#pragma unroll
+    for (int i = 0; i < RDM; ++i)
+      if (i < rd) ic[i * rd] = Mc[i];
+  }
+
+  if (fT) {  // transposed factors: A0^{-T} v_j and u_j
+#pragma unroll
+    for (int j = 0; j < RDM; ++j) {
+      if (j >= rd) break;
+      double WT[NCH], U[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int k = ch * WAVE + lane;
+        U[ch] = uC[j * mp + (k < m ? k : m - 1)];
+      }
+      const double* vf = vC + j * mp + L;
+      smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V[j], vf[0], vf[1], vf[2], WT);
+      put(fT + (P_W + j) * mp, WT);
+      put(fT + (P_W + rd + j) * mp, U);
+    }
+  }
   const unsigned long long anybad = __ballot(bad);
   if (anybad && lane == 0) atomicMin(status, c);
 }
 
-hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
-                            double* invC, int* status, hipStream_t s) {
+template <int RDM>
+static hipError_t launch_setup_r(const Mesh& g, const double* rec, double* facF, double* facT,
+                                 double* invC, int* status, hipStream_t s) {
   const int grid = (g.N + WPB - 1) / WPB;
   switch ((g.m + WAVE - 1) / WAVE) {
-    case 1: hipLaunchKernelGGL(k_smw_setup<1>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
-    case 2: hipLaunchKernelGGL(k_smw_setup<2>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
-    case 3: hipLaunchKernelGGL(k_smw_setup<3>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
-    case 4: hipLaunchKernelGGL(k_smw_setup<4>, dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 1: hipLaunchKernelGGL((k_smw_setup<1, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 2: hipLaunchKernelGGL((k_smw_setup<2, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 3: hipLaunchKernelGGL((k_smw_setup<3, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
+    case 4: hipLaunchKernelGGL((k_smw_setup<4, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, rec, facF, facT, invC, status); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
+                            double* invC, int* status, hipStream_t s) {
+  if (g.rd == 1) return launch_setup_r<1>(g, rec, facF, facT, invC, status, s);
+  if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
+  return launch_setup_r<RANK_DIAG_MAX>(g, rec, facF, facT, invC, status, s);
+}
+
 // ---------------------------------------------------------------- apply ----
+// z = x0 - W C^{-1} (V^T x0) with x0 = A0^{-1} r.  With one pair C^{-1} is a
+// scalar per cell; with rd pairs lane t of the wave holds entries t and
+// 64 + t of the cell's row-major C^{-1} (rd^2 <= 81 values), read back with
+// v_readlane (transposed apply: (C^{-1})^T, the same values read transposed).
+template <typename TV, int RDM>
+struct CapInv {
+  static constexpr int NV = (RDM * RDM + WAVE - 1) / WAVE;
+  TV v[NV];
+  __device__ inline void load(const TV* invC, int c, int rd, int lane) {
+    if (RDM == 1) {
+      v[0] = invC[c];
+    } else {
+      const int cnt = rd * rd;
+      const TV* p = invC + (long long)c * cnt;
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        const int t = h * WAVE + lane;
+        v[h] = p[t < cnt ? t : cnt - 1];
+      }
+    }
+  }
+  // z_i = sum_l Cinv(i, l) s_l   (TRANS: Cinv(l, i))
+  template <bool TRANS>
+  __device__ inline void apply(const TV (&s)[RDM], TV (&z)[RDM], int rd) const {
+    if (RDM == 1) {
+      z[0] = s[0] * v[0];
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) {
+      TV acc = TV(0);
+#pragma unroll
+      for (int l = 0; l < RDM; ++l) {
+        if (i < rd && l < rd) {
+          const int t = TRANS ? l * rd + i : i * rd + l;
+          const TV e = t < WAVE ? readlane(v[0], t) : readlane(v[NV - 1], t - (NV - 1) * WAVE);
+          acc += e * s[l];
+        }
+      }
+      z[i] = acc;
+    }
+  }
+};
+
 // One wavefront per CPW cells (the loads of all of them are issued before
 // the first scan), NCH = ceil(m / 64) chunks of 64 unknowns held in
 // registers, NR right-hand sides per launch starting at r0.  Scans and the
@@ -221,23 +349,27 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 #ifndef R1S_APPLY_CPW
 #define R1S_APPLY_CPW 1
 #endif
-template <typename TV, int NCH, int NR, bool TRANS>
+template <typename TV, int NCH, int NR, bool TRANS, int RDM>
 __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
                                                        const TV* __restrict__ invC,
                                                        const double* __restrict__ rin,
                                                        double* __restrict__ zout, int r0) {
-  constexpr int CPW = NCH == 1 ? R1S_APPLY_CPW : 1;
+  constexpr int CPW = (NCH == 1 && RDM == 1) ? R1S_APPLY_CPW : 1;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int c0 = __builtin_amdgcn_readfirstlane((tile * WPB + (int)(threadIdx.x >> 6)) * CPW);
   if (c0 >= g.N) return;
   const int lane = lane_id();
-  const int L = g.L, m = g.m, mp = g.mp;
-  TV A[CPW][NCH], DI[CPW][NCH], B[CPW][NCH], W[CPW][NCH], V[CPW][NCH];
-  TV R[CPW][NR][NCH], RF[CPW][NR][3], IC[CPW];
+  const int L = g.L, m = g.m;
+  const long long mp = g.mp;
+  const int rd = RDM == 1 ? 1 : g.rd;
+  const int SR = 3 + 2 * rd;
+  TV A[CPW][NCH], DI[CPW][NCH], B[CPW][NCH], W[CPW][RDM][NCH], V[CPW][RDM][NCH];
+  TV R[CPW][NR][NCH], RF[CPW][NR][3];
+  CapInv<TV, RDM> IC[CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int c = c0 + j < g.N ? c0 + j : g.N - 1;
-    const TV* fc = fac + (long long)c * F_SMW * mp;
+    const TV* fc = fac + (long long)c * SR * mp;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int k = ch * WAVE + lane;
@@ -245,8 +377,11 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
       A[j][ch] = ld_stream(fc + P_A * mp + kk);
       DI[j][ch] = ld_stream(fc + P_DINV * mp + kk);
       B[j][ch] = ld_stream(fc + P_B * mp + kk);
-      W[j][ch] = ld_stream(fc + P_W * mp + kk);
-      V[j][ch] = ld_stream(fc + P_V * mp + kk);
+#pragma unroll
+      for (int i = 0; i < RDM; ++i) {
+        W[j][i][ch] = i < rd ? ld_stream(fc + (P_W + i) * mp + kk) : TV(0);
+        V[j][i][ch] = i < rd ? ld_stream(fc + (P_W + rd + i) * mp + kk) : TV(0);
+      }
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         R[j][r][ch] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + kk];
@@ -256,7 +391,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
 #pragma unroll
       for (int i = 0; i < 3; ++i)
         RF[j][r][i] = (TV)rin[(long long)(r0 + r) * g.n + (long long)c * m + L + i];
-    IC[j] = invC[c];
+    IC[j].load(invC, c, rd, lane);
   }
 
 #pragma unroll
@@ -267,16 +402,24 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
       TV X0[NCH];
       smw_sweeps<TV, NCH, TRANS>(L, m, A[j], DI[j], B[j], R[j][r], RF[j][r][0], RF[j][r][1],
                                  RF[j][r][2], X0);
-      TV s = TV(0);
+      TV s[RDM], z[RDM];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) s += V[j][ch] * X0[ch];
-      s = wave_sum_u(s) * IC[j];
+      for (int i = 0; i < RDM; ++i) {
+        TV t = TV(0);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) t += V[j][i][ch] * X0[ch];
+        s[i] = i < rd ? wave_sum_u(t) : TV(0);
+      }
+      IC[j].template apply<TRANS>(s, z, rd);
       if (c < g.N) {
         double* zv = zout + (long long)(r0 + r) * g.n + (long long)c * m;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
           const int k = ch * WAVE + lane;
-          if (k < m) zv[k] = (double)(X0[ch] - s * W[j][ch]);
+          TV o = X0[ch];
+#pragma unroll
+          for (int i = 0; i < RDM; ++i) o -= z[i] * W[j][i][ch];
+          if (k < m) zv[k] = (double)o;
         }
       }
     }
@@ -287,26 +430,33 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
 // Each wave scans its chunk; the chunk compositions go through LDS and every
 // wave folds in the compositions of the chunks before it (forward sweep) or
 // after it (backward sweep), in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS>
+template <typename TV, int NCH, int NR, bool TRANS, int RDM>
 __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __restrict__ fac,
                                                            const TV* __restrict__ invC,
                                                            const double* __restrict__ rin,
                                                            double* __restrict__ zout, int r0) {
-  __shared__ TV fa[NR][NCH], fb[NR][NCH], ga[NR][NCH], gb[NR][NCH], ss[NR][NCH];
+  __shared__ TV fa[NR][NCH], fb[NR][NCH], ga[NR][NCH], gb[NR][NCH], ss[NR][RDM][NCH];
   const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
-  const int L = g.L, m = g.m, mp = g.mp;
+  const int L = g.L, m = g.m;
+  const long long mp = g.mp;
+  const int rd = RDM == 1 ? 1 : g.rd;
+  const int SR = 3 + 2 * rd;
   const int k = wv * WAVE + lane;
   const int kk = k < m ? k : m - 1;
   const bool lev = k < L;
   const bool has_lev = wv * WAVE < L;  // wave-uniform
-  const TV* fc = fac + (long long)c * F_SMW * mp;
+  const TV* fc = fac + (long long)c * SR * mp;
   const TV A = ld_stream(fc + P_A * mp + kk);
   const TV DI = ld_stream(fc + P_DINV * mp + kk);
   const TV B = ld_stream(fc + P_B * mp + kk);
-  const TV W = ld_stream(fc + P_W * mp + kk);
-  const TV V = ld_stream(fc + P_V * mp + kk);
+  TV W[RDM], V[RDM];
+#pragma unroll
+  for (int i = 0; i < RDM; ++i) {
+    W[i] = i < rd ? ld_stream(fc + (P_W + i) * mp + kk) : TV(0);
+    V[i] = i < rd ? ld_stream(fc + (P_W + rd + i) * mp + kk) : TV(0);
+  }
   TV R[NR], RF[NR][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -316,7 +466,8 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
     RF[r][1] = (TV)rv[L + 1];
     RF[r][2] = (TV)rv[L + 2];
   }
-  const TV ic = invC[c];
+  CapInv<TV, RDM> IC;
+  IC.load(invC, c, rd, lane);
 
   TV a[NR], bb[NR];
 #pragma unroll
@@ -353,21 +504,37 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
     const TV x0 = b2[r] + a2[r] * carry;
     const TV xf = A * RF[r][0] + DI * RF[r][1] + B * RF[r][2];
     X0[r] = lev ? x0 : (k < m ? xf : TV(0));
-    const TV sp = wave_sum_u(V * X0[r]);
-    if (lane == 0) ss[r][wv] = sp;
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) {
+      if (i >= rd) break;
+      const TV sp = wave_sum_u(V[i] * X0[r]);
+      if (lane == 0) ss[r][i][wv] = sp;
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    TV st = ss[r][0];
+    TV s[RDM], z[RDM];
 #pragma unroll
-    for (int w = 1; w < NCH; ++w) st += ss[r][w];
-    st *= ic;
-    if (k < m) zout[(long long)(r0 + r) * g.n + (long long)c * m + k] = (double)(X0[r] - st * W);
+    for (int i = 0; i < RDM; ++i) {
+      TV st = TV(0);
+      if (i < rd) {
+        st = ss[r][i][0];
+#pragma unroll
+        for (int w = 1; w < NCH; ++w) st += ss[r][i][w];
+      }
+      s[i] = st;
+    }
+    IC.template apply<TRANS>(s, z, rd);
+    TV o = X0[r];
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) o -= z[i] * W[i];
+    if (k < m) zout[(long long)(r0 + r) * g.n + (long long)c * m + k] = (double)o;
   }
 }
 
-template <typename TV, int NCH, bool TRANS>
+// Right-hand sides per launch: 4 / 2 / 1 (2 / 1 with several diagonal pairs).
+template <typename TV, int NCH, bool TRANS, int RDM>
 static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                  double* z, int nrhs, hipStream_t s) {
 #ifndef R1S_NO_WG_CELL
@@ -375,59 +542,67 @@ static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, c
     int r0 = 0;
     while (r0 < nrhs) {
       const int rem = nrhs - r0;
-      if (rem >= 4) {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 4, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
-        r0 += 4;
+      if (RDM == 1 && rem >= 4) {
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        r0 += RDM == 1 ? 4 : 2;
       } else if (rem >= 2) {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 2, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 2, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += 2;
       } else {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 1, TRANS>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 1, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += 1;
       }
     }
     return hipGetLastError();
   }
 #endif
-  constexpr int CPW = NCH == 1 ? R1S_APPLY_CPW : 1;
+  constexpr int CPW = (NCH == 1 && RDM == 1) ? R1S_APPLY_CPW : 1;
   const int grid = (g.N + WPB * CPW - 1) / (WPB * CPW);
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
-    if (rem >= 4) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 4, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
-      r0 += 4;
+    if (RDM == 1 && rem >= 4) {
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      r0 += RDM == 1 ? 4 : 2;
     } else if (rem >= 2) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 1;
     }
   }
   return hipGetLastError();
 }
 
-template <typename TV, bool TRANS>
+template <typename TV, bool TRANS, int RDM>
 static hipError_t launch_apply_nch(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                    double* z, int nrhs, hipStream_t s) {
   const int nch = (g.m + WAVE - 1) / WAVE;
   switch (nch) {
-    case 1: return launch_apply_t<TV, 1, TRANS>(g, fac, invC, r, z, nrhs, s);
-    case 2: return launch_apply_t<TV, 2, TRANS>(g, fac, invC, r, z, nrhs, s);
-    case 3: return launch_apply_t<TV, 3, TRANS>(g, fac, invC, r, z, nrhs, s);
-    case 4: return launch_apply_t<TV, 4, TRANS>(g, fac, invC, r, z, nrhs, s);
+    case 1: return launch_apply_t<TV, 1, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
+    case 2: return launch_apply_t<TV, 2, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
+    case 3: return launch_apply_t<TV, 3, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
+    case 4: return launch_apply_t<TV, 4, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename TV, bool TRANS>
+static hipError_t launch_apply_rank(const Mesh& g, const TV* fac, const TV* invC, const double* r,
+                                    double* z, int nrhs, hipStream_t s) {
+  if (g.rd == 1) return launch_apply_nch<TV, TRANS, 1>(g, fac, invC, r, z, nrhs, s);
+  if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
+  return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX>(g, fac, invC, r, z, nrhs, s);
 }
 
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s) {
   if (f32)
-    return trans ? launch_apply_nch<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
-                 : launch_apply_nch<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);
-  return trans ? launch_apply_nch<double, true>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s)
-               : launch_apply_nch<double, false>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s);
+    return trans ? launch_apply_rank<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
+                 : launch_apply_rank<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);
+  return trans ? launch_apply_rank<double, true>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s)
+               : launch_apply_rank<double, false>(g, (const double*)fac, (const double*)invC, r, z, nrhs, s);
 }
 
 }  // namespace r1s

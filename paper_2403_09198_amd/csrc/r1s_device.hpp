@@ -1,16 +1,18 @@
 // Device-side helpers shared by the r1s kernels (gfx950, wave64).
 //
 // Internal layout of the packed Jacobian ("record" layout): one contiguous
-// record per mesh cell, [N][F][mp] values, F = 17 field rows of mp = m
-// rounded up to a multiple of 8 (64-byte rows).  Lane k of the wave that owns
-// cell c reads element k of every row, so every load is one contiguous run.
+// record per mesh cell, [N][F][mp] values, F = 7 + 2P field rows of mp = m
+// rounded up to a multiple of 8 (64-byte rows), P = rank-one pairs per cell.
+// Lane k of the wave that owns cell c reads element k of every row, so every
+// load is one contiguous run.
 //
-//   row 0      diag    S_cc[k][k]
-//   row 1      lo      level k: S_cc[k][k-1]; flow row i: S_cc[L+i][L+(i+2)%3]
-//   row 2      hi      level k: S_cc[k][k+1]; flow row i: S_cc[L+i][L+(i+1)%3]
-//   rows 3..6  nbr     diagonal of S_{c,d}, d = S, W, E, N
-//   rows 7..11 u       u_{c,d}, d = S, W, C, E, N
-//   rows 12..16 v      v_{c,d}, d = S, W, C, E, N
+//   row 0          diag  S_cc[k][k]
+//   row 1          lo    level k: S_cc[k][k-1]; flow row i: S_cc[L+i][L+(i+2)%3]
+//   row 2          hi    level k: S_cc[k][k+1]; flow row i: S_cc[L+i][L+(i+1)%3]
+//   rows 3..6      nbr   diagonal of S_{c,d}, d = S, W, E, N
+//   rows 7..6+P    u     the pairs of blocks S, W, C, E, N in that order
+//                        (ro pairs per neighbour block, rd for the diagonal)
+//   rows 7+P..6+2P v     same order
 //
 // Padding elements and the rows of blocks that do not exist (mesh boundary)
 // are zero.
@@ -26,18 +28,22 @@ constexpr int WAVE = 64;
 #endif
 constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
-constexpr int F_REC = 17;    // field rows per cell record
-constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_U = 7, F_V = 12;
+constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_U = 7;  // v rows at F_U + P
 constexpr int D_S = 0, D_W = 1, D_C = 2, D_E = 3, D_N = 4;
 constexpr int MAX_CHUNKS = 4;  // m <= 256
+// Largest pair counts of the general-rank kernels (a diagonal block / a
+// neighbour block); one pair per block has kernels of its own.
+constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 2;
 
-// SMW factor records, [N][5][mp] per direction of application.
-//   forward:   a = -l_k,  dinv = 1/d_k,  b = -s_k/d_k,  w = S_cc^{-1} u_cC, v_cC
-//   transpose: a = -s_{k-1}/d_k, dinv, b = -l_{k+1},  wt = S_cc^{-T} v_cC, u_cC
+// SMW factor records, [N][3 + 2 rd][mp] per direction of application, plus
+// the rd x rd inverse capacitance per cell ([N][rd][rd], row-major).
+//   forward:   a = -l_k,  dinv = 1/d_k,  b = -s_k/d_k,
+//              W_i = S_cc^{-1} u_i, V_i = v_i   (i < rd, the diagonal pairs)
+//   transpose: a = -s_{k-1}/d_k, dinv, b = -l_{k+1},
+//              W_i = S_cc^{-T} v_i, V_i = u_i, and the transposed C^{-1}
 // Flow lanes L+i hold row i of the 3x3 corner inverse (transpose: of its
 // transpose) in the a / dinv / b rows.
-constexpr int F_SMW = 5;
-constexpr int P_A = 0, P_DINV = 1, P_B = 2, P_W = 3, P_V = 4;
+constexpr int P_A = 0, P_DINV = 1, P_B = 2, P_W = 3;  // V rows at P_W + rd
 
 __host__ __device__ inline int pad_m(int m) { return (m + 7) & ~7; }
 __host__ __device__ inline int nbr_slot(int d) { return d < 2 ? d : d - 1; }
@@ -47,7 +53,17 @@ struct Mesh {
   int nx, ny, L, m, mp;
   int N;           // nx*ny
   long long n;     // N*m, stride between right-hand sides
+  int rd, ro;      // rank-one pairs of a diagonal / a neighbour block
+  int P;           // pairs per cell, rd + 4 ro
+  int F;           // record rows per cell, 7 + 2 P
 };
+
+// First record slot and number of the pairs of block direction d.
+__host__ __device__ inline int pair_count(const Mesh& g, int d) { return d == 2 ? g.rd : g.ro; }
+__host__ __device__ inline int pair_start(const Mesh& g, int d) {
+  return d <= 1 ? d * g.ro : d == 2 ? 2 * g.ro : d == 3 ? 2 * g.ro + g.rd : 3 * g.ro + g.rd;
+}
+__host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * g.rd; }
 
 // Workgroup id -> logical tile.  With R1S_XCD_REMAP each XCD (which
 // receives every NXCD-th workgroup) works on one contiguous range of tiles;

@@ -14,6 +14,9 @@ struct GradOut {
   double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
 };
 
+// pair counts the kernels are built for
+bool ranks_supported(int rd, int ro);
+
 // packing / casting
 hipError_t launch_pack(const Mesh& g, const PackIn& in, double* rec64, float* rec32, hipStream_t s);
 hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipStream_t s);
@@ -25,6 +28,8 @@ hipError_t launch_residual(const Mesh& g, const double* rec, bool trans, const d
                            const double* x, double* r, int nrhs, hipStream_t s);
 
 // SMW block-Jacobi
+// invC: per cell the rd x rd inverse capacitance matrix, forward then (when
+// facT) transposed, [2][N][rd][rd] (one [N][rd][rd] without facT)
 hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
                             double* invC, int* status, hipStream_t s);
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,

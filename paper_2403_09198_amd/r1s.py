@@ -45,10 +45,14 @@ def _buffer(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv):
+def _shapes(nx, ny, Lv, n_pairs):
     N, m = nx * ny, Lv + 3
-    shapes = {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
-              "s_nbr": (N, 4, m), "u": (N, 5, m), "v": (N, 5, m)}
+    return {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
+            "s_nbr": (N, 4, m), "u": (N, n_pairs, m), "v": (N, n_pairs, m)}
+
+
+def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv, n_pairs):
+    shapes = _shapes(nx, ny, Lv, n_pairs)
     ins = L.Inputs()
     for k in FIELDS:
         t = values[k]
@@ -65,22 +69,22 @@ def r1s_last_error() -> str:
     return lib().r1s_last_error().decode()
 
 
-def r1s_mat_size(nx, ny, Lv, flags=0) -> int:
+def r1s_mat_size(nx, ny, Lv, r_diag=1, r_off=1, flags=0) -> int:
     b = C.c_size_t()
-    check(lib().r1s_mat_size(nx, ny, Lv, flags, C.byref(b)))
+    check(lib().r1s_mat_size(nx, ny, Lv, r_diag, r_off, flags, C.byref(b)))
     return b.value
 
 
-def r1s_mat_init(nx, ny, Lv, flags, values, mem, stream=None):
+def r1s_mat_init(nx, ny, Lv, r_diag, r_off, flags, values, mem, stream=None):
     h = C.c_void_p()
-    ins = _inputs(values, nx, ny, Lv)
-    check(lib().r1s_mat_init(nx, ny, Lv, flags, C.byref(ins), _ptr(mem), mem.numel(),
-                             _stream(stream), C.byref(h)))
+    ins = _inputs(values, nx, ny, Lv, r_diag + 4 * r_off)
+    check(lib().r1s_mat_init(nx, ny, Lv, r_diag, r_off, flags, C.byref(ins), _ptr(mem),
+                             mem.numel(), _stream(stream), C.byref(h)))
     return h
 
 
-def r1s_mat_update(h, values, nx, ny, Lv, stream=None):
-    ins = _inputs(values, nx, ny, Lv)
+def r1s_mat_update(h, values, nx, ny, Lv, n_pairs, stream=None):
+    ins = _inputs(values, nx, ny, Lv, n_pairs)
     check(lib().r1s_mat_update(h, C.byref(ins), _stream(stream)))
 
 
@@ -164,19 +168,26 @@ def r1s_grad(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
 
 # -------------------------------------------------------------- classes ---
 class R1Matrix:
-    """Structured block r1-sparse Jacobian on one GPU (packed, caller memory)."""
+    """Structured block r1-sparse Jacobian on one GPU (packed, caller memory).
+
+    ranks = (r_diag, r_off): rank-one pairs of every diagonal / neighbour
+    block; u and v have shape [N, r_diag + 4 r_off, m]."""
 
     def __init__(self, nx, ny, L_levels, values: Dict[str, torch.Tensor], keep_f32=False,
-                 stream=None):
+                 stream=None, ranks=(1, 1)):
         self.nx, self.ny, self.L = nx, ny, L_levels
         self.m = L_levels + 3
         self.N = nx * ny
         self.n = self.N * self.m
+        self.r_diag, self.r_off = (int(r) for r in ranks)
+        self.n_pairs = self.r_diag + 4 * self.r_off
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device
         self.device = dev
-        self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.flags), dev)
-        self.h = r1s_mat_init(nx, ny, L_levels, self.flags, values, self.mem, stream)
+        self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.r_diag, self.r_off, self.flags),
+                           dev)
+        self.h = r1s_mat_init(nx, ny, L_levels, self.r_diag, self.r_off, self.flags, values,
+                              self.mem, stream)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -185,7 +196,7 @@ class R1Matrix:
             self.h = None
 
     def update(self, values, stream=None):
-        r1s_mat_update(self.h, values, self.nx, self.ny, self.L, stream)
+        r1s_mat_update(self.h, values, self.nx, self.ny, self.L, self.n_pairs, stream)
 
     def storage(self):
         return r1s_mat_storage(self.h)
@@ -310,9 +321,7 @@ def grad(A: R1Matrix, lam, x, stream=None) -> Dict[str, torch.Tensor]:
     """Gradients w.r.t. the structured arrays given lambda = J^{-T} dLoss/dx."""
     nrhs = _need_vec(lam, "lambda", A.n)
     _need_vec(x, "x", A.n)
-    N, m, Lv = A.N, A.m, A.L
-    shapes = {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
-              "s_nbr": (N, 4, m), "u": (N, 5, m), "v": (N, 5, m)}
+    shapes = _shapes(A.nx, A.ny, A.L, A.n_pairs)
     out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device) for k in FIELDS}
     r1s_grad(A.h, nrhs, lam, x, out, stream)
     return out

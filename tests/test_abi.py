@@ -37,22 +37,45 @@ def _rc(code_call):
 def test_size_validation():
     lib = L.lib()
     b = C.c_size_t()
-    assert lib.r1s_mat_size(0, 4, 4, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(0, 4, 4, 1, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
     assert "must be >= 1" in lib.r1s_last_error().decode()
-    assert lib.r1s_mat_size(4, 4, 0, 0, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 254, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
-    assert lib.r1s_mat_size(4, 4, 4, 0, None) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 4, 0x10, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 253, 1, C.byref(b)) == L.R1S_OK
+    assert lib.r1s_mat_size(4, 4, 0, 1, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 254, 1, 1, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, 1, 1, 0, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, 1, 1, 0x10, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 253, 1, 1, 1, C.byref(b)) == L.R1S_OK
     # packed rows are padded to 8 values: 17 rows of 256 doubles + floats
     assert b.value >= 16 * 17 * 256 * 12
+
+
+def test_rank_validation():
+    lib = L.lib()
+    b = C.c_size_t()
+    assert lib.r1s_mat_size(4, 4, 4, 0, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert "r_diag" in lib.r1s_last_error().decode()
+    assert lib.r1s_mat_size(4, 4, 4, 1, -1, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, 10, 2, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, 9, 3, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    for rd, ro in ((9, 2), (1, 0), (2, 0), (3, 1)):
+        assert lib.r1s_mat_size(4, 4, 4, rd, ro, 0, C.byref(b)) == L.R1S_OK
+        # one record of 7 + 2 (rd + 4 ro) rows of 8 doubles per cell
+        assert b.value >= 16 * (7 + 2 * (rd + 4 * ro)) * 8 * 8
+
+
+def test_size_grows_with_pairs():
+    lib = L.lib()
+    a, b = C.c_size_t(), C.c_size_t()
+    lib.r1s_mat_size(64, 32, 61, 1, 1, 0, C.byref(a))
+    lib.r1s_mat_size(64, 32, 61, 9, 2, 0, C.byref(b))
+    mp = 64
+    assert b.value - a.value == 64 * 32 * 2 * (17 - 5) * mp * 8
 
 
 def test_size_is_linear_in_cells():
     lib = L.lib()
     a, b = C.c_size_t(), C.c_size_t()
-    lib.r1s_mat_size(64, 32, 61, 0, C.byref(a))
-    lib.r1s_mat_size(128, 32, 61, 0, C.byref(b))
+    lib.r1s_mat_size(64, 32, 61, 1, 1, 0, C.byref(a))
+    lib.r1s_mat_size(128, 32, 61, 1, 1, 0, C.byref(b))
     assert abs(b.value - 2 * a.value) <= 512
 
 
@@ -61,20 +84,20 @@ def test_init_rejects_bad_arguments_before_device_work():
     ins = L.Inputs()
     h = C.c_void_p()
     fake = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
-    assert lib.r1s_mat_init(4, 4, 4, 0, None, fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, None, fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "is NULL" in lib.r1s_last_error().decode()
     for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"):
         setattr(ins, k, 1 << 21)
     ins.u = (1 << 21) + 4  # misaligned
-    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "aligned" in lib.r1s_last_error().decode()
     ins.u = 1 << 21
-    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 16, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 16, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "mem_bytes" in lib.r1s_last_error().decode()
-    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), C.c_void_p((1 << 20) + 8), 1 << 30, None,
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), C.c_void_p((1 << 20) + 8), 1 << 30, None,
                             C.byref(h)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_init(4, 4, 4, 0, C.byref(ins), fake, 1 << 30, None, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, None) == L.R1S_ERR_ARG
 
 
 def test_null_handles_rejected():
