@@ -6,9 +6,13 @@ definition of r1-sparsity in section 4.1):
 
     D_{c,d} = S_{c,d} + sum over the block's pairs p of  u_p v_p^T.
 
-S_{c,C} (the diagonal block) has a full diagonal, a tridiagonal band coupling
-neighbouring levels k, k+1 (k < L) and a dense 3 x 3 corner for the flow
-unknowns L, L+1, L+2.  S_{c,d} for d != C is diagonal.
+S_{c,C} (the diagonal block) has a full diagonal, a band coupling levels k, k'
+with 0 < |k - k'| <= band (band = 1: tridiagonal; section 4, "Temporal Source
+Jacobian": level-changing processes up to a threshold jump give a banded
+pattern), a dense 3 x 3 corner for the flow unknowns L, L+1, L+2 and, with
+the arrow option, dense coupling between the level rows and the flow columns
+and between the flow rows and the level columns.  S_{c,d} for d != C is
+diagonal.
 
 The result is stored in the paper's BSR format (section 5.1): block_indptr,
 block_indices (ascending block columns within a block row) and a 3-D data
@@ -31,6 +35,16 @@ def diagonal_sparse_block(p, c: int, L: int) -> np.ndarray:
         A[k, k + 1] = p["s_sup"][c, k]
     for t, (i, j) in enumerate(FLOW_PAIRS):
         A[L + i, L + j] = p["s_flow"][c, t]
+    band, arrow = mesh.pattern(p)
+    for j in range(2, band + 1):
+        for k in range(j, L):
+            A[k, k - j] = p["s_band"][c, j - 2, k]
+        for k in range(0, L - j):
+            A[k, k + j] = p["s_band"][c, band - 1 + j - 2, k]
+    if arrow:
+        for i in range(3):
+            A[:L, L + i] = p["s_lev_flow"][c, i]
+            A[L + i, :L] = p["s_flow_lev"][c, i]
     return A
 
 

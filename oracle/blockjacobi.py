@@ -18,7 +18,7 @@ uses that sign; a test shows the printed sign fails to invert the block.
 """
 import numpy as np
 
-from . import mesh
+from . import assemble, mesh
 
 
 class SingularBlock(ArithmeticError):
@@ -117,9 +117,13 @@ def tridiag_solve(diag, sub, sup, r):
 
 
 def sparse_diag_solve(p, c, L, r):
-    """x = (S_{c,C})^{-1} r: the level band and the 3 x 3 flow corner are
-    uncoupled, so solve each on its own."""
+    """x = (S_{c,C})^{-1} r.  Tridiagonal band without coupling: the level
+    band and the 3 x 3 flow corner are uncoupled, so solve each on its own.
+    A wider band or level/flow coupling: LAPACK's dense solve of the
+    assembled sparse block."""
     r = np.asarray(r, dtype=np.float64)
+    if mesh.pattern(p) != (1, 0):
+        return np.linalg.solve(assemble.diagonal_sparse_block(p, c, L), r)
     x = np.zeros(L + 3)
     x[:L] = tridiag_solve(p["s_diag"][c, :L], p["s_sub"][c], p["s_sup"][c], r[:L])
     F = np.diag(p["s_diag"][c, L:])

@@ -167,6 +167,19 @@ def structured_csr(p, nx, ny, L):
                 for t, (a, b) in enumerate(assemble.FLOW_PAIRS):
                     if a == i:
                         row[c * m + L + b] = p["s_flow"][c, t]
+            band, arrow = mesh.pattern(p)
+            if k < L:
+                for j in range(2, band + 1):
+                    if k - j >= 0:
+                        row[c * m + k - j] = p["s_band"][c, j - 2, k]
+                    if k + j < L:
+                        row[c * m + k + j] = p["s_band"][c, band - 1 + j - 2, k]
+                if arrow:
+                    for i in range(3):
+                        row[c * m + L + i] = p["s_lev_flow"][c, i, k]
+            elif arrow:
+                for kk in range(L):
+                    row[c * m + kk] = p["s_flow_lev"][c, k - L, kk]
             # neighbour blocks are diagonal
             for d in (mesh.S, mesh.W, mesh.E, mesh.N):
                 nb = mesh.neighbour(nx, ny, c, d)

@@ -28,8 +28,11 @@ def structured_grads(p, nx, ny, L, lam, x):
     if lam.ndim == 2:
         lam, x = lam[None], x[None]
     N, m = nx * ny, L + 3
-    g = {k: np.zeros_like(p[k]) for k in ("s_diag", "s_sub", "s_sup", "s_flow",
-                                          "s_nbr", "u", "v")}
+    band, arrow = mesh.pattern(p)
+    keys = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
+    if (band, arrow) != (1, 0):
+        keys = keys + ("s_band", "s_lev_flow", "s_flow_lev")
+    g = {k: np.zeros_like(p[k]) for k in keys}
     for c in range(N):
         for d in (mesh.S, mesh.W, mesh.C, mesh.E, mesh.N):
             nb = mesh.neighbour(nx, ny, c, d)
@@ -47,6 +50,15 @@ def structured_grads(p, nx, ny, L, lam, x):
                     g["s_sup"][c, k] = G[k, k + 1]
                 for t, (i, j) in enumerate(assemble.FLOW_PAIRS):
                     g["s_flow"][c, t] = G[L + i, L + j]
+                for j in range(2, band + 1):
+                    for k in range(j, L):
+                        g["s_band"][c, j - 2, k] = G[k, k - j]
+                    for k in range(0, L - j):
+                        g["s_band"][c, band - 1 + j - 2, k] = G[k, k + j]
+                if arrow:
+                    for i in range(3):
+                        g["s_lev_flow"][c, i] = G[:L, L + i]
+                        g["s_flow_lev"][c, i] = G[L + i, :L]
             else:
                 g["s_nbr"][c, mesh.NBR_SLOT[d]] = np.diag(G)
     return g

@@ -60,6 +60,17 @@ def pair_range(p, d: int):
     return sum(counts[:d]), counts[d]
 
 
+def pattern(p):
+    """(band, arrow) of the diagonal sparse block: level diagonals up to
+    |k - k'| <= band, and whether level rows and flow rows are coupled (the
+    temperature dependence of the level sources, section 4, "Temporal Source
+    Jacobian").  Default (1, 0): tridiagonal band, no coupling."""
+    if "pattern" not in p:
+        return 1, 0
+    band, arrow = (int(v) for v in p["pattern"])
+    return band, arrow
+
+
 def opposite(d: int) -> int:
     """The direction pointing back: the neighbour's block towards c."""
     return {S: N, W: E, C: C, E: W, N: S}[d]

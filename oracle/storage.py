@@ -26,10 +26,15 @@ def bsr_values(nx: int, ny: int, m: int) -> int:
     return n_blocks(nx, ny) * m * m
 
 
-def structured_values(nx: int, ny: int, m: int, r_diag: int = 1, r_off: int = 1) -> int:
-    """r_diag pairs on every diagonal block, r_off on every neighbour block."""
+def structured_values(nx: int, ny: int, m: int, r_diag: int = 1, r_off: int = 1,
+                      band: int = 1, arrow: bool = False) -> int:
+    """r_diag pairs on every diagonal block, r_off on every neighbour block;
+    the diagonal block's level band has half-width `band` (2 (L - j) entries
+    on the j-th diagonals) and `arrow` adds 6 L level/flow couplings."""
     N = nx * ny
     B = n_blocks(nx, ny)
     L = m - 3
-    diag_block = m + 2 * (L - 1) + 6
+    diag_block = m + sum(2 * max(L - j, 0) for j in range(1, band + 1)) + 6
+    if arrow:
+        diag_block += 6 * L
     return N * diag_block + (B - N) * m + (N * r_diag + (B - N) * r_off) * 2 * m

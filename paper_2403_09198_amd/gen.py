@@ -23,6 +23,16 @@ Array layout (all float64, C-contiguous; N = nx*ny, cell c = iy*nx + ix):
                      diagonal block, P = r_diag + 4 r_off (P = 5 for one pair
                      per block)
 
+Optional, for a wider sparse diagonal block (band > 1 and/or arrow):
+  s_band     [N][2(band-1)][L]  further level diagonals: row j-2 holds
+                                S_cc[k][k-j] and row band-1+j-2 holds
+                                S_cc[k][k+j] at index k, j = 2..band
+                                (entries outside the block are zero)
+  s_lev_flow [N][3][L]          S_cc[k][L+i] at [c][i][k]: level rows coupled
+                                to the flow unknowns (temperature dependence)
+  s_flow_lev [N][3][L]          S_cc[L+i][k] at [c][i][k]: flow rows coupled
+                                to the levels
+
 Directions: 0 = S (iy-1), 1 = W (ix-1), 2 = C, 3 = E (ix+1), 4 = N (iy+1).
 The paper's structure (section 4, "Overall Structure") has r_diag = 9 (one
 source term and two per face) and r_off = 2 (two trace-flux terms); the
@@ -32,7 +42,9 @@ missing neighbour, and the slots for such blocks are zero.
 
 Value distributions (one fixed draw order from numpy's PCG64):
   s_diag = inv_dt + 10*|N(0,1)|, s_sub, s_sup, s_flow ~ N(0,1),
-  s_nbr ~ U(-1,0), u, v ~ N(0, 0.1^2).  Right-hand sides from seed+1, loss
+  s_nbr ~ U(-1,0), u, v ~ N(0, 0.1^2), then (only when requested) s_band ~
+  N(0,1), s_lev_flow ~ N(0, 0.1^2), s_flow_lev ~ N(0,1)/L (row sums of the
+  flow rows stay O(1) at any L).  Right-hand sides from seed+1, loss
   weights from seed+2, both N(0,1).  inv_dt = 20 makes S strictly row
   diagonally dominant with overwhelming probability; inv_dt = 1 is a stress
   case that forces GMRES restarts.
@@ -49,6 +61,8 @@ DIR_S, DIR_W, DIR_C, DIR_E, DIR_N = 0, 1, 2, 3, 4
 NBR_DIRS = (DIR_S, DIR_W, DIR_E, DIR_N)
 
 FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
+# arrays of the wider diagonal-block pattern (present when band > 1 or arrow)
+PATTERN_FIELDS = ("s_band", "s_lev_flow", "s_flow_lev")
 
 
 @dataclass(frozen=True)
@@ -109,13 +123,17 @@ def pair_slots(r_diag: int = 1, r_off: int = 1):
 
 
 def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
-                 r_diag: int = 1, r_off: int = 1) -> Dict[str, np.ndarray]:
+                 r_diag: int = 1, r_off: int = 1, band: int = 1,
+                 arrow: bool = False) -> Dict[str, np.ndarray]:
     """Draw the structured values of one Jacobian (float64 arrays).  The
-    returned dict also holds "ranks" = [r_diag, r_off]."""
+    returned dict also holds "ranks" = [r_diag, r_off] and, for a wider
+    diagonal block, "pattern" = [band, arrow] with the PATTERN_FIELDS."""
     if nx < 1 or ny < 1 or L < 1:
         raise ValueError("nx, ny, L must be >= 1")
     if r_diag < 1 or r_off < 0:
         raise ValueError("need r_diag >= 1 and r_off >= 0")
+    if band < 1:
+        raise ValueError("need band >= 1")
     N, m = nx * ny, L + 3
     P = r_diag + 4 * r_off
     rng = np.random.default_rng(seed)
@@ -133,9 +151,25 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
     for d, (a, cnt) in enumerate(pair_slots(r_diag, r_off)):
         p["u"][~ex[:, d], a:a + cnt, :] = 0.0
         p["v"][~ex[:, d], a:a + cnt, :] = 0.0
-    for k in FIELDS:
+    wide = band > 1 or arrow
+    if wide:
+        nb = band - 1
+        p["s_band"] = rng.standard_normal((N, 2 * nb, L))
+        k = np.arange(L)
+        for j in range(2, band + 1):
+            p["s_band"][:, j - 2, k < j] = 0.0             # S[k][k-j] needs k >= j
+            p["s_band"][:, nb + j - 2, k + j > L - 1] = 0.0  # S[k][k+j] needs k+j < L
+        if arrow:
+            p["s_lev_flow"] = 0.1 * rng.standard_normal((N, 3, L))
+            p["s_flow_lev"] = rng.standard_normal((N, 3, L)) / L
+        else:
+            p["s_lev_flow"] = np.zeros((N, 3, L))
+            p["s_flow_lev"] = np.zeros((N, 3, L))
+    for k in FIELDS + (PATTERN_FIELDS if wide else ()):
         p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
     p["ranks"] = np.array([r_diag, r_off])
+    if wide:
+        p["pattern"] = np.array([band, int(bool(arrow))])
     return p
 
 
