@@ -201,6 +201,50 @@ def profile_pass(torch, A, M, x, y, z):
                                                                           src.numel() * 8))
 
 
+def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0):
+    """The float64 pair with several rank-one pairs per block (the paper's
+    9 / 2 structure); algorithmic bytes from the library's storage counts."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks}")
+    p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1])
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
+    del p
+    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks)
+    del vals
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
+    t_setup = time.perf_counter() - t0
+    st = A.storage()
+    mv, ap = st["matvec_bytes"], st["smw_apply_bytes"]
+    x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    N = nx * ny
+    row = {"r_diag": ranks[0], "r_off": ranks[1], "stored_values": st["structured_values"],
+           "smw_setup_ms": round(t_setup * 1e3, 2)}
+    for tag, f1, f2, vb in (
+            ("f64", lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z), 8),
+            ("f32", lambda: A.matvec(x, out=y, precision="f32"),
+             lambda: M.apply(y, out=z, precision="f32"), 4),
+            ("adjoint", lambda: A.matvec(x, out=y, trans=True),
+             lambda: M.apply(y, out=z, trans=True), 8)):
+        # float32 values halve the matrix-side bytes; vectors stay float64
+        vec_b = 8 * 2 * N * (L + 3)
+        nbytes = (mv - vec_b) * vb // 8 + vec_b + (ap - vec_b) * vb // 8 + vec_b
+        wall, k1, k2 = measure_pair(torch, f1, f2, steps, warm)
+        row[tag] = {"gbs": round(nbytes / (wall / steps) / 1e9, 1),
+                    "us_per_step": round(wall / steps * 1e6, 2),
+                    "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
+                    "matvec_gbs": round(((mv - vec_b) * vb // 8 + vec_b) / (k1 / 1e3) / 1e9, 1),
+                    "apply_gbs": round(((ap - vec_b) * vb // 8 + vec_b) / (k2 / 1e3) / 1e9, 1)}
+    del A, M, x, y, z
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return row
+
+
 def sweep(torch, levels=(32, 61, 120, 200), steps=50, warm=5):
     """Level sweep on the 512 x 256 mesh: structured pairs (float64, float32,
     adjoint) against the dense-block BSR pair.  BSR storage grows as m^2, so
@@ -396,6 +440,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="mesh256x128_L61")
+    ap.add_argument("--ranks", default="1,1",
+                    help="rank-one pairs per diagonal,neighbour block of the timed step "
+                         "(the workload's own layout is 1,1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 pair (for profiling runs)")
@@ -431,9 +478,11 @@ def main():
     B = 5 * N - 2 * nx - 2 * ny
     dev = "cuda:0"
     log(f"workload {w.name}: mesh {nx}x{ny}, L={L}, m={m}, blocks={B}")
-    p = gen.make_problem(nx, ny, L, seed=w.seed, inv_dt=w.inv_dt)
+    ranks = tuple(int(v) for v in args.ranks.split(","))
+    p = gen.make_problem(nx, ny, L, seed=w.seed, inv_dt=w.inv_dt, r_diag=ranks[0],
+                         r_off=ranks[1])
     vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
-    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True)
+    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks)
     M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
     del vals
     x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
@@ -441,6 +490,9 @@ def main():
     z = torch.empty_like(x)
 
     mv_b, ap_b = pair_bytes(N, B, m)
+    if ranks != (1, 1):
+        st = A.storage()
+        mv_b, ap_b = st["matvec_bytes"], st["smw_apply_bytes"]
     steps, warm = args.steps, args.warmup
     if args.profile_pass:
         profile_pass(torch, A, M, x, y, z)
@@ -474,14 +526,16 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "nx": nx, "ny": ny, "L": L, "m": m, "nrhs": 1,
+                   "pairs_per_block": {"diagonal": ranks[0], "neighbour": ranks[1]},
                    "step": "y = J x then z = M y (SMW block-Jacobi), float64, replayed as a HIP graph",
                    "bytes_per_step": mv_b + ap_b},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "cell_updates_per_s": round(N / (wall / steps), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false> (J x)",
+        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false,1,1> (J x)",
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic("void r1s::k_matvec<double, 1, 1, false, false>"),
+                     "traffic": counter_traffic(
+                         "void r1s::k_matvec<double, 1, 1, false, false, 1, 1>"),
                      "avg_launch_us": round(mv_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": mv_b},
         "kernels_us": {"matvec_f64": round(mv_ms * 1e3, 2), "smw_apply_f64": round(ap_ms * 1e3, 2)},
@@ -540,6 +594,9 @@ def main():
             del Bm, P
         except Exception as e:  # report, never hide
             out["bsr_pair"] = {"error": str(e)}
+        # the paper's rank structure (9 pairs per diagonal block, 2 per
+        # neighbour block) on the same mesh
+        out["paper_ranks_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm)
         # full GMRES(50) solve to 1e-10 (float64) and the mixed-precision solve
         b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
         for mode in ("f64", "mixed"):
