@@ -16,6 +16,14 @@
  * temporal-source pair plus two per trace flux; 1 and 1 is the smallest
  * layout).  Supported: 1 <= r_diag <= 9, 0 <= r_off <= 2.
  *
+ * The sparse diagonal block S_{c,C} has a level band of half-width `band`
+ * (section 4, Temporal Source Jacobian: level-changing processes up to a
+ * threshold jump give a banded pattern; band = 1 is tridiagonal) and, with
+ * `arrow`, dense coupling of the level rows to the three flow columns
+ * (temperature dependence of the level sources) and of the flow rows to the
+ * levels.  These are described by r1s_layout; a NULL layout means one pair
+ * per block, band = 1, no coupling.
+ *
  * The library multiplies by J and J^T (section 5.2), applies the block-Jacobi
  * preconditioner through the Sherman-Morrison-Woodbury identity (section 6,
  * eq. SMW, with the sign of the correction term corrected to minus), and
@@ -57,10 +65,17 @@
  *   u, v   [N][P][m]  rank-one pairs, P = r_diag + 4 r_off, in block order
  *                     S (r_off slots), W (r_off), C (r_diag), E (r_off),
  *                     N (r_off)
+ *   s_band [N][2(band-1)][L]  (band > 1) level diagonals j = 2..band: row
+ *                     j-2 holds S_{c,C}[k][k-j], row band-1+j-2 holds
+ *                     S_{c,C}[k][k+j], both at index k (entries outside the
+ *                     block must be finite and are ignored)
+ *   s_lev_flow [N][3][L]  (arrow) S_{c,C}[k][L+i] at [c][i][k]
+ *   s_flow_lev [N][3][L]  (arrow) S_{c,C}[L+i][k] at [c][i][k]
  * Directions: S = (ix, iy-1), W = (ix-1, iy), C = the cell, E = (ix+1, iy),
  * N = (ix, iy+1).  The mesh is not periodic: slots of blocks that do not
  * exist must hold finite values and are treated as zero.  s_sub / s_sup may
- * be NULL when L = 1.
+ * be NULL when L = 1; s_band, s_lev_flow, s_flow_lev may be NULL when the
+ * layout does not use them.
  */
 #ifndef R1S_H
 #define R1S_H
@@ -89,11 +104,20 @@ extern "C" {
 #define R1S_KEEP_F32 1   /* also keep float32 copies (mixed precision)      */
 #define R1S_WITH_TRANS 2 /* preconditioner: also set up the transposed apply */
 
-#define R1S_MAX_M 256 /* largest supported block size m = L + 3 */
+#define R1S_MAX_M 256   /* largest supported block size m = L + 3 */
+#define R1S_MAX_BAND 8  /* largest level-band half-width of S_{c,C} */
 
 typedef struct r1s_mat_s* r1s_mat;   /* structured r1-sparse Jacobian      */
 typedef struct r1s_prec_s* r1s_prec; /* block-Jacobi preconditioner        */
 typedef struct r1s_bsr_s* r1s_bsr;   /* dense-block BSR copy of a Jacobian */
+
+/* Block structure of the Jacobian (see the layout above). */
+typedef struct {
+  int r_diag; /* rank-one pairs per diagonal block, 1..9          */
+  int r_off;  /* rank-one pairs per neighbour block, 0..2         */
+  int band;   /* level-band half-width of S_{c,C}, 1..R1S_MAX_BAND */
+  int arrow;  /* 1: level rows x flow columns, flow rows x levels  */
+} r1s_layout;
 
 typedef struct {
   const double* s_diag;
@@ -103,9 +127,13 @@ typedef struct {
   const double* s_nbr;
   const double* u;
   const double* v;
+  const double* s_band;
+  const double* s_lev_flow;
+  const double* s_flow_lev;
 } r1s_inputs;
 
-/* Gradient outputs, same shapes as r1s_inputs (device pointers, written). */
+/* Gradient outputs, same shapes as r1s_inputs (device pointers, written;
+ * the last three only for layouts that have them). */
 typedef struct {
   double* s_diag;
   double* s_sub;
@@ -114,6 +142,9 @@ typedef struct {
   double* s_nbr;
   double* u;
   double* v;
+  double* s_band;
+  double* s_lev_flow;
+  double* s_flow_lev;
 } r1s_grads;
 
 typedef struct {
@@ -161,11 +192,12 @@ typedef struct {
 const char* r1s_last_error(void);
 
 /* Device bytes of the packed matrix for an nx x ny mesh with L levels and
- * r_diag / r_off rank-one pairs per diagonal / neighbour block.
- * flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG for
- * nx, ny, L < 1, r_diag < 1, r_off < 0 or a NULL `bytes`;
- * R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M or r_diag > 9 or r_off > 2. */
-int r1s_mat_size(int nx, int ny, int L, int r_diag, int r_off, int flags,
+ * the block structure `layout` (NULL: one pair per block, band 1, no
+ * coupling).  flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG
+ * for nx, ny, L < 1, r_diag < 1, r_off < 0, band < 1, arrow not 0/1, or a
+ * NULL `bytes`; R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M, r_diag > 9,
+ * r_off > 2 or band > R1S_MAX_BAND. */
+int r1s_mat_size(int nx, int ny, int L, const r1s_layout* layout, int flags,
                  size_t* bytes);
 
 /* Pack the structured arrays (see the layout above) into `mem` and create a
@@ -173,7 +205,7 @@ int r1s_mat_size(int nx, int ny, int L, int r_diag, int r_off, int flags,
  * and the block size by m; here it is implicit in (nx, ny, L).
  * Errors: R1S_ERR_ARG (dims, NULL or misaligned pointer, mem_bytes too
  * small), R1S_ERR_HIP. */
-int r1s_mat_init(int nx, int ny, int L, int r_diag, int r_off, int flags,
+int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int flags,
                  const r1s_inputs* in, void* mem, size_t mem_bytes,
                  void* stream, r1s_mat* out);
 
@@ -203,13 +235,14 @@ int r1s_prec_size(r1s_mat A, int flags, size_t* bytes);
 
 /* Section 6: block-Jacobi with D_c = A0_c + U_c V_c^T (eq. R1_Block_Jacobian;
  * the r_diag columns of U_c, V_c are the pairs of the diagonal block).
- * Factors the sparse diagonal block A0_c (tridiagonal level band by LU
- * without pivoting, 3 x 3 flow corner by its inverse), solves
- * A0_c W_c = U_c (SMW-1), forms the r_diag x r_diag capacitance
- * C_c = I + V_c^T W_c (SMW-2) and inverts it (Gauss-Jordan, partial
- * pivoting).  Synchronises; returns R1S_ERR_SINGULAR naming the first cell
- * with a zero pivot of A0_c or of C_c (|pivot| <= 1e-12 (1 + |V_c| |W_c|),
- * Frobenius norms). */
+ * Factors the sparse diagonal block A0_c by LU without pivoting: the level
+ * band (Thomas algorithm for band 1, banded LU otherwise), the flow corner
+ * by its 3 x 3 inverse or, with level/flow coupling, by the inverse of its
+ * 3 x 3 Schur complement; solves A0_c W_c = U_c (SMW-1), forms the
+ * r_diag x r_diag capacitance C_c = I + V_c^T W_c (SMW-2) and inverts it
+ * (Gauss-Jordan, partial pivoting).  Synchronises; returns R1S_ERR_SINGULAR
+ * naming the first cell with a zero pivot of A0_c or of C_c
+ * (|pivot| <= 1e-12 (1 + |V_c| |W_c|), Frobenius norms). */
 int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
                    void* stream, r1s_prec* out);
 

@@ -27,16 +27,25 @@ ERROR_NAMES = {
 R1S_F64, R1S_F32 = 0, 1
 R1S_KEEP_F32, R1S_WITH_TRANS = 1, 2
 R1S_MAX_M = 256
+R1S_MAX_BAND = 8
 R1S_OP_STRUCTURED, R1S_OP_BSR = 0, 1
 R1S_MODE_F64, R1S_MODE_MIXED_IR = 0, 1
 
 
+INPUT_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v", "s_band", "s_lev_flow",
+                "s_flow_lev")
+
+
+class Layout(C.Structure):
+    _fields_ = [("r_diag", C.c_int), ("r_off", C.c_int), ("band", C.c_int), ("arrow", C.c_int)]
+
+
 class Inputs(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")]
+    _fields_ = [(k, C.c_void_p) for k in INPUT_FIELDS]
 
 
 class Grads(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")]
+    _fields_ = [(k, C.c_void_p) for k in INPUT_FIELDS]
 
 
 class Storage(C.Structure):
@@ -64,8 +73,8 @@ _PSZ = C.POINTER(C.c_size_t)
 # name -> (restype, argtypes); every function declared in include/r1s.h
 SIGNATURES = {
     "r1s_last_error": (C.c_char_p, []),
-    "r1s_mat_size": (_I, [_I, _I, _I, _I, _I, _I, _PSZ]),
-    "r1s_mat_init": (_I, [_I, _I, _I, _I, _I, _I, C.POINTER(Inputs), _VP, _SZ, _VP,
+    "r1s_mat_size": (_I, [_I, _I, _I, C.POINTER(Layout), _I, _PSZ]),
+    "r1s_mat_init": (_I, [_I, _I, _I, C.POINTER(Layout), _I, C.POINTER(Inputs), _VP, _SZ, _VP,
                           C.POINTER(_VP)]),
     "r1s_mat_update": (_I, [_VP, C.POINTER(Inputs), _VP]),
     "r1s_mat_destroy": (_I, [_VP]),

@@ -15,17 +15,23 @@ FIELDS = r1s.FIELDS
 
 
 class R1SolveFn(torch.autograd.Function):
+    """apply(b, cfg, *arrays): arrays are the structured arrays the layout in
+    cfg uses, in the order of r1s_inputs (FIELDS, then s_band and/or
+    s_lev_flow, s_flow_lev)."""
+
     @staticmethod
-    def forward(ctx, b, s_diag, s_sub, s_sup, s_flow, s_nbr, u, v, cfg):
+    def forward(ctx, b, cfg, *arrays):
         nx, ny, L = cfg["nx"], cfg["ny"], cfg["L"]
-        vals = dict(zip(FIELDS, (s_diag, s_sub, s_sup, s_flow, s_nbr, u, v)))
-        vals = {k: t.detach().contiguous() for k, t in vals.items()}
-        A = r1s.R1Matrix(nx, ny, L, vals, ranks=cfg.get("ranks", (1, 1)))
+        lay = r1s.layout(*cfg.get("ranks", (1, 1)), cfg.get("band", 1), cfg.get("arrow", False))
+        names = r1s._used_fields(lay)
+        vals = {k: t.detach().contiguous() for k, t in zip(names, arrays)}
+        A = r1s.R1Matrix(nx, ny, L, vals, ranks=(lay.r_diag, lay.r_off), band=lay.band,
+                         arrow=bool(lay.arrow))
         M = r1s.SMWPreconditioner(A, with_trans=True)
         bb = b.detach().contiguous()
         res = r1s.gmres(A, M, bb, restart=cfg.get("restart", 50), rtol=cfg.get("rtol", 1e-12),
                         max_cycles=cfg.get("max_cycles", 200))
-        ctx.A, ctx.M, ctx.cfg = A, M, cfg
+        ctx.A, ctx.M, ctx.cfg, ctx.names = A, M, cfg, names
         ctx.stats = res.stats
         ctx.save_for_backward(res.x)
         return res.x
@@ -39,13 +45,13 @@ class R1SolveFn(torch.autograd.Function):
                         rtol=cfg.get("adj_rtol", cfg.get("rtol", 1e-12)),
                         max_cycles=cfg.get("max_cycles", 200)).x
         g = r1s.grad(ctx.A, lam, x)
-        return (lam, g["s_diag"], g["s_sub"], g["s_sup"], g["s_flow"], g["s_nbr"], g["u"],
-                g["v"], None)
+        return (lam, None) + tuple(g[k] for k in ctx.names)
 
 
 def solve(b, values, nx, ny, L, **cfg):
     """x = J^{-1} b, differentiable w.r.t. b and every structured array.
-    cfg: ranks=(r_diag, r_off) (default (1, 1)), restart, rtol, adj_rtol,
-    max_cycles."""
+    cfg: ranks=(r_diag, r_off) (default (1, 1)), band (default 1), arrow
+    (default False), restart, rtol, adj_rtol, max_cycles."""
     c = dict(cfg, nx=nx, ny=ny, L=L)
-    return R1SolveFn.apply(b, *(values[k] for k in FIELDS), c)
+    lay = r1s.layout(*c.get("ranks", (1, 1)), c.get("band", 1), c.get("arrow", False))
+    return R1SolveFn.apply(b, c, *(values[k] for k in r1s._used_fields(lay)))

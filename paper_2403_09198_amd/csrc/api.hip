@@ -67,23 +67,37 @@ static int check_dims(int nx, int ny, int L) {
   return R1S_OK;
 }
 
-static int check_ranks(int r_diag, int r_off) {
-  if (r_diag < 1 || r_off < 0)
-    return fail(R1S_ERR_ARG, "need r_diag >= 1 and r_off >= 0 (got %d, %d)", r_diag, r_off);
-  if (!ranks_supported(r_diag, r_off))
-    return fail(R1S_ERR_UNSUPPORTED, "pair counts r_diag = %d, r_off = %d exceed %d, %d", r_diag,
-                r_off, RANK_DIAG_MAX, RANK_OFF_MAX);
+// NULL layout: one pair per block, tridiagonal band, no coupling.
+static r1s_layout layout_or_default(const r1s_layout* lay) {
+  return lay ? *lay : r1s_layout{1, 1, 1, 0};
+}
+
+static int check_layout(const r1s_layout& lay) {
+  if (lay.r_diag < 1 || lay.r_off < 0)
+    return fail(R1S_ERR_ARG, "need r_diag >= 1 and r_off >= 0 (got %d, %d)", lay.r_diag,
+                lay.r_off);
+  if (!ranks_supported(lay.r_diag, lay.r_off))
+    return fail(R1S_ERR_UNSUPPORTED, "pair counts r_diag = %d, r_off = %d exceed %d, %d",
+                lay.r_diag, lay.r_off, RANK_DIAG_MAX, RANK_OFF_MAX);
+  if (lay.band < 1 || (lay.arrow != 0 && lay.arrow != 1))
+    return fail(R1S_ERR_ARG, "need band >= 1 and arrow 0 or 1 (got %d, %d)", lay.band, lay.arrow);
+  if (lay.band > R1S_MAX_BAND)
+    return fail(R1S_ERR_UNSUPPORTED, "band %d exceeds %d", lay.band, R1S_MAX_BAND);
   return R1S_OK;
 }
 
-static Mesh make_mesh(int nx, int ny, int L, int r_diag, int r_off) {
+static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay) {
   Mesh g;
   g.nx = nx; g.ny = ny; g.L = L; g.m = L + 3; g.mp = pad_m(L + 3);
   g.N = nx * ny;
   g.n = (long long)g.N * g.m;
-  g.rd = r_diag; g.ro = r_off;
-  g.P = r_diag + 4 * r_off;
-  g.F = F_U + 2 * g.P;
+  g.rd = lay.r_diag; g.ro = lay.r_off;
+  g.P = g.rd + 4 * g.ro;
+  g.band = lay.band; g.arrow = lay.arrow;
+  g.fb = F_BAND;
+  g.fa = g.fb + 2 * (g.band - 1);
+  g.fu = g.fa + 6 * g.arrow;
+  g.F = g.fu + 2 * g.P;
   return g;
 }
 
@@ -103,26 +117,33 @@ static void mat_layout(Carver& cv, const Mesh& g, int flags, double** r64, float
   *r32 = (flags & R1S_KEEP_F32) ? cv.take<float>(cnt) : nullptr;
 }
 
-extern "C" int r1s_mat_size(int nx, int ny, int L, int r_diag, int r_off, int flags,
+extern "C" int r1s_mat_size(int nx, int ny, int L, const r1s_layout* layout, int flags,
                             size_t* bytes) {
   if (int e = check_dims(nx, ny, L)) return e;
-  if (int e = check_ranks(r_diag, r_off)) return e;
+  const r1s_layout lay = layout_or_default(layout);
+  if (int e = check_layout(lay)) return e;
   if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
   if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   Carver cv(nullptr);
   double* a;
   float* b;
-  mat_layout(cv, make_mesh(nx, ny, L, r_diag, r_off), flags, &a, &b);
+  mat_layout(cv, make_mesh(nx, ny, L, lay), flags, &a, &b);
   *bytes = cv.off;
   return R1S_OK;
 }
 
-static int check_inputs(const r1s_inputs* in, int L) {
+// Which inputs a layout reads: the seven base arrays (s_sub / s_sup not for
+// L = 1), s_band for band > 1, the coupling arrays with arrow.
+static int check_inputs(const r1s_inputs* in, const Mesh& g) {
   if (!in) return fail(R1S_ERR_ARG, "inputs is NULL");
-  const void* ps[7] = {in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr, in->u, in->v};
-  const char* names[7] = {"s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"};
-  for (int i = 0; i < 7; ++i) {
-    if ((i == 1 || i == 2) && L == 1) continue;
+  const void* ps[10] = {in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr,
+                        in->u,      in->v,     in->s_band, in->s_lev_flow, in->s_flow_lev};
+  const char* names[10] = {"s_diag", "s_sub", "s_sup", "s_flow", "s_nbr",
+                           "u",      "v",     "s_band", "s_lev_flow", "s_flow_lev"};
+  const bool used[10] = {true, g.L > 1, g.L > 1, true, true, true, true,
+                         g.band > 1, g.arrow != 0, g.arrow != 0};
+  for (int i = 0; i < 10; ++i) {
+    if (!used[i]) continue;
     if (!ps[i]) return fail(R1S_ERR_ARG, "input %s is NULL", names[i]);
     if (!aligned(ps[i], 8)) return fail(R1S_ERR_ARG, "input %s is not 8-byte aligned", names[i]);
   }
@@ -130,24 +151,26 @@ static int check_inputs(const r1s_inputs* in, int L) {
 }
 
 static int do_pack(r1s_mat A, const r1s_inputs* in, hipStream_t s) {
-  PackIn p{in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr, in->u, in->v};
+  PackIn p{in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_nbr, in->u, in->v,
+           in->s_band, in->s_lev_flow, in->s_flow_lev};
   HIP_TRY(launch_pack(A->g, p, A->rec64, A->rec32, s));
   return R1S_OK;
 }
 
-extern "C" int r1s_mat_init(int nx, int ny, int L, int r_diag, int r_off, int flags,
+extern "C" int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int flags,
                             const r1s_inputs* in, void* mem, size_t mem_bytes, void* stream,
                             r1s_mat* out) {
   size_t need;
-  if (int e = r1s_mat_size(nx, ny, L, r_diag, r_off, flags, &need)) return e;
+  if (int e = r1s_mat_size(nx, ny, L, layout, flags, &need)) return e;
   if (!out) return fail(R1S_ERR_ARG, "out is NULL");
-  if (int e = check_inputs(in, L)) return e;
+  const Mesh g = make_mesh(nx, ny, L, layout_or_default(layout));
+  if (int e = check_inputs(in, g)) return e;
   if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
   if (mem_bytes < need)
     return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
   r1s_mat A = (r1s_mat)calloc(1, sizeof(r1s_mat_s));
   if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
-  A->g = make_mesh(nx, ny, L, r_diag, r_off);
+  A->g = g;
   A->flags = flags;
   Carver cv(mem);
   mat_layout(cv, A->g, flags, &A->rec64, &A->rec32);
@@ -166,7 +189,7 @@ extern "C" int r1s_mat_init(int nx, int ny, int L, int r_diag, int r_off, int fl
 
 extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
   if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
-  if (int e = check_inputs(in, A->g.L)) return e;
+  if (int e = check_inputs(in, A->g)) return e;
   if (int e = do_pack(A, in, as_stream(stream))) return e;
   HIP_TRY(hipStreamSynchronize(as_stream(stream)));
   return R1S_OK;
@@ -185,13 +208,20 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   out->n_blocks = B;
   out->m = m;
   const long long pairs = N * g.rd + (B - N) * g.ro;
-  out->structured_values = N * (3 * m - 2) + (B - N) * m + 2 * pairs * m;
+  const long long L = g.L;
+  long long diag_block = 3 * m - 2;  // diagonal, tridiagonal band, 3 x 3 corner
+  for (int j = 2; j <= g.band; ++j) diag_block += 2 * std::max(L - j, 0LL);
+  if (g.arrow) diag_block += 6 * L;
+  out->structured_values = N * diag_block + (B - N) * m + 2 * pairs * m;
   out->structured_padded = N * (long long)g.F * g.mp;
   out->bsr_values = B * m * m;
   out->index_bytes = 0;
   out->matvec_bytes = 8 * out->structured_values + 8 * 2 * N * m;
-  // A0 factors (as many values as S_cc), W and V, C^{-1}; r read, z written
-  out->smw_apply_bytes = 8 * N * ((3 * m - 2) + 2 * g.rd * m + (long long)g.rd * g.rd) + 8 * 2 * N * m;
+  // A0 factors (as many values as S_cc; with the wide pattern the band LU
+  // factors, the coupling factors and the 3 x 3 Schur inverse), W and V,
+  // C^{-1}; r read, z written
+  const long long a0 = wide_pattern(g) ? (2 * g.band + 1 + 6 * g.arrow) * L + 9 : 3 * m - 2;
+  out->smw_apply_bytes = 8 * N * (a0 + 2 * g.rd * m + (long long)g.rd * g.rd) + 8 * 2 * N * m;
   return R1S_OK;
 }
 
@@ -237,16 +267,37 @@ struct r1s_prec_s {
   int kind;
   int flags;
   Mesh g;
-  // SMW
+  // SMW, tridiagonal uncoupled diagonal block (one wave per cell)
   double *facF, *facT, *invC;
   float *facF32, *facT32, *invC32;
   int* status;
+  // SMW, wide diagonal-block pattern (one lane per cell, tile-interleaved):
+  // band / coupling factors, Schur inverse, W and V rows per direction, C^{-1}
+  double *bf, *s3i, *wv, *wvT, *cinv;
+  float *bf32, *s3i32, *wv32, *wvT32, *cinv32;
+  long long n_bf, n_s3i, n_wv, n_cinv;  // element counts
   // BSR dense LU
   double* lu;
   int* piv;
 };
 
 static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
+  const bool f32 = flags & R1S_KEEP_F32, tr = flags & R1S_WITH_TRANS;
+  if (wide_pattern(g)) {
+    band_prec_counts(g, &P->n_bf, &P->n_s3i, &P->n_wv, &P->n_cinv);
+    P->bf = cv.take<double>(P->n_bf);
+    P->s3i = cv.take<double>(P->n_s3i);
+    P->wv = cv.take<double>(P->n_wv);
+    P->wvT = tr ? cv.take<double>(P->n_wv) : nullptr;
+    P->cinv = cv.take<double>(P->n_cinv);
+    P->status = cv.take<int>(64);
+    P->bf32 = f32 ? cv.take<float>(P->n_bf) : nullptr;
+    P->s3i32 = f32 ? cv.take<float>(P->n_s3i) : nullptr;
+    P->wv32 = f32 ? cv.take<float>(P->n_wv) : nullptr;
+    P->wvT32 = (f32 && tr) ? cv.take<float>(P->n_wv) : nullptr;
+    P->cinv32 = f32 ? cv.take<float>(P->n_cinv) : nullptr;
+    return;
+  }
   const size_t f = (size_t)g.N * smw_rows(g) * g.mp;
   const size_t ic = (size_t)g.N * g.rd * g.rd;
   P->facF = cv.take<double>(f);
@@ -258,11 +309,14 @@ static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
   P->invC32 = (flags & R1S_KEEP_F32) ? cv.take<float>(ic) : nullptr;
 }
 
+static bool smw_has_trans(const r1s_prec_s* M) { return M->facT || M->wvT; }
+static bool smw_has_f32(const r1s_prec_s* M) { return M->facF32 || M->bf32; }
+
 extern "C" int r1s_prec_size(r1s_mat A, int flags, size_t* bytes) {
   if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
   if (flags & ~(R1S_KEEP_F32 | R1S_WITH_TRANS)) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   Carver cv(nullptr);
-  r1s_prec_s tmp;
+  r1s_prec_s tmp = {};
   prec_layout(cv, A->g, flags, &tmp);
   *bytes = cv.off;
   return R1S_OK;
@@ -294,8 +348,18 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
   do {
     hipError_t e;
     if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
-    if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
-    if (P->facF32) {
+    if (wide_pattern(A->g)) {
+      if ((e = launch_band_setup(A->g, A->rec64, P->bf, P->s3i, P->wv, P->wvT, P->cinv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "band setup: %s", hipGetErrorString(e)); break; }
+      if (P->bf32) {
+        const double* src[5] = {P->bf, P->s3i, P->wv, P->wvT, P->cinv};
+        float* dst[5] = {P->bf32, P->s3i32, P->wv32, P->wvT32, P->cinv32};
+        const long long cnt[5] = {P->n_bf, P->n_s3i, P->n_wv, P->n_wv, P->n_cinv};
+        for (int i = 0; i < 5 && e == hipSuccess; ++i)
+          if (dst[i]) e = launch_cast_f32(src[i], dst[i], cnt[i], s);
+        if (e != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+      }
+    } else if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
+    if (!wide_pattern(A->g) && P->facF32) {
       const long long f = (long long)A->g.N * smw_rows(A->g) * A->g.mp;
       if ((e = launch_cast_f32(P->facF, P->facF32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       if (P->facT32 && (e = launch_cast_f32(P->facT, P->facT32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
@@ -329,6 +393,18 @@ extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, co
     if (trans || precision != R1S_F64)
       return fail(R1S_ERR_UNSUPPORTED, "the dense-LU preconditioner applies M r in float64 only");
     HIP_TRY(launch_bsr_lu_apply(M->g, M->lu, M->piv, r, z, nrhs, s));
+    return R1S_OK;
+  }
+  if (wide_pattern(M->g)) {
+    if (trans && !M->wvT) return fail(R1S_ERR_ARG, "transposed apply needs R1S_WITH_TRANS at setup");
+    const bool f32 = precision == R1S_F32;
+    if (f32 && !M->bf32) return fail(R1S_ERR_ARG, "float32 apply needs R1S_KEEP_F32 at setup");
+    const void* w = f32 ? (trans ? (const void*)M->wvT32 : (const void*)M->wv32)
+                        : (trans ? (const void*)M->wvT : (const void*)M->wv);
+    HIP_TRY(launch_band_apply(M->g, f32 ? (const void*)M->bf32 : (const void*)M->bf,
+                              f32 ? (const void*)M->s3i32 : (const void*)M->s3i, w,
+                              f32 ? (const void*)M->cinv32 : (const void*)M->cinv, f32, trans != 0,
+                              r, z, nrhs, s));
     return R1S_OK;
   }
   if (trans && !M->facT) return fail(R1S_ERR_ARG, "transposed apply needs R1S_WITH_TRANS at setup");
@@ -789,12 +865,15 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
     return fail(R1S_ERR_ARG, "BSR handle does not match the matrix");
   if (M->g.nx != A->g.nx || M->g.ny != A->g.ny || M->g.L != A->g.L)
     return fail(R1S_ERR_ARG, "preconditioner does not match the matrix");
-  if (opts->trans && M->kind == PREC_SMW && !M->facT)
+  if (M->g.rd != A->g.rd || M->g.ro != A->g.ro || M->g.band != A->g.band ||
+      M->g.arrow != A->g.arrow)
+    return fail(R1S_ERR_ARG, "preconditioner was set up for another block layout");
+  if (opts->trans && M->kind == PREC_SMW && !smw_has_trans(M))
     return fail(R1S_ERR_ARG, "transposed solve needs a preconditioner set up with R1S_WITH_TRANS");
   if (opts->trans && M->kind == PREC_BSR_LU)
     return fail(R1S_ERR_UNSUPPORTED, "dense-LU preconditioner: no transposed apply");
   const bool mixed = opts->mode == R1S_MODE_MIXED_IR;
-  if (mixed && (!A->rec32 || M->kind != PREC_SMW || !M->facF32))
+  if (mixed && (!A->rec32 || M->kind != PREC_SMW || !smw_has_f32(M)))
     return fail(R1S_ERR_ARG, "mixed mode needs R1S_KEEP_F32 on the matrix and the preconditioner");
   if (!work || !aligned(work, 256)) return fail(R1S_ERR_ARG, "work is NULL or not 256-byte aligned");
   size_t need;
@@ -868,12 +947,17 @@ extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double*
   if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
   if (int e = check_vec(lambda, "lambda")) return e;
   if (int e = check_vec(x, "x")) return e;
-  const void* ps[7] = {out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v};
-  for (int i = 0; i < 7; ++i) {
-    if ((i == 1 || i == 2) && A->g.L == 1) continue;
+  const Mesh& g = A->g;
+  const void* ps[10] = {out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr,
+                        out->u,      out->v,     out->s_band, out->s_lev_flow, out->s_flow_lev};
+  const bool used[10] = {true, g.L > 1, g.L > 1, true, true, true, true,
+                         g.band > 1, g.arrow != 0, g.arrow != 0};
+  for (int i = 0; i < 10; ++i) {
+    if (!used[i]) continue;
     if (int e = check_vec(ps[i], "gradient output")) return e;
   }
-  GradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v};
+  GradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v,
+            out->s_band, out->s_lev_flow, out->s_flow_lev};
   HIP_TRY(launch_grad(A->g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
   return R1S_OK;
 }

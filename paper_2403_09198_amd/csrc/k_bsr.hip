@@ -22,8 +22,8 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
   const int c = blk_row[b], d = blk_dir[b];
   const int m = g.m, mp = g.mp, L = g.L;
   const double* rc = rec + (long long)c * g.F * mp;
-  const double* u = rc + (long long)(F_U + pair_start(g, d)) * mp;         // pair p at + p mp
-  const double* v = rc + (long long)(F_U + g.P + pair_start(g, d)) * mp;
+  const double* u = rc + (long long)(g.fu + pair_start(g, d)) * mp;         // pair p at + p mp
+  const double* v = rc + (long long)(g.fu + g.P + pair_start(g, d)) * mp;
   const int cnt = pair_count(g, d);
   double* out = data + b * m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
@@ -39,6 +39,16 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
         const int a = i - L, bb = j - L;
         if (bb == (a + 2) % 3) s = rc[F_LO * mp + i];
         if (bb == (a + 1) % 3) s = rc[F_HI * mp + i];
+      }
+      // wide pattern: level diagonals j = 2..band and the level/flow coupling
+      if (i < L && j < L && i != j) {
+        const int dd = i - j, nbd = g.band - 1;
+        if (dd >= 2 && dd <= g.band) s = rc[(g.fb + dd - 2) * mp + i];
+        if (-dd >= 2 && -dd <= g.band) s = rc[(g.fb + nbd - dd - 2) * mp + i];
+      } else if (g.arrow && i < L && j >= L) {
+        s = rc[(g.fa + j - L) * mp + i];
+      } else if (g.arrow && i >= L && j < L) {
+        s = rc[(g.fa + 3 + i - L) * mp + j];
       }
     } else if (i == j) {
       s = rc[(F_NBR + nbr_slot(d)) * mp + i];

@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
     const int q0 = pair_start(g, d), cnt = pair_count(g, d);
     for (int p = 0; p < cnt; ++p) {
       const int q = q0 + p;
-      const double* uq = rc + (long long)(F_U + q) * mp;
-      const double* vq = rc + (long long)(F_U + P + q) * mp;
+      const double* uq = rc + (long long)(g.fu + q) * mp;
+      const double* vq = rc + (long long)(g.fu + P + q) * mp;
       for (int r = 0; r < nrhs; ++r) {
         double a = 0.0, b = 0.0;
         if (nb[d] >= 0) {
@@ -99,6 +99,35 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
 #pragma unroll
     for (int d = 0; d < 5; ++d)
       if (d != D_C) o.s_nbr[((long long)c * 4 + nbr_slot(d)) * m + k] = gnbr[d];
+    // wide pattern: further level diagonals and the level/flow coupling
+    // (zero in the slots outside the block)
+    if (k < L) {
+      const int nbd = g.band - 1;
+      for (int j = 2; j <= g.band; ++j) {
+        double glj = 0.0, guj = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+          const double* xc = x + (long long)r * g.n + (long long)c * m;
+          const double lk = lam[(long long)r * g.n + (long long)c * m + k];
+          if (k >= j) glj -= lk * xc[k - j];
+          if (k + j < L) guj -= lk * xc[k + j];
+        }
+        o.s_band[((long long)c * 2 * nbd + j - 2) * L + k] = glj;
+        o.s_band[((long long)c * 2 * nbd + nbd + j - 2) * L + k] = guj;
+      }
+      if (g.arrow) {
+        for (int i = 0; i < 3; ++i) {
+          double glf = 0.0, gfl = 0.0;
+          for (int r = 0; r < nrhs; ++r) {
+            const double* xc = x + (long long)r * g.n + (long long)c * m;
+            const double* lc = lam + (long long)r * g.n + (long long)c * m;
+            glf -= lc[k] * xc[L + i];
+            gfl -= lc[L + i] * xc[k];
+          }
+          o.s_lev_flow[((long long)c * 3 + i) * L + k] = glf;
+          o.s_flow_lev[((long long)c * 3 + i) * L + k] = gfl;
+        }
+      }
+    }
   }
 
   // rank-one pairs (zero for the pairs of blocks outside the mesh)

@@ -53,15 +53,25 @@ __global__ __launch_bounds__(256) void k_pack(Mesh g, PackIn in, TV* __restrict_
           const int j = f == F_LO ? (i + 2) % 3 : (i + 1) % 3;
           val = in.s_flow[(long long)c * 6 + i * 2 + (j > i ? j - 1 : j)];
         }
-      } else if (f < F_U) {
+      } else if (f < F_BAND) {
         const int slot = f - F_NBR;
         const int d = slot < 2 ? slot : slot + 1;
         if (nb[d]) val = in.s_nbr[((long long)c * 4 + slot) * m + k];
-      } else if (f < F_U + P) {
-        const int q = f - F_U;
+      } else if (f < g.fa) {
+        // band row: lower j = 2..band, then upper; level rows only, entries
+        // outside the block stay zero
+        const int t = f - g.fb, nbd = g.band - 1;
+        const int j = (t < nbd ? t : t - nbd) + 2;
+        const bool ok = k < L && (t < nbd ? k >= j : k + j < L);
+        if (ok) val = in.s_band[((long long)c * 2 * nbd + t) * L + k];
+      } else if (f < g.fu) {
+        const int t = f - g.fa;  // 0..2 level->flow, 3..5 flow->level
+        if (k < L) val = (t < 3 ? in.s_lev_flow : in.s_flow_lev)[((long long)c * 3 + t % 3) * L + k];
+      } else if (f < g.fu + P) {
+        const int q = f - g.fu;
         if (nb[dir_of_slot(g, q)]) val = in.u[((long long)c * P + q) * m + k];
       } else {
-        const int q = f - F_U - P;
+        const int q = f - g.fu - P;
         if (nb[dir_of_slot(g, q)]) val = in.v[((long long)c * P + q) * m + k];
       }
     }
@@ -96,22 +106,77 @@ struct CellRows {
     for (int d = 0; d < 5; ++d) {
       const int bd = TRANS ? opposite(d) : d;
       base[d] = TRANS ? rec + (long long)nbc[d] * RS : rc;
-      coef0[d] = F_U + (TRANS ? 0 : g.P) + pair_start(g, bd);
-      out0[d] = F_U + (TRANS ? g.P : 0) + pair_start(g, bd);
+      coef0[d] = g.fu + (TRANS ? 0 : g.P) + pair_start(g, bd);
+      out0[d] = g.fu + (TRANS ? g.P : 0) + pair_start(g, bd);
       nbr[d] = F_NBR + nbr_slot(bd == D_C ? 0 : bd);
     }
   }
 };
 
-// Kernel-side mesh: with one pair per block (EXACT) the pair counts become
-// compile-time constants and all row offsets fold.
+// Kernel-side mesh: with one pair per block, band 1 and no coupling (EXACT)
+// the counts become compile-time constants and all row offsets fold.
 template <bool EXACT>
 __device__ inline Mesh kmesh(Mesh g) {
   if (EXACT) {
-    g.rd = 1; g.ro = 1; g.P = 5; g.F = F_U + 10;
+    g.rd = 1; g.ro = 1; g.P = 5; g.band = 1; g.arrow = 0;
+    g.fb = F_BAND; g.fa = F_BAND; g.fu = F_BAND; g.F = F_BAND + 10;
   }
   return g;
 }
+
+// ----------------------------------------- wide diagonal-block pattern ----
+// Terms of S_cc beyond the tridiagonal band and the 3x3 corner: the level
+// diagonals j = 2..band and the level/flow coupling.  Forward, lane k adds
+// row k; transposed, column k (the band entries of rows k -+ j).
+//
+// Coupling rows dotted with the cell's levels (a wave sum per flow unknown):
+// forward the flow rows S[L+i][.] (fa + 3 + i), transposed the flow columns
+// S[.][L+i] (fa + i).  Per-lane coupling rows times x_{L+i}: forward
+// S[k][L+i] (fa + i), transposed S[L+i][k] (fa + 3 + i).
+template <bool TRANS>
+__device__ inline int arrow_sum_row(const Mesh& g, int i) { return g.fa + (TRANS ? 0 : 3) + i; }
+template <bool TRANS>
+__device__ inline int arrow_lane_row(const Mesh& g, int i) { return g.fa + (TRANS ? 3 : 0) + i; }
+
+// Band coefficients of lane kk (clamped lane index) and the x indices they
+// multiply; invalid positions get a zero coefficient and a valid index.
+template <typename TV, bool TRANS>
+struct BandLane {
+  TV alo[BAND_MAX - 1], ahi[BAND_MAX - 1];
+  int ilo[BAND_MAX - 1], ihi[BAND_MAX - 1];
+
+  __device__ inline void load(const Mesh& g, const TV* rc, int kk) {
+    const long long mp = g.mp;
+    const int L = g.L, nbd = g.band - 1;
+#pragma unroll
+    for (int j = 2; j <= BAND_MAX; ++j) {
+      const int t = j - 2;
+      const bool on = j <= g.band;
+      const bool vlo = on && kk < L && kk >= j;  // x_{k-j}: S[k][k-j] or S[k-j][k]
+      const bool vhi = on && kk + j < L;         // x_{k+j}: S[k][k+j] or S[k+j][k]
+      ilo[t] = vlo ? kk - j : kk;
+      ihi[t] = vhi ? kk + j : kk;
+      TV a = TV(0), b = TV(0);
+      if (on) {
+        // forward: lower row j at k, upper row j at k; transposed: upper row
+        // j at k - j (entry S[k-j][k]), lower row j at k + j (S[k+j][k])
+        a = TRANS ? rc[(g.fb + nbd + t) * mp + ilo[t]] : rc[(g.fb + t) * mp + kk];
+        b = TRANS ? rc[(g.fb + t) * mp + ihi[t]] : rc[(g.fb + nbd + t) * mp + kk];
+      }
+      alo[t] = vlo ? a : TV(0);
+      ahi[t] = vhi ? b : TV(0);
+    }
+  }
+  __device__ inline TV apply(const Mesh& g, const double* xc) const {
+    TV s = TV(0);
+#pragma unroll
+    for (int t = 0; t < BAND_MAX - 1; ++t) {
+      if (t + 2 > g.band) break;
+      s += alo[t] * (TV)xc[ilo[t]] + ahi[t] * (TV)xc[ihi[t]];
+    }
+    return s;
+  }
+};
 
 // --------------------------------------------------------------- matvec ----
 // TV: value / accumulation type.  NCH = ceil(m / 64) chunks of 64 unknowns,
@@ -122,7 +187,8 @@ __device__ inline Mesh kmesh(Mesh g) {
 // cell's own, valid addresses and are masked out of the sums instead of
 // being skipped by a branch.  Lanes past m read element m-1 and are masked.
 // Pair slots past a block's count are skipped by wave-uniform guards.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM>
+// WIDE: the diagonal block has further band diagonals or level/flow coupling.
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
 __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
@@ -229,6 +295,32 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         s = wave_sum_u(s);
         acc[r][d][p] = ex[d] ? s : TV(0);
       }
+  // coupling sums of the flow unknowns over the cell's levels
+  TV asum[NR][3];
+  if constexpr (WIDE) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) asum[r][i] = TV(0);
+    if (g.arrow) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        TV ar[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int k = ch * WAVE + lane;
+          ar[ch] = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + (k < m ? k : m - 1)] : TV(0);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          TV t = TV(0);
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) t += ar[ch] * xv[r][D_C][ch];
+          asum[r][i] = wave_sum_u(t);
+        }
+      }
+    }
+  }
 
   // Lanes past m computed exactly what lane m-1 computes (all their indices
   // are clamped), so every lane stores to its clamped index: duplicate lanes
@@ -238,6 +330,14 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     if (!PRELOAD) load_sparse(ch);
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
+    BandLane<TV, TRANS> bl;
+    TV al[3] = {TV(0), TV(0), TV(0)};
+    if constexpr (WIDE) {
+      bl.load(g, R.rc, kk);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        al[i] = g.arrow ? R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk] : TV(0);
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       TV t = dg[ch] * xv[r][D_C][ch] + ca[ch] * xa[r][ch] + cb[ch] * xb[r][ch];
@@ -246,6 +346,18 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         if (d != D_C && ex[d]) t += nv[d][ch] * xv[r][d][ch];
 #pragma unroll
         for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) t += uv[d][p][ch] * acc[r][d][p];
+      }
+      if constexpr (WIDE) {
+        const double* xc = xr + (long long)r * g.n + (long long)c * m;
+        t += bl.apply(g, xc);
+        if (g.arrow) {
+          // level lanes: coupling entries times the flow unknowns; flow lane
+          // L + i: the coupling sum
+#pragma unroll
+          for (int i = 0; i < 3; ++i) t += al[i] * (TV)xc[L + i];
+          const int fi = kk - L;
+          t += fi == 0 ? asum[r][0] : fi == 1 ? asum[r][1] : fi == 2 ? asum[r][2] : TV(0);
+        }
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
       y[o] = RESID ? b[o] - (double)t : (double)t;
@@ -257,7 +369,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
 // 64w .. 64w+63 of one cell, issues all of its loads at once (like the
 // single-chunk kernel), and the pair coefficients are summed over the waves
 // through LDS in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM>
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
 __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __restrict__ rec,
                                                         const double* __restrict__ x,
                                                         const double* __restrict__ b,
@@ -265,6 +377,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   constexpr bool EXACT = RDM == 1 && ROM == 1;
   constexpr int RM = RDM > ROM ? RDM : ROM;
   __shared__ TV part[NR][5][RM][NCH];
+  __shared__ TV apart[WIDE ? NR : 1][3][NCH];
   const Mesh g = kmesh<EXACT>(g_);
   const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -341,6 +454,24 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
         const TV s = wave_sum_u(k < m ? pv[d][p] * xv[r][d] : TV(0));
         if (lane == 0) part[r][d][p][wv] = s;
       }
+  // wide pattern: this chunk's share of the coupling sums, band terms
+  BandLane<TV, TRANS> bl;
+  TV al[3] = {TV(0), TV(0), TV(0)};
+  if constexpr (WIDE) {
+    if (g.arrow) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const TV ar = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + kk] : TV(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const TV s = wave_sum_u(ar * xv[r][D_C]);
+          if (lane == 0) apart[r][i][wv] = s;
+        }
+        al[i] = R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk];
+      }
+    }
+    bl.load(g, R.rc, kk);
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -354,6 +485,21 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
 #pragma unroll
         for (int w = 1; w < NCH; ++w) s += part[r][d][p][w];
         t += uv[d][p] * (ex[d] ? s : TV(0));
+      }
+    }
+    if constexpr (WIDE) {
+      const double* xc = xr + (long long)r * g.n + (long long)c * m;
+      t += bl.apply(g, xc);
+      if (g.arrow) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) t += al[i] * (TV)xc[L + i];
+        const int fi = kk - L;
+        if (fi >= 0 && fi < 3) {
+          TV s = apart[r][fi][0];
+#pragma unroll
+          for (int w = 1; w < NCH; ++w) s += apart[r][fi][w];
+          t += s;
+        }
       }
     }
     const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
@@ -393,7 +539,7 @@ bool ranks_supported(int rd, int ro) {
 // Right-hand sides per launch: 8 / 4 / 2 / 1 with one pair per block (4 / 2 / 1
 // in the workgroup form), 2 / 1 with several (their coefficient registers
 // grow with the pair count).
-template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM>
+template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
 static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
                           double* y, int nrhs, hipStream_t s) {
   constexpr bool EXACT = RDM == 1 && ROM == 1;
@@ -404,18 +550,18 @@ static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
       const int rem = nrhs - r0;
       if constexpr (EXACT) {
         if (rem >= 4) {
-          hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID, RDM, ROM>), dim3(g.N),
+          hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
                              dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
           r0 += 4;
           continue;
         }
       }
       if (rem >= 2) {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID, RDM, ROM>), dim3(g.N),
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
                            dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
         r0 += 2;
       } else {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID, RDM, ROM>), dim3(g.N),
+        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
                            dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
         r0 += 1;
       }
@@ -429,49 +575,55 @@ static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
     const int rem = nrhs - r0;
     if constexpr (NCH <= 2 && EXACT) {
       if (rem >= 8) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID, RDM, ROM>), dim3(grid),
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
                            dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 8;
         continue;
       }
       if (rem >= 4) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM>), dim3(grid),
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
                            dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
         r0 += 4;
         continue;
       }
     }
     if (rem >= 2) {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM>), dim3(grid),
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
                          dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM>), dim3(grid),
+      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
                          dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
       r0 += 1;
     }
   }
 }
 
-template <typename TV, bool TRANS, bool RESID, int RDM, int ROM>
+template <typename TV, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
 static hipError_t launch_mv_r(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   switch ((g.m + WAVE - 1) / WAVE) {
-    case 1: launch_mv_nch<TV, 1, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
-    case 2: launch_mv_nch<TV, 2, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
-    case 3: launch_mv_nch<TV, 3, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
-    case 4: launch_mv_nch<TV, 4, TRANS, RESID, RDM, ROM>(g, rec, x, b, y, nrhs, s); break;
+    case 1: launch_mv_nch<TV, 1, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
+    case 2: launch_mv_nch<TV, 2, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
+    case 3: launch_mv_nch<TV, 3, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
+    case 4: launch_mv_nch<TV, 4, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// Kernel choice: one pair per block with the tridiagonal uncoupled diagonal
+// block (all counts compile-time), any supported pair counts, or any pair
+// counts with the wide diagonal-block pattern.
 template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
-  if (g.rd == 1 && g.ro == 1) return launch_mv_r<TV, TRANS, RESID, 1, 1>(g, rec, x, b, y, nrhs, s);
-  if (!ranks_supported(g.rd, g.ro)) return hipErrorInvalidValue;
-  return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX>(g, rec, x, b, y, nrhs, s);
+  if (!ranks_supported(g.rd, g.ro) || g.band > BAND_MAX) return hipErrorInvalidValue;
+  if (wide_pattern(g))
+    return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX, true>(g, rec, x, b, y, nrhs, s);
+  if (g.rd == 1 && g.ro == 1)
+    return launch_mv_r<TV, TRANS, RESID, 1, 1, false>(g, rec, x, b, y, nrhs, s);
+  return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX, false>(g, rec, x, b, y, nrhs, s);
 }
 
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,

@@ -65,8 +65,8 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   const double* dg = rc + (long long)F_DIAG * mp;
   const double* lo = rc + (long long)F_LO * mp;
   const double* hi = rc + (long long)F_HI * mp;
-  const double* uC = rc + (long long)(F_U + pair_start(g, D_C)) * mp;         // pair i at + i mp
-  const double* vC = rc + (long long)(F_U + g.P + pair_start(g, D_C)) * mp;
+  const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;         // pair i at + i mp
+  const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
 
   double AD[NCH], LO[NCH], HI[NCH], HM1[NCH], LP1[NCH];
 #pragma unroll
@@ -291,6 +291,7 @@ static hipError_t launch_setup_r(const Mesh& g, const double* rec, double* facF,
 
 hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
                             double* invC, int* status, hipStream_t s) {
+  if (wide_pattern(g)) return hipErrorInvalidValue;  // the band kernels serve those
   if (g.rd == 1) return launch_setup_r<1>(g, rec, facF, facT, invC, status, s);
   if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
   return launch_setup_r<RANK_DIAG_MAX>(g, rec, facF, facT, invC, status, s);
@@ -598,6 +599,7 @@ static hipError_t launch_apply_rank(const Mesh& g, const TV* fac, const TV* invC
 
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s) {
+  if (wide_pattern(g)) return hipErrorInvalidValue;
   if (f32)
     return trans ? launch_apply_rank<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
                  : launch_apply_rank<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);

@@ -1,18 +1,23 @@
 // Device-side helpers shared by the r1s kernels (gfx950, wave64).
 //
 // Internal layout of the packed Jacobian ("record" layout): one contiguous
-// record per mesh cell, [N][F][mp] values, F = 7 + 2P field rows of mp = m
-// rounded up to a multiple of 8 (64-byte rows), P = rank-one pairs per cell.
-// Lane k of the wave that owns cell c reads element k of every row, so every
-// load is one contiguous run.
+// record per mesh cell, [N][F][mp] values, F field rows of mp = m rounded up
+// to a multiple of 8 (64-byte rows).  Lane k of the wave that owns cell c
+// reads element k of every row, so every load is one contiguous run.
 //
 //   row 0          diag  S_cc[k][k]
 //   row 1          lo    level k: S_cc[k][k-1]; flow row i: S_cc[L+i][L+(i+2)%3]
 //   row 2          hi    level k: S_cc[k][k+1]; flow row i: S_cc[L+i][L+(i+1)%3]
 //   rows 3..6      nbr   diagonal of S_{c,d}, d = S, W, E, N
-//   rows 7..6+P    u     the pairs of blocks S, W, C, E, N in that order
+//   fb + j - 2     band  S_cc[k][k-j], j = 2..band (level rows only)
+//   fb + band-1 + j-2    S_cc[k][k+j]
+//   fa + i         S_cc[k][L+i] (level rows), i < 3, with level/flow coupling
+//   fa + 3 + i     S_cc[L+i][k] at index k (the flow row i over the levels)
+//   fu .. fu+P-1   u     the pairs of blocks S, W, C, E, N in that order
 //                        (ro pairs per neighbour block, rd for the diagonal)
-//   rows 7+P..6+2P v     same order
+//   fu+P .. F-1    v     same order
+// fb = 7, fa = fb + 2 (band - 1), fu = fa + 6 arrow, F = fu + 2 P
+// (17 rows with one pair per block, band 1 and no coupling).
 //
 // Padding elements and the rows of blocks that do not exist (mesh boundary)
 // are zero.
@@ -28,12 +33,13 @@ constexpr int WAVE = 64;
 #endif
 constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
-constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_U = 7;  // v rows at F_U + P
+constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_BAND = 7;
 constexpr int D_S = 0, D_W = 1, D_C = 2, D_E = 3, D_N = 4;
 constexpr int MAX_CHUNKS = 4;  // m <= 256
 // Largest pair counts of the general-rank kernels (a diagonal block / a
 // neighbour block); one pair per block has kernels of its own.
 constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 2;
+constexpr int BAND_MAX = 8;  // level-band half-width of S_cc
 
 // SMW factor records, [N][3 + 2 rd][mp] per direction of application, plus
 // the rd x rd inverse capacitance per cell ([N][rd][rd], row-major).
@@ -55,8 +61,13 @@ struct Mesh {
   long long n;     // N*m, stride between right-hand sides
   int rd, ro;      // rank-one pairs of a diagonal / a neighbour block
   int P;           // pairs per cell, rd + 4 ro
-  int F;           // record rows per cell, 7 + 2 P
+  int band, arrow; // level-band half-width of S_cc; level/flow coupling
+  int fb, fa, fu;  // first band row (j >= 2), first coupling row, first u row
+  int F;           // record rows per cell, fu + 2 P
 };
+
+// Band or coupling beyond the tridiagonal / uncoupled diagonal block.
+__host__ __device__ inline bool wide_pattern(const Mesh& g) { return g.band > 1 || g.arrow; }
 
 // First record slot and number of the pairs of block direction d.
 __host__ __device__ inline int pair_count(const Mesh& g, int d) { return d == 2 ? g.rd : g.ro; }

@@ -8,10 +8,12 @@ namespace r1s {
 
 struct PackIn {
   const double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
+  const double *s_band, *s_lev_flow, *s_flow_lev;  // wide diagonal-block pattern only
 };
 
 struct GradOut {
   double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
+  double *s_band, *s_lev_flow, *s_flow_lev;
 };
 
 // pair counts the kernels are built for
@@ -35,6 +37,16 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
+
+// SMW block-Jacobi for the wide diagonal-block pattern (band > 1 or level/flow
+// coupling): tile-interleaved factors, one lane per cell.  wvT may be null.
+void band_prec_counts(const Mesh& g, long long* bf, long long* s3i, long long* wv,
+                      long long* cinv);
+hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, double* s3i,
+                             double* wv, double* wvT, double* cinv, int* status, hipStream_t s);
+hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, const void* wv,
+                             const void* cinv, bool f32, bool trans, const double* r, double* z,
+                             int nrhs, hipStream_t s);
 
 // dense-block BSR baseline
 hipError_t launch_bsr_assemble(const Mesh& g, const double* rec, const int* blk_row,

@@ -18,6 +18,8 @@ from . import _lib as L
 from ._lib import R1SError, check, lib
 
 FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
+# arrays of the wide diagonal-block pattern (band > 1 or level/flow coupling)
+PATTERN_FIELDS = ("s_band", "s_lev_flow", "s_flow_lev")
 
 
 def _stream(stream=None):
@@ -45,16 +47,30 @@ def _buffer(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def _shapes(nx, ny, Lv, n_pairs):
+def layout(r_diag=1, r_off=1, band=1, arrow=False) -> "L.Layout":
+    return L.Layout(r_diag=int(r_diag), r_off=int(r_off), band=int(band), arrow=int(bool(arrow)))
+
+
+def _used_fields(lay):
+    """The arrays a layout reads, in r1s_inputs order."""
+    extra = (("s_band",) if lay.band > 1 else ()) + (
+        ("s_lev_flow", "s_flow_lev") if lay.arrow else ())
+    return FIELDS + extra
+
+
+def _shapes(nx, ny, Lv, lay):
     N, m = nx * ny, Lv + 3
+    P = lay.r_diag + 4 * lay.r_off
     return {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
-            "s_nbr": (N, 4, m), "u": (N, n_pairs, m), "v": (N, n_pairs, m)}
+            "s_nbr": (N, 4, m), "u": (N, P, m), "v": (N, P, m),
+            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, 3, Lv),
+            "s_flow_lev": (N, 3, Lv)}
 
 
-def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv, n_pairs):
-    shapes = _shapes(nx, ny, Lv, n_pairs)
+def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv, lay):
+    shapes = _shapes(nx, ny, Lv, lay)
     ins = L.Inputs()
-    for k in FIELDS:
+    for k in _used_fields(lay):
         t = values[k]
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
             raise TypeError(f"{k} must be a float64 CUDA tensor")
@@ -69,22 +85,24 @@ def r1s_last_error() -> str:
     return lib().r1s_last_error().decode()
 
 
-def r1s_mat_size(nx, ny, Lv, r_diag=1, r_off=1, flags=0) -> int:
+def r1s_mat_size(nx, ny, Lv, lay=None, flags=0) -> int:
     b = C.c_size_t()
-    check(lib().r1s_mat_size(nx, ny, Lv, r_diag, r_off, flags, C.byref(b)))
+    check(lib().r1s_mat_size(nx, ny, Lv, C.byref(lay) if lay is not None else None, flags,
+                             C.byref(b)))
     return b.value
 
 
-def r1s_mat_init(nx, ny, Lv, r_diag, r_off, flags, values, mem, stream=None):
+def r1s_mat_init(nx, ny, Lv, lay, flags, values, mem, stream=None):
     h = C.c_void_p()
-    ins = _inputs(values, nx, ny, Lv, r_diag + 4 * r_off)
-    check(lib().r1s_mat_init(nx, ny, Lv, r_diag, r_off, flags, C.byref(ins), _ptr(mem),
+    lay = lay if lay is not None else layout()
+    ins = _inputs(values, nx, ny, Lv, lay)
+    check(lib().r1s_mat_init(nx, ny, Lv, C.byref(lay), flags, C.byref(ins), _ptr(mem),
                              mem.numel(), _stream(stream), C.byref(h)))
     return h
 
 
-def r1s_mat_update(h, values, nx, ny, Lv, n_pairs, stream=None):
-    ins = _inputs(values, nx, ny, Lv, n_pairs)
+def r1s_mat_update(h, values, nx, ny, Lv, lay, stream=None):
+    ins = _inputs(values, nx, ny, Lv, lay)
     check(lib().r1s_mat_update(h, C.byref(ins), _stream(stream)))
 
 
@@ -161,7 +179,7 @@ def r1s_gmres(h, bh, p, opts, nrhs, b, x, work, stream=None):
 
 def r1s_grad(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
     g = L.Grads()
-    for k in FIELDS:
+    for k in out:
         setattr(g, k, _ptr(out[k]).value)
     check(lib().r1s_grad(h, nrhs, _ptr(lam), _ptr(x), C.byref(g), _stream(stream)))
 
@@ -171,23 +189,27 @@ class R1Matrix:
     """Structured block r1-sparse Jacobian on one GPU (packed, caller memory).
 
     ranks = (r_diag, r_off): rank-one pairs of every diagonal / neighbour
-    block; u and v have shape [N, r_diag + 4 r_off, m]."""
+    block; u and v have shape [N, r_diag + 4 r_off, m].  band (level-band
+    half-width of the diagonal block) and arrow (level/flow coupling) select
+    the wide diagonal-block pattern and its arrays s_band, s_lev_flow,
+    s_flow_lev."""
 
     def __init__(self, nx, ny, L_levels, values: Dict[str, torch.Tensor], keep_f32=False,
-                 stream=None, ranks=(1, 1)):
+                 stream=None, ranks=(1, 1), band=1, arrow=False):
         self.nx, self.ny, self.L = nx, ny, L_levels
         self.m = L_levels + 3
         self.N = nx * ny
         self.n = self.N * self.m
         self.r_diag, self.r_off = (int(r) for r in ranks)
         self.n_pairs = self.r_diag + 4 * self.r_off
+        self.band, self.arrow = int(band), bool(arrow)
+        self.layout = layout(self.r_diag, self.r_off, self.band, self.arrow)
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device
         self.device = dev
-        self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.r_diag, self.r_off, self.flags),
-                           dev)
-        self.h = r1s_mat_init(nx, ny, L_levels, self.r_diag, self.r_off, self.flags, values,
-                              self.mem, stream)
+        self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.layout, self.flags), dev)
+        self.h = r1s_mat_init(nx, ny, L_levels, self.layout, self.flags, values, self.mem,
+                              stream)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -196,7 +218,7 @@ class R1Matrix:
             self.h = None
 
     def update(self, values, stream=None):
-        r1s_mat_update(self.h, values, self.nx, self.ny, self.L, self.n_pairs, stream)
+        r1s_mat_update(self.h, values, self.nx, self.ny, self.L, self.layout, stream)
 
     def storage(self):
         return r1s_mat_storage(self.h)
@@ -321,7 +343,8 @@ def grad(A: R1Matrix, lam, x, stream=None) -> Dict[str, torch.Tensor]:
     """Gradients w.r.t. the structured arrays given lambda = J^{-T} dLoss/dx."""
     nrhs = _need_vec(lam, "lambda", A.n)
     _need_vec(x, "x", A.n)
-    shapes = _shapes(A.nx, A.ny, A.L, A.n_pairs)
-    out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device) for k in FIELDS}
+    shapes = _shapes(A.nx, A.ny, A.L, A.layout)
+    out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device)
+           for k in _used_fields(A.layout)}
     r1s_grad(A.h, nrhs, lam, x, out, stream)
     return out

@@ -17,7 +17,8 @@ def log(msg):
 
 
 def to_dev(p):
-    return {k: torch.from_numpy(np.ascontiguousarray(p[k])).to(DEV) for k in gen.FIELDS}
+    keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
+    return {k: torch.from_numpy(np.ascontiguousarray(p[k])).to(DEV) for k in keys}
 
 
 def vec(a):

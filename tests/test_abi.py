@@ -28,6 +28,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def _lay(r_diag, r_off, band=1, arrow=0):
+    return C.byref(L.Layout(r_diag=r_diag, r_off=r_off, band=band, arrow=arrow))
+
+
 def _rc(code_call):
     rc = code_call
     msg = L.lib().r1s_last_error().decode()
@@ -37,13 +41,13 @@ def _rc(code_call):
 def test_size_validation():
     lib = L.lib()
     b = C.c_size_t()
-    assert lib.r1s_mat_size(0, 4, 4, 1, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(0, 4, 4, _lay(1, 1), 0, C.byref(b)) == L.R1S_ERR_ARG
     assert "must be >= 1" in lib.r1s_last_error().decode()
-    assert lib.r1s_mat_size(4, 4, 0, 1, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 254, 1, 1, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
-    assert lib.r1s_mat_size(4, 4, 4, 1, 1, 0, None) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 4, 1, 1, 0x10, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 253, 1, 1, 1, C.byref(b)) == L.R1S_OK
+    assert lib.r1s_mat_size(4, 4, 0, _lay(1, 1), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 254, _lay(1, 1), 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1), 0, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1), 0x10, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 253, _lay(1, 1), 1, C.byref(b)) == L.R1S_OK
     # packed rows are padded to 8 values: 17 rows of 256 doubles + floats
     assert b.value >= 16 * 17 * 256 * 12
 
@@ -51,22 +55,54 @@ def test_size_validation():
 def test_rank_validation():
     lib = L.lib()
     b = C.c_size_t()
-    assert lib.r1s_mat_size(4, 4, 4, 0, 1, 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(0, 1), 0, C.byref(b)) == L.R1S_ERR_ARG
     assert "r_diag" in lib.r1s_last_error().decode()
-    assert lib.r1s_mat_size(4, 4, 4, 1, -1, 0, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 4, 10, 2, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
-    assert lib.r1s_mat_size(4, 4, 4, 9, 3, 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, -1), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(10, 2), 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
+    assert lib.r1s_mat_size(4, 4, 4, _lay(9, 3), 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
     for rd, ro in ((9, 2), (1, 0), (2, 0), (3, 1)):
-        assert lib.r1s_mat_size(4, 4, 4, rd, ro, 0, C.byref(b)) == L.R1S_OK
+        assert lib.r1s_mat_size(4, 4, 4, _lay(rd, ro), 0, C.byref(b)) == L.R1S_OK
         # one record of 7 + 2 (rd + 4 ro) rows of 8 doubles per cell
         assert b.value >= 16 * (7 + 2 * (rd + 4 * ro)) * 8 * 8
+
+
+def test_layout_validation_and_sizes():
+    lib = L.lib()
+    b, a = C.c_size_t(), C.c_size_t()
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 0), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 1, 2), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, L.R1S_MAX_BAND + 1), 0, C.byref(b)) == \
+        L.R1S_ERR_UNSUPPORTED
+    # NULL layout = one pair per block, band 1, no coupling
+    assert lib.r1s_mat_size(8, 4, 61, None, 0, C.byref(a)) == L.R1S_OK
+    assert lib.r1s_mat_size(8, 4, 61, _lay(1, 1), 0, C.byref(b)) == L.R1S_OK
+    assert a.value == b.value
+    # band 4 with coupling: 2 (4 - 1) + 6 more rows of 64 doubles per cell
+    assert lib.r1s_mat_size(8, 4, 61, _lay(1, 1, 4, 1), 0, C.byref(b)) == L.R1S_OK
+    assert b.value - a.value == 32 * 12 * 64 * 8
+
+
+def test_init_requires_pattern_arrays():
+    lib = L.lib()
+    ins = L.Inputs()
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 20)
+    for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"):
+        setattr(ins, k, 1 << 21)
+    assert lib.r1s_mat_init(4, 4, 4, _lay(1, 1, 3), 0, C.byref(ins), fake, 1 << 30, None,
+                            C.byref(h)) == L.R1S_ERR_ARG
+    assert "s_band" in lib.r1s_last_error().decode()
+    ins.s_band = 1 << 21
+    assert lib.r1s_mat_init(4, 4, 4, _lay(1, 1, 3, 1), 0, C.byref(ins), fake, 1 << 30, None,
+                            C.byref(h)) == L.R1S_ERR_ARG
+    assert "s_lev_flow" in lib.r1s_last_error().decode()
 
 
 def test_size_grows_with_pairs():
     lib = L.lib()
     a, b = C.c_size_t(), C.c_size_t()
-    lib.r1s_mat_size(64, 32, 61, 1, 1, 0, C.byref(a))
-    lib.r1s_mat_size(64, 32, 61, 9, 2, 0, C.byref(b))
+    lib.r1s_mat_size(64, 32, 61, _lay(1, 1), 0, C.byref(a))
+    lib.r1s_mat_size(64, 32, 61, _lay(9, 2), 0, C.byref(b))
     mp = 64
     assert b.value - a.value == 64 * 32 * 2 * (17 - 5) * mp * 8
 
@@ -74,8 +110,8 @@ def test_size_grows_with_pairs():
 def test_size_is_linear_in_cells():
     lib = L.lib()
     a, b = C.c_size_t(), C.c_size_t()
-    lib.r1s_mat_size(64, 32, 61, 1, 1, 0, C.byref(a))
-    lib.r1s_mat_size(128, 32, 61, 1, 1, 0, C.byref(b))
+    lib.r1s_mat_size(64, 32, 61, _lay(1, 1), 0, C.byref(a))
+    lib.r1s_mat_size(128, 32, 61, _lay(1, 1), 0, C.byref(b))
     assert abs(b.value - 2 * a.value) <= 512
 
 
@@ -84,20 +120,20 @@ def test_init_rejects_bad_arguments_before_device_work():
     ins = L.Inputs()
     h = C.c_void_p()
     fake = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, None, fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, None, fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "is NULL" in lib.r1s_last_error().decode()
     for k in ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v"):
         setattr(ins, k, 1 << 21)
     ins.u = (1 << 21) + 4  # misaligned
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, C.byref(ins), fake, 1 << 30, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "aligned" in lib.r1s_last_error().decode()
     ins.u = 1 << 21
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 16, None, C.byref(h)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, C.byref(ins), fake, 16, None, C.byref(h)) == L.R1S_ERR_ARG
     assert "mem_bytes" in lib.r1s_last_error().decode()
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), C.c_void_p((1 << 20) + 8), 1 << 30, None,
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, C.byref(ins), C.c_void_p((1 << 20) + 8), 1 << 30, None,
                             C.byref(h)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_init(4, 4, 4, 1, 1, 0, C.byref(ins), fake, 1 << 30, None, None) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_init(4, 4, 4, None, 0, C.byref(ins), fake, 1 << 30, None, None) == L.R1S_ERR_ARG
 
 
 def test_null_handles_rejected():
