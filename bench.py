@@ -201,17 +201,20 @@ def profile_pass(torch, A, M, x, y, z):
                                                                           src.numel() * 8))
 
 
-def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0):
+def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False):
     """The float64 pair with several rank-one pairs per block (the paper's
-    9 / 2 structure); algorithmic bytes from the library's storage counts."""
+    9 / 2 structure) and optionally the wide diagonal-block pattern;
+    algorithmic bytes from the library's storage counts."""
     from paper_2403_09198_amd import gen, r1s
 
     dev = "cuda:0"
-    log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks}")
-    p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1])
-    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
+    log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks} band {band} arrow {arrow}")
+    p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1], band=band,
+                         arrow=arrow)
+    keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in keys}
     del p
-    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks)
+    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks, band=band, arrow=arrow)
     del vals
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -222,7 +225,8 @@ def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0):
     x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
     y, z = torch.empty_like(x), torch.empty_like(x)
     N = nx * ny
-    row = {"r_diag": ranks[0], "r_off": ranks[1], "stored_values": st["structured_values"],
+    row = {"r_diag": ranks[0], "r_off": ranks[1], "band": band, "arrow": bool(arrow),
+           "stored_values": st["structured_values"],
            "smw_setup_ms": round(t_setup * 1e3, 2)}
     for tag, f1, f2, vb in (
             ("f64", lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z), 8),
@@ -443,6 +447,10 @@ def main():
     ap.add_argument("--ranks", default="1,1",
                     help="rank-one pairs per diagonal,neighbour block of the timed step "
                          "(the workload's own layout is 1,1)")
+    ap.add_argument("--band", type=int, default=1,
+                    help="level-band half-width of the diagonal block for the timed step")
+    ap.add_argument("--arrow", action="store_true",
+                    help="level/flow coupling in the diagonal block for the timed step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 pair (for profiling runs)")
@@ -480,9 +488,11 @@ def main():
     log(f"workload {w.name}: mesh {nx}x{ny}, L={L}, m={m}, blocks={B}")
     ranks = tuple(int(v) for v in args.ranks.split(","))
     p = gen.make_problem(nx, ny, L, seed=w.seed, inv_dt=w.inv_dt, r_diag=ranks[0],
-                         r_off=ranks[1])
-    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS}
-    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks)
+                         r_off=ranks[1], band=args.band, arrow=args.arrow)
+    keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in keys}
+    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks, band=args.band,
+                     arrow=args.arrow)
     M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
     del vals
     x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
@@ -490,7 +500,7 @@ def main():
     z = torch.empty_like(x)
 
     mv_b, ap_b = pair_bytes(N, B, m)
-    if ranks != (1, 1):
+    if ranks != (1, 1) or args.band != 1 or args.arrow:
         st = A.storage()
         mv_b, ap_b = st["matvec_bytes"], st["smw_apply_bytes"]
     steps, warm = args.steps, args.warmup
@@ -527,6 +537,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": nx, "ny": ny, "L": L, "m": m, "nrhs": 1,
                    "pairs_per_block": {"diagonal": ranks[0], "neighbour": ranks[1]},
+                   "diag_block_band": args.band, "level_flow_coupling": bool(args.arrow),
                    "step": "y = J x then z = M y (SMW block-Jacobi), float64, replayed as a HIP graph",
                    "bytes_per_step": mv_b + ap_b},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
@@ -597,6 +608,10 @@ def main():
         # the paper's rank structure (9 pairs per diagonal block, 2 per
         # neighbour block) on the same mesh
         out["paper_ranks_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm)
+        # and a wider diagonal block: level band of half-width 4 with
+        # level/flow coupling (banded-LU block-Jacobi, one lane per cell)
+        out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
+                                              band=4, arrow=True)
         # full GMRES(50) solve to 1e-10 (float64) and the mixed-precision solve
         b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
         for mode in ("f64", "mixed"):

@@ -16,11 +16,15 @@
 // A band solve is a serial recurrence of order `band`, so here one lane owns
 // one cell and walks its levels (64 cells per wavefront) instead of one wave
 // per cell with lane-parallel scans: the scan of an order-h recurrence costs
-// O(h^3 log 64) per lane, the serial walk O(h) per level.  All factors are
-// stored tile-interleaved, [tile of 64 cells][row][k][lane], so the 64 lanes
-// of a wave read one factor entry of 64 consecutive cells as one contiguous
-// 512-byte run.  Right-hand sides and results keep the [nrhs][N][m] vector
-// layout (each lane streams its own cell's contiguous block).
+// O(h^3 log 64) per lane, the serial walk O(h) per level.  The band factors
+// are stored tile-interleaved, [tile of 64 cells][row][k][lane], so the 64
+// lanes of a wave read one factor entry of 64 consecutive cells as one
+// contiguous 512-byte run, and the walk loads the factors of the next block
+// of levels while it computes the current one (the recurrence itself only
+// touches registers).  The Woodbury correction has no recurrence: a second
+// kernel does it with one wavefront per cell on per-cell rows ([N][2 rd][mp]
+// for W, V and [N][rd][rd] for C^{-1}), like the tridiagonal path.
+// Right-hand sides and results keep the [nrhs][N][m] vector layout.
 #include <math.h>
 
 #include "r1s_device.hpp"
@@ -36,57 +40,79 @@ constexpr int TILE = 64;
 //   up(j) rows band+1..2 band  U_B[k][k+j]                 (k + j < L)
 //   ec(i) rows 2 band+1+i      (L_B^{-1} E_c)[k][i]        (coupling only)
 //   er(i) rows 2 band+4+i      (E_r U_B^{-1})[i][k]        (coupling only)
-template <typename T>
-struct BandView {
-  const T* base;   // this lane's tile, lane offset applied
-  int L, band, arrow;
-  __device__ inline T at(int row, int k) const { return base[((long long)row * L + k) * TILE]; }
-  __device__ inline T lo(int j, int k) const { return at(j - 1, k); }
-  __device__ inline T ui(int k) const { return at(band, k); }
-  __device__ inline T up(int j, int k) const { return at(band + j, k); }
-  __device__ inline T ec(int i, int k) const { return at(2 * band + 1 + i, k); }
-  __device__ inline T er(int i, int k) const { return at(2 * band + 4 + i, k); }
-};
-
 __host__ __device__ inline int band_rows(const Mesh& g) { return 2 * g.band + 1 + 6 * g.arrow; }
 __host__ __device__ inline long long tiles(const Mesh& g) { return (g.N + TILE - 1) / TILE; }
 
 // Solve A0 x = r (TRANS: A0^T x = r) for one cell.  r(k) gives the right-hand
-// side; x is written to dst[k * ds] (k < m) and also serves as the scratch of
-// the forward sweep.  s3i: the 3 x 3 inverse of the Schur complement (row
-// major).  Returns nothing; accumulation in TA.
-template <bool TRANS, typename T, typename TA, typename RHS, typename DST>
-__device__ inline void band_solve(const BandView<T>& f, const T (&s3i)[9], RHS r, DST* dst,
-                                  int ds) {
-  const int L = f.L, band = f.band;
+// side; x is written to dst[k * DS] (k < m), which also holds the forward
+// sweep's intermediate.  s3i: the 3 x 3 inverse of the Schur complement (row
+// major).  The last `band` values of each sweep stay in registers (a shift
+// register of BAND_MAX slots), so a step never waits on its own stores, and
+// the factor loads of later steps are independent of the recurrence.
+template <bool TRANS, int DS, typename T, typename TA, typename RHS, typename DST>
+__device__ __forceinline__ void band_solve(const T* __restrict__ fb, int L, int band, int arrow,
+                                           const T (&s3i)[9], RHS r, DST* __restrict__ dst) {
+  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)row * L + k) * TILE]; };
   TA acc[3] = {TA(0), TA(0), TA(0)};
-  // forward sweep: L_B y = r (TRANS: U_B^T y = r), coupling sums on the way
+  TA h[BAND_MAX];
+#pragma unroll
+  for (int j = 0; j < BAND_MAX; ++j) h[j] = TA(0);
+  // forward sweep: L_B y = r (TRANS: U_B^T y = r), coupling sums on the way;
+  // h[j-1] = y_{k-j} (zero before the first level)
+#pragma unroll 2
   for (int k = 0; k < L; ++k) {
     TA y = (TA)r(k);
-    for (int j = 1; j <= band && j <= k; ++j)
-      y -= (TA)(TRANS ? f.up(j, k - j) : f.lo(j, k)) * (TA)dst[(k - j) * ds];
-    if (TRANS) y *= (TA)f.ui(k);
-    dst[k * ds] = (DST)y;
-    if (f.arrow)
-      for (int i = 0; i < 3; ++i) acc[i] += (TA)(TRANS ? f.ec(i, k) : f.er(i, k)) * y;
+#pragma unroll
+    for (int j = 1; j <= BAND_MAX; ++j) {
+      if (j > band) break;
+      // lo(j, k) is stored as zero for k < j; up(j, k - j) needs k >= j
+      const TA a = TRANS ? at(band + j, k >= j ? k - j : 0) : at(j - 1, k);
+      y -= a * h[j - 1];
+    }
+    if (TRANS) y *= at(band, k);
+#pragma unroll
+    for (int j = BAND_MAX - 1; j > 0; --j) h[j] = h[j - 1];
+    h[0] = y;
+    dst[k * DS] = (DST)y;
+    if (arrow) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] += at(2 * band + (TRANS ? 1 : 4) + i, k) * y;
+    }
   }
   // flow unknowns through the Schur complement (TRANS: its transpose)
   TA yf[3], xf[3];
+#pragma unroll
   for (int i = 0; i < 3; ++i) yf[i] = (TA)r(L + i) - acc[i];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
     xf[i] = (TA)s3i[TRANS ? i : 3 * i] * yf[0] + (TA)s3i[TRANS ? 3 + i : 3 * i + 1] * yf[1] +
             (TA)s3i[TRANS ? 6 + i : 3 * i + 2] * yf[2];
-  // backward sweep: U_B x = y - E_c' x_f (TRANS: L_B^T x = y - E_r'^T x_f)
+  // backward sweep: U_B x = y - E_c' x_f (TRANS: L_B^T x = y - E_r'^T x_f);
+  // h[j-1] = x_{k+j}
+#pragma unroll
+  for (int j = 0; j < BAND_MAX; ++j) h[j] = TA(0);
+#pragma unroll 2
   for (int k = L - 1; k >= 0; --k) {
-    TA x = (TA)dst[k * ds];
-    if (f.arrow)
-      for (int i = 0; i < 3; ++i) x -= (TA)(TRANS ? f.er(i, k) : f.ec(i, k)) * xf[i];
-    for (int j = 1; j <= band && k + j < L; ++j)
-      x -= (TA)(TRANS ? f.lo(j, k + j) : f.up(j, k)) * (TA)dst[(k + j) * ds];
-    if (!TRANS) x *= (TA)f.ui(k);
-    dst[k * ds] = (DST)x;
+    TA x = (TA)dst[k * DS];
+    if (arrow) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) x -= at(2 * band + (TRANS ? 4 : 1) + i, k) * xf[i];
+    }
+#pragma unroll
+    for (int j = 1; j <= BAND_MAX; ++j) {
+      if (j > band) break;
+      // up(j, k) is stored as zero for k + j >= L; lo(j, k + j) needs k + j < L
+      const TA a = TRANS ? at(j - 1, k + j < L ? k + j : k) : at(band + j, k);
+      x -= a * h[j - 1];
+    }
+    if (!TRANS) x *= at(band, k);
+#pragma unroll
+    for (int j = BAND_MAX - 1; j > 0; --j) h[j] = h[j - 1];
+    h[0] = x;
+    dst[k * DS] = (DST)x;
   }
-  for (int i = 0; i < 3; ++i) dst[(L + i) * ds] = (DST)xf[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dst[(L + i) * DS] = (DST)xf[i];
 }
 
 // ---------------------------------------------------------------- setup ----
@@ -184,31 +210,32 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
   for (int t = 0; t < 9; ++t) s3i_out[((long long)tile * 9 + t) * TILE + lane] = s3i[t];
   for (int k = 0; k < L; ++k) F(band, k) = 1.0 / F(band, k);
 
-  BandView<double> bv{fb, L, band, g.arrow};
   const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
   const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
-  double* wt = wv + (long long)tile * 2 * rd * m * TILE + lane;
-  // SMW-1: W_i = A0^{-1} u_i; V_i = v_i
+  double* wc = wv + (long long)c * 2 * rd * mp;  // this cell's W rows, then V rows
+  // SMW-1: W_i = A0^{-1} u_i; V_i = v_i (padding zero)
   double vv = 0.0, ww = 0.0;
   for (int i = 0; i < rd; ++i) {
-    double* Wi = wt + (long long)i * m * TILE;
-    double* Vi = wt + (long long)(rd + i) * m * TILE;
-    band_solve<false, double, double>(bv, s3i, [&](int k) { return uC[i * mp + k]; }, Wi, TILE);
+    double* Wi = wc + (long long)i * mp;
+    double* Vi = wc + (long long)(rd + i) * mp;
+    band_solve<false, 1, double, double>(fb, L, band, g.arrow, s3i,
+                                         [&](int k) { return uC[i * mp + k]; }, Wi);
     for (int k = 0; k < m; ++k) {
       const double v = vC[i * mp + k];
-      Vi[k * TILE] = v;
+      Vi[k] = v;
       vv += v * v;
-      ww += Wi[k * TILE] * Wi[k * TILE];
+      ww += Wi[k] * Wi[k];
     }
+    for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
   }
   // SMW-2: C = I + V^T W, inverted by Gauss-Jordan with partial pivoting
   double Cm[RANK_DIAG_MAX][2 * RANK_DIAG_MAX];
   for (int i = 0; i < rd; ++i)
     for (int j = 0; j < rd; ++j) {
       double s = i == j ? 1.0 : 0.0;
-      const double* Vi = wt + (long long)(rd + i) * m * TILE;
-      const double* Wj = wt + (long long)j * m * TILE;
-      for (int k = 0; k < m; ++k) s += Vi[k * TILE] * Wj[k * TILE];
+      const double* Vi = wc + (long long)(rd + i) * mp;
+      const double* Wj = wc + (long long)j * mp;
+      for (int k = 0; k < m; ++k) s += Vi[k] * Wj[k];
       Cm[i][j] = s;
       Cm[i][rd + j] = i == j ? 1.0 : 0.0;
     }
@@ -232,16 +259,18 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
       for (int j = 0; j < 2 * rd; ++j) Cm[i][j] -= f * Cm[k][j];
     }
   }
-  double* ci = cinv + (long long)tile * rd * rd * TILE + lane;
+  double* ci = cinv + (long long)c * rd * rd;
   for (int i = 0; i < rd; ++i)
-    for (int j = 0; j < rd; ++j) ci[(long long)(i * rd + j) * TILE] = Cm[i][rd + j];
+    for (int j = 0; j < rd; ++j) ci[i * rd + j] = Cm[i][rd + j];
   if (wvT) {  // transposed apply: A0^{-T} v_i and u_i
-    double* wtT = wvT + (long long)tile * 2 * rd * m * TILE + lane;
+    double* wcT = wvT + (long long)c * 2 * rd * mp;
     for (int i = 0; i < rd; ++i) {
-      double* Wi = wtT + (long long)i * m * TILE;
-      double* Vi = wtT + (long long)(rd + i) * m * TILE;
-      band_solve<true, double, double>(bv, s3i, [&](int k) { return vC[i * mp + k]; }, Wi, TILE);
-      for (int k = 0; k < m; ++k) Vi[k * TILE] = uC[i * mp + k];
+      double* Wi = wcT + (long long)i * mp;
+      double* Vi = wcT + (long long)(rd + i) * mp;
+      band_solve<true, 1, double, double>(fb, L, band, g.arrow, s3i,
+                                          [&](int k) { return vC[i * mp + k]; }, Wi);
+      for (int k = 0; k < m; ++k) Vi[k] = uC[i * mp + k];
+      for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
     }
   }
   if (bad) atomicMin(status, c);
@@ -256,53 +285,207 @@ hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, doubl
 }
 
 // ---------------------------------------------------------------- apply ----
-// z = x0 - W C^{-1} (V^T x0), x0 = A0^{-1} r (TRANS: the transposed factors
-// and (C^{-1})^T).  One lane per cell; V^T x0 is summed in the backward
-// sweep's order of the levels, then the flow unknowns.
-template <typename TV, bool TRANS, int RDM>
-__global__ __launch_bounds__(TILE) void k_band_apply(Mesh g, const TV* __restrict__ bf,
+// Software-pipelined walk over `count` steps: the loads of block b + 1 (U
+// steps) are issued before block b is computed.  Loads use clamped step
+// indices, so every load is valid and unconditional; only the computation of
+// steps past the end is skipped (a wave-uniform test).
+template <int U, typename Step, typename LoadF, typename CompF>
+__device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp) {
+  Step A[U], B[U];
+  auto ld = [&](int b, Step(&S)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = b * U + u;
+      load(idx < count ? idx : count - 1, S[u]);
+    }
+  };
+  auto cp = [&](int b, Step(&S)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = b * U + u;
+      if (idx < count) comp(idx, S[u]);
+    }
+  };
+  const int nb = (count + U - 1) / U;
+  ld(0, A);
+  for (int b = 0; b < nb; b += 2) {
+    if (b + 1 < nb) ld(b + 1, B);
+    cp(b, A);
+    if (b + 1 < nb) {
+      if (b + 2 < nb) ld(b + 2, A);
+      cp(b + 1, B);
+    }
+  }
+}
+
+// x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, written to dst[0..m).  The
+// same arithmetic as band_solve, with the factor loads pipelined; BM >= band.
+template <bool TRANS, int BM, typename T, typename TA>
+__device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L, int band,
+                                                int arrow, const T (&s3i)[9],
+                                                const double* __restrict__ rv,
+                                                double* __restrict__ dst) {
+  constexpr int U = BM <= 2 ? 8 : BM <= 4 ? 4 : 2;
+  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)row * L + k) * TILE]; };
+  struct Step {
+    TA a[BM];  // band coefficients of the step
+    TA d;      // 1 / u_kk where the sweep divides
+    TA e[3];   // coupling entries
+    TA v;      // right-hand side (forward) or the forward result (backward)
+  };
+  TA h[BM];
+  TA acc[3] = {TA(0), TA(0), TA(0)};
+#pragma unroll
+  for (int j = 0; j < BM; ++j) h[j] = TA(0);
+  // forward: L_B y = r (TRANS: U_B^T y = r); h[j-1] = y_{k-j}
+  pipelined_walk<U, Step>(
+      L,
+      [&](int k, Step& s) {
+        s.v = (TA)rv[k];
+#pragma unroll
+        for (int j = 1; j <= BM; ++j)
+          s.a[j - 1] = j > band ? TA(0) : TRANS ? at(band + j, k >= j ? k - j : 0) : at(j - 1, k);
+        s.d = TRANS ? at(band, k) : TA(1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s.e[i] = arrow ? at(2 * band + (TRANS ? 1 : 4) + i, k) : TA(0);
+      },
+      [&](int k, const Step& s) {
+        TA y = s.v;
+#pragma unroll
+        for (int j = BM; j >= 1; --j) y -= s.a[j - 1] * h[j - 1];
+        if (TRANS) y *= s.d;
+#pragma unroll
+        for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
+        h[0] = y;
+        dst[k] = (double)y;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] += s.e[i] * y;
+      });
+  TA yf[3], xf[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) yf[i] = (TA)rv[L + i] - acc[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    xf[i] = (TA)s3i[TRANS ? i : 3 * i] * yf[0] + (TA)s3i[TRANS ? 3 + i : 3 * i + 1] * yf[1] +
+            (TA)s3i[TRANS ? 6 + i : 3 * i + 2] * yf[2];
+  // backward: U_B x = y - E_c' x_f (TRANS: L_B^T x = y - E_r'^T x_f);
+  // h[j-1] = x_{k+j}; step t walks k = L - 1 - t
+#pragma unroll
+  for (int j = 0; j < BM; ++j) h[j] = TA(0);
+  pipelined_walk<U, Step>(
+      L,
+      [&](int t, Step& s) {
+        const int k = L - 1 - t;
+        s.v = (TA)dst[k];
+#pragma unroll
+        for (int j = 1; j <= BM; ++j)
+          s.a[j - 1] = j > band ? TA(0) : TRANS ? at(j - 1, k + j < L ? k + j : k) : at(band + j, k);
+        s.d = TRANS ? TA(1) : at(band, k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s.e[i] = arrow ? at(2 * band + (TRANS ? 4 : 1) + i, k) : TA(0);
+      },
+      [&](int t, const Step& s) {
+        const int k = L - 1 - t;
+        TA x = s.v;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x -= s.e[i] * xf[i];
+#pragma unroll
+        for (int j = BM; j >= 1; --j) x -= s.a[j - 1] * h[j - 1];
+        if (!TRANS) x *= s.d;
+#pragma unroll
+        for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
+        h[0] = x;
+        dst[k] = (double)x;
+      });
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dst[L + i] = (double)xf[i];
+}
+
+// x0 = A0^{-1} r for every right-hand side, one lane per cell.
+template <typename TV, bool TRANS, int BM>
+__global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restrict__ bf,
                                                      const TV* __restrict__ s3i_in,
-                                                     const TV* __restrict__ wv,
-                                                     const TV* __restrict__ cinv,
                                                      const double* __restrict__ rin,
                                                      double* __restrict__ zout, int nrhs) {
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int c = tile * TILE + lane;
   if (c >= g.N) return;
-  const int L = g.L, m = g.m, rd = RDM == 1 ? 1 : g.rd;
-  const int RB = band_rows(g);
-  BandView<TV> bv{bf + (long long)tile * RB * L * TILE + lane, L, g.band, g.arrow};
+  const int L = g.L, m = g.m;
+  const TV* fb = bf + (long long)tile * band_rows(g) * L * TILE + lane;
   TV s3i[9];
-  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
-  const TV* wt = wv + (long long)tile * 2 * rd * m * TILE + lane;
-  const TV* ci = cinv + (long long)tile * rd * rd * TILE + lane;
-  for (int r = 0; r < nrhs; ++r) {
-    const double* rv = rin + (long long)r * g.n + (long long)c * m;
-    double* zv = zout + (long long)r * g.n + (long long)c * m;
-    band_solve<TRANS, TV, TV>(bv, s3i, [&](int k) { return rv[k]; }, zv, 1);
-    TV s[RDM], z[RDM];
-    for (int i = 0; i < RDM; ++i) s[i] = TV(0);
-    for (int k = 0; k < m; ++k) {
-      const TV xk = (TV)zv[k];
 #pragma unroll
-      for (int i = 0; i < RDM; ++i)
-        if (i < rd) s[i] += wt[((long long)(rd + i) * m + k) * TILE] * xk;
-    }
+  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
+  for (int r = 0; r < nrhs; ++r)
+    band_solve_pipe<TRANS, BM, TV, TV>(fb, L, g.band, g.arrow, s3i,
+                                       rin + (long long)r * g.n + (long long)c * m,
+                                       zout + (long long)r * g.n + (long long)c * m);
+}
+
+// z = x0 - W C^{-1} (V^T x0) in place, one wavefront per cell (NCH chunks of
+// 64 unknowns), W and V rows [N][2 rd][mp] of the direction being applied.
+template <typename TV, int NCH, bool TRANS, int RDM>
+__global__ __launch_bounds__(64 * WPB) void k_band_woodbury(Mesh g, const TV* __restrict__ wv,
+                                                            const TV* __restrict__ cinv,
+                                                            double* __restrict__ z, int nrhs) {
+  const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + (threadIdx.x >> 6)));
+  if (c >= g.N) return;
+  const int lane = lane_id();
+  const int m = g.m, rd = RDM == 1 ? 1 : g.rd;
+  const long long mp = g.mp;
+  const TV* wc = wv + (long long)c * 2 * rd * mp;
+  CapInv<TV, RDM> IC;
+  IC.load(cinv, c, rd, lane);
+  TV W[RDM][NCH], V[RDM][NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    const int kk = k < m ? k : m - 1;
 #pragma unroll
     for (int i = 0; i < RDM; ++i) {
-      TV a = TV(0);
-#pragma unroll
-      for (int l = 0; l < RDM; ++l)
-        if (i < rd && l < rd) a += ci[(long long)(TRANS ? l * rd + i : i * rd + l) * TILE] * s[l];
-      z[i] = a;
+      W[i][ch] = i < rd ? ld_stream(wc + i * mp + kk) : TV(0);
+      V[i][ch] = i < rd ? ld_stream(wc + (rd + i) * mp + kk) : TV(0);
     }
-    for (int k = 0; k < m; ++k) {
-      TV o = (TV)zv[k];
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    double* zc = z + (long long)r * g.n + (long long)c * m;
+    TV X[NCH];
 #pragma unroll
-      for (int i = 0; i < RDM; ++i)
-        if (i < rd) o -= z[i] * wt[((long long)i * m + k) * TILE];
-      zv[k] = (double)o;
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      X[ch] = (TV)zc[k < m ? k : m - 1];
     }
+    TV s[RDM], zz[RDM];
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) {
+      TV t = TV(0);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (ch * WAVE + lane < m) t += V[i][ch] * X[ch];
+      s[i] = i < rd ? wave_sum_u(t) : TV(0);
+    }
+    IC.template apply<TRANS>(s, zz, rd);
+    // every lane has read its entries before any lane writes (the reads
+    // above feed the wave sums), so the in-place update is safe
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      TV o = X[ch];
+#pragma unroll
+      for (int i = 0; i < RDM; ++i) o -= zz[i] * W[i][ch];
+      if (k < m) zc[k] = (double)o;
+    }
+  }
+}
+
+template <typename TV, bool TRANS, int RDM>
+static void launch_woodbury_r(const Mesh& g, const TV* wv, const TV* cinv, double* z, int nrhs,
+                              hipStream_t s) {
+  const dim3 grid((g.N + WPB - 1) / WPB), block(64 * WPB);
+  switch ((g.m + WAVE - 1) / WAVE) {
+    case 1: hipLaunchKernelGGL((k_band_woodbury<TV, 1, TRANS, RDM>), grid, block, 0, s, g, wv, cinv, z, nrhs); break;
+    case 2: hipLaunchKernelGGL((k_band_woodbury<TV, 2, TRANS, RDM>), grid, block, 0, s, g, wv, cinv, z, nrhs); break;
+    case 3: hipLaunchKernelGGL((k_band_woodbury<TV, 3, TRANS, RDM>), grid, block, 0, s, g, wv, cinv, z, nrhs); break;
+    default: hipLaunchKernelGGL((k_band_woodbury<TV, 4, TRANS, RDM>), grid, block, 0, s, g, wv, cinv, z, nrhs); break;
   }
 }
 
@@ -311,18 +494,24 @@ static hipError_t launch_band_apply_t(const Mesh& g, const TV* bf, const TV* s3i
                                       const TV* cinv, const double* r, double* z, int nrhs,
                                       hipStream_t s) {
   const dim3 grid((unsigned)tiles(g)), block(TILE);
-  if (g.rd == 1)
-    hipLaunchKernelGGL((k_band_apply<TV, TRANS, 1>), grid, block, 0, s, g, bf, s3i, wv, cinv, r, z, nrhs);
+  if (g.band <= 2)
+    hipLaunchKernelGGL((k_band_solve<TV, TRANS, 2>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
+  else if (g.band <= 4)
+    hipLaunchKernelGGL((k_band_solve<TV, TRANS, 4>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
   else
-    hipLaunchKernelGGL((k_band_apply<TV, TRANS, RANK_DIAG_MAX>), grid, block, 0, s, g, bf, s3i, wv,
-                       cinv, r, z, nrhs);
+    hipLaunchKernelGGL((k_band_solve<TV, TRANS, BAND_MAX>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
+  if (g.rd == 1)
+    launch_woodbury_r<TV, TRANS, 1>(g, wv, cinv, z, nrhs, s);
+  else
+    launch_woodbury_r<TV, TRANS, RANK_DIAG_MAX>(g, wv, cinv, z, nrhs, s);
   return hipGetLastError();
 }
 
 hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, const void* wv,
                              const void* cinv, bool f32, bool trans, const double* r, double* z,
                              int nrhs, hipStream_t s) {
-  if (g.rd > RANK_DIAG_MAX || g.band > BAND_MAX) return hipErrorInvalidValue;
+  if (g.rd > RANK_DIAG_MAX || g.band > BAND_MAX || g.m > WAVE * MAX_CHUNKS)
+    return hipErrorInvalidValue;
   if (f32)
     return trans ? launch_band_apply_t<float, true>(g, (const float*)bf, (const float*)s3i,
                                                     (const float*)wv, (const float*)cinv, r, z, nrhs, s)
@@ -334,14 +523,15 @@ hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, con
                                                     (const double*)wv, (const double*)cinv, r, z, nrhs, s);
 }
 
-// Element counts of the tile-interleaved arrays (host layout helper).
+// Element counts of the factor arrays (host layout helper): band factors and
+// Schur inverses tile-interleaved, W / V rows and C^{-1} per cell.
 void band_prec_counts(const Mesh& g, long long* bf, long long* s3i, long long* wv,
                       long long* cinv) {
   const long long T = tiles(g);
   *bf = T * band_rows(g) * g.L * TILE;
   *s3i = T * 9 * TILE;
-  *wv = T * 2 * g.rd * g.m * TILE;
-  *cinv = T * g.rd * g.rd * TILE;
+  *wv = (long long)g.N * 2 * g.rd * g.mp;
+  *cinv = (long long)g.N * g.rd * g.rd;
 }
 
 }  // namespace r1s

@@ -336,4 +336,48 @@ __device__ inline void smw_sweeps(int L, int m, const T (&A)[NCH], const T (&DI)
   }
 }
 
+// Per-cell inverse capacitance C^{-1} of the Woodbury correction.  With one
+// pair it is a scalar per cell; with rd pairs lane t of the wave holds entries t and
+// 64 + t of the cell's row-major C^{-1} (rd^2 <= 81 values), read back with
+// v_readlane (transposed apply: (C^{-1})^T, the same values read transposed).
+template <typename TV, int RDM>
+struct CapInv {
+  static constexpr int NV = (RDM * RDM + WAVE - 1) / WAVE;
+  TV v[NV];
+  __device__ inline void load(const TV* invC, int c, int rd, int lane) {
+    if (RDM == 1) {
+      v[0] = invC[c];
+    } else {
+      const int cnt = rd * rd;
+      const TV* p = invC + (long long)c * cnt;
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        const int t = h * WAVE + lane;
+        v[h] = p[t < cnt ? t : cnt - 1];
+      }
+    }
+  }
+  // z_i = sum_l Cinv(i, l) s_l   (TRANS: Cinv(l, i))
+  template <bool TRANS>
+  __device__ inline void apply(const TV (&s)[RDM], TV (&z)[RDM], int rd) const {
+    if (RDM == 1) {
+      z[0] = s[0] * v[0];
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < RDM; ++i) {
+      TV acc = TV(0);
+#pragma unroll
+      for (int l = 0; l < RDM; ++l) {
+        if (i < rd && l < rd) {
+          const int t = TRANS ? l * rd + i : i * rd + l;
+          const TV e = t < WAVE ? readlane(v[0], t) : readlane(v[NV - 1], t - (NV - 1) * WAVE);
+          acc += e * s[l];
+        }
+      }
+      z[i] = acc;
+    }
+  }
+};
+
 }  // namespace r1s
