@@ -32,7 +32,11 @@
 
 namespace r1s {
 
-constexpr int TILE = 64;
+// Cells per band-walk workgroup (one wavefront; lanes past TILE idle).
+#ifndef R1S_BAND_TILE
+#define R1S_BAND_TILE 64
+#endif
+constexpr int TILE = R1S_BAND_TILE;
 
 // Row offsets of the band factors inside one tile ([rows][L][64]):
 //   lo(j) rows 0..band-1       l_{k,j} = L_B[k][k-j]      (k >= j)
