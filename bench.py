@@ -542,11 +542,11 @@ def main():
                    "bytes_per_step": mv_b + ap_b},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "cell_updates_per_s": round(N / (wall / steps), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false,1,1> (J x)",
+        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false,1,1,false> (J x)",
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(
-                         "void r1s::k_matvec<double, 1, 1, false, false, 1, 1>"),
+                         "void r1s::k_matvec<double, 1, 1, false, false, 1, 1, false>"),
                      "avg_launch_us": round(mv_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": mv_b},
         "kernels_us": {"matvec_f64": round(mv_ms * 1e3, 2), "smw_apply_f64": round(ap_ms * 1e3, 2)},
