@@ -216,3 +216,80 @@ def structured_matvec(p, nx, ny, L, x, csr=None, br1=None):
     y = csr_matvec(*csr, np.ravel(x))
     y, _ = br1_matvec(br1, np.ravel(x), m, m, y=y)
     return y
+
+
+# -------------------------------------------------------- general mesh --
+def graph_csr(p, L):
+    """CSR of the fully sparse part S on a general mesh (per-cell diagonal
+    block pattern, diagonal off-diagonal blocks), row by row."""
+    indptr, indices = p["graph_indptr"], p["graph_indices"]
+    N, m = len(indptr) - 1, L + 3
+    band, arrow = mesh.pattern(p)
+    data, cols, rowptr = [], [], [0]
+    for c in range(N):
+        offs = []  # column cells of the row's off-diagonal blocks, in order
+        for b in range(indptr[c], indptr[c + 1]):
+            j = int(indices[b])
+            if j != c:
+                offs.append(j)
+        # off-block numbers of this row: consecutive, starting after all
+        # off blocks of earlier rows
+        first = int(indptr[c]) - c
+        for k in range(m):
+            row = {c * m + k: p["s_diag"][c, k]}
+            if k < L:
+                if k >= 1:
+                    row[c * m + k - 1] = p["s_sub"][c, k - 1]
+                if k <= L - 2:
+                    row[c * m + k + 1] = p["s_sup"][c, k]
+                for j in range(2, band + 1):
+                    if k - j >= 0:
+                        row[c * m + k - j] = p["s_band"][c, j - 2, k]
+                    if k + j < L:
+                        row[c * m + k + j] = p["s_band"][c, band - 1 + j - 2, k]
+                if arrow:
+                    for i in range(3):
+                        row[c * m + L + i] = p["s_lev_flow"][c, i, k]
+            else:
+                i = k - L
+                for t, (a, b) in enumerate(assemble.FLOW_PAIRS):
+                    if a == i:
+                        row[c * m + L + b] = p["s_flow"][c, t]
+                if arrow:
+                    for kk in range(L):
+                        row[c * m + kk] = p["s_flow_lev"][c, i, kk]
+            for t, j in enumerate(offs):
+                row[j * m + k] = p["s_nbr"][first + t, k]
+            for col in sorted(row):
+                data.append(row[col])
+                cols.append(col)
+            rowptr.append(len(data))
+    return np.array(data), np.array(cols, dtype=np.int64), np.array(rowptr, dtype=np.int64)
+
+
+def graph_br1(p):
+    """BR1-BSR arrays of the rank-one part on a general mesh."""
+    indptr, indices = p["graph_indptr"], p["graph_indices"]
+    blocks, o = [], 0
+    for c in range(len(indptr) - 1):
+        for b in range(indptr[c], indptr[c + 1]):
+            j = int(indices[b])
+            if j == c:
+                pairs = list(zip(p["u_diag"][c], p["v_diag"][c]))
+            else:
+                pairs = list(zip(p["u_off"][o], p["v_off"][o]))
+                o += 1
+            blocks.append((c, j, pairs))
+    return br1_bsr(blocks, len(indptr) - 1)
+
+
+def graph_matvec(p, L, x, csr=None, br1=None):
+    """y = S x (CSR) + the BR1 product accumulated on top (section 5.2)."""
+    m = L + 3
+    if csr is None:
+        csr = graph_csr(p, L)
+    if br1 is None:
+        br1 = graph_br1(p)
+    y = csr_matvec(*csr, np.ravel(x))
+    y, _ = br1_matvec(br1, np.ravel(x), m, m, y=y)
+    return y

@@ -194,3 +194,142 @@ def make_vector(nx: int, ny: int, L: int, nrhs: int = 1, seed: int = 0) -> np.nd
 
 def workload_problem(w: Workload) -> Dict[str, np.ndarray]:
     return make_problem(w.nx, w.ny, w.L, seed=w.seed, inv_dt=w.inv_dt)
+
+
+# ------------------------------------------------------------- general mesh --
+# A general 2-D mesh is given by its block structure in the index arrays of
+# the BR1-BSR format (section 5.1): block_indptr [N+1] and block_indices
+# [nnzb] (int32), the block columns of every block row, the diagonal block
+# included once.  The adjacency is structurally symmetric (a face joins two
+# cells).  Off-diagonal blocks are numbered in the order of block_indices,
+# skipping each row's diagonal entry.
+GRAPH_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u_diag", "v_diag", "u_off",
+                "v_off")
+
+
+def structured_graph(nx: int, ny: int):
+    """Index arrays of the structured nx x ny mesh (blocks S, W, C, E, N)."""
+    indptr, indices = [0], []
+    for c in range(nx * ny):
+        iy, ix = divmod(c, nx)
+        cols = []
+        if iy > 0:
+            cols.append(c - nx)
+        if ix > 0:
+            cols.append(c - 1)
+        cols.append(c)
+        if ix < nx - 1:
+            cols.append(c + 1)
+        if iy < ny - 1:
+            cols.append(c + nx)
+        indices += cols
+        indptr.append(len(indices))
+    return np.array(indptr, dtype=np.int32), np.array(indices, dtype=np.int32)
+
+
+def delaunay_graph(n_points: int, seed: int = 0, shuffle: bool = True):
+    """Cell adjacency of a Delaunay triangulation of random points in the unit
+    square: every triangle is a cell, neighbours share an edge (at most 3).
+    Rows list the diagonal first, then the neighbours in ascending order.
+    With `shuffle`, cells are renumbered at random (no locality)."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    tri = Delaunay(rng.random((n_points, 2)))
+    nbrs = tri.neighbors  # [n_tri][3], -1 on the hull
+    n = nbrs.shape[0]
+    perm = rng.permutation(n) if shuffle else np.arange(n)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)          # old -> new
+    indptr, indices = [0], []
+    for new in range(n):
+        old = perm[new]
+        cols = sorted(int(inv[t]) for t in nbrs[old] if t >= 0)
+        indices += [new] + cols
+        indptr.append(len(indices))
+    return np.array(indptr, dtype=np.int32), np.array(indices, dtype=np.int32)
+
+
+def graph_off_blocks(indptr, indices):
+    """(row, column) of every off-diagonal block in input order."""
+    rows, cols = [], []
+    for c in range(len(indptr) - 1):
+        for b in range(indptr[c], indptr[c + 1]):
+            if indices[b] != c:
+                rows.append(c)
+                cols.append(int(indices[b]))
+    return np.array(rows, dtype=np.int64), np.array(cols, dtype=np.int64)
+
+
+def make_graph_problem(indptr, indices, L: int, seed: int = 0, inv_dt: float = 20.0,
+                       r_diag: int = 1, r_off: int = 1, band: int = 1,
+                       arrow: bool = False) -> Dict[str, np.ndarray]:
+    """Structured values on a general mesh, same distributions as
+    make_problem: per cell the diagonal block (s_diag, s_sub, s_sup, s_flow,
+    optional s_band / s_lev_flow / s_flow_lev, r_diag pairs u_diag, v_diag
+    [N][r_diag][m]); per off-diagonal block its diagonal s_nbr [n_off][m]
+    and r_off pairs u_off, v_off [n_off][r_off][m]."""
+    N, m = len(indptr) - 1, L + 3
+    n_off = len(indices) - N
+    rng = np.random.default_rng(seed)
+    p = {"graph_indptr": np.asarray(indptr, dtype=np.int32),
+         "graph_indices": np.asarray(indices, dtype=np.int32)}
+    p["s_diag"] = inv_dt + 10.0 * np.abs(rng.standard_normal((N, m)))
+    p["s_sub"] = rng.standard_normal((N, L - 1))
+    p["s_sup"] = rng.standard_normal((N, L - 1))
+    p["s_flow"] = rng.standard_normal((N, 6))
+    p["s_nbr"] = rng.uniform(-1.0, 0.0, size=(n_off, m))
+    p["u_diag"] = 0.1 * rng.standard_normal((N, r_diag, m))
+    p["v_diag"] = 0.1 * rng.standard_normal((N, r_diag, m))
+    p["u_off"] = 0.1 * rng.standard_normal((n_off, r_off, m))
+    p["v_off"] = 0.1 * rng.standard_normal((n_off, r_off, m))
+    wide = band > 1 or arrow
+    if wide:
+        nb = band - 1
+        p["s_band"] = rng.standard_normal((N, 2 * nb, L))
+        k = np.arange(L)
+        for j in range(2, band + 1):
+            p["s_band"][:, j - 2, k < j] = 0.0
+            p["s_band"][:, nb + j - 2, k + j > L - 1] = 0.0
+        if arrow:
+            p["s_lev_flow"] = 0.1 * rng.standard_normal((N, 3, L))
+            p["s_flow_lev"] = rng.standard_normal((N, 3, L)) / L
+        else:
+            p["s_lev_flow"] = np.zeros((N, 3, L))
+            p["s_flow_lev"] = np.zeros((N, 3, L))
+        p["pattern"] = np.array([band, int(bool(arrow))])
+    for k in GRAPH_FIELDS + (PATTERN_FIELDS if wide else ()):
+        p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
+    p["ranks"] = np.array([r_diag, r_off])
+    return p
+
+
+def graph_from_structured(p: Dict[str, np.ndarray], nx: int, ny: int) -> Dict[str, np.ndarray]:
+    """The same Jacobian as a structured problem, in the general-mesh layout
+    (blocks of missing neighbours dropped; a re-layout, no arithmetic)."""
+    r_diag, r_off = (int(v) for v in p.get("ranks", (1, 1)))
+    slots = pair_slots(r_diag, r_off)
+    indptr, indices = structured_graph(nx, ny)
+    q = {"graph_indptr": indptr, "graph_indices": indices, "ranks": np.array([r_diag, r_off])}
+    for k in ("s_diag", "s_sub", "s_sup", "s_flow") + tuple(k for k in PATTERN_FIELDS if k in p):
+        q[k] = p[k].copy()
+    if "pattern" in p:
+        q["pattern"] = p["pattern"].copy()
+    a, cnt = slots[DIR_C]
+    q["u_diag"] = p["u"][:, a:a + cnt].copy()
+    q["v_diag"] = p["v"][:, a:a + cnt].copy()
+    nbr, uo, vo = [], [], []
+    for c in range(nx * ny):
+        iy, ix = divmod(c, nx)
+        for d, ok in ((DIR_S, iy > 0), (DIR_W, ix > 0), (DIR_E, ix < nx - 1), (DIR_N, iy < ny - 1)):
+            if ok:
+                nbr.append(p["s_nbr"][c, NBR_DIRS.index(d)])
+                a, cnt = slots[d]
+                uo.append(p["u"][c, a:a + cnt])
+                vo.append(p["v"][c, a:a + cnt])
+    m = p["s_diag"].shape[1]
+    n_off = len(nbr)
+    q["s_nbr"] = np.array(nbr).reshape(n_off, m)
+    q["u_off"] = np.array(uo).reshape(n_off, r_off, m)
+    q["v_off"] = np.array(vo).reshape(n_off, r_off, m)
+    return q
