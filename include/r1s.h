@@ -106,6 +106,7 @@ extern "C" {
 
 #define R1S_MAX_M 256   /* largest supported block size m = L + 3 */
 #define R1S_MAX_BAND 8  /* largest level-band half-width of S_{c,C} */
+#define R1S_MAX_NBR 8   /* general mesh: most off-diagonal blocks in a block row */
 
 typedef struct r1s_mat_s* r1s_mat;   /* structured r1-sparse Jacobian      */
 typedef struct r1s_prec_s* r1s_prec; /* block-Jacobi preconditioner        */
@@ -147,12 +148,50 @@ typedef struct {
   double* s_flow_lev;
 } r1s_grads;
 
+/* Inputs on a general mesh (r1s_mat_init_graph).  Per cell, the diagonal
+ * block as on the structured mesh: s_diag [N][m], s_sub, s_sup [N][L-1],
+ * s_flow [N][6], s_band / s_lev_flow / s_flow_lev (layouts that use them),
+ * its r_diag pairs u_diag, v_diag [N][r_diag][m].  Per off-diagonal block, in
+ * the order of block_indices with each row's diagonal entry skipped: its
+ * diagonal s_nbr [n_off][m] and r_off pairs u_off, v_off [n_off][r_off][m]. */
+typedef struct {
+  const double* s_diag;
+  const double* s_sub;
+  const double* s_sup;
+  const double* s_flow;
+  const double* s_band;
+  const double* s_lev_flow;
+  const double* s_flow_lev;
+  const double* s_nbr;
+  const double* u_diag;
+  const double* v_diag;
+  const double* u_off;
+  const double* v_off;
+} r1s_graph_inputs;
+
+/* Gradient outputs on a general mesh, same shapes as r1s_graph_inputs. */
+typedef struct {
+  double* s_diag;
+  double* s_sub;
+  double* s_sup;
+  double* s_flow;
+  double* s_band;
+  double* s_lev_flow;
+  double* s_flow_lev;
+  double* s_nbr;
+  double* u_diag;
+  double* v_diag;
+  double* u_off;
+  double* v_off;
+} r1s_graph_grads;
+
 typedef struct {
   int64_t n_cells, n_blocks, m;
   int64_t structured_values;  /* algorithmic stored values of S + u/v      */
   int64_t structured_padded;  /* values actually held (64-byte row padding) */
   int64_t bsr_values;         /* B * m^2 of the dense-block representation */
-  int64_t index_bytes;        /* explicit index data: 0 (mesh-implicit)    */
+  int64_t index_bytes;        /* explicit index data: 0 on the structured
+                                 mesh; the int32 slot tables on a general one */
   int64_t matvec_bytes;       /* algorithmic HBM bytes of one F64 matvec   */
   int64_t smw_apply_bytes;    /* algorithmic HBM bytes of one F64 apply    */
 } r1s_storage;
@@ -214,6 +253,28 @@ int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int flags,
 int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream);
 
 int r1s_mat_destroy(r1s_mat A);
+
+/* General 2-D mesh (section 5.1: the block structure of a BSR / BR1-BSR
+ * matrix).  block_indptr [n_cells + 1] and block_indices [nnzb] are host
+ * int32 arrays: the block columns of every block row, in any order, the
+ * diagonal block exactly once; the structure must be symmetric (block (c, j)
+ * exists iff (j, c) does, as for the faces of a finite-volume mesh) and a
+ * row holds at most R1S_MAX_NBR off-diagonal blocks.  The library copies what
+ * it needs; the arrays may be freed after the call.  Every other call
+ * (matvec, residual, preconditioners, BSR copy, GMRES) takes the returned
+ * handle like a structured one.  Errors: R1S_ERR_ARG for a malformed or
+ * unsymmetric structure (the message names the row or block),
+ * R1S_ERR_UNSUPPORTED for more than R1S_MAX_NBR neighbours, as for
+ * r1s_mat_size / r1s_mat_init otherwise. */
+int r1s_mat_size_graph(int n_cells, int L, const r1s_layout* layout,
+                       const int* block_indptr, const int* block_indices,
+                       int flags, size_t* bytes);
+int r1s_mat_init_graph(int n_cells, int L, const r1s_layout* layout,
+                       const int* block_indptr, const int* block_indices,
+                       int flags, const r1s_graph_inputs* in, void* mem,
+                       size_t mem_bytes, void* stream, r1s_mat* out);
+/* New values for a general-mesh matrix (same structure). */
+int r1s_mat_update_graph(r1s_mat A, const r1s_graph_inputs* in, void* stream);
 
 /* Stored-value counts of the structured and dense-block representations
  * (section 3, Jacobian Complexity: N_A = sum m^2 (N_e + 1)). */
@@ -295,6 +356,11 @@ int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
  * slots of blocks that do not exist.  nrhs <= 64.  Asynchronous. */
 int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
              const r1s_grads* out, void* stream);
+
+/* The same gradients for a general-mesh matrix, in its input layout (zero
+ * for no block: every listed block exists). */
+int r1s_grad_graph(r1s_mat A, int nrhs, const double* lambda, const double* x,
+                   const r1s_graph_grads* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -157,3 +157,49 @@ def structured_values(p, L):
     diag_block_vals = m + sum(2 * max(L - j, 0) for j in range(1, band + 1)) + 6 + (6 * L if arrow else 0)
     rd, ro = p["u_diag"].shape[1], p["u_off"].shape[1]
     return N * diag_block_vals + n_off * m + 2 * m * (N * rd + n_off * ro)
+
+
+def _row_blocks(p, c, L):
+    """(column, dense block) of block row c."""
+    indptr, indices = p["graph_indptr"], p["graph_indices"]
+    o = int(indptr[c]) - c  # off-diagonal blocks of the rows before c
+    out = []
+    for b in range(indptr[c], indptr[c + 1]):
+        j = int(indices[b])
+        if j == c:
+            out.append((j, diag_block(p, c, L)))
+        else:
+            out.append((j, off_block(p, o)))
+            o += 1
+    return out
+
+
+def matvec_rows(p, L, x, cells):
+    """(J x) restricted to the block rows `cells`: [nrhs][len(cells)][m]."""
+    x3 = _as3(x)
+    out = np.zeros((x3.shape[0], len(cells), L + 3))
+    for t, c in enumerate(cells):
+        for j, D in _row_blocks(p, c, L):
+            out[:, t, :] += x3[:, j, :] @ D.T
+    return out
+
+
+def matvec_T_rows(p, L, x, cells):
+    """(J^T x) restricted to the block rows `cells`: row j of J^T sums the
+    transposed blocks (c, j) over the cells c whose row lists j (the
+    structure is symmetric, so those are j's own neighbours and j)."""
+    x3 = _as3(x)
+    indptr, indices = p["graph_indptr"], p["graph_indices"]
+    out = np.zeros((x3.shape[0], len(cells), L + 3))
+    for t, j in enumerate(cells):
+        for c in indices[indptr[j]:indptr[j + 1]]:
+            for jj, D in _row_blocks(p, int(c), L):
+                if jj == j:
+                    out[:, t, :] += x3[:, int(c), :] @ D
+    return out
+
+
+def abs_problem(p):
+    """The same structure with every value replaced by its absolute value
+    (|J| for the componentwise error scale)."""
+    return {k: (np.abs(v) if v.dtype.kind == "f" else v) for k, v in p.items()}

@@ -28,6 +28,7 @@ R1S_F64, R1S_F32 = 0, 1
 R1S_KEEP_F32, R1S_WITH_TRANS = 1, 2
 R1S_MAX_M = 256
 R1S_MAX_BAND = 8
+R1S_MAX_NBR = 8
 R1S_OP_STRUCTURED, R1S_OP_BSR = 0, 1
 R1S_MODE_F64, R1S_MODE_MIXED_IR = 0, 1
 
@@ -46,6 +47,18 @@ class Inputs(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in INPUT_FIELDS]
+
+
+GRAPH_INPUT_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_band", "s_lev_flow", "s_flow_lev",
+                      "s_nbr", "u_diag", "v_diag", "u_off", "v_off")
+
+
+class GraphInputs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in GRAPH_INPUT_FIELDS]
+
+
+class GraphGrads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in GRAPH_INPUT_FIELDS]
 
 
 class Storage(C.Structure):
@@ -78,6 +91,10 @@ SIGNATURES = {
                           C.POINTER(_VP)]),
     "r1s_mat_update": (_I, [_VP, C.POINTER(Inputs), _VP]),
     "r1s_mat_destroy": (_I, [_VP]),
+    "r1s_mat_size_graph": (_I, [_I, _I, C.POINTER(Layout), _VP, _VP, _I, _PSZ]),
+    "r1s_mat_init_graph": (_I, [_I, _I, C.POINTER(Layout), _VP, _VP, _I, C.POINTER(GraphInputs),
+                                _VP, _SZ, _VP, C.POINTER(_VP)]),
+    "r1s_mat_update_graph": (_I, [_VP, C.POINTER(GraphInputs), _VP]),
     "r1s_mat_storage": (_I, [_VP, C.POINTER(Storage)]),
     "r1s_matvec": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "r1s_residual": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
@@ -95,6 +112,7 @@ SIGNATURES = {
     "r1s_gmres": (_I, [_VP, _VP, _VP, C.POINTER(GmresOpts), _I, _VP, _VP, _VP, _SZ,
                        C.POINTER(GmresStats), _VP]),
     "r1s_grad": (_I, [_VP, _I, _VP, _VP, C.POINTER(Grads), _VP]),
+    "r1s_grad_graph": (_I, [_VP, _I, _VP, _VP, C.POINTER(GraphGrads), _VP]),
 }
 
 _lib = None

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include <rocblas/rocblas.h>
@@ -86,15 +87,20 @@ static int check_layout(const r1s_layout& lay) {
   return R1S_OK;
 }
 
-static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay) {
-  Mesh g;
+// nbmax: neighbour slots per cell record (4 on the structured mesh; the
+// largest number of off-diagonal blocks of a block row on a general mesh).
+static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay, bool graph = false,
+                      int nbmax = 4) {
+  Mesh g{};
   g.nx = nx; g.ny = ny; g.L = L; g.m = L + 3; g.mp = pad_m(L + 3);
   g.N = nx * ny;
   g.n = (long long)g.N * g.m;
   g.rd = lay.r_diag; g.ro = lay.r_off;
-  g.P = g.rd + 4 * g.ro;
+  g.graph = graph ? 1 : 0;
+  g.nbmax = nbmax;
+  g.P = g.rd + nbmax * g.ro;
   g.band = lay.band; g.arrow = lay.arrow;
-  g.fb = F_BAND;
+  g.fb = F_NBR + nbmax;
   g.fa = g.fb + 2 * (g.band - 1);
   g.fu = g.fa + 6 * g.arrow;
   g.F = g.fu + 2 * g.P;
@@ -109,7 +115,17 @@ struct r1s_mat_s {
   int flags;
   double* rec64;
   float* rec32;
+  // general mesh: the caller's block structure (host copy) and the device
+  // neighbour tables carved from the matrix buffer
+  std::vector<int> indptr, indices;
+  int *d_nbr, *d_tslot, *d_offb;
 };
+
+// Blocks of the Jacobian: 5N - 2nx - 2ny on the structured mesh, the
+// length of block_indices on a general one.
+static long long mat_blocks(const r1s_mat_s* A) {
+  return A->g.graph ? (long long)A->indices.size() : n_blocks(A->g.nx, A->g.ny);
+}
 
 static void mat_layout(Carver& cv, const Mesh& g, int flags, double** r64, float** r32) {
   const size_t cnt = (size_t)g.N * g.F * g.mp;
@@ -168,19 +184,19 @@ extern "C" int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int
   if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
   if (mem_bytes < need)
     return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
-  r1s_mat A = (r1s_mat)calloc(1, sizeof(r1s_mat_s));
+  r1s_mat A = new (std::nothrow) r1s_mat_s();
   if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
   A->g = g;
   A->flags = flags;
   Carver cv(mem);
   mat_layout(cv, A->g, flags, &A->rec64, &A->rec32);
   if (int e = do_pack(A, in, as_stream(stream))) {
-    free(A);
+    delete A;
     return e;
   }
   hipError_t he = hipStreamSynchronize(as_stream(stream));
   if (he != hipSuccess) {
-    free(A);
+    delete A;
     return fail(R1S_ERR_HIP, "pack: %s", hipGetErrorString(he));
   }
   *out = A;
@@ -189,6 +205,7 @@ extern "C" int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int
 
 extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
   if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (A->g.graph) return fail(R1S_ERR_ARG, "general-mesh matrix: use r1s_mat_update_graph");
   if (int e = check_inputs(in, A->g)) return e;
   if (int e = do_pack(A, in, as_stream(stream))) return e;
   HIP_TRY(hipStreamSynchronize(as_stream(stream)));
@@ -196,14 +213,173 @@ extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
 }
 
 extern "C" int r1s_mat_destroy(r1s_mat A) {
-  free(A);
+  delete A;
+  return R1S_OK;
+}
+
+// ------------------------------------------------------- general mesh ----
+// Validates the block structure and builds the slot tables: nbr[c][s] = the
+// s-th off-diagonal block column of row c (input order, -1 past the row's
+// degree), tslot[c][s] = the slot of c in that neighbour's row, offb[c] =
+// number of off-diagonal blocks in the rows before c.
+struct GraphTables {
+  int nbmax = 0;
+  long long n_off = 0;
+  std::vector<int> nbr, tslot, offb;
+};
+
+static int build_graph(int N, const int* indptr, const int* indices, GraphTables* t) {
+  if (N < 1) return fail(R1S_ERR_ARG, "n_cells must be >= 1 (got %d)", N);
+  if (N > (1 << 30)) return fail(R1S_ERR_ARG, "mesh too large");
+  if (!indptr || !indices) return fail(R1S_ERR_ARG, "block_indptr or block_indices is NULL");
+  if (indptr[0] != 0) return fail(R1S_ERR_ARG, "block_indptr[0] must be 0");
+  int nbmax = 0;
+  for (int c = 0; c < N; ++c) {
+    const int b0 = indptr[c], b1 = indptr[c + 1];
+    if (b1 < b0) return fail(R1S_ERR_ARG, "block_indptr decreases at row %d", c);
+    int ndiag = 0;
+    for (int b = b0; b < b1; ++b) {
+      const int j = indices[b];
+      if (j < 0 || j >= N) return fail(R1S_ERR_ARG, "block column %d of row %d out of range", j, c);
+      if (j == c) ++ndiag;
+      for (int b2 = b0; b2 < b; ++b2)
+        if (indices[b2] == j) return fail(R1S_ERR_ARG, "row %d lists block column %d twice", c, j);
+    }
+    if (ndiag != 1) return fail(R1S_ERR_ARG, "row %d must list its diagonal block once", c);
+    nbmax = std::max(nbmax, b1 - b0 - 1);
+  }
+  if (nbmax > GRAPH_NBR_MAX)
+    return fail(R1S_ERR_UNSUPPORTED, "a cell has %d neighbours (at most %d)", nbmax, GRAPH_NBR_MAX);
+  t->nbmax = nbmax;
+  t->n_off = (long long)indptr[N] - N;
+  t->nbr.assign((size_t)N * nbmax, -1);
+  t->tslot.assign((size_t)N * nbmax, -1);
+  t->offb.resize(N);
+  for (int c = 0; c < N; ++c) {
+    t->offb[c] = indptr[c] - c;
+    int s = 0;
+    for (int b = indptr[c]; b < indptr[c + 1]; ++b)
+      if (indices[b] != c) t->nbr[(size_t)c * nbmax + s++] = indices[b];
+  }
+  for (int c = 0; c < N; ++c)
+    for (int s = 0; s < nbmax; ++s) {
+      const int j = t->nbr[(size_t)c * nbmax + s];
+      if (j < 0) break;
+      for (int u = 0; u < nbmax; ++u)
+        if (t->nbr[(size_t)j * nbmax + u] == c) t->tslot[(size_t)c * nbmax + s] = u;
+      if (t->tslot[(size_t)c * nbmax + s] < 0)
+        return fail(R1S_ERR_ARG, "block (%d, %d) has no transposed partner (%d, %d)", c, j, j, c);
+    }
+  return R1S_OK;
+}
+
+static void graph_layout(Carver& cv, const Mesh& g, int flags, r1s_mat_s* A) {
+  mat_layout(cv, g, flags, &A->rec64, &A->rec32);
+  A->d_nbr = cv.take<int>((size_t)g.N * g.nbmax);
+  A->d_tslot = cv.take<int>((size_t)g.N * g.nbmax);
+  A->d_offb = cv.take<int>(g.N);
+}
+
+extern "C" int r1s_mat_size_graph(int n_cells, int L, const r1s_layout* layout,
+                                  const int* block_indptr, const int* block_indices, int flags,
+                                  size_t* bytes) {
+  if (int e = check_dims(n_cells, 1, L)) return e;
+  const r1s_layout lay = layout_or_default(layout);
+  if (int e = check_layout(lay)) return e;
+  if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
+  if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
+  GraphTables t;
+  if (int e = build_graph(n_cells, block_indptr, block_indices, &t)) return e;
+  Carver cv(nullptr);
+  r1s_mat_s tmp;
+  graph_layout(cv, make_mesh(n_cells, 1, L, lay, true, t.nbmax), flags, &tmp);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+static int check_graph_inputs(const r1s_graph_inputs* in, const Mesh& g, long long n_off) {
+  if (!in) return fail(R1S_ERR_ARG, "inputs is NULL");
+  const void* ps[12] = {in->s_diag, in->s_sub, in->s_sup, in->s_flow, in->s_band, in->s_lev_flow,
+                        in->s_flow_lev, in->s_nbr, in->u_diag, in->v_diag, in->u_off, in->v_off};
+  const char* names[12] = {"s_diag", "s_sub", "s_sup", "s_flow", "s_band", "s_lev_flow",
+                           "s_flow_lev", "s_nbr", "u_diag", "v_diag", "u_off", "v_off"};
+  const bool used[12] = {true, g.L > 1, g.L > 1, true, g.band > 1, g.arrow != 0, g.arrow != 0,
+                         n_off > 0, true, true, n_off > 0 && g.ro > 0, n_off > 0 && g.ro > 0};
+  for (int i = 0; i < 12; ++i) {
+    if (!used[i]) continue;
+    if (!ps[i]) return fail(R1S_ERR_ARG, "input %s is NULL", names[i]);
+    if (!aligned(ps[i], 8)) return fail(R1S_ERR_ARG, "input %s is not 8-byte aligned", names[i]);
+  }
+  return R1S_OK;
+}
+
+static int do_pack_graph(r1s_mat A, const r1s_graph_inputs* in, hipStream_t s) {
+  GraphPackIn p{in->s_diag, in->s_sub,  in->s_sup,  in->s_flow,  in->s_band, in->s_lev_flow,
+                in->s_flow_lev, in->s_nbr, in->u_diag, in->v_diag, in->u_off, in->v_off};
+  HIP_TRY(launch_pack_graph(A->g, p, A->rec64, A->rec32, s));
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_init_graph(int n_cells, int L, const r1s_layout* layout,
+                                  const int* block_indptr, const int* block_indices, int flags,
+                                  const r1s_graph_inputs* in, void* mem, size_t mem_bytes,
+                                  void* stream, r1s_mat* out) {
+  size_t need;
+  if (int e = r1s_mat_size_graph(n_cells, L, layout, block_indptr, block_indices, flags, &need))
+    return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  GraphTables t;
+  build_graph(n_cells, block_indptr, block_indices, &t);  // validated by the size call
+  Mesh g = make_mesh(n_cells, 1, L, layout_or_default(layout), true, t.nbmax);
+  if (int e = check_graph_inputs(in, g, t.n_off)) return e;
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need)
+    return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  r1s_mat A = new (std::nothrow) r1s_mat_s();
+  if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  A->flags = flags;
+  A->indptr.assign(block_indptr, block_indptr + n_cells + 1);
+  A->indices.assign(block_indices, block_indices + block_indptr[n_cells]);
+  Carver cv(mem);
+  graph_layout(cv, g, flags, A);
+  g.nbr = A->d_nbr;
+  g.tslot = A->d_tslot;
+  g.offb = A->d_offb;
+  A->g = g;
+  hipStream_t s = as_stream(stream);
+  int rc = R1S_OK;
+  do {
+    hipError_t e;
+    const size_t tb = t.nbr.size() * sizeof(int);
+    if (tb && (e = hipMemcpyAsync(A->d_nbr, t.nbr.data(), tb, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "copy: %s", hipGetErrorString(e)); break; }
+    if (tb && (e = hipMemcpyAsync(A->d_tslot, t.tslot.data(), tb, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "copy: %s", hipGetErrorString(e)); break; }
+    if ((e = hipMemcpyAsync(A->d_offb, t.offb.data(), t.offb.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "copy: %s", hipGetErrorString(e)); break; }
+    if ((rc = do_pack_graph(A, in, s))) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "pack: %s", hipGetErrorString(e)); break; }
+  } while (0);
+  if (rc) {
+    // the copies read the host tables: wait for them before they go away
+    (void)hipStreamSynchronize(s);
+    delete A;
+    return rc;
+  }
+  *out = A;
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_update_graph(r1s_mat A, const r1s_graph_inputs* in, void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (!A->g.graph) return fail(R1S_ERR_ARG, "structured-mesh matrix: use r1s_mat_update");
+  if (int e = check_graph_inputs(in, A->g, mat_blocks(A) - A->g.N)) return e;
+  if (int e = do_pack_graph(A, in, as_stream(stream))) return e;
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
   return R1S_OK;
 }
 
 extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
   const Mesh& g = A->g;
-  const long long B = n_blocks(g.nx, g.ny), N = g.N, m = g.m;
+  const long long B = mat_blocks(A), N = g.N, m = g.m;
   out->n_cells = N;
   out->n_blocks = B;
   out->m = m;
@@ -215,8 +391,10 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   out->structured_values = N * diag_block + (B - N) * m + 2 * pairs * m;
   out->structured_padded = N * (long long)g.F * g.mp;
   out->bsr_values = B * m * m;
-  out->index_bytes = 0;
-  out->matvec_bytes = 8 * out->structured_values + 8 * 2 * N * m;
+  // structured mesh: neighbours implicit; general mesh: the int32 slot
+  // tables (neighbour, reverse slot) and first off-block per cell
+  out->index_bytes = g.graph ? 4 * (2 * N * g.nbmax + N) : 0;
+  out->matvec_bytes = 8 * out->structured_values + 8 * 2 * N * m + out->index_bytes;
   // A0 factors (as many values as S_cc; with the wide pattern the band LU
   // factors, the coupling factors and the 3 x 3 Schur inverse), W and V,
   // C^{-1}; r read, z written
@@ -432,8 +610,8 @@ struct r1s_bsr_s {
   double* data;
 };
 
-static void bsr_layout(Carver& cv, const Mesh& g, r1s_bsr_s* B) {
-  B->nblocks = n_blocks(g.nx, g.ny);
+static void bsr_layout(Carver& cv, const Mesh& g, long long nblocks, r1s_bsr_s* B) {
+  B->nblocks = nblocks;
   B->data = cv.take<double>((size_t)B->nblocks * g.m * g.m);
   B->indptr = cv.take<int>(g.N + 1);
   B->indices = cv.take<int>(B->nblocks);
@@ -446,7 +624,7 @@ extern "C" int r1s_bsr_size(r1s_mat A, size_t* bytes) {
   if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
   Carver cv(nullptr);
   r1s_bsr_s tmp;
-  bsr_layout(cv, A->g, &tmp);
+  bsr_layout(cv, A->g, mat_blocks(A), &tmp);
   *bytes = cv.off;
   return R1S_OK;
 }
@@ -458,18 +636,29 @@ extern "C" int r1s_bsr_init(r1s_mat A, void* mem, size_t mem_bytes, void* stream
   if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
   if (mem_bytes < need) return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
   const Mesh& g = A->g;
-  if ((long long)n_blocks(g.nx, g.ny) * g.m * g.m > (1LL << 62))
-    return fail(R1S_ERR_UNSUPPORTED, "BSR too large");
+  if (mat_blocks(A) * g.m * g.m > (1LL << 62)) return fail(R1S_ERR_UNSUPPORTED, "BSR too large");
   r1s_bsr B = (r1s_bsr)calloc(1, sizeof(r1s_bsr_s));
   if (!B) return fail(R1S_ERR_ALLOC, "host allocation failed");
   B->g = g;
   Carver cv(mem);
-  bsr_layout(cv, g, B);
-  // block structure in BSR order: block rows by cell, columns ascending
+  bsr_layout(cv, g, mat_blocks(A), B);
+  // block structure in BSR order: block rows by cell; structured mesh:
+  // columns ascending (S, W, C, E, N); general mesh: the caller's order
   std::vector<int> indptr(g.N + 1), indices, row, dir, diag(g.N);
   indices.reserve(B->nblocks);
   for (int c = 0; c < g.N; ++c) {
     indptr[c] = (int)indices.size();
+    if (g.graph) {
+      int slot = 0;
+      for (int b = A->indptr[c]; b < A->indptr[c + 1]; ++b) {
+        const int j = A->indices[b];
+        if (j == c) diag[c] = (int)indices.size();
+        indices.push_back(j);
+        row.push_back(c);
+        dir.push_back(j == c ? D_C : GSLOT + slot++);
+      }
+      continue;
+    }
     const int iy = c / g.nx, ix = c % g.nx;
     const int nbs[5] = {iy > 0 ? c - g.nx : -1, ix > 0 ? c - 1 : -1, c,
                         ix < g.nx - 1 ? c + 1 : -1, iy < g.ny - 1 ? c + g.nx : -1};
@@ -944,6 +1133,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
 extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
                         const r1s_grads* out, void* stream) {
   if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
+  if (A->g.graph) return fail(R1S_ERR_ARG, "general-mesh matrix: use r1s_grad_graph");
   if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
   if (int e = check_vec(lambda, "lambda")) return e;
   if (int e = check_vec(x, "x")) return e;
@@ -959,5 +1149,29 @@ extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double*
   GradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v,
             out->s_band, out->s_lev_flow, out->s_flow_lev};
   HIP_TRY(launch_grad(A->g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
+  return R1S_OK;
+}
+
+extern "C" int r1s_grad_graph(r1s_mat A, int nrhs, const double* lambda, const double* x,
+                              const r1s_graph_grads* out, void* stream) {
+  if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
+  if (!A->g.graph) return fail(R1S_ERR_ARG, "structured-mesh matrix: use r1s_grad");
+  if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
+  if (int e = check_vec(lambda, "lambda")) return e;
+  if (int e = check_vec(x, "x")) return e;
+  const Mesh& g = A->g;
+  const long long n_off = mat_blocks(A) - g.N;
+  const void* ps[12] = {out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_band,
+                        out->s_lev_flow, out->s_flow_lev, out->s_nbr, out->u_diag, out->v_diag,
+                        out->u_off, out->v_off};
+  const bool used[12] = {true, g.L > 1, g.L > 1, true, g.band > 1, g.arrow != 0, g.arrow != 0,
+                         n_off > 0, true, true, n_off > 0 && g.ro > 0, n_off > 0 && g.ro > 0};
+  for (int i = 0; i < 12; ++i) {
+    if (!used[i]) continue;
+    if (int e = check_vec(ps[i], "gradient output")) return e;
+  }
+  GraphGradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_band, out->s_lev_flow,
+                 out->s_flow_lev, out->s_nbr, out->u_diag, out->v_diag, out->u_off, out->v_off};
+  HIP_TRY(launch_grad_graph(g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
   return R1S_OK;
 }

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
         s = rc[(g.fa + 3 + i - L) * mp + j];
       }
     } else if (i == j) {
-      s = rc[(F_NBR + nbr_slot(d)) * mp + i];
+      s = rc[nbr_row(g, d) * mp + i];
     }
     for (int p = 0; p < cnt; ++p) s += u[p * mp + i] * v[p * mp + j];
     out[e] = s;

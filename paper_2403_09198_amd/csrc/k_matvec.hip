@@ -120,63 +120,10 @@ __device__ inline Mesh kmesh(Mesh g) {
   if (EXACT) {
     g.rd = 1; g.ro = 1; g.P = 5; g.band = 1; g.arrow = 0;
     g.fb = F_BAND; g.fa = F_BAND; g.fu = F_BAND; g.F = F_BAND + 10;
+    g.graph = 0; g.nbmax = 4;
   }
   return g;
 }
-
-// ----------------------------------------- wide diagonal-block pattern ----
-// Terms of S_cc beyond the tridiagonal band and the 3x3 corner: the level
-// diagonals j = 2..band and the level/flow coupling.  Forward, lane k adds
-// row k; transposed, column k (the band entries of rows k -+ j).
-//
-// Coupling rows dotted with the cell's levels (a wave sum per flow unknown):
-// forward the flow rows S[L+i][.] (fa + 3 + i), transposed the flow columns
-// S[.][L+i] (fa + i).  Per-lane coupling rows times x_{L+i}: forward
-// S[k][L+i] (fa + i), transposed S[L+i][k] (fa + 3 + i).
-template <bool TRANS>
-__device__ inline int arrow_sum_row(const Mesh& g, int i) { return g.fa + (TRANS ? 0 : 3) + i; }
-template <bool TRANS>
-__device__ inline int arrow_lane_row(const Mesh& g, int i) { return g.fa + (TRANS ? 3 : 0) + i; }
-
-// Band coefficients of lane kk (clamped lane index) and the x indices they
-// multiply; invalid positions get a zero coefficient and a valid index.
-template <typename TV, bool TRANS>
-struct BandLane {
-  TV alo[BAND_MAX - 1], ahi[BAND_MAX - 1];
-  int ilo[BAND_MAX - 1], ihi[BAND_MAX - 1];
-
-  __device__ inline void load(const Mesh& g, const TV* rc, int kk) {
-    const long long mp = g.mp;
-    const int L = g.L, nbd = g.band - 1;
-#pragma unroll
-    for (int j = 2; j <= BAND_MAX; ++j) {
-      const int t = j - 2;
-      const bool on = j <= g.band;
-      const bool vlo = on && kk < L && kk >= j;  // x_{k-j}: S[k][k-j] or S[k-j][k]
-      const bool vhi = on && kk + j < L;         // x_{k+j}: S[k][k+j] or S[k+j][k]
-      ilo[t] = vlo ? kk - j : kk;
-      ihi[t] = vhi ? kk + j : kk;
-      TV a = TV(0), b = TV(0);
-      if (on) {
-        // forward: lower row j at k, upper row j at k; transposed: upper row
-        // j at k - j (entry S[k-j][k]), lower row j at k + j (S[k+j][k])
-        a = TRANS ? rc[(g.fb + nbd + t) * mp + ilo[t]] : rc[(g.fb + t) * mp + kk];
-        b = TRANS ? rc[(g.fb + t) * mp + ihi[t]] : rc[(g.fb + nbd + t) * mp + kk];
-      }
-      alo[t] = vlo ? a : TV(0);
-      ahi[t] = vhi ? b : TV(0);
-    }
-  }
-  __device__ inline TV apply(const Mesh& g, const double* xc) const {
-    TV s = TV(0);
-#pragma unroll
-    for (int t = 0; t < BAND_MAX - 1; ++t) {
-      if (t + 2 > g.band) break;
-      s += alo[t] * (TV)xc[ilo[t]] + ahi[t] * (TV)xc[ihi[t]];
-    }
-    return s;
-  }
-};
 
 // --------------------------------------------------------------- matvec ----
 // TV: value / accumulation type.  NCH = ceil(m / 64) chunks of 64 unknowns,
@@ -628,6 +575,7 @@ static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, con
 
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,
                          double* y, int nrhs, hipStream_t s) {
+  if (g.graph) return launch_matvec_graph(g, rec, f32, trans, x, nullptr, y, nrhs, false, s);
   if (f32) {
     const float* r = (const float*)rec;
     return trans ? launch_mv_t<float, true, false>(g, r, x, nullptr, y, nrhs, s)
@@ -640,6 +588,7 @@ hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, c
 
 hipError_t launch_residual(const Mesh& g, const double* rec, bool trans, const double* b,
                            const double* x, double* r, int nrhs, hipStream_t s) {
+  if (g.graph) return launch_matvec_graph(g, rec, false, trans, x, b, r, nrhs, true, s);
   return trans ? launch_mv_t<double, true, true>(g, rec, x, b, r, nrhs, s)
                : launch_mv_t<double, false, true>(g, rec, x, b, r, nrhs, s);
 }

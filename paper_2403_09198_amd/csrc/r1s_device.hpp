@@ -9,15 +9,19 @@
 //   row 1          lo    level k: S_cc[k][k-1]; flow row i: S_cc[L+i][L+(i+2)%3]
 //   row 2          hi    level k: S_cc[k][k+1]; flow row i: S_cc[L+i][L+(i+1)%3]
 //   rows 3..6      nbr   diagonal of S_{c,d}, d = S, W, E, N
+//                        (general mesh: rows 3..2+nbmax, one per neighbour slot)
 //   fb + j - 2     band  S_cc[k][k-j], j = 2..band (level rows only)
 //   fb + band-1 + j-2    S_cc[k][k+j]
 //   fa + i         S_cc[k][L+i] (level rows), i < 3, with level/flow coupling
 //   fa + 3 + i     S_cc[L+i][k] at index k (the flow row i over the levels)
 //   fu .. fu+P-1   u     the pairs of blocks S, W, C, E, N in that order
-//                        (ro pairs per neighbour block, rd for the diagonal)
+//                        (ro pairs per neighbour block, rd for the diagonal;
+//                        general mesh: the diagonal block's rd, then slot by
+//                        slot ro each)
 //   fu+P .. F-1    v     same order
-// fb = 7, fa = fb + 2 (band - 1), fu = fa + 6 arrow, F = fu + 2 P
-// (17 rows with one pair per block, band 1 and no coupling).
+// fb = 3 + nbmax (7 on the structured mesh), fa = fb + 2 (band - 1),
+// fu = fa + 6 arrow, F = fu + 2 P (17 rows with one pair per block, band 1
+// and no coupling).
 //
 // Padding elements and the rows of blocks that do not exist (mesh boundary)
 // are zero.
@@ -34,6 +38,8 @@ constexpr int WAVE = 64;
 constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
 constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_BAND = 7;
+// General mesh: neighbour slot s is addressed as direction GSLOT + s.
+constexpr int GSLOT = 5, GRAPH_NBR_MAX = 8;
 constexpr int D_S = 0, D_W = 1, D_C = 2, D_E = 3, D_N = 4;
 constexpr int MAX_CHUNKS = 4;  // m <= 256
 // Largest pair counts of the general-rank kernels (a diagonal block / a
@@ -64,15 +70,29 @@ struct Mesh {
   int band, arrow; // level-band half-width of S_cc; level/flow coupling
   int fb, fa, fu;  // first band row (j >= 2), first coupling row, first u row
   int F;           // record rows per cell, fu + 2 P
+  // general mesh (graph = 1): nbmax neighbour slots per cell; device tables
+  // [N][nbmax]: nbr = neighbour cell of each slot (-1: none), tslot = the
+  // slot of this cell in the neighbour's list; offb [N] = first off-diagonal
+  // block of each cell in input order
+  int graph, nbmax;
+  const int* nbr;
+  const int* tslot;
+  const int* offb;
 };
 
 // Band or coupling beyond the tridiagonal / uncoupled diagonal block.
 __host__ __device__ inline bool wide_pattern(const Mesh& g) { return g.band > 1 || g.arrow; }
 
-// First record slot and number of the pairs of block direction d.
+// First record slot and number of the pairs of block direction d (general
+// mesh: d = D_C or GSLOT + slot).
 __host__ __device__ inline int pair_count(const Mesh& g, int d) { return d == 2 ? g.rd : g.ro; }
 __host__ __device__ inline int pair_start(const Mesh& g, int d) {
+  if (g.graph) return d == D_C ? 0 : g.rd + (d - GSLOT) * g.ro;
   return d <= 1 ? d * g.ro : d == 2 ? 2 * g.ro : d == 3 ? 2 * g.ro + g.rd : 3 * g.ro + g.rd;
+}
+// Record row of the diagonal of the off-diagonal block of direction d.
+__host__ __device__ inline int nbr_row(const Mesh& g, int d) {
+  return F_NBR + (g.graph ? d - GSLOT : (d < 2 ? d : d - 1));
 }
 __host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * g.rd; }
 
@@ -377,6 +397,60 @@ struct CapInv {
       }
       z[i] = acc;
     }
+  }
+};
+
+// ----------------------------------------- wide diagonal-block pattern ----
+// Terms of S_cc beyond the tridiagonal band and the 3x3 corner: the level
+// diagonals j = 2..band and the level/flow coupling.  Forward, lane k adds
+// row k; transposed, column k (the band entries of rows k -+ j).
+//
+// Coupling rows dotted with the cell's levels (a wave sum per flow unknown):
+// forward the flow rows S[L+i][.] (fa + 3 + i), transposed the flow columns
+// S[.][L+i] (fa + i).  Per-lane coupling rows times x_{L+i}: forward
+// S[k][L+i] (fa + i), transposed S[L+i][k] (fa + 3 + i).
+template <bool TRANS>
+__device__ inline int arrow_sum_row(const Mesh& g, int i) { return g.fa + (TRANS ? 0 : 3) + i; }
+template <bool TRANS>
+__device__ inline int arrow_lane_row(const Mesh& g, int i) { return g.fa + (TRANS ? 3 : 0) + i; }
+
+// Band coefficients of lane kk (clamped lane index) and the x indices they
+// multiply; invalid positions get a zero coefficient and a valid index.
+template <typename TV, bool TRANS>
+struct BandLane {
+  TV alo[BAND_MAX - 1], ahi[BAND_MAX - 1];
+  int ilo[BAND_MAX - 1], ihi[BAND_MAX - 1];
+
+  __device__ inline void load(const Mesh& g, const TV* rc, int kk) {
+    const long long mp = g.mp;
+    const int L = g.L, nbd = g.band - 1;
+#pragma unroll
+    for (int j = 2; j <= BAND_MAX; ++j) {
+      const int t = j - 2;
+      const bool on = j <= g.band;
+      const bool vlo = on && kk < L && kk >= j;  // x_{k-j}: S[k][k-j] or S[k-j][k]
+      const bool vhi = on && kk + j < L;         // x_{k+j}: S[k][k+j] or S[k+j][k]
+      ilo[t] = vlo ? kk - j : kk;
+      ihi[t] = vhi ? kk + j : kk;
+      TV a = TV(0), b = TV(0);
+      if (on) {
+        // forward: lower row j at k, upper row j at k; transposed: upper row
+        // j at k - j (entry S[k-j][k]), lower row j at k + j (S[k+j][k])
+        a = TRANS ? rc[(g.fb + nbd + t) * mp + ilo[t]] : rc[(g.fb + t) * mp + kk];
+        b = TRANS ? rc[(g.fb + t) * mp + ihi[t]] : rc[(g.fb + nbd + t) * mp + kk];
+      }
+      alo[t] = vlo ? a : TV(0);
+      ahi[t] = vhi ? b : TV(0);
+    }
+  }
+  __device__ inline TV apply(const Mesh& g, const double* xc) const {
+    TV s = TV(0);
+#pragma unroll
+    for (int t = 0; t < BAND_MAX - 1; ++t) {
+      if (t + 2 > g.band) break;
+      s += alo[t] * (TV)xc[ilo[t]] + ahi[t] * (TV)xc[ihi[t]];
+    }
+    return s;
   }
 };
 

@@ -11,6 +11,18 @@ struct PackIn {
   const double *s_band, *s_lev_flow, *s_flow_lev;  // wide diagonal-block pattern only
 };
 
+// inputs on a general mesh (per cell: diagonal block; per off-diagonal block
+// in input order: its diagonal and pairs)
+struct GraphPackIn {
+  const double *s_diag, *s_sub, *s_sup, *s_flow, *s_band, *s_lev_flow, *s_flow_lev;
+  const double *s_nbr, *u_diag, *v_diag, *u_off, *v_off;
+};
+
+struct GraphGradOut {
+  double *s_diag, *s_sub, *s_sup, *s_flow, *s_band, *s_lev_flow, *s_flow_lev;
+  double *s_nbr, *u_diag, *v_diag, *u_off, *v_off;
+};
+
 struct GradOut {
   double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
   double *s_band, *s_lev_flow, *s_flow_lev;
@@ -22,6 +34,15 @@ bool ranks_supported(int rd, int ro);
 // packing / casting
 hipError_t launch_pack(const Mesh& g, const PackIn& in, double* rec64, float* rec32, hipStream_t s);
 hipError_t launch_cast_f32(const double* src, float* dst, long long count, hipStream_t s);
+
+// general mesh: packing, matvec / residual, gradients
+hipError_t launch_pack_graph(const Mesh& g, const GraphPackIn& in, double* rec64, float* rec32,
+                             hipStream_t s);
+hipError_t launch_matvec_graph(const Mesh& g, const void* rec, bool f32, bool trans,
+                               const double* x, const double* b, double* y, int nrhs, bool resid,
+                               hipStream_t s);
+hipError_t launch_grad_graph(const Mesh& g, const double* rec, const double* lam, const double* x,
+                             int nrhs, const GraphGradOut& out, hipStream_t s);
 
 // structured matvec (rec: packed record, float when f32)
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,

@@ -106,6 +106,77 @@ def r1s_mat_update(h, values, nx, ny, Lv, lay, stream=None):
     check(lib().r1s_mat_update(h, C.byref(ins), _stream(stream)))
 
 
+def _host_i32(a):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _graph_shapes(N, n_off, Lv, lay):
+    m = Lv + 3
+    return {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
+            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, 3, Lv),
+            "s_flow_lev": (N, 3, Lv), "s_nbr": (n_off, m), "u_diag": (N, lay.r_diag, m),
+            "v_diag": (N, lay.r_diag, m), "u_off": (n_off, lay.r_off, m),
+            "v_off": (n_off, lay.r_off, m)}
+
+
+def _graph_used(lay, L_levels, n_off):
+    used = ["s_diag", "s_flow", "u_diag", "v_diag"]
+    if L_levels > 1:
+        used += ["s_sub", "s_sup"]
+    if lay.band > 1:
+        used += ["s_band"]
+    if lay.arrow:
+        used += ["s_lev_flow", "s_flow_lev"]
+    if n_off > 0:
+        used += ["s_nbr"] + (["u_off", "v_off"] if lay.r_off > 0 else [])
+    return used
+
+
+def _graph_inputs(values, N, n_off, Lv, lay):
+    shapes = _graph_shapes(N, n_off, Lv, lay)
+    ins = L.GraphInputs()
+    for k in _graph_used(lay, Lv, n_off):
+        t = values[k]
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+            raise TypeError(f"{k} must be a float64 CUDA tensor")
+        if tuple(t.shape) != shapes[k] or not t.is_contiguous():
+            raise ValueError(f"{k} must be contiguous with shape {shapes[k]}")
+        setattr(ins, k, _ptr(t).value)
+    return ins
+
+
+def r1s_mat_size_graph(n_cells, Lv, lay, indptr, indices, flags=0) -> int:
+    b = C.c_size_t()
+    ip, pip = _host_i32(indptr)
+    ix, pix = _host_i32(indices)
+    check(lib().r1s_mat_size_graph(n_cells, Lv, C.byref(lay), pip, pix, flags, C.byref(b)))
+    return b.value
+
+
+def r1s_mat_init_graph(n_cells, Lv, lay, indptr, indices, flags, values, mem, stream=None):
+    h = C.c_void_p()
+    ip, pip = _host_i32(indptr)
+    ix, pix = _host_i32(indices)
+    ins = _graph_inputs(values, n_cells, len(ix) - n_cells, Lv, lay)
+    check(lib().r1s_mat_init_graph(n_cells, Lv, C.byref(lay), pip, pix, flags, C.byref(ins),
+                                   _ptr(mem), mem.numel(), _stream(stream), C.byref(h)))
+    return h
+
+
+def r1s_mat_update_graph(h, values, n_cells, n_off, Lv, lay, stream=None):
+    ins = _graph_inputs(values, n_cells, n_off, Lv, lay)
+    check(lib().r1s_mat_update_graph(h, C.byref(ins), _stream(stream)))
+
+
+def r1s_grad_graph(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
+    g = L.GraphGrads()
+    for k in out:
+        setattr(g, k, _ptr(out[k]).value)
+    check(lib().r1s_grad_graph(h, nrhs, _ptr(lam), _ptr(x), C.byref(g), _stream(stream)))
+
+
 def r1s_mat_storage(h) -> dict:
     s = L.Storage()
     check(lib().r1s_mat_storage(h, C.byref(s)))
@@ -239,6 +310,37 @@ class R1Matrix:
         return r
 
 
+class R1GraphMatrix(R1Matrix):
+    """The block r1-sparse Jacobian on a general mesh: block structure from
+    BR1-BSR style index arrays (block_indptr, block_indices; host arrays),
+    values in the general-mesh layout (see gen.make_graph_problem)."""
+
+    def __init__(self, indptr, indices, L_levels, values: Dict[str, torch.Tensor],
+                 keep_f32=False, stream=None, ranks=(1, 1), band=1, arrow=False):
+        import numpy as np
+        self.indptr = np.asarray(indptr, dtype=np.int32)
+        self.indices = np.asarray(indices, dtype=np.int32)
+        N = len(self.indptr) - 1
+        self.nx, self.ny, self.L = N, 1, L_levels
+        self.m = L_levels + 3
+        self.N = N
+        self.n = N * self.m
+        self.n_off = len(self.indices) - N
+        self.r_diag, self.r_off = (int(r) for r in ranks)
+        self.band, self.arrow = int(band), bool(arrow)
+        self.layout = layout(self.r_diag, self.r_off, self.band, self.arrow)
+        self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
+        dev = values["s_diag"].device
+        self.device = dev
+        self.mem = _buffer(r1s_mat_size_graph(N, L_levels, self.layout, self.indptr, self.indices,
+                                              self.flags), dev)
+        self.h = r1s_mat_init_graph(N, L_levels, self.layout, self.indptr, self.indices,
+                                    self.flags, values, self.mem, stream)
+
+    def update(self, values, stream=None):
+        r1s_mat_update_graph(self.h, values, self.N, self.n_off, self.L, self.layout, stream)
+
+
 class SMWPreconditioner:
     """Block-Jacobi through the Sherman-Morrison-Woodbury identity."""
 
@@ -343,6 +445,12 @@ def grad(A: R1Matrix, lam, x, stream=None) -> Dict[str, torch.Tensor]:
     """Gradients w.r.t. the structured arrays given lambda = J^{-T} dLoss/dx."""
     nrhs = _need_vec(lam, "lambda", A.n)
     _need_vec(x, "x", A.n)
+    if isinstance(A, R1GraphMatrix):
+        shapes = _graph_shapes(A.N, A.n_off, A.L, A.layout)
+        out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device)
+               for k in _graph_used(A.layout, A.L, A.n_off)}
+        r1s_grad_graph(A.h, nrhs, lam, x, out, stream)
+        return out
     shapes = _shapes(A.nx, A.ny, A.L, A.layout)
     out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device)
            for k in _used_fields(A.layout)}

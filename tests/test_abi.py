@@ -155,3 +155,44 @@ def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         L.lib()
+
+
+def _graph_size(indptr, indices, lay=None):
+    lib = L.lib()
+    b = C.c_size_t()
+    ip = (C.c_int * len(indptr))(*indptr)
+    ix = (C.c_int * len(indices))(*indices)
+    rc = lib.r1s_mat_size_graph(len(indptr) - 1, 4, lay, ip, ix, 0, C.byref(b))
+    return rc, lib.r1s_last_error().decode(), b.value
+
+
+def test_general_mesh_structure_is_validated():
+    # two cells joined by a face: fine
+    assert _graph_size([0, 2, 4], [0, 1, 1, 0])[0] == L.R1S_OK
+    # missing diagonal, diagonal twice, out of range, duplicate, unsymmetric
+    assert _graph_size([0, 1, 3], [1, 1, 0])[0] == L.R1S_ERR_ARG
+    rc, msg, _ = _graph_size([0, 2, 3], [0, 0, 1])
+    assert rc == L.R1S_ERR_ARG and "twice" in msg
+    assert _graph_size([0, 2, 4], [0, 5, 1, 0])[0] == L.R1S_ERR_ARG
+    rc, msg, _ = _graph_size([0, 2, 3], [0, 1, 1])
+    assert rc == L.R1S_ERR_ARG and "transposed partner" in msg
+    assert _graph_size([1, 2, 4], [0, 1, 1, 0])[0] == L.R1S_ERR_ARG
+    # a star: cell 0 has 9 neighbours (more than 8)
+    n = 10
+    ix = list(range(n))       # row 0: itself and cells 1..9
+    ip = [0, n]
+    for c in range(1, n):
+        ix += [0, c]          # row c: cell 0 and itself
+        ip.append(ip[-1] + 2)
+    assert _graph_size(ip, ix)[0] == L.R1S_ERR_UNSUPPORTED
+
+
+def test_general_mesh_size_matches_structured_record():
+    # a 4 x 3 structured mesh as a graph: the same record plus int32 tables
+    from paper_2403_09198_amd import gen
+    ip, ix = gen.structured_graph(4, 3)
+    rc, _, gb = _graph_size(list(ip), list(ix), _lay(1, 1))
+    assert rc == L.R1S_OK
+    b = C.c_size_t()
+    assert L.lib().r1s_mat_size(4, 3, 4, _lay(1, 1), 0, C.byref(b)) == L.R1S_OK
+    assert gb > b.value and gb - b.value <= 3 * 256 + 4 * (2 * 12 * 4 + 12)
