@@ -249,6 +249,42 @@ def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False
     return row
 
 
+def mesh_pair(torch, n_points, L, ranks, steps, warm, shuffle=True, seed=0):
+    """The float64 pair on a general mesh: a Delaunay triangulation of
+    n_points random points (every triangle a cell, at most 3 neighbours),
+    cell numbering shuffled unless shuffle is False."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    ip, ix = gen.delaunay_graph(n_points, seed=seed, shuffle=shuffle)
+    N = len(ip) - 1
+    log(f"mesh pair: delaunay {N} cells L={L} ranks {ranks} shuffle={shuffle}")
+    p = gen.make_graph_problem(ip, ix, L, seed=seed, r_diag=ranks[0], r_off=ranks[1])
+    vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.GRAPH_FIELDS}
+    del p
+    A = r1s.R1GraphMatrix(ip, ix, L, vals, keep_f32=True, ranks=ranks)
+    del vals
+    M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
+    st = A.storage()
+    mv, ap = st["matvec_bytes"], st["smw_apply_bytes"]
+    x = torch.from_numpy(np.random.default_rng(0).standard_normal((1, N, L + 3))).to(dev)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    row = {"cells": N, "blocks": int(st["n_blocks"]), "L": L, "r_diag": ranks[0],
+           "r_off": ranks[1], "shuffled": shuffle, "index_bytes": int(st["index_bytes"])}
+    for tag, f1, f2 in (("f64", lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z)),
+                        ("adjoint", lambda: A.matvec(x, out=y, trans=True),
+                         lambda: M.apply(y, out=z, trans=True))):
+        wall, k1, k2 = measure_pair(torch, f1, f2, steps, warm)
+        row[tag] = {"gbs": round((mv + ap) / (wall / steps) / 1e9, 1),
+                    "us_per_step": round(wall / steps * 1e6, 2),
+                    "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
+                    "matvec_gbs": round(mv / (k1 / 1e3) / 1e9, 1)}
+    del A, M, x, y, z
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return row
+
+
 def sweep(torch, levels=(32, 61, 120, 200), steps=50, warm=5):
     """Level sweep on the 512 x 256 mesh: structured pairs (float64, float32,
     adjoint) against the dense-block BSR pair.  BSR storage grows as m^2, so
@@ -612,6 +648,12 @@ def main():
         # level/flow coupling (banded-LU block-Jacobi, one lane per cell)
         out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
                                               band=4, arrow=True)
+        # general mesh: about 32 800 triangle cells (Delaunay of 16 400 random
+        # points), the same L, one pair per block; shuffled and mesh-ordered
+        # cell numbering
+        out["general_mesh_pair"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm)
+        out["general_mesh_pair_ordered"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm,
+                                                     shuffle=False)
         # full GMRES(50) solve to 1e-10 (float64) and the mixed-precision solve
         b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
         for mode in ("f64", "mixed"):

@@ -209,12 +209,130 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_graph(Mesh g, const TV* __r
   }
 }
 
+
+// Single-chunk form (m <= 64) for meshes with at most NBM <= 4 neighbours
+// per cell and the plain diagonal-block pattern: like the structured kernel,
+// every load of the wave is issued before the first reduction.  Slots past
+// a cell's degree read the cell's own record (valid addresses) and are
+// masked out of the sums.
+template <typename TV, bool TRANS, bool RESID, int NBM, int RDM, int ROM>
+__global__ __launch_bounds__(64 * WPB) void k_matvec_graph1(Mesh g, const TV* __restrict__ rec,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ y, int r) {
+  constexpr bool EXACT = RDM == 1 && ROM == 1;
+  const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + (threadIdx.x >> 6)));
+  if (c >= g.N) return;
+  const int lane = lane_id();
+  const int m = g.m, L = g.L;
+  const int rd = EXACT ? 1 : g.rd, ro = EXACT ? 1 : g.ro, P = rd + g.nbmax * ro;
+  const long long mp = g.mp, RS = (long long)g.F * mp;
+  const TV* rc = rec + (long long)c * RS;
+  const double* xr = x + (long long)r * g.n;
+  const int kk = lane < m ? lane : m - 1;
+  const bool in = lane < m;
+
+  bool ex[NBM];
+  int nbc[NBM];
+  const TV* base[NBM];
+  int coef0[NBM], out0[NBM], nrow[NBM];
+#pragma unroll
+  for (int s = 0; s < NBM; ++s) {
+    const int nb = s < g.nbmax ? g.nbr[(long long)c * g.nbmax + s] : -1;
+    ex[s] = nb >= 0;
+    nbc[s] = ex[s] ? nb : c;
+    const int t = (TRANS && ex[s]) ? g.tslot[(long long)c * g.nbmax + s]
+                                   : (s < g.nbmax ? s : g.nbmax - 1);
+    base[s] = (TRANS && ex[s]) ? rec + (long long)nb * RS : rc;
+    coef0[s] = g.fu + (TRANS ? 0 : P) + rd + t * ro;
+    out0[s] = g.fu + (TRANS ? P : 0) + rd + t * ro;
+    nrow[s] = F_NBR + t;
+  }
+  const int dcoef0 = g.fu + (TRANS ? 0 : P), dout0 = g.fu + (TRANS ? P : 0);
+
+  // every load first
+  TV pd[RDM], ud[RDM], ps[NBM][ROM], us[NBM][ROM], xn[NBM], nv[NBM];
+#pragma unroll
+  for (int p = 0; p < RDM; ++p) {
+    pd[p] = p < rd ? ld_stream(rc + (dcoef0 + p) * mp + kk) : TV(0);
+    ud[p] = p < rd ? ld_stream(rc + (dout0 + p) * mp + kk) : TV(0);
+  }
+#pragma unroll
+  for (int s = 0; s < NBM; ++s) {
+    xn[s] = (TV)xr[(long long)nbc[s] * m + kk];
+    nv[s] = ld_stream(base[s] + nrow[s] * mp + kk);
+#pragma unroll
+    for (int p = 0; p < ROM; ++p) {
+      ps[s][p] = p < ro ? ld_stream(base[s] + (coef0[s] + p) * mp + kk) : TV(0);
+      us[s][p] = p < ro ? ld_stream(base[s] + (out0[s] + p) * mp + kk) : TV(0);
+    }
+  }
+  int pa, pb;
+  bool va, vb;
+  if (kk < L) {
+    va = kk >= 1; pa = va ? kk - 1 : kk;
+    vb = kk <= L - 2; pb = vb ? kk + 1 : kk;
+  } else {
+    const int i = kk - L;
+    pa = L + (i + 2) % 3; va = true;
+    pb = L + (i + 1) % 3; vb = true;
+  }
+  const double* xc = xr + (long long)c * m;
+  const TV xk = (TV)xc[kk], xa = (TV)xc[pa], xb = (TV)xc[pb];
+  const TV dg = ld_stream(rc + F_DIAG * mp + kk);
+  TV ca, cb;
+  if (!TRANS) {
+    ca = ld_stream(rc + F_LO * mp + kk);
+    cb = ld_stream(rc + F_HI * mp + kk);
+  } else {
+    const TV ta = rc[F_HI * mp + pa];
+    const TV tb = rc[F_LO * mp + pb];
+    ca = va ? ta : TV(0);
+    cb = vb ? tb : TV(0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  TV t = dg * xk + ca * xa + cb * xb;
+#pragma unroll
+  for (int p = 0; p < RDM; ++p) {
+    const TV a = wave_sum_u(in ? pd[p] * xk : TV(0));
+    t += ud[p] * a;
+  }
+#pragma unroll
+  for (int s = 0; s < NBM; ++s) {
+    if (ex[s]) t += nv[s] * xn[s];
+#pragma unroll
+    for (int p = 0; p < ROM; ++p) {
+      const TV a = wave_sum_u(in ? ps[s][p] * xn[s] : TV(0));
+      t += us[s][p] * (ex[s] ? a : TV(0));
+    }
+  }
+  const long long o = (long long)r * g.n + (long long)c * m + kk;
+  y[o] = RESID ? b[o] - (double)t : (double)t;
+}
+
+template <typename TV, bool TRANS, bool RESID, int NBM>
+static void launch_graph1(const Mesh& g, const TV* rec, const double* x, const double* b,
+                          double* y, int r, hipStream_t s) {
+  const dim3 grid((g.N + WPB - 1) / WPB), block(64 * WPB);
+  if (g.rd == 1 && g.ro == 1)
+    hipLaunchKernelGGL((k_matvec_graph1<TV, TRANS, RESID, NBM, 1, 1>), grid, block, 0, s, g, rec, x, b, y, r);
+  else
+    hipLaunchKernelGGL((k_matvec_graph1<TV, TRANS, RESID, NBM, RANK_DIAG_MAX, RANK_OFF_MAX>), grid,
+                       block, 0, s, g, rec, x, b, y, r);
+}
+
 template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_graph_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                                  double* y, int nrhs, hipStream_t s) {
   const dim3 grid((g.N + WPB - 1) / WPB), block(64 * WPB);
+  const bool fast = !wide_pattern(g) && g.m <= WAVE && g.nbmax >= 1 && g.nbmax <= 4;
   for (int r = 0; r < nrhs; ++r) {
-    if (wide_pattern(g))
+    if (fast && g.nbmax <= 3)
+      launch_graph1<TV, TRANS, RESID, 3>(g, rec, x, b, y, r, s);
+    else if (fast)
+      launch_graph1<TV, TRANS, RESID, 4>(g, rec, x, b, y, r, s);
+    else if (wide_pattern(g))
       hipLaunchKernelGGL((k_matvec_graph<TV, TRANS, RESID, true>), grid, block, 0, s, g, rec, x, b, y, r);
     else
       hipLaunchKernelGGL((k_matvec_graph<TV, TRANS, RESID, false>), grid, block, 0, s, g, rec, x, b, y, r);
