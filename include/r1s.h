@@ -14,7 +14,9 @@
  * Every diagonal block carries r_diag pairs and every neighbour block r_off
  * (section 4, Overall Structure: 9 and 2 for the state-to-state model, one
  * temporal-source pair plus two per trace flux; 1 and 1 is the smallest
- * layout).  Supported: 1 <= r_diag <= 9, 0 <= r_off <= 2.
+ * layout).  Supported: 1 <= r_diag <= 9, 0 <= r_off <= 6 (an HLL flux
+ * Jacobian in primitive variables puts the non-diagonal sparse entries of a
+ * neighbour block into four more exact pairs: 2 + 4 = 6).
  *
  * The sparse diagonal block S_{c,C} has a level band of half-width `band`
  * (section 4, Temporal Source Jacobian: level-changing processes up to a
@@ -115,7 +117,7 @@ typedef struct r1s_bsr_s* r1s_bsr;   /* dense-block BSR copy of a Jacobian */
 /* Block structure of the Jacobian (see the layout above). */
 typedef struct {
   int r_diag; /* rank-one pairs per diagonal block, 1..9          */
-  int r_off;  /* rank-one pairs per neighbour block, 0..2         */
+  int r_off;  /* rank-one pairs per neighbour block, 0..6         */
   int band;   /* level-band half-width of S_{c,C}, 1..R1S_MAX_BAND */
   int arrow;  /* 1: level rows x flow columns, flow rows x levels  */
 } r1s_layout;
@@ -235,7 +237,7 @@ const char* r1s_last_error(void);
  * coupling).  flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG
  * for nx, ny, L < 1, r_diag < 1, r_off < 0, band < 1, arrow not 0/1, or a
  * NULL `bytes`; R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M, r_diag > 9,
- * r_off > 2 or band > R1S_MAX_BAND. */
+ * r_off > 6 or band > R1S_MAX_BAND. */
 int r1s_mat_size(int nx, int ny, int L, const r1s_layout* layout, int flags,
                  size_t* bytes);
 

@@ -12,10 +12,11 @@
 //
 // Pair counts: a diagonal block has g.rd pairs, a neighbour block g.ro.  The
 // kernels are compiled for maxima RDM / ROM: <1, 1> is the one-pair-per-block
-// layout (counts fixed at compile time), <9, 2> takes any rd <= 9, ro <= 2
-// with the counts as wave-uniform guards.
-#include "r1s_device.hpp"
-#include "r1s_kernels.hpp"
+// layout (counts fixed at compile time), <9, 2> and <9, 6> take any rd <= 9
+// and ro <= 2 or ro <= 6 with the counts as wave-uniform guards.
+#include <type_traits>
+
+#include "k_matvec_impl.hpp"
 
 namespace r1s {
 
@@ -87,373 +88,6 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ src, TO* __
     dst[i] = (TO)src[i];
 }
 
-// ------------------------------------------------ per-cell row pointers ----
-// The rows a cell's output depends on, per block direction d.  Forward: the
-// cell's own record (v rows give the coefficients, u rows the output).
-// Transpose: block (nb, opposite d) of the neighbour's record (its u rows give
-// the coefficients, its v rows the output; its diagonal is symmetric).
-template <typename TV, bool TRANS>
-struct CellRows {
-  const TV* rc;          // own record
-  const TV* base[5];     // record holding the block of direction d
-  int coef0[5], out0[5]; // first coefficient row, first output row
-  int nbr[5];            // neighbour-diagonal row
-
-  __device__ inline void init(const Mesh& g, const TV* rec, int c, const int (&nbc)[5]) {
-    const long long RS = (long long)g.F * g.mp;
-    rc = rec + (long long)c * RS;
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      const int bd = TRANS ? opposite(d) : d;
-      base[d] = TRANS ? rec + (long long)nbc[d] * RS : rc;
-      coef0[d] = g.fu + (TRANS ? 0 : g.P) + pair_start(g, bd);
-      out0[d] = g.fu + (TRANS ? g.P : 0) + pair_start(g, bd);
-      nbr[d] = F_NBR + nbr_slot(bd == D_C ? 0 : bd);
-    }
-  }
-};
-
-// Kernel-side mesh: with one pair per block, band 1 and no coupling (EXACT)
-// the counts become compile-time constants and all row offsets fold.
-template <bool EXACT>
-__device__ inline Mesh kmesh(Mesh g) {
-  if (EXACT) {
-    g.rd = 1; g.ro = 1; g.P = 5; g.band = 1; g.arrow = 0;
-    g.fb = F_BAND; g.fa = F_BAND; g.fu = F_BAND; g.F = F_BAND + 10;
-    g.graph = 0; g.nbmax = 4;
-  }
-  return g;
-}
-
-// --------------------------------------------------------------- matvec ----
-// TV: value / accumulation type.  NCH = ceil(m / 64) chunks of 64 unknowns,
-// NR right-hand sides per launch starting at rhs r0.  RESID: write b - J x.
-//
-// Every load of a wave is independent of the reductions, so all of them are
-// issued before the first wait: missing neighbours (mesh boundary) read the
-// cell's own, valid addresses and are masked out of the sums instead of
-// being skipped by a branch.  Lanes past m read element m-1 and are masked.
-// Pair slots past a block's count are skipped by wave-uniform guards.
-// WIDE: the diagonal block has further band diagonals or level/flow coupling.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
-__global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
-                                                     const double* __restrict__ x,
-                                                     const double* __restrict__ b,
-                                                     double* __restrict__ y, int r0) {
-  constexpr bool EXACT = RDM == 1 && ROM == 1;
-  constexpr int RM = RDM > ROM ? RDM : ROM;
-  constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
-  const Mesh g = kmesh<EXACT>(g_);
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
-  if (c >= g.N) return;
-  const int lane = lane_id();
-  const int m = g.m, L = g.L;
-  const long long mp = g.mp;
-  int nb[5], nbc[5], cnt[5];
-  bool ex[5];
-  neighbours(g, c, nb);
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    ex[d] = nb[d] >= 0;
-    nbc[d] = ex[d] ? nb[d] : c;
-    cnt[d] = pair_count(g, d);
-  }
-  CellRows<TV, TRANS> R;
-  R.init(g, rec, c, nbc);
-  const double* xr = x + (long long)r0 * g.n;
-
-  TV pv[5][RM][NCH], xv[NR][5][NCH];
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    const int k = ch * WAVE + lane;
-    const int kk = k < m ? k : m - 1;
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-        pv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        xv[r][d][ch] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
-    }
-  }
-
-  // sparse part of the row: diagonal, level band / flow corner partners,
-  // neighbour diagonals, and the output rows of the pairs
-  TV dg[NCH], ca[NCH], cb[NCH], nv[5][NCH], uv[5][RM][NCH], xa[NR][NCH], xb[NR][NCH];
-  auto load_sparse = [&](int ch) {
-    const int k = ch * WAVE + lane;
-    const int kk = k < m ? k : m - 1;
-    int pa, pb;
-    bool va, vb;
-    if (kk < L) {
-      va = kk >= 1; pa = va ? kk - 1 : kk;
-      vb = kk <= L - 2; pb = vb ? kk + 1 : kk;
-    } else {
-      const int i = kk - L;
-      pa = L + (i + 2) % 3; va = true;
-      pb = L + (i + 1) % 3; vb = true;
-    }
-    dg[ch] = ld_stream(R.rc + F_DIAG * mp + kk);
-    if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
-      ca[ch] = ld_stream(R.rc + F_LO * mp + kk);
-      cb[ch] = ld_stream(R.rc + F_HI * mp + kk);
-    } else {       // column k of S_cc: hi of row pa, lo of row pb
-      const TV ta = R.rc[F_HI * mp + pa];
-      const TV tb = R.rc[F_LO * mp + pb];
-      ca[ch] = va ? ta : TV(0);
-      cb[ch] = vb ? tb : TV(0);
-    }
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      if (d != D_C) nv[d][ch] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-        uv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
-      xa[r][ch] = (TV)xv_c[pa];
-      xb[r][ch] = (TV)xv_c[pb];
-    }
-  };
-  if (PRELOAD) {
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) load_sparse(ch);
-    // keep these loads in flight during the reductions (one memory round
-    // trip per wave instead of two)
-    __builtin_amdgcn_sched_barrier(0);
-  }
-
-  // pair coefficients: forward v_p . x_nb, transpose u_p(nb, opp d) . x_nb
-  TV acc[NR][5][RM];
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int d = 0; d < 5; ++d)
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-        TV s = TV(0);
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-          if (ch * WAVE + lane < m) s += pv[d][p][ch] * xv[r][d][ch];
-        s = wave_sum_u(s);
-        acc[r][d][p] = ex[d] ? s : TV(0);
-      }
-  // coupling sums of the flow unknowns over the cell's levels
-  TV asum[NR][3];
-  if constexpr (WIDE) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) asum[r][i] = TV(0);
-    if (g.arrow) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        TV ar[NCH];
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          const int k = ch * WAVE + lane;
-          ar[ch] = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + (k < m ? k : m - 1)] : TV(0);
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          TV t = TV(0);
-#pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) t += ar[ch] * xv[r][D_C][ch];
-          asum[r][i] = wave_sum_u(t);
-        }
-      }
-    }
-  }
-
-  // Lanes past m computed exactly what lane m-1 computes (all their indices
-  // are clamped), so every lane stores to its clamped index: duplicate lanes
-  // write identical values and no branch is needed around the stores.
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch) {
-    if (!PRELOAD) load_sparse(ch);
-    const int k = ch * WAVE + lane;
-    const int kk = k < m ? k : m - 1;
-    BandLane<TV, TRANS> bl;
-    TV al[3] = {TV(0), TV(0), TV(0)};
-    if constexpr (WIDE) {
-      bl.load(g, R.rc, kk);
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        al[i] = g.arrow ? R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk] : TV(0);
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      TV t = dg[ch] * xv[r][D_C][ch] + ca[ch] * xa[r][ch] + cb[ch] * xb[r][ch];
-#pragma unroll
-      for (int d = 0; d < 5; ++d) {
-        if (d != D_C && ex[d]) t += nv[d][ch] * xv[r][d][ch];
-#pragma unroll
-        for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) t += uv[d][p][ch] * acc[r][d][p];
-      }
-      if constexpr (WIDE) {
-        const double* xc = xr + (long long)r * g.n + (long long)c * m;
-        t += bl.apply(g, xc);
-        if (g.arrow) {
-          // level lanes: coupling entries times the flow unknowns; flow lane
-          // L + i: the coupling sum
-#pragma unroll
-          for (int i = 0; i < 3; ++i) t += al[i] * (TV)xc[L + i];
-          const int fi = kk - L;
-          t += fi == 0 ? asum[r][0] : fi == 1 ? asum[r][1] : fi == 2 ? asum[r][2] : TV(0);
-        }
-      }
-      const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-      y[o] = RESID ? b[o] - (double)t : (double)t;
-    }
-  }
-}
-
-// Workgroup-per-cell form for m > 64: wave w of the workgroup owns unknowns
-// 64w .. 64w+63 of one cell, issues all of its loads at once (like the
-// single-chunk kernel), and the pair coefficients are summed over the waves
-// through LDS in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
-__global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __restrict__ rec,
-                                                        const double* __restrict__ x,
-                                                        const double* __restrict__ b,
-                                                        double* __restrict__ y, int r0) {
-  constexpr bool EXACT = RDM == 1 && ROM == 1;
-  constexpr int RM = RDM > ROM ? RDM : ROM;
-  __shared__ TV part[NR][5][RM][NCH];
-  __shared__ TV apart[WIDE ? NR : 1][3][NCH];
-  const Mesh g = kmesh<EXACT>(g_);
-  const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
-  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = lane_id();
-  const int m = g.m, L = g.L;
-  const long long mp = g.mp;
-  int nb[5], nbc[5], cnt[5];
-  bool ex[5];
-  neighbours(g, c, nb);
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    ex[d] = nb[d] >= 0;
-    nbc[d] = ex[d] ? nb[d] : c;
-    cnt[d] = pair_count(g, d);
-  }
-  CellRows<TV, TRANS> R;
-  R.init(g, rec, c, nbc);
-  const double* xr = x + (long long)r0 * g.n;
-  const int k = wv * WAVE + lane;
-  const int kk = k < m ? k : m - 1;
-
-  TV pv[5][RM], xv[NR][5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-#pragma unroll
-    for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-      pv[d][p] = p < cnt[d] ? ld_stream(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) xv[r][d] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
-  }
-  int pa, pb;
-  bool va, vb;
-  if (kk < L) {
-    va = kk >= 1; pa = va ? kk - 1 : kk;
-    vb = kk <= L - 2; pb = vb ? kk + 1 : kk;
-  } else {
-    const int i = kk - L;
-    pa = L + (i + 2) % 3; va = true;
-    pb = L + (i + 1) % 3; vb = true;
-  }
-  const TV dg = ld_stream(R.rc + F_DIAG * mp + kk);
-  TV ca, cb;
-  if (!TRANS) {
-    ca = ld_stream(R.rc + F_LO * mp + kk);
-    cb = ld_stream(R.rc + F_HI * mp + kk);
-  } else {
-    const TV ta = R.rc[F_HI * mp + pa];
-    const TV tb = R.rc[F_LO * mp + pb];
-    ca = va ? ta : TV(0);
-    cb = vb ? tb : TV(0);
-  }
-  TV nv[5], uv[5][RM], xa[NR], xb[NR];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    if (d != D_C) nv[d] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
-#pragma unroll
-    for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-      uv[d][p] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
-    xa[r] = (TV)xv_c[pa];
-    xb[r] = (TV)xv_c[pb];
-  }
-  __builtin_amdgcn_sched_barrier(0);
-
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-#pragma unroll
-    for (int d = 0; d < 5; ++d)
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-        const TV s = wave_sum_u(k < m ? pv[d][p] * xv[r][d] : TV(0));
-        if (lane == 0) part[r][d][p][wv] = s;
-      }
-  // wide pattern: this chunk's share of the coupling sums, band terms
-  BandLane<TV, TRANS> bl;
-  TV al[3] = {TV(0), TV(0), TV(0)};
-  if constexpr (WIDE) {
-    if (g.arrow) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const TV ar = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + kk] : TV(0);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const TV s = wave_sum_u(ar * xv[r][D_C]);
-          if (lane == 0) apart[r][i][wv] = s;
-        }
-        al[i] = R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk];
-      }
-    }
-    bl.load(g, R.rc, kk);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    TV t = dg * xv[r][D_C] + ca * xa[r] + cb * xb[r];
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      if (d != D_C && ex[d]) t += nv[d] * xv[r][d];
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-        TV s = part[r][d][p][0];
-#pragma unroll
-        for (int w = 1; w < NCH; ++w) s += part[r][d][p][w];
-        t += uv[d][p] * (ex[d] ? s : TV(0));
-      }
-    }
-    if constexpr (WIDE) {
-      const double* xc = xr + (long long)r * g.n + (long long)c * m;
-      t += bl.apply(g, xc);
-      if (g.arrow) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) t += al[i] * (TV)xc[L + i];
-        const int fi = kk - L;
-        if (fi >= 0 && fi < 3) {
-          TV s = apart[r][fi][0];
-#pragma unroll
-          for (int w = 1; w < NCH; ++w) s += apart[r][fi][w];
-          t += s;
-        }
-      }
-    }
-    const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-    y[o] = RESID ? b[o] - (double)t : (double)t;
-  }
-}
-
 // ------------------------------------------------------------ launchers ----
 static inline int grid_for(long long work, int per_block, int cap = 1 << 20) {
   long long g = (work + per_block - 1) / per_block;
@@ -486,91 +120,17 @@ bool ranks_supported(int rd, int ro) {
 // Right-hand sides per launch: 8 / 4 / 2 / 1 with one pair per block (4 / 2 / 1
 // in the workgroup form), 2 / 1 with several (their coefficient registers
 // grow with the pair count).
-template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
-static void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
-                          double* y, int nrhs, hipStream_t s) {
-  constexpr bool EXACT = RDM == 1 && ROM == 1;
-#ifndef R1S_NO_WG_CELL
-  if constexpr (NCH > 1) {
-    int r0 = 0;
-    while (r0 < nrhs) {
-      const int rem = nrhs - r0;
-      if constexpr (EXACT) {
-        if (rem >= 4) {
-          hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
-                             dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
-          r0 += 4;
-          continue;
-        }
-      }
-      if (rem >= 2) {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
-                           dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
-        r0 += 2;
-      } else {
-        hipLaunchKernelGGL((k_matvec_wg<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(g.N),
-                           dim3(64 * NCH), 0, s, g, rec, x, b, y, r0);
-        r0 += 1;
-      }
-    }
-    return;
-  }
-#endif
-  const int grid = (g.N + WPB - 1) / WPB;
-  int r0 = 0;
-  while (r0 < nrhs) {
-    const int rem = nrhs - r0;
-    if constexpr (NCH <= 2 && EXACT) {
-      if (rem >= 8) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
-        r0 += 8;
-        continue;
-      }
-      if (rem >= 4) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
-        r0 += 4;
-        continue;
-      }
-    }
-    if (rem >= 2) {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
-      r0 += 2;
-    } else {
-      hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
-      r0 += 1;
-    }
-  }
-}
-
-template <typename TV, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
-static hipError_t launch_mv_r(const Mesh& g, const TV* rec, const double* x, const double* b,
-                              double* y, int nrhs, hipStream_t s) {
-  switch ((g.m + WAVE - 1) / WAVE) {
-    case 1: launch_mv_nch<TV, 1, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
-    case 2: launch_mv_nch<TV, 2, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
-    case 3: launch_mv_nch<TV, 3, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
-    case 4: launch_mv_nch<TV, 4, TRANS, RESID, RDM, ROM, WIDE>(g, rec, x, b, y, nrhs, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-// Kernel choice: one pair per block with the tridiagonal uncoupled diagonal
-// block (all counts compile-time), any supported pair counts, or any pair
-// counts with the wide diagonal-block pattern.
 template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   if (!ranks_supported(g.rd, g.ro) || g.band > BAND_MAX) return hipErrorInvalidValue;
-  if (wide_pattern(g))
-    return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX, true>(g, rec, x, b, y, nrhs, s);
-  if (g.rd == 1 && g.ro == 1)
+  if (!wide_pattern(g) && g.rd == 1 && g.ro == 1)
     return launch_mv_r<TV, TRANS, RESID, 1, 1, false>(g, rec, x, b, y, nrhs, s);
-  return launch_mv_r<TV, TRANS, RESID, RANK_DIAG_MAX, RANK_OFF_MAX, false>(g, rec, x, b, y, nrhs, s);
+  // several pairs per block or the wide diagonal block: the general
+  // instantiations, compiled in files of their own
+  const int kind = (TRANS ? 1 : 0) | (RESID ? 2 : 0) | (std::is_same<TV, float>::value ? 4 : 0);
+  return g.ro <= RANK_OFF_SMALL ? launch_mv_general_r2(g, rec, kind, x, b, y, nrhs, s)
+                                : launch_mv_general_r6(g, rec, kind, x, b, y, nrhs, s);
 }
 
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,

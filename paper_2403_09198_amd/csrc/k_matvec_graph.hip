@@ -318,7 +318,7 @@ static void launch_graph1(const Mesh& g, const TV* rec, const double* x, const d
   if (g.rd == 1 && g.ro == 1)
     hipLaunchKernelGGL((k_matvec_graph1<TV, TRANS, RESID, NBM, 1, 1>), grid, block, 0, s, g, rec, x, b, y, r);
   else
-    hipLaunchKernelGGL((k_matvec_graph1<TV, TRANS, RESID, NBM, RANK_DIAG_MAX, RANK_OFF_MAX>), grid,
+    hipLaunchKernelGGL((k_matvec_graph1<TV, TRANS, RESID, NBM, RANK_DIAG_MAX, RANK_OFF_SMALL>), grid,
                        block, 0, s, g, rec, x, b, y, r);
 }
 
@@ -326,7 +326,8 @@ template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_graph_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                                  double* y, int nrhs, hipStream_t s) {
   const dim3 grid((g.N + WPB - 1) / WPB), block(64 * WPB);
-  const bool fast = !wide_pattern(g) && g.m <= WAVE && g.nbmax >= 1 && g.nbmax <= 4;
+  const bool fast = !wide_pattern(g) && g.m <= WAVE && g.nbmax >= 1 && g.nbmax <= 4 &&
+                    g.ro <= RANK_OFF_SMALL;
   for (int r = 0; r < nrhs; ++r) {
     if (fast && g.nbmax <= 3)
       launch_graph1<TV, TRANS, RESID, 3>(g, rec, x, b, y, r, s);

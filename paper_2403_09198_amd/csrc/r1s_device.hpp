@@ -43,8 +43,9 @@ constexpr int GSLOT = 5, GRAPH_NBR_MAX = 8;
 constexpr int D_S = 0, D_W = 1, D_C = 2, D_E = 3, D_N = 4;
 constexpr int MAX_CHUNKS = 4;  // m <= 256
 // Largest pair counts of the general-rank kernels (a diagonal block / a
-// neighbour block); one pair per block has kernels of its own.
-constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 2;
+// neighbour block); one pair per block has kernels of its own, and up to
+// RANK_OFF_SMALL pairs per neighbour block a lighter instantiation.
+constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 6, RANK_OFF_SMALL = 2;
 constexpr int BAND_MAX = 8;  // level-band half-width of S_cc
 
 // SMW factor records, [N][3 + 2 rd][mp] per direction of application, plus

@@ -44,6 +44,13 @@ hipError_t launch_matvec_graph(const Mesh& g, const void* rec, bool f32, bool tr
 hipError_t launch_grad_graph(const Mesh& g, const double* rec, const double* lam, const double* x,
                              int nrhs, const GraphGradOut& out, hipStream_t s);
 
+// structured matvec, general-rank instantiations (kind: bit 0 transpose,
+// bit 1 residual, bit 2 float32 values); ro <= 2 and ro <= 6
+hipError_t launch_mv_general_r2(const Mesh& g, const void* rec, int kind, const double* x,
+                                const double* b, double* y, int nrhs, hipStream_t s);
+hipError_t launch_mv_general_r6(const Mesh& g, const void* rec, int kind, const double* x,
+                                const double* b, double* y, int nrhs, hipStream_t s);
+
 // structured matvec (rec: packed record, float when f32)
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,
                          double* y, int nrhs, hipStream_t s);

@@ -1,0 +1,313 @@
+"""Physics-shaped inputs: the Jacobian of an implicit first-order
+finite-volume step for a multi-species calorically perfect gas with an HLL
+flux, split into the block r1-sparse layout.
+
+This module only builds inputs (it holds none of the linear-algebra path:
+no matvec, factorisation or solve).  It follows the paper's setting:
+
+* conserved variables u = (rho_k, rho u, rho v, rho e_tot) and primitive
+  solution variables q = (rho_k, u, v, T) (section 2, "Compressible Flow
+  Model"; section 3, "Solution Representation"), m = L + 3 with L species;
+* the HLL numerical flux written with the scalar coefficients a_f, c_f
+  (section 3, eq. HLL_flux; section 4, eq. HLL_flux_compact), the wave-speed
+  bounds from (u_n, a) of both sides;
+* the trace-flux Jacobians split into a sparse part and two rank-one terms
+  (section 4, eqs. r1_flux_left / r1_flux_right), with the sparse parts
+  built from H = du/dq and A_n = df_n/dq, both sparse in q.
+
+Gas: species k has the gas constant r_k = 1/M_k, energy e_k(T) = cv_k T +
+e0_k (calorically perfect), nondimensional units (reference molar mass,
+temperature and density 1).  Species 0..L-2 are levels of one diatomic
+species (M = 1, cv = 5/2 r, level energies e0 = 0.3 j r), species L-1 is its
+atom (M = 1/2, cv = 3/2 r, e0 = 4 r).  Structured nx x ny mesh of unit
+cells, outward unit normals, far-field state on the boundary faces, local
+time step dt = cfl / (|u| + |v| + 2 a) frozen in the Jacobian.
+
+Residual of cell c (conservative form with outward normals):
+    R_c(Q) = u(q_c) - u(q_c^n) + dt_c sum_faces f_hat(q_c, q_nb, n).
+Its Jacobian blocks in the library's layout:
+* diagonal block: sparse part H_c + dt_c sum_f [(1/2 + a_f) A_n(q_c) -
+  c_f H_c] (diagonal, level rows x flow columns, flow rows x levels, 3 x 3
+  corner: the `arrow` pattern with no level band), plus two rank-one pairs
+  per face, -(f_nR - f_nL) (da_f/dq_L)^T and (u_R - u_L) (dc_f/dq_L)^T scaled
+  by dt_c: r_diag = 8;
+* neighbour block: dt_c [(1/2 - a_f) A_n(q_nb) + c_f H_nb] plus the two flux
+  pairs with d/dq_R.  Its sparse part is not diagonal (level rows x
+  velocity columns, flow rows x everything); the library's neighbour blocks
+  keep a diagonal sparse part, so the rest becomes four more exact rank-one
+  pairs: (1/2 - a_f) rho_k (levels) x (n_x e_u + n_y e_v), and one pair per
+  flow row (unit vector x the row without its diagonal): r_off = 6.
+"""
+from __future__ import annotations
+
+from typing import Dict
+
+import numpy as np
+
+from .gen import DIR_C, DIR_E, DIR_N, DIR_S, DIR_W, NBR_DIRS, pair_slots
+
+# outward unit normal of each face direction
+NORMALS = {DIR_S: (0.0, -1.0), DIR_W: (-1.0, 0.0), DIR_E: (1.0, 0.0), DIR_N: (0.0, 1.0)}
+FACE_DIRS = (DIR_S, DIR_W, DIR_E, DIR_N)
+R_DIAG, R_OFF = 8, 6
+
+
+def gas(L: int):
+    """r_k, cv_k, e0_k of the L species."""
+    M = np.ones(L)
+    M[-1] = 0.5
+    r = 1.0 / M
+    cv = 2.5 * r
+    cv[-1] = 1.5 * r[-1]
+    e0 = 0.3 * np.arange(L) * r
+    e0[-1] = 4.0 * r[-1]
+    return r, cv, e0
+
+
+# ---------------------------------------------------- state functions ----
+def _split(q, L):
+    return q[..., :L], q[..., L], q[..., L + 1], q[..., L + 2]
+
+
+def conserved(q, L, g):
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    rho = rk.sum(-1)
+    rhoE = (rk * (cv * T[..., None] + e0)).sum(-1) + 0.5 * rho * (u * u + v * v)
+    return np.concatenate([rk, (rho * u)[..., None], (rho * v)[..., None], rhoE[..., None]], -1)
+
+
+def flux_n(q, n, L, g):
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    rho = rk.sum(-1)
+    p = (rk * r).sum(-1) * T
+    un = n[0] * u + n[1] * v
+    rhoE = (rk * (cv * T[..., None] + e0)).sum(-1) + 0.5 * rho * (u * u + v * v)
+    return np.concatenate([rk * un[..., None], (rho * u * un + p * n[0])[..., None],
+                           (rho * v * un + p * n[1])[..., None], ((rhoE + p) * un)[..., None]], -1)
+
+
+def sound_speed(q, L, g):
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    rho = rk.sum(-1)
+    Scv, Sr = (rk * cv).sum(-1), (rk * r).sum(-1)
+    return np.sqrt((Scv + Sr) * Sr * T / (Scv * rho))
+
+
+def H_matrix(q, L, g):
+    """du/dq for one state q [m]."""
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    m = L + 3
+    rho = rk.sum()
+    H = np.zeros((m, m))
+    H[:L, :L] = np.eye(L)
+    H[L, :L] = u
+    H[L, L] = rho
+    H[L + 1, :L] = v
+    H[L + 1, L + 1] = rho
+    H[L + 2, :L] = cv * T + e0 + 0.5 * (u * u + v * v)
+    H[L + 2, L] = rho * u
+    H[L + 2, L + 1] = rho * v
+    H[L + 2, L + 2] = (rk * cv).sum()
+    return H
+
+
+def A_matrix(q, n, L, g):
+    """df_n/dq for one state q [m] and normal n."""
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    m = L + 3
+    rho = rk.sum()
+    Sr, Scv = (rk * r).sum(), (rk * cv).sum()
+    un = n[0] * u + n[1] * v
+    ek = cv * T + e0 + 0.5 * (u * u + v * v)
+    rhoE = (rk * (cv * T + e0)).sum() + 0.5 * rho * (u * u + v * v)
+    p = Sr * T
+    A = np.zeros((m, m))
+    A[:L, :L] = un * np.eye(L)
+    A[:L, L] = rk * n[0]
+    A[:L, L + 1] = rk * n[1]
+    A[L, :L] = u * un + r * T * n[0]
+    A[L, L] = rho * (un + u * n[0])
+    A[L, L + 1] = rho * u * n[1]
+    A[L, L + 2] = Sr * n[0]
+    A[L + 1, :L] = v * un + r * T * n[1]
+    A[L + 1, L] = rho * v * n[0]
+    A[L + 1, L + 1] = rho * (un + v * n[1])
+    A[L + 1, L + 2] = Sr * n[1]
+    A[L + 2, :L] = (ek + r * T) * un
+    A[L + 2, L] = rho * u * un + (rhoE + p) * n[0]
+    A[L + 2, L + 1] = rho * v * un + (rhoE + p) * n[1]
+    A[L + 2, L + 2] = (Scv + Sr) * un
+    return A
+
+
+def grad_sound_speed(q, L, g):
+    """da/dq for one state q [m]."""
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    rho = rk.sum()
+    Scv, Sr = (rk * cv).sum(), (rk * r).sum()
+    a2 = (Scv + Sr) * Sr * T / (Scv * rho)
+    a = np.sqrt(a2)
+    da2 = np.zeros(L + 3)
+    da2[:L] = T * ((cv + r) * Sr / (Scv * rho) + (Scv + Sr) * r / (Scv * rho)
+                   - (Scv + Sr) * Sr * cv / (Scv * Scv * rho) - (Scv + Sr) * Sr / (Scv * rho * rho))
+    da2[L + 2] = a2 / T
+    return da2 / (2.0 * a)
+
+
+# ------------------------------------------------------------ HLL flux ----
+def hll(qL, qR, n, L, g):
+    """HLL flux and its pieces: f_hat, a_f, c_f, and da_f, dc_f w.r.t. qL
+    and qR (wave-speed bounds s_L = min(u_nL - a_L, u_nR - a_R), s_R =
+    max(u_nL + a_L, u_nR + a_R), the branch taken at ties: left)."""
+    m = L + 3
+    aL, aR = sound_speed(qL, L, g), sound_speed(qR, L, g)
+    unL = n[0] * qL[L] + n[1] * qL[L + 1]
+    unR = n[0] * qR[L] + n[1] * qR[L + 1]
+    dun = np.zeros(m)
+    dun[L], dun[L + 1] = n
+    daL, daR = grad_sound_speed(qL, L, g), grad_sound_speed(qR, L, g)
+    zero = np.zeros(m)
+    if unL - aL <= unR - aR:
+        sL, dsL_L, dsL_R = unL - aL, dun - daL, zero
+    else:
+        sL, dsL_L, dsL_R = unR - aR, zero, dun - daR
+    if unL + aL >= unR + aR:
+        sR, dsR_L, dsR_R = unL + aL, dun + daL, zero
+    else:
+        sR, dsR_L, dsR_R = unR + aR, zero, dun + daR
+    D = sR - sL
+    af = 0.5 * (sL + sR) / D
+    cf = sL * sR / D
+    # a_f = (s_L + s_R) / (2 (s_R - s_L)):  da_f = (s_R ds_L - s_L ds_R) / D^2
+    # c_f = s_L s_R / (s_R - s_L):          dc_f = (s_R^2 ds_L - s_L^2 ds_R) / D^2
+    daf_L = (sR * dsL_L - sL * dsR_L) / D ** 2
+    daf_R = (sR * dsL_R - sL * dsR_R) / D ** 2
+    dcf_L = (sR * sR * dsL_L - sL * sL * dsR_L) / D ** 2
+    dcf_R = (sR * sR * dsL_R - sL * sL * dsR_R) / D ** 2
+    fL, fR = flux_n(qL, n, L, g), flux_n(qR, n, L, g)
+    uL, uR = conserved(qL, L, g), conserved(qR, L, g)
+    fhat = 0.5 * (fL + fR) - af * (fR - fL) + cf * (uR - uL)
+    return dict(fhat=fhat, af=af, cf=cf, daf_L=daf_L, daf_R=daf_R, dcf_L=dcf_L, dcf_R=dcf_R,
+                fL=fL, fR=fR, uL=uL, uR=uR)
+
+
+# ---------------------------------------------------------------- state ----
+def make_state(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0):
+    """A smooth subsonic state on the mesh, the far-field state and the
+    local time steps: {"q": [N][m], "q_inf": [m], "dt": [N]}."""
+    rng = np.random.default_rng(seed)
+    N = nx * ny
+    iy, ix = np.divmod(np.arange(N), nx)
+    X, Y = (ix + 0.5) / nx, (iy + 0.5) / ny
+    # Boltzmann-like level populations, a few percent atoms, smooth waves
+    lev = np.exp(-0.4 * np.arange(L - 1)) if L > 1 else np.zeros(0)
+    base = np.concatenate([lev / max(lev.sum(), 1e-300) * 0.95, [0.05]]) if L > 1 else np.ones(1)
+    wave = 1.0 + 0.1 * np.sin(2 * np.pi * X)[:, None] * np.cos(2 * np.pi * Y)[:, None]
+    rk = base[None, :] * wave * (1.0 + 0.05 * rng.standard_normal((N, L)))
+    u = 0.3 + 0.05 * np.sin(2 * np.pi * Y) + 0.02 * rng.standard_normal(N)
+    v = 0.1 * np.sin(2 * np.pi * X) + 0.02 * rng.standard_normal(N)
+    T = 1.0 + 0.1 * np.cos(2 * np.pi * X) + 0.02 * rng.standard_normal(N)
+    q = np.concatenate([rk, u[:, None], v[:, None], T[:, None]], 1)
+    q_inf = np.concatenate([base, [0.3, 0.0, 1.0]])
+    g = gas(L)
+    a = sound_speed(q, L, g)
+    dt = cfl / (np.abs(u) + np.abs(v) + 2.0 * a)
+    return {"q": q, "q_inf": q_inf, "dt": dt}
+
+
+def _neighbour(nx, ny, c, d):
+    iy, ix = divmod(c, nx)
+    if d == DIR_S:
+        return c - nx if iy > 0 else -1
+    if d == DIR_W:
+        return c - 1 if ix > 0 else -1
+    if d == DIR_E:
+        return c + 1 if ix < nx - 1 else -1
+    return c + nx if iy < ny - 1 else -1
+
+
+def residual(st, nx: int, ny: int, L: int, Q=None, u_old=None):
+    """R_c(Q) = u(q_c) - u_old_c + dt_c sum_faces f_hat (dt frozen); with the
+    defaults Q is the state and u_old its conserved variables (R = flux
+    part only)."""
+    g = gas(L)
+    Q = st["q"] if Q is None else Q
+    R = conserved(Q, L, g) - (conserved(st["q"], L, g) if u_old is None else u_old)
+    for c in range(nx * ny):
+        for d in FACE_DIRS:
+            nb = _neighbour(nx, ny, c, d)
+            qR = Q[nb] if nb >= 0 else st["q_inf"]
+            R[c] += st["dt"][c] * hll(Q[c], qR, NORMALS[d], L, g)["fhat"]
+    return R
+
+
+def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> Dict[str, np.ndarray]:
+    """The Jacobian dR/dQ at the state, in the library's structured layout
+    with 8 pairs per diagonal block, 6 per neighbour block, no level band and
+    level/flow coupling (see the module docstring)."""
+    if L < 2:
+        raise ValueError("need at least two species")
+    st = make_state(nx, ny, L, seed, cfl)
+    g = gas(L)
+    N, m = nx * ny, L + 3
+    P = R_DIAG + 4 * R_OFF
+    slots = pair_slots(R_DIAG, R_OFF)
+    p = {k: np.zeros(s) for k, s in (("s_diag", (N, m)), ("s_sub", (N, L - 1)),
+                                      ("s_sup", (N, L - 1)), ("s_flow", (N, 6)),
+                                      ("s_nbr", (N, 4, m)), ("u", (N, P, m)), ("v", (N, P, m)),
+                                      ("s_band", (N, 0, L)), ("s_lev_flow", (N, 3, L)),
+                                      ("s_flow_lev", (N, 3, L)))}
+    corner = ((0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1))
+    for c in range(N):
+        qc, dt = st["q"][c], st["dt"][c]
+        Hc = H_matrix(qc, L, g)
+        S = Hc.copy()
+        a0 = slots[DIR_C][0]
+        for t, d in enumerate(FACE_DIRS):
+            n = NORMALS[d]
+            nb = _neighbour(nx, ny, c, d)
+            qR = st["q"][nb] if nb >= 0 else st["q_inf"]
+            h = hll(qc, qR, n, L, g)
+            S += dt * ((0.5 + h["af"]) * A_matrix(qc, n, L, g) - h["cf"] * Hc)
+            # the two flux pairs of the diagonal block (d/dq_L)
+            p["u"][c, a0 + 2 * t] = -dt * (h["fR"] - h["fL"])
+            p["v"][c, a0 + 2 * t] = h["daf_L"]
+            p["u"][c, a0 + 2 * t + 1] = dt * (h["uR"] - h["uL"])
+            p["v"][c, a0 + 2 * t + 1] = h["dcf_L"]
+            if nb < 0:
+                continue
+            # neighbour block: dt [(1/2 - a_f) A_n(q_nb) + c_f H_nb] + flux pairs
+            G = dt * ((0.5 - h["af"]) * A_matrix(qR, n, L, g) + h["cf"] * H_matrix(qR, L, g))
+            j = NBR_DIRS.index(d)
+            p["s_nbr"][c, j] = np.diag(G)
+            a = slots[d][0]
+            p["u"][c, a] = -dt * (h["fR"] - h["fL"])
+            p["v"][c, a] = h["daf_R"]
+            p["u"][c, a + 1] = dt * (h["uR"] - h["uL"])
+            p["v"][c, a + 1] = h["dcf_R"]
+            # level rows x velocity columns: dt (1/2 - a_f) rho_k (n_x e_u + n_y e_v)
+            p["u"][c, a + 2, :L] = dt * (0.5 - h["af"]) * qR[:L]
+            p["v"][c, a + 2, L], p["v"][c, a + 2, L + 1] = n
+            # flow rows without their diagonal entries
+            for i in range(3):
+                p["u"][c, a + 3 + i, L + i] = 1.0
+                row = G[L + i].copy()
+                row[L + i] = 0.0
+                p["v"][c, a + 3 + i] = row
+        p["s_diag"][c] = np.diag(S)
+        p["s_lev_flow"][c] = S[:L, L:].T
+        p["s_flow_lev"][c] = S[L:, :L]
+        for t, (i, j) in enumerate(corner):
+            p["s_flow"][c, t] = S[L + i, L + j]
+    for k in list(p):
+        p[k] = np.ascontiguousarray(p[k])
+    p["ranks"] = np.array([R_DIAG, R_OFF])
+    p["pattern"] = np.array([1, 1])
+    p["state"] = st["q"]
+    return p

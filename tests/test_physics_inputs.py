@@ -1,0 +1,87 @@
+"""Pins of the physics-shaped inputs: the HLL finite-volume Jacobian of a
+multi-species calorically perfect gas (section 3, eq. HLL_flux; section 4,
+eqs. HLL_flux_compact, r1_flux_left / r1_flux_right), split into the block
+r1-sparse layout.  The split is checked against central finite differences
+of the residual itself, and its pieces (H = du/dq, A_n = df_n/dq, da/dq)
+against finite differences of the state functions."""
+import numpy as np
+import pytest
+
+from oracle import assemble, blockjacobi, gmres, mesh, ops
+from paper_2403_09198_amd import physics
+
+
+def _fd(f, q, h=1e-6):
+    cols = []
+    for j in range(q.size):
+        e = np.zeros_like(q)
+        e[j] = h * max(1.0, abs(q[j]))
+        cols.append((f(q + e) - f(q - e)) / (2 * e[j]))
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("L", [2, 5])
+def test_state_derivatives_match_finite_differences(L):
+    g = physics.gas(L)
+    st = physics.make_state(2, 2, L, seed=1)
+    q = st["q"][3]
+    n = (0.6, -0.8)
+    assert np.allclose(physics.H_matrix(q, L, g), _fd(lambda z: physics.conserved(z, L, g), q),
+                       rtol=1e-7, atol=1e-8)
+    assert np.allclose(physics.A_matrix(q, n, L, g), _fd(lambda z: physics.flux_n(z, n, L, g), q),
+                       rtol=1e-7, atol=1e-8)
+    da = _fd(lambda z: np.array([physics.sound_speed(z, L, g)]), q)[0]
+    assert np.allclose(physics.grad_sound_speed(q, L, g), da, rtol=1e-7, atol=1e-9)
+
+
+def test_hll_flux_is_consistent_and_its_pieces_match_fd():
+    L = 4
+    g = physics.gas(L)
+    st = physics.make_state(3, 1, L, seed=2)
+    qL, qR = st["q"][0], st["q"][1]
+    n = (1.0, 0.0)
+    # consistency: f_hat(q, q) = f_n(q)
+    assert np.allclose(physics.hll(qL, qL, n, L, g)["fhat"], physics.flux_n(qL, n, L, g))
+    h = physics.hll(qL, qR, n, L, g)
+    # eq. r1_flux_left: the dense left Jacobian is a sparse part plus two
+    # rank-one terms
+    AL = ((0.5 + h["af"]) * physics.A_matrix(qL, n, L, g) - h["cf"] * physics.H_matrix(qL, L, g)
+          - np.outer(h["fR"] - h["fL"], h["daf_L"]) + np.outer(h["uR"] - h["uL"], h["dcf_L"]))
+    AR = ((0.5 - h["af"]) * physics.A_matrix(qR, n, L, g) + h["cf"] * physics.H_matrix(qR, L, g)
+          - np.outer(h["fR"] - h["fL"], h["daf_R"]) + np.outer(h["uR"] - h["uL"], h["dcf_R"]))
+    assert np.allclose(AL, _fd(lambda z: physics.hll(z, qR, n, L, g)["fhat"], qL), rtol=1e-6,
+                       atol=1e-8)
+    assert np.allclose(AR, _fd(lambda z: physics.hll(qL, z, n, L, g)["fhat"], qR), rtol=1e-6,
+                       atol=1e-8)
+
+
+def test_layout_reassembles_the_finite_difference_jacobian():
+    nx, ny, L = 3, 2, 4
+    p = physics.make_problem(nx, ny, L, seed=3)
+    st = physics.make_state(nx, ny, L, seed=3)
+    N, m = nx * ny, L + 3
+    u_old = physics.conserved(st["q"], L, physics.gas(L))
+
+    def R(flat):
+        return physics.residual(st, nx, ny, L, Q=flat.reshape(N, m), u_old=u_old).ravel()
+
+    J_fd = _fd(R, st["q"].ravel())
+    J = ops.dense_matrix(p, nx, ny, L)
+    assert np.abs(J - J_fd).max() <= 1e-6 * np.abs(J_fd).max()
+    # the pair counts are the paper's flux part: two per face
+    assert tuple(p["ranks"]) == (8, 6) and mesh.pattern(p) == (1, 1)
+
+
+def test_physics_jacobian_solves_with_the_smw_block_jacobi():
+    nx, ny, L = 6, 5, 8
+    p = physics.make_problem(nx, ny, L, seed=4)
+    N, m = nx * ny, L + 3
+    for c in (0, 7, N - 1):
+        D = assemble.dense_block(p, c, mesh.C, L)
+        assert np.abs(blockjacobi.smw_inverse(p, c, L) @ D - np.eye(m)).max() <= 1e-10
+    b = np.random.default_rng(0).standard_normal((N, m))
+    M = blockjacobi.BlockJacobi(assemble.diagonal_blocks(p, nx, ny, L))
+    res = gmres.gmres(lambda v: ops.matvec(p, nx, ny, L, v), M.apply, b, restart=40, rtol=1e-10)
+    J = ops.dense_matrix(p, nx, ny, L)
+    assert res.converged
+    assert np.linalg.norm(J @ res.x.ravel() - b.ravel()) <= 1e-9 * np.linalg.norm(b)
