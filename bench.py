@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "J*x + SMW precond apply GB/s (%HBM peak); FP32-precond & adjoint vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "counters_pair_fp64_mesh256x128_L61.json")
-KERNEL_SOURCES = ("k_matvec.hip", "k_smw.hip", "r1s_device.hpp")
+KERNEL_SOURCES = ("k_matvec.hip", "k_matvec_impl.hpp", "k_smw.hip", "r1s_device.hpp")
 
 
 def kernel_source_hash():
@@ -201,16 +201,26 @@ def profile_pass(torch, A, M, x, y, z):
                                                                           src.numel() * 8))
 
 
-def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False):
+def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False,
+               physics_values=False, solve=None):
     """The float64 pair with several rank-one pairs per block (the paper's
     9 / 2 structure) and optionally the wide diagonal-block pattern;
-    algorithmic bytes from the library's storage counts."""
-    from paper_2403_09198_amd import gen, r1s
+    algorithmic bytes from the library's storage counts.  physics_values:
+    the HLL finite-volume Jacobian of a multi-species gas (8 / 6 pairs,
+    level/flow coupling) in place of random values; solve = (restart, rtol)
+    adds GMRES solves of it."""
+    from paper_2403_09198_amd import gen, physics, r1s
 
     dev = "cuda:0"
-    log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks} band {band} arrow {arrow}")
-    p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1], band=band,
-                         arrow=arrow)
+    if physics_values:
+        ranks, band, arrow = (physics.R_DIAG, physics.R_OFF), 1, True
+    log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks} band {band} arrow {arrow}"
+        + (" (HLL Jacobian)" if physics_values else ""))
+    if physics_values:
+        p = physics.make_problem(nx, ny, L, seed=seed)
+    else:
+        p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1], band=band,
+                             arrow=arrow)
     keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
     vals = {k: torch.from_numpy(p[k]).to(dev) for k in keys}
     del p
@@ -243,6 +253,19 @@ def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False
                     "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
                     "matvec_gbs": round(((mv - vec_b) * vb // 8 + vec_b) / (k1 / 1e3) / 1e9, 1),
                     "apply_gbs": round(((ap - vec_b) * vb // 8 + vec_b) / (k2 / 1e3) / 1e9, 1)}
+    if solve is not None:
+        b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=seed)).to(dev)
+        for mode in ("f64", "mixed"):
+            r1s.gmres(A, M, b, restart=solve[0], rtol=solve[1], mode=mode)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = r1s.gmres(A, M, b, restart=solve[0], rtol=solve[1], mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row[f"solve_{mode}"] = {"ms": round(el * 1e3, 2), "iters": res.stats[0]["iters"],
+                                    "outer": res.stats[0]["outer"],
+                                    "rel_residual": res.stats[0]["rel_residual"]}
+        del b
     del A, M, x, y, z
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -648,6 +671,14 @@ def main():
         # level/flow coupling (banded-LU block-Jacobi, one lane per cell)
         out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
                                               band=4, arrow=True)
+        # the same mesh with physics-shaped values: the HLL finite-volume
+        # Jacobian of a multi-species gas (8 / 6 pairs, level/flow coupling),
+        # with GMRES solves of it
+        try:
+            out["physics_pair"] = ranks_pair(torch, nx, ny, L, None, steps, warm,
+                                             physics_values=True, solve=(w.restart, w.rtol))
+        except Exception as e:  # report, never hide
+            out["physics_pair"] = {"error": str(e)}
         # general mesh: about 32 800 triangle cells (Delaunay of 16 400 random
         # points), the same L, one pair per block; shuffled and mesh-ordered
         # cell numbering

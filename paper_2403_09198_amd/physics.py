@@ -96,103 +96,144 @@ def sound_speed(q, L, g):
     return np.sqrt((Scv + Sr) * Sr * T / (Scv * rho))
 
 
-def H_matrix(q, L, g):
-    """du/dq for one state q [m]."""
+# H and A_n are nonzero only on the level diagonal, in the level rows x flow
+# columns and in the three flow rows; a "parts" triple holds exactly those:
+# (level diagonal [..., L], level x flow [..., L, 3], flow rows [..., 3, m]).
+def dense(parts, L):
+    """The m x m matrices of a parts triple."""
+    lev, lf, fr = parts
+    m = L + 3
+    X = np.zeros(np.shape(lev)[:-1] + (m, m))
+    k = np.arange(L)
+    X[..., k, k] = lev
+    X[..., :L, L:] = lf
+    X[..., L:, :] = fr
+    return X
+
+
+def combine(terms):
+    """sum_i c_i X_i over (c_i [...], parts_i) on the parts triples."""
+    out = None
+    for c, (lev, lf, fr) in terms:
+        c = np.asarray(c)[..., None]
+        t = (c * lev, c[..., None] * lf, c[..., None] * fr)
+        out = t if out is None else tuple(a + b for a, b in zip(out, t))
+    return out
+
+
+def H_parts(q, L, g):
+    """du/dq for states q [..., m], as a parts triple."""
     r, cv, e0 = g
     rk, u, v, T = _split(q, L)
     m = L + 3
-    rho = rk.sum()
-    H = np.zeros((m, m))
-    H[:L, :L] = np.eye(L)
-    H[L, :L] = u
-    H[L, L] = rho
-    H[L + 1, :L] = v
-    H[L + 1, L + 1] = rho
-    H[L + 2, :L] = cv * T + e0 + 0.5 * (u * u + v * v)
-    H[L + 2, L] = rho * u
-    H[L + 2, L + 1] = rho * v
-    H[L + 2, L + 2] = (rk * cv).sum()
-    return H
+    rho = rk.sum(-1)
+    lev = np.ones(np.shape(rk))
+    lf = np.zeros(np.shape(rk) + (3,))
+    fr = np.zeros(np.shape(q)[:-1] + (3, m))
+    fr[..., 0, :L] = u[..., None]
+    fr[..., 0, L] = rho
+    fr[..., 1, :L] = v[..., None]
+    fr[..., 1, L + 1] = rho
+    fr[..., 2, :L] = cv * T[..., None] + e0 + 0.5 * (u * u + v * v)[..., None]
+    fr[..., 2, L] = rho * u
+    fr[..., 2, L + 1] = rho * v
+    fr[..., 2, L + 2] = (rk * cv).sum(-1)
+    return lev, lf, fr
+
+
+def A_parts(q, n, L, g):
+    """df_n/dq for states q [..., m] and the normal n, as a parts triple."""
+    r, cv, e0 = g
+    rk, u, v, T = _split(q, L)
+    m = L + 3
+    rho = rk.sum(-1)
+    Sr, Scv = (rk * r).sum(-1), (rk * cv).sum(-1)
+    un = n[0] * u + n[1] * v
+    ek = cv * T[..., None] + e0 + 0.5 * (u * u + v * v)[..., None]
+    rhoE = (rk * (cv * T[..., None] + e0)).sum(-1) + 0.5 * rho * (u * u + v * v)
+    p = Sr * T
+    lev = un[..., None] * np.ones(np.shape(rk))
+    lf = np.zeros(np.shape(rk) + (3,))
+    lf[..., 0] = rk * n[0]
+    lf[..., 1] = rk * n[1]
+    fr = np.zeros(np.shape(q)[:-1] + (3, m))
+    fr[..., 0, :L] = (u * un)[..., None] + r * T[..., None] * n[0]
+    fr[..., 0, L] = rho * (un + u * n[0])
+    fr[..., 0, L + 1] = rho * u * n[1]
+    fr[..., 0, L + 2] = Sr * n[0]
+    fr[..., 1, :L] = (v * un)[..., None] + r * T[..., None] * n[1]
+    fr[..., 1, L] = rho * v * n[0]
+    fr[..., 1, L + 1] = rho * (un + v * n[1])
+    fr[..., 1, L + 2] = Sr * n[1]
+    fr[..., 2, :L] = (ek + r * T[..., None]) * un[..., None]
+    fr[..., 2, L] = rho * u * un + (rhoE + p) * n[0]
+    fr[..., 2, L + 1] = rho * v * un + (rhoE + p) * n[1]
+    fr[..., 2, L + 2] = (Scv + Sr) * un
+    return lev, lf, fr
+
+
+def H_matrix(q, L, g):
+    """du/dq for states q [..., m] (one dense matrix per state)."""
+    return dense(H_parts(q, L, g), L)
 
 
 def A_matrix(q, n, L, g):
-    """df_n/dq for one state q [m] and normal n."""
-    r, cv, e0 = g
-    rk, u, v, T = _split(q, L)
-    m = L + 3
-    rho = rk.sum()
-    Sr, Scv = (rk * r).sum(), (rk * cv).sum()
-    un = n[0] * u + n[1] * v
-    ek = cv * T + e0 + 0.5 * (u * u + v * v)
-    rhoE = (rk * (cv * T + e0)).sum() + 0.5 * rho * (u * u + v * v)
-    p = Sr * T
-    A = np.zeros((m, m))
-    A[:L, :L] = un * np.eye(L)
-    A[:L, L] = rk * n[0]
-    A[:L, L + 1] = rk * n[1]
-    A[L, :L] = u * un + r * T * n[0]
-    A[L, L] = rho * (un + u * n[0])
-    A[L, L + 1] = rho * u * n[1]
-    A[L, L + 2] = Sr * n[0]
-    A[L + 1, :L] = v * un + r * T * n[1]
-    A[L + 1, L] = rho * v * n[0]
-    A[L + 1, L + 1] = rho * (un + v * n[1])
-    A[L + 1, L + 2] = Sr * n[1]
-    A[L + 2, :L] = (ek + r * T) * un
-    A[L + 2, L] = rho * u * un + (rhoE + p) * n[0]
-    A[L + 2, L + 1] = rho * v * un + (rhoE + p) * n[1]
-    A[L + 2, L + 2] = (Scv + Sr) * un
-    return A
+    """df_n/dq for states q [..., m] and the normal n (dense)."""
+    return dense(A_parts(q, n, L, g), L)
 
 
 def grad_sound_speed(q, L, g):
-    """da/dq for one state q [m]."""
+    """da/dq for states q [..., m]."""
     r, cv, e0 = g
     rk, u, v, T = _split(q, L)
-    rho = rk.sum()
-    Scv, Sr = (rk * cv).sum(), (rk * r).sum()
+    rho = rk.sum(-1)
+    Scv, Sr = (rk * cv).sum(-1), (rk * r).sum(-1)
     a2 = (Scv + Sr) * Sr * T / (Scv * rho)
     a = np.sqrt(a2)
-    da2 = np.zeros(L + 3)
-    da2[:L] = T * ((cv + r) * Sr / (Scv * rho) + (Scv + Sr) * r / (Scv * rho)
-                   - (Scv + Sr) * Sr * cv / (Scv * Scv * rho) - (Scv + Sr) * Sr / (Scv * rho * rho))
-    da2[L + 2] = a2 / T
-    return da2 / (2.0 * a)
+    da2 = np.zeros(np.shape(q))
+    Scv_, Sr_, rho_, T_ = Scv[..., None], Sr[..., None], rho[..., None], T[..., None]
+    da2[..., :L] = T_ * ((cv + r) * Sr_ / (Scv_ * rho_) + (Scv_ + Sr_) * r / (Scv_ * rho_)
+                         - (Scv_ + Sr_) * Sr_ * cv / (Scv_ * Scv_ * rho_)
+                         - (Scv_ + Sr_) * Sr_ / (Scv_ * rho_ * rho_))
+    da2[..., L + 2] = a2 / T
+    return da2 / (2.0 * a[..., None])
 
 
 # ------------------------------------------------------------ HLL flux ----
 def hll(qL, qR, n, L, g):
-    """HLL flux and its pieces: f_hat, a_f, c_f, and da_f, dc_f w.r.t. qL
-    and qR (wave-speed bounds s_L = min(u_nL - a_L, u_nR - a_R), s_R =
-    max(u_nL + a_L, u_nR + a_R), the branch taken at ties: left)."""
+    """HLL flux and its pieces for states [..., m]: f_hat, a_f, c_f, and
+    da_f, dc_f w.r.t. qL and qR (wave-speed bounds s_L = min(u_nL - a_L,
+    u_nR - a_R), s_R = max(u_nL + a_L, u_nR + a_R), the branch taken at
+    ties: left)."""
     m = L + 3
     aL, aR = sound_speed(qL, L, g), sound_speed(qR, L, g)
-    unL = n[0] * qL[L] + n[1] * qL[L + 1]
-    unR = n[0] * qR[L] + n[1] * qR[L + 1]
+    unL = n[0] * qL[..., L] + n[1] * qL[..., L + 1]
+    unR = n[0] * qR[..., L] + n[1] * qR[..., L + 1]
     dun = np.zeros(m)
     dun[L], dun[L + 1] = n
     daL, daR = grad_sound_speed(qL, L, g), grad_sound_speed(qR, L, g)
-    zero = np.zeros(m)
-    if unL - aL <= unR - aR:
-        sL, dsL_L, dsL_R = unL - aL, dun - daL, zero
-    else:
-        sL, dsL_L, dsL_R = unR - aR, zero, dun - daR
-    if unL + aL >= unR + aR:
-        sR, dsR_L, dsR_R = unL + aL, dun + daL, zero
-    else:
-        sR, dsR_L, dsR_R = unR + aR, zero, dun + daR
+    zero = np.zeros(np.shape(daL))
+    left_lo = (unL - aL <= unR - aR)[..., None]
+    left_hi = (unL + aL >= unR + aR)[..., None]
+    sL = np.where(left_lo[..., 0], unL - aL, unR - aR)
+    dsL_L = np.where(left_lo, dun - daL, zero)
+    dsL_R = np.where(left_lo, zero, dun - daR)
+    sR = np.where(left_hi[..., 0], unL + aL, unR + aR)
+    dsR_L = np.where(left_hi, dun + daL, zero)
+    dsR_R = np.where(left_hi, zero, dun + daR)
     D = sR - sL
     af = 0.5 * (sL + sR) / D
     cf = sL * sR / D
     # a_f = (s_L + s_R) / (2 (s_R - s_L)):  da_f = (s_R ds_L - s_L ds_R) / D^2
     # c_f = s_L s_R / (s_R - s_L):          dc_f = (s_R^2 ds_L - s_L^2 ds_R) / D^2
-    daf_L = (sR * dsL_L - sL * dsR_L) / D ** 2
-    daf_R = (sR * dsL_R - sL * dsR_R) / D ** 2
-    dcf_L = (sR * sR * dsL_L - sL * sL * dsR_L) / D ** 2
-    dcf_R = (sR * sR * dsL_R - sL * sL * dsR_R) / D ** 2
+    sL_, sR_, D2 = sL[..., None], sR[..., None], (D * D)[..., None]
+    daf_L = (sR_ * dsL_L - sL_ * dsR_L) / D2
+    daf_R = (sR_ * dsL_R - sL_ * dsR_R) / D2
+    dcf_L = (sR_ * sR_ * dsL_L - sL_ * sL_ * dsR_L) / D2
+    dcf_R = (sR_ * sR_ * dsL_R - sL_ * sL_ * dsR_R) / D2
     fL, fR = flux_n(qL, n, L, g), flux_n(qR, n, L, g)
     uL, uR = conserved(qL, L, g), conserved(qR, L, g)
-    fhat = 0.5 * (fL + fR) - af * (fR - fL) + cf * (uR - uL)
+    fhat = (0.5 * (fL + fR) - af[..., None] * (fR - fL) + cf[..., None] * (uR - uL))
     return dict(fhat=fhat, af=af, cf=cf, daf_L=daf_L, daf_R=daf_R, dcf_L=dcf_L, dcf_R=dcf_R,
                 fL=fL, fR=fR, uL=uL, uR=uR)
 
@@ -221,15 +262,22 @@ def make_state(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0):
     return {"q": q, "q_inf": q_inf, "dt": dt}
 
 
-def _neighbour(nx, ny, c, d):
-    iy, ix = divmod(c, nx)
+def _neighbours(nx, ny, d):
+    """Neighbour of every cell across face direction d (-1 on the boundary)."""
+    c = np.arange(nx * ny)
+    iy, ix = np.divmod(c, nx)
     if d == DIR_S:
-        return c - nx if iy > 0 else -1
+        return np.where(iy > 0, c - nx, -1)
     if d == DIR_W:
-        return c - 1 if ix > 0 else -1
+        return np.where(ix > 0, c - 1, -1)
     if d == DIR_E:
-        return c + 1 if ix < nx - 1 else -1
-    return c + nx if iy < ny - 1 else -1
+        return np.where(ix < nx - 1, c + 1, -1)
+    return np.where(iy < ny - 1, c + nx, -1)
+
+
+def _right_states(Q, q_inf, nb):
+    """The state across each face: the neighbour's, or the far field."""
+    return np.where((nb >= 0)[:, None], Q[np.maximum(nb, 0)], q_inf)
 
 
 def residual(st, nx: int, ny: int, L: int, Q=None, u_old=None):
@@ -239,12 +287,13 @@ def residual(st, nx: int, ny: int, L: int, Q=None, u_old=None):
     g = gas(L)
     Q = st["q"] if Q is None else Q
     R = conserved(Q, L, g) - (conserved(st["q"], L, g) if u_old is None else u_old)
-    for c in range(nx * ny):
-        for d in FACE_DIRS:
-            nb = _neighbour(nx, ny, c, d)
-            qR = Q[nb] if nb >= 0 else st["q_inf"]
-            R[c] += st["dt"][c] * hll(Q[c], qR, NORMALS[d], L, g)["fhat"]
+    for d in FACE_DIRS:
+        qR = _right_states(Q, st["q_inf"], _neighbours(nx, ny, d))
+        R = R + st["dt"][:, None] * hll(Q, qR, NORMALS[d], L, g)["fhat"]
     return R
+
+
+CHUNK = 1024  # cells per batch in make_problem (bounds the m x m temporaries)
 
 
 def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> Dict[str, np.ndarray]:
@@ -264,47 +313,61 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> D
                                       ("s_band", (N, 0, L)), ("s_lev_flow", (N, 3, L)),
                                       ("s_flow_lev", (N, 3, L)))}
     corner = ((0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1))
-    for c in range(N):
-        qc, dt = st["q"][c], st["dt"][c]
-        Hc = H_matrix(qc, L, g)
-        S = Hc.copy()
-        a0 = slots[DIR_C][0]
+    nbrs = {d: _neighbours(nx, ny, d) for d in FACE_DIRS}
+    a0 = slots[DIR_C][0]
+    u, v = p["u"], p["v"]
+    for c0 in range(0, N, CHUNK):
+        cs = slice(c0, min(N, c0 + CHUNK))
+        qc, dt = st["q"][cs], st["dt"][cs]
+        Hc = H_parts(qc, L, g)
+        S = [(np.ones_like(dt), Hc)]
         for t, d in enumerate(FACE_DIRS):
             n = NORMALS[d]
-            nb = _neighbour(nx, ny, c, d)
-            qR = st["q"][nb] if nb >= 0 else st["q_inf"]
+            nb = nbrs[d][cs]
+            inside = nb >= 0
+            qR = _right_states(st["q"], st["q_inf"], nb)
             h = hll(qc, qR, n, L, g)
-            S += dt * ((0.5 + h["af"]) * A_matrix(qc, n, L, g) - h["cf"] * Hc)
+            af, cf = h["af"], h["cf"]
+            S += [(dt * (0.5 + af), A_parts(qc, n, L, g)), (-dt * cf, Hc)]
+            dt2 = dt[:, None]
             # the two flux pairs of the diagonal block (d/dq_L)
-            p["u"][c, a0 + 2 * t] = -dt * (h["fR"] - h["fL"])
-            p["v"][c, a0 + 2 * t] = h["daf_L"]
-            p["u"][c, a0 + 2 * t + 1] = dt * (h["uR"] - h["uL"])
-            p["v"][c, a0 + 2 * t + 1] = h["dcf_L"]
-            if nb < 0:
-                continue
-            # neighbour block: dt [(1/2 - a_f) A_n(q_nb) + c_f H_nb] + flux pairs
-            G = dt * ((0.5 - h["af"]) * A_matrix(qR, n, L, g) + h["cf"] * H_matrix(qR, L, g))
+            u[cs, a0 + 2 * t] = -dt2 * (h["fR"] - h["fL"])
+            v[cs, a0 + 2 * t] = h["daf_L"]
+            u[cs, a0 + 2 * t + 1] = dt2 * (h["uR"] - h["uL"])
+            v[cs, a0 + 2 * t + 1] = h["dcf_L"]
+            # neighbour block (interior faces only): dt [(1/2 - a_f) A_n(q_nb)
+            # + c_f H_nb] + flux pairs
+            w = np.where(inside, dt, 0.0)
+            glev, glf, gfr = combine([(w * (0.5 - af), A_parts(qR, n, L, g)),
+                                      (w * cf, H_parts(qR, L, g))])
             j = NBR_DIRS.index(d)
-            p["s_nbr"][c, j] = np.diag(G)
+            p["s_nbr"][cs, j, :L] = glev
+            for i in range(3):
+                p["s_nbr"][cs, j, L + i] = gfr[:, i, L + i]
             a = slots[d][0]
-            p["u"][c, a] = -dt * (h["fR"] - h["fL"])
-            p["v"][c, a] = h["daf_R"]
-            p["u"][c, a + 1] = dt * (h["uR"] - h["uL"])
-            p["v"][c, a + 1] = h["dcf_R"]
+            ins = inside[:, None]
+            u[cs, a] = np.where(ins, -dt2 * (h["fR"] - h["fL"]), 0.0)
+            v[cs, a] = np.where(ins, h["daf_R"], 0.0)
+            u[cs, a + 1] = np.where(ins, dt2 * (h["uR"] - h["uL"]), 0.0)
+            v[cs, a + 1] = np.where(ins, h["dcf_R"], 0.0)
             # level rows x velocity columns: dt (1/2 - a_f) rho_k (n_x e_u + n_y e_v)
-            p["u"][c, a + 2, :L] = dt * (0.5 - h["af"]) * qR[:L]
-            p["v"][c, a + 2, L], p["v"][c, a + 2, L + 1] = n
+            u[cs, a + 2, :L] = (w * (0.5 - af))[:, None] * qR[:, :L]
+            v[cs, a + 2, L] = np.where(inside, n[0], 0.0)
+            v[cs, a + 2, L + 1] = np.where(inside, n[1], 0.0)
             # flow rows without their diagonal entries
             for i in range(3):
-                p["u"][c, a + 3 + i, L + i] = 1.0
-                row = G[L + i].copy()
-                row[L + i] = 0.0
-                p["v"][c, a + 3 + i] = row
-        p["s_diag"][c] = np.diag(S)
-        p["s_lev_flow"][c] = S[:L, L:].T
-        p["s_flow_lev"][c] = S[L:, :L]
+                u[cs, a + 3 + i, L + i] = inside
+                row = gfr[:, i].copy()
+                row[:, L + i] = 0.0
+                v[cs, a + 3 + i] = row
+        slev, slf, sfr = combine(S)
+        p["s_diag"][cs, :L] = slev
+        for i in range(3):
+            p["s_diag"][cs, L + i] = sfr[:, i, L + i]
+        p["s_lev_flow"][cs] = slf.transpose(0, 2, 1)
+        p["s_flow_lev"][cs] = sfr[:, :, :L]
         for t, (i, j) in enumerate(corner):
-            p["s_flow"][c, t] = S[L + i, L + j]
+            p["s_flow"][cs, t] = sfr[:, i, L + j]
     for k in list(p):
         p[k] = np.ascontiguousarray(p[k])
     p["ranks"] = np.array([R_DIAG, R_OFF])

@@ -18,7 +18,7 @@ from paper_2403_09198_amd._lib import R1S_ERR_SINGULAR
 
 pytestmark = pytest.mark.gpu
 
-RANKS = [(9, 2), (3, 1), (2, 0), (1, 0), (1, 2)]
+RANKS = [(9, 2), (3, 1), (2, 0), (1, 0), (1, 2), (2, 6), (9, 6)]
 SHAPES = [(16, 16, 8), (1, 1, 1), (5, 3, 2), (7, 5, 61), (3, 4, 62), (2, 3, 125), (3, 2, 200),
           (2, 2, 253)]
 TOL64 = 1e-12
@@ -155,7 +155,7 @@ def test_gmres_paper_ranks():
         assert relnorm(host(rb.x)[r].ravel(), np.linalg.solve(J, b[r].ravel())) <= 1e-10
 
 
-@pytest.mark.parametrize("ranks", [(9, 2), (3, 1), (2, 0)], ids=lambda r: f"r{r[0]}_{r[1]}")
+@pytest.mark.parametrize("ranks", [(9, 2), (3, 1), (2, 0), (9, 6)], ids=lambda r: f"r{r[0]}_{r[1]}")
 def test_grad_kernel_matches_oracle(ranks):
     nx, ny, L, nrhs = 5, 4, 6, 3
     log(f"grad kernel ranks {ranks}")
