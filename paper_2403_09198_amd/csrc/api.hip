@@ -445,11 +445,12 @@ struct r1s_prec_s {
   int kind;
   int flags;
   Mesh g;
-  // SMW, tridiagonal uncoupled diagonal block (one wave per cell)
+  // SMW, tridiagonal level band with or without level/flow coupling (one
+  // wave per cell)
   double *facF, *facT, *invC;
   float *facF32, *facT32, *invC32;
   int* status;
-  // SMW, wide diagonal-block pattern (one lane per cell, tile-interleaved):
+  // SMW, level band wider than tridiagonal (one lane per cell, tile-interleaved):
   // band / coupling factors, Schur inverse, W and V rows per direction, C^{-1}
   double *bf, *s3i, *wv, *wvT, *cinv;
   float *bf32, *s3i32, *wv32, *wvT32, *cinv32;
@@ -461,7 +462,7 @@ struct r1s_prec_s {
 
 static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
   const bool f32 = flags & R1S_KEEP_F32, tr = flags & R1S_WITH_TRANS;
-  if (wide_pattern(g)) {
+  if (band_walk(g)) {
     band_prec_counts(g, &P->n_bf, &P->n_s3i, &P->n_wv, &P->n_cinv);
     P->bf = cv.take<double>(P->n_bf);
     P->s3i = cv.take<double>(P->n_s3i);
@@ -526,7 +527,7 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
   do {
     hipError_t e;
     if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
-    if (wide_pattern(A->g)) {
+    if (band_walk(A->g)) {
       if ((e = launch_band_setup(A->g, A->rec64, P->bf, P->s3i, P->wv, P->wvT, P->cinv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "band setup: %s", hipGetErrorString(e)); break; }
       if (P->bf32) {
         const double* src[5] = {P->bf, P->s3i, P->wv, P->wvT, P->cinv};
@@ -537,7 +538,7 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
         if (e != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       }
     } else if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
-    if (!wide_pattern(A->g) && P->facF32) {
+    if (!band_walk(A->g) && P->facF32) {
       const long long f = (long long)A->g.N * smw_rows(A->g) * A->g.mp;
       if ((e = launch_cast_f32(P->facF, P->facF32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       if (P->facT32 && (e = launch_cast_f32(P->facT, P->facT32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
@@ -573,7 +574,7 @@ extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, co
     HIP_TRY(launch_bsr_lu_apply(M->g, M->lu, M->piv, r, z, nrhs, s));
     return R1S_OK;
   }
-  if (wide_pattern(M->g)) {
+  if (band_walk(M->g)) {
     if (trans && !M->wvT) return fail(R1S_ERR_ARG, "transposed apply needs R1S_WITH_TRANS at setup");
     const bool f32 = precision == R1S_F32;
     if (f32 && !M->bf32) return fail(R1S_ERR_ARG, "float32 apply needs R1S_KEEP_F32 at setup");

@@ -8,12 +8,15 @@
 // Woodbury identity subtracts it, which is what is computed here.  With one
 // pair C is the scalar 1 + v . w.
 //
-// A0_c is the tridiagonal level band (no level/flow coupling) plus a dense
-// 3 x 3 flow corner.  The band is factored once (LU without pivoting, the
-// Thomas algorithm); each apply then runs the two bidiagonal sweeps as
-// affine-map scans across the 64 lanes of one wavefront (a serial recurrence
-// y_k = a_k y_{k-1} + b_k is a prefix composition of affine maps), carrying
-// the last value from one 64-level chunk to the next.
+// A0_c is the tridiagonal level band T plus a dense 3 x 3 flow corner F,
+// optionally with level/flow coupling (dense level rows x flow columns Ec
+// and flow rows x level columns Er).  The band is factored once (LU without
+// pivoting, the Thomas algorithm); each apply then runs the two bidiagonal
+// sweeps as affine-map scans across the 64 lanes of one wavefront (a serial
+// recurrence y_k = a_k y_{k-1} + b_k is a prefix composition of affine
+// maps), carrying the last value from one 64-level chunk to the next.  The
+// coupling is eliminated through the 3 x 3 Schur complement S3 = F - Er
+// T^{-1} Ec, which takes the place of F^{-1} in the factor record.
 #include <math.h>
 
 #include "r1s_device.hpp"
@@ -60,7 +63,8 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   const int lane = lane_id();
   const int L = g.L, m = g.m, mp = g.mp;
   const int rd = RDM == 1 ? 1 : g.rd;
-  const int SR = 3 + 2 * rd;
+  const int SR = smw_rows(g);
+  const bool arw = g.arrow;  // wave-uniform
   const double* rc = rec + (long long)c * g.F * mp;
   const double* dg = rc + (long long)F_DIAG * mp;
   const double* lo = rc + (long long)F_LO * mp;
@@ -94,9 +98,10 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   const double det = F[0][0] * Fi[0][0] + F[0][1] * Fi[1][0] + F[0][2] * Fi[2][0];
   double rn = 1.0;
   for (int i = 0; i < 3; ++i) rn *= fabs(F[i][0]) + fabs(F[i][1]) + fabs(F[i][2]);
-  bool bad = !(fabs(det) > 1e-14 * rn);
+  // with coupling only the Schur complement must be regular (below)
+  bool bad = !arw && !(fabs(det) > 1e-14 * rn);
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Fi[i][j] /= det;
+    for (int j = 0; j < 3; ++j) Fi[i][j] = arw ? 0.0 : Fi[i][j] / det;
 
   // pivots d_k by the matrix-product scan, chunk by chunk
   double D[NCH], DP[NCH];  // d_k and d_{k-1}
@@ -160,6 +165,64 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
       if (k < mp) rec_row[k] = k < m ? val[ch] : 0.0;
     }
   };
+
+  // level/flow coupling: XC = T^{-1} Ec, XR = T^{-T} Er^T, S3 = F - Er XC
+  // (the flow lanes of the factor rows are zero here, so the sweeps of the
+  // coupling columns leave zeros there)
+  double EC[3][NCH], ER[3][NCH], XC[3][NCH], XR[3][NCH];
+  if (arw) {
+    const int PX = smw_arrow_row(g);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int k = ch * WAVE + lane;
+        EC[i][ch] = k < L ? rc[(long long)(g.fa + i) * mp + k] : 0.0;
+        ER[i][ch] = k < L ? rc[(long long)(g.fa + 3 + i) * mp + k] : 0.0;
+      }
+      smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, EC[i], 0.0, 0.0, 0.0, XC[i]);
+      smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, ER[i], 0.0, 0.0, 0.0, XR[i]);
+    }
+    double S3[3][3], Si[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double sp = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) sp += ER[i][ch] * XC[j][ch];
+        S3[i][j] = F[i][j] - wave_sum_u(sp);
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int r1 = (j + 1) % 3, r2 = (j + 2) % 3, c1 = (i + 1) % 3, c2 = (i + 2) % 3;
+        Si[i][j] = S3[r1][c1] * S3[r2][c2] - S3[r1][c2] * S3[r2][c1];
+      }
+    const double d3 = S3[0][0] * Si[0][0] + S3[0][1] * Si[1][0] + S3[0][2] * Si[2][0];
+    double rn3 = 1.0;
+    for (int i = 0; i < 3; ++i) rn3 *= fabs(S3[i][0]) + fabs(S3[i][1]) + fabs(S3[i][2]);
+    if (!(fabs(d3) > 1e-14 * rn3)) bad = true;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      if (k >= L) {
+        const int i = k - L < 3 ? k - L : 0;
+        FA[ch] = Si[i][0] / d3;
+        FDI[ch] = Si[i][1] / d3;
+        FB[ch] = Si[i][2] / d3;
+        TA[ch] = Si[0][i] / d3;
+        TDI[ch] = Si[1][i] / d3;
+        TB[ch] = Si[2][i] / d3;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      put(fA + (long long)(PX + i) * mp, XC[i]);
+      put(fA + (long long)(PX + 3 + i) * mp, ER[i]);
+      if (fT) {
+        put(fT + (long long)(PX + i) * mp, XR[i]);
+        put(fT + (long long)(PX + 3 + i) * mp, EC[i]);
+      }
+    }
+  }
   put(fA + P_A * mp, FA);
   put(fA + P_DINV * mp, FDI);
   put(fA + P_B * mp, FB);
@@ -185,6 +248,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
     }
     const double* uf = uC + j * mp + L;
     smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, uf[0], uf[1], uf[2], W[j]);
+    if (arw) arrow_schur<double, NCH>(L, m, FA, FDI, FB, XC, ER, W[j]);
     put(fA + (P_W + j) * mp, W[j]);
     put(fA + (P_W + rd + j) * mp, V[j]);
     double sv = 0.0, sw = 0.0;
@@ -267,6 +331,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
       }
       const double* vf = vC + j * mp + L;
       smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V[j], vf[0], vf[1], vf[2], WT);
+      if (arw) arrow_schur<double, NCH>(L, m, TA, TDI, TB, XR, EC, WT);
       put(fT + (P_W + j) * mp, WT);
       put(fT + (P_W + rd + j) * mp, U);
     }
@@ -291,7 +356,7 @@ static hipError_t launch_setup_r(const Mesh& g, const double* rec, double* facF,
 
 hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
                             double* invC, int* status, hipStream_t s) {
-  if (wide_pattern(g)) return hipErrorInvalidValue;  // the band kernels serve those
+  if (band_walk(g)) return hipErrorInvalidValue;  // the band kernels serve those
   if (g.rd == 1) return launch_setup_r<1>(g, rec, facF, facT, invC, status, s);
   if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
   return launch_setup_r<RANK_DIAG_MAX>(g, rec, facF, facT, invC, status, s);
@@ -307,7 +372,7 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 #ifndef R1S_APPLY_CPW
 #define R1S_APPLY_CPW 1
 #endif
-template <typename TV, int NCH, int NR, bool TRANS, int RDM>
+template <typename TV, int NCH, int NR, bool TRANS, int RDM, bool ARW>
 __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __restrict__ fac,
                                                        const TV* __restrict__ invC,
                                                        const double* __restrict__ rin,
@@ -320,8 +385,11 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
   const int L = g.L, m = g.m;
   const long long mp = g.mp;
   const int rd = RDM == 1 ? 1 : g.rd;
-  const int SR = 3 + 2 * rd;
+  const int SR = smw_rows(g);
+  const int PX = smw_arrow_row(g);
+  constexpr int NX = ARW ? 3 : 1;
   TV A[CPW][NCH], DI[CPW][NCH], B[CPW][NCH], W[CPW][RDM][NCH], V[CPW][RDM][NCH];
+  TV X[CPW][NX][NCH], E[CPW][NX][NCH];
   TV R[CPW][NR][NCH], RF[CPW][NR][3];
   CapInv<TV, RDM> IC[CPW];
 #pragma unroll
@@ -339,6 +407,13 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
       for (int i = 0; i < RDM; ++i) {
         W[j][i][ch] = i < rd ? ld_stream(fc + (P_W + i) * mp + kk) : TV(0);
         V[j][i][ch] = i < rd ? ld_stream(fc + (P_W + rd + i) * mp + kk) : TV(0);
+      }
+      if constexpr (ARW) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          X[j][i][ch] = ld_stream(fc + (PX + i) * mp + kk);
+          E[j][i][ch] = ld_stream(fc + (PX + 3 + i) * mp + kk);
+        }
       }
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -360,6 +435,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
       TV X0[NCH];
       smw_sweeps<TV, NCH, TRANS>(L, m, A[j], DI[j], B[j], R[j][r], RF[j][r][0], RF[j][r][1],
                                  RF[j][r][2], X0);
+      if constexpr (ARW) arrow_schur<TV, NCH>(L, m, A[j], DI[j], B[j], X[j], E[j], X0);
       TV s[RDM], z[RDM];
 #pragma unroll
       for (int i = 0; i < RDM; ++i) {
@@ -388,19 +464,22 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
 // Each wave scans its chunk; the chunk compositions go through LDS and every
 // wave folds in the compositions of the chunks before it (forward sweep) or
 // after it (backward sweep), in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, int RDM>
+template <typename TV, int NCH, int NR, bool TRANS, int RDM, bool ARW>
 __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __restrict__ fac,
                                                            const TV* __restrict__ invC,
                                                            const double* __restrict__ rin,
                                                            double* __restrict__ zout, int r0) {
   __shared__ TV fa[NR][NCH], fb[NR][NCH], ga[NR][NCH], gb[NR][NCH], ss[NR][RDM][NCH];
+  constexpr int NX = ARW ? 3 : 1;
+  __shared__ TV tt[NR][NX][NCH], zz[NR][NX];
   const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
   const int L = g.L, m = g.m;
   const long long mp = g.mp;
   const int rd = RDM == 1 ? 1 : g.rd;
-  const int SR = 3 + 2 * rd;
+  const int SR = smw_rows(g);
+  const int PX = smw_arrow_row(g);
   const int k = wv * WAVE + lane;
   const int kk = k < m ? k : m - 1;
   const bool lev = k < L;
@@ -414,6 +493,14 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
   for (int i = 0; i < RDM; ++i) {
     W[i] = i < rd ? ld_stream(fc + (P_W + i) * mp + kk) : TV(0);
     V[i] = i < rd ? ld_stream(fc + (P_W + rd + i) * mp + kk) : TV(0);
+  }
+  TV X[NX], E[NX];
+  if constexpr (ARW) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      X[i] = ld_stream(fc + (PX + i) * mp + kk);
+      E[i] = ld_stream(fc + (PX + 3 + i) * mp + kk);
+    }
   }
   TV R[NR], RF[NR][3];
 #pragma unroll
@@ -462,6 +549,37 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
     const TV x0 = b2[r] + a2[r] * carry;
     const TV xf = A * RF[r][0] + DI * RF[r][1] + B * RF[r][2];
     X0[r] = lev ? x0 : (k < m ? xf : TV(0));
+  }
+  if constexpr (ARW) {  // the Schur step of the coupling, across the waves
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const TV tp = wave_sum_u(lev ? E[i] * X0[r] : TV(0));
+        if (lane == 0) tt[r][i][wv] = tp;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      TV t[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        t[i] = tt[r][i][0];
+#pragma unroll
+        for (int w = 1; w < NCH; ++w) t[i] += tt[r][i][w];
+      }
+      if (!lev && k < m) {
+        X0[r] -= A * t[0] + DI * t[1] + B * t[2];
+        zz[r][k - L] = X0[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (lev) X0[r] -= X[0] * zz[r][0] + X[1] * zz[r][1] + X[2] * zz[r][2];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
 #pragma unroll
     for (int i = 0; i < RDM; ++i) {
       if (i >= rd) break;
@@ -492,7 +610,7 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
 }
 
 // Right-hand sides per launch: 4 / 2 / 1 (2 / 1 with several diagonal pairs).
-template <typename TV, int NCH, bool TRANS, int RDM>
+template <typename TV, int NCH, bool TRANS, int RDM, bool ARW>
 static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                  double* z, int nrhs, hipStream_t s) {
 #ifndef R1S_NO_WG_CELL
@@ -501,13 +619,13 @@ static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, c
     while (r0 < nrhs) {
       const int rem = nrhs - r0;
       if (RDM == 1 && rem >= 4) {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM, ARW>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += RDM == 1 ? 4 : 2;
       } else if (rem >= 2) {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 2, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 2, TRANS, RDM, ARW>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += 2;
       } else {
-        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 1, TRANS, RDM>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
+        hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, 1, TRANS, RDM, ARW>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += 1;
       }
     }
@@ -520,28 +638,28 @@ static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, c
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
     if (RDM == 1 && rem >= 4) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM, ARW>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += RDM == 1 ? 4 : 2;
     } else if (rem >= 2) {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 2, TRANS, RDM, ARW>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 2;
     } else {
-      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS, RDM>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+      hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS, RDM, ARW>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += 1;
     }
   }
   return hipGetLastError();
 }
 
-template <typename TV, bool TRANS, int RDM>
+template <typename TV, bool TRANS, int RDM, bool ARW>
 static hipError_t launch_apply_nch(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                    double* z, int nrhs, hipStream_t s) {
   const int nch = (g.m + WAVE - 1) / WAVE;
   switch (nch) {
-    case 1: return launch_apply_t<TV, 1, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
-    case 2: return launch_apply_t<TV, 2, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
-    case 3: return launch_apply_t<TV, 3, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
-    case 4: return launch_apply_t<TV, 4, TRANS, RDM>(g, fac, invC, r, z, nrhs, s);
+    case 1: return launch_apply_t<TV, 1, TRANS, RDM, ARW>(g, fac, invC, r, z, nrhs, s);
+    case 2: return launch_apply_t<TV, 2, TRANS, RDM, ARW>(g, fac, invC, r, z, nrhs, s);
+    case 3: return launch_apply_t<TV, 3, TRANS, RDM, ARW>(g, fac, invC, r, z, nrhs, s);
+    case 4: return launch_apply_t<TV, 4, TRANS, RDM, ARW>(g, fac, invC, r, z, nrhs, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -549,14 +667,16 @@ static hipError_t launch_apply_nch(const Mesh& g, const TV* fac, const TV* invC,
 template <typename TV, bool TRANS>
 static hipError_t launch_apply_rank(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                     double* z, int nrhs, hipStream_t s) {
-  if (g.rd == 1) return launch_apply_nch<TV, TRANS, 1>(g, fac, invC, r, z, nrhs, s);
   if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
-  return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX>(g, fac, invC, r, z, nrhs, s);
+  // level/flow coupling: one instantiation at the largest pair count
+  if (g.arrow) return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX, true>(g, fac, invC, r, z, nrhs, s);
+  if (g.rd == 1) return launch_apply_nch<TV, TRANS, 1, false>(g, fac, invC, r, z, nrhs, s);
+  return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX, false>(g, fac, invC, r, z, nrhs, s);
 }
 
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s) {
-  if (wide_pattern(g)) return hipErrorInvalidValue;
+  if (band_walk(g)) return hipErrorInvalidValue;
   if (f32)
     return trans ? launch_apply_rank<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
                  : launch_apply_rank<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);

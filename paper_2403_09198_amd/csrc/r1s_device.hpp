@@ -95,7 +95,15 @@ __host__ __device__ inline int pair_start(const Mesh& g, int d) {
 __host__ __device__ inline int nbr_row(const Mesh& g, int d) {
   return F_NBR + (g.graph ? d - GSLOT : (d < 2 ? d : d - 1));
 }
-__host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * g.rd; }
+// Rows of the wave-per-cell SMW factor record of a cell: the three sweep
+// rows, W and V (rd each), and with level/flow coupling the three columns
+// T^{-1} E and the three coupling rows of the Schur step.
+__host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * g.rd + (g.arrow ? 6 : 0); }
+__host__ __device__ inline int smw_arrow_row(const Mesh& g) { return 3 + 2 * g.rd; }
+// The block-Jacobi needs the one-lane-per-cell band factorisation when the
+// level band is wider than tridiagonal; the tridiagonal band, with or
+// without level/flow coupling, runs wave-per-cell.
+__host__ __device__ inline bool band_walk(const Mesh& g) { return g.band > 1; }
 
 // Workgroup id -> logical tile.  With R1S_XCD_REMAP each XCD (which
 // receives every NXCD-th workgroup) works on one contiguous range of tiles;
@@ -355,6 +363,47 @@ __device__ inline void smw_sweeps(int L, int m, const T (&A)[NCH], const T (&DI)
     const T xf = A[ch] * rf0 + DI[ch] * rf1 + B[ch] * rf2;
     X0[ch] = lev ? x0 : (k < m ? xf : T(0));
   }
+}
+
+// Level/flow coupling on a tridiagonal level band, A0 = [T Ec; Er F]: the
+// block solve by the Schur complement of the flow unknowns, S3 = F - Er
+// T^{-1} Ec.  On entry X0 holds the sweeps' output: T^{-1} r on the level
+// lanes, S3^{-1} r_F on the flow lanes (the lane's S3^{-1} row sits in the
+// flow lanes of A, DI, B).  With t = Er (T^{-1} r_L): x_F = S3^{-1} (r_F -
+// t) and x_L = T^{-1} r_L - X x_F, X = T^{-1} Ec (rows X[i], zero past the
+// levels; E[i] the coupling rows Er, zero past the levels).  The transposed
+// solve uses the same steps on A0^T = [T^T Er^T; Ec^T F^T].
+template <typename T, int NCH>
+__device__ inline void arrow_schur(int L, int m, const T (&A)[NCH], const T (&DI)[NCH],
+                                   const T (&B)[NCH], const T (&X)[3][NCH], const T (&E)[3][NCH],
+                                   T (&X0)[NCH]) {
+  const int lane = lane_id();
+  T t[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) s += ch * WAVE + lane < L ? E[i][ch] * X0[ch] : T(0);
+    t[i] = wave_sum_u(s);
+  }
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int k = ch * WAVE + lane;
+    if (k >= L && k < m) X0[ch] -= A[ch] * t[0] + DI[ch] * t[1] + B[ch] * t[2];
+  }
+  T z[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int k = L + i, kc = k / WAVE, kl = k % WAVE;
+    T v = T(0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      if (ch == kc) v = readlane(X0[ch], kl);
+    z[i] = v;
+  }
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+    if (ch * WAVE + lane < L) X0[ch] -= X[0][ch] * z[0] + X[1][ch] * z[1] + X[2][ch] * z[2];
 }
 
 // Per-cell inverse capacitance C^{-1} of the Woodbury correction.  With one

@@ -75,11 +75,12 @@ def test_matvec_and_smw_parity(nx, ny, L, band, arrow, ranks):
     assert _per_cell_rel(host(M.apply(rd, trans=True, precision="f32")), zreft) <= tol32s
 
 
+@pytest.mark.parametrize("band,L", [(3, 61), (1, 61), (1, 125)])
 @pytest.mark.parametrize("nrhs", [1, 2, 5])
-def test_batched_rhs_match_single(nrhs):
-    nx, ny, L = 9, 5, 61
-    log(f"pattern batches nrhs={nrhs}")
-    p, A, M = _setup(nx, ny, L, 3, True, (9, 2), seed=2)
+def test_batched_rhs_match_single(nrhs, band, L):
+    nx, ny = 9, 5
+    log(f"pattern batches nrhs={nrhs} band={band} L={L}")
+    p, A, M = _setup(nx, ny, L, band, True, (9, 2), seed=2)
     x = vec(gen.make_vector(nx, ny, L, nrhs=nrhs, seed=3))
     for name, f in (("J x", lambda v: A.matvec(v)), ("J^T x", lambda v: A.matvec(v, trans=True)),
                     ("M r", lambda v: M.apply(v)), ("M^T r", lambda v: M.apply(v, trans=True))):
@@ -190,6 +191,22 @@ def test_zero_level_row_is_reported():
     with pytest.raises(r1s.R1SError) as ei:
         r1s.SMWPreconditioner(A)
     assert ei.value.code == R1S_ERR_SINGULAR and "cell 9" in str(ei.value)
+
+
+@pytest.mark.parametrize("band", [1, 3])
+def test_singular_schur_complement_is_reported(band):
+    nx, ny, L = 4, 3, 6
+    p = gen.make_problem(nx, ny, L, seed=1, band=band, arrow=True)
+    c = 5
+    # flow row 0 of S_cc is zero (with its coupling row): F - Er T^{-1} Ec
+    # has a zero row
+    p["s_diag"][c, L] = 0.0
+    p["s_flow"][c, 0:2] = 0.0
+    p["s_flow_lev"][c, 0] = 0.0
+    A = r1s.R1Matrix(nx, ny, L, to_dev(p), band=band, arrow=True)
+    with pytest.raises(r1s.R1SError) as ei:
+        r1s.SMWPreconditioner(A)
+    assert ei.value.code == R1S_ERR_SINGULAR and "cell 5" in str(ei.value)
 
 
 def test_pattern_arrays_are_checked():
