@@ -216,7 +216,9 @@ typedef struct {
   double inner_rtol;/* mixed mode: relative tolerance of each inner solve   */
   int max_outer;    /* mixed mode: iterative-refinement steps               */
   int always_reorth;/* 1: reorthogonalise every Arnoldi step (CGS2); 0: only
-                       when |w - V h| < |w| / sqrt(2) (selective CGS)       */
+                       when |w - V h| < |w| / sqrt(2) (selective CGS,
+                       decided per right-hand side; steps with more than 16
+                       basis vectors always reorthogonalise)                */
 } r1s_gmres_opts;
 
 typedef struct {

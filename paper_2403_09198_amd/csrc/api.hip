@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -782,6 +783,7 @@ extern "C" int r1s_bsr_destroy(r1s_bsr B) {
 // ---------------------------------------------------------------- GMRES ---
 struct GmresWork {
   double *V, *w, *z, *t, *part, *hdev, *ydev, *scal, *r64, *d;
+  int* need;  // per right-hand side: the second Gram-Schmidt pass ran
   int nblk;
 };
 
@@ -798,7 +800,70 @@ static void gmres_layout(Carver& cv, const Mesh& g, int k, int nrhs, bool mixed,
   W->scal = cv.take<double>((size_t)nrhs * 4);
   W->r64 = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
   W->d = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
+  W->need = cv.take<int>((size_t)nrhs);
 }
+
+// Pinned host staging for the Arnoldi coefficients, written by the last
+// kernel of each step, so that the host reads them behind the next step's
+// kernels.  Two slots (alternating steps), each h1, h2 [nrhs][k + 2] and
+// need [nrhs] (as doubles), plus one event per slot.  Pooled per device and reused across solves; the pool is
+// never freed (the memory returns to the system at process exit).
+struct Staging {
+  int device = -1;
+  size_t bytes = 0;
+  char* mem = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+static std::mutex g_staging_mu;
+static std::vector<Staging*> g_staging_free;
+
+static int staging_acquire(size_t bytes, Staging** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Staging* st = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_staging_mu);
+    for (size_t i = 0; i < g_staging_free.size(); ++i)
+      if (g_staging_free[i]->device == dev) {
+        st = g_staging_free[i];
+        g_staging_free.erase(g_staging_free.begin() + i);
+        break;
+      }
+  }
+  if (!st) {
+    st = new (std::nothrow) Staging();
+    if (!st) return fail(R1S_ERR_ALLOC, "host allocation failed");
+    st->device = dev;
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming) != hipSuccess) {
+        delete st;
+        return fail(R1S_ERR_HIP, "event creation failed");
+      }
+  }
+  if (st->bytes < bytes) {
+    if (st->mem) (void)hipHostFree(st->mem);
+    st->mem = nullptr;
+    st->bytes = 0;
+    if (hipHostMalloc((void**)&st->mem, bytes, hipHostMallocDefault) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_staging_mu);
+      g_staging_free.push_back(st);
+      return fail(R1S_ERR_ALLOC, "pinned host allocation of %zu bytes failed", bytes);
+    }
+    st->bytes = bytes;
+  }
+  *out = st;
+  return R1S_OK;
+}
+
+struct StagingLease {
+  Staging* st = nullptr;
+  ~StagingLease() {
+    if (st) {
+      std::lock_guard<std::mutex> lk(g_staging_mu);
+      g_staging_free.push_back(st);
+    }
+  }
+};
 
 static int check_opts(const r1s_gmres_opts* o) {
   if (!o) return fail(R1S_ERR_ARG, "opts is NULL");
@@ -899,19 +964,24 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
   Basis Vb{W.V, n, (long long)(k + 1) * n};
   std::vector<double> H((size_t)nrhs * (k + 1) * k), cs((size_t)nrhs * k), sn((size_t)nrhs * k),
-      gv((size_t)nrhs * (k + 1)), y((size_t)nrhs * (k + 1)), hbuf((size_t)nrhs * HS * 2),
+      gv((size_t)nrhs * (k + 1)), y((size_t)nrhs * (k + 1)),
       beta, w0(nrhs);
   std::vector<int> jend(nrhs), done(nrhs);
   auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
+  StagingLease lease;
+  const size_t slot_doubles = (size_t)nrhs * (2 * HS + 1);
+  if (int e = staging_acquire(2 * slot_doubles * sizeof(double), &lease.st)) return e;
+  double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
 
   for (int cycle = 0;; ++cycle) {
-    // true residual of the current iterate
-    if (cycle == 0 && !x0_given) {
-      HIP_TRY(hipMemcpyAsync(W.w, b, (size_t)nrhs * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // true residual of the current iterate (x0 = 0: r = b, whose norms are known)
+    const bool from_b = cycle == 0 && !x0_given;
+    if (from_b) {
+      beta = bnorm;
     } else {
       if (int e = op_residual(c, b, x, W.w, nrhs)) return e;
+      if (int e = norms(g, W, W.w, nrhs, s, beta)) return e;
     }
-    if (int e = norms(g, W, W.w, nrhs, s, beta)) return e;
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
       if (!(beta[r] == beta[r]) || isinf(beta[r])) return fail(R1S_ERR_NONFINITE, "residual of right-hand side %d is not finite", r);
@@ -929,65 +999,28 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       gv[(size_t)r * (k + 1)] = beta[r];
     }
     HIP_TRY(hipMemcpyAsync(W.scal, y.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale(W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
+    HIP_TRY(launch_scale(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
 
-    for (int j = 0; j < k; ++j) {
-      double* Vj = W.V + (long long)j * n;
-      // z = M v_j ; w = op(z)   (v_j of every rhs: strided copy into t)
-      if (nrhs == 1) {
-        if (int e = prec_apply(c, Vj, W.z, 1)) return e;
-      } else {
-        HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
-                                 n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
-        if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
-      }
-      if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
+    // Arnoldi steps.  The coefficients of step j reach the host through the
+    // pinned staging slot j % 2 while step j + 1 runs on the device; the host
+    // updates the least-squares problem of step j only after it has queued
+    // step j + 1, so the device never waits for the host.  When step j meets
+    // the tolerance, step j + 1 was computed for nothing and is dropped.
+    auto process = [&](int j) -> bool {  // true: every right-hand side is done
       const int nv = j + 1;
-      // Classical Gram-Schmidt: h1 = V^T w and |w|^2 in one pass.  The norm
-      // of w - V h1 follows from |w|^2 - |h1|^2 (V orthonormal); a second
-      // pass (reorthogonalisation) runs only when that norm drops below
-      // |w| / sqrt(2) for some right-hand side (Daniel-Gragg-Kaufman-Stewart
-      // criterion), where the subtraction would lose accuracy.
-      HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
-      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, W.hdev, s));
-      HIP_TRY(hipMemcpyAsync(hbuf.data(), W.hdev, (size_t)nrhs * (nv + 1) * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      bool reorth = always_reorth;
-      for (int r = 0; r < nrhs; ++r) {
-        if (done[r]) continue;
-        const double* h1r = hbuf.data() + (size_t)r * (nv + 1);
-        double hh = 0.0;
-        for (int i = 0; i < nv; ++i) hh += h1r[i] * h1r[i];
-        if (!(h1r[nv] - hh > 0.5 * h1r[nv])) reorth = true;
-      }
-      double* h2 = W.hdev + (size_t)nrhs * HS;
-      if (reorth) {
-        if (nv <= update_multidot_max()) {  // w -= V h1 and V^T w in one pass
-          HIP_TRY(launch_update_multidot(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, W.part,
-                                         W.nblk, s));
-        } else {
-          HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
-          HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
-        }
-        HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
-        HIP_TRY(hipMemcpyAsync(hbuf.data() + (size_t)nrhs * HS, h2,
-                               (size_t)nrhs * (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-      }
-      // v_{j+1} = (w - V h) / |w - V h| with h the last pass's coefficients
-      const double* hlast = reorth ? h2 : W.hdev;
-      HIP_TRY(launch_update_normalize(Vb, nv, hlast, nv + 1, hlast + nv, nv + 1, W.w, n,
-                                      W.V + (long long)(j + 1) * n, n, nrhs, s));
-      if (reorth) HIP_TRY(hipStreamSynchronize(s));
+      const double* h1 = stage[j & 1];  // layout of k_update_normalize's staging
+      const double* h2s = h1 + (size_t)nrhs * (nv + 1);
+      const double* needs = h2s + (size_t)nrhs * (nv + 1);
       bool all_done = true;
       for (int r = 0; r < nrhs; ++r) {
         if (done[r]) continue;
-        const double* h1r = hbuf.data() + (size_t)r * (nv + 1);
-        const double* h2r = hbuf.data() + (size_t)nrhs * HS + (size_t)r * (nv + 1);
-        const double* hl = reorth ? h2r : h1r;  // the pass the new vector comes from
+        const double* h1r = h1 + (size_t)r * (nv + 1);
+        const double* h2r = h2s + (size_t)r * (nv + 1);
+        const bool two = needs[r] != 0.0;
+        const double* hl = two ? h2r : h1r;  // the pass the new vector comes from
         double hh = 0.0;
         for (int i = 0; i < nv; ++i) {
-          Hat(r, i, j) = h1r[i] + (reorth ? h2r[i] : 0.0);
+          Hat(r, i, j) = h1r[i] + (two ? h2r[i] : 0.0);
           hh += hl[i] * hl[i];
         }
         const double q = hl[nv] - hh;
@@ -1016,7 +1049,61 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         if (breakdown || fabs(gr[j + 1]) <= rtol * bnorm[r]) done[r] = 1;
         all_done = all_done && done[r];
       }
-      if (all_done) break;
+      return all_done;
+    };
+    int pending = -1;  // step whose coefficients are staged but not yet used
+    bool finished = false;
+    for (int j = 0; j < k; ++j) {
+      double* Vj = W.V + (long long)j * n;
+      // z = M v_j ; w = op(z)   (v_j of every rhs: strided copy into t)
+      if (nrhs == 1) {
+        if (int e = prec_apply(c, Vj, W.z, 1)) return e;
+      } else {
+        HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
+                                 n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+        if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
+      }
+      if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
+      const int nv = j + 1;
+      // Classical Gram-Schmidt: h1 = V^T w and |w|^2 in one pass.  The norm
+      // of w - V h1 follows from |w|^2 - |h1|^2 (V orthonormal); a second
+      // pass (reorthogonalisation) runs where that norm dropped below |w| /
+      // sqrt(2) (Daniel-Gragg-Kaufman-Stewart criterion, decided on the
+      // device per right-hand side), or on every step with always_reorth or
+      // a basis of more than 16 vectors.
+      // (h1, h2: rows of nv + 1 values per rhs)
+      double* h2 = W.hdev + (size_t)nrhs * HS;
+      HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, W.hdev, s));
+      const bool fused = nv <= update_multidot_max();
+      if (fused) {  // w -= V h1 and V^T w in one pass, where needed
+        HIP_TRY(launch_update_multidot(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, W.part, W.nblk,
+                                       always_reorth, W.need, s));
+      } else {
+        HIP_TRY(launch_update(Vb, nv, W.hdev, nv + 1, W.w, n, n, nrhs, s));
+        HIP_TRY(launch_multidot(Vb, nv, W.w, n, n, nrhs, W.part, W.nblk, true, s));
+      }
+      HIP_TRY(launch_reduce(W.part, nrhs * (nv + 1), W.nblk, h2, s));
+      // v_{j+1} = (w - V h) / |w - V h| with h the last pass's coefficients;
+      // the coefficients go to the host staging slot of this step
+      const int slot = j & 1;
+      HIP_TRY(launch_update_normalize(Vb, nv, W.hdev, h2, nv + 1, fused ? W.need : nullptr, W.w,
+                                      n, W.V + (long long)(j + 1) * n, n, nrhs, s, stage[slot]));
+      HIP_TRY(hipEventRecord(lease.st->ev[slot], s));
+      if (pending >= 0) {
+        HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));
+        const bool all_done = process(pending);
+        pending = -1;
+        if (all_done) {
+          finished = true;
+          break;
+        }
+      }
+      pending = j;
+    }
+    if (!finished && pending >= 0) {
+      HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));
+      process(pending);
     }
     // y = R^{-1} g per rhs; x += M (V y)
     std::fill(y.begin(), y.end(), 0.0);

@@ -113,16 +113,31 @@ static inline dim3 vec_grid(long long n, int nrhs) {
 // loads V_i[e] once into registers, forms w1[e] = w[e] - sum_i h_i V_i[e],
 // stores it, and accumulates V_i[e] w1[e] and w1[e]^2 for the next
 // coefficients (partials per block, reduced by k_reduce as for k_multidot).
+// The pass runs only where it is needed (Daniel-Gragg-Kaufman-Stewart: the
+// first pass left |w - V h|^2 = |w|^2 - |h|^2 <= |w|^2 / 2), or always; the
+// decision per right-hand side goes to need[r], and a skipped pass leaves w
+// and writes zero partials.
 template <int NVMAX>
 __global__ __launch_bounds__(KB) void k_update_multidot(Basis B, int nv, const double* __restrict__ h,
                                                         int hstride, double* __restrict__ w,
                                                         long long wstride, long long n,
-                                                        double* __restrict__ part, int nblk) {
+                                                        double* __restrict__ part, int nblk,
+                                                        int always, int* __restrict__ need) {
   __shared__ double sh[KB / WAVE];
   const int r = blockIdx.y;
   const double* Vr = B.V + (long long)r * B.rstride;
   const double* hr = h + (long long)r * hstride;
   double* wr = w + (long long)r * wstride;
+  double* pr = part + (long long)r * (nv + 1) * nblk;
+  double h2sum = 0.0;
+  for (int i = 0; i < nv; ++i) h2sum += hr[i] * hr[i];
+  const bool run = always || !(hr[nv] - h2sum > 0.5 * hr[nv]);  // block-uniform
+  if (blockIdx.x == 0 && threadIdx.x == 0) need[r] = run ? 1 : 0;
+  if (!run) {  // every block of this right-hand side takes this branch
+    if (threadIdx.x == 0)
+      for (int i = 0; i <= nv; ++i) pr[(long long)i * nblk + blockIdx.x] = 0.0;
+    return;
+  }
   double hv[NVMAX], acc[NVMAX];
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) {
@@ -144,7 +159,6 @@ __global__ __launch_bounds__(KB) void k_update_multidot(Basis B, int nv, const d
     for (int i = 0; i < NVMAX; ++i) acc[i] += v[i] * a;
     accn += a * a;
   }
-  double* pr = part + (long long)r * (nv + 1) * nblk;
 #pragma unroll
   for (int i = 0; i < NVMAX; ++i) {
     if (i >= nv) break;
@@ -159,13 +173,13 @@ int update_multidot_max() { return 16; }
 
 hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride, double* w,
                                   long long wstride, long long n, int nrhs, double* part, int nblk,
-                                  hipStream_t s) {
+                                  bool always, int* need, hipStream_t s) {
   if (nv <= 8)
     hipLaunchKernelGGL(k_update_multidot<8>, dim3(nblk, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
-                       w, wstride, n, part, nblk);
+                       w, wstride, n, part, nblk, (int)always, need);
   else if (nv <= 16)
     hipLaunchKernelGGL(k_update_multidot<16>, dim3(nblk, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
-                       w, wstride, n, part, nblk);
+                       w, wstride, n, part, nblk, (int)always, need);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -194,24 +208,43 @@ hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* 
 }
 
 // vout = (w - sum_i h_i V_i) / sqrt(max(0, nrm2 - sum_i h_i^2)); zero if that
-// norm is zero.  The norm of the new vector follows from the norm before
-// this pass because V is orthonormal.  NVMAX > 0: the basis values of an
-// element are all loaded before use (nv <= NVMAX); NVMAX = 0: any nv.
+// norm is zero, with (h, nrm2) = the coefficients and |w|^2 of the last pass
+// that ran: h2 where need[r] (or need == nullptr: the second pass always
+// ran), else h1 (rows of hstride values, |w|^2 at index nv).  The norm of the
+// new vector follows from the norm before this pass because V is
+// orthonormal.  NVMAX > 0: the basis values of an element are all loaded
+// before use (nv <= NVMAX); NVMAX = 0: any nv.  With stage (host memory the
+// device can write), block (0, r) also copies row r of h1, h2 and need[r]
+// there: h1 rows at stage, h2 rows at stage + nrhs * hstride, the flags
+// after them (as doubles, 1 where the second pass ran).
 template <int NVMAX>
 __global__ __launch_bounds__(KB) void k_update_normalize(Basis B, int nv,
-                                                         const double* __restrict__ h, int hstride,
-                                                         const double* __restrict__ nrm2,
-                                                         int nstride, const double* __restrict__ w,
+                                                         const double* __restrict__ h1,
+                                                         const double* __restrict__ h2,
+                                                         int hstride, const int* __restrict__ need,
+                                                         const double* __restrict__ w,
                                                          long long wstride,
-                                                         double* __restrict__ vout, long long n) {
+                                                         double* __restrict__ vout, long long n,
+                                                         double* stage) {
   const int r = blockIdx.y;
+  if (stage && blockIdx.x == 0) {
+    const int nrhs = gridDim.y;
+    const long long o = (long long)r * hstride;
+    for (int i = threadIdx.x; i < hstride; i += KB) {
+      stage[o + i] = h1[o + i];
+      stage[(long long)nrhs * hstride + o + i] = h2[o + i];
+    }
+    if (threadIdx.x == 0)
+      stage[2LL * nrhs * hstride + r] = (need == nullptr || need[r]) ? 1.0 : 0.0;
+    __threadfence_system();
+  }
   const double* Vr = B.V + (long long)r * B.rstride;
-  const double* hr = h + (long long)r * hstride;
+  const double* hr = ((need == nullptr || need[r]) ? h2 : h1) + (long long)r * hstride;
   const double* wr = w + (long long)r * wstride;
   double* vr = vout + (long long)r * B.rstride;
   double hh = 0.0;
   for (int i = 0; i < nv; ++i) hh += hr[i] * hr[i];
-  const double q = nrm2[(long long)r * nstride] - hh;
+  const double q = hr[nv] - hh;
   const double inv = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
   if constexpr (NVMAX > 0) {
     double hv[NVMAX];
@@ -237,19 +270,19 @@ __global__ __launch_bounds__(KB) void k_update_normalize(Basis B, int nv,
   }
 }
 
-hipError_t launch_update_normalize(Basis B, int nv, const double* h, int hstride,
-                                   const double* nrm2, int nstride, const double* w,
+hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const double* h2,
+                                   int hstride, const int* need, const double* w,
                                    long long wstride, double* vout, long long n, int nrhs,
-                                   hipStream_t s) {
+                                   hipStream_t s, double* stage) {
   if (nv <= 8)
-    hipLaunchKernelGGL(k_update_normalize<8>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
-                       nrm2, nstride, w, wstride, vout, n);
+    hipLaunchKernelGGL(k_update_normalize<8>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h1, h2,
+                       hstride, need, w, wstride, vout, n, stage);
   else if (nv <= 16)
-    hipLaunchKernelGGL(k_update_normalize<16>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h,
-                       hstride, nrm2, nstride, w, wstride, vout, n);
+    hipLaunchKernelGGL(k_update_normalize<16>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h1, h2,
+                       hstride, need, w, wstride, vout, n, stage);
   else
-    hipLaunchKernelGGL(k_update_normalize<0>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h, hstride,
-                       nrm2, nstride, w, wstride, vout, n);
+    hipLaunchKernelGGL(k_update_normalize<0>, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, h1, h2,
+                       hstride, need, w, wstride, vout, n, stage);
   return hipGetLastError();
 }
 

@@ -106,13 +106,13 @@ hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hi
 int update_multidot_max();
 hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride, double* w,
                                   long long wstride, long long n, int nrhs, double* part, int nblk,
-                                  hipStream_t s);
+                                  bool always, int* need, hipStream_t s);
 hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* w,
                          long long wstride, long long n, int nrhs, hipStream_t s);
-hipError_t launch_update_normalize(Basis B, int nv, const double* h, int hstride,
-                                   const double* nrm2, int nstride, const double* w,
+hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const double* h2,
+                                   int hstride, const int* need, const double* w,
                                    long long wstride, double* vout, long long n, int nrhs,
-                                   hipStream_t s);
+                                   hipStream_t s, double* stage = nullptr);
 hipError_t launch_scale(const double* w, long long wstride, const double* inv, double* out,
                         long long ostride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_combine(Basis B, int nv, const double* y, int ystride, double* out,

@@ -256,6 +256,19 @@ def r1s_grad(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
 
 
 # -------------------------------------------------------------- classes ---
+def _release(obj, destroy):
+    """Destroy obj.h through the library handle the object took at creation
+    (at interpreter exit the module's own state may already be gone)."""
+    h = getattr(obj, "h", None)
+    if h is None or not h.value:
+        return
+    handle = getattr(obj, "_lib", None)
+    if handle is None:
+        return
+    getattr(handle, destroy)(h)
+    obj.h = None
+
+
 class R1Matrix:
     """Structured block r1-sparse Jacobian on one GPU (packed, caller memory).
 
@@ -278,15 +291,13 @@ class R1Matrix:
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device
         self.device = dev
+        self._lib = lib()
         self.mem = _buffer(r1s_mat_size(nx, ny, L_levels, self.layout, self.flags), dev)
         self.h = r1s_mat_init(nx, ny, L_levels, self.layout, self.flags, values, self.mem,
                               stream)
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().r1s_mat_destroy(h)
-            self.h = None
+    def __del__(self, _release=_release):  # bound now: module globals are gone at exit
+        _release(self, "r1s_mat_destroy")
 
     def update(self, values, stream=None):
         r1s_mat_update(self.h, values, self.nx, self.ny, self.L, self.layout, stream)
@@ -332,6 +343,7 @@ class R1GraphMatrix(R1Matrix):
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device
         self.device = dev
+        self._lib = lib()
         self.mem = _buffer(r1s_mat_size_graph(N, L_levels, self.layout, self.indptr, self.indices,
                                               self.flags), dev)
         self.h = r1s_mat_init_graph(N, L_levels, self.layout, self.indptr, self.indices,
@@ -347,14 +359,12 @@ class SMWPreconditioner:
     def __init__(self, A: R1Matrix, keep_f32=False, with_trans=False, stream=None):
         self.A = A
         self.flags = (L.R1S_KEEP_F32 if keep_f32 else 0) | (L.R1S_WITH_TRANS if with_trans else 0)
+        self._lib = lib()
         self.mem = _buffer(r1s_prec_size(A.h, self.flags), A.device)
         self.h = r1s_prec_setup(A.h, self.flags, self.mem, stream)
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().r1s_prec_destroy(h)
-            self.h = None
+    def __del__(self, _release=_release):  # bound now: module globals are gone at exit
+        _release(self, "r1s_prec_destroy")
 
     def apply(self, r, trans=False, precision="f64", out=None, stream=None):
         nrhs = _need_vec(r, "r", self.A.n)
@@ -369,14 +379,12 @@ class BSRMatrix:
 
     def __init__(self, A: R1Matrix, stream=None):
         self.A = A
+        self._lib = lib()
         self.mem = _buffer(r1s_bsr_size(A.h), A.device)
         self.h = r1s_bsr_init(A.h, self.mem, stream)
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().r1s_bsr_destroy(h)
-            self.h = None
+    def __del__(self, _release=_release):  # bound now: module globals are gone at exit
+        _release(self, "r1s_bsr_destroy")
 
     def matvec(self, x, out=None, stream=None):
         nrhs = _need_vec(x, "x", self.A.n)
@@ -391,14 +399,12 @@ class DenseLUPreconditioner:
     def __init__(self, B: BSRMatrix, stream=None):
         self.B = B
         self.A = B.A
+        self._lib = lib()
         self.mem = _buffer(r1s_bsr_prec_size(B.h), B.A.device)
         self.h = r1s_bsr_prec_setup(B.h, self.mem, stream)
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().r1s_prec_destroy(h)
-            self.h = None
+    def __del__(self, _release=_release):  # bound now: module globals are gone at exit
+        _release(self, "r1s_prec_destroy")
 
     def apply(self, r, out=None, stream=None):
         nrhs = _need_vec(r, "r", self.A.n)
