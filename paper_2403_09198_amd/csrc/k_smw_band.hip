@@ -289,46 +289,44 @@ hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, doubl
 }
 
 // ---------------------------------------------------------------- apply ----
-// Software-pipelined walk over `count` steps: the loads of block b + 1 (U
-// steps) are issued before block b is computed.  Loads use clamped step
-// indices, so every load is valid and unconditional; only the computation of
-// steps past the end is skipped (a wave-uniform test).
+// Software-pipelined walk: the loads of block b + 1 (U steps) are issued
+// before block b is computed, and the walk runs whole pairs of blocks, so
+// nothing in the loop is conditional: steps past the end are dead steps
+// that the load and compute functions turn into no-ops (zero coefficients,
+// a scratch slot for their result).  With no load or store under a branch,
+// the compiler waits for exactly the loads of the block being computed.
 template <int U, typename Step, typename LoadF, typename CompF>
 __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp) {
   Step A[U], B[U];
   auto ld = [&](int b, Step(&S)[U]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = b * U + u;
-      load(idx < count ? idx : count - 1, S[u]);
-    }
+    for (int u = 0; u < U; ++u) load(b * U + u, S[u]);
   };
   auto cp = [&](int b, Step(&S)[U]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int idx = b * U + u;
-      if (idx < count) comp(idx, S[u]);
-    }
+    for (int u = 0; u < U; ++u) comp(b * U + u, S[u]);
   };
   const int nb = (count + U - 1) / U;
   ld(0, A);
   for (int b = 0; b < nb; b += 2) {
-    if (b + 1 < nb) ld(b + 1, B);
+    ld(b + 1, B);
     cp(b, A);
-    if (b + 1 < nb) {
-      if (b + 2 < nb) ld(b + 2, A);
-      cp(b + 1, B);
-    }
+    ld(b + 2, A);
+    cp(b + 1, B);
   }
 }
 
-// x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, written to dst[0..m).  The
-// same arithmetic as band_solve, with the factor loads pipelined; BM >= band.
+// x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, in place in the cell's
+// vector v[0..m) (v[m] is the dead steps' scratch slot).  The same
+// arithmetic as band_solve, with the factor loads pipelined; BM >= band, and
+// band >= 2 (the tridiagonal band runs wave-per-cell).  Every load address
+// is valid and computed without conditions on the step: an absent
+// coefficient (j > band, coupling without `arrow`) reads some other factor
+// entry of the cell and is zeroed by a 0/1 weight in the arithmetic, and a
+// dead step reads the last level's entries and writes the scratch slot.
 template <bool TRANS, int BM, typename T, typename TA>
-__device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L, int band,
-                                                int arrow, const T (&s3i)[9],
-                                                const double* __restrict__ rv,
-                                                double* __restrict__ dst) {
+__device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L, int m, int band,
+                                                int arrow, const T (&s3i)[9], double* v) {
   constexpr int U = BM <= 2 ? 8 : BM <= 4 ? 4 : 2;
   auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)row * L + k) * TILE]; };
   struct Step {
@@ -337,6 +335,10 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
     TA e[3];   // coupling entries
     TA v;      // right-hand side (forward) or the forward result (backward)
   };
+  TA wj[BM];  // 1 for the band's diagonals, 0 past `band`
+#pragma unroll
+  for (int j = 0; j < BM; ++j) wj[j] = j < band ? TA(1) : TA(0);
+  const TA we = arrow ? TA(1) : TA(0);
   TA h[BM];
   TA acc[3] = {TA(0), TA(0), TA(0)};
 #pragma unroll
@@ -345,29 +347,35 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
   pipelined_walk<U, Step>(
       L,
       [&](int k, Step& s) {
-        s.v = (TA)rv[k];
+        const int kk = min(k, L - 1);
+        s.v = (TA)v[min(k, m)];
 #pragma unroll
-        for (int j = 1; j <= BM; ++j)
-          s.a[j - 1] = j > band ? TA(0) : TRANS ? at(band + j, k >= j ? k - j : 0) : at(j - 1, k);
-        s.d = TRANS ? at(band, k) : TA(1);
+        for (int j = 1; j <= BM; ++j) {
+          // lo(j) is row j - 1, up(j) row band + j; past `band`, rows j - band
+          // (TRANS) or j - 1 - band, all below 2 band
+          s.a[j - 1] = TRANS ? at(j <= band ? band + j : j - band, max(kk - j, 0))
+                             : at(j <= band ? j - 1 : j - 1 - band, kk);
+        }
+        s.d = TRANS ? at(band, kk) : TA(1);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) s.e[i] = arrow ? at(2 * band + (TRANS ? 1 : 4) + i, k) : TA(0);
+        for (int i = 0; i < 3; ++i) s.e[i] = at(arrow ? 2 * band + (TRANS ? 1 : 4) + i : i, kk);
       },
       [&](int k, const Step& s) {
         TA y = s.v;
 #pragma unroll
-        for (int j = BM; j >= 1; --j) y -= s.a[j - 1] * h[j - 1];
+        for (int j = BM; j >= 1; --j) y -= (s.a[j - 1] * wj[j - 1]) * h[j - 1];
         if (TRANS) y *= s.d;
 #pragma unroll
         for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
         h[0] = y;
-        dst[k] = (double)y;
+        const bool live = k < L;
+        v[live ? k : m] = (double)y;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) acc[i] += s.e[i] * y;
+        for (int i = 0; i < 3; ++i) acc[i] += live ? (s.e[i] * we) * y : TA(0);
       });
   TA yf[3], xf[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) yf[i] = (TA)rv[L + i] - acc[i];
+  for (int i = 0; i < 3; ++i) yf[i] = (TA)v[L + i] - acc[i];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     xf[i] = (TA)s3i[TRANS ? i : 3 * i] * yf[0] + (TA)s3i[TRANS ? 3 + i : 3 * i + 1] * yf[1] +
@@ -379,50 +387,76 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
   pipelined_walk<U, Step>(
       L,
       [&](int t, Step& s) {
-        const int k = L - 1 - t;
-        s.v = (TA)dst[k];
+        const int kk = max(L - 1 - t, 0);
+        s.v = (TA)v[kk];
 #pragma unroll
         for (int j = 1; j <= BM; ++j)
-          s.a[j - 1] = j > band ? TA(0) : TRANS ? at(j - 1, k + j < L ? k + j : k) : at(band + j, k);
-        s.d = TRANS ? TA(1) : at(band, k);
+          s.a[j - 1] = TRANS ? at(j <= band ? j - 1 : j - 1 - band, min(kk + j, L - 1))
+                             : at(j <= band ? band + j : j - band, kk);
+        s.d = TRANS ? TA(1) : at(band, kk);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) s.e[i] = arrow ? at(2 * band + (TRANS ? 4 : 1) + i, k) : TA(0);
+        for (int i = 0; i < 3; ++i) s.e[i] = at(arrow ? 2 * band + (TRANS ? 4 : 1) + i : i, kk);
       },
       [&](int t, const Step& s) {
-        const int k = L - 1 - t;
         TA x = s.v;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) x -= s.e[i] * xf[i];
+        for (int i = 0; i < 3; ++i) x -= (s.e[i] * we) * xf[i];
 #pragma unroll
-        for (int j = BM; j >= 1; --j) x -= s.a[j - 1] * h[j - 1];
+        for (int j = BM; j >= 1; --j) x -= (s.a[j - 1] * wj[j - 1]) * h[j - 1];
         if (!TRANS) x *= s.d;
 #pragma unroll
         for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
         h[0] = x;
-        dst[k] = (double)x;
+        v[t < L ? L - 1 - t : m] = (double)x;
       });
 #pragma unroll
-  for (int i = 0; i < 3; ++i) dst[L + i] = (double)xf[i];
+  for (int i = 0; i < 3; ++i) v[L + i] = (double)xf[i];
 }
 
-// x0 = A0^{-1} r for every right-hand side, one lane per cell.
+// x0 = A0^{-1} r for every right-hand side, one lane per cell.  The tile's
+// right-hand sides go through LDS ([TILE][(m + 1) | 1]: an odd row stride, so
+// that the lanes' rows fall in different banks, and a scratch slot at m):
+// loaded and stored row by row with the 64 lanes on consecutive elements,
+// while the walk reads and writes its own row in place.  Lanes past the last
+// cell walk whatever their LDS row holds and store nothing.
 template <typename TV, bool TRANS, int BM>
 __global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restrict__ bf,
                                                      const TV* __restrict__ s3i_in,
                                                      const double* __restrict__ rin,
                                                      double* __restrict__ zout, int nrhs) {
+  extern __shared__ double sv[];
   const int tile = blockIdx.x, lane = threadIdx.x;
-  const int c = tile * TILE + lane;
-  if (c >= g.N) return;
-  const int L = g.L, m = g.m;
+  const int L = g.L, m = g.m, ls = (m + 1) | 1;
+  const long long c0 = (long long)tile * TILE;
+  const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
   const TV* fb = bf + (long long)tile * band_rows(g) * L * TILE + lane;
   TV s3i[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
-  for (int r = 0; r < nrhs; ++r)
-    band_solve_pipe<TRANS, BM, TV, TV>(fb, L, g.band, g.arrow, s3i,
-                                       rin + (long long)r * g.n + (long long)c * m,
-                                       zout + (long long)r * g.n + (long long)c * m);
+  double* mine = sv + lane * ls;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* rr = rin + (long long)r * g.n + c0 * m;
+    for (int cc = 0; cc < cells; ++cc)
+      for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * m + k];
+    __syncthreads();
+    band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, s3i, mine);
+    __syncthreads();
+    double* zz = zout + (long long)r * g.n + c0 * m;
+    for (int cc = 0; cc < cells; ++cc)
+      for (int k = lane; k < m; k += TILE) zz[(long long)cc * m + k] = sv[cc * ls + k];
+    __syncthreads();
+  }
+}
+
+template <typename TV, bool TRANS, int BM>
+static void launch_band_solve(const Mesh& g, const TV* bf, const TV* s3i, const double* r,
+                              double* z, int nrhs, hipStream_t s) {
+  const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
+  if (lds > 65536)  // up to the 160 KiB of a CU for m > 127
+    (void)hipFuncSetAttribute((const void*)k_band_solve<TV, TRANS, BM>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_band_solve<TV, TRANS, BM>), dim3((unsigned)tiles(g)), dim3(TILE), lds, s,
+                     g, bf, s3i, r, z, nrhs);
 }
 
 // z = x0 - W C^{-1} (V^T x0) in place, one wavefront per cell (NCH chunks of
@@ -497,13 +531,12 @@ template <typename TV, bool TRANS>
 static hipError_t launch_band_apply_t(const Mesh& g, const TV* bf, const TV* s3i, const TV* wv,
                                       const TV* cinv, const double* r, double* z, int nrhs,
                                       hipStream_t s) {
-  const dim3 grid((unsigned)tiles(g)), block(TILE);
   if (g.band <= 2)
-    hipLaunchKernelGGL((k_band_solve<TV, TRANS, 2>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
+    launch_band_solve<TV, TRANS, 2>(g, bf, s3i, r, z, nrhs, s);
   else if (g.band <= 4)
-    hipLaunchKernelGGL((k_band_solve<TV, TRANS, 4>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
+    launch_band_solve<TV, TRANS, 4>(g, bf, s3i, r, z, nrhs, s);
   else
-    hipLaunchKernelGGL((k_band_solve<TV, TRANS, BAND_MAX>), grid, block, 0, s, g, bf, s3i, r, z, nrhs);
+    launch_band_solve<TV, TRANS, BAND_MAX>(g, bf, s3i, r, z, nrhs, s);
   if (g.rd == 1)
     launch_woodbury_r<TV, TRANS, 1>(g, wv, cinv, z, nrhs, s);
   else
