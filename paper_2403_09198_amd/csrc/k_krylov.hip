@@ -85,18 +85,31 @@ hipError_t launch_multidot(Basis B, int nv, const double* w, long long wstride, 
   return hipGetLastError();
 }
 
-// out[row] = sum_blk part[row*nblk + blk] in a fixed order, one wave per row.
+// out[row] = sum_blk part[row*nblk + blk] in a fixed order, one wave per row:
+// lane l adds blocks l, l + 64, ... in turn, then the wave sum.  nblk <=
+// 1024 (dot_blocks), so each lane holds at most 16 partials, all loaded
+// before the first add.
+constexpr int REDUCE_PER_LANE = 16;
 __global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, int rows, int nblk,
                                                double* __restrict__ out) {
   const int row = blockIdx.x * (KB / WAVE) + (threadIdx.x >> 6);
   if (row >= rows) return;
+  const double* pr = part + (long long)row * nblk;
+  double v[REDUCE_PER_LANE];
+#pragma unroll
+  for (int t = 0; t < REDUCE_PER_LANE; ++t) {
+    const int b = lane_id() + t * WAVE;
+    v[t] = b < nblk ? pr[b] : 0.0;
+  }
   double a = 0.0;
-  for (int b = lane_id(); b < nblk; b += WAVE) a += part[(long long)row * nblk + b];
+#pragma unroll
+  for (int t = 0; t < REDUCE_PER_LANE; ++t) a += v[t];
   a = wave_sum(a);
   if (lane_id() == 0) out[row] = a;
 }
 
 hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hipStream_t s) {
+  if (nblk > REDUCE_PER_LANE * WAVE) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3((rows + KB / WAVE - 1) / (KB / WAVE)), dim3(KB), 0, s, part,
                      rows, nblk, out);
   return hipGetLastError();
