@@ -478,6 +478,18 @@ def solvers(torch):
     print(json.dumps(row), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(p, nx, ny, L, budget_s=12.0):
     """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
     sample of block rows (blocks assembled and factored beforehand), repeated
@@ -513,7 +525,7 @@ def cpu_baseline(p, nx, ny, L, budget_s=12.0):
                    f"assembled and factored beforehand, {reps} passes in {el:.1f} s, "
                    f"1 BLAS thread"),
         "seconds": round(el, 2),
-        "host": platform.processor() or platform.machine(),
+        "host": cpu_model() or platform.processor() or platform.machine(),
         "host_cpus": os.cpu_count(),
     }
 
@@ -629,6 +641,9 @@ def main():
                      "avg_launch_us": round(mv_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": mv_b},
         "kernels_us": {"matvec_f64": round(mv_ms * 1e3, 2), "smw_apply_f64": round(ap_ms * 1e3, 2)},
+        "kernels_us_median_min": {
+            "matvec_f64": [round(float(np.median(t_mv)) * 1e3, 2), round(float(np.min(t_mv)) * 1e3, 2)],
+            "smw_apply_f64": [round(float(np.median(t_ap)) * 1e3, 2), round(float(np.min(t_ap)) * 1e3, 2)]},
         "kernel_gbs": {"matvec_f64": round(ach, 1),
                        "smw_apply_f64": round(ap_b / (ap_ms / 1e3) / 1e9, 1)},
     }
