@@ -637,6 +637,13 @@ static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, c
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
+    if constexpr (NCH == 1 && RDM == 1 && !ARW) {  // factors read once per 8 right-hand sides
+      if (rem >= 8) {
+        hipLaunchKernelGGL((k_smw_apply<TV, NCH, 8, TRANS, RDM, ARW>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+        r0 += 8;
+        continue;
+      }
+    }
     if (RDM == 1 && rem >= 4) {
       hipLaunchKernelGGL((k_smw_apply<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM, ARW>), dim3(grid), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
       r0 += RDM == 1 ? 4 : 2;

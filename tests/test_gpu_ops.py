@@ -26,7 +26,7 @@ def _setup(nx, ny, L, seed=1, keep_f32=True, with_trans=True):
 
 
 @pytest.mark.parametrize("nx,ny,L", SHAPES)
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 3, 11])  # 11 = batches of 8, 2 and 1
 def test_matvec_parity(nx, ny, L, nrhs):
     log(f"matvec parity nx={nx} ny={ny} L={L} nrhs={nrhs}")
     p, A, M = _setup(nx, ny, L)
@@ -60,7 +60,7 @@ def _per_cell_rel(z, ref):
 
 
 @pytest.mark.parametrize("nx,ny,L", SHAPES)
-@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("nrhs", [1, 5, 13])  # 13 = batches of 8, 4 and 1
 def test_smw_apply_parity(nx, ny, L, nrhs):
     log(f"smw apply parity nx={nx} ny={ny} L={L} nrhs={nrhs}")
     p, A, M = _setup(nx, ny, L)
