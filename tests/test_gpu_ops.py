@@ -106,6 +106,30 @@ def test_full_size_sampled_parity():
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + float(torch.linalg.norm(wd)) * float(torch.linalg.norm(xd)))
 
 
+@pytest.mark.parametrize("L", [32, 120, 200])
+def test_level_sweep_full_size_sampled_parity(L):
+    # the 512 x 256 level-sweep workloads at full size (m = 35 / 123 / 203:
+    # one wave per cell, and workgroups of 2 and 4 waves), sampled cells
+    nx, ny = 512, 256
+    log(f"level sweep full-size sampled parity 512x256 L={L}")
+    p, A, M = _setup(nx, ny, L, seed=0, keep_f32=False)
+    x = gen.make_vector(nx, ny, L, seed=0)
+    xd = vec(x)
+    cells = sample_cells(nx, ny, k=32, seed=L)
+    y = host(A.matvec(xd))[:, cells]
+    check_componentwise(y, ops.matvec_rows(p, nx, ny, L, x, cells),
+                        matvec_scale(p, nx, ny, L, x, cells), TOL64, "J x sampled")
+    yt = host(A.matvec(xd, trans=True))[:, cells]
+    check_componentwise(yt, ops.matvec_T_rows(p, nx, ny, L, x, cells),
+                        matvec_scale(p, nx, ny, L, x, cells, trans=True), TOL64, "J^T x sampled")
+    z = host(M.apply(xd))[:, cells]
+    assert _per_cell_rel(z, block_jacobi_ref(p, nx, ny, L, x, cells)) <= TOL64
+    zt = host(M.apply(xd, trans=True))[:, cells]
+    assert _per_cell_rel(zt, block_jacobi_ref(p, nx, ny, L, x, cells, trans=True)) <= TOL64
+    del A, M
+    torch.cuda.empty_cache()
+
+
 def test_bitwise_deterministic():
     p, A, M = _setup(64, 32, 61, seed=3)
     x = vec(gen.make_vector(64, 32, 61, nrhs=2, seed=2))
