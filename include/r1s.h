@@ -215,11 +215,19 @@ typedef struct {
   int mode;         /* R1S_MODE_F64 or R1S_MODE_MIXED_IR                    */
   double inner_rtol;/* mixed mode: relative tolerance of each inner solve   */
   int max_outer;    /* mixed mode: iterative-refinement steps               */
-  int always_reorth;/* 1: reorthogonalise every Arnoldi step (CGS2); 0: only
-                       when |w - V h| < |w| / sqrt(2) (selective CGS,
-                       decided per right-hand side; steps with more than 16
-                       basis vectors always reorthogonalise)                */
+  int ortho;        /* Arnoldi orthogonalisation, R1S_ORTHO_*             */
 } r1s_gmres_opts;
+
+/* Orthogonalisation of the Arnoldi vectors (all classical Gram-Schmidt with
+ * a second pass, float64): */
+#define R1S_ORTHO_SELECTIVE 0 /* second pass where |w - V h| < |w| / sqrt(2)
+                                 (decided per right-hand side; always above
+                                 16 basis vectors): three passes over the
+                                 basis per step                             */
+#define R1S_ORTHO_CGS2 1      /* second pass on every step                 */
+#define R1S_ORTHO_DELAYED 2   /* second pass delayed to the next step and
+                                 merged with its first: one reduction and
+                                 two passes over the basis per step         */
 
 typedef struct {
   int iters;            /* Arnoldi steps (summed over inner solves)         */
@@ -343,8 +351,8 @@ int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
 
 /* Restarted right-preconditioned GMRES (section 6): solves (J M) y = b and
  * returns x = M y, for nrhs independent right-hand sides advanced together.
- * Classical Gram-Schmidt with selective (or, with always_reorth, unconditional)
- * reorthogonalisation, float64.  Mixed mode
+ * Classical Gram-Schmidt with a second pass chosen by opts->ortho
+ * (R1S_ORTHO_*), float64.  Mixed mode
  * wraps float32-operator inner solves in float64 iterative refinement.
  * `B` is used when opts->op == R1S_OP_BSR (may be NULL otherwise).
  * On R1S_ERR_NOCONV, x holds the last iterate and stats are filled (one

@@ -31,6 +31,7 @@ R1S_MAX_BAND = 8
 R1S_MAX_NBR = 8
 R1S_OP_STRUCTURED, R1S_OP_BSR = 0, 1
 R1S_MODE_F64, R1S_MODE_MIXED_IR = 0, 1
+R1S_ORTHO_SELECTIVE, R1S_ORTHO_CGS2, R1S_ORTHO_DELAYED = 0, 1, 2
 
 
 INPUT_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v", "s_band", "s_lev_flow",
@@ -70,7 +71,7 @@ class Storage(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double),
                 ("trans", C.c_int), ("x0_given", C.c_int), ("op", C.c_int), ("mode", C.c_int),
-                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("always_reorth", C.c_int)]
+                ("inner_rtol", C.c_double), ("max_outer", C.c_int), ("ortho", C.c_int)]
 
 
 class GmresStats(C.Structure):

@@ -784,6 +784,8 @@ extern "C" int r1s_bsr_destroy(r1s_bsr B) {
 struct GmresWork {
   double *V, *w, *z, *t, *part, *hdev, *ydev, *scal, *r64, *d;
   int* need;  // per right-hand side: the second Gram-Schmidt pass ran
+  double* dstate;       // delayed reorthogonalisation: per-rhs H, s, a, g, r, rho
+  long long dstride;
   int nblk;
 };
 
@@ -794,13 +796,15 @@ static void gmres_layout(Carver& cv, const Mesh& g, int k, int nrhs, bool mixed,
   W->w = cv.take<double>((size_t)nrhs * n);
   W->z = cv.take<double>((size_t)nrhs * n);
   W->t = cv.take<double>((size_t)nrhs * n);
-  W->part = cv.take<double>((size_t)nrhs * (k + 2) * W->nblk);
+  W->part = cv.take<double>((size_t)nrhs * (2 * k + 3) * W->nblk);
   W->hdev = cv.take<double>((size_t)nrhs * (k + 2) * 2);
   W->ydev = cv.take<double>((size_t)nrhs * (k + 1));
   W->scal = cv.take<double>((size_t)nrhs * 4);
   W->r64 = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
   W->d = mixed ? cv.take<double>((size_t)nrhs * n) : nullptr;
   W->need = cv.take<int>((size_t)nrhs);
+  W->dstride = (long long)k * (k + 1) + 3LL * k + 2 + 4;
+  W->dstate = cv.take<double>((size_t)nrhs * W->dstride);
 }
 
 // Pinned host staging for the Arnoldi coefficients, written by the last
@@ -872,6 +876,8 @@ static int check_opts(const r1s_gmres_opts* o) {
   if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return fail(R1S_ERR_ARG, "rtol must be in (0, 1)");
   if (o->op != R1S_OP_STRUCTURED && o->op != R1S_OP_BSR) return fail(R1S_ERR_ARG, "unknown op");
   if (o->mode != R1S_MODE_F64 && o->mode != R1S_MODE_MIXED_IR) return fail(R1S_ERR_ARG, "unknown mode");
+  if (o->ortho != R1S_ORTHO_SELECTIVE && o->ortho != R1S_ORTHO_CGS2 && o->ortho != R1S_ORTHO_DELAYED)
+    return fail(R1S_ERR_ARG, "unknown orthogonalisation %d", o->ortho);
   if (o->mode == R1S_MODE_MIXED_IR) {
     if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0)) return fail(R1S_ERR_ARG, "inner_rtol must be in (0, 1)");
     if (o->max_outer < 1) return fail(R1S_ERR_ARG, "max_outer must be >= 1");
@@ -952,7 +958,9 @@ struct SolveStat {
 // from x (x0_given) or zero.  rtol is relative to |b| per right-hand side.
 static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
                       double rtol, int nrhs, const double* b, double* x, bool x0_given,
-                      bool always_reorth, std::vector<SolveStat>& st) {
+                      int ortho, std::vector<SolveStat>& st) {
+  const bool always_reorth = ortho == R1S_ORTHO_CGS2;
+  const bool delayed = ortho == R1S_ORTHO_DELAYED;
   hipStream_t s = c.s;
   const long long n = g.n;
   const int HS = k + 2;  // stride of the per-rhs h arrays
@@ -969,7 +977,8 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   std::vector<int> jend(nrhs), done(nrhs);
   auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
   StagingLease lease;
-  const size_t slot_doubles = (size_t)nrhs * (2 * HS + 1);
+  const int SS = 2 * k + 6;  // delayed scheme: staging doubles per right-hand side
+  const size_t slot_doubles = (size_t)nrhs * std::max(2 * HS + 1, SS);
   if (int e = staging_acquire(2 * slot_doubles * sizeof(double), &lease.st)) return e;
   double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
 
@@ -1051,9 +1060,120 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       return all_done;
     };
+    // Givens update of the least-squares problem with column j of H (rows
+    // 0..j+1 in Hat); returns the residual estimate |g_{j+1}| and sets done
+    // on breakdown or convergence when `decide`.
+    auto givens = [&](int r, int j) {
+      for (int i = 0; i < j; ++i) {
+        const double a = Hat(r, i, j), bb = Hat(r, i + 1, j);
+        Hat(r, i, j) = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
+        Hat(r, i + 1, j) = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
+      }
+      const double a = Hat(r, j, j), bb = Hat(r, j + 1, j);
+      const double rho = hypot(a, bb);
+      const double cj = rho > 0 ? a / rho : 1.0, sj = rho > 0 ? bb / rho : 0.0;
+      cs[(size_t)r * k + j] = cj;
+      sn[(size_t)r * k + j] = sj;
+      Hat(r, j, j) = rho;
+      Hat(r, j + 1, j) = 0.0;
+      double* gr = gv.data() + (size_t)r * (k + 1);
+      gr[j + 1] = -sj * gr[j];
+      gr[j] = cj * gr[j];
+      jend[r] = j + 1;
+      st[r].iters += 1;
+    };
+    if (delayed) {
+      // One reduction per step (device kernels k_dcgs_*): step j turns the
+      // lagged u_j in slot j into the final v_j, finalises column j - 1 of H
+      // and estimates column j; the host takes the final columns for the
+      // least-squares problem and tests the estimated one for convergence.
+      // lastcol[r]: the last column of right-hand side r once it has met the
+      // tolerance (or broken down) on an estimated column, else -1.
+      std::vector<int> lastcol(nrhs, -1);
+      for (int r = 0; r < nrhs; ++r)
+        if (done[r]) lastcol[r] = -2;  // converged before this cycle: nothing to do
+      auto final_col = [&](int j, const double* stg) {  // column j, staged by step j + 1
+        for (int r = 0; r < nrhs; ++r) {
+          if (lastcol[r] == -2 || (lastcol[r] >= 0 && j > lastcol[r])) continue;
+          const double* h = stg + (size_t)r * SS;
+          for (int i = 0; i <= j + 1; ++i) Hat(r, i, j) = h[i];
+          givens(r, j);
+        }
+      };
+      auto trial = [&](int j, const double* stg) {  // estimated column j, staged by step j
+        for (int r = 0; r < nrhs; ++r) {
+          if (lastcol[r] != -1) continue;
+          const double* h = stg + (size_t)r * SS;
+          std::vector<double> col(j + 2);
+          for (int i = 0; i <= j; ++i) col[i] = h[k + 1 + i];
+          col[j + 1] = h[2 * k + 2];
+          for (int i = 0; i < j; ++i) {
+            const double a = col[i], bb = col[i + 1];
+            col[i] = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
+            col[i + 1] = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
+          }
+          const double rho = hypot(col[j], col[j + 1]);
+          const double sj = rho > 0 ? col[j + 1] / rho : 0.0;
+          const double res = fabs(sj * gv[(size_t)r * (k + 1) + j]);
+          const bool breakdown = h[2 * k + 2] <= 1e-14 * h[2 * k + 3] || h[2 * k + 5] != 0.0;
+          if (breakdown || res <= rtol * bnorm[r]) lastcol[r] = j;
+        }
+      };
+      auto launch_step = [&](int j) -> int {
+        double* Vj = W.V + (long long)j * n;
+        if (nrhs == 1) {
+          if (int e = prec_apply(c, Vj, W.z, 1)) return e;
+        } else {
+          HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
+                                   n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+          if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
+        }
+        if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
+        HIP_TRY(launch_dcgs_dots(Vb, j, W.w, n, n, nrhs, W.part, W.nblk, s));
+        HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, stage[j & 1], SS,
+                                  false, nrhs, s));
+        HIP_TRY(launch_dcgs_update(Vb, j, k, W.dstate, W.dstride, W.w, n, n, nrhs, s));
+        HIP_TRY(hipEventRecord(lease.st->ev[j & 1], s));
+        return R1S_OK;
+      };
+      auto all_stopped = [&]() {
+        for (int r = 0; r < nrhs; ++r)
+          if (lastcol[r] == -1) return false;
+        return true;
+      };
+      bool stopped = false;
+      for (int j = 0; j < k && !stopped; ++j) {
+        if (int e = launch_step(j)) return e;
+        if (j == 0) continue;
+        HIP_TRY(hipEventSynchronize(lease.st->ev[(j - 1) & 1]));
+        if (j >= 2) final_col(j - 2, stage[(j - 1) & 1]);
+        trial(j - 1, stage[(j - 1) & 1]);
+        if (all_stopped()) {  // the final column j - 1 comes from step j
+          HIP_TRY(hipEventSynchronize(lease.st->ev[j & 1]));
+          final_col(j - 1, stage[j & 1]);
+          stopped = true;
+        }
+      }
+      if (!stopped) {
+        // the cycle's last step k - 1: its final column needs one more
+        // reduction on u_k (slot k), without the operator
+        HIP_TRY(hipEventSynchronize(lease.st->ev[(k - 1) & 1]));
+        if (k >= 2) final_col(k - 2, stage[(k - 1) & 1]);
+        trial(k - 1, stage[(k - 1) & 1]);
+        const double* uk = W.V + (long long)k * n;
+        HIP_TRY(launch_dcgs_dots(Vb, k, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
+        HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, stage[k & 1], SS,
+                                  true, nrhs, s));
+        HIP_TRY(hipEventRecord(lease.st->ev[k & 1], s));
+        HIP_TRY(hipEventSynchronize(lease.st->ev[k & 1]));
+        final_col(k - 1, stage[k & 1]);
+      }
+      for (int r = 0; r < nrhs; ++r)
+        if (lastcol[r] == -2) jend[r] = 0;
+    }
     int pending = -1;  // step whose coefficients are staged but not yet used
-    bool finished = false;
-    for (int j = 0; j < k; ++j) {
+    bool finished = delayed;
+    for (int j = 0; j < k && !delayed; ++j) {
       double* Vj = W.V + (long long)j * n;
       // z = M v_j ; w = op(z)   (v_j of every rhs: strided copy into t)
       if (nrhs == 1) {
@@ -1101,7 +1221,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       pending = j;
     }
-    if (!finished && pending >= 0) {
+    if (!finished && pending >= 0) {  // (not reached in the delayed scheme)
       HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));
       process(pending);
     }
@@ -1168,7 +1288,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
   int rc;
   if (!mixed) {
     rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
-                    opts->x0_given != 0, opts->always_reorth != 0, st);
+                    opts->x0_given != 0, opts->ortho, st);
     if (rc) return rc;
   } else {
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
@@ -1191,7 +1311,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
       if (all || outer == opts->max_outer) break;
       std::vector<SolveStat> in;
       rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs, W.r64,
-                      W.d, false, opts->always_reorth != 0, in);
+                      W.d, false, opts->ortho, in);
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r) {
         tot[r].iters += in[r].iters;

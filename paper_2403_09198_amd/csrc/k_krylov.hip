@@ -299,6 +299,282 @@ hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const doub
   return hipGetLastError();
 }
 
+// ------------------------------------------- delayed reorthogonalisation ----
+// Arnoldi with one global reduction per step (classical Gram-Schmidt with
+// the second pass delayed to the next step, after the DCGS2 scheme of
+// Swirydowicz et al. and Bielich et al.).  Step j holds the final
+// orthonormal v_0..v_{j-1} and a lagged vector u_j (slot j: once
+// orthogonalised, scaled by a Pythagorean norm estimate).  It applies the
+// operator to u_j, then one reduction gives a = V^T u_j, |u_j|^2, c = V^T w,
+// u_j . w and |w|^2; from these
+//   r = |u_j - V a| (by Pythagoras), v_j = (u_j - V a) / r   (final),
+//   column j-1 of H final:  s_{j-1} + rho_j a, and rho_j r below it,
+//   B v_j = (w - V H a) / r, so the first-pass coefficients of column j are
+//   s_j = (V_{j+1}^T w - t) / r with t = H a, and
+//   u_{j+1} = (w - V_{j+1} (t + r s_j)) / (r rho_{j+1}),
+//   rho_{j+1} = sqrt(|B v_j|^2 - |s_j|^2).
+// Step 0 starts from v_0 itself (u_0 = v_0, r = 1).
+//
+// Device state per right-hand side (doubles, stride dstride): H column-major
+// [K][K + 1], s_{j-1} [K + 1], a [K], t + r s [K + 1], then r, 1 / (r rho),
+// rho.  Host staging per right-hand side (stride sstride): the final column
+// j - 1 (rows 0..j), at K + 1 the estimated column j (rows 0..j), then
+// rho_{j+1}, |B v_j|, r and a breakdown flag.
+
+constexpr int DC_GROUP = 16;  // basis vectors per pass of the dot products
+
+// rows of step j's reduction per right-hand side: a_0..a_{j-1}, |u|^2,
+// c_0..c_{j-1}, u . w, |w|^2
+__global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* __restrict__ w,
+                                                  long long wstride, long long n,
+                                                  double* __restrict__ part, int nblk) {
+  __shared__ double sh[2 * DC_GROUP][KB / WAVE];
+  const int r = blockIdx.y, wave = threadIdx.x >> 6, tid = threadIdx.x;
+  const double* Vr = B.V + (long long)r * B.rstride;
+  const double* u = Vr + (long long)j * B.vstride;
+  const double* wr = w + (long long)r * wstride;
+  const int rows = 2 * j + 3;
+  double* pr = part + (long long)r * rows * nblk;
+  const long long stride = (long long)nblk * KB;
+  const long long e0 = (long long)blockIdx.x * KB + tid;
+  for (int i = 0; i < j; i += DC_GROUP) {
+    const int g = j - i < DC_GROUP ? j - i : DC_GROUP;  // block-uniform
+    double acc[2 * DC_GROUP];
+#pragma unroll
+    for (int q = 0; q < 2 * DC_GROUP; ++q) acc[q] = 0.0;
+    for (long long e = e0; e < n; e += stride) {
+      const double ue = u[e], we = wr[e];
+#pragma unroll
+      for (int q = 0; q < DC_GROUP; ++q) {
+        if (q < g) {
+          const double ve = Vr[(long long)(i + q) * B.vstride + e];
+          acc[q] += ve * ue;
+          acc[DC_GROUP + q] += ve * we;
+        }
+      }
+    }
+    // block sums: value q < DC_GROUP is a_{i+q} (row i + q), value
+    // DC_GROUP + q is c_{i+q} (row j + 1 + i + q)
+#pragma unroll
+    for (int q = 0; q < 2 * DC_GROUP; ++q) {
+      if (q % DC_GROUP < g) {
+        const double t = wave_sum(acc[q]);
+        if (lane_id() == 0) sh[q][wave] = t;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * DC_GROUP && tid % DC_GROUP < g) {
+      double t = 0.0;
+      for (int w2 = 0; w2 < KB / WAVE; ++w2) t += sh[tid][w2];
+      const int row = tid < DC_GROUP ? i + tid : j + 1 + i + (tid - DC_GROUP);
+      pr[(long long)row * nblk + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  double uu = 0.0, uw = 0.0, ww = 0.0;
+  for (long long e = e0; e < n; e += stride) {
+    const double ue = u[e], we = wr[e];
+    uu += ue * ue;
+    uw += ue * we;
+    ww += we * we;
+  }
+  uu = wave_sum(uu);
+  uw = wave_sum(uw);
+  ww = wave_sum(ww);
+  if (lane_id() == 0) {
+    sh[0][wave] = uu;
+    sh[1][wave] = uw;
+    sh[2][wave] = ww;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double t = 0.0;
+    for (int w2 = 0; w2 < KB / WAVE; ++w2) t += sh[tid][w2];
+    const int row = tid == 0 ? j : tid == 1 ? 2 * j + 1 : 2 * j + 2;
+    pr[(long long)row * nblk + blockIdx.x] = t;
+  }
+}
+
+hipError_t launch_dcgs_dots(Basis B, int j, const double* w, long long wstride, long long n,
+                            int nrhs, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblk, nrhs), dim3(KB), 0, s, B, j, w, wstride, n, part,
+                     nblk);
+  return hipGetLastError();
+}
+
+// One block per right-hand side: the fixed-order reduction of step j's rows
+// (as k_reduce), then the small dense algebra spread over the block's
+// threads (one thread per row of a column, sums by fixed-order block
+// reductions): r, the final column j - 1, t = H a, s_j, rho_{j+1} and the
+// update coefficients, staged for the host.  final_only: only r and the
+// final column j - 1 (a cycle's last column).
+__device__ inline void block_sum3(double& x, double& y, double& z, double (*sh)[KB / WAVE]) {
+  x = wave_sum(x);
+  y = wave_sum(y);
+  z = wave_sum(z);
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    sh[0][wave] = x;
+    sh[1][wave] = y;
+    sh[2][wave] = z;
+  }
+  __syncthreads();
+  x = y = z = 0.0;
+  for (int w = 0; w < KB / WAVE; ++w) {
+    x += sh[0][w];
+    y += sh[1][w];
+    z += sh[2][w];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* __restrict__ part,
+                                                   int nblk, double* __restrict__ dstate,
+                                                   long long dstride, double* stage, int sstride,
+                                                   int final_only) {
+  extern __shared__ double red[];  // the 2j + 3 sums, then t [j + 1]
+  __shared__ double bs[3][KB / WAVE];
+  const int r = blockIdx.x, rows = 2 * j + 3, tid = threadIdx.x;
+  const double* pr = part + (long long)r * rows * nblk;
+  for (int row = tid >> 6; row < rows; row += KB / WAVE) {
+    double v[REDUCE_PER_LANE];
+#pragma unroll
+    for (int t = 0; t < REDUCE_PER_LANE; ++t) {
+      const int b = lane_id() + t * WAVE;
+      v[t] = b < nblk ? pr[(long long)row * nblk + b] : 0.0;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < REDUCE_PER_LANE; ++t) a += v[t];
+    a = wave_sum(a);
+    if (lane_id() == 0) red[row] = a;
+  }
+  __syncthreads();
+  double* H = dstate + (long long)r * dstride;
+  double* sprev = H + (long long)K * (K + 1);
+  double* aco = sprev + (K + 1);
+  double* gco = aco + K;
+  double* sc = gco + (K + 1);
+  double* st = stage + (long long)r * sstride;
+  const double* a = red;
+  const double alpha = red[j];
+  const double* c = red + j + 1;
+  const double gam = red[2 * j + 1], om = red[2 * j + 2];
+  double* tsh = red + rows;
+  // |a|^2 and a . c
+  double aa = 0.0, ac = 0.0, dummy = 0.0;
+  for (int i = tid; i < j; i += KB) {
+    aa += a[i] * a[i];
+    ac += a[i] * c[i];
+  }
+  block_sum3(aa, ac, dummy, bs);
+  double rr = 1.0;
+  bool brk = false;
+  if (j > 0) {
+    const double r2 = alpha - aa;
+    brk = !(r2 > 0.0);
+    rr = brk ? 1.0 : sqrt(r2);
+    const double rho_prev = sc[2];
+    double* col = H + (long long)(j - 1) * (K + 1);
+    for (int i = tid; i <= j; i += KB) {
+      const double h = i < j ? sprev[i] + rho_prev * a[i] : rho_prev * rr;
+      col[i] = h;
+      st[i] = h;
+    }
+  }
+  for (int i = tid; i < j; i += KB) aco[i] = a[i];
+  if (tid == 0) sc[0] = rr;
+  if (final_only) {
+    if (tid == 0) {
+      st[2 * K + 4] = rr;
+      st[2 * K + 5] = brk ? 1.0 : 0.0;
+    }
+    __threadfence_system();
+    return;
+  }
+  __syncthreads();  // column j - 1 of H written before it is read below
+  // t_i = sum_l H[l][i] a_l over the columns l >= i - 1 (column l has rows 0..l+1)
+  for (int i = tid; i <= j; i += KB) {
+    double t = 0.0;
+    for (int l = i > 0 ? i - 1 : 0; l < j; ++l) t += H[(long long)l * (K + 1) + i] * a[l];
+    tsh[i] = t;
+  }
+  __syncthreads();
+  // d = V_{j+1}^T w, s = (d - t) / r, g = t + r s; |B v_j|^2 from t.d, |t|^2
+  const double inv_r = 1.0 / rr;
+  double td = 0.0, tt = 0.0, ss = 0.0;
+  for (int i = tid; i <= j; i += KB) {
+    const double di = i < j ? c[i] : (j == 0 ? gam : (gam - ac) * inv_r);
+    const double ti = tsh[i];
+    const double si = (di - ti) * inv_r;
+    td += ti * di;
+    tt += ti * ti;
+    ss += si * si;
+    sprev[i] = si;
+    st[K + 1 + i] = si;
+    gco[i] = ti + rr * si;
+  }
+  block_sum3(td, tt, ss, bs);
+  if (tid == 0) {
+    const double nw2 = (om - 2.0 * td + tt) * inv_r * inv_r;
+    const double q = nw2 - ss;
+    const double rho = q > 0.0 ? sqrt(q) : 0.0;
+    sc[1] = rho > 0.0 ? 1.0 / (rr * rho) : 0.0;
+    sc[2] = rho;
+    st[2 * K + 2] = rho;
+    st[2 * K + 3] = nw2 > 0.0 ? sqrt(nw2) : 0.0;
+    st[2 * K + 4] = rr;
+    st[2 * K + 5] = brk ? 1.0 : 0.0;
+  }
+  __threadfence_system();
+}
+
+hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double* dstate,
+                             long long dstride, double* stage, int sstride, bool final_only,
+                             int nrhs, hipStream_t s) {
+  if (nblk > REDUCE_PER_LANE * WAVE) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dcgs_small, dim3(nrhs), dim3(KB), (size_t)(3 * j + 4) * sizeof(double), s,
+                     j, K, part, nblk, dstate, dstride, stage, sstride, (int)final_only);
+  return hipGetLastError();
+}
+
+// v_j = (u_j - V a) / r in slot j (j > 0) and u_{j+1} = (w - V_{j+1} g) / (r rho)
+// in slot j + 1, g = t + r s (device state of k_dcgs_small).
+__global__ __launch_bounds__(KB) void k_dcgs_update(Basis B, int j, int K,
+                                                    const double* __restrict__ dstate,
+                                                    long long dstride, const double* __restrict__ w,
+                                                    long long wstride, long long n) {
+  const int r = blockIdx.y;
+  double* Vr = B.V + (long long)r * B.rstride;
+  const double* wr = w + (long long)r * wstride;
+  const double* sprev = dstate + (long long)r * dstride + (long long)K * (K + 1);
+  const double* aco = sprev + (K + 1);
+  const double* gco = aco + K;
+  const double* sc = gco + (K + 1);
+  const double inv_r = 1.0 / sc[0], inv2 = sc[1], gj = gco[j];
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
+       e += (long long)gridDim.x * KB) {
+    const double uj = Vr[(long long)j * B.vstride + e];
+    double av = uj, au = wr[e];
+    for (int i = 0; i < j; ++i) {
+      const double vi = Vr[(long long)i * B.vstride + e];
+      av -= aco[i] * vi;
+      au -= gco[i] * vi;
+    }
+    const double vj = j == 0 ? uj : av * inv_r;
+    if (j > 0) Vr[(long long)j * B.vstride + e] = vj;
+    Vr[(long long)(j + 1) * B.vstride + e] = (au - gj * vj) * inv2;
+  }
+}
+
+hipError_t launch_dcgs_update(Basis B, int j, int K, const double* dstate, long long dstride,
+                              const double* w, long long wstride, long long n, int nrhs,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_update, vec_grid(n, nrhs), dim3(KB), 0, s, B, j, K, dstate, dstride,
+                     w, wstride, n);
+  return hipGetLastError();
+}
+
 // out_r = w_r * inv[r]
 __global__ __launch_bounds__(KB) void k_scale(const double* __restrict__ w, long long wstride,
                                               const double* __restrict__ inv,

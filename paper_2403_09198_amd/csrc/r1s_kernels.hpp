@@ -109,6 +109,15 @@ hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride,
                                   bool always, int* need, hipStream_t s);
 hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* w,
                          long long wstride, long long n, int nrhs, hipStream_t s);
+// Delayed reorthogonalisation (one reduction per Arnoldi step; k_krylov.hip)
+hipError_t launch_dcgs_dots(Basis B, int j, const double* w, long long wstride, long long n,
+                            int nrhs, double* part, int nblk, hipStream_t s);
+hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double* dstate,
+                             long long dstride, double* stage, int sstride, bool final_only,
+                             int nrhs, hipStream_t s);
+hipError_t launch_dcgs_update(Basis B, int j, int K, const double* dstate, long long dstride,
+                              const double* w, long long wstride, long long n, int nrhs,
+                              hipStream_t s);
 hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const double* h2,
                                    int hstride, const int* need, const double* w,
                                    long long wstride, double* vout, long long n, int nrhs,

@@ -426,16 +426,22 @@ class GmresResult:
 
 def gmres(A: R1Matrix, M, b, x0=None, restart=50, rtol=1e-10, max_cycles=200, trans=False,
           op="structured", B: Optional[BSRMatrix] = None, mode="f64", inner_rtol=1e-5,
-          max_outer=10, always_reorth=False, raise_on_noconv=True, work=None,
+          max_outer=10, ortho="delayed", raise_on_noconv=True, work=None,
           stream=None) -> GmresResult:
-    """Restarted right-preconditioned GMRES through r1s_gmres."""
+    """Restarted right-preconditioned GMRES through r1s_gmres.  ortho: the
+    Gram-Schmidt second pass, "delayed" (merged with the next step's first:
+    one reduction per step), "selective" or "cgs2" (every step)."""
+    orthos = {"selective": L.R1S_ORTHO_SELECTIVE, "cgs2": L.R1S_ORTHO_CGS2,
+              "delayed": L.R1S_ORTHO_DELAYED}
+    if ortho not in orthos:
+        raise ValueError(f"ortho must be one of {sorted(orthos)}")
     nrhs = _need_vec(b, "b", A.n)
     opts = L.GmresOpts(restart=restart, max_cycles=max_cycles, rtol=rtol, trans=int(trans),
                        x0_given=int(x0 is not None),
                        op=L.R1S_OP_BSR if op == "bsr" else L.R1S_OP_STRUCTURED,
                        mode=L.R1S_MODE_MIXED_IR if mode == "mixed" else L.R1S_MODE_F64,
                        inner_rtol=inner_rtol, max_outer=max_outer,
-                       always_reorth=int(always_reorth))
+                       ortho=orthos[ortho])
     x = torch.empty_like(b) if x0 is None else x0.clone()
     need = r1s_gmres_work_size(A.h, opts, nrhs)
     if work is None or work.numel() < need:

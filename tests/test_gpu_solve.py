@@ -212,16 +212,16 @@ def test_zero_rhs_gives_zero():
     assert float(res.x.abs().max()) == 0.0 and res.stats[0]["converged"] == 1
 
 
-@pytest.mark.parametrize("always_reorth", [False, True])
-def test_gram_schmidt_variants_agree(always_reorth):
-    # selective and unconditional reorthogonalisation reach the same solution
+@pytest.mark.parametrize("ortho", ["selective", "cgs2", "delayed"])
+def test_gram_schmidt_variants_agree(ortho):
+    # selective, unconditional and delayed reorthogonalisation reach the same
+    # solution (restart stress case: many short cycles)
     nx, ny, L = 12, 10, 9
     p = gen.make_problem(nx, ny, L, seed=11, inv_dt=1.0)
     b = gen.make_rhs(nx, ny, L, nrhs=2, seed=11)
     A = r1s.R1Matrix(nx, ny, L, to_dev(p))
     M = r1s.SMWPreconditioner(A)
-    res = r1s.gmres(A, M, vec(b), restart=8, rtol=1e-11, max_cycles=500,
-                    always_reorth=always_reorth)
+    res = r1s.gmres(A, M, vec(b), restart=8, rtol=1e-11, max_cycles=500, ortho=ortho)
     J = ops.dense_matrix(p, nx, ny, L)
     x = host(res.x)
     for r in range(2):
@@ -252,3 +252,32 @@ def test_mixed_precision_full_size_workload():
     assert np.max(np.abs(rr)) <= 1e-9 * np.max(np.abs(b))
     ref = r1s.gmres(A, M, bd, restart=50, rtol=1e-10)
     assert relnorm(x, host(ref.x)) <= 1e-9
+
+
+@pytest.mark.parametrize("restart", [1, 2, 3, 50])
+def test_delayed_orthogonalisation_matches_cgs2(restart):
+    # the delayed scheme against the per-step second pass: same solutions,
+    # iteration counts within one step, for short and long cycles and two
+    # right-hand sides that converge at different steps
+    nx, ny, L = 16, 16, 8
+    p = gen.make_problem(nx, ny, L, seed=12)
+    b = gen.make_rhs(nx, ny, L, nrhs=2, seed=12)
+    b[1] *= 1e-3  # a smaller right-hand side (the tolerance is relative)
+    b[1, :5] += 1.0
+    A = r1s.R1Matrix(nx, ny, L, to_dev(p))
+    M = r1s.SMWPreconditioner(A, with_trans=True)
+    bd = vec(b)
+    for trans in (False, True):
+        ref = r1s.gmres(A, M, bd, restart=restart, rtol=1e-10, max_cycles=2000, ortho="cgs2",
+                        trans=trans)
+        res = r1s.gmres(A, M, bd, restart=restart, rtol=1e-10, max_cycles=2000, ortho="delayed",
+                        trans=trans)
+        for r in range(2):
+            assert res.stats[r]["converged"] == 1
+            assert abs(res.stats[r]["iters"] - ref.stats[r]["iters"]) <= max(1, ref.stats[r]["iters"] // 20)
+        assert relnorm(host(res.x), host(ref.x)) <= 1e-8
+        f = ops.matvec_T if trans else ops.matvec
+        xr = host(res.x)
+        for r in range(2):
+            rr = b[r] - f(p, nx, ny, L, xr[r])
+            assert np.linalg.norm(rr) <= 1.5e-10 * np.linalg.norm(b[r])
