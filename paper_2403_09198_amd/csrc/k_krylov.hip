@@ -342,15 +342,19 @@ __global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* 
     double acc[2 * DC_GROUP];
 #pragma unroll
     for (int q = 0; q < 2 * DC_GROUP; ++q) acc[q] = 0.0;
+    // every load is unconditional (a short last group re-reads its last
+    // vector and discards the products), so all of them are in flight at once
     for (long long e = e0; e < n; e += stride) {
       const double ue = u[e], we = wr[e];
+      double ve[DC_GROUP];
+#pragma unroll
+      for (int q = 0; q < DC_GROUP; ++q)
+        ve[q] = Vr[(long long)(i + (q < g ? q : g - 1)) * B.vstride + e];
+      __builtin_amdgcn_sched_barrier(0);  // all loads issued before the first use
 #pragma unroll
       for (int q = 0; q < DC_GROUP; ++q) {
-        if (q < g) {
-          const double ve = Vr[(long long)(i + q) * B.vstride + e];
-          acc[q] += ve * ue;
-          acc[DC_GROUP + q] += ve * we;
-        }
+        acc[q] += q < g ? ve[q] * ue : 0.0;
+        acc[DC_GROUP + q] += q < g ? ve[q] * we : 0.0;
       }
     }
     // block sums: value q < DC_GROUP is a_{i+q} (row i + q), value
@@ -495,9 +499,16 @@ __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* _
   __syncthreads();  // column j - 1 of H written before it is read below
   // t_i = sum_l H[l][i] a_l over the columns l >= i - 1 (column l has rows 0..l+1)
   for (int i = tid; i <= j; i += KB) {
-    double t = 0.0;
-    for (int l = i > 0 ? i - 1 : 0; l < j; ++l) t += H[(long long)l * (K + 1) + i] * a[l];
-    tsh[i] = t;
+    // four independent partial sums so that their loads overlap, added in a
+    // fixed order
+    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    int l = i > 0 ? i - 1 : 0;
+    for (; l + 4 <= j; l += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t4[q] += H[(long long)(l + q) * (K + 1) + i] * a[l + q];
+    }
+    for (; l < j; ++l) t4[0] += H[(long long)l * (K + 1) + i] * a[l];
+    tsh[i] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
   }
   __syncthreads();
   // d = V_{j+1}^T w, s = (d - t) / r, g = t + r s; |B v_j|^2 from t.d, |t|^2
