@@ -1010,6 +1010,28 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     HIP_TRY(hipMemcpyAsync(W.scal, y.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_scale(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
 
+    // Givens update of the least-squares problem with column j of H (rows
+    // 0..j+1 in Hat): the previous rotations, then a new one eliminating
+    // H[j+1][j]; g_{j+1} is then the residual estimate.
+    auto givens = [&](int r, int j) {
+      for (int i = 0; i < j; ++i) {
+        const double a = Hat(r, i, j), bb = Hat(r, i + 1, j);
+        Hat(r, i, j) = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
+        Hat(r, i + 1, j) = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
+      }
+      const double a = Hat(r, j, j), bb = Hat(r, j + 1, j);
+      const double rho = hypot(a, bb);
+      const double cj = rho > 0 ? a / rho : 1.0, sj = rho > 0 ? bb / rho : 0.0;
+      cs[(size_t)r * k + j] = cj;
+      sn[(size_t)r * k + j] = sj;
+      Hat(r, j, j) = rho;
+      Hat(r, j + 1, j) = 0.0;
+      double* gr = gv.data() + (size_t)r * (k + 1);
+      gr[j + 1] = -sj * gr[j];
+      gr[j] = cj * gr[j];
+      jend[r] = j + 1;
+      st[r].iters += 1;
+    };
     // Arnoldi steps.  The coefficients of step j reach the host through the
     // pinned staging slot j % 2 while step j + 1 runs on the device; the host
     // updates the least-squares problem of step j only after it has queued
@@ -1036,51 +1058,12 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         const double hn = q > 0.0 ? sqrt(q) : 0.0;
         const double wnorm0 = sqrt(h1r[nv]);
         Hat(r, j + 1, j) = hn;
-        st[r].iters += 1;
-        // previous rotations, then a new one eliminating H[j+1][j]
-        for (int i = 0; i < j; ++i) {
-          const double a = Hat(r, i, j), bb = Hat(r, i + 1, j);
-          Hat(r, i, j) = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
-          Hat(r, i + 1, j) = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
-        }
-        const double a = Hat(r, j, j), bb = Hat(r, j + 1, j);
-        const double rho = hypot(a, bb);
+        givens(r, j);
         const bool breakdown = hn <= 1e-14 * wnorm0;
-        const double cj = rho > 0 ? a / rho : 1.0, sj = rho > 0 ? bb / rho : 0.0;
-        cs[(size_t)r * k + j] = cj;
-        sn[(size_t)r * k + j] = sj;
-        Hat(r, j, j) = rho;
-        Hat(r, j + 1, j) = 0.0;
-        double* gr = gv.data() + (size_t)r * (k + 1);
-        gr[j + 1] = -sj * gr[j];
-        gr[j] = cj * gr[j];
-        jend[r] = j + 1;
-        if (breakdown || fabs(gr[j + 1]) <= rtol * bnorm[r]) done[r] = 1;
+        if (breakdown || fabs(gv[(size_t)r * (k + 1) + j + 1]) <= rtol * bnorm[r]) done[r] = 1;
         all_done = all_done && done[r];
       }
       return all_done;
-    };
-    // Givens update of the least-squares problem with column j of H (rows
-    // 0..j+1 in Hat); returns the residual estimate |g_{j+1}| and sets done
-    // on breakdown or convergence when `decide`.
-    auto givens = [&](int r, int j) {
-      for (int i = 0; i < j; ++i) {
-        const double a = Hat(r, i, j), bb = Hat(r, i + 1, j);
-        Hat(r, i, j) = cs[(size_t)r * k + i] * a + sn[(size_t)r * k + i] * bb;
-        Hat(r, i + 1, j) = -sn[(size_t)r * k + i] * a + cs[(size_t)r * k + i] * bb;
-      }
-      const double a = Hat(r, j, j), bb = Hat(r, j + 1, j);
-      const double rho = hypot(a, bb);
-      const double cj = rho > 0 ? a / rho : 1.0, sj = rho > 0 ? bb / rho : 0.0;
-      cs[(size_t)r * k + j] = cj;
-      sn[(size_t)r * k + j] = sj;
-      Hat(r, j, j) = rho;
-      Hat(r, j + 1, j) = 0.0;
-      double* gr = gv.data() + (size_t)r * (k + 1);
-      gr[j + 1] = -sj * gr[j];
-      gr[j] = cj * gr[j];
-      jend[r] = j + 1;
-      st[r].iters += 1;
     };
     if (delayed) {
       // One reduction per step (device kernels k_dcgs_*): step j turns the
