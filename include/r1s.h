@@ -220,14 +220,15 @@ typedef struct {
 
 /* Orthogonalisation of the Arnoldi vectors (all classical Gram-Schmidt with
  * a second pass, float64): */
-#define R1S_ORTHO_SELECTIVE 0 /* second pass where |w - V h| < |w| / sqrt(2)
+#define R1S_ORTHO_DELAYED 0   /* second pass delayed to the next step and
+                                 merged with its first: one reduction and
+                                 two passes over the basis per step (the
+                                 fastest; a zeroed r1s_gmres_opts selects it) */
+#define R1S_ORTHO_SELECTIVE 1 /* second pass where |w - V h| < |w| / sqrt(2)
                                  (decided per right-hand side; always above
                                  16 basis vectors): three passes over the
                                  basis per step                             */
-#define R1S_ORTHO_CGS2 1      /* second pass on every step                 */
-#define R1S_ORTHO_DELAYED 2   /* second pass delayed to the next step and
-                                 merged with its first: one reduction and
-                                 two passes over the basis per step         */
+#define R1S_ORTHO_CGS2 2      /* second pass on every step                 */
 
 typedef struct {
   int iters;            /* Arnoldi steps (summed over inner solves)         */

@@ -31,7 +31,7 @@ R1S_MAX_BAND = 8
 R1S_MAX_NBR = 8
 R1S_OP_STRUCTURED, R1S_OP_BSR = 0, 1
 R1S_MODE_F64, R1S_MODE_MIXED_IR = 0, 1
-R1S_ORTHO_SELECTIVE, R1S_ORTHO_CGS2, R1S_ORTHO_DELAYED = 0, 1, 2
+R1S_ORTHO_DELAYED, R1S_ORTHO_SELECTIVE, R1S_ORTHO_CGS2 = 0, 1, 2
 
 
 INPUT_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v", "s_band", "s_lev_flow",

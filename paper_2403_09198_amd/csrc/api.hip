@@ -859,10 +859,14 @@ static int staging_acquire(size_t bytes, Staging** out) {
   return R1S_OK;
 }
 
+// Returns the staging buffer to the pool once the solve's stream has drained
+// (on an early error return kernels may still write into it).
 struct StagingLease {
   Staging* st = nullptr;
+  hipStream_t stream = nullptr;
   ~StagingLease() {
     if (st) {
+      (void)hipStreamSynchronize(stream);
       std::lock_guard<std::mutex> lk(g_staging_mu);
       g_staging_free.push_back(st);
     }
@@ -977,6 +981,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   std::vector<int> jend(nrhs), done(nrhs);
   auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
   StagingLease lease;
+  lease.stream = s;
   const int SS = 2 * k + 6;  // delayed scheme: staging doubles per right-hand side
   const size_t slot_doubles = (size_t)nrhs * std::max(2 * HS + 1, SS);
   if (int e = staging_acquire(2 * slot_doubles * sizeof(double), &lease.st)) return e;
@@ -1083,11 +1088,11 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
           givens(r, j);
         }
       };
+      std::vector<double> col(k + 2);
       auto trial = [&](int j, const double* stg) {  // estimated column j, staged by step j
         for (int r = 0; r < nrhs; ++r) {
           if (lastcol[r] != -1) continue;
           const double* h = stg + (size_t)r * SS;
-          std::vector<double> col(j + 2);
           for (int i = 0; i <= j; ++i) col[i] = h[k + 1 + i];
           col[j + 1] = h[2 * k + 2];
           for (int i = 0; i < j; ++i) {
