@@ -110,6 +110,11 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
   constexpr bool PRE_ARROW = WIDE && PRELOAD && ROM > RANK_OFF_SMALL;
   constexpr int NA = PRE_ARROW ? 3 : 1;
   TV arw[NA][NCH], alw[NA][NCH], xfl[NR][NA];
+  // single chunk: the band / corner partners x[pa], x[pb] of the cell's own
+  // block come from the lanes that loaded them (a lane permutation) instead
+  // of further loads
+  constexpr bool SHUFFLE_X = PRELOAD && NCH == 1;
+  int pa_s[NCH], pb_s[NCH];
   auto load_sparse = [&](int ch) {
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
@@ -140,11 +145,15 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
       for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
         uv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
     }
+    pa_s[ch] = pa;
+    pb_s[ch] = pb;
+    if constexpr (!SHUFFLE_X) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
-      xa[r][ch] = (TV)xv_c[pa];
-      xb[r][ch] = (TV)xv_c[pb];
+      for (int r = 0; r < NR; ++r) {
+        const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
+        xa[r][ch] = (TV)xv_c[pa];
+        xb[r][ch] = (TV)xv_c[pb];
+      }
     }
     if constexpr (PRE_ARROW) {
 #pragma unroll
@@ -232,6 +241,10 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+      if constexpr (SHUFFLE_X) {
+        xa[r][ch] = __shfl(xv[r][D_C][ch], pa_s[ch], WAVE);
+        xb[r][ch] = __shfl(xv[r][D_C][ch], pb_s[ch], WAVE);
+      }
       TV t = dg[ch] * xv[r][D_C][ch] + ca[ch] * xa[r][ch] + cb[ch] * xb[r][ch];
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
