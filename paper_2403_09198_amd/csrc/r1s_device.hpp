@@ -365,6 +365,18 @@ __device__ inline void smw_sweeps(int L, int m, const T (&A)[NCH], const T (&DI)
   }
 }
 
+// Element k of a cell vector held by one wave as NCH chunks of 64 lanes
+// (chunk k / 64, lane k % 64), returned wave-uniform; k is wave-uniform.
+template <typename T, int NCH>
+__device__ inline T lane_value(const T (&v)[NCH], int k) {
+  const int kc = k / WAVE, kl = k % WAVE;
+  T out = T(0);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+    if (ch == kc) out = readlane(v[ch], kl);
+  return out;
+}
+
 // Level/flow coupling on a tridiagonal level band, A0 = [T Ec; Er F]: the
 // block solve by the Schur complement of the flow unknowns, S3 = F - Er
 // T^{-1} Ec.  On entry X0 holds the sweeps' output: T^{-1} r on the level
@@ -393,14 +405,7 @@ __device__ inline void arrow_schur(int L, int m, const T (&A)[NCH], const T (&DI
   }
   T z[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int k = L + i, kc = k / WAVE, kl = k % WAVE;
-    T v = T(0);
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-      if (ch == kc) v = readlane(X0[ch], kl);
-    z[i] = v;
-  }
+  for (int i = 0; i < 3; ++i) z[i] = lane_value<T, NCH>(X0, L + i);
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch)
     if (ch * WAVE + lane < L) X0[ch] -= X[0][ch] * z[0] + X[1][ch] * z[1] + X[2][ch] * z[2];
