@@ -278,7 +278,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_graph1(Mesh g, const TV* __
     pb = L + (i + 1) % 3; vb = true;
   }
   const double* xc = xr + (long long)c * m;
-  const TV xk = (TV)xc[kk], xa = (TV)xc[pa], xb = (TV)xc[pb];
+  const TV xk = (TV)xc[kk];  // the band / corner partners come from other lanes below
   const TV dg = ld_stream(rc + F_DIAG * mp + kk);
   TV ca, cb;
   if (!TRANS) {
@@ -292,6 +292,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_graph1(Mesh g, const TV* __
   }
   __builtin_amdgcn_sched_barrier(0);
 
+  const TV xa = __shfl(xk, pa, WAVE), xb = __shfl(xk, pb, WAVE);
   TV t = dg * xk + ca * xa + cb * xb;
 #pragma unroll
   for (int p = 0; p < RDM; ++p) {
