@@ -208,6 +208,26 @@ def measure_pair(torch, f1, f2, steps, warmup):
     return wall, float(np.mean(t1)), float(np.mean(t2))
 
 
+def measure_one(torch, f, steps, warmup):
+    """Graph-replayed single-kernel steps: wall seconds for `steps` replays
+    and the kernel's average duration in ms (events around each launch)."""
+    graphs = step_graphs(torch, f)
+    replay(graphs, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    replay(graphs, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record()
+        f()
+        e1.record()
+    torch.cuda.synchronize()
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
 def profile_pass(torch, A, M, x, y, z):
     """Kernels for a counter run: 20 matvecs, 20 applies, and 5 copies of a
     256 MiB buffer (the calibration kernel of known size)."""
@@ -669,6 +689,22 @@ def main():
             "us_per_step": round(wallT / steps * 1e6, 2),
             "matvec_T_us": round(k1 * 1e3, 2), "apply_T_us": round(k2 * 1e3, 2),
             "ratio_vs_fp64": round(wallT / wall, 3)}
+        # the same pair as one kernel (r1s_matvec_prec: y = J x is written and
+        # goes straight into the SMW solve, so it is not read back); bytes are
+        # the pair's less that read of y
+        if ranks == (1, 1) and args.band == 1 and not args.arrow:
+            for key, prec, vb in (("fused_pair", "f64", mv_b + ap_b),
+                                  ("fused_fp32_pair", "f32", sum(pair_bytes(N, B, m, value_bytes=4)))):
+                fb = vb - 8 * N * m
+                wallF, kF = measure_one(
+                    torch, lambda prec=prec: M.apply_after_matvec(x, precision=prec, out_y=y, out_z=z),
+                    steps, warm)
+                two = wall if prec == "f64" else wall32
+                out[key] = {"gbs": round(fb / (wallF / steps) / 1e9, 1),
+                            "us_per_step": round(wallF / steps * 1e6, 2),
+                            "kernel_us": round(kF * 1e3, 2), "bytes_per_step": fb,
+                            "speedup_vs_two_kernels": round(two / wallF, 3)}
+                log(f"{key}: {wallF / steps * 1e6:.1f} us/step ({two / wallF:.3f}x the two kernels)")
         # eight right-hand sides per call: the matrix and factors are read
         # once per batch (the adjoint workload's batch size)
         if ranks == (1, 1) and args.band == 1 and not args.arrow:

@@ -328,6 +328,22 @@ int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
 int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs,
                    const double* r, double* z, void* stream);
 
+/* y = J x and z = M y in one call: the operator M J of the left-preconditioned
+ * system (section 6, eq. left_precond_system), with J x kept.  M must be an
+ * SMW preconditioner set up on A (R1S_ERR_ARG for another layout,
+ * R1S_ERR_UNSUPPORTED for a BSR dense-LU one).  For one right-hand side on
+ * the structured mesh with m <= 64, a tridiagonal level band without
+ * level/flow coupling, and either one pair per block or float32 values, a
+ * single kernel forms y_c and goes on to the local SMW solve of z_c in the
+ * same wavefront (y is written, never read back); otherwise the call is
+ * r1s_matvec followed by r1s_prec_apply.  The single
+ * kernel gives the same y as r1s_matvec and z equal to r1s_prec_apply's up to
+ * rounding (a few units in the last place).  precision R1S_F32 uses the float32
+ * matrix values and the float32 factors (R1S_KEEP_F32 on both).  x, y, z:
+ * device [nrhs][n] float64, caller-owned, pairwise distinct.  Asynchronous. */
+int r1s_matvec_prec(r1s_mat A, r1s_prec M, int precision, int nrhs,
+                    const double* x, double* y, double* z, void* stream);
+
 int r1s_prec_destroy(r1s_prec M);
 
 /* Dense-block BSR copy of A: every existing block D = S_{c,d} + sum u v^T stored

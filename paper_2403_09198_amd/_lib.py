@@ -102,6 +102,7 @@ SIGNATURES = {
     "r1s_prec_size": (_I, [_VP, _I, _PSZ]),
     "r1s_prec_setup": (_I, [_VP, _I, _VP, _SZ, _VP, C.POINTER(_VP)]),
     "r1s_prec_apply": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
+    "r1s_matvec_prec": (_I, [_VP, _VP, _I, _I, _VP, _VP, _VP, _VP]),
     "r1s_prec_destroy": (_I, [_VP]),
     "r1s_bsr_size": (_I, [_VP, _PSZ]),
     "r1s_bsr_init": (_I, [_VP, _VP, _SZ, _VP, C.POINTER(_VP)]),

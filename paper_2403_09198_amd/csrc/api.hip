@@ -599,6 +599,40 @@ extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, co
   return R1S_OK;
 }
 
+static bool same_layout(const Mesh& a, const Mesh& b) {
+  return a.nx == b.nx && a.ny == b.ny && a.N == b.N && a.L == b.L && a.m == b.m && a.rd == b.rd &&
+         a.ro == b.ro && a.band == b.band && a.arrow == b.arrow && a.graph == b.graph;
+}
+
+extern "C" int r1s_matvec_prec(r1s_mat A, r1s_prec M, int precision, int nrhs, const double* x,
+                               double* y, double* z, void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (!M) return fail(R1S_ERR_ARG, "preconditioner handle is NULL");
+  if (M->kind != PREC_SMW)
+    return fail(R1S_ERR_UNSUPPORTED, "r1s_matvec_prec takes an SMW preconditioner");
+  if (!same_layout(A->g, M->g)) return fail(R1S_ERR_ARG, "A and M have different layouts");
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  if (precision != R1S_F64 && precision != R1S_F32)
+    return fail(R1S_ERR_ARG, "unknown precision %d", precision);
+  const bool f32 = precision == R1S_F32;
+  if (f32 && !A->rec32)
+    return fail(R1S_ERR_ARG, "float32 matvec needs a matrix made with R1S_KEEP_F32");
+  if (f32 && !smw_has_f32(M)) return fail(R1S_ERR_ARG, "float32 apply needs R1S_KEEP_F32 at setup");
+  if (int e = check_vec(x, "x")) return e;
+  if (int e = check_vec(y, "y")) return e;
+  if (int e = check_vec(z, "z")) return e;
+  if (x == y || x == z || y == z) return fail(R1S_ERR_ARG, "x, y and z must not alias");
+  if (nrhs == 1 && matvec_prec_fused(A->g, f32)) {
+    HIP_TRY(launch_matvec_prec(A->g, f32 ? (const void*)A->rec32 : (const void*)A->rec64,
+                               f32 ? (const void*)M->facF32 : (const void*)M->facF,
+                               f32 ? (const void*)M->invC32 : (const void*)M->invC, f32, x, y, z,
+                               as_stream(stream)));
+    return R1S_OK;
+  }
+  if (int e = r1s_matvec(A, precision, 0, nrhs, x, y, stream)) return e;
+  return r1s_prec_apply(M, precision, 0, nrhs, y, z, stream);
+}
+
 extern "C" int r1s_prec_destroy(r1s_prec M) {
   free(M);
   return R1S_OK;

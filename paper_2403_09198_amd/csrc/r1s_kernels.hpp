@@ -65,6 +65,11 @@ hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, doub
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
+// y = J x and z = M y in one kernel (one right-hand side, forward); only
+// where matvec_prec_fused(g, f32) holds (else hipErrorInvalidValue)
+bool matvec_prec_fused(const Mesh& g, bool f32);
+hipError_t launch_matvec_prec(const Mesh& g, const void* rec, const void* fac, const void* invC,
+                              bool f32, const double* x, double* y, double* z, hipStream_t s);
 
 // SMW block-Jacobi for the wide diagonal-block pattern (band > 1 or level/flow
 // coupling): tile-interleaved factors, one lane per cell.  wvT may be null.

@@ -207,6 +207,10 @@ def r1s_prec_apply(p, precision, trans, nrhs, r, z, stream=None):
     check(lib().r1s_prec_apply(p, precision, int(trans), nrhs, _ptr(r), _ptr(z), _stream(stream)))
 
 
+def r1s_matvec_prec(h, p, precision, nrhs, x, y, z, stream=None):
+    check(lib().r1s_matvec_prec(h, p, precision, nrhs, _ptr(x), _ptr(y), _ptr(z), _stream(stream)))
+
+
 def r1s_bsr_size(h) -> int:
     b = C.c_size_t()
     check(lib().r1s_bsr_size(h, C.byref(b)))
@@ -372,6 +376,16 @@ class SMWPreconditioner:
         prec = L.R1S_F32 if precision == "f32" else L.R1S_F64
         r1s_prec_apply(self.h, prec, trans, nrhs, r, z, stream)
         return z
+
+    def apply_after_matvec(self, x, precision="f64", out_y=None, out_z=None, stream=None):
+        """(y, z) with y = J x and z = M y (the left-preconditioned operator
+        M J), computed by one fused kernel where the layout allows."""
+        nrhs = _need_vec(x, "x", self.A.n)
+        y = torch.empty_like(x) if out_y is None else out_y
+        z = torch.empty_like(x) if out_z is None else out_z
+        prec = L.R1S_F32 if precision == "f32" else L.R1S_F64
+        r1s_matvec_prec(self.A.h, self.h, prec, nrhs, x, y, z, stream)
+        return y, z
 
 
 class BSRMatrix:

@@ -1,7 +1,8 @@
 /*
  * A plain C caller of libr1s (no Python, no torch): reads a small problem
  * from a binary file, runs the library's matvec, transposed matvec, SMW
- * block-Jacobi apply (and its transpose) and a GMRES solve through the C ABI
+ * block-Jacobi apply (and its transpose), the fused J x / M (J x) call and a
+ * GMRES solve through the C ABI
  * of include/r1s.h with device memory from the HIP runtime, and writes the
  * results to a binary file for the parity test to compare with the oracle.
  *
@@ -12,7 +13,8 @@
  *          s_nbr [N][4][m], u [N][P][m], v [N][P][m], x [N][m], b [N][m]
  *          (tridiagonal level band, no level/flow coupling).
  * out.bin: float64 J x, J^T x, M x, M^T x, the GMRES solution of J x = b
- *          (rtol 1e-12), each [N][m]; then int32 iterations, converged.
+ *          (rtol 1e-12), J x and M (J x) from r1s_matvec_prec, each [N][m];
+ *          then int32 iterations, converged.
  * Exit status 0 on success; on failure the library's message goes to stderr.
  */
 #include <hip/hip_runtime_api.h>
@@ -115,12 +117,14 @@ int main(int argc, char** argv) {
   r1s_mat A = NULL;
   CHECK_R1S(r1s_mat_init(nx, ny, L, &lay, 0, &in, mat_mem, bytes, NULL, &A));
 
-  double *y, *yt, *z, *zt, *xs;
+  double *y, *yt, *z, *zt, *xs, *yf, *zf;
   CHECK_HIP(hipMalloc((void**)&y, n * sizeof(double)));
   CHECK_HIP(hipMalloc((void**)&yt, n * sizeof(double)));
   CHECK_HIP(hipMalloc((void**)&z, n * sizeof(double)));
   CHECK_HIP(hipMalloc((void**)&zt, n * sizeof(double)));
   CHECK_HIP(hipMalloc((void**)&xs, n * sizeof(double)));
+  CHECK_HIP(hipMalloc((void**)&yf, n * sizeof(double)));
+  CHECK_HIP(hipMalloc((void**)&zf, n * sizeof(double)));
   CHECK_R1S(r1s_matvec(A, R1S_F64, 0, 1, x, y, NULL));
   CHECK_R1S(r1s_matvec(A, R1S_F64, 1, 1, x, yt, NULL));
 
@@ -132,6 +136,7 @@ int main(int argc, char** argv) {
   CHECK_R1S(r1s_prec_setup(A, R1S_WITH_TRANS, prec_mem, bytes, NULL, &M));
   CHECK_R1S(r1s_prec_apply(M, R1S_F64, 0, 1, x, z, NULL));
   CHECK_R1S(r1s_prec_apply(M, R1S_F64, 1, 1, x, zt, NULL));
+  CHECK_R1S(r1s_matvec_prec(A, M, R1S_F64, 1, x, yf, zf, NULL));
 
   /* GMRES(30) solve of J xs = b */
   r1s_gmres_opts opts = {0};
@@ -155,7 +160,7 @@ int main(int argc, char** argv) {
     return 1;
   }
   if (save_dev(fo, y, n) || save_dev(fo, yt, n) || save_dev(fo, z, n) || save_dev(fo, zt, n) ||
-      save_dev(fo, xs, n)) {
+      save_dev(fo, xs, n) || save_dev(fo, yf, n) || save_dev(fo, zf, n)) {
     fprintf(stderr, "writing results failed\n");
     return 1;
   }

@@ -1,7 +1,7 @@
 """The C ABI without Python in between: tests/abi_client.c (built by
 __graft_entry__.build) reads a problem from a file, calls the library's
-matvec, transposed matvec, SMW block-Jacobi apply (both directions) and
-GMRES through include/r1s.h with its own hipMalloc'd buffers, and writes the
+matvec, transposed matvec, SMW block-Jacobi apply (both directions), the
+fused matvec + apply call and GMRES through include/r1s.h with its own hipMalloc'd buffers, and writes the
 results; they are compared here with the CPU oracle (section 5.2, section 6
 eq. SMW, right-preconditioned GMRES)."""
 import os
@@ -46,9 +46,9 @@ def test_c_client_matches_oracle(tmp_path, nx, ny, L, ranks):
     assert r.returncode == 0, r.stderr
     n = nx * ny * (L + 3)
     raw = open(fout, "rb").read()
-    vals = np.frombuffer(raw[:5 * n * 8], dtype=np.float64).reshape(5, nx * ny, L + 3)
-    iters, converged = np.frombuffer(raw[5 * n * 8:], dtype=np.int32)
-    y, yt, z, zt, xs = vals
+    vals = np.frombuffer(raw[:7 * n * 8], dtype=np.float64).reshape(7, nx * ny, L + 3)
+    iters, converged = np.frombuffer(raw[7 * n * 8:], dtype=np.int32)
+    y, yt, z, zt, xs, yf, zf = vals
     sc, sct = matvec_scale(p, nx, ny, L, x[None])[0], matvec_scale(p, nx, ny, L, x[None], trans=True)[0]
     assert np.all(np.abs(y - ops.matvec(p, nx, ny, L, x)) <= 1e-12 * sc + 1e-300)
     assert np.all(np.abs(yt - ops.matvec_T(p, nx, ny, L, x)) <= 1e-12 * sct + 1e-300)
@@ -56,6 +56,9 @@ def test_c_client_matches_oracle(tmp_path, nx, ny, L, ranks):
         ref = block_jacobi_ref(p, nx, ny, L, x[None], trans=trans)[0]
         rel = np.linalg.norm(got - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
         assert rel.max() <= 1e-12
+    assert np.array_equal(yf, y)
+    zref = block_jacobi_ref(p, nx, ny, L, y[None])[0]
+    assert (np.linalg.norm(zf - zref, axis=-1) / np.linalg.norm(zref, axis=-1)).max() <= 1e-12
     assert converged == 1 and iters >= 1
     J = ops.dense_matrix(p, nx, ny, L)
     assert np.linalg.norm(b.ravel() - J @ xs.ravel()) <= 2e-12 * np.linalg.norm(b)
