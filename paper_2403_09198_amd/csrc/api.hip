@@ -1008,7 +1008,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
   for (int r = 0; r < nrhs; ++r)
     if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
-  Basis Vb{W.V, n, (long long)(k + 1) * n};
+  // vector-major basis [k + 1][nrhs][n]: v_j of every right-hand side is one
+  // contiguous [nrhs][n] block, the layout the operator kernels take
+  Basis Vb{W.V, (long long)nrhs * n, n};
   std::vector<double> H((size_t)nrhs * (k + 1) * k), cs((size_t)nrhs * k), sn((size_t)nrhs * k),
       gv((size_t)nrhs * (k + 1)), y((size_t)nrhs * (k + 1)),
       beta, w0(nrhs);
@@ -1142,14 +1144,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         }
       };
       auto launch_step = [&](int j) -> int {
-        double* Vj = W.V + (long long)j * n;
-        if (nrhs == 1) {
-          if (int e = prec_apply(c, Vj, W.z, 1)) return e;
-        } else {
-          HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
-                                   n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
-          if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
-        }
+        if (int e = prec_apply(c, W.V + (long long)j * Vb.vstride, W.z, nrhs)) return e;
         if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
         HIP_TRY(launch_dcgs_dots(Vb, j, W.w, n, n, nrhs, W.part, W.nblk, s));
         HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, stage[j & 1], SS,
@@ -1182,7 +1177,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         HIP_TRY(hipEventSynchronize(lease.st->ev[(k - 1) & 1]));
         if (k >= 2) final_col(k - 2, stage[(k - 1) & 1]);
         trial(k - 1, stage[(k - 1) & 1]);
-        const double* uk = W.V + (long long)k * n;
+        const double* uk = W.V + (long long)k * Vb.vstride;
         HIP_TRY(launch_dcgs_dots(Vb, k, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
         HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, stage[k & 1], SS,
                                   true, nrhs, s));
@@ -1196,15 +1191,8 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     int pending = -1;  // step whose coefficients are staged but not yet used
     bool finished = delayed;
     for (int j = 0; j < k && !delayed; ++j) {
-      double* Vj = W.V + (long long)j * n;
-      // z = M v_j ; w = op(z)   (v_j of every rhs: strided copy into t)
-      if (nrhs == 1) {
-        if (int e = prec_apply(c, Vj, W.z, 1)) return e;
-      } else {
-        HIP_TRY(hipMemcpy2DAsync(W.t, n * sizeof(double), Vj, Vb.rstride * sizeof(double),
-                                 n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
-        if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
-      }
+      // z = M v_j ; w = op(z)
+      if (int e = prec_apply(c, W.V + (long long)j * Vb.vstride, W.z, nrhs)) return e;
       if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
       const int nv = j + 1;
       // Classical Gram-Schmidt: h1 = V^T w and |w|^2 in one pass.  The norm
@@ -1230,7 +1218,8 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       // the coefficients go to the host staging slot of this step
       const int slot = j & 1;
       HIP_TRY(launch_update_normalize(Vb, nv, W.hdev, h2, nv + 1, fused ? W.need : nullptr, W.w,
-                                      n, W.V + (long long)(j + 1) * n, n, nrhs, s, stage[slot]));
+                                      n, W.V + (long long)(j + 1) * Vb.vstride, n, nrhs, s,
+                                      stage[slot]));
       HIP_TRY(hipEventRecord(lease.st->ev[slot], s));
       if (pending >= 0) {
         HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));

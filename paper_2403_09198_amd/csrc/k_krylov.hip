@@ -337,6 +337,9 @@ __global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* 
   double* pr = part + (long long)r * rows * nblk;
   const long long stride = (long long)nblk * KB;
   const long long e0 = (long long)blockIdx.x * KB + tid;
+  // u.u, u.w, w.w ride along the first group's pass (a separate pass when
+  // there is no basis vector yet)
+  double uu = 0.0, uw = 0.0, ww = 0.0;
   for (int i = 0; i < j; i += DC_GROUP) {
     const int g = j - i < DC_GROUP ? j - i : DC_GROUP;  // block-uniform
     double acc[2 * DC_GROUP];
@@ -355,6 +358,11 @@ __global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* 
       for (int q = 0; q < DC_GROUP; ++q) {
         acc[q] += q < g ? ve[q] * ue : 0.0;
         acc[DC_GROUP + q] += q < g ? ve[q] * we : 0.0;
+      }
+      if (i == 0) {
+        uu += ue * ue;
+        uw += ue * we;
+        ww += we * we;
       }
     }
     // block sums: value q < DC_GROUP is a_{i+q} (row i + q), value
@@ -375,12 +383,13 @@ __global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* 
     }
     __syncthreads();
   }
-  double uu = 0.0, uw = 0.0, ww = 0.0;
-  for (long long e = e0; e < n; e += stride) {
-    const double ue = u[e], we = wr[e];
-    uu += ue * ue;
-    uw += ue * we;
-    ww += we * we;
+  if (j == 0) {
+    for (long long e = e0; e < n; e += stride) {
+      const double ue = u[e], we = wr[e];
+      uu += ue * ue;
+      uw += ue * we;
+      ww += we * we;
+    }
   }
   uu = wave_sum(uu);
   uw = wave_sum(uw);
