@@ -323,9 +323,37 @@ hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const doub
 
 constexpr int DC_GROUP = 16;  // basis vectors per pass of the dot products
 
+// One pass over G basis vectors i .. i+G-1 (G exact, so every load is one
+// the pass needs): acc[q] += v_{i+q} . u, acc[DC_GROUP + q] += v_{i+q} . w,
+// and with `first` also u.u, u.w, w.w.  All G + 2 loads of an element are
+// issued before the first product.
+template <int G>
+__device__ inline void dcgs_pass(const double* Vr, long long vstride, int i, const double* u,
+                                 const double* wr, long long e0, long long stride, long long n,
+                                 bool first, double (&acc)[2 * DC_GROUP], double& uu, double& uw,
+                                 double& ww) {
+  for (long long e = e0; e < n; e += stride) {
+    const double ue = u[e], we = wr[e];
+    double ve[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) ve[q] = Vr[(long long)(i + q) * vstride + e];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      acc[q] += ve[q] * ue;
+      acc[DC_GROUP + q] += ve[q] * we;
+    }
+    if (first) {
+      uu += ue * ue;
+      uw += ue * we;
+      ww += we * we;
+    }
+  }
+}
+
 // rows of step j's reduction per right-hand side: a_0..a_{j-1}, |u|^2,
 // c_0..c_{j-1}, u . w, |w|^2
-__global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* __restrict__ w,
+__global__ __launch_bounds__(KB, 4) void k_dcgs_dots(Basis B, int j, const double* __restrict__ w,
                                                   long long wstride, long long n,
                                                   double* __restrict__ part, int nblk) {
   __shared__ double sh[2 * DC_GROUP][KB / WAVE];
@@ -345,25 +373,15 @@ __global__ __launch_bounds__(KB) void k_dcgs_dots(Basis B, int j, const double* 
     double acc[2 * DC_GROUP];
 #pragma unroll
     for (int q = 0; q < 2 * DC_GROUP; ++q) acc[q] = 0.0;
-    // every load is unconditional (a short last group re-reads its last
-    // vector and discards the products), so all of them are in flight at once
-    for (long long e = e0; e < n; e += stride) {
-      const double ue = u[e], we = wr[e];
-      double ve[DC_GROUP];
-#pragma unroll
-      for (int q = 0; q < DC_GROUP; ++q)
-        ve[q] = Vr[(long long)(i + (q < g ? q : g - 1)) * B.vstride + e];
-      __builtin_amdgcn_sched_barrier(0);  // all loads issued before the first use
-#pragma unroll
-      for (int q = 0; q < DC_GROUP; ++q) {
-        acc[q] += q < g ? ve[q] * ue : 0.0;
-        acc[DC_GROUP + q] += q < g ? ve[q] * we : 0.0;
-      }
-      if (i == 0) {
-        uu += ue * ue;
-        uw += ue * we;
-        ww += we * we;
-      }
+    const bool first = i == 0;
+    switch (g) {
+#define R1S_PASS(G_) \
+  case G_: dcgs_pass<G_>(Vr, B.vstride, i, u, wr, e0, stride, n, first, acc, uu, uw, ww); break;
+      R1S_PASS(1) R1S_PASS(2) R1S_PASS(3) R1S_PASS(4) R1S_PASS(5) R1S_PASS(6) R1S_PASS(7)
+      R1S_PASS(8) R1S_PASS(9) R1S_PASS(10) R1S_PASS(11) R1S_PASS(12) R1S_PASS(13)
+      R1S_PASS(14) R1S_PASS(15) R1S_PASS(16)
+#undef R1S_PASS
+      default: break;
     }
     // block sums: value q < DC_GROUP is a_{i+q} (row i + q), value
     // DC_GROUP + q is c_{i+q} (row j + 1 + i + q)
