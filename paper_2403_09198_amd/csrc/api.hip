@@ -994,9 +994,13 @@ struct SolveStat {
 
 // Restarted right-preconditioned GMRES on nrhs systems op(x) = b, starting
 // from x (x0_given) or zero.  rtol is relative to |b| per right-hand side.
+// trust_estimate: a cycle whose least-squares residual estimate meets rtol
+// for every right-hand side ends the solve without the true residual (for
+// the inner solves of iterative refinement, whose caller forms the float64
+// residual itself).
 static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
                       double rtol, int nrhs, const double* b, double* x, bool x0_given,
-                      int ortho, std::vector<SolveStat>& st) {
+                      int ortho, bool trust_estimate, std::vector<SolveStat>& st) {
   const bool always_reorth = ortho == R1S_ORTHO_CGS2;
   const bool delayed = ortho == R1S_ORTHO_DELAYED;
   hipStream_t s = c.s;
@@ -1015,6 +1019,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       gv((size_t)nrhs * (k + 1)), y((size_t)nrhs * (k + 1)),
       beta, w0(nrhs);
   std::vector<int> jend(nrhs), done(nrhs);
+  std::vector<double> est(nrhs, -1.0);  // residual estimate at the end of the last cycle
   auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
   StagingLease lease;
   lease.stream = s;
@@ -1024,6 +1029,19 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
 
   for (int cycle = 0;; ++cycle) {
+    if (trust_estimate && cycle > 0) {
+      bool met = true;
+      for (int r = 0; r < nrhs; ++r)
+        met = met && (st[r].converged || (est[r] >= 0.0 && est[r] <= rtol * bnorm[r]));
+      if (met) {
+        for (int r = 0; r < nrhs; ++r) {
+          if (st[r].converged) continue;
+          st[r].rel = bnorm[r] > 0 ? est[r] / bnorm[r] : 0.0;
+          st[r].converged = true;
+        }
+        break;
+      }
+    }
     // true residual of the current iterate (x0 = 0: r = b, whose norms are known)
     const bool from_b = cycle == 0 && !x0_given;
     if (from_b) {
@@ -1247,6 +1265,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         for (int l = i + 1; l < je; ++l) acc -= Hat(r, i, l) * yr[l];
         yr[i] = Hat(r, i, i) != 0.0 ? acc / Hat(r, i, i) : 0.0;
       }
+      if (!st[r].converged) est[r] = fabs(gr[je]);  // |g_je| after the rotations
     }
     HIP_TRY(hipMemcpyAsync(W.ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
     int kmax = 0;
@@ -1299,19 +1318,25 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
   int rc;
   if (!mixed) {
     rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
-                    opts->x0_given != 0, opts->ortho, st);
+                    opts->x0_given != 0, opts->ortho, false, st);
     if (rc) return rc;
   } else {
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
+    // (from x = 0 the first residual is b, and the first correction is x)
     std::vector<double> bnorm, rn;
     if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;
-    if (!opts->x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * g.n * sizeof(double), s));
+    const bool zero_start = !opts->x0_given;
     OpCtx ci = c;
     ci.f32 = true;
     std::vector<SolveStat> tot(nrhs);
     for (;; ++outer) {
-      if (int e = op_residual(c, b, x, W.r64, nrhs)) return e;
-      if (int e = norms(g, W, W.r64, nrhs, s, rn)) return e;
+      const bool first = outer == 0 && zero_start;
+      if (first) {
+        rn = bnorm;
+      } else {
+        if (int e = op_residual(c, b, x, W.r64, nrhs)) return e;
+        if (int e = norms(g, W, W.r64, nrhs, s, rn)) return e;
+      }
       bool all = true;
       for (int r = 0; r < nrhs; ++r) {
         if (!(rn[r] == rn[r]) || isinf(rn[r])) return fail(R1S_ERR_NONFINITE, "refinement residual %d is not finite", r);
@@ -1319,16 +1344,19 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
         tot[r].converged = rn[r] <= opts->rtol * bnorm[r];
         all = all && tot[r].converged;
       }
-      if (all || outer == opts->max_outer) break;
+      if (all || outer == opts->max_outer) {
+        if (first) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * g.n * sizeof(double), s));
+        break;
+      }
       std::vector<SolveStat> in;
-      rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs, W.r64,
-                      W.d, false, opts->ortho, in);
+      rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs,
+                      first ? b : W.r64, first ? x : W.d, false, opts->ortho, true, in);
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r) {
         tot[r].iters += in[r].iters;
         tot[r].cycles += in[r].cycles;
       }
-      HIP_TRY(launch_axpy(nullptr, W.d, x, g.n, nrhs, s));
+      if (!first) HIP_TRY(launch_axpy(nullptr, W.d, x, g.n, nrhs, s));
     }
     st = tot;
   }
