@@ -54,17 +54,24 @@ __device__ inline Mesh kmesh(Mesh g) {
 // being skipped by a branch.  Lanes past m read element m-1 and are masked.
 // Pair slots past a block's count are skipped by wave-uniform guards.
 // WIDE: the diagonal block has further band diagonals or level/flow coupling.
+// pair2: two neighbouring waves of a workgroup share a cell, the second
+// taking right-hand sides r0 + NR .. r0 + 2 NR - 1 (the cell's rows come
+// from HBM once and from L2 for the second wave; half the registers of one
+// wave holding all 2 NR).
 template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
 __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
-                                                     double* __restrict__ y, int r0) {
+                                                     double* __restrict__ y, int r0_,
+                                                     int pair2) {
   constexpr bool EXACT = RDM == 1 && ROM == 1;
   constexpr int RM = RDM > ROM ? RDM : ROM;
   constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
   const Mesh g = kmesh<EXACT>(g_);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
+  const int wid = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
+  const int c = pair2 ? wid >> 1 : wid;
+  const int r0 = pair2 ? r0_ + (wid & 1) * NR : r0_;
   if (c >= g.N) return;
   const int lane = lane_id();
   const int m = g.m, L = g.L;
@@ -452,26 +459,29 @@ inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
     if constexpr (NCH <= 2 && EXACT) {
-      if (rem >= 8) {
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 8, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+      if (rem >= 8) {  // two waves per cell, four right-hand sides each
+        // (256 x 128, L = 61: 145 us against 159 us for one wave with all
+        // eight at 184 registers, 2 waves per SIMD; four waves of two: 175 us)
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>),
+                           dim3((2 * g.N + WPB - 1) / WPB), dim3(64 * WPB), 0, s, g, rec, x, b, y,
+                           r0, 1);
         r0 += 8;
         continue;
       }
       if (rem >= 4) {
         hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
         r0 += 4;
         continue;
       }
     }
     if (rem >= 2) {
       hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
       r0 += 2;
     } else {
       hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0);
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
       r0 += 1;
     }
   }

@@ -132,6 +132,30 @@ def test_mixed_precision_refinement():
     assert relnorm(x, host(ref.x)) <= 1e-9
 
 
+@pytest.mark.parametrize("ortho", ["delayed", "cgs2"])
+def test_mixed_refinement_batch_with_zero_rhs(ortho):
+    # one right-hand side is zero (converged before any cycle), one is small:
+    # the refinement starts from r = b, the inner solves end on their
+    # residual estimates, and every iterate meets the float64 tolerance
+    nx, ny, L = 12, 9, 20
+    log(f"mixed refinement, batch with a zero rhs, {ortho}")
+    p = gen.make_problem(nx, ny, L, seed=8)
+    b = gen.make_rhs(nx, ny, L, nrhs=3, seed=8)
+    b[1] = 0.0
+    b[2] *= 1e-3
+    A = r1s.R1Matrix(nx, ny, L, to_dev(p), keep_f32=True)
+    M = r1s.SMWPreconditioner(A, keep_f32=True)
+    res = r1s.gmres(A, M, vec(b), restart=30, rtol=1e-10, mode="mixed", ortho=ortho)
+    x = host(res.x)
+    assert np.all(x[1] == 0.0)
+    assert np.all(_true_rel_residual(p, nx, ny, L, b[[0, 2]], x[[0, 2]]) <= 1e-10)
+    assert all(st["converged"] == 1 for st in res.stats)
+    assert all(st["outer"] >= 2 for st in res.stats)
+    # an all-zero batch: no inner solve, x (allocated uninitialised) is zeroed
+    res0 = r1s.gmres(A, M, torch.zeros_like(vec(b)), mode="mixed", ortho=ortho)
+    assert float(res0.x.abs().max()) == 0.0 and all(st["converged"] == 1 for st in res0.stats)
+
+
 def test_bsr_operator_solve():
     nx, ny, L = 10, 6, 20
     p = gen.make_problem(nx, ny, L, seed=8)
