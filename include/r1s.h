@@ -370,7 +370,10 @@ int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
  * returns x = M y, for nrhs independent right-hand sides advanced together.
  * Classical Gram-Schmidt with a second pass chosen by opts->ortho
  * (R1S_ORTHO_*), float64.  Mixed mode
- * wraps float32-operator inner solves in float64 iterative refinement.
+ * wraps float32-operator inner solves in float64 iterative refinement: the
+ * float64 residual b - J x before each inner solve (b itself from x = 0)
+ * and after the last; an inner solve ends when its least-squares residual
+ * estimate meets inner_rtol.
  * `B` is used when opts->op == R1S_OP_BSR (may be NULL otherwise).
  * On R1S_ERR_NOCONV, x holds the last iterate and stats are filled (one
  * r1s_gmres_stats per right-hand side, stats may be NULL). Synchronises. */
