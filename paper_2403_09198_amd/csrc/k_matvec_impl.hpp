@@ -295,6 +295,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   constexpr int RM = RDM > ROM ? RDM : ROM;
   __shared__ TV part[NR][5][RM][NCH];
   __shared__ TV apart[WIDE ? NR : 1][3][NCH];
+  __shared__ TV xs[NR][WAVE * NCH];  // the cell's own x block (band / corner partners)
   const Mesh g = kmesh<EXACT>(g_);
   const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
     ca = va ? ta : TV(0);
     cb = vb ? tb : TV(0);
   }
-  TV nv[5], uv[5][RM], xa[NR], xb[NR];
+  TV nv[5], uv[5][RM];
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
     if (d != D_C) nv[d] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
@@ -354,13 +355,11 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
     for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
       uv[d][p] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double* xv_c = xr + (long long)r * g.n + (long long)c * m;
-    xa[r] = (TV)xv_c[pa];
-    xb[r] = (TV)xv_c[pb];
-  }
   __builtin_amdgcn_sched_barrier(0);
+  // partners x[pa], x[pb] may sit in another wave's chunk: each wave puts
+  // its chunk in LDS and reads them back after the barrier below
+#pragma unroll
+  for (int r = 0; r < NR; ++r) xs[r][k] = xv[r][D_C];
 
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    TV t = dg * xv[r][D_C] + ca * xa[r] + cb * xb[r];
+    TV t = dg * xv[r][D_C] + ca * xs[r][pa] + cb * xs[r][pb];
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
       if (d != D_C && ex[d]) t += nv[d] * xv[r][d];
