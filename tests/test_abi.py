@@ -141,6 +141,10 @@ def test_null_handles_rejected():
     fake = C.c_void_p(1 << 20)
     assert lib.r1s_matvec(None, 0, 0, 1, fake, fake, None) == L.R1S_ERR_ARG
     assert lib.r1s_prec_apply(None, 0, 0, 1, fake, fake, None) == L.R1S_ERR_ARG
+    assert lib.r1s_matvec_prec(None, fake, 0, 1, fake, fake, fake, None) == L.R1S_ERR_ARG
+    assert "matrix handle" in lib.r1s_last_error().decode()
+    assert lib.r1s_matvec_prec(fake, None, 0, 1, fake, fake, fake, None) == L.R1S_ERR_ARG
+    assert "preconditioner handle" in lib.r1s_last_error().decode()
     assert lib.r1s_bsr_matvec(None, 1, fake, fake, None) == L.R1S_ERR_ARG
     assert lib.r1s_mat_storage(None, None) == L.R1S_ERR_ARG
     assert lib.r1s_grad(None, 1, fake, fake, None, None) == L.R1S_ERR_ARG
