@@ -430,11 +430,20 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int c = c0 + j;
+    // several right-hand sides of a single-chunk cell share the coefficient
+    // half of the sweeps' scans
+    TV X0n[NR][NCH];
+    if constexpr (NCH == 1 && NR > 1)
+      smw_sweeps_nr<TV, NR, TRANS>(L, m, A[j][0], DI[j][0], B[j][0], R[j], RF[j], X0n);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       TV X0[NCH];
-      smw_sweeps<TV, NCH, TRANS>(L, m, A[j], DI[j], B[j], R[j][r], RF[j][r][0], RF[j][r][1],
-                                 RF[j][r][2], X0);
+      if constexpr (NCH == 1 && NR > 1) {
+        X0[0] = X0n[r][0];
+      } else {
+        smw_sweeps<TV, NCH, TRANS>(L, m, A[j], DI[j], B[j], R[j][r], RF[j][r][0], RF[j][r][1],
+                                   RF[j][r][2], X0);
+      }
       if constexpr (ARW) arrow_schur<TV, NCH>(L, m, A[j], DI[j], B[j], X[j], E[j], X0);
       TV s[RDM], z[RDM];
 #pragma unroll

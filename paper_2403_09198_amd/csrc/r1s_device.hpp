@@ -365,6 +365,71 @@ __device__ inline void smw_sweeps(int L, int m, const T (&A)[NCH], const T (&DI)
   }
 }
 
+// The sweeps of smw_sweeps for NR right-hand sides of one single-chunk cell
+// (m <= 64).  The coefficient half of each affine scan (the products of A or
+// B within a row of 16 lanes, and the row prefixes) is the same for every
+// right-hand side, so it is formed once; each right-hand side then takes
+// only its own half.  The operations, and their order, are those of
+// smw_sweeps (the results agree with it to rounding).
+template <typename T, int NR, bool TRANS>
+__device__ inline void smw_sweeps_nr(int L, int m, T A, T DI, T B, const T (&R)[NR][1],
+                                     const T (&RF)[NR][3], T (&X0)[NR][1]) {
+  const int lane = lane_id();
+  const bool lev = lane < L;
+  const int row = lane >> 4;
+  T Y[NR];
+  {  // forward: y_k = A_k y_{k-1} + (TRANS ? DI_k R_k : R_k)
+    T a = lev ? A : T(0);
+    T as[4];
+#define R1S_STAGE(S, N)                         \
+    as[S] = a;                                  \
+    a = a * dpp<DPP_ROW_SHR + N>(T(1), a);
+    R1S_STAGE(0, 1) R1S_STAGE(1, 2) R1S_STAGE(2, 4) R1S_STAGE(3, 8)
+#undef R1S_STAGE
+    const T a1 = readlane(a, 31), a2 = readlane(a, 47);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T b = lev ? (TRANS ? DI * R[r][0] : R[r][0]) : T(0);
+      b = as[0] * dpp<DPP_ROW_SHR + 1>(T(0), b) + b;
+      b = as[1] * dpp<DPP_ROW_SHR + 2>(T(0), b) + b;
+      b = as[2] * dpp<DPP_ROW_SHR + 4>(T(0), b) + b;
+      b = as[3] * dpp<DPP_ROW_SHR + 8>(T(0), b) + b;
+      const T b0 = readlane(b, 15), b1 = readlane(b, 31), b2 = readlane(b, 47);
+      const T pb1 = b0;
+      const T pb2 = a1 * pb1 + b1;
+      const T pb3 = a2 * pb2 + b2;
+      const T pb = row == 0 ? T(0) : row == 1 ? pb1 : row == 2 ? pb2 : pb3;
+      Y[r] = a * pb + b;
+    }
+  }
+  {  // backward: x_k = B_k x_{k+1} + (TRANS ? y_k : DI_k y_k); flow lanes
+    T a = lev ? B : T(0);
+    T as[4];
+#define R1S_STAGE(S, N)                         \
+    as[S] = a;                                  \
+    a = a * dpp<DPP_ROW_SHL + N>(T(1), a);
+    R1S_STAGE(0, 1) R1S_STAGE(1, 2) R1S_STAGE(2, 4) R1S_STAGE(3, 8)
+#undef R1S_STAGE
+    const T a2 = readlane(a, 32), a1 = readlane(a, 16);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T b = lev ? (TRANS ? Y[r] : DI * Y[r]) : T(0);
+      b = as[0] * dpp<DPP_ROW_SHL + 1>(T(0), b) + b;
+      b = as[1] * dpp<DPP_ROW_SHL + 2>(T(0), b) + b;
+      b = as[2] * dpp<DPP_ROW_SHL + 4>(T(0), b) + b;
+      b = as[3] * dpp<DPP_ROW_SHL + 8>(T(0), b) + b;
+      const T b3 = readlane(b, 48), b2 = readlane(b, 32), b1 = readlane(b, 16);
+      const T sb2 = b3;
+      const T sb1 = a2 * sb2 + b2;
+      const T sb0 = a1 * sb1 + b1;
+      const T sb = row == 3 ? T(0) : row == 2 ? sb2 : row == 1 ? sb1 : sb0;
+      const T x0 = a * sb + b;
+      const T xf = A * RF[r][0] + DI * RF[r][1] + B * RF[r][2];
+      X0[r][0] = lev ? x0 : (lane < m ? xf : T(0));
+    }
+  }
+}
+
 // Element k of a cell vector held by one wave as NCH chunks of 64 lanes
 // (chunk k / 64, lane k % 64), returned wave-uniform; k is wave-uniform.
 template <typename T, int NCH>

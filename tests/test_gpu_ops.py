@@ -139,6 +139,25 @@ def test_bitwise_deterministic():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("L", [8, 61])
+def test_batched_apply_equals_one_at_a_time(L):
+    # several right-hand sides per launch share the coefficient half of the
+    # sweeps' scans; the results agree with one right-hand side per launch
+    # to rounding (8 = one launch of eight, 7 = 4 + 2 + 1)
+    nx, ny = 9, 7
+    log(f"batched apply vs single nx={nx} ny={ny} L={L}")
+    p, A, M = _setup(nx, ny, L, seed=5)
+    for nrhs in (8, 7):
+        r = vec(gen.make_rhs(nx, ny, L, nrhs=nrhs, seed=nrhs))
+        for trans in (False, True):
+            for prec, tol in (("f64", 1e-14), ("f32", 8 * (L + 3) * U32)):
+                zb = host(M.apply(r, trans=trans, precision=prec))
+                zs = np.concatenate([host(M.apply(r[i:i + 1].contiguous(), trans=trans,
+                                                  precision=prec)) for i in range(nrhs)])
+                log(f"  nrhs={nrhs} trans={trans} {prec}: {int(np.sum(zb == zs))}/{zb.size} equal")
+                assert _per_cell_rel(zb, zs) <= tol, (nrhs, trans, prec)
+
+
 @pytest.mark.parametrize("nx,ny,L", [(16, 16, 8), (1, 1, 1), (5, 3, 2), (7, 5, 61), (3, 4, 62),
                                      (2, 3, 125), (3, 2, 200)])
 def test_bsr_parity(nx, ny, L):
