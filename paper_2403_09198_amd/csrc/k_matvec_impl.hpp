@@ -261,7 +261,10 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
       }
       if constexpr (WIDE) {
         const double* xc = xr + (long long)r * g.n + (long long)c * m;
-        t += bl.apply(g, xc);
+        if constexpr (SHUFFLE_X)
+          t += bl.apply_lanes(g, xv[r][D_C][ch]);
+        else
+          t += bl.apply(g, xc);
         if (g.arrow) {
           // level lanes: coupling entries times the flow unknowns; flow lane
           // L + i: the coupling sum
@@ -269,6 +272,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
           for (int i = 0; i < 3; ++i) {
             if constexpr (PRE_ARROW)
               t += al[i] * xfl[r][i];
+            else if constexpr (SHUFFLE_X)
+              t += al[i] * readlane(xv[r][D_C][ch], L + i);
             else
               t += al[i] * (TV)xc[L + i];
           }

@@ -572,6 +572,17 @@ struct BandLane {
     }
     return s;
   }
+  // The same with the cell's x block held one element per lane (m <= 64):
+  // the partners come from the lanes that hold them.
+  __device__ inline TV apply_lanes(const Mesh& g, TV xk) const {
+    TV s = TV(0);
+#pragma unroll
+    for (int t = 0; t < BAND_MAX - 1; ++t) {
+      if (t + 2 > g.band) break;
+      s += alo[t] * __shfl(xk, ilo[t], WAVE) + ahi[t] * __shfl(xk, ihi[t], WAVE);
+    }
+    return s;
+  }
 };
 
 }  // namespace r1s
