@@ -80,9 +80,9 @@ def summarize_counters(fetch_csv, write_csv):
            "write_factor": round(wf, 4), "calibration_kernel": cp,
            "commands": [
                "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-               "-d <repo>/gpurun_out/pmc_fetch -o fetch -- python3 <repo>/bench.py --profile-pass",
+               "-d <out>/pmc_fetch -o fetch -- python3 <repo>/bench.py --profile-pass",
                "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-               "-d <repo>/gpurun_out/pmc_write -o write -- python3 <repo>/bench.py --profile-pass",
+               "-d <out>/pmc_write -o write -- python3 <repo>/bench.py --profile-pass",
                "python bench.py --summarize-counters <fetch csv> <write csv>"],
            "kernels": {}}
     for name in fetch:
@@ -583,7 +583,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is a design, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
