@@ -1007,9 +1007,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   const long long n = g.n;
   const int HS = k + 2;  // stride of the per-rhs h arrays
   std::vector<double> bnorm;
-  if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;
-  st.assign(nrhs, SolveStat());
   if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
+  if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;  // leaves |b|^2 in W.scal
+  st.assign(nrhs, SolveStat());
   for (int r = 0; r < nrhs; ++r)
     if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
   // vector-major basis [k + 1][nrhs][n]: v_j of every right-hand side is one
@@ -1061,13 +1061,12 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     if (all || cycle == max_cycles) break;
     for (int r = 0; r < nrhs; ++r) {
       st[r].cycles += done[r] ? 0 : 1;
-      y[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;  // scale factors for v_0
       jend[r] = 0;
       for (int i = 0; i <= k; ++i) gv[(size_t)r * (k + 1) + i] = 0.0;
       gv[(size_t)r * (k + 1)] = beta[r];
     }
-    HIP_TRY(hipMemcpyAsync(W.scal, y.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_scale(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
+    // v_0 = r / |r|, the squared norms still in W.scal from the last norms()
+    HIP_TRY(launch_scale_unit(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
 
     // Givens update of the least-squares problem with column j of H (rows
     // 0..j+1 in Hat): the previous rotations, then a new one eliminating

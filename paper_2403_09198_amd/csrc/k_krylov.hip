@@ -631,6 +631,26 @@ hipError_t launch_scale(const double* w, long long wstride, const double* inv, d
   return hipGetLastError();
 }
 
+// out_r = w_r / |w_r| from the squared norms sq[r] (0 where |w_r| = 0)
+__global__ __launch_bounds__(KB) void k_scale_unit(const double* __restrict__ w, long long wstride,
+                                                   const double* __restrict__ sq,
+                                                   double* __restrict__ out, long long ostride,
+                                                   long long n) {
+  const int r = blockIdx.y;
+  const double q = sq[r];
+  const double s = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
+       e += (long long)gridDim.x * KB)
+    out[(long long)r * ostride + e] = w[(long long)r * wstride + e] * s;
+}
+
+hipError_t launch_scale_unit(const double* w, long long wstride, const double* sq, double* out,
+                             long long ostride, long long n, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_unit, vec_grid(n, nrhs), dim3(KB), 0, s, w, wstride, sq, out, ostride,
+                     n);
+  return hipGetLastError();
+}
+
 // out_r = sum_i y[r*ystride + i] V_i
 __global__ __launch_bounds__(KB) void k_combine(Basis B, int nv, const double* __restrict__ y,
                                                 int ystride, double* __restrict__ out,

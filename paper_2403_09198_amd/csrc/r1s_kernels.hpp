@@ -129,6 +129,8 @@ hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const doub
                                    hipStream_t s, double* stage = nullptr);
 hipError_t launch_scale(const double* w, long long wstride, const double* inv, double* out,
                         long long ostride, long long n, int nrhs, hipStream_t s);
+hipError_t launch_scale_unit(const double* w, long long wstride, const double* sq, double* out,
+                             long long ostride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_combine(Basis B, int nv, const double* y, int ystride, double* out,
                           long long ostride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_rsub(const double* bv, double* yv, long long n, int nrhs, hipStream_t s);
