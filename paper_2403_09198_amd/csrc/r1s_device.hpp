@@ -33,9 +33,9 @@ namespace r1s {
 
 constexpr int WAVE = 64;
 #ifndef R1S_WPB
-#define R1S_WPB 4
+#define R1S_WPB 2  // 256 x 128, L = 61: matvec 53.9 us against 54.7 with 4 or 8
 #endif
-constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels
+constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels (even)
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
 constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_BAND = 7;
 // General mesh: neighbour slot s is addressed as direction GSLOT + s.
