@@ -974,15 +974,18 @@ static int op_residual(const OpCtx& c, const double* b, const double* x, double*
 }
 
 // Norms of nrhs contiguous vectors of length n (deterministic, float64).
+// |v_r| per right-hand side (|v_r|^2 stays in W.scal); `pinned` (nrhs
+// doubles of pinned host memory, or null) receives the device copy.
 static int norms(const Mesh& g, GmresWork& W, const double* v, int nrhs, hipStream_t s,
-                 std::vector<double>& out) {
+                 std::vector<double>& out, double* pinned = nullptr) {
   Basis none{W.V, 0, 0};
   HIP_TRY(launch_multidot(none, 0, v, g.n, g.n, nrhs, W.part, W.nblk, true, s));
   HIP_TRY(launch_reduce(W.part, nrhs, W.nblk, W.scal, s));
   out.assign(nrhs, 0.0);
-  HIP_TRY(hipMemcpyAsync(out.data(), W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  double* dst = pinned ? pinned : out.data();
+  HIP_TRY(hipMemcpyAsync(dst, W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  for (auto& x : out) x = sqrt(x);
+  for (int r = 0; r < nrhs; ++r) out[r] = sqrt(dst[r]);
   return R1S_OK;
 }
 
@@ -1006,9 +1009,21 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   hipStream_t s = c.s;
   const long long n = g.n;
   const int HS = k + 2;  // stride of the per-rhs h arrays
+  // pinned host staging: two slots of Arnoldi coefficients, then the norms
+  // and the least-squares solution of a cycle
+  StagingLease lease;
+  lease.stream = s;
+  const int SS = 2 * k + 6;  // delayed scheme: staging doubles per right-hand side
+  const size_t slot_doubles = (size_t)nrhs * std::max(2 * HS + 1, SS);
+  const size_t y_doubles = (size_t)nrhs * (k + 1);
+  if (int e = staging_acquire((2 * slot_doubles + nrhs + y_doubles) * sizeof(double), &lease.st))
+    return e;
+  double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
+  double* pin_norm = (double*)lease.st->mem + 2 * slot_doubles;
+  double* pin_y = pin_norm + nrhs;
   std::vector<double> bnorm;
   if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
-  if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;  // leaves |b|^2 in W.scal
+  if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm)) return e;  // leaves |b|^2 in W.scal
   st.assign(nrhs, SolveStat());
   for (int r = 0; r < nrhs; ++r)
     if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
@@ -1021,12 +1036,6 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   std::vector<int> jend(nrhs), done(nrhs);
   std::vector<double> est(nrhs, -1.0);  // residual estimate at the end of the last cycle
   auto Hat = [&](int r, int i, int j) -> double& { return H[((size_t)r * (k + 1) + i) * k + j]; };
-  StagingLease lease;
-  lease.stream = s;
-  const int SS = 2 * k + 6;  // delayed scheme: staging doubles per right-hand side
-  const size_t slot_doubles = (size_t)nrhs * std::max(2 * HS + 1, SS);
-  if (int e = staging_acquire(2 * slot_doubles * sizeof(double), &lease.st)) return e;
-  double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
 
   for (int cycle = 0;; ++cycle) {
     if (trust_estimate && cycle > 0) {
@@ -1048,7 +1057,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       beta = bnorm;
     } else {
       if (int e = op_residual(c, b, x, W.w, nrhs)) return e;
-      if (int e = norms(g, W, W.w, nrhs, s, beta)) return e;
+      if (int e = norms(g, W, W.w, nrhs, s, beta, pin_norm)) return e;
     }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
@@ -1266,7 +1275,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       if (!st[r].converged) est[r] = fabs(gr[je]);  // |g_je| after the rotations
     }
-    HIP_TRY(hipMemcpyAsync(W.ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    // (the next cycle's norms synchronise before pin_y is written again)
+    std::copy(y.begin(), y.end(), pin_y);
+    HIP_TRY(hipMemcpyAsync(W.ydev, pin_y, y.size() * sizeof(double), hipMemcpyHostToDevice, s));
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, jend[r]);
     HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
