@@ -1334,7 +1334,11 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
     // (from x = 0 the first residual is b, and the first correction is x)
     std::vector<double> bnorm, rn;
-    if (int e = norms(g, W, b, nrhs, s, bnorm)) return e;
+    StagingLease nlease;  // pinned landing buffer of the outer norms
+    nlease.stream = s;
+    if (int e = staging_acquire((size_t)nrhs * sizeof(double), &nlease.st)) return e;
+    double* pin_norm = (double*)nlease.st->mem;
+    if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm)) return e;
     const bool zero_start = !opts->x0_given;
     OpCtx ci = c;
     ci.f32 = true;
@@ -1345,7 +1349,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
         rn = bnorm;
       } else {
         if (int e = op_residual(c, b, x, W.r64, nrhs)) return e;
-        if (int e = norms(g, W, W.r64, nrhs, s, rn)) return e;
+        if (int e = norms(g, W, W.r64, nrhs, s, rn, pin_norm)) return e;
       }
       bool all = true;
       for (int r = 0; r < nrhs; ++r) {
