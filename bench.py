@@ -1,7 +1,9 @@
 """Benchmark of the r1-sparse hot path on one MI355X.
 
-A step is one application of the operator pair the metric names, on the
-256 x 128 mesh with L = 61 levels (m = 64), float64:
+A step is one application of the operator pair the metric names, float64,
+on the 512 x 256 mesh with L = 200 levels (m = 203), the largest of the
+single-GPU configurations (the mixed-precision case and the top of the level
+sweep):
 
     y = J x        (structured matvec kernel)
     z = M y        (SMW block-Jacobi apply kernel)
@@ -9,10 +11,14 @@ A step is one application of the operator pair the metric names, on the
 `value` is the algorithmic HBM bytes of the pair (stored structural values
 plus input and output vectors, section-3 counts) per second over the timed
 steps.  Per-kernel times come from HIP events on the launch stream.  The
-same JSON line carries the float32-preconditioner pair, the adjoint pair
-(J^T x, M^T y), the dense-block BSR baseline pair on the same matrix, a
-cold-cache variant, a full GMRES solve, a device copy ceiling and the CPU
-oracle timed on a bounded sample of the same workload.
+same JSON line carries, at the same size, the float32-preconditioner pair,
+the adjoint pair (J^T x, M^T y), float64 and mixed-precision GMRES solves
+and the dense-block BSR baseline (on the 512 x 128 half mesh: the full one
+needs 216 GB of blocks); then the 256 x 128, L = 61 workload (the pair, the
+fused kernel, eight right-hand sides, the paper's pair counts, the wide
+diagonal block, the physics-shaped Jacobian, a general mesh, solves), a
+device copy ceiling, and the CPU oracle timed on a bounded sample of the
+headline workload, which also checks the GPU solves on sampled rows.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -30,8 +36,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "J*x + SMW precond apply GB/s (%HBM peak); FP32-precond & adjoint vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "counters_pair_fp64_mesh256x128_L61.json")
-KERNEL_SOURCES = ("k_matvec.hip", "k_matvec_impl.hpp", "k_smw.hip", "r1s_device.hpp")
+DEFAULT_WORKLOAD = "mesh512x256_L200"
+KERNEL_SOURCES = ("k_matvec.hip", "k_matvec_impl.hpp", "k_packed.hip", "k_packed_impl.hpp",
+                  "k_smw.hip", "r1s_device.hpp")
+
 
 
 def kernel_source_hash():
@@ -44,21 +52,37 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic(kernel_prefix):
-    """HBM bytes per launch from the committed counter summary, or None when
-    it was taken on other kernel sources."""
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"counters_pair_fp64_{workload}.json")
+
+
+def counter_kind(name):
+    """'matvec' / 'apply' for the structured matvec and SMW apply kernels."""
+    if name.startswith("void r1s::k_matvec") and "k_matvec_prec" not in name:
+        return "matvec"
+    if name.startswith("void r1s::k_smw_apply"):
+        return "apply"
+    return None
+
+
+def counter_traffic(workload, kind):
+    """HBM bytes per launch of the matvec or apply kernel from the committed
+    counter summary of `workload`, or None when it was taken on other kernel
+    sources."""
     try:
-        with open(COUNTERS) as f:
+        with open(counters_path(workload)) as f:
             c = json.load(f)
     except OSError:
         return None
     if c.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    k = c["kernels"].get(kernel_prefix)
-    return None if k is None else k["traffic_bytes"]
+    for name, k in c["kernels"].items():
+        if counter_kind(name) == kind:
+            return {"kernel": name, "traffic_bytes": k["traffic_bytes"]}
+    return None
 
 
-def summarize_counters(fetch_csv, write_csv):
+def summarize_counters(workload, fetch_csv, write_csv):
     """Write the counter summary from the FETCH_SIZE and WRITE_SIZE runs of
     --profile-pass.  Each counter is scaled by what it reads for the 256 MiB
     device copy in the same run (268435456 bytes read and written)."""
@@ -76,24 +100,27 @@ def summarize_counters(fetch_csv, write_csv):
     cp = [k for k in fetch if "copyBuffer" in k or "copy" in k.lower()][0]
     ff = copy_bytes / (max(fetch[cp]) * 1024)
     wf = copy_bytes / (max(write[cp]) * 1024)
-    out = {"kernel_source_sha256": kernel_source_hash(), "fetch_factor": round(ff, 4),
-           "write_factor": round(wf, 4), "calibration_kernel": cp,
+    out = {"workload": workload, "kernel_source_sha256": kernel_source_hash(),
+           "fetch_factor": round(ff, 4), "write_factor": round(wf, 4), "calibration_kernel": cp,
            "commands": [
                "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-               "-d <out>/pmc_fetch -o fetch -- python3 <repo>/bench.py --profile-pass",
+               f"-d <out>/pmc_fetch -o fetch -- python3 <repo>/bench.py --workload {workload} "
+               "--profile-pass",
                "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-               "-d <out>/pmc_write -o write -- python3 <repo>/bench.py --profile-pass",
-               "python bench.py --summarize-counters <fetch csv> <write csv>"],
+               f"-d <out>/pmc_write -o write -- python3 <repo>/bench.py --workload {workload} "
+               "--profile-pass",
+               f"python bench.py --workload {workload} --summarize-counters <fetch csv> "
+               "<write csv>"],
            "kernels": {}}
     for name in fetch:
-        if not name.startswith(("void r1s::k_matvec", "void r1s::k_smw_apply")):
+        if counter_kind(name) is None:
             continue
         fk = sum(fetch[name]) / len(fetch[name])
         wk = sum(write[name]) / len(write[name])
         out["kernels"][name] = {"fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
                                 "dispatches": len(fetch[name]),
                                 "traffic_bytes": int(fk * 1024 * ff + wk * 1024 * wf)}
-    with open(COUNTERS, "w") as f:
+    with open(counters_path(workload), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
 
@@ -513,52 +540,278 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(p, nx, ny, L, budget_s=12.0):
-    """The oracle's dense-block matvec + dense-LU block-Jacobi apply on a
-    sample of block rows (blocks assembled and factored beforehand), repeated
-    for about `budget_s` seconds; GB/s of the same algorithmic bytes."""
+def host_cores():
+    """Worker processes for the all-cores legs: the CPU share the process may
+    use (OMP_NUM_THREADS where the job sets it), at most 16."""
+    n = os.environ.get("OMP_NUM_THREADS")
+    n = int(n) if n and n.isdigit() else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+# The CPU legs run the oracle on a sub-mesh of the headline workload's
+# generator (same L and m, same value distributions): every block row of it
+# has the full workload's structure.
+CPU_SUBMESH = (16, 16)
+
+
+def _cpu_leg(args):
+    """One worker of a CPU leg: the oracle's float64 pair on its share of the
+    sub-mesh's block rows, repeated for `budget` seconds.  path 'dense': the
+    dense-block matvec + dense-LU block-Jacobi (blocks assembled and factored
+    beforehand); 'structured': the CSR + BR1 product of section 5.2 and the
+    SMW solve of section 6 (formats and index arrays built beforehand).
+    Returns (passes, cells, seconds)."""
+    path, L, seed, part, nparts, budget = args
     from threadpoolctl import threadpool_limits
 
-    from oracle import assemble, blockjacobi, ops
+    from oracle import assemble, blockjacobi, formats, ops
+    from paper_2403_09198_amd import gen
 
+    nx, ny = CPU_SUBMESH
     N, m = nx * ny, L + 3
-    ncell = min(N, 1024)
-    cells = list(range(ncell))
-    x = np.random.default_rng(5).standard_normal((1, N, m))
-    indptr, indices, data, rows = assemble.assemble_bsr(p, nx, ny, L, cells)
-    D = assemble.diagonal_blocks(p, nx, ny, L, cells)
-    LU, piv = blockjacobi.lu_factor(D)
-    B_s = len(indices)
-    mv, ap = pair_bytes(ncell, B_s, m)
-    reps = 0
+    p = gen.make_problem(nx, ny, L, seed=seed)
+    cells = list(range(part, N, nparts))
+    x = np.random.default_rng(5).standard_normal((N, m))
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+        if path == "dense":
+            indptr, indices, data, rows = assemble.assemble_bsr(p, nx, ny, L, cells)
+            LU, piv = blockjacobi.lu_factor(assemble.diagonal_blocks(p, nx, ny, L, cells))
+
+            def once():
+                y = ops.bsr_matvec(indptr, indices, data, rows, x, N)
+                blockjacobi.lu_solve(LU, piv, y[0])
+        else:
+            csr = formats.structured_csr(p, nx, ny, L)
+            br1 = formats.structured_br1(p, nx, ny)
+            # the rows of this worker's cells: CSR rows and BR1 block rows
+            ind, ptr = csr[1], csr[2]
+            sub_rows = [c * m + k for c in cells for k in range(m)]
+            sub_ptr = np.concatenate([[0], np.cumsum([ptr[r + 1] - ptr[r] for r in sub_rows])])
+            sel = np.concatenate([np.arange(ptr[r], ptr[r + 1]) for r in sub_rows])
+            sub_csr = (csr[0][sel], ind[sel], sub_ptr)
+            # the worker's block rows, renumbered 0..len(cells)-1
+            blocks = []
+            for i, c in enumerate(cells):
+                for b in range(br1["block_indptr"][c], br1["block_indptr"][c + 1]):
+                    q0, q1 = br1["pair_indptr"][b], br1["pair_indptr"][b + 1]
+                    blocks.append((i, int(br1["block_indices"][b]),
+                                   [(br1["column_data"][q], br1["row_data"][q])
+                                    for q in range(q0, q1)]))
+            sub_br1 = formats.br1_bsr(blocks, len(cells))
+            xf = np.ravel(x)
+
+            def once():
+                y = formats.csr_matvec(*sub_csr, xf)
+                y, _ = formats.br1_matvec(sub_br1, xf, m, m, y=y)
+                yc = y.reshape(len(cells), m)
+                for i, c in enumerate(cells):
+                    blockjacobi.smw_solve(p, c, L, yc[i])
+        once()
+        reps, t0 = 0, time.perf_counter()
         while True:
-            y = ops.bsr_matvec(indptr, indices, data, rows, x, N)
-            blockjacobi.lu_solve(LU, piv, y[0])
+            once()
             reps += 1
             el = time.perf_counter() - t0
-            if el >= budget_s:
+            if el >= budget:
                 break
+    return reps, len(cells), el
+
+
+def cpu_baseline(L, seed=0, budget_s=4.0):
+    """The oracle's float64 pair (dense path and structured path) on the
+    sub-mesh, one process and one per host core.  Rates are in GB/s of the
+    same algorithmic bytes as the GPU line (the structured pair's per-cell
+    bytes times the cells processed), so the figures compare work done."""
+    import concurrent.futures as cf
+
+    nx, ny = CPU_SUBMESH
+    N, m = nx * ny, L + 3
+    B = 5 * N - 2 * nx - 2 * ny
+    mv, ap = pair_bytes(N, B, m)
+    per_cell = (mv + ap) / N
+    cores = host_cores()
+    legs = {}
+    for path in ("dense", "structured"):
+        for nproc in (1, cores):
+            jobs = [(path, L, seed, i, nproc, budget_s) for i in range(nproc)]
+            if nproc == 1:
+                res = [_cpu_leg(jobs[0])]
+            else:
+                with cf.ProcessPoolExecutor(max_workers=nproc) as ex:
+                    res = list(ex.map(_cpu_leg, jobs))
+            gbs = sum(r * c * per_cell / el for r, c, el in res) / 1e9
+            legs[f"{path}_{'1core' if nproc == 1 else f'{nproc}cores'}"] = {
+                "gbs": round(gbs, 4), "processes": nproc,
+                "passes": [r for r, _, _ in res], "seconds": round(max(el for _, _, el in res), 2)}
+            log(f"cpu baseline {path} x{nproc}: {gbs:.4f} GB/s")
+    best = max(legs, key=lambda k: legs[k]["gbs"])
     return {
-        "value": round((mv + ap) * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1,
+        "value": legs[best]["gbs"], "unit": "GB/s", "cores": legs[best]["processes"],
         "kind": "oracle",
-        "sample": (f"{ncell} of {N} block rows ({B_s} dense blocks, m={m}) of the same "
-                   f"workload, dense-block matvec + dense-LU block-Jacobi apply, blocks "
-                   f"assembled and factored beforehand, {reps} passes in {el:.1f} s, "
-                   f"1 BLAS thread"),
-        "seconds": round(el, 2),
+        "sample": (f"{nx}x{ny} sub-mesh of the same generator at L={L} (m={m}, {N} block rows); "
+                   f"float64 pair y = J x, z = M y by the oracle: 'dense' = dense-block matvec + "
+                   f"dense-LU block-Jacobi, 'structured' = CSR + BR1 product (sec. 5.2) + SMW "
+                   f"solve (sec. 6), each for {budget_s:.0f} s on 1 process and on one process "
+                   f"per core (block rows split between them, 1 BLAS thread each); GB/s of the "
+                   f"structured pair's algorithmic bytes per cell; value = the best leg ({best})"),
+        "legs": legs,
         "host": cpu_model() or platform.processor() or platform.machine(),
-        "host_cpus": os.cpu_count(),
+        "host_cpus": os.cpu_count(), "cores_used": cores,
     }
+
+
+def oracle_solve_checks(p, nx, ny, L, b, xs, k=24):
+    """The float64 residual b - J x of each GPU solve on sampled block rows,
+    by the oracle's dense-block rows: componentwise against (|J||x| + |b|)
+    and normwise over the rows, for each solution in `xs` (host arrays)."""
+    from oracle import ops
+
+    rng = np.random.default_rng(11)
+    N = nx * ny
+    cells = sorted(set(rng.choice(N, size=min(k, N), replace=False).tolist()) |
+                   {0, nx - 1, N - nx, N - 1})
+    pa = {key: np.abs(v) for key, v in p.items() if isinstance(v, np.ndarray)}
+    bs = b[:, cells]
+    out = {}
+    for tag, x in xs.items():
+        r = bs - ops.matvec_rows(p, nx, ny, L, x, cells)
+        scale = ops.matvec_rows(pa, nx, ny, L, np.abs(x), cells) + np.abs(bs)
+        out[tag] = {"cells": len(cells),
+                    "max_componentwise": float(np.max(np.abs(r) / scale)),
+                    "sampled_rel_residual": float(np.linalg.norm(r) / np.linalg.norm(bs))}
+    return out
+
+
+def pair_line(torch, A, M, x, y, z, steps, warm, mv_b, ap_b):
+    """Graph-replayed float64 pair steps and per-kernel event durations."""
+    graphs = step_graphs(torch, lambda: (A.matvec(x, out=y), M.apply(y, out=z)))
+    replay(graphs, warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    replay(graphs, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-kernel durations: HIP events around every launch of the same
+    # alternating sequence, on the stream the library launches on (timing a
+    # kernel back-to-back with itself would let the 256 MB Infinity Cache
+    # hold part of its working set)
+    _, t_mv, t_ap = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
+                              steps, warm)
+    return wall, t_mv, t_ap
+
+
+def solve_rows(torch, A, M, b, restart, rtol, modes=("f64", "mixed")):
+    from paper_2403_09198_amd import r1s
+    out, xs = {}, {}
+    for mode in modes:
+        r1s.gmres(A, M, b, restart=restart, rtol=rtol, mode=mode)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(SOLVE_REPS):
+            res = r1s.gmres(A, M, b, restart=restart, rtol=rtol, mode=mode)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / SOLVE_REPS
+        out[f"solve_{mode}"] = {"ms": round(el * 1e3, 2), "iters": res.stats[0]["iters"],
+                                "outer": res.stats[0]["outer"],
+                                "rel_residual": res.stats[0]["rel_residual"]}
+        xs[mode] = res.x
+    if "f64" in xs and "mixed" in xs:
+        out["solve_mixed"]["rel_diff_vs_f64_solve"] = float(
+            torch.linalg.norm(xs["mixed"] - xs["f64"]) / torch.linalg.norm(xs["f64"]))
+    return out, xs
+
+
+def c2_block(torch, steps, warm):
+    """The 256 x 128, L = 61 workload (m = 64): the pair, the pair as one
+    kernel, eight right-hand sides, the paper's pair counts, the wide
+    diagonal block, the physics-shaped Jacobian, a general mesh, solves."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    w = gen.WORKLOADS["mesh256x128_L61"]
+    nx, ny, L, m, N = w.nx, w.ny, w.L, w.m, w.N
+    B = 5 * N - 2 * nx - 2 * ny
+    log(f"c2 block: {w.name}")
+    p = gen.make_problem(nx, ny, L, seed=w.seed)
+    A = r1s.R1Matrix(nx, ny, L, {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS},
+                     keep_f32=True)
+    M = r1s.SMWPreconditioner(A, keep_f32=True, with_trans=True)
+    del p
+    x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    mv_b, ap_b = pair_bytes(N, B, m)
+    wall, t_mv, t_ap = pair_line(torch, A, M, x, y, z, steps, warm, mv_b, ap_b)
+    mv_ms, ap_ms = float(np.mean(t_mv)), float(np.mean(t_ap))
+    out = {"workload": w.name, "bytes_per_step": mv_b + ap_b,
+           "gbs": round((mv_b + ap_b) / (wall / steps) / 1e9, 1),
+           "us_per_step": round(wall / steps * 1e6, 2),
+           "pct_hbm_peak": round(100 * (mv_b + ap_b) / (wall / steps) / 1e9 / HBM_PEAK_GBS, 2),
+           "matvec_us": round(mv_ms * 1e3, 2), "apply_us": round(ap_ms * 1e3, 2),
+           "matvec_gbs": round(mv_b / (mv_ms / 1e3) / 1e9, 1),
+           "apply_gbs": round(ap_b / (ap_ms / 1e3) / 1e9, 1),
+           "matvec_traffic": counter_traffic(w.name, "matvec"),
+           "apply_traffic": counter_traffic(w.name, "apply")}
+    # the pair as one kernel (r1s_matvec_prec: y = J x is written and goes
+    # straight into the SMW solve, so it is not read back)
+    for key, prec, vb in (("fused_pair", "f64", mv_b + ap_b),
+                          ("fused_fp32_pair", "f32", sum(pair_bytes(N, B, m, value_bytes=4)))):
+        fb = vb - 8 * N * m
+        wallF, kF = measure_one(
+            torch, lambda prec=prec: M.apply_after_matvec(x, precision=prec, out_y=y, out_z=z),
+            steps, warm)
+        out[key] = {"gbs": round(fb / (wallF / steps) / 1e9, 1),
+                    "us_per_step": round(wallF / steps * 1e6, 2),
+                    "kernel_us": round(kF * 1e3, 2), "bytes_per_step": fb}
+    # eight right-hand sides per call: the matrix and factors are read once
+    # per batch (the adjoint workload's batch size)
+    nb8 = 8
+    x8 = torch.from_numpy(gen.make_vector(nx, ny, L, nrhs=nb8, seed=1)).to(dev)
+    y8, z8 = torch.empty_like(x8), torch.empty_like(x8)
+    mv8, ap8 = pair_bytes(N, B, m, nrhs=nb8)
+    n8 = max(20, steps // 4)
+    wall8, k1, k2 = measure_pair(torch, lambda: A.matvec(x8, out=y8),
+                                 lambda: M.apply(y8, out=z8), n8, 10)
+    out["batched_pair_nrhs8"] = {
+        "gbs": round((mv8 + ap8) / (wall8 / n8) / 1e9, 1),
+        "us_per_step": round(wall8 / n8 * 1e6, 2),
+        "us_per_rhs": round(wall8 / n8 / nb8 * 1e6, 2),
+        "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
+        "speedup_per_rhs_vs_single": round((wall / steps) / (wall8 / n8 / nb8), 2)}
+    del x8, y8, z8
+    b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
+    rows, _ = solve_rows(torch, A, M, b, w.restart, w.rtol)
+    out.update(rows)
+    del A, M, x, y, z, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # the paper's rank structure (9 pairs per diagonal block, 2 per
+    # neighbour block) on the same mesh
+    out["paper_ranks_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm)
+    # and a wider diagonal block: level band of half-width 4 with
+    # level/flow coupling (banded-LU block-Jacobi)
+    out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
+                                          band=4, arrow=True)
+    # physics-shaped values: the HLL finite-volume Jacobian of a multi-species
+    # gas (8 / 6 pairs, level/flow coupling), with GMRES solves of it
+    try:
+        out["physics_pair"] = ranks_pair(torch, nx, ny, L, None, steps, warm,
+                                         physics_values=True, solve=(w.restart, w.rtol))
+    except Exception as e:  # report, never hide
+        out["physics_pair"] = {"error": str(e)}
+    # general mesh: about 32 800 triangle cells (Delaunay of 16 400 random
+    # points), the same L, one pair per block; shuffled and mesh-ordered
+    out["general_mesh_pair"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm)
+    out["general_mesh_pair_ordered"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm,
+                                                 shuffle=False)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="mesh256x128_L61")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--ranks", default="1,1",
                     help="rank-one pairs per diagonal,neighbour block of the timed step "
                          "(the workload's own layout is 1,1)")
@@ -570,7 +823,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the FP64 pair (for profiling runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the counter summary from two --pmc runs of --profile-pass")
+                    help="write the counter summary of --workload from two --pmc runs of "
+                         "--profile-pass")
     ap.add_argument("--solvers", action="store_true",
                     help="mixed-precision and adjoint time-to-solution (one JSON line each)")
     ap.add_argument("--sweep", action="store_true",
@@ -579,7 +833,7 @@ def main():
                     help="run the fixed kernel sequence used for hardware-counter runs")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        summarize_counters(args.workload, *args.summarize_counters)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -602,6 +856,7 @@ def main():
     dev = "cuda:0"
     log(f"workload {w.name}: mesh {nx}x{ny}, L={L}, m={m}, blocks={B}")
     ranks = tuple(int(v) for v in args.ranks.split(","))
+    plain = ranks == (1, 1) and args.band == 1 and not args.arrow
     p = gen.make_problem(nx, ny, L, seed=w.seed, inv_dt=w.inv_dt, r_diag=ranks[0],
                          r_off=ranks[1], band=args.band, arrow=args.arrow)
     keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
@@ -615,7 +870,7 @@ def main():
     z = torch.empty_like(x)
 
     mv_b, ap_b = pair_bytes(N, B, m)
-    if ranks != (1, 1) or args.band != 1 or args.arrow:
+    if not plain:
         st = A.storage()
         mv_b, ap_b = st["matvec_bytes"], st["smw_apply_bytes"]
     steps, warm = args.steps, args.warmup
@@ -625,25 +880,15 @@ def main():
 
     # one step = matvec + apply, captured as HIP graphs (STEPS_PER_GRAPH steps
     # per graph) and replayed
-    graphs = step_graphs(torch, lambda: (A.matvec(x, out=y), M.apply(y, out=z)))
-    replay(graphs, warm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    replay(graphs, steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, t_mv, t_ap = pair_line(torch, A, M, x, y, z, steps, warm, mv_b, ap_b)
     ms_step = wall / steps * 1e3
     value = (mv_b + ap_b) / (wall / steps) / 1e9
-    # per-kernel durations: HIP events around every launch of the same
-    # alternating sequence, on the stream the library launches on (timing a
-    # kernel back-to-back with itself would let the 256 MB Infinity Cache
-    # hold most of its working set)
-    _, t_mv, t_ap = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
-                              steps, warm)
     mv_ms, ap_ms = float(np.mean(t_mv)), float(np.mean(t_ap))
     log(f"fp64 pair: {ms_step * 1e3:.1f} us/step, matvec {mv_ms * 1e3:.1f} us, "
         f"apply {ap_ms * 1e3:.1f} us, {value:.0f} GB/s")
     ach = mv_b / (mv_ms / 1e3) / 1e9
+    tr = counter_traffic(w.name, "matvec") if plain else None
+    tra = counter_traffic(w.name, "apply") if plain else None
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": steps, "warmup": warm, "ms_per_step": round(ms_step, 5),
@@ -652,15 +897,16 @@ def main():
         "config": {"workload": w.name, "nx": nx, "ny": ny, "L": L, "m": m, "nrhs": 1,
                    "pairs_per_block": {"diagonal": ranks[0], "neighbour": ranks[1]},
                    "diag_block_band": args.band, "level_flow_coupling": bool(args.arrow),
-                   "step": "y = J x then z = M y (SMW block-Jacobi), float64, replayed from HIP graphs of %d steps" % STEPS_PER_GRAPH,
+                   "step": "y = J x then z = M y (SMW block-Jacobi), float64, replayed from "
+                           "HIP graphs of %d steps" % STEPS_PER_GRAPH,
                    "bytes_per_step": mv_b + ap_b},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "cell_updates_per_s": round(N / (wall / steps), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_matvec<double,1,1,false,false,1,1,false> (J x)",
+        "roofline": {"bound": "hbm",
+                     "kernel": (tr["kernel"] if tr else "structured matvec (J x)"),
                      "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(
-                         "void r1s::k_matvec<double, 1, 1, false, false, 1, 1, false>"),
+                     "traffic": tr["traffic_bytes"] if tr else None,
                      "avg_launch_us": round(mv_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": mv_b},
         "kernels_us": {"matvec_f64": round(mv_ms * 1e3, 2), "smw_apply_f64": round(ap_ms * 1e3, 2)},
@@ -669,8 +915,15 @@ def main():
             "smw_apply_f64": [round(float(np.median(t_ap)) * 1e3, 2), round(float(np.min(t_ap)) * 1e3, 2)]},
         "kernel_gbs": {"matvec_f64": round(ach, 1),
                        "smw_apply_f64": round(ap_b / (ap_ms / 1e3) / 1e9, 1)},
+        "smw_apply_roofline": {"achieved": round(ap_b / (ap_ms / 1e3) / 1e9, 1),
+                               "frac": round(ap_b / (ap_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "traffic": tra["traffic_bytes"] if tra else None,
+                               "kernel": tra["kernel"] if tra else None,
+                               "algorithmic_bytes_per_launch": ap_b},
     }
 
+    xs = {}
+    b = None
     if not args.no_extras:
         # float32 values + accumulation (vectors stay float64)
         mv32, ap32 = pair_bytes(N, B, m, value_bytes=4)
@@ -689,110 +942,74 @@ def main():
             "us_per_step": round(wallT / steps * 1e6, 2),
             "matvec_T_us": round(k1 * 1e3, 2), "apply_T_us": round(k2 * 1e3, 2),
             "ratio_vs_fp64": round(wallT / wall, 3)}
-        # the same pair as one kernel (r1s_matvec_prec: y = J x is written and
-        # goes straight into the SMW solve, so it is not read back); bytes are
-        # the pair's less that read of y
-        if ranks == (1, 1) and args.band == 1 and not args.arrow:
-            for key, prec, vb in (("fused_pair", "f64", mv_b + ap_b),
-                                  ("fused_fp32_pair", "f32", sum(pair_bytes(N, B, m, value_bytes=4)))):
-                fb = vb - 8 * N * m
-                wallF, kF = measure_one(
-                    torch, lambda prec=prec: M.apply_after_matvec(x, precision=prec, out_y=y, out_z=z),
-                    steps, warm)
-                two = wall if prec == "f64" else wall32
-                out[key] = {"gbs": round(fb / (wallF / steps) / 1e9, 1),
-                            "us_per_step": round(wallF / steps * 1e6, 2),
-                            "kernel_us": round(kF * 1e3, 2), "bytes_per_step": fb,
-                            "speedup_vs_two_kernels": round(two / wallF, 3)}
-                log(f"{key}: {wallF / steps * 1e6:.1f} us/step ({two / wallF:.3f}x the two kernels)")
-        # eight right-hand sides per call: the matrix and factors are read
-        # once per batch (the adjoint workload's batch size)
-        if ranks == (1, 1) and args.band == 1 and not args.arrow:
-            nb8 = 8
-            x8 = torch.from_numpy(gen.make_vector(nx, ny, L, nrhs=nb8, seed=1)).to(dev)
-            y8, z8 = torch.empty_like(x8), torch.empty_like(x8)
-            mv8, ap8 = pair_bytes(N, B, m, nrhs=nb8)
-            n8 = max(20, steps // 4)
-            wall8, k1, k2 = measure_pair(torch, lambda: A.matvec(x8, out=y8),
-                                         lambda: M.apply(y8, out=z8), n8, 10)
-            out["batched_pair_nrhs8"] = {
-                "gbs": round((mv8 + ap8) / (wall8 / n8) / 1e9, 1),
-                "us_per_step": round(wall8 / n8 * 1e6, 2),
-                "us_per_rhs": round(wall8 / n8 / nb8 * 1e6, 2),
-                "matvec_us": round(k1 * 1e3, 2), "apply_us": round(k2 * 1e3, 2),
-                "speedup_per_rhs_vs_single": round((wall / steps) / (wall8 / n8 / nb8), 2)}
-            del x8, y8, z8
-        # cold: a 1 GiB buffer is read before every step (a read leaves clean
-        # lines, so no write-back of the flush competes with the timed kernels)
-        scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        sink = torch.empty((), dtype=torch.float64, device=dev)
-        _, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
-                              min(steps, 50), 5, flush=lambda: torch.sum(scratch, dim=0, out=sink))
-        cold = (float(np.mean(t1)) + float(np.mean(t2))) / 1e3
-        out["cold_fp64_pair"] = {"gbs": round((mv_b + ap_b) / cold / 1e9, 1),
-                                 "matvec_us": round(float(np.mean(t1)) * 1e3, 2),
-                                 "apply_us": round(float(np.mean(t2)) * 1e3, 2)}
+        # GMRES(50) to 1e-10 in float64 and in mixed-precision refinement
+        b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
+        rows, xsd = solve_rows(torch, A, M, b, w.restart, w.rtol)
+        out.update(rows)
+        xs = {k: v.cpu().numpy() for k, v in xsd.items()}
         # device copy ceiling (torch copy kernel, read + write bytes)
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         cp_ms = kernel_ms(torch, lambda: dst.copy_(src), reps=10)
         out["torch_copy_gbs"] = round(2 * src.numel() * 8 / (cp_ms / 1e3) / 1e9, 1)
-        del scratch, src, dst
-        # dense-block BSR baseline on the same matrix
+        del src, dst, xsd
+    del A, M, x, y, z
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_extras and plain:
+        # dense-block BSR baseline: quadratic in m, so at m > 128 on the half
+        # mesh (512 x 128 at L = 200: 107.6 GB of blocks + 21.6 GB of LU)
+        hx, hy = (nx, ny // 2) if m > 128 else (nx, ny)
         try:
-            Bm = r1s.BSRMatrix(A)
-            P = r1s.DenseLUPreconditioner(Bm)
-            bmv, bap = bsr_pair_bytes(N, B, m)
-            nb = max(10, steps // 10)
-            wallB, k1, k2 = measure_pair(torch, lambda: Bm.matvec(x, out=y),
-                                         lambda: P.apply(y, out=z), nb, 3)
-            out["bsr_pair"] = {
-                "gbs": round((bmv + bap) / (wallB / nb) / 1e9, 1),
-                "us_per_step": round(wallB / nb * 1e6, 2),
-                "matvec_us": round(k1 * 1e3, 2), "lu_apply_us": round(k2 * 1e3, 2),
-                "stored_values": B * m * m,
-                "speedup_structured_vs_bsr": round((wallB / nb) / (wall / steps), 2)}
-            del Bm, P
+            out["bsr_pair"] = bsr_compare(torch, hx, hy, L, w.seed, steps)
         except Exception as e:  # report, never hide
             out["bsr_pair"] = {"error": str(e)}
-        # the paper's rank structure (9 pairs per diagonal block, 2 per
-        # neighbour block) on the same mesh
-        out["paper_ranks_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm)
-        # and a wider diagonal block: level band of half-width 4 with
-        # level/flow coupling (banded-LU block-Jacobi, one lane per cell)
-        out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
-                                              band=4, arrow=True)
-        # the same mesh with physics-shaped values: the HLL finite-volume
-        # Jacobian of a multi-species gas (8 / 6 pairs, level/flow coupling),
-        # with GMRES solves of it
-        try:
-            out["physics_pair"] = ranks_pair(torch, nx, ny, L, None, steps, warm,
-                                             physics_values=True, solve=(w.restart, w.rtol))
-        except Exception as e:  # report, never hide
-            out["physics_pair"] = {"error": str(e)}
-        # general mesh: about 32 800 triangle cells (Delaunay of 16 400 random
-        # points), the same L, one pair per block; shuffled and mesh-ordered
-        # cell numbering
-        out["general_mesh_pair"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm)
-        out["general_mesh_pair_ordered"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm,
-                                                     shuffle=False)
-        # full GMRES(50) solve to 1e-10 (float64) and the mixed-precision solve
-        b = torch.from_numpy(gen.make_rhs(nx, ny, L, seed=w.seed)).to(dev)
-        for mode in ("f64", "mixed"):
-            r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol, mode=mode)  # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(SOLVE_REPS):
-                res = r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol, mode=mode)
-            torch.cuda.synchronize()
-            el = (time.perf_counter() - t0) / SOLVE_REPS
-            out[f"solve_{mode}"] = {"ms": round(el * 1e3, 2), "iters": res.stats[0]["iters"],
-                                    "outer": res.stats[0]["outer"],
-                                    "rel_residual": res.stats[0]["rel_residual"]}
+        out["c2"] = c2_block(torch, steps, warm)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, nx, ny, L)
+        out["cpu_baseline"] = cpu_baseline(L, seed=w.seed)
+        if xs:
+            log("oracle checks of the solves on sampled rows ...")
+            chk = oracle_solve_checks(p, nx, ny, L, b.cpu().numpy(), xs)
+            for mode, c in chk.items():
+                out[f"solve_{mode}"]["oracle_rows"] = c
     print(json.dumps(out), flush=True)
+
+
+def bsr_compare(torch, nx, ny, L, seed, steps):
+    """The structured float64 pair against the dense-block BSR pair (BSR
+    matvec + dense-LU block-Jacobi apply) on the same matrix."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    m, N = L + 3, nx * ny
+    B = 5 * N - 2 * nx - 2 * ny
+    log(f"bsr comparison: mesh {nx}x{ny} L={L}")
+    p = gen.make_problem(nx, ny, L, seed=seed)
+    A = r1s.R1Matrix(nx, ny, L, {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS})
+    del p
+    M = r1s.SMWPreconditioner(A)
+    x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    mv, ap = pair_bytes(N, B, m)
+    ws, _, _ = measure_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z),
+                            steps, 10)
+    Bm = r1s.BSRMatrix(A)
+    P = r1s.DenseLUPreconditioner(Bm)
+    bmv, bap = bsr_pair_bytes(N, B, m)
+    nb = 5 if m > 128 else max(10, steps // 10)
+    wallB, k1, k2 = measure_pair(torch, lambda: Bm.matvec(x, out=y), lambda: P.apply(y, out=z),
+                                 nb, 2)
+    res = {"mesh": f"{nx}x{ny}", "L": L, "stored_values": B * m * m,
+           "gbs": round((bmv + bap) / (wallB / nb) / 1e9, 1),
+           "us_per_step": round(wallB / nb * 1e6, 2),
+           "matvec_us": round(k1 * 1e3, 2), "lu_apply_us": round(k2 * 1e3, 2),
+           "structured_us_per_step": round(ws / steps * 1e6, 2),
+           "speedup_structured_vs_bsr": round((wallB / nb) / (ws / steps), 2)}
+    del A, M, Bm, P, x, y, z
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -124,8 +124,14 @@ template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   if (!ranks_supported(g.rd, g.ro) || g.band > BAND_MAX) return hipErrorInvalidValue;
-  if (!wide_pattern(g) && g.rd == 1 && g.ro == 1)
+  if (!wide_pattern(g) && g.rd == 1 && g.ro == 1) {
+#ifndef R1S_NO_PACKED
+    if (nrhs == 1 && packed_ok(g))
+      return launch_matvec_packed(g, rec, std::is_same<TV, float>::value, TRANS, RESID, x, b, y, 0,
+                                  s);
+#endif
     return launch_mv_r<TV, TRANS, RESID, 1, 1, false>(g, rec, x, b, y, nrhs, s);
+  }
   // several pairs per block or the wide diagonal block: the general
   // instantiations, compiled in files of their own
   const int kind = (TRANS ? 1 : 0) | (RESID ? 2 : 0) | (std::is_same<TV, float>::value ? 4 : 0);

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         }
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-      y[o] = RESID ? b[o] - (double)t : (double)t;
+      st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
     }
   }
 }
@@ -291,7 +291,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
 // 64w .. 64w+63 of one cell, issues all of its loads at once (like the
 // single-chunk kernel), and the pair coefficients are summed over the waves
 // through LDS in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE,
+          bool BAND = false>
 __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __restrict__ rec,
                                                         const double* __restrict__ x,
                                                         const double* __restrict__ b,
@@ -302,7 +303,14 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   __shared__ TV apart[WIDE ? NR : 1][3][NCH];
   __shared__ TV xs[NR][WAVE * NCH];  // the cell's own x block (band / corner partners)
   const Mesh g = kmesh<EXACT>(g_);
-  const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+  int c0, qn;
+  if (BAND) {
+    band_tile(g, (int)blockIdx.x, 1, c0, qn);
+    if (qn == 0) return;  // the whole workgroup
+  } else {
+    c0 = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  }
+  const int c = __builtin_amdgcn_readfirstlane(c0);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
   const int m = g.m, L = g.L;
@@ -424,7 +432,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
       }
     }
     const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-    y[o] = RESID ? b[o] - (double)t : (double)t;
+    st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
   }
 }
 

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
           TV o = X0[ch];
 #pragma unroll
           for (int i = 0; i < RDM; ++i) o -= z[i] * W[j][i][ch];
-          if (k < m) zv[k] = (double)o;
+          if (k < m) st_out(zv + k, (double)o, g.ntst);
         }
       }
     }
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
   __shared__ TV fa[NR][NCH], fb[NR][NCH], ga[NR][NCH], gb[NR][NCH], ss[NR][RDM][NCH];
   constexpr int NX = ARW ? 3 : 1;
   __shared__ TV tt[NR][NX][NCH], zz[NR][NX];
-  const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+  const int c = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, (int)gridDim.x));
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = lane_id();
   const int L = g.L, m = g.m;
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
     TV o = X0[r];
 #pragma unroll
     for (int i = 0; i < RDM; ++i) o -= z[i] * W[i];
-    if (k < m) zout[(long long)(r0 + r) * g.n + (long long)c * m + k] = (double)o;
+    if (k < m) st_out(zout + (long long)(r0 + r) * g.n + (long long)c * m + k, (double)o, g.ntst);
   }
 }
 
@@ -627,6 +627,14 @@ static hipError_t launch_apply_t(const Mesh& g, const TV* fac, const TV* invC, c
     int r0 = 0;
     while (r0 < nrhs) {
       const int rem = nrhs - r0;
+      // m > 128, one pair: a single right-hand side runs one wave per cell
+      // over its chunks (no workgroup barrier; 249 us against 263 us for the
+      // workgroup form at 512 x 256, m = 203)
+      if (NCH > 2 && RDM == 1 && !ARW && rem == 1) {
+        hipLaunchKernelGGL((k_smw_apply<TV, NCH, 1, TRANS, RDM, ARW>), dim3((g.N + WPB - 1) / WPB), dim3(64 * WPB), 0, s, g, fac, invC, r, z, r0);
+        r0 += 1;
+        continue;
+      }
       if (RDM == 1 && rem >= 4) {
         hipLaunchKernelGGL((k_smw_apply_wg<TV, NCH, RDM == 1 ? 4 : 2, TRANS, RDM, ARW>), dim3(g.N), dim3(64 * NCH), 0, s, g, fac, invC, r, z, r0);
         r0 += RDM == 1 ? 4 : 2;
@@ -693,6 +701,10 @@ static hipError_t launch_apply_rank(const Mesh& g, const TV* fac, const TV* invC
 hipError_t launch_smw_apply(const Mesh& g, const void* fac, const void* invC, bool f32, bool trans,
                             const double* r, double* z, int nrhs, hipStream_t s) {
   if (band_walk(g)) return hipErrorInvalidValue;
+#ifndef R1S_NO_PACKED
+  if (nrhs == 1 && packed_apply_ok(g))
+    return launch_smw_apply_packed(g, fac, invC, f32, trans, r, z, 0, s);
+#endif
   if (f32)
     return trans ? launch_apply_rank<float, true>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s)
                  : launch_apply_rank<float, false>(g, (const float*)fac, (const float*)invC, r, z, nrhs, s);

@@ -76,6 +76,9 @@ struct Mesh {
   // slot of this cell in the neighbour's list; offb [N] = first off-diagonal
   // block of each cell in input order
   int graph, nbmax;
+  // output vectors written with non-temporal stores (vectors larger than
+  // the Infinity Cache share they could stay in; see st_out)
+  int ntst;
   const int* nbr;
   const int* tslot;
   const int* offb;
@@ -119,6 +122,51 @@ __device__ inline int xcd_tile(int bid, int grid) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// ------------------------------------------------------------ tile maps ----
+// Column-band map: tiles are TQ consecutive cells of one mesh row inside one
+// of NXCD column bands, and workgroup b takes band b % NXCD, row by row.
+// The dispatcher sends workgroup b to XCD b % NXCD, so each XCD sweeps one
+// column band upwards: the x blocks a cell reads from its S, W, E and N
+// neighbours were read moments before by the same XCD and come from its L2.
+// (Consecutive cells dealt round-robin over the XCDs fetch each x block into
+// three L2s, and N/S rows apart again from HBM.)
+__host__ __device__ inline int band_tiles(int nx, int TQ) {
+  const int bw = (nx + NXCD - 1) / NXCD;
+  return (bw + TQ - 1) / TQ;
+}
+__host__ inline int band_grid(const Mesh& g, int TQ) { return NXCD * g.ny * band_tiles(g.nx, TQ); }
+
+// First cell and cell count (0: an empty tile of a narrow band) of tile b.
+__device__ inline void band_tile(const Mesh& g, int b, int TQ, int& c0, int& qn) {
+  const int band = b % NXCD, local = b / NXCD;
+  const int tb = band_tiles(g.nx, TQ);
+  const int iy = local / tb, s = local - iy * tb;
+  const int x0 = (int)((long long)band * g.nx / NXCD);
+  const int x1 = (int)((long long)(band + 1) * g.nx / NXCD);
+  const int a = x0 + s * TQ;
+  c0 = iy * g.nx + a;
+  const int w = x1 - a;
+  qn = iy < g.ny ? (w < TQ ? (w > 0 ? w : 0) : TQ) : 0;
+}
+
+// Plain map: tile b is cells b TQ .. b TQ + TQ - 1.
+__device__ inline void plain_tile(const Mesh& g, int b, int TQ, int& c0, int& qn) {
+  c0 = b * TQ;
+  qn = g.N - c0 < TQ ? g.N - c0 : TQ;
+}
+
+template <bool BAND>
+__device__ inline void cell_tile(const Mesh& g, int b, int TQ, int& c0, int& qn) {
+  if (BAND)
+    band_tile(g, b, TQ, c0, qn);
+  else
+    plain_tile(g, b, TQ, c0, qn);
+}
+template <bool BAND>
+__host__ inline int cell_grid(const Mesh& g, int TQ) {
+  return BAND ? band_grid(g, TQ) : (g.N + TQ - 1) / TQ;
+}
+
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
 
 // Load of streamed matrix data (read once per kernel), marked non-temporal
@@ -131,6 +179,21 @@ __device__ inline T ld_stream(const T* p) {
 #else
   return __builtin_nontemporal_load(p);
 #endif
+}
+
+// Store of a kernel's output vector.  Large outputs (Mesh::ntst) are
+// written non-temporally: an output written back through the caches as
+// ordinary lines competes with the streamed matrix reads for HBM turnarounds
+// (measured on MI355X: a streaming read with 1/16 as many bytes written
+// drops from 7.37 TB/s to 5.78 with ordinary stores and to 5.94 with
+// non-temporal ones).  Small outputs are written normally, so that the next
+// kernel (the SMW apply after the matvec) finds them in the 256 MB Infinity
+// Cache.
+__device__ inline void st_out(double* p, double v, int nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Neighbour cells of c in the order S, W, C, E, N (-1 where no block).

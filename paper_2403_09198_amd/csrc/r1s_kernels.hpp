@@ -57,6 +57,19 @@ hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, c
 hipError_t launch_residual(const Mesh& g, const double* rec, bool trans, const double* b,
                            const double* x, double* r, int nrhs, hipStream_t s);
 
+// Packed workgroup forms (one pair per block, tridiagonal band, no
+// coupling, one right-hand side r0 per launch): y = J x / J^T x / b - J x
+// for 32 <= m <= 256 (packed_ok), and z = M r / M^T r for 32 <= m < 64
+// (packed_apply_ok)
+bool packed_ok(const Mesh& g);
+bool packed_apply_ok(const Mesh& g);
+hipError_t launch_matvec_packed(const Mesh& g, const void* rec, bool f32, bool trans, bool resid,
+                                const double* x, const double* b, double* y, int r0,
+                                hipStream_t s);
+hipError_t launch_smw_apply_packed(const Mesh& g, const void* fac, const void* invC, bool f32,
+                                   bool trans, const double* r, double* z, int r0,
+                                   hipStream_t s);
+
 // SMW block-Jacobi
 // invC: per cell the rd x rd inverse capacitance matrix, forward then (when
 // facT) transposed, [2][N][rd][rd] (one [N][rd][rd] without facT)

@@ -189,3 +189,44 @@ def test_storage_counts():
         assert s["structured_values"] == storage.structured_values(nx, ny, m)
         assert s["bsr_values"] == storage.bsr_values(nx, ny, m)
         assert s["n_blocks"] == storage.n_blocks(nx, ny)
+
+
+# Meshes whose rows span several packed tiles: one pair per block, m not a
+# multiple of 64 (Q = floor(1024 / m) cells per workgroup; the matvec tiles
+# are Q cells of a row inside one of eight column bands, the last ragged),
+# nx below, at and above the band count.
+PACKED_SHAPES = [(50, 3, 200), (61, 3, 126), (250, 2, 32), (37, 5, 32), (9, 4, 62), (5, 7, 120),
+                 (17, 3, 29), (3, 11, 70)]
+
+
+@pytest.mark.parametrize("nx,ny,L", PACKED_SHAPES)
+def test_packed_parity(nx, ny, L):
+    log(f"packed parity nx={nx} ny={ny} L={L}")
+    p, A, M = _setup(nx, ny, L, seed=2)
+    x = gen.make_vector(nx, ny, L, seed=8)
+    xd = vec(x)
+    ref = ops.matvec(p, nx, ny, L, x)
+    sc = matvec_scale(p, nx, ny, L, x)
+    check_componentwise(host(A.matvec(xd)), ref, sc, TOL64, "J x")
+    reft = ops.matvec_T(p, nx, ny, L, x)
+    sct = matvec_scale(p, nx, ny, L, x, trans=True)
+    check_componentwise(host(A.matvec(xd, trans=True)), reft, sct, TOL64, "J^T x")
+    tol32 = (L + 3 + 16) * U32
+    check_componentwise(host(A.matvec(xd, precision="f32")), ref, sc, tol32, "J x (f32)")
+    check_componentwise(host(A.matvec(xd, trans=True, precision="f32")), reft, sct, tol32,
+                        "J^T x (f32)")
+    b = gen.make_rhs(nx, ny, L, seed=3)
+    check_componentwise(host(A.residual(vec(b), xd)), b - ref, sc + np.abs(b), TOL64, "b - J x")
+    zr = block_jacobi_ref(p, nx, ny, L, x)
+    assert _per_cell_rel(host(M.apply(xd)), zr) <= TOL64
+    zrt = block_jacobi_ref(p, nx, ny, L, x, trans=True)
+    assert _per_cell_rel(host(M.apply(xd, trans=True)), zrt) <= TOL64
+    tol32a = 8 * (L + 3) * U32
+    assert _per_cell_rel(host(M.apply(xd, precision="f32")), zr) <= tol32a
+    assert _per_cell_rel(host(M.apply(xd, trans=True, precision="f32")), zrt) <= tol32a
+    # every output entry written: poisoned outputs must be overwritten
+    y = torch.full_like(xd, float("nan"))
+    A.matvec(xd, out=y)
+    z = torch.full_like(xd, float("nan"))
+    M.apply(xd, out=z)
+    assert bool(torch.isfinite(y).all()) and bool(torch.isfinite(z).all())
