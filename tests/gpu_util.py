@@ -71,3 +71,30 @@ def sample_cells(nx, ny, k=48, seed=0):
     fixed = {0, nx - 1, N - nx, N - 1, nx, nx + 1, N // 2}
     picks = set(rng.choice(N, size=min(k, N), replace=False).tolist())
     return sorted(c for c in fixed | picks if 0 <= c < N)
+
+
+U64 = 2.0 ** -53  # unit roundoff of float64
+
+
+def gamma(k, u=U64):
+    """gamma_k = k u / (1 - k u): the bound on the relative rounding error of
+    a sum of k products (Higham, Accuracy and Stability, Lemma 3.1)."""
+    return k * u / (1.0 - k * u)
+
+
+def residual_bound(p, nx, ny, L, b, x, rtol, terms, cells=None, trans=False):
+    """What the oracle's residual b - J x may reach, in the 2-norm over the
+    block rows `cells` (all by default), for an x whose float64 residual the
+    library computed to be at most rtol |b|_2 per right-hand side: the
+    library's residual on those rows (at most its whole norm) plus the
+    difference of two float64 evaluations of b - J x, each within
+    gamma_terms (|J||x| + |b|) componentwise.  Returns one bound per
+    right-hand side."""
+    b3 = np.asarray(b)
+    x3 = np.asarray(x)
+    scale = matvec_scale(p, nx, ny, L, x3, cells, trans)
+    bc = b3 if cells is None else b3[:, cells]
+    s = scale + np.abs(bc)
+    nb = np.linalg.norm(b3.reshape(b3.shape[0], -1), axis=1)
+    ns = np.linalg.norm(s.reshape(s.shape[0], -1), axis=1)
+    return rtol * nb + 2.0 * gamma(terms) * ns

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DEV, host, log, relnorm, to_dev, vec
+from gpu_util import DEV, host, log, relnorm, residual_bound, sample_cells, to_dev, vec
 from oracle import grads as ograds, ops
 from paper_2403_09198_amd import autograd, gen, r1s
 
@@ -74,10 +74,11 @@ def test_gradients_finite_differences():
 
 
 def test_adjoint_batch_full_size_properties():
-    # the 256 x 128, L = 61 batch-of-8 adjoint workload: gradients w.r.t. b
-    # solve J^T lambda = w (checked by the oracle's transposed rows), and the
-    # structured gradients agree with the oracle's dense chain rule on
-    # sampled cells
+    # the 256 x 128, L = 61 batch-of-8 adjoint workload: lambda = dL/db solves
+    # J^T lambda = w and x solves J x = b, both checked by the oracle's rows
+    # (transposed / forward) on the sampled cells of the forward parity
+    # checks; the structured gradients agree with the oracle's dense chain
+    # rule on the same cells
     nx, ny, L, nrhs = 256, 128, 61, 8
     log("adjoint full size batch 8")
     p = gen.make_problem(nx, ny, L, seed=0)
@@ -85,16 +86,100 @@ def test_adjoint_batch_full_size_properties():
     w = gen.make_loss_weights(nx, ny, L, nrhs=nrhs, seed=0)
     params = _params(p)
     bt = vec(b).requires_grad_(True)
-    x = autograd.solve(bt, params, nx, ny, L, rtol=1e-12)
+    rtol = 1e-12
+    x = autograd.solve(bt, params, nx, ny, L, rtol=rtol)
     (x * vec(w)).sum().backward()
     lam = host(bt.grad)
     X = host(x)
-    cells = [0, 255, 256 * 64 + 17, 256 * 127, 256 * 128 - 1]
+    cells = sample_cells(nx, ny)
+    K = 5 * (L + 3) + 17  # terms of a row: the oracle's dense block rows
     rr = w[:, cells] - ops.matvec_T_rows(p, nx, ny, L, lam, cells)
-    assert np.max(np.abs(rr)) <= 1e-10 * np.max(np.abs(w))
+    bound = residual_bound(p, nx, ny, L, w, lam, rtol, K, cells, trans=True)
+    for r in range(nrhs):
+        assert np.linalg.norm(rr[r]) <= bound[r], (r, np.linalg.norm(rr[r]), bound[r])
+    rx = b[:, cells] - ops.matvec_rows(p, nx, ny, L, X, cells)
+    bound = residual_bound(p, nx, ny, L, b, X, rtol, K, cells)
+    for r in range(nrhs):
+        assert np.linalg.norm(rx[r]) <= bound[r], (r, np.linalg.norm(rx[r]), bound[r])
     # the oracle's dense-block chain rule at full size, compared on sampled cells
     g = ograds.structured_grads(p, nx, ny, L, lam, X)
     for k in FIELDS:
         gk = host(params[k].grad)
         assert relnorm(gk[cells], g[k][cells]) <= 1e-8, k
     assert relnorm(host(params["u"].grad), g["u"]) <= 1e-8
+
+
+def test_full_size_finite_differences():
+    # central differences of the batch-of-8 loss sum(w . x) at 256 x 128,
+    # L = 61, along two random directions per parameter array (b and each
+    # structured array), each supported on 16 random cells, against the
+    # directional derivative of the R1SolveFn gradients.
+    #
+    # The quotient is formed as sum(w . (x(+h) - x(-h))) / 2h: differencing
+    # the solutions before the sum keeps the float64 rounding of the
+    # 16.7-million-term loss out of it.  Error budget: the truncation error
+    # (h^2 / 6 times the third derivative of the loss along d, below 1e-12
+    # here) and the solve noise (|e+| + |e-|) / 2h, e+- the errors of
+    # w . x(+-h) for solves to rtol = 1e-14.  Their size is measured as
+    # e_x = |w . (x_a - x_b)| for two solves of the unperturbed system to the
+    # same tolerance from different starting points (zero, and a random
+    # vector of norm 1e-6 |x|); the quotient must agree with the gradient to
+    # 1e-5 of sum |g_i d_i| plus 2 e_x / h.
+    nx, ny, L, nrhs = 256, 128, 61, 8
+    log("adjoint full-size finite differences")
+    p = gen.make_problem(nx, ny, L, seed=0)
+    b = gen.make_rhs(nx, ny, L, nrhs=nrhs, seed=0)
+    wd = vec(gen.make_loss_weights(nx, ny, L, nrhs=nrhs, seed=0))
+    params = _params(p)
+    bt = vec(b).requires_grad_(True)
+    (autograd.solve(bt, params, nx, ny, L, rtol=1e-14, adj_rtol=1e-14) * wd).sum().backward()
+    grads = {k: params[k].grad.detach() for k in FIELDS}
+    grads["b"] = bt.grad.detach()
+    base = {k: params[k].detach() for k in FIELDS}
+    bd = vec(b)
+
+    def x_at(vals, bb, x0=None):
+        A = r1s.R1Matrix(nx, ny, L, vals)
+        M = r1s.SMWPreconditioner(A)
+        return r1s.gmres(A, M, bb, x0=x0, restart=50, rtol=1e-14).x
+
+    def wdot(dx):
+        return float(torch.sum(wd * dx, dtype=torch.float64))
+
+    xa = x_at(base, bd)
+    x0 = torch.randn_like(xa)
+    x0 *= 1e-6 * float(torch.linalg.norm(xa)) / float(torch.linalg.norm(x0))
+    e_x = abs(wdot(xa - x_at(base, bd, x0=xa + x0)))
+    h = 1e-6
+    rng = np.random.default_rng(7)
+    ex = gen.block_exists(nx, ny)
+    N = nx * ny
+    for k in list(FIELDS) + ["b"]:
+        shape = tuple(grads[k].shape)
+        for trial in range(2):
+            cells = rng.choice(N, size=16, replace=False)
+            d = np.zeros(shape)
+            if k == "b":
+                d[:, cells] = rng.standard_normal((nrhs, 16) + shape[2:])
+            else:
+                d[cells] = rng.standard_normal((16,) + shape[1:])
+            if k in ("u", "v"):
+                d[~ex] = 0.0
+            if k == "s_nbr":
+                for j, dd in enumerate(gen.NBR_DIRS):
+                    d[~ex[:, dd], j] = 0.0
+            d /= np.linalg.norm(d)
+            dt = vec(d)
+            if k == "b":
+                xp, xm = x_at(base, bd + h * dt), x_at(base, bd - h * dt)
+            else:
+                xp = x_at(dict(base, **{k: base[k] + h * dt}), bd)
+                xm = x_at(dict(base, **{k: base[k] - h * dt}), bd)
+            fd = wdot(xp - xm) / (2 * h)
+            gk = grads[k]
+            an = float(torch.sum(gk * dt))
+            scale = float(torch.sum(torch.abs(gk) * torch.abs(dt)))
+            tol = 1e-5 * scale + 2 * e_x / h
+            log(f"  {k} #{trial}: fd {fd:.10g} grad {an:.10g} diff {abs(fd - an):.3g} "
+                f"scale {scale:.3g} noise {2 * e_x / h:.3g} tol {tol:.3g}")
+            assert abs(fd - an) <= tol, (k, trial, fd, an, tol)
