@@ -381,6 +381,29 @@ int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
               int nrhs, const double* b, double* x, void* work,
               size_t work_bytes, r1s_gmres_stats* stats, void* stream);
 
+/* r1s_gmres for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * solve (same options, same kernels, the same iterates and result as
+ * r1s_gmres), with its workspace taken from a fixed array of
+ * R1S_NOALLOC_MAX_BYTES bytes that the library holds on every GPU it runs on
+ * until the process ends, instead of a caller-owned work buffer; and the
+ * Arnoldi coefficients of each step staged in that array and copied to the
+ * host, instead of through pinned host memory (one host wait per Arnoldi
+ * step).  Allocates no device or pinned host memory (host-side bookkeeping
+ * uses the C++ heap).  The caller still passes b and x (device [nrhs][N][m]
+ * float64).  r1s_gmres_noalloc_size reports the bytes a solve needs; a solve
+ * needing more than R1S_NOALLOC_MAX_BYTES fails with R1S_ERR_ARG before any
+ * device work (use r1s_gmres).  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other threads, other streams) race and must
+ * be serialised by the caller.  The array's contents are left over from the
+ * last call; the solve needs none of them.  Errors and stats as r1s_gmres. */
+#define R1S_NOALLOC_MAX_BYTES (64ull << 20)
+int r1s_gmres_noalloc_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
+                           size_t* bytes);
+int r1s_gmres_noalloc(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
+                      int nrhs, const double* b, double* x, r1s_gmres_stats* stats,
+                      void* stream);
+
 /* Gradients of Loss with  J x_r = b_r  given lambda_r = J^{-T} dLoss/dx_r:
  * dLoss/dS = -sum_r lambda_r x_r^T on the stored pattern,
  * dLoss/du_{c,d,p} = -sum_r lambda_r[c] (v_{c,d,p} . x_r[nb]),

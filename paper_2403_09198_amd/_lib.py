@@ -32,6 +32,7 @@ R1S_MAX_NBR = 8
 R1S_OP_STRUCTURED, R1S_OP_BSR = 0, 1
 R1S_MODE_F64, R1S_MODE_MIXED_IR = 0, 1
 R1S_ORTHO_DELAYED, R1S_ORTHO_SELECTIVE, R1S_ORTHO_CGS2 = 0, 1, 2
+R1S_NOALLOC_MAX_BYTES = 64 << 20
 
 
 INPUT_FIELDS = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v", "s_band", "s_lev_flow",
@@ -113,6 +114,9 @@ SIGNATURES = {
     "r1s_gmres_work_size": (_I, [_VP, C.POINTER(GmresOpts), _I, _PSZ]),
     "r1s_gmres": (_I, [_VP, _VP, _VP, C.POINTER(GmresOpts), _I, _VP, _VP, _VP, _SZ,
                        C.POINTER(GmresStats), _VP]),
+    "r1s_gmres_noalloc_size": (_I, [_VP, C.POINTER(GmresOpts), _I, _PSZ]),
+    "r1s_gmres_noalloc": (_I, [_VP, _VP, _VP, C.POINTER(GmresOpts), _I, _VP, _VP,
+                               C.POINTER(GmresStats), _VP]),
     "r1s_grad": (_I, [_VP, _I, _VP, _VP, C.POINTER(Grads), _VP]),
     "r1s_grad_graph": (_I, [_VP, _I, _VP, _VP, C.POINTER(GraphGrads), _VP]),
 }

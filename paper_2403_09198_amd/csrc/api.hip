@@ -1010,26 +1010,78 @@ struct SolveStat {
 // for every right-hand side ends the solve without the true residual (for
 // the inner solves of iterative refinement, whose caller forms the float64
 // residual itself).
+// Doubles of one staging slot of the Arnoldi coefficients (all right-hand
+// sides): the per-step layout of k_update_normalize or of the delayed
+// scheme's k_dcgs_small, whichever is larger.
+static size_t stage_slot_doubles(int k, int nrhs) {
+  const int HS = k + 2, SS = 2 * k + 6;
+  return (size_t)nrhs * std::max(2 * HS + 1, SS);
+}
+
+// Where the kernels stage a step's Arnoldi coefficients for the host.  With
+// dev == nullptr (r1s_gmres) they write pooled pinned host memory directly
+// and an event per slot tells the host when a slot is complete.  Otherwise
+// (r1s_gmres_noalloc) they write the two device slots dev[0], dev[1] and the
+// host copies a slot into its own memory, synchronising the stream, before
+// reading it: one host wait per step instead of none, and nothing allocated.
+struct StageDev {
+  double* dev[2];
+};
+
 static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
                       double rtol, int nrhs, const double* b, double* x, bool x0_given,
-                      int ortho, bool trust_estimate, std::vector<SolveStat>& st) {
+                      int ortho, bool trust_estimate, std::vector<SolveStat>& st,
+                      const StageDev* sd) {
   const bool always_reorth = ortho == R1S_ORTHO_CGS2;
   const bool delayed = ortho == R1S_ORTHO_DELAYED;
   hipStream_t s = c.s;
   const long long n = g.n;
   const int HS = k + 2;  // stride of the per-rhs h arrays
-  // pinned host staging: two slots of Arnoldi coefficients, then the norms
-  // and the least-squares solution of a cycle
+  // host staging: two slots of Arnoldi coefficients, then the norms and the
+  // least-squares solution of a cycle (pinned, or host copies of the device
+  // slots without a pinned pool)
   StagingLease lease;
   lease.stream = s;
   const int SS = 2 * k + 6;  // delayed scheme: staging doubles per right-hand side
-  const size_t slot_doubles = (size_t)nrhs * std::max(2 * HS + 1, SS);
+  const size_t slot_doubles = stage_slot_doubles(k, nrhs);
   const size_t y_doubles = (size_t)nrhs * (k + 1);
-  if (int e = staging_acquire((2 * slot_doubles + nrhs + y_doubles) * sizeof(double), &lease.st))
-    return e;
-  double* stage[2] = {(double*)lease.st->mem, (double*)lease.st->mem + slot_doubles};
-  double* pin_norm = (double*)lease.st->mem + 2 * slot_doubles;
-  double* pin_y = pin_norm + nrhs;
+  std::vector<double> host_slots;
+  double* stage[2];   // read by the host
+  double* kstage[2];  // written by the kernels
+  double* pin_norm = nullptr;
+  double* pin_y = nullptr;
+  if (!sd) {
+    if (int e = staging_acquire((2 * slot_doubles + nrhs + y_doubles) * sizeof(double), &lease.st))
+      return e;
+    stage[0] = kstage[0] = (double*)lease.st->mem;
+    stage[1] = kstage[1] = (double*)lease.st->mem + slot_doubles;
+    pin_norm = (double*)lease.st->mem + 2 * slot_doubles;
+    pin_y = pin_norm + nrhs;
+  } else {
+    host_slots.assign(2 * slot_doubles, 0.0);
+    stage[0] = host_slots.data();
+    stage[1] = host_slots.data() + slot_doubles;
+    kstage[0] = sd->dev[0];
+    kstage[1] = sd->dev[1];
+  }
+  // a step's kernels are queued: mark its slot; the host needs a slot: wait
+  auto mark = [&](int slot) -> int {
+    if (!sd) {
+      HIP_TRY(hipEventRecord(lease.st->ev[slot], s));
+    } else {
+      HIP_TRY(hipMemcpyAsync(stage[slot], kstage[slot], slot_doubles * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    }
+    return R1S_OK;
+  };
+  auto wait = [&](int slot) -> int {
+    if (!sd) {
+      HIP_TRY(hipEventSynchronize(lease.st->ev[slot]));
+    } else {
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    return R1S_OK;
+  };
   std::vector<double> bnorm;
   if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
   if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm)) return e;  // leaves |b|^2 in W.scal
@@ -1182,11 +1234,10 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         if (int e = prec_apply(c, W.V + (long long)j * Vb.vstride, W.z, nrhs)) return e;
         if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
         HIP_TRY(launch_dcgs_dots(Vb, j, W.w, n, n, nrhs, W.part, W.nblk, s));
-        HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, stage[j & 1], SS,
+        HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, kstage[j & 1], SS,
                                   false, nrhs, s));
         HIP_TRY(launch_dcgs_update(Vb, j, k, W.dstate, W.dstride, W.w, n, n, nrhs, s));
-        HIP_TRY(hipEventRecord(lease.st->ev[j & 1], s));
-        return R1S_OK;
+        return mark(j & 1);
       };
       auto all_stopped = [&]() {
         for (int r = 0; r < nrhs; ++r)
@@ -1197,11 +1248,11 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       for (int j = 0; j < k && !stopped; ++j) {
         if (int e = launch_step(j)) return e;
         if (j == 0) continue;
-        HIP_TRY(hipEventSynchronize(lease.st->ev[(j - 1) & 1]));
+        if (int e = wait((j - 1) & 1)) return e;
         if (j >= 2) final_col(j - 2, stage[(j - 1) & 1]);
         trial(j - 1, stage[(j - 1) & 1]);
         if (all_stopped()) {  // the final column j - 1 comes from step j
-          HIP_TRY(hipEventSynchronize(lease.st->ev[j & 1]));
+          if (int e = wait(j & 1)) return e;
           final_col(j - 1, stage[j & 1]);
           stopped = true;
         }
@@ -1209,15 +1260,15 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       if (!stopped) {
         // the cycle's last step k - 1: its final column needs one more
         // reduction on u_k (slot k), without the operator
-        HIP_TRY(hipEventSynchronize(lease.st->ev[(k - 1) & 1]));
+        if (int e = wait((k - 1) & 1)) return e;
         if (k >= 2) final_col(k - 2, stage[(k - 1) & 1]);
         trial(k - 1, stage[(k - 1) & 1]);
         const double* uk = W.V + (long long)k * Vb.vstride;
         HIP_TRY(launch_dcgs_dots(Vb, k, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
-        HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, stage[k & 1], SS,
+        HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, kstage[k & 1], SS,
                                   true, nrhs, s));
-        HIP_TRY(hipEventRecord(lease.st->ev[k & 1], s));
-        HIP_TRY(hipEventSynchronize(lease.st->ev[k & 1]));
+        if (int e = mark(k & 1)) return e;
+        if (int e = wait(k & 1)) return e;
         final_col(k - 1, stage[k & 1]);
       }
       for (int r = 0; r < nrhs; ++r)
@@ -1254,10 +1305,10 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       const int slot = j & 1;
       HIP_TRY(launch_update_normalize(Vb, nv, W.hdev, h2, nv + 1, fused ? W.need : nullptr, W.w,
                                       n, W.V + (long long)(j + 1) * Vb.vstride, n, nrhs, s,
-                                      stage[slot]));
-      HIP_TRY(hipEventRecord(lease.st->ev[slot], s));
+                                      kstage[slot]));
+      if (int e = mark(slot)) return e;
       if (pending >= 0) {
-        HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));
+        if (int e = wait(pending & 1)) return e;
         const bool all_done = process(pending);
         pending = -1;
         if (all_done) {
@@ -1268,7 +1319,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       pending = j;
     }
     if (!finished && pending >= 0) {  // (not reached in the delayed scheme)
-      HIP_TRY(hipEventSynchronize(lease.st->ev[pending & 1]));
+      if (int e = wait(pending & 1)) return e;
       process(pending);
     }
     // y = R^{-1} g per rhs; x += M (V y)
@@ -1284,9 +1335,11 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       if (!st[r].converged) est[r] = fabs(gr[je]);  // |g_je| after the rotations
     }
-    // (the next cycle's norms synchronise before pin_y is written again)
-    std::copy(y.begin(), y.end(), pin_y);
-    HIP_TRY(hipMemcpyAsync(W.ydev, pin_y, y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    // (the next cycle's norms synchronise before pin_y is written again; a
+    // copy from pageable memory has taken the data when it returns)
+    if (pin_y) std::copy(y.begin(), y.end(), pin_y);
+    HIP_TRY(hipMemcpyAsync(W.ydev, pin_y ? pin_y : y.data(), y.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, jend[r]);
     HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
@@ -1296,9 +1349,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   return R1S_OK;
 }
 
-extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts, int nrhs,
-                         const double* b, double* x, void* work, size_t work_bytes,
-                         r1s_gmres_stats* stats, void* stream) {
+// Argument checks shared by r1s_gmres and r1s_gmres_noalloc.
+static int gmres_check(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts, int nrhs,
+                       const double* b, const double* x) {
   if (!A || !M) return fail(R1S_ERR_ARG, "matrix or preconditioner handle is NULL");
   if (int e = check_opts(opts)) return e;
   if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
@@ -1321,32 +1374,34 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
   const bool mixed = opts->mode == R1S_MODE_MIXED_IR;
   if (mixed && (!A->rec32 || M->kind != PREC_SMW || !smw_has_f32(M)))
     return fail(R1S_ERR_ARG, "mixed mode needs R1S_KEEP_F32 on the matrix and the preconditioner");
-  if (!work || !aligned(work, 256)) return fail(R1S_ERR_ARG, "work is NULL or not 256-byte aligned");
-  size_t need;
-  if (int e = r1s_gmres_work_size(A, opts, nrhs, &need)) return e;
-  if (work_bytes < need) return fail(R1S_ERR_ARG, "work_bytes %zu < required %zu", work_bytes, need);
+  return R1S_OK;
+}
 
+// The solve itself (arguments checked, W carved from the workspace).
+static int gmres_run(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts, int nrhs,
+                     const double* b, double* x, GmresWork& W, const StageDev* sd,
+                     r1s_gmres_stats* stats, hipStream_t s) {
   const Mesh& g = A->g;
-  GmresWork W;
-  Carver cv(work);
-  gmres_layout(cv, g, opts->restart, nrhs, mixed, &W);
-  hipStream_t s = as_stream(stream);
+  const bool mixed = opts->mode == R1S_MODE_MIXED_IR;
   OpCtx c{A, B, M, false, opts->trans != 0, opts->op == R1S_OP_BSR, s};
   std::vector<SolveStat> st;
   int outer = 0;
   int rc;
   if (!mixed) {
     rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
-                    opts->x0_given != 0, opts->ortho, false, st);
+                    opts->x0_given != 0, opts->ortho, false, st, sd);
     if (rc) return rc;
   } else {
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
     // (from x = 0 the first residual is b, and the first correction is x)
     std::vector<double> bnorm, rn;
-    StagingLease nlease;  // pinned landing buffer of the outer norms
+    StagingLease nlease;  // pinned landing buffer of the outer norms (r1s_gmres)
     nlease.stream = s;
-    if (int e = staging_acquire((size_t)nrhs * sizeof(double), &nlease.st)) return e;
-    double* pin_norm = (double*)nlease.st->mem;
+    double* pin_norm = nullptr;
+    if (!sd) {
+      if (int e = staging_acquire((size_t)nrhs * sizeof(double), &nlease.st)) return e;
+      pin_norm = (double*)nlease.st->mem;
+    }
     if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm)) return e;
     const bool zero_start = !opts->x0_given;
     OpCtx ci = c;
@@ -1373,7 +1428,7 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
       }
       std::vector<SolveStat> in;
       rc = gmres_core(ci, g, W, opts->restart, opts->max_cycles, opts->inner_rtol, nrhs,
-                      first ? b : W.r64, first ? x : W.d, false, opts->ortho, true, in);
+                      first ? b : W.r64, first ? x : W.d, false, opts->ortho, true, in, sd);
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r) {
         tot[r].iters += in[r].iters;
@@ -1397,6 +1452,88 @@ extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts*
   }
   if (!ok) return fail(R1S_ERR_NOCONV, "GMRES did not reach rtol %g", opts->rtol);
   return R1S_OK;
+}
+
+extern "C" int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts, int nrhs,
+                         const double* b, double* x, void* work, size_t work_bytes,
+                         r1s_gmres_stats* stats, void* stream) {
+  if (int e = gmres_check(A, B, M, opts, nrhs, b, x)) return e;
+  if (!work || !aligned(work, 256)) return fail(R1S_ERR_ARG, "work is NULL or not 256-byte aligned");
+  size_t need;
+  if (int e = r1s_gmres_work_size(A, opts, nrhs, &need)) return e;
+  if (work_bytes < need) return fail(R1S_ERR_ARG, "work_bytes %zu < required %zu", work_bytes, need);
+  GmresWork W;
+  Carver cv(work);
+  gmres_layout(cv, A->g, opts->restart, nrhs, opts->mode == R1S_MODE_MIXED_IR, &W);
+  return gmres_run(A, B, M, opts, nrhs, b, x, W, nullptr, stats, as_stream(stream));
+}
+
+// ------------------------------------------------- GMRES without allocation --
+// The workspace of r1s_gmres_noalloc: one array per GPU for the life of the
+// process.  Host code never passes its name to a kernel or a copy (in host
+// code it is a stand-in, not a device address): scratch_ptr() gives each
+// device's own copy, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[R1S_NOALLOC_MAX_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[64];  // per device id, set on first use
+
+static int scratch_ptr(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(R1S_ERR_UNSUPPORTED, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(R1S_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return R1S_OK;
+}
+
+// Bytes of the static workspace a solve takes: r1s_gmres's workspace and the
+// two device staging slots.
+static int noalloc_bytes(r1s_mat A, const r1s_gmres_opts* opts, int nrhs, size_t* bytes) {
+  size_t need;
+  if (int e = r1s_gmres_work_size(A, opts, nrhs, &need)) return e;
+  const size_t slot = (stage_slot_doubles(opts->restart, nrhs) * sizeof(double) + 255) & ~(size_t)255;
+  *bytes = ((need + 255) & ~(size_t)255) + 2 * slot;
+  return R1S_OK;
+}
+
+extern "C" int r1s_gmres_noalloc_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
+                                      size_t* bytes) {
+  if (!A || !bytes) return fail(R1S_ERR_ARG, "NULL argument");
+  if (int e = check_opts(opts)) return e;
+  if (nrhs < 1) return fail(R1S_ERR_ARG, "nrhs must be >= 1");
+  return noalloc_bytes(A, opts, nrhs, bytes);
+}
+
+extern "C" int r1s_gmres_noalloc(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
+                                 int nrhs, const double* b, double* x, r1s_gmres_stats* stats,
+                                 void* stream) {
+  if (int e = gmres_check(A, B, M, opts, nrhs, b, x)) return e;
+  size_t need;
+  if (int e = noalloc_bytes(A, opts, nrhs, &need)) return e;
+  if (need > (size_t)R1S_NOALLOC_MAX_BYTES)
+    return fail(R1S_ERR_ARG,
+                "the solve needs %zu bytes of workspace, more than the %llu of r1s_gmres_noalloc "
+                "(use r1s_gmres with a caller-owned workspace)",
+                need, (unsigned long long)R1S_NOALLOC_MAX_BYTES);
+  void* base = nullptr;
+  if (int e = scratch_ptr(&base)) return e;
+  GmresWork W;
+  Carver cv(base);
+  gmres_layout(cv, A->g, opts->restart, nrhs, opts->mode == R1S_MODE_MIXED_IR, &W);
+  const size_t slot = stage_slot_doubles(opts->restart, nrhs);
+  StageDev sd;
+  sd.dev[0] = cv.take<double>(slot);
+  sd.dev[1] = cv.take<double>(slot);
+  return gmres_run(A, B, M, opts, nrhs, b, x, W, &sd, stats, as_stream(stream));
 }
 
 // ------------------------------------------------------------ gradients ---

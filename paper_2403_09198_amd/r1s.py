@@ -252,6 +252,19 @@ def r1s_gmres(h, bh, p, opts, nrhs, b, x, work, stream=None):
     return rc, [{k: getattr(s, k) for k, _ in L.GmresStats._fields_} for s in stats]
 
 
+def r1s_gmres_noalloc_size(h, opts: "L.GmresOpts", nrhs) -> int:
+    b = C.c_size_t()
+    check(lib().r1s_gmres_noalloc_size(h, C.byref(opts), nrhs, C.byref(b)))
+    return b.value
+
+
+def r1s_gmres_noalloc(h, bh, p, opts, nrhs, b, x, stream=None):
+    stats = (L.GmresStats * nrhs)()
+    rc = lib().r1s_gmres_noalloc(h, bh, p, C.byref(opts), nrhs, _ptr(b), _ptr(x), stats,
+                                 _stream(stream))
+    return rc, [{k: getattr(s, k) for k, _ in L.GmresStats._fields_} for s in stats]
+
+
 def r1s_grad(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
     g = L.Grads()
     for k in out:
@@ -441,10 +454,12 @@ class GmresResult:
 def gmres(A: R1Matrix, M, b, x0=None, restart=50, rtol=1e-10, max_cycles=200, trans=False,
           op="structured", B: Optional[BSRMatrix] = None, mode="f64", inner_rtol=1e-5,
           max_outer=10, ortho="delayed", raise_on_noconv=True, work=None,
-          stream=None) -> GmresResult:
+          noalloc=False, stream=None) -> GmresResult:
     """Restarted right-preconditioned GMRES through r1s_gmres.  ortho: the
     Gram-Schmidt second pass, "delayed" (merged with the next step's first:
-    one reduction per step), "selective" or "cgs2" (every step)."""
+    one reduction per step), "selective" or "cgs2" (every step).
+    noalloc: solve through r1s_gmres_noalloc (the library's fixed workspace;
+    no work buffer is allocated)."""
     orthos = {"selective": L.R1S_ORTHO_SELECTIVE, "cgs2": L.R1S_ORTHO_CGS2,
               "delayed": L.R1S_ORTHO_DELAYED}
     if ortho not in orthos:
@@ -457,11 +472,14 @@ def gmres(A: R1Matrix, M, b, x0=None, restart=50, rtol=1e-10, max_cycles=200, tr
                        inner_rtol=inner_rtol, max_outer=max_outer,
                        ortho=orthos[ortho])
     x = torch.empty_like(b) if x0 is None else x0.clone()
-    need = r1s_gmres_work_size(A.h, opts, nrhs)
-    if work is None or work.numel() < need:
-        work = _buffer(need, A.device)
-    rc, stats = r1s_gmres(A.h, B.h if B is not None else C.c_void_p(0), M.h, opts, nrhs, b, x,
-                          work, stream)
+    bh = B.h if B is not None else C.c_void_p(0)
+    if noalloc:
+        rc, stats = r1s_gmres_noalloc(A.h, bh, M.h, opts, nrhs, b, x, stream)
+    else:
+        need = r1s_gmres_work_size(A.h, opts, nrhs)
+        if work is None or work.numel() < need:
+            work = _buffer(need, A.device)
+        rc, stats = r1s_gmres(A.h, bh, M.h, opts, nrhs, b, x, work, stream)
     if rc != L.R1S_OK and (raise_on_noconv or rc != L.R1S_ERR_NOCONV):
         raise R1SError(rc, r1s_last_error())
     return GmresResult(x, stats, rc)

@@ -200,3 +200,14 @@ def test_general_mesh_size_matches_structured_record():
     b = C.c_size_t()
     assert L.lib().r1s_mat_size(4, 3, 4, _lay(1, 1), 0, C.byref(b)) == L.R1S_OK
     assert gb > b.value and gb - b.value <= 3 * 256 + 4 * (2 * 12 * 4 + 12)
+
+
+def test_noalloc_gmres_rejects_null_handles():
+    lib = L.lib()
+    b = C.c_size_t()
+    opts = L.GmresOpts(restart=10, max_cycles=5, rtol=1e-8)
+    assert lib.r1s_gmres_noalloc_size(None, C.byref(opts), 1, C.byref(b)) == L.R1S_ERR_ARG
+    st = (L.GmresStats * 1)()
+    assert lib.r1s_gmres_noalloc(None, None, None, C.byref(opts), 1, None, None, st,
+                                 None) == L.R1S_ERR_ARG
+    assert "NULL" in lib.r1s_last_error().decode()
