@@ -88,14 +88,6 @@ static int check_layout(const r1s_layout& lay) {
   return R1S_OK;
 }
 
-// Output vectors above this size are stored non-temporally (st_out): at
-// 512 x 256, L = 200 (213 MB vectors) the pair gains 5-6%; at 256 x 128,
-// L = 61 (17 MB) the SMW apply reads the matvec's output from the Infinity
-// Cache instead (21.5 us against 23.5 us).
-#ifndef R1S_NT_MIN_BYTES
-#define R1S_NT_MIN_BYTES (64LL << 20)
-#endif
-
 // nbmax: neighbour slots per cell record (4 on the structured mesh; the
 // largest number of off-diagonal blocks of a block row on a general mesh).
 static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay, bool graph = false,
@@ -113,7 +105,6 @@ static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay, bool graph =
   g.fa = g.fb + 2 * (g.band - 1);
   g.fu = g.fa + 6 * g.arrow;
   g.F = g.fu + 2 * g.P;
-  g.ntst = g.n * (long long)sizeof(double) > R1S_NT_MIN_BYTES;
   return g;
 }
 

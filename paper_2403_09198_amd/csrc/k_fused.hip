@@ -118,7 +118,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_prec(Mesh g_, const TV* __r
     for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) t += uv[d][p] * acc[d][p];
   }
   const double yv = (double)t;
-  st_out(y + (long long)c * m + kk, yv, g.ntst);  // lanes past m repeat lane m-1's value
+  st_out(y + (long long)c * m + kk, yv);  // lanes past m repeat lane m-1's value
 
   // z_c = x0 - W C^{-1} (V^T x0), x0 = A0^{-1} y_c
   if constexpr (!EARLY) load_factors();
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_prec(Mesh g_, const TV* __r
   TV o = X0[0];
 #pragma unroll
   for (int i = 0; i < RDM; ++i) o -= zc[i] * W[i];
-  if (lane < m) st_out(z + (long long)c * m + lane, (double)o, g.ntst);
+  if (lane < m) st_out(z + (long long)c * m + lane, (double)o);
 }
 
 // Where the single kernel is used: the layouts it covers, and among them

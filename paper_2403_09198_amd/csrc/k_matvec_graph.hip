@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_graph(Mesh g, const TV* __r
       }
     }
     const long long o = (long long)r * g.n + (long long)c * m + kk;
-    st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
+    st_out(y + o, RESID ? b[o] - (double)t : (double)t);
   }
 }
 
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_graph1(Mesh g, const TV* __
     }
   }
   const long long o = (long long)r * g.n + (long long)c * m + kk;
-  st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
+  st_out(y + o, RESID ? b[o] - (double)t : (double)t);
 }
 
 template <typename TV, bool TRANS, bool RESID, int NBM>

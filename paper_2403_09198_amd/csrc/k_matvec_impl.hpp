@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         }
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-      st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
+      st_out(y + o, RESID ? b[o] - (double)t : (double)t);
     }
   }
 }
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
       }
     }
     const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
-    st_out(y + o, RESID ? b[o] - (double)t : (double)t, g.ntst);
+    st_out(y + o, RESID ? b[o] - (double)t : (double)t);
   }
 }
 

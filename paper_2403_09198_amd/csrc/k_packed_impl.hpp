@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64 * NW) void k_matvec_pk(Mesh g_, const TV* __rest
   }
   if (act) {
     const long long o = (long long)r0 * g.n + (long long)c * m + k;
-    st_out(y + o, RESID ? b[o] - (double)r : (double)r, g.ntst);
+    st_out(y + o, RESID ? b[o] - (double)r : (double)r);
   }
 }
 
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64 * NW) void k_smw_apply_pk(Mesh g, const TV* __re
   __syncthreads();
   const TV sc = pk_cell_sum<TV, NS>(ss, qq, m);
   const TV o = X0 - (sc * ic) * W;
-  if (act) st_out(zout + (long long)r0 * g.n + (long long)c * m + k, (double)o, g.ntst);
+  if (act) st_out(zout + (long long)r0 * g.n + (long long)c * m + k, (double)o);
 }
 
 }  // namespace r1s

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
           TV o = X0[ch];
 #pragma unroll
           for (int i = 0; i < RDM; ++i) o -= z[i] * W[j][i][ch];
-          if (k < m) st_out(zv + k, (double)o, g.ntst);
+          if (k < m) st_out(zv + k, (double)o);
         }
       }
     }
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
     TV o = X0[r];
 #pragma unroll
     for (int i = 0; i < RDM; ++i) o -= z[i] * W[i];
-    if (k < m) st_out(zout + (long long)(r0 + r) * g.n + (long long)c * m + k, (double)o, g.ntst);
+    if (k < m) st_out(zout + (long long)(r0 + r) * g.n + (long long)c * m + k, (double)o);
   }
 }
 

@@ -76,9 +76,6 @@ struct Mesh {
   // slot of this cell in the neighbour's list; offb [N] = first off-diagonal
   // block of each cell in input order
   int graph, nbmax;
-  // output vectors written with non-temporal stores (vectors larger than
-  // the Infinity Cache share they could stay in; see st_out)
-  int ntst;
   const int* nbr;
   const int* tslot;
   const int* offb;
@@ -181,20 +178,17 @@ __device__ inline T ld_stream(const T* p) {
 #endif
 }
 
-// Store of a kernel's output vector.  Large outputs (Mesh::ntst) are
-// written non-temporally: an output written back through the caches as
-// ordinary lines competes with the streamed matrix reads for HBM turnarounds
-// (measured on MI355X: a streaming read with 1/16 as many bytes written
-// drops from 7.37 TB/s to 5.78 with ordinary stores and to 5.94 with
-// non-temporal ones).  Small outputs are written normally, so that the next
-// kernel (the SMW apply after the matvec) finds them in the 256 MB Infinity
-// Cache.
-__device__ inline void st_out(double* p, double v, int nt) {
-  if (nt)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-}
+// Store of a kernel's output vector, non-temporal: an output written back
+// through the caches as ordinary lines competes with the streamed matrix
+// reads for HBM turnarounds.  Measured on MI355X: a streaming read with 1/16
+// as many bytes written drops from 7.37 TB/s to 5.78 with ordinary stores
+// and to 5.94 with non-temporal ones; the 512 x 256, L = 200 matvec + SMW
+// apply pair takes 934-942 us against 1053 us with ordinary stores.  Even
+// where the next kernel reads the output back (the apply after the matvec)
+// and an ordinary store would leave it in the Infinity Cache, non-temporal
+// stores measured faster (256 x 128, L = 61: 75.6-76.5 us against
+// 77.3-79.1 us per pair).
+__device__ inline void st_out(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 // Neighbour cells of c in the order S, W, C, E, N (-1 where no block).
 __device__ inline void neighbours(const Mesh& g, int c, int nb[5]) {

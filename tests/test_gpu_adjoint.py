@@ -118,9 +118,9 @@ def test_full_size_finite_differences():
     # The quotient is formed as sum(w . (x(+h) - x(-h))) / 2h: differencing
     # the solutions before the sum keeps the float64 rounding of the
     # 16.7-million-term loss out of it.  Error budget: the truncation error
-    # (h^2 / 6 times the third derivative of the loss along d, below 1e-12
-    # here) and the solve noise (|e+| + |e-|) / 2h, e+- the errors of
-    # w . x(+-h) for solves to rtol = 1e-14.  Their size is measured as
+    # (h^2 / 6 = 1.7e-13 times the third derivative of the loss along d) and
+    # the solve noise (|e+| + |e-|) / 2h, e+- the errors of w . x(+-h) for
+    # solves to rtol = 1e-14.  Their size is measured as
     # e_x = |w . (x_a - x_b)| for two solves of the unperturbed system to the
     # same tolerance from different starting points (zero, and a random
     # vector of norm 1e-6 |x|); the quotient must agree with the gradient to
