@@ -11,8 +11,14 @@ with 0 < |k - k'| <= band (band = 1: tridiagonal; section 4, "Temporal Source
 Jacobian": level-changing processes up to a threshold jump give a banded
 pattern), a dense 3 x 3 corner for the flow unknowns L, L+1, L+2 and, with
 the arrow option, dense coupling between the level rows and the flow columns
-and between the flow rows and the level columns.  S_{c,d} for d != C is
-diagonal.
+and between the flow rows and the level columns.  With arrow = 2 the last
+level a = L - 1 is the atom density (the DRa processes of the same passage:
+each molecule level's row depends on its own density, the atom density and
+the temperature, and the atom's row on every level): a dense atom column
+S[k][a] and atom row S[a][k] over the molecule levels k < a are added to the
+block (the generator draws the band entries that reach the atom as zero, so
+every entry has one source; the block is the sum of its parts).  S_{c,d} for
+d != C is diagonal.
 
 The result is stored in the paper's BSR format (section 5.1): block_indptr,
 block_indices (ascending block columns within a block row) and a 3-D data
@@ -45,6 +51,10 @@ def diagonal_sparse_block(p, c: int, L: int) -> np.ndarray:
         for i in range(3):
             A[:L, L + i] = p["s_lev_flow"][c, i]
             A[L + i, :L] = p["s_flow_lev"][c, i]
+    if arrow == 2:
+        a = L - 1
+        A[:a, a] += p["s_lev_flow"][c, 3, :a]
+        A[a, :a] += p["s_flow_lev"][c, 3, :a]
     return A
 
 

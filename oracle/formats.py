@@ -147,6 +147,19 @@ def br1_matvec(br1, x, column_size, row_size, y=None):
 
 
 # ------------------------------------------ structured Jacobian, both parts --
+def _add_atom(row, p, c, k, L, base):
+    """Level row k of cell c gains the atom's column (k < a) or, for the
+    atom a = L - 1 itself, its row over the molecule levels (arrow = 2: the
+    DRa couplings of section 4, "Temporal Source Jacobian"), added to what
+    the band already put there."""
+    a = L - 1
+    if k < a:
+        row[base + a] = row.get(base + a, 0.0) + p["s_lev_flow"][c, 3, k]
+    else:
+        for kk in range(a):
+            row[base + kk] = row.get(base + kk, 0.0) + p["s_flow_lev"][c, 3, kk]
+
+
 def structured_csr(p, nx, ny, L):
     """CSR of the fully sparse part S (section 4, Fig. 7(b)), built from the
     per-cell pattern directly (no dense block is formed)."""
@@ -177,6 +190,8 @@ def structured_csr(p, nx, ny, L):
                 if arrow:
                     for i in range(3):
                         row[c * m + L + i] = p["s_lev_flow"][c, i, k]
+                if arrow == 2:
+                    _add_atom(row, p, c, k, L, c * m)
             elif arrow:
                 for kk in range(L):
                     row[c * m + kk] = p["s_flow_lev"][c, k - L, kk]
@@ -250,6 +265,8 @@ def graph_csr(p, L):
                 if arrow:
                     for i in range(3):
                         row[c * m + L + i] = p["s_lev_flow"][c, i, k]
+                if arrow == 2:
+                    _add_atom(row, p, c, k, L, c * m)
             else:
                 i = k - L
                 for t, (a, b) in enumerate(assemble.FLOW_PAIRS):

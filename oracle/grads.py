@@ -59,6 +59,9 @@ def structured_grads(p, nx, ny, L, lam, x):
                     for i in range(3):
                         g["s_lev_flow"][c, i] = G[:L, L + i]
                         g["s_flow_lev"][c, i] = G[L + i, :L]
+                if arrow == 2:
+                    g["s_lev_flow"][c, 3, :L - 1] = G[:L - 1, L - 1]
+                    g["s_flow_lev"][c, 3, :L - 1] = G[L - 1, :L - 1]
             else:
                 g["s_nbr"][c, mesh.NBR_SLOT[d]] = np.diag(G)
     return g

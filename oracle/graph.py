@@ -138,6 +138,9 @@ def grads(p, L, lam, x):
                     for i in range(3):
                         g["s_lev_flow"][c, i] = G[:L, L + i]
                         g["s_flow_lev"][c, i] = G[L + i, :L]
+                if arrow == 2:
+                    g["s_lev_flow"][c, 3, :L - 1] = G[:L - 1, L - 1]
+                    g["s_flow_lev"][c, 3, :L - 1] = G[L - 1, :L - 1]
             else:
                 for q in range(p["u_off"].shape[1]):
                     g["u_off"][o, q] = G @ p["v_off"][o, q]
@@ -154,7 +157,7 @@ def structured_values(p, L):
     n_off = len(p["graph_indices"]) - N
     m = L + 3
     band, arrow = mesh.pattern(p)
-    diag_block_vals = m + sum(2 * max(L - j, 0) for j in range(1, band + 1)) + 6 + (6 * L if arrow else 0)
+    diag_block_vals = m + sum(2 * max(L - j, 0) for j in range(1, band + 1)) + 6 + (6 * L if arrow else 0) + (2 * max(L - 1 - band, 0) if arrow == 2 else 0)
     rd, ro = p["u_diag"].shape[1], p["u_off"].shape[1]
     return N * diag_block_vals + n_off * m + 2 * m * (N * rd + n_off * ro)
 

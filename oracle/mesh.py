@@ -64,7 +64,9 @@ def pattern(p):
     """(band, arrow) of the diagonal sparse block: level diagonals up to
     |k - k'| <= band, and whether level rows and flow rows are coupled (the
     temperature dependence of the level sources, section 4, "Temporal Source
-    Jacobian").  Default (1, 0): tridiagonal band, no coupling."""
+    Jacobian"; arrow = 2 adds the atom density, the last level, coupled to
+    every level by the DRa processes).  Default (1, 0): tridiagonal band, no
+    coupling."""
     if "pattern" not in p:
         return 1, 0
     band, arrow = (int(v) for v in p["pattern"])

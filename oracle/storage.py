@@ -27,14 +27,19 @@ def bsr_values(nx: int, ny: int, m: int) -> int:
 
 
 def structured_values(nx: int, ny: int, m: int, r_diag: int = 1, r_off: int = 1,
-                      band: int = 1, arrow: bool = False) -> int:
+                      band: int = 1, arrow: int = 0) -> int:
     """r_diag pairs on every diagonal block, r_off on every neighbour block;
     the diagonal block's level band has half-width `band` (2 (L - j) entries
-    on the j-th diagonals) and `arrow` adds 6 L level/flow couplings."""
+    on the j-th diagonals), `arrow` adds 6 L level/flow couplings and
+    arrow = 2 the atom's column and row over the molecule levels, of which
+    the band already holds the 2 min(band, L - 1) positions next to the
+    atom: 2 (L - 1 - band) more entries."""
     N = nx * ny
     B = n_blocks(nx, ny)
     L = m - 3
     diag_block = m + sum(2 * max(L - j, 0) for j in range(1, band + 1)) + 6
     if arrow:
         diag_block += 6 * L
+    if arrow == 2:
+        diag_block += 2 * max(L - 1 - band, 0)
     return N * diag_block + (B - N) * m + (N * r_diag + (B - N) * r_off) * 2 * m

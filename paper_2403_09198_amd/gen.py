@@ -32,6 +32,11 @@ Optional, for a wider sparse diagonal block (band > 1 and/or arrow):
                                 to the flow unknowns (temperature dependence)
   s_flow_lev [N][3][L]          S_cc[L+i][k] at [c][i][k]: flow rows coupled
                                 to the levels
+  With arrow = 2 the last level a = L-1 is the atom density (DRa processes,
+  section 4, "Temporal Source Jacobian") and both arrays are [N][4][L]:
+  slot 3 holds the atom column S_cc[k][a] (s_lev_flow) and the atom row
+  S_cc[a][k] (s_flow_lev) at index k < a; index a of slot 3 is unused (zero)
+  and the level-band entries that reach the atom are drawn as zero.
 
 Directions: 0 = S (iy-1), 1 = W (ix-1), 2 = C, 3 = E (ix+1), 4 = N (iy+1).
 The paper's structure (section 4, "Overall Structure") has r_diag = 9 (one
@@ -44,7 +49,8 @@ Value distributions (one fixed draw order from numpy's PCG64):
   s_diag = inv_dt + 10*|N(0,1)|, s_sub, s_sup, s_flow ~ N(0,1),
   s_nbr ~ U(-1,0), u, v ~ N(0, 0.1^2), then (only when requested) s_band ~
   N(0,1), s_lev_flow ~ N(0, 0.1^2), s_flow_lev ~ N(0,1)/L (row sums of the
-  flow rows stay O(1) at any L).  Right-hand sides from seed+1, loss
+  flow rows stay O(1) at any L), for arrow = 2 then the atom column
+  ~ N(0, 0.1^2) and the atom row ~ N(0,1)/L.  Right-hand sides from seed+1, loss
   weights from seed+2, both N(0,1).  inv_dt = 20 makes S strictly row
   diagonally dominant with overwhelming probability; inv_dt = 1 is a stress
   case that forces GMRES restarts.
@@ -122,9 +128,44 @@ def pair_slots(r_diag: int = 1, r_off: int = 1):
     return [(int(a), int(b)) for a, b in zip(starts, counts)]
 
 
+def _check_arrow(L: int, arrow: int) -> None:
+    if arrow not in (0, 1, 2):
+        raise ValueError("arrow must be 0, 1 or 2")
+    if arrow == 2 and L < 2:
+        raise ValueError("arrow = 2 needs L >= 2 (the atom plus a molecule level)")
+
+
+def _draw_arrow(p, rng, N: int, L: int, band: int, arrow: int) -> None:
+    """Level/flow coupling arrays (zero without arrow); arrow = 2 draws the
+    atom slot after the three flow slots and clears what the atom replaces."""
+    if not arrow:
+        p["s_lev_flow"] = np.zeros((N, 3, L))
+        p["s_flow_lev"] = np.zeros((N, 3, L))
+        return
+    p["s_lev_flow"] = 0.1 * rng.standard_normal((N, 3, L))
+    p["s_flow_lev"] = rng.standard_normal((N, 3, L)) / L
+    if arrow == 2:
+        a = L - 1
+        col = 0.1 * rng.standard_normal((N, 1, L))
+        row = rng.standard_normal((N, 1, L)) / L
+        col[:, 0, a] = 0.0
+        row[:, 0, a] = 0.0
+        p["s_lev_flow"] = np.concatenate([p["s_lev_flow"], col], axis=1)
+        p["s_flow_lev"] = np.concatenate([p["s_flow_lev"], row], axis=1)
+        # the atom is not a vibrational level: no band entries reach it
+        if L >= 2:
+            p["s_sub"][:, a - 1] = 0.0
+            p["s_sup"][:, a - 1] = 0.0
+        nb = band - 1
+        for j in range(2, band + 1):
+            if a - j >= 0:
+                p["s_band"][:, j - 2, a] = 0.0        # S[a][a-j]
+                p["s_band"][:, nb + j - 2, a - j] = 0.0  # S[a-j][a]
+
+
 def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
                  r_diag: int = 1, r_off: int = 1, band: int = 1,
-                 arrow: bool = False) -> Dict[str, np.ndarray]:
+                 arrow: int = 0) -> Dict[str, np.ndarray]:
     """Draw the structured values of one Jacobian (float64 arrays).  The
     returned dict also holds "ranks" = [r_diag, r_off] and, for a wider
     diagonal block, "pattern" = [band, arrow] with the PATTERN_FIELDS."""
@@ -134,6 +175,7 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
         raise ValueError("need r_diag >= 1 and r_off >= 0")
     if band < 1:
         raise ValueError("need band >= 1")
+    _check_arrow(L, arrow)
     N, m = nx * ny, L + 3
     P = r_diag + 4 * r_off
     rng = np.random.default_rng(seed)
@@ -159,17 +201,12 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, inv_dt: float = 20.0,
         for j in range(2, band + 1):
             p["s_band"][:, j - 2, k < j] = 0.0             # S[k][k-j] needs k >= j
             p["s_band"][:, nb + j - 2, k + j > L - 1] = 0.0  # S[k][k+j] needs k+j < L
-        if arrow:
-            p["s_lev_flow"] = 0.1 * rng.standard_normal((N, 3, L))
-            p["s_flow_lev"] = rng.standard_normal((N, 3, L)) / L
-        else:
-            p["s_lev_flow"] = np.zeros((N, 3, L))
-            p["s_flow_lev"] = np.zeros((N, 3, L))
+        _draw_arrow(p, rng, N, L, band, arrow)
     for k in FIELDS + (PATTERN_FIELDS if wide else ()):
         p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
     p["ranks"] = np.array([r_diag, r_off])
     if wide:
-        p["pattern"] = np.array([band, int(bool(arrow))])
+        p["pattern"] = np.array([band, int(arrow)])
     return p
 
 
@@ -263,12 +300,13 @@ def graph_off_blocks(indptr, indices):
 
 def make_graph_problem(indptr, indices, L: int, seed: int = 0, inv_dt: float = 20.0,
                        r_diag: int = 1, r_off: int = 1, band: int = 1,
-                       arrow: bool = False) -> Dict[str, np.ndarray]:
+                       arrow: int = 0) -> Dict[str, np.ndarray]:
     """Structured values on a general mesh, same distributions as
     make_problem: per cell the diagonal block (s_diag, s_sub, s_sup, s_flow,
     optional s_band / s_lev_flow / s_flow_lev, r_diag pairs u_diag, v_diag
     [N][r_diag][m]); per off-diagonal block its diagonal s_nbr [n_off][m]
     and r_off pairs u_off, v_off [n_off][r_off][m]."""
+    _check_arrow(L, arrow)
     N, m = len(indptr) - 1, L + 3
     n_off = len(indices) - N
     rng = np.random.default_rng(seed)
@@ -291,13 +329,8 @@ def make_graph_problem(indptr, indices, L: int, seed: int = 0, inv_dt: float = 2
         for j in range(2, band + 1):
             p["s_band"][:, j - 2, k < j] = 0.0
             p["s_band"][:, nb + j - 2, k + j > L - 1] = 0.0
-        if arrow:
-            p["s_lev_flow"] = 0.1 * rng.standard_normal((N, 3, L))
-            p["s_flow_lev"] = rng.standard_normal((N, 3, L)) / L
-        else:
-            p["s_lev_flow"] = np.zeros((N, 3, L))
-            p["s_flow_lev"] = np.zeros((N, 3, L))
-        p["pattern"] = np.array([band, int(bool(arrow))])
+        _draw_arrow(p, rng, N, L, band, arrow)
+        p["pattern"] = np.array([band, int(arrow)])
     for k in GRAPH_FIELDS + (PATTERN_FIELDS if wide else ()):
         p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
     p["ranks"] = np.array([r_diag, r_off])

@@ -199,6 +199,57 @@ def grad_sound_speed(q, L, g):
     return da2 / (2.0 * a[..., None])
 
 
+# ------------------------------------------------- DRa source (optional) ----
+# Dissociation and recombination of the molecule levels by atom impact
+# (section 4, "Temporal Source Jacobian": each level's rate depends on its own
+# density, the atom density and the temperature; the atom's on every level).
+# Toy Arrhenius-like rates, level v = 0..L-2, atom a = L-1:
+#   Omega_v = -kd_v(T) rho_v rho_a + kr_v(T) rho_a^3,   Omega_a = -sum_v Omega_v
+#   kd_v = DRA_KD exp(-theta_v / T), theta_v = DRA_THETA (1 - v / (L-1)),
+#   kr_v = DRA_KR exp(-0.1 v) / T.
+DRA_KD, DRA_THETA, DRA_KR = 20.0, 3.0, 200.0
+
+
+def dra_rates(T, L):
+    """kd, kr [..., L-1] and their T-derivatives at temperatures T [...]."""
+    v = np.arange(L - 1)
+    theta = DRA_THETA * (1.0 - v / (L - 1))
+    T_ = np.asarray(T)[..., None]
+    kd = DRA_KD * np.exp(-theta / T_)
+    kr = DRA_KR * np.exp(-0.1 * v) / T_
+    return kd, kr, kd * theta / (T_ * T_), -kr / T_
+
+
+def dra_source(q, L):
+    """Omega [..., m] (zero in the flow rows: the source moves mass between
+    species and leaves momentum and total energy unchanged)."""
+    rk, T = q[..., :L], q[..., L + 2]
+    kd, kr, _, _ = dra_rates(T, L)
+    ra = rk[..., L - 1:L]
+    om = np.zeros(np.shape(q))
+    om[..., :L - 1] = -kd * rk[..., :L - 1] * ra + kr * ra ** 3
+    om[..., L - 1] = -om[..., :L - 1].sum(-1)
+    return om
+
+
+def dra_parts(q, L):
+    """dOmega/dq as its nonzero pieces: level diagonal [..., L], the T column
+    [..., L], the atom column over the molecule levels [..., L-1] and the
+    atom row over them [..., L-1]."""
+    rk, T = q[..., :L], q[..., L + 2]
+    kd, kr, dkd, dkr = dra_rates(T, L)
+    rv, ra = rk[..., :L - 1], rk[..., L - 1:L]
+    diag = np.zeros(np.shape(rk))
+    diag[..., :L - 1] = -kd * ra
+    col = -kd * rv + 3.0 * kr * ra * ra
+    diag[..., L - 1] = -col.sum(-1)
+    tcol = np.zeros(np.shape(rk))
+    tcol[..., :L - 1] = -dkd * rv * ra + dkr * ra ** 3
+    tcol[..., L - 1] = -tcol[..., :L - 1].sum(-1)
+    row = kd * ra
+    return diag, tcol, col, row
+
+
 # ------------------------------------------------------------ HLL flux ----
 def hll(qL, qR, n, L, g):
     """HLL flux and its pieces for states [..., m]: f_hat, a_f, c_f, and
@@ -280,26 +331,31 @@ def _right_states(Q, q_inf, nb):
     return np.where((nb >= 0)[:, None], Q[np.maximum(nb, 0)], q_inf)
 
 
-def residual(st, nx: int, ny: int, L: int, Q=None, u_old=None):
-    """R_c(Q) = u(q_c) - u_old_c + dt_c sum_faces f_hat (dt frozen); with the
-    defaults Q is the state and u_old its conserved variables (R = flux
-    part only)."""
+def residual(st, nx: int, ny: int, L: int, Q=None, u_old=None, dra: bool = False):
+    """R_c(Q) = u(q_c) - u_old_c + dt_c sum_faces f_hat (dt frozen), and
+    - dt_c Omega(q_c) with the DRa source; with the defaults Q is the state
+    and u_old its conserved variables (R = flux part only)."""
     g = gas(L)
     Q = st["q"] if Q is None else Q
     R = conserved(Q, L, g) - (conserved(st["q"], L, g) if u_old is None else u_old)
     for d in FACE_DIRS:
         qR = _right_states(Q, st["q_inf"], _neighbours(nx, ny, d))
         R = R + st["dt"][:, None] * hll(Q, qR, NORMALS[d], L, g)["fhat"]
+    if dra:
+        R = R - st["dt"][:, None] * dra_source(Q, L)
     return R
 
 
 CHUNK = 1024  # cells per batch in make_problem (bounds the m x m temporaries)
 
 
-def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> Dict[str, np.ndarray]:
+def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0,
+                 dra: bool = False) -> Dict[str, np.ndarray]:
     """The Jacobian dR/dQ at the state, in the library's structured layout
     with 8 pairs per diagonal block, 6 per neighbour block, no level band and
-    level/flow coupling (see the module docstring)."""
+    level/flow coupling (see the module docstring).  With the DRa source the
+    pattern is arrow = 2: its atom column and row go to slot 3 of s_lev_flow
+    and s_flow_lev, its diagonal and T column to s_diag and slot 2."""
     if L < 2:
         raise ValueError("need at least two species")
     st = make_state(nx, ny, L, seed, cfl)
@@ -310,8 +366,8 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> D
     p = {k: np.zeros(s) for k, s in (("s_diag", (N, m)), ("s_sub", (N, L - 1)),
                                       ("s_sup", (N, L - 1)), ("s_flow", (N, 6)),
                                       ("s_nbr", (N, 4, m)), ("u", (N, P, m)), ("v", (N, P, m)),
-                                      ("s_band", (N, 0, L)), ("s_lev_flow", (N, 3, L)),
-                                      ("s_flow_lev", (N, 3, L)))}
+                                      ("s_band", (N, 0, L)), ("s_lev_flow", (N, 3 + dra, L)),
+                                      ("s_flow_lev", (N, 3 + dra, L)))}
     corner = ((0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1))
     nbrs = {d: _neighbours(nx, ny, d) for d in FACE_DIRS}
     a0 = slots[DIR_C][0]
@@ -364,13 +420,20 @@ def make_problem(nx: int, ny: int, L: int, seed: int = 0, cfl: float = 1.0) -> D
         p["s_diag"][cs, :L] = slev
         for i in range(3):
             p["s_diag"][cs, L + i] = sfr[:, i, L + i]
-        p["s_lev_flow"][cs] = slf.transpose(0, 2, 1)
-        p["s_flow_lev"][cs] = sfr[:, :, :L]
+        p["s_lev_flow"][cs, :3] = slf.transpose(0, 2, 1)
+        p["s_flow_lev"][cs, :3] = sfr[:, :, :L]
         for t, (i, j) in enumerate(corner):
             p["s_flow"][cs, t] = sfr[:, i, L + j]
+        if dra:
+            sd, tcol, col, row = dra_parts(qc, L)
+            w = -dt[:, None]
+            p["s_diag"][cs, :L] += w * sd
+            p["s_lev_flow"][cs, 2] += w * tcol
+            p["s_lev_flow"][cs, 3, :L - 1] = w * col
+            p["s_flow_lev"][cs, 3, :L - 1] = w * row
     for k in list(p):
         p[k] = np.ascontiguousarray(p[k])
     p["ranks"] = np.array([R_DIAG, R_OFF])
-    p["pattern"] = np.array([1, 1])
+    p["pattern"] = np.array([1, 2 if dra else 1])
     p["state"] = st["q"]
     return p

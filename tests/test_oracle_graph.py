@@ -12,7 +12,7 @@ from paper_2403_09198_amd import gen
 
 
 @pytest.mark.parametrize("ranks,band,arrow", [((1, 1), 1, False), ((9, 2), 3, True),
-                                              ((2, 0), 2, False)])
+                                              ((2, 0), 2, False), ((2, 1), 2, 2)])
 def test_structured_mesh_as_graph_matches_structured_oracle(ranks, band, arrow):
     nx, ny, L = 5, 4, 7
     p = gen.make_problem(nx, ny, L, seed=3, r_diag=ranks[0], r_off=ranks[1], band=band,
@@ -25,7 +25,7 @@ def test_structured_mesh_as_graph_matches_structured_oracle(ranks, band, arrow):
 
 
 @pytest.mark.parametrize("ranks,band,arrow", [((1, 1), 1, False), ((9, 2), 4, True),
-                                              ((3, 1), 1, True)])
+                                              ((3, 1), 1, True), ((2, 1), 1, 2)])
 def test_delaunay_dense_product_equals_csr_plus_br1(ranks, band, arrow):
     indptr, indices = gen.delaunay_graph(60, seed=4)
     L = 6
@@ -86,7 +86,7 @@ def test_gmres_on_delaunay_mesh_matches_dense_solve():
 def test_storage_counts_on_graph():
     indptr, indices = gen.delaunay_graph(50, seed=1)
     L = 7
-    for ranks, band, arrow in (((1, 1), 1, False), ((9, 2), 3, True)):
+    for ranks, band, arrow in (((1, 1), 1, False), ((9, 2), 3, True), ((2, 1), 2, 2)):
         p = gen.make_graph_problem(indptr, indices, L, seed=1, r_diag=ranks[0], r_off=ranks[1],
                                    band=band, arrow=arrow)
         csr = formats.graph_csr(p, L)

@@ -5,7 +5,9 @@ threshold jump in the level index give a banded pattern whose width is set by
 that threshold, and the level sources also depend on the temperature, so the
 level rows see the flow unknowns.  The generator's `band` is the band
 half-width over the levels (1 = tridiagonal) and `arrow` adds level/flow
-coupling (level rows x flow columns and flow rows x level columns)."""
+coupling (level rows x flow columns and flow rows x level columns); arrow = 2
+also couples the last level, the atom density, to every molecule level (the
+DRa processes of the same passage: a dense atom column and atom row)."""
 import numpy as np
 import pytest
 from scipy.linalg import solve_banded
@@ -14,7 +16,7 @@ from conftest import rel
 from oracle import assemble, blockjacobi, formats, gmres, grads, mesh, ops, storage
 from paper_2403_09198_amd import gen
 
-PATTERNS = [(2, False), (3, True), (4, False), (1, True), (4, True)]
+PATTERNS = [(2, False), (3, True), (4, False), (1, True), (4, True), (1, 2), (3, 2)]
 
 
 @pytest.mark.parametrize("band,arrow", PATTERNS)
@@ -65,6 +67,57 @@ def test_arrow_entries_sit_in_level_flow_positions():
                           assemble.diagonal_sparse_block(plain, 0, L))
 
 
+@pytest.mark.parametrize("band", [1, 3])
+def test_atom_entries_sit_in_atom_column_and_row(band):
+    L = 7
+    a = L - 1
+    p = gen.make_problem(1, 1, L, seed=2, band=band, arrow=2)
+    A = assemble.diagonal_sparse_block(p, 0, L)
+    assert np.array_equal(A[:a, a], p["s_lev_flow"][0, 3, :a])
+    assert np.array_equal(A[a, :a], p["s_flow_lev"][0, 3, :a])
+    assert A[a, a] == p["s_diag"][0, a]
+    # the atom keeps its flow couplings from the three flow slots
+    for i in range(3):
+        assert np.array_equal(A[:L, L + i], p["s_lev_flow"][0, i])
+        assert np.array_equal(A[L + i, :L], p["s_flow_lev"][0, i])
+    # index a of the atom slot is not an entry
+    q = {k: v.copy() for k, v in p.items()}
+    q["s_lev_flow"][0, 3, a] = 7.0
+    q["s_flow_lev"][0, 3, a] = -7.0
+    assert np.array_equal(assemble.diagonal_sparse_block(q, 0, L), A)
+    # a band entry that reaches the atom adds to the atom column (the block
+    # is the sum of its parts); the generator draws those as zero
+    assert p["s_sup"][0, a - 1] == 0.0 and p["s_sub"][0, a - 1] == 0.0
+    q["s_sup"][0, a - 1] = 0.5
+    assert assemble.diagonal_sparse_block(q, 0, L)[a - 1, a] == 0.5 + p["s_lev_flow"][0, 3, a - 1]
+    # clearing the atom slot gives the arrow = 1 block of the same draw
+    q = {k: v.copy() for k, v in p.items()}
+    q["s_lev_flow"] = q["s_lev_flow"][:, :3].copy()
+    q["s_flow_lev"] = q["s_flow_lev"][:, :3].copy()
+    q["pattern"] = np.array([band, 1])
+    B = assemble.diagonal_sparse_block(q, 0, L)
+    assert np.array_equal(B[:a, a], np.zeros(a)) and np.array_equal(B[a, :a], np.zeros(a))
+    C = A.copy()
+    C[:a, a] = 0.0
+    C[a, :a] = 0.0
+    assert np.array_equal(C, B)
+
+
+def test_atom_pattern_counts_per_row():
+    # molecule rows: own density, the atom density and the three flow
+    # unknowns (plus the band); the atom row: every level and the flow
+    L = 9
+    a = L - 1
+    p = gen.make_problem(1, 1, L, seed=3, band=1, arrow=2)
+    q = {k: v.copy() for k, v in p.items()}
+    q["s_sub"][:] = 0.0
+    q["s_sup"][:] = 0.0
+    A = assemble.diagonal_sparse_block(q, 0, L)
+    for k in range(a):
+        assert set(np.flatnonzero(A[k])) == {k, a, L, L + 1, L + 2}
+    assert set(np.flatnonzero(A[a])) == set(range(L + 3))
+
+
 @pytest.mark.parametrize("band,arrow", PATTERNS)
 @pytest.mark.parametrize("r_diag", [1, 9])
 def test_woodbury_inverse_times_block_is_identity(band, arrow, r_diag):
@@ -100,9 +153,10 @@ def test_storage_counts_with_wide_pattern():
         assert s[2] - 2 * s[1] + s[0] == 0
 
 
-def test_generator_keeps_dominance_with_wide_pattern():
+@pytest.mark.parametrize("arrow", [True, 2])
+def test_generator_keeps_dominance_with_wide_pattern(arrow):
     nx, ny, L = 8, 8, 200
-    p = gen.make_problem(nx, ny, L, seed=0, band=4, arrow=True)
+    p = gen.make_problem(nx, ny, L, seed=0, band=4, arrow=arrow)
     for c in (0, 9, 27, 63):
         A = assemble.diagonal_sparse_block(p, c, L)
         off = np.abs(A).sum(axis=1) - np.abs(np.diag(A))
@@ -110,9 +164,10 @@ def test_generator_keeps_dominance_with_wide_pattern():
         assert np.all(np.abs(np.diag(A)) > off + nbr)
 
 
-def test_gradients_with_wide_pattern_match_finite_differences():
+@pytest.mark.parametrize("arrow", [True, 2])
+def test_gradients_with_wide_pattern_match_finite_differences(arrow):
     nx, ny, L, nrhs = 3, 2, 6, 2
-    p = gen.make_problem(nx, ny, L, seed=4, band=3, arrow=True, r_diag=2, r_off=1)
+    p = gen.make_problem(nx, ny, L, seed=4, band=3, arrow=arrow, r_diag=2, r_off=1)
     b = gen.make_rhs(nx, ny, L, nrhs=nrhs, seed=4)
     w = gen.make_loss_weights(nx, ny, L, nrhs=nrhs, seed=4)
     n = nx * ny * (L + 3)
@@ -127,9 +182,17 @@ def test_gradients_with_wide_pattern_match_finite_differences():
     g = grads.structured_grads(p, nx, ny, L, lam, x)
     rng = np.random.default_rng(3)
     h = 1e-6
+    picks = {k: [tuple(int(rng.integers(s)) for s in p[k].shape) for _ in range(6)]
+             for k in gen.PATTERN_FIELDS}
+    if arrow == 2:
+        a = L - 1
+        # every atom-slot entry, its unused index a, and a band entry that
+        # reaches the atom (drawn as zero, still a parameter of the sum)
+        picks["s_lev_flow"] += [(1, 3, k) for k in range(L)]
+        picks["s_flow_lev"] += [(4, 3, k) for k in range(L)]
+        picks["s_band"] += [(2, 0, a), (2, 2, a - 3)]
     for key in gen.PATTERN_FIELDS:
-        for _ in range(6):
-            idx = tuple(int(rng.integers(s)) for s in p[key].shape)
+        for idx in picks[key]:
             qp = {kk: vv.copy() for kk, vv in p.items()}
             qm = {kk: vv.copy() for kk, vv in p.items()}
             qp[key][idx] += h

@@ -85,3 +85,59 @@ def test_physics_jacobian_solves_with_the_smw_block_jacobi():
     J = ops.dense_matrix(p, nx, ny, L)
     assert res.converged
     assert np.linalg.norm(J @ res.x.ravel() - b.ravel()) <= 1e-9 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("L", [2, 6])
+def test_dra_source_derivatives_match_finite_differences(L):
+    st = physics.make_state(3, 1, L, seed=5)
+    m = L + 3
+    for q in st["q"]:
+        om = physics.dra_source(q, L)
+        # mass moves between species only; momentum and energy unchanged
+        assert abs(om[:L].sum()) <= 1e-14 * np.abs(om).max() and not om[L:].any()
+        diag, tcol, col, row = physics.dra_parts(q, L)
+        D = np.zeros((m, m))
+        D[np.arange(L), np.arange(L)] = diag
+        D[:L, L + 2] = tcol
+        D[:L - 1, L - 1] += col
+        D[L - 1, :L - 1] += row
+        assert np.allclose(D, _fd(lambda z: physics.dra_source(z, L), q), rtol=1e-7, atol=1e-10)
+
+
+def test_dra_layout_reassembles_the_finite_difference_jacobian():
+    nx, ny, L = 3, 2, 5
+    p = physics.make_problem(nx, ny, L, seed=6, dra=True)
+    st = physics.make_state(nx, ny, L, seed=6)
+    N, m = nx * ny, L + 3
+    u_old = physics.conserved(st["q"], L, physics.gas(L))
+
+    def R(flat):
+        return physics.residual(st, nx, ny, L, Q=flat.reshape(N, m), u_old=u_old, dra=True).ravel()
+
+    J_fd = _fd(R, st["q"].ravel())
+    J = ops.dense_matrix(p, nx, ny, L)
+    assert np.abs(J - J_fd).max() <= 1e-6 * np.abs(J_fd).max()
+    assert mesh.pattern(p) == (1, 2) and p["s_lev_flow"].shape == (N, 4, L)
+    # the source reaches the atom column and row, which the flux part leaves empty
+    q = physics.make_problem(nx, ny, L, seed=6)
+    a = L - 1
+    for c in range(N):
+        A = assemble.diagonal_sparse_block(p, c, L)
+        B = assemble.diagonal_sparse_block(q, c, L)
+        assert not B[:a, a].any() and not B[a, :a].any()
+        assert np.all(A[:a, a] != 0.0) and np.all(A[a, :a] != 0.0)
+
+
+def test_dra_physics_jacobian_solves_with_the_smw_block_jacobi():
+    nx, ny, L = 6, 5, 8
+    p = physics.make_problem(nx, ny, L, seed=7, dra=True)
+    N, m = nx * ny, L + 3
+    for c in (0, 7, N - 1):
+        D = assemble.dense_block(p, c, mesh.C, L)
+        assert np.abs(blockjacobi.smw_inverse(p, c, L) @ D - np.eye(m)).max() <= 1e-10
+    b = np.random.default_rng(1).standard_normal((N, m))
+    M = blockjacobi.BlockJacobi(assemble.diagonal_blocks(p, nx, ny, L))
+    res = gmres.gmres(lambda v: ops.matvec(p, nx, ny, L, v), M.apply, b, restart=40, rtol=1e-10)
+    J = ops.dense_matrix(p, nx, ny, L)
+    assert res.converged
+    assert np.linalg.norm(J @ res.x.ravel() - b.ravel()) <= 1e-9 * np.linalg.norm(b)
