@@ -23,8 +23,12 @@
  * threshold jump give a banded pattern; band = 1 is tridiagonal) and, with
  * `arrow`, dense coupling of the level rows to the three flow columns
  * (temperature dependence of the level sources) and of the flow rows to the
- * levels.  These are described by r1s_layout; a NULL layout means one pair
- * per block, band = 1, no coupling.
+ * levels.  With arrow = 2 the last level a = L - 1 is the atom density, and
+ * the dissociation-recombination processes of the same passage couple it to
+ * every molecule level: a dense atom column S_{c,C}[k][a] and atom row
+ * S_{c,C}[a][k], k < a, are added to the block (on top of any band entry at
+ * those positions).  These are described by r1s_layout; a NULL layout means
+ * one pair per block, band = 1, no coupling.
  *
  * The library multiplies by J and J^T (section 5.2), applies the block-Jacobi
  * preconditioner through the Sherman-Morrison-Woodbury identity (section 6,
@@ -71,8 +75,13 @@
  *                     j-2 holds S_{c,C}[k][k-j], row band-1+j-2 holds
  *                     S_{c,C}[k][k+j], both at index k (entries outside the
  *                     block must be finite and are ignored)
- *   s_lev_flow [N][3][L]  (arrow) S_{c,C}[k][L+i] at [c][i][k]
- *   s_flow_lev [N][3][L]  (arrow) S_{c,C}[L+i][k] at [c][i][k]
+ *   s_lev_flow [N][ns][L]  (arrow) S_{c,C}[k][L+i] at [c][i][k], i < 3;
+ *                     arrow = 2 (ns = 4): slot 3 holds the atom column
+ *                     S_{c,C}[k][a] at [c][3][k], k < a
+ *   s_flow_lev [N][ns][L]  (arrow) S_{c,C}[L+i][k] at [c][i][k], i < 3;
+ *                     arrow = 2: slot 3 holds the atom row S_{c,C}[a][k]
+ *                     ns = 3 for arrow = 1, 4 for arrow = 2; index a of slot
+ *                     3 must be finite and is ignored
  * Directions: S = (ix, iy-1), W = (ix-1, iy), C = the cell, E = (ix+1, iy),
  * N = (ix, iy+1).  The mesh is not periodic: slots of blocks that do not
  * exist must hold finite values and are treated as zero.  s_sub / s_sup may
@@ -119,7 +128,8 @@ typedef struct {
   int r_diag; /* rank-one pairs per diagonal block, 1..9          */
   int r_off;  /* rank-one pairs per neighbour block, 0..6         */
   int band;   /* level-band half-width of S_{c,C}, 1..R1S_MAX_BAND */
-  int arrow;  /* 1: level rows x flow columns, flow rows x levels  */
+  int arrow;  /* 1: level rows x flow columns, flow rows x levels;
+                 2: also the atom (level L-1) x every level        */
 } r1s_layout;
 
 typedef struct {
@@ -246,9 +256,9 @@ const char* r1s_last_error(void);
 /* Device bytes of the packed matrix for an nx x ny mesh with L levels and
  * the block structure `layout` (NULL: one pair per block, band 1, no
  * coupling).  flags: R1S_KEEP_F32 adds float32 copies.  Errors: R1S_ERR_ARG
- * for nx, ny, L < 1, r_diag < 1, r_off < 0, band < 1, arrow not 0/1, or a
- * NULL `bytes`; R1S_ERR_UNSUPPORTED for L + 3 > R1S_MAX_M, r_diag > 9,
- * r_off > 6 or band > R1S_MAX_BAND. */
+ * for nx, ny, L < 1, r_diag < 1, r_off < 0, band < 1, arrow not 0/1/2,
+ * arrow = 2 with L < 2, or a NULL `bytes`; R1S_ERR_UNSUPPORTED for
+ * L + 3 > R1S_MAX_M, r_diag > 9, r_off > 6 or band > R1S_MAX_BAND. */
 int r1s_mat_size(int nx, int ny, int L, const r1s_layout* layout, int flags,
                  size_t* bytes);
 
@@ -277,7 +287,8 @@ int r1s_mat_destroy(r1s_mat A);
  * (matvec, residual, preconditioners, BSR copy, GMRES) takes the returned
  * handle like a structured one.  Errors: R1S_ERR_ARG for a malformed or
  * unsymmetric structure (the message names the row or block),
- * R1S_ERR_UNSUPPORTED for more than R1S_MAX_NBR neighbours, as for
+ * R1S_ERR_UNSUPPORTED for more than R1S_MAX_NBR neighbours or arrow = 2
+ * (the atom coupling is built for the structured mesh), as for
  * r1s_mat_size / r1s_mat_init otherwise. */
 int r1s_mat_size_graph(int n_cells, int L, const r1s_layout* layout,
                        const int* block_indptr, const int* block_indices,
@@ -314,7 +325,9 @@ int r1s_prec_size(r1s_mat A, int flags, size_t* bytes);
  * by its 3 x 3 inverse or, with level/flow coupling, by the inverse of its
  * 3 x 3 Schur complement; solves A0_c W_c = U_c (SMW-1), forms the
  * r_diag x r_diag capacitance C_c = I + V_c^T W_c (SMW-2) and inverts it
- * (Gauss-Jordan, partial pivoting).  Synchronises; returns R1S_ERR_SINGULAR
+ * (Gauss-Jordan, partial pivoting).  With arrow = 2, A0_c leaves out the
+ * atom's column c and row r, which join U_c, V_c as two more terms
+ * (c, e_a) and (e_a, r): the capacitance is (r_diag + 2) square.  Synchronises; returns R1S_ERR_SINGULAR
  * naming the first cell with a zero pivot of A0_c or of C_c
  * (|pivot| <= 1e-12 (1 + |V_c| |W_c|), Frobenius norms). */
 int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,

@@ -26,7 +26,7 @@ class R1SolveFn(torch.autograd.Function):
         names = r1s._used_fields(lay)
         vals = {k: t.detach().contiguous() for k, t in zip(names, arrays)}
         A = r1s.R1Matrix(nx, ny, L, vals, ranks=(lay.r_diag, lay.r_off), band=lay.band,
-                         arrow=bool(lay.arrow))
+                         arrow=int(lay.arrow))
         M = r1s.SMWPreconditioner(A, with_trans=True)
         bb = b.detach().contiguous()
         res = r1s.gmres(A, M, bb, restart=cfg.get("restart", 50), rtol=cfg.get("rtol", 1e-12),

@@ -81,8 +81,8 @@ static int check_layout(const r1s_layout& lay) {
   if (!ranks_supported(lay.r_diag, lay.r_off))
     return fail(R1S_ERR_UNSUPPORTED, "pair counts r_diag = %d, r_off = %d exceed %d, %d",
                 lay.r_diag, lay.r_off, RANK_DIAG_MAX, RANK_OFF_MAX);
-  if (lay.band < 1 || (lay.arrow != 0 && lay.arrow != 1))
-    return fail(R1S_ERR_ARG, "need band >= 1 and arrow 0 or 1 (got %d, %d)", lay.band, lay.arrow);
+  if (lay.band < 1 || lay.arrow < 0 || lay.arrow > 2)
+    return fail(R1S_ERR_ARG, "need band >= 1 and arrow 0, 1 or 2 (got %d, %d)", lay.band, lay.arrow);
   if (lay.band > R1S_MAX_BAND)
     return fail(R1S_ERR_UNSUPPORTED, "band %d exceeds %d", lay.band, R1S_MAX_BAND);
   return R1S_OK;
@@ -103,7 +103,7 @@ static Mesh make_mesh(int nx, int ny, int L, const r1s_layout& lay, bool graph =
   g.band = lay.band; g.arrow = lay.arrow;
   g.fb = F_NBR + nbmax;
   g.fa = g.fb + 2 * (g.band - 1);
-  g.fu = g.fa + 6 * g.arrow;
+  g.fu = g.fa + 2 * arrow_slots(g);
   g.F = g.fu + 2 * g.P;
   return g;
 }
@@ -139,6 +139,8 @@ extern "C" int r1s_mat_size(int nx, int ny, int L, const r1s_layout* layout, int
   if (int e = check_dims(nx, ny, L)) return e;
   const r1s_layout lay = layout_or_default(layout);
   if (int e = check_layout(lay)) return e;
+  if (lay.arrow == 2 && L < 2)
+    return fail(R1S_ERR_ARG, "arrow = 2 needs L >= 2 (the atom and a molecule level)");
   if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
   if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   Carver cv(nullptr);
@@ -287,6 +289,8 @@ extern "C" int r1s_mat_size_graph(int n_cells, int L, const r1s_layout* layout,
   if (int e = check_dims(n_cells, 1, L)) return e;
   const r1s_layout lay = layout_or_default(layout);
   if (int e = check_layout(lay)) return e;
+  if (lay.arrow == 2)
+    return fail(R1S_ERR_UNSUPPORTED, "the atom coupling (arrow = 2) is built for the structured mesh only");
   if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
   if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   GraphTables t;
@@ -389,6 +393,8 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   long long diag_block = 3 * m - 2;  // diagonal, tridiagonal band, 3 x 3 corner
   for (int j = 2; j <= g.band; ++j) diag_block += 2 * std::max(L - j, 0LL);
   if (g.arrow) diag_block += 6 * L;
+  // the atom's column and row, less the positions the band already holds
+  if (g.arrow == 2) diag_block += 2 * std::max(L - 1 - g.band, 0LL);
   out->structured_values = N * diag_block + (B - N) * m + 2 * pairs * m;
   out->structured_padded = N * (long long)g.F * g.mp;
   out->bsr_values = B * m * m;
@@ -399,8 +405,9 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   // A0 factors (as many values as S_cc; with the wide pattern the band LU
   // factors, the coupling factors and the 3 x 3 Schur inverse), W and V,
   // C^{-1}; r read, z written
-  const long long a0 = wide_pattern(g) ? (2 * g.band + 1 + 6 * g.arrow) * L + 9 : 3 * m - 2;
-  out->smw_apply_bytes = 8 * N * (a0 + 2 * g.rd * m + (long long)g.rd * g.rd) + 8 * 2 * N * m;
+  const long long a0 = wide_pattern(g) ? (2 * g.band + 1 + (g.arrow ? 6 : 0)) * L + 9 : 3 * m - 2;
+  const long long pw = smw_pairs(g);  // with the atom: two more Woodbury terms
+  out->smw_apply_bytes = 8 * N * (a0 + 2 * pw * m + pw * pw) + 8 * 2 * N * m;
   return R1S_OK;
 }
 
@@ -479,7 +486,7 @@ static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
     return;
   }
   const size_t f = (size_t)g.N * smw_rows(g) * g.mp;
-  const size_t ic = (size_t)g.N * g.rd * g.rd;
+  const size_t ic = (size_t)g.N * smw_pairs(g) * smw_pairs(g);
   P->facF = cv.take<double>(f);
   P->facT = (flags & R1S_WITH_TRANS) ? cv.take<double>(f) : nullptr;
   P->invC = cv.take<double>(ic);
@@ -543,7 +550,7 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
       const long long f = (long long)A->g.N * smw_rows(A->g) * A->g.mp;
       if ((e = launch_cast_f32(P->facF, P->facF32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       if (P->facT32 && (e = launch_cast_f32(P->facT, P->facT32, f, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
-      if ((e = launch_cast_f32(P->invC, P->invC32, (long long)A->g.N * A->g.rd * A->g.rd, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
+      if ((e = launch_cast_f32(P->invC, P->invC32, (long long)A->g.N * smw_pairs(A->g) * smw_pairs(A->g), s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
     }
     if ((rc = read_status(P->status, s, &st))) break;
     if (st != 0x7fffffff) {

@@ -50,6 +50,12 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
       } else if (g.arrow && i >= L && j < L) {
         s = rc[(g.fa + 3 + i - L) * mp + j];
       }
+      // the atom's column and row, added to what the band holds there
+      if (g.arrow == 2) {
+        const int a = L - 1;
+        if (j == a && i < a) s += rc[(long long)arrow_col_row(g, 3) * mp + i];
+        if (i == a && j < a) s += rc[(long long)arrow_row_row(g, 3) * mp + j];
+      }
     } else if (i == j) {
       s = rc[nbr_row(g, d) * mp + i];
     }

@@ -147,18 +147,21 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
         o.s_band[((long long)c * 2 * nbd + j - 2) * L + k] = glj;
         o.s_band[((long long)c * 2 * nbd + nbd + j - 2) * L + k] = guj;
       }
-      if (g.arrow) {
-        for (int i = 0; i < 3; ++i) {
-          double glf = 0.0, gfl = 0.0;
-          for (int r = 0; r < nrhs; ++r) {
-            const double* xc = x + (long long)r * g.n + (long long)c * m;
-            const double* lc = lam + (long long)r * g.n + (long long)c * m;
-            glf -= lc[k] * xc[L + i];
-            gfl -= lc[L + i] * xc[k];
-          }
-          o.s_lev_flow[((long long)c * 3 + i) * L + k] = glf;
-          o.s_flow_lev[((long long)c * 3 + i) * L + k] = gfl;
+      // coupling slot i: S[k][X_i] and S[X_i][k] with X_i = L + i, or the
+      // atom a = L - 1 for slot 3 (entries k < a; index a is not one)
+      const int ns = arrow_slots(g);
+      for (int i = 0; i < ns; ++i) {
+        const int xi = arrow_unknown(L, i);
+        const bool on = i < 3 || k < L - 1;
+        double glf = 0.0, gfl = 0.0;
+        for (int r = 0; r < nrhs && on; ++r) {
+          const double* xc = x + (long long)r * g.n + (long long)c * m;
+          const double* lc = lam + (long long)r * g.n + (long long)c * m;
+          glf -= lc[k] * xc[xi];
+          gfl -= lc[xi] * xc[k];
         }
+        o.s_lev_flow[((long long)c * ns + i) * L + k] = glf;
+        o.s_flow_lev[((long long)c * ns + i) * L + k] = gfl;
       }
     }
   }

@@ -66,8 +66,13 @@ __global__ __launch_bounds__(256) void k_pack(Mesh g, PackIn in, TV* __restrict_
         const bool ok = k < L && (t < nbd ? k >= j : k + j < L);
         if (ok) val = in.s_band[((long long)c * 2 * nbd + t) * L + k];
       } else if (f < g.fu) {
-        const int t = f - g.fa;  // 0..2 level->flow, 3..5 flow->level
-        if (k < L) val = (t < 3 ? in.s_lev_flow : in.s_flow_lev)[((long long)c * 3 + t % 3) * L + k];
+        // 0..2 level->flow, 3..5 flow->level; arrow = 2: 6 atom column, 7
+        // atom row (inputs [N][4][L], slot 3; index a = L - 1 is not an entry)
+        const int t = f - g.fa, ns = arrow_slots(g);
+        const int slot = t < 6 ? t % 3 : 3;
+        const bool lev_flow = t < 3 || t == 6;
+        if (k < (t < 6 ? L : L - 1))
+          val = (lev_flow ? in.s_lev_flow : in.s_flow_lev)[((long long)c * ns + slot) * L + k];
       } else if (f < g.fu + P) {
         const int q = f - g.fu;
         if (nb[dir_of_slot(g, q)]) val = in.u[((long long)c * P + q) * m + k];

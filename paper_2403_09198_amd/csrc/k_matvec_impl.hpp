@@ -115,7 +115,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
   // the rows read are other rows of the record (distinct, always present)
   // and their values are discarded.
   constexpr bool PRE_ARROW = WIDE && PRELOAD && ROM > RANK_OFF_SMALL;
-  constexpr int NA = PRE_ARROW ? 3 : 1;
+  constexpr int NA = PRE_ARROW ? ARROW_SLOTS_MAX : 1;
+  const int nsl = arrow_slots(g);  // coupling slots (wave-uniform)
   TV arw[NA][NCH], alw[NA][NCH], xfl[NR][NA];
   // single chunk: the band / corner partners x[pa], x[pb] of the cell's own
   // block come from the lanes that loaded them (a lane permutation) instead
@@ -164,12 +165,13 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     }
     if constexpr (PRE_ARROW) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        arw[i][ch] = ld_stream(R.rc + (g.arrow ? arrow_sum_row<TRANS>(g, i) : F_DIAG + i) * mp + kk);
-        alw[i][ch] = ld_stream(R.rc + (g.arrow ? arrow_lane_row<TRANS>(g, i) : F_NBR + i) * mp + kk);
+      for (int i = 0; i < NA; ++i) {
+        const bool on = i < nsl;
+        arw[i][ch] = ld_stream(R.rc + (on ? arrow_sum_row<TRANS>(g, i) : F_DIAG + i) * mp + kk);
+        alw[i][ch] = ld_stream(R.rc + (on ? arrow_lane_row<TRANS>(g, i) : F_NBR + i % 3) * mp + kk);
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          xfl[r][i] = (TV)xr[(long long)r * g.n + (long long)c * m + L + i];
+          xfl[r][i] = (TV)xr[(long long)r * g.n + (long long)c * m + arrow_unknown(L, i)];
       }
     }
   };
@@ -196,16 +198,17 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         s = wave_sum_u(s);
         acc[r][d][p] = ex[d] ? s : TV(0);
       }
-  // coupling sums of the flow unknowns over the cell's levels
-  TV asum[NR][3];
+  // coupling sums of the flow unknowns (and the atom) over the cell's levels
+  TV asum[NR][ARROW_SLOTS_MAX];
   if constexpr (WIDE) {
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) asum[r][i] = TV(0);
+      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) asum[r][i] = TV(0);
     if (g.arrow) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+        if (i >= nsl) break;
         TV ar[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
@@ -235,15 +238,16 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
     BandLane<TV, TRANS> bl;
-    TV al[3] = {TV(0), TV(0), TV(0)};
+    TV al[ARROW_SLOTS_MAX] = {TV(0), TV(0), TV(0), TV(0)};
     if constexpr (WIDE) {
       bl.load(g, R.rc, kk);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+        if (i >= nsl) break;
         if constexpr (PRE_ARROW)
-          al[i] = g.arrow ? alw[i][ch] : TV(0);
+          al[i] = alw[i][ch];
         else
-          al[i] = g.arrow ? R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk] : TV(0);
+          al[i] = R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk];
       }
     }
 #pragma unroll
@@ -266,19 +270,21 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         else
           t += bl.apply(g, xc);
         if (g.arrow) {
-          // level lanes: coupling entries times the flow unknowns; flow lane
-          // L + i: the coupling sum
+          // level lanes: coupling entries times the flow unknowns (and the
+          // atom); flow lane L + i (atom lane L - 1): the coupling sum
 #pragma unroll
-          for (int i = 0; i < 3; ++i) {
+          for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+            if (i >= nsl) break;
             if constexpr (PRE_ARROW)
               t += al[i] * xfl[r][i];
             else if constexpr (SHUFFLE_X)
-              t += al[i] * readlane(xv[r][D_C][ch], L + i);
+              t += al[i] * readlane(xv[r][D_C][ch], arrow_unknown(L, i));
             else
-              t += al[i] * (TV)xc[L + i];
+              t += al[i] * (TV)xc[arrow_unknown(L, i)];
           }
           const int fi = kk - L;
           t += fi == 0 ? asum[r][0] : fi == 1 ? asum[r][1] : fi == 2 ? asum[r][2] : TV(0);
+          if (nsl > 3 && fi == -1) t += asum[r][3];
         }
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   constexpr bool EXACT = RDM == 1 && ROM == 1;
   constexpr int RM = RDM > ROM ? RDM : ROM;
   __shared__ TV part[NR][5][RM][NCH];
-  __shared__ TV apart[WIDE ? NR : 1][3][NCH];
+  __shared__ TV apart[WIDE ? NR : 1][ARROW_SLOTS_MAX][NCH];
   __shared__ TV xs[NR][WAVE * NCH];  // the cell's own x block (band / corner partners)
   const Mesh g = kmesh<EXACT>(g_);
   int c0, qn;
@@ -385,11 +391,13 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
       }
   // wide pattern: this chunk's share of the coupling sums, band terms
   BandLane<TV, TRANS> bl;
-  TV al[3] = {TV(0), TV(0), TV(0)};
+  TV al[ARROW_SLOTS_MAX] = {TV(0), TV(0), TV(0), TV(0)};
+  const int nsl = arrow_slots(g);
   if constexpr (WIDE) {
     if (g.arrow) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+        if (i >= nsl) break;
         const TV ar = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + kk] : TV(0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -421,12 +429,16 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
       t += bl.apply(g, xc);
       if (g.arrow) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) t += al[i] * (TV)xc[L + i];
+        for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+          if (i >= nsl) break;
+          t += al[i] * (TV)xc[arrow_unknown(L, i)];
+        }
         const int fi = kk - L;
-        if (fi >= 0 && fi < 3) {
-          TV s = apart[r][fi][0];
+        const int si = fi >= 0 && fi < 3 ? fi : (nsl > 3 && fi == -1 ? 3 : -1);
+        if (si >= 0) {
+          TV s = apart[r][si][0];
 #pragma unroll
-          for (int w = 1; w < NCH; ++w) s += apart[r][fi][w];
+          for (int w = 1; w < NCH; ++w) s += apart[r][si][w];
           t += s;
         }
       }

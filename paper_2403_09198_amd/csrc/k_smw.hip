@@ -17,6 +17,12 @@
 // maps), carrying the last value from one 64-level chunk to the next.  The
 // coupling is eliminated through the 3 x 3 Schur complement S3 = F - Er
 // T^{-1} Ec, which takes the place of F^{-1} in the factor record.
+//
+// With the atom density coupled to every molecule level (arrow = 2, a dense
+// column and row through the band), A0 keeps the three-slot pattern and the
+// atom's column c and row r join the Woodbury terms as two more pairs,
+// D_c = A0 + U V^T + c e_a^T + e_a r^T: the band sweeps stay affine scans and
+// the capacitance grows from rd x rd to (rd + 2) x (rd + 2).
 #include <math.h>
 
 #include "r1s_device.hpp"
@@ -62,7 +68,8 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   if (c >= g.N) return;
   const int lane = lane_id();
   const int L = g.L, m = g.m, mp = g.mp;
-  const int rd = RDM == 1 ? 1 : g.rd;
+  const int rd = RDM == 1 ? 1 : smw_pairs(g);  // Woodbury terms
+  const int rdu = RDM == 1 ? 1 : g.rd;          // of them, the block's own pairs
   const int SR = smw_rows(g);
   const bool arw = g.arrow;  // wave-uniform
   const double* rc = rec + (long long)c * g.F * mp;
@@ -71,6 +78,19 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
   const double* hi = rc + (long long)F_HI * mp;
   const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;         // pair i at + i mp
   const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
+  // pair j's u and v at element kk (kk < m): the block's pairs, then the
+  // atom's column (u = column, v = e_a) and row (u = e_a, v = row)
+  const int ia = L - 1;
+  auto pair_u = [&](int j, int kk) -> double {
+    if (j < rdu) return uC[j * mp + kk];
+    if (j == rdu) return kk < ia ? rc[(long long)arrow_col_row(g, 3) * mp + kk] : 0.0;
+    return kk == ia ? 1.0 : 0.0;
+  };
+  auto pair_v = [&](int j, int kk) -> double {
+    if (j < rdu) return vC[j * mp + kk];
+    if (j == rdu) return kk == ia ? 1.0 : 0.0;
+    return kk < ia ? rc[(long long)arrow_row_row(g, 3) * mp + kk] : 0.0;
+  };
 
   double AD[NCH], LO[NCH], HI[NCH], HM1[NCH], LP1[NCH];
 #pragma unroll
@@ -243,11 +263,11 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
     for (int ch = 0; ch < NCH; ++ch) {
       const int k = ch * WAVE + lane;
       const int kk = k < m ? k : m - 1;
-      U[ch] = uC[j * mp + kk];
-      V[j][ch] = vC[j * mp + kk];
+      U[ch] = pair_u(j, kk);
+      V[j][ch] = pair_v(j, kk);
     }
-    const double* uf = uC + j * mp + L;
-    smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, uf[0], uf[1], uf[2], W[j]);
+    smw_sweeps<double, NCH, false>(L, m, FA, FDI, FB, U, pair_u(j, L), pair_u(j, L + 1),
+                                   pair_u(j, L + 2), W[j]);
     if (arw) arrow_schur<double, NCH>(L, m, FA, FDI, FB, XC, ER, W[j]);
     put(fA + (P_W + j) * mp, W[j]);
     put(fA + (P_W + rd + j) * mp, V[j]);
@@ -327,10 +347,10 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_setup(Mesh g, const double* __
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
         const int k = ch * WAVE + lane;
-        U[ch] = uC[j * mp + (k < m ? k : m - 1)];
+        U[ch] = pair_u(j, k < m ? k : m - 1);
       }
-      const double* vf = vC + j * mp + L;
-      smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V[j], vf[0], vf[1], vf[2], WT);
+      smw_sweeps<double, NCH, true>(L, m, TA, TDI, TB, V[j], pair_v(j, L), pair_v(j, L + 1),
+                                    pair_v(j, L + 2), WT);
       if (arw) arrow_schur<double, NCH>(L, m, TA, TDI, TB, XR, EC, WT);
       put(fT + (P_W + j) * mp, WT);
       put(fT + (P_W + rd + j) * mp, U);
@@ -357,9 +377,11 @@ static hipError_t launch_setup_r(const Mesh& g, const double* rec, double* facF,
 hipError_t launch_smw_setup(const Mesh& g, const double* rec, double* facF, double* facT,
                             double* invC, int* status, hipStream_t s) {
   if (band_walk(g)) return hipErrorInvalidValue;  // the band kernels serve those
-  if (g.rd == 1) return launch_setup_r<1>(g, rec, facF, facT, invC, status, s);
-  if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
-  return launch_setup_r<RANK_DIAG_MAX>(g, rec, facF, facT, invC, status, s);
+  const int pw = smw_pairs(g);
+  if (pw == 1) return launch_setup_r<1>(g, rec, facF, facT, invC, status, s);
+  if (pw <= RANK_DIAG_MAX) return launch_setup_r<RANK_DIAG_MAX>(g, rec, facF, facT, invC, status, s);
+  if (pw <= SMW_PAIRS_MAX) return launch_setup_r<SMW_PAIRS_MAX>(g, rec, facF, facT, invC, status, s);
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------- apply ----
@@ -384,7 +406,7 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
   const int lane = lane_id();
   const int L = g.L, m = g.m;
   const long long mp = g.mp;
-  const int rd = RDM == 1 ? 1 : g.rd;
+  const int rd = RDM == 1 ? 1 : smw_pairs(g);
   const int SR = smw_rows(g);
   const int PX = smw_arrow_row(g);
   constexpr int NX = ARW ? 3 : 1;
@@ -486,7 +508,7 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
   const int lane = lane_id();
   const int L = g.L, m = g.m;
   const long long mp = g.mp;
-  const int rd = RDM == 1 ? 1 : g.rd;
+  const int rd = RDM == 1 ? 1 : smw_pairs(g);
   const int SR = smw_rows(g);
   const int PX = smw_arrow_row(g);
   const int k = wv * WAVE + lane;
@@ -692,8 +714,13 @@ template <typename TV, bool TRANS>
 static hipError_t launch_apply_rank(const Mesh& g, const TV* fac, const TV* invC, const double* r,
                                     double* z, int nrhs, hipStream_t s) {
   if (g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
-  // level/flow coupling: one instantiation at the largest pair count
-  if (g.arrow) return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX, true>(g, fac, invC, r, z, nrhs, s);
+  // level/flow coupling: one instantiation at the largest pair count (with
+  // the atom's two terms beyond RANK_DIAG_MAX, a wider one)
+  if (g.arrow) {
+    if (smw_pairs(g) > RANK_DIAG_MAX)
+      return launch_apply_nch<TV, TRANS, SMW_PAIRS_MAX, true>(g, fac, invC, r, z, nrhs, s);
+    return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX, true>(g, fac, invC, r, z, nrhs, s);
+  }
   if (g.rd == 1) return launch_apply_nch<TV, TRANS, 1, false>(g, fac, invC, r, z, nrhs, s);
   return launch_apply_nch<TV, TRANS, RANK_DIAG_MAX, false>(g, fac, invC, r, z, nrhs, s);
 }

@@ -23,7 +23,9 @@
 // of levels while it computes the current one (the recurrence itself only
 // touches registers).  The Woodbury correction has no recurrence: a second
 // kernel does it with one wavefront per cell on per-cell rows ([N][2 rd][mp]
-// for W, V and [N][rd][rd] for C^{-1}), like the tridiagonal path.
+// for W, V and [N][rd][rd] for C^{-1}), like the tridiagonal path.  With the
+// atom density coupled to every molecule level (arrow = 2) the atom's column
+// and row are two more Woodbury terms (rd + 2 in place of rd), as there.
 // Right-hand sides and results keep the [nrhs][N][m] vector layout.
 #include <math.h>
 
@@ -44,7 +46,7 @@ constexpr int TILE = R1S_BAND_TILE;
 //   up(j) rows band+1..2 band  U_B[k][k+j]                 (k + j < L)
 //   ec(i) rows 2 band+1+i      (L_B^{-1} E_c)[k][i]        (coupling only)
 //   er(i) rows 2 band+4+i      (E_r U_B^{-1})[i][k]        (coupling only)
-__host__ __device__ inline int band_rows(const Mesh& g) { return 2 * g.band + 1 + 6 * g.arrow; }
+__host__ __device__ inline int band_rows(const Mesh& g) { return 2 * g.band + 1 + (g.arrow ? 6 : 0); }
 __host__ __device__ inline long long tiles(const Mesh& g) { return (g.N + TILE - 1) / TILE; }
 
 // Solve A0 x = r (TRANS: A0^T x = r) for one cell.  r(k) gives the right-hand
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int c = tile * TILE + lane;
   if (c >= g.N) return;  // no cross-lane work in this kernel
-  const int L = g.L, m = g.m, band = g.band, rd = g.rd;
+  const int L = g.L, m = g.m, band = g.band, rd = smw_pairs(g), rdu = g.rd;
   const long long mp = g.mp;
   const double* rc = rec + (long long)c * g.F * mp;
   const int RB = band_rows(g);
@@ -216,6 +218,19 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
 
   const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
   const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
+  // Woodbury term i at element k: the block's pairs, then the atom's column
+  // (u = column, v = e_a) and row (u = e_a, v = row)
+  const int ia = L - 1;
+  auto pair_u = [&](int i, int k) -> double {
+    if (i < rdu) return uC[i * mp + k];
+    if (i == rdu) return k < ia ? rc[(long long)arrow_col_row(g, 3) * mp + k] : 0.0;
+    return k == ia ? 1.0 : 0.0;
+  };
+  auto pair_v = [&](int i, int k) -> double {
+    if (i < rdu) return vC[i * mp + k];
+    if (i == rdu) return k == ia ? 1.0 : 0.0;
+    return k < ia ? rc[(long long)arrow_row_row(g, 3) * mp + k] : 0.0;
+  };
   double* wc = wv + (long long)c * 2 * rd * mp;  // this cell's W rows, then V rows
   // SMW-1: W_i = A0^{-1} u_i; V_i = v_i (padding zero)
   double vv = 0.0, ww = 0.0;
@@ -223,9 +238,9 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
     double* Wi = wc + (long long)i * mp;
     double* Vi = wc + (long long)(rd + i) * mp;
     band_solve<false, 1, double, double>(fb, L, band, g.arrow, s3i,
-                                         [&](int k) { return uC[i * mp + k]; }, Wi);
+                                         [&](int k) { return pair_u(i, k); }, Wi);
     for (int k = 0; k < m; ++k) {
-      const double v = vC[i * mp + k];
+      const double v = pair_v(i, k);
       Vi[k] = v;
       vv += v * v;
       ww += Wi[k] * Wi[k];
@@ -233,7 +248,7 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
     for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
   }
   // SMW-2: C = I + V^T W, inverted by Gauss-Jordan with partial pivoting
-  double Cm[RANK_DIAG_MAX][2 * RANK_DIAG_MAX];
+  double Cm[SMW_PAIRS_MAX][2 * SMW_PAIRS_MAX];
   for (int i = 0; i < rd; ++i)
     for (int j = 0; j < rd; ++j) {
       double s = i == j ? 1.0 : 0.0;
@@ -272,8 +287,8 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
       double* Wi = wcT + (long long)i * mp;
       double* Vi = wcT + (long long)(rd + i) * mp;
       band_solve<true, 1, double, double>(fb, L, band, g.arrow, s3i,
-                                          [&](int k) { return vC[i * mp + k]; }, Wi);
-      for (int k = 0; k < m; ++k) Vi[k] = uC[i * mp + k];
+                                          [&](int k) { return pair_v(i, k); }, Wi);
+      for (int k = 0; k < m; ++k) Vi[k] = pair_u(i, k);
       for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
     }
   }
@@ -468,7 +483,7 @@ __global__ __launch_bounds__(64 * WPB) void k_band_woodbury(Mesh g, const TV* __
   const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + (threadIdx.x >> 6)));
   if (c >= g.N) return;
   const int lane = lane_id();
-  const int m = g.m, rd = RDM == 1 ? 1 : g.rd;
+  const int m = g.m, rd = RDM == 1 ? 1 : smw_pairs(g);
   const long long mp = g.mp;
   const TV* wc = wv + (long long)c * 2 * rd * mp;
   CapInv<TV, RDM> IC;
@@ -537,10 +552,13 @@ static hipError_t launch_band_apply_t(const Mesh& g, const TV* bf, const TV* s3i
     launch_band_solve<TV, TRANS, 4>(g, bf, s3i, r, z, nrhs, s);
   else
     launch_band_solve<TV, TRANS, BAND_MAX>(g, bf, s3i, r, z, nrhs, s);
-  if (g.rd == 1)
+  const int pw = smw_pairs(g);
+  if (pw == 1)
     launch_woodbury_r<TV, TRANS, 1>(g, wv, cinv, z, nrhs, s);
-  else
+  else if (pw <= RANK_DIAG_MAX)
     launch_woodbury_r<TV, TRANS, RANK_DIAG_MAX>(g, wv, cinv, z, nrhs, s);
+  else
+    launch_woodbury_r<TV, TRANS, SMW_PAIRS_MAX>(g, wv, cinv, z, nrhs, s);
   return hipGetLastError();
 }
 
@@ -567,8 +585,8 @@ void band_prec_counts(const Mesh& g, long long* bf, long long* s3i, long long* w
   const long long T = tiles(g);
   *bf = T * band_rows(g) * g.L * TILE;
   *s3i = T * 9 * TILE;
-  *wv = (long long)g.N * 2 * g.rd * g.mp;
-  *cinv = (long long)g.N * g.rd * g.rd;
+  *wv = (long long)g.N * 2 * smw_pairs(g) * g.mp;
+  *cinv = (long long)g.N * smw_pairs(g) * smw_pairs(g);
 }
 
 }  // namespace r1s

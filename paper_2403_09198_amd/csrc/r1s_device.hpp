@@ -14,14 +14,17 @@
 //   fb + band-1 + j-2    S_cc[k][k+j]
 //   fa + i         S_cc[k][L+i] (level rows), i < 3, with level/flow coupling
 //   fa + 3 + i     S_cc[L+i][k] at index k (the flow row i over the levels)
+//   fa + 6         arrow = 2: the atom column S_cc[k][a] at index k < a
+//   fa + 7         arrow = 2: the atom row S_cc[a][k] at index k < a
+//                  (a = L - 1, the atom density; zero at k >= a)
 //   fu .. fu+P-1   u     the pairs of blocks S, W, C, E, N in that order
 //                        (ro pairs per neighbour block, rd for the diagonal;
 //                        general mesh: the diagonal block's rd, then slot by
 //                        slot ro each)
 //   fu+P .. F-1    v     same order
 // fb = 3 + nbmax (7 on the structured mesh), fa = fb + 2 (band - 1),
-// fu = fa + 6 arrow, F = fu + 2 P (17 rows with one pair per block, band 1
-// and no coupling).
+// fu = fa + 2 * (coupling slots: 0, 3 or 4), F = fu + 2 P (17 rows with one
+// pair per block, band 1 and no coupling).
 //
 // Padding elements and the rows of blocks that do not exist (mesh boundary)
 // are zero.
@@ -46,6 +49,9 @@ constexpr int MAX_CHUNKS = 4;  // m <= 256
 // neighbour block); one pair per block has kernels of its own, and up to
 // RANK_OFF_SMALL pairs per neighbour block a lighter instantiation.
 constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 6, RANK_OFF_SMALL = 2;
+// Woodbury terms of the block-Jacobi at most: the diagonal pairs and the
+// atom's column and row
+constexpr int SMW_PAIRS_MAX = RANK_DIAG_MAX + 2;
 constexpr int BAND_MAX = 8;  // level-band half-width of S_cc
 
 // SMW factor records, [N][3 + 2 rd][mp] per direction of application, plus
@@ -84,6 +90,17 @@ struct Mesh {
 // Band or coupling beyond the tridiagonal / uncoupled diagonal block.
 __host__ __device__ inline bool wide_pattern(const Mesh& g) { return g.band > 1 || g.arrow; }
 
+// Coupling slots of the diagonal block: slot i < 3 couples the levels to the
+// flow unknown L + i; with arrow = 2, slot 3 couples the molecule levels to
+// the atom density a = L - 1 (the DRa processes of section 4, "Temporal
+// Source Jacobian").  Each slot has a column row (S[k][X_i] at lane k) and a
+// row row (S[X_i][k] at lane k) in the record.
+constexpr int ARROW_SLOTS_MAX = 4;
+__host__ __device__ inline int arrow_slots(const Mesh& g) { return g.arrow == 2 ? 4 : g.arrow ? 3 : 0; }
+__host__ __device__ inline int arrow_unknown(int L, int i) { return i < 3 ? L + i : L - 1; }
+__host__ __device__ inline int arrow_col_row(const Mesh& g, int i) { return g.fa + (i < 3 ? i : 6); }
+__host__ __device__ inline int arrow_row_row(const Mesh& g, int i) { return g.fa + (i < 3 ? 3 + i : 7); }
+
 // First record slot and number of the pairs of block direction d (general
 // mesh: d = D_C or GSLOT + slot).
 __host__ __device__ inline int pair_count(const Mesh& g, int d) { return d == 2 ? g.rd : g.ro; }
@@ -95,11 +112,15 @@ __host__ __device__ inline int pair_start(const Mesh& g, int d) {
 __host__ __device__ inline int nbr_row(const Mesh& g, int d) {
   return F_NBR + (g.graph ? d - GSLOT : (d < 2 ? d : d - 1));
 }
+// Woodbury terms of the block-Jacobi: the diagonal block's rd pairs and, with
+// arrow = 2, two more for the atom's column and row (u = atom column, v =
+// e_a; u = e_a, v = atom row), so that A0 keeps the three-slot pattern.
+__host__ __device__ inline int smw_pairs(const Mesh& g) { return g.rd + (g.arrow == 2 ? 2 : 0); }
 // Rows of the wave-per-cell SMW factor record of a cell: the three sweep
-// rows, W and V (rd each), and with level/flow coupling the three columns
-// T^{-1} E and the three coupling rows of the Schur step.
-__host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * g.rd + (g.arrow ? 6 : 0); }
-__host__ __device__ inline int smw_arrow_row(const Mesh& g) { return 3 + 2 * g.rd; }
+// rows, W and V (smw_pairs each), and with level/flow coupling the three
+// columns T^{-1} E and the three coupling rows of the Schur step.
+__host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * smw_pairs(g) + (g.arrow ? 6 : 0); }
+__host__ __device__ inline int smw_arrow_row(const Mesh& g) { return 3 + 2 * smw_pairs(g); }
 // The block-Jacobi needs the one-lane-per-cell band factorisation when the
 // level band is wider than tridiagonal; the tridiagonal band, with or
 // without level/flow coupling, runs wave-per-cell.
@@ -586,10 +607,16 @@ struct CapInv {
 // forward the flow rows S[L+i][.] (fa + 3 + i), transposed the flow columns
 // S[.][L+i] (fa + i).  Per-lane coupling rows times x_{L+i}: forward
 // S[k][L+i] (fa + i), transposed S[L+i][k] (fa + 3 + i).
+// Slot 3 (the atom) the same way, with x_a and lane a in place of x_{L+i}
+// and lane L + i.
 template <bool TRANS>
-__device__ inline int arrow_sum_row(const Mesh& g, int i) { return g.fa + (TRANS ? 0 : 3) + i; }
+__device__ inline int arrow_sum_row(const Mesh& g, int i) {
+  return TRANS ? arrow_col_row(g, i) : arrow_row_row(g, i);
+}
 template <bool TRANS>
-__device__ inline int arrow_lane_row(const Mesh& g, int i) { return g.fa + (TRANS ? 3 : 0) + i; }
+__device__ inline int arrow_lane_row(const Mesh& g, int i) {
+  return TRANS ? arrow_row_row(g, i) : arrow_col_row(g, i);
+}
 
 // Band coefficients of lane kk (clamped lane index) and the x indices they
 // multiply; invalid positions get a zero coefficient and a valid index.

@@ -47,8 +47,10 @@ def _buffer(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def layout(r_diag=1, r_off=1, band=1, arrow=False) -> "L.Layout":
-    return L.Layout(r_diag=int(r_diag), r_off=int(r_off), band=int(band), arrow=int(bool(arrow)))
+def layout(r_diag=1, r_off=1, band=1, arrow=0) -> "L.Layout":
+    """arrow: 0 none, 1 (or True) level/flow coupling, 2 also the atom density
+    coupled to every molecule level."""
+    return L.Layout(r_diag=int(r_diag), r_off=int(r_off), band=int(band), arrow=int(arrow))
 
 
 def _used_fields(lay):
@@ -63,8 +65,14 @@ def _shapes(nx, ny, Lv, lay):
     P = lay.r_diag + 4 * lay.r_off
     return {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
             "s_nbr": (N, 4, m), "u": (N, P, m), "v": (N, P, m),
-            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, 3, Lv),
-            "s_flow_lev": (N, 3, Lv)}
+            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, _slots(lay), Lv),
+            "s_flow_lev": (N, _slots(lay), Lv)}
+
+
+def _slots(lay):
+    """Coupling slots of the level/flow arrays: the three flow unknowns, and
+    the atom with arrow = 2."""
+    return 4 if lay.arrow == 2 else 3
 
 
 def _inputs(values: Dict[str, torch.Tensor], nx, ny, Lv, lay):
@@ -115,8 +123,8 @@ def _host_i32(a):
 def _graph_shapes(N, n_off, Lv, lay):
     m = Lv + 3
     return {"s_diag": (N, m), "s_sub": (N, Lv - 1), "s_sup": (N, Lv - 1), "s_flow": (N, 6),
-            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, 3, Lv),
-            "s_flow_lev": (N, 3, Lv), "s_nbr": (n_off, m), "u_diag": (N, lay.r_diag, m),
+            "s_band": (N, 2 * (lay.band - 1), Lv), "s_lev_flow": (N, _slots(lay), Lv),
+            "s_flow_lev": (N, _slots(lay), Lv), "s_nbr": (n_off, m), "u_diag": (N, lay.r_diag, m),
             "v_diag": (N, lay.r_diag, m), "u_off": (n_off, lay.r_off, m),
             "v_off": (n_off, lay.r_off, m)}
 
@@ -303,7 +311,7 @@ class R1Matrix:
         self.n = self.N * self.m
         self.r_diag, self.r_off = (int(r) for r in ranks)
         self.n_pairs = self.r_diag + 4 * self.r_off
-        self.band, self.arrow = int(band), bool(arrow)
+        self.band, self.arrow = int(band), int(arrow)
         self.layout = layout(self.r_diag, self.r_off, self.band, self.arrow)
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device
@@ -355,7 +363,7 @@ class R1GraphMatrix(R1Matrix):
         self.n = N * self.m
         self.n_off = len(self.indices) - N
         self.r_diag, self.r_off = (int(r) for r in ranks)
-        self.band, self.arrow = int(band), bool(arrow)
+        self.band, self.arrow = int(band), int(arrow)
         self.layout = layout(self.r_diag, self.r_off, self.band, self.arrow)
         self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
         dev = values["s_diag"].device

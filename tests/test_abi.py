@@ -70,7 +70,11 @@ def test_layout_validation_and_sizes():
     lib = L.lib()
     b, a = C.c_size_t(), C.c_size_t()
     assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 0), 0, C.byref(b)) == L.R1S_ERR_ARG
-    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 1, 2), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 1, 3), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, 1, -1), 0, C.byref(b)) == L.R1S_ERR_ARG
+    # the atom coupling needs the atom and at least one molecule level
+    assert lib.r1s_mat_size(4, 4, 1, _lay(1, 1, 1, 2), 0, C.byref(b)) == L.R1S_ERR_ARG
+    assert "L >= 2" in lib.r1s_last_error().decode()
     assert lib.r1s_mat_size(4, 4, 4, _lay(1, 1, L.R1S_MAX_BAND + 1), 0, C.byref(b)) == \
         L.R1S_ERR_UNSUPPORTED
     # NULL layout = one pair per block, band 1, no coupling
@@ -80,6 +84,10 @@ def test_layout_validation_and_sizes():
     # band 4 with coupling: 2 (4 - 1) + 6 more rows of 64 doubles per cell
     assert lib.r1s_mat_size(8, 4, 61, _lay(1, 1, 4, 1), 0, C.byref(b)) == L.R1S_OK
     assert b.value - a.value == 32 * 12 * 64 * 8
+    # the atom's column and row: two more rows
+    c = C.c_size_t()
+    assert lib.r1s_mat_size(8, 4, 61, _lay(1, 1, 4, 2), 0, C.byref(c)) == L.R1S_OK
+    assert c.value - b.value == 32 * 2 * 64 * 8
 
 
 def test_init_requires_pattern_arrays():
@@ -189,6 +197,12 @@ def test_general_mesh_structure_is_validated():
         ix += [0, c]          # row c: cell 0 and itself
         ip.append(ip[-1] + 2)
     assert _graph_size(ip, ix)[0] == L.R1S_ERR_UNSUPPORTED
+
+
+def test_general_mesh_rejects_the_atom_coupling():
+    rc, msg, _ = _graph_size([0, 2, 4], [0, 1, 1, 0], _lay(1, 1, 1, 2))
+    assert rc == L.R1S_ERR_UNSUPPORTED and "structured mesh" in msg
+    assert _graph_size([0, 2, 4], [0, 1, 1, 0], _lay(1, 1, 1, 1))[0] == L.R1S_OK
 
 
 def test_general_mesh_size_matches_structured_record():

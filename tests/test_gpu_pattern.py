@@ -5,8 +5,11 @@ threshold jump give the sparse diagonal block a band over the levels, and the
 level sources depend on the temperature, coupling the level rows with the
 flow unknowns.  The library takes a band half-width `band` and a coupling
 switch `arrow`; its block-Jacobi factors the band by LU without pivoting and
-the flow unknowns through a 3 x 3 Schur complement, one lane per cell.  All
-checks against the CPU oracle (dense blocks, dense LU)."""
+the flow unknowns through a 3 x 3 Schur complement, one lane per cell.  With
+arrow = 2 the last level is the atom density, coupled to every molecule level
+(a dense atom column and row, the DRa processes of the same passage); the
+block-Jacobi takes them as two more Woodbury terms.  All checks against the
+CPU oracle (dense blocks, dense LU)."""
 import numpy as np
 import pytest
 import torch
@@ -19,7 +22,7 @@ from paper_2403_09198_amd._lib import R1S_ERR_SINGULAR
 
 pytestmark = pytest.mark.gpu
 
-PATTERNS = [(2, False), (4, True), (1, True), (3, False), (8, True)]
+PATTERNS = [(2, False), (4, True), (1, True), (3, False), (8, True), (1, 2), (3, 2)]
 SHAPES = [(16, 16, 8), (1, 1, 1), (5, 3, 2), (7, 5, 61), (3, 4, 62), (2, 3, 125), (3, 2, 200),
           (2, 2, 253), (70, 2, 6)]
 TOL64 = 1e-12
@@ -44,6 +47,8 @@ def _per_cell_rel(z, ref):
 @pytest.mark.parametrize("nx,ny,L", SHAPES)
 @pytest.mark.parametrize("ranks", [(1, 1), (9, 2)], ids=lambda r: f"r{r[0]}_{r[1]}")
 def test_matvec_and_smw_parity(nx, ny, L, band, arrow, ranks):
+    if arrow == 2 and L < 2:
+        pytest.skip("the atom coupling needs a molecule level besides the atom")
     log(f"pattern band={band} arrow={arrow} ranks={ranks} nx={nx} ny={ny} L={L}")
     p, A, M = _setup(nx, ny, L, band, arrow, ranks)
     m, P = L + 3, ranks[0] + 4 * ranks[1]
@@ -69,18 +74,21 @@ def test_matvec_and_smw_parity(nx, ny, L, band, arrow, ranks):
     assert _per_cell_rel(host(M.apply(rd)), zref) <= TOL64
     assert _per_cell_rel(host(M.apply(rd, trans=True)), zreft) <= TOL64
     # float32 factors and arithmetic: the serial band sweeps accumulate about
-    # m (2 band + 1) rounded terms per unknown in well-conditioned blocks
-    tol32s = 8 * (m * (band + 1) + ranks[0] ** 2) * U32
+    # m (2 band + 1) rounded terms per unknown in well-conditioned blocks,
+    # the Woodbury step (rd + 2 terms with the atom) its square
+    pw = ranks[0] + (2 if arrow == 2 else 0)
+    tol32s = 8 * (m * (band + 1) + pw ** 2) * U32
     assert _per_cell_rel(host(M.apply(rd, precision="f32")), zref) <= tol32s
     assert _per_cell_rel(host(M.apply(rd, trans=True, precision="f32")), zreft) <= tol32s
 
 
-@pytest.mark.parametrize("band,L", [(3, 61), (1, 61), (1, 125)])
+@pytest.mark.parametrize("band,L,arrow", [(3, 61, 1), (1, 61, 1), (1, 125, 1), (1, 61, 2),
+                                          (3, 125, 2)])
 @pytest.mark.parametrize("nrhs", [1, 2, 5])
-def test_batched_rhs_match_single(nrhs, band, L):
+def test_batched_rhs_match_single(nrhs, band, L, arrow):
     nx, ny = 9, 5
-    log(f"pattern batches nrhs={nrhs} band={band} L={L}")
-    p, A, M = _setup(nx, ny, L, band, True, (9, 2), seed=2)
+    log(f"pattern batches nrhs={nrhs} band={band} L={L} arrow={arrow}")
+    p, A, M = _setup(nx, ny, L, band, arrow, (9, 2), seed=2)
     x = vec(gen.make_vector(nx, ny, L, nrhs=nrhs, seed=3))
     for name, f in (("J x", lambda v: A.matvec(v)), ("J^T x", lambda v: A.matvec(v, trans=True)),
                     ("M r", lambda v: M.apply(v)), ("M^T r", lambda v: M.apply(v, trans=True))):
@@ -92,9 +100,10 @@ def test_batched_rhs_match_single(nrhs, band, L):
 
 
 @pytest.mark.parametrize("nx,ny,L", [(16, 16, 8), (5, 3, 2), (3, 4, 62), (2, 3, 125)])
-def test_bsr_parity_wide_pattern(nx, ny, L):
-    log(f"bsr parity wide pattern nx={nx} ny={ny} L={L}")
-    p, A, M = _setup(nx, ny, L, 4, True, (9, 2), keep_f32=False, with_trans=False)
+@pytest.mark.parametrize("arrow", [1, 2])
+def test_bsr_parity_wide_pattern(nx, ny, L, arrow):
+    log(f"bsr parity wide pattern nx={nx} ny={ny} L={L} arrow={arrow}")
+    p, A, M = _setup(nx, ny, L, 4, arrow, (9, 2), keep_f32=False, with_trans=False)
     B = r1s.BSRMatrix(A)
     Pl = r1s.DenseLUPreconditioner(B)
     x = gen.make_vector(nx, ny, L, nrhs=2, seed=9)
@@ -104,10 +113,11 @@ def test_bsr_parity_wide_pattern(nx, ny, L):
     assert _per_cell_rel(host(Pl.apply(xd)), block_jacobi_ref(p, nx, ny, L, x)) <= TOL64
 
 
-def test_full_size_sampled_parity_wide_pattern():
+@pytest.mark.parametrize("band,arrow", [(4, 1), (1, 2)])
+def test_full_size_sampled_parity_wide_pattern(band, arrow):
     nx, ny, L = 256, 128, 61
-    log("full-size sampled parity 256x128 L=61 band 4 + coupling, ranks (9, 2)")
-    p, A, M = _setup(nx, ny, L, 4, True, gen.PAPER_RANKS, seed=0, keep_f32=False)
+    log(f"full-size sampled parity 256x128 L=61 band {band} arrow {arrow}, ranks (9, 2)")
+    p, A, M = _setup(nx, ny, L, band, arrow, gen.PAPER_RANKS, seed=0, keep_f32=False)
     x = gen.make_vector(nx, ny, L, seed=0)
     xd = vec(x)
     cells = sample_cells(nx, ny)
@@ -123,10 +133,11 @@ def test_full_size_sampled_parity_wide_pattern():
     assert _per_cell_rel(zt, block_jacobi_ref(p, nx, ny, L, x, cells, trans=True)) <= TOL64
 
 
-def test_gmres_wide_pattern():
+@pytest.mark.parametrize("arrow", [1, 2])
+def test_gmres_wide_pattern(arrow):
     nx, ny, L = 16, 16, 8
-    log("gmres wide pattern")
-    p, A, M = _setup(nx, ny, L, 3, True, gen.PAPER_RANKS, seed=3)
+    log(f"gmres wide pattern arrow={arrow}")
+    p, A, M = _setup(nx, ny, L, 3, arrow, gen.PAPER_RANKS, seed=3)
     b = gen.make_rhs(nx, ny, L, nrhs=2, seed=3)
     J = ops.dense_matrix(p, nx, ny, L)
     for kw in (dict(), dict(trans=True), dict(mode="mixed")):
@@ -137,7 +148,8 @@ def test_gmres_wide_pattern():
             assert relnorm(host(res.x)[r].ravel(), np.linalg.solve(Jm, b[r].ravel())) <= 1e-10, kw
 
 
-@pytest.mark.parametrize("band,arrow", [(3, True), (2, False), (1, True)], ids=lambda v: str(v))
+@pytest.mark.parametrize("band,arrow", [(3, True), (2, False), (1, True), (1, 2), (3, 2)],
+                         ids=lambda v: str(v))
 def test_grad_kernel_matches_oracle(band, arrow):
     nx, ny, L, nrhs = 5, 4, 7, 3
     log(f"grad kernel band={band} arrow={arrow}")
@@ -155,11 +167,12 @@ def test_grad_kernel_matches_oracle(band, arrow):
         assert relnorm(host(g[k]), ref[k]) <= 1e-13, k
 
 
-def test_adjoint_solve_wide_pattern():
+@pytest.mark.parametrize("arrow", [1, 2])
+def test_adjoint_solve_wide_pattern(arrow):
     nx, ny, L, nrhs = 5, 4, 6, 2
-    log("adjoint solve wide pattern")
-    kw = dict(ranks=(3, 1), band=3, arrow=True)
-    p = gen.make_problem(nx, ny, L, seed=2, r_diag=3, r_off=1, band=3, arrow=True)
+    log(f"adjoint solve wide pattern arrow={arrow}")
+    kw = dict(ranks=(3, 1), band=3, arrow=arrow)
+    p = gen.make_problem(nx, ny, L, seed=2, r_diag=3, r_off=1, band=3, arrow=arrow)
     b = gen.make_rhs(nx, ny, L, nrhs=nrhs, seed=2)
     w = gen.make_loss_weights(nx, ny, L, nrhs=nrhs, seed=2)
     keys = r1s.FIELDS + r1s.PATTERN_FIELDS
@@ -221,3 +234,32 @@ def test_pattern_arrays_are_checked():
     m, N = L + 3, nx * ny
     diag_block = (3 * m - 2) + 2 * (L - 2) + 2 * (L - 3) + 6 * L
     assert s["structured_values"] == N * diag_block + (B - N) * m + 2 * m * B
+
+
+@pytest.mark.parametrize("band", [1, 3])
+def test_zero_atom_row_is_reported(band):
+    # the atom row of cell c zeroed with its diagonal, flow couplings and the
+    # pairs' entries: D_c has a zero row, and A0 (the block without the
+    # atom's column and row) a zero pivot at the atom
+    nx, ny, L = 4, 3, 6
+    p = gen.make_problem(nx, ny, L, seed=1, band=band, arrow=2, r_diag=1, r_off=1)
+    c, a = 7, L - 1
+    p["s_diag"][c, a] = 0.0
+    p["s_flow_lev"][c, 3] = 0.0
+    p["s_lev_flow"][c, :3, a] = 0.0
+    p["u"][c, :, a] = 0.0  # no pair reaches row a
+    A = r1s.R1Matrix(nx, ny, L, to_dev(p), band=band, arrow=2)
+    with pytest.raises(r1s.R1SError) as ei:
+        r1s.SMWPreconditioner(A)
+    assert ei.value.code == R1S_ERR_SINGULAR and "cell 7" in str(ei.value)
+
+
+def test_atom_pattern_storage_counts():
+    nx, ny, L = 3, 2, 9
+    for band in (1, 3):
+        p = gen.make_problem(nx, ny, L, seed=0, band=band, arrow=2)
+        A = r1s.R1Matrix(nx, ny, L, to_dev(p), band=band, arrow=2)
+        q = gen.make_problem(nx, ny, L, seed=0, band=band, arrow=1)
+        B = r1s.R1Matrix(nx, ny, L, to_dev(q), band=band, arrow=1)
+        extra = A.storage()["structured_values"] - B.storage()["structured_values"]
+        assert extra == nx * ny * 2 * (L - 1 - band)
