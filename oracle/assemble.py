@@ -17,8 +17,9 @@ each molecule level's row depends on its own density, the atom density and
 the temperature, and the atom's row on every level): a dense atom column
 S[k][a] and atom row S[a][k] over the molecule levels k < a are added to the
 block (the generator draws the band entries that reach the atom as zero, so
-every entry has one source; the block is the sum of its parts).  S_{c,d} for
-d != C is diagonal.
+every entry has one source; the block is the sum of its parts).  A general
+pattern shared by every cell (explicit CSR pattern, values s_cc in entry
+order) replaces all of these.  S_{c,d} for d != C is diagonal.
 
 The result is stored in the paper's BSR format (section 5.1): block_indptr,
 block_indices (ascending block columns within a block row) and a 3-D data
@@ -34,6 +35,14 @@ FLOW_PAIRS = ((0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1))
 def diagonal_sparse_block(p, c: int, L: int) -> np.ndarray:
     """S_{c,C} as a dense m x m array (sparse pattern, zeros elsewhere)."""
     m = L + 3
+    ep = mesh.explicit_pattern(p)
+    if ep is not None:  # a general pattern: entry e of row i sits at column indices[e]
+        indptr, indices = ep
+        A = np.zeros((m, m))
+        for i in range(m):
+            for e in range(indptr[i], indptr[i + 1]):
+                A[i, indices[e]] = p["s_cc"][c, e]
+        return A
     A = np.zeros((m, m))
     A[np.arange(m), np.arange(m)] = p["s_diag"][c]
     for k in range(L - 1):

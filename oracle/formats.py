@@ -165,9 +165,23 @@ def structured_csr(p, nx, ny, L):
     per-cell pattern directly (no dense block is formed)."""
     N, m = nx * ny, L + 3
     data, indices, indptr = [], [], [0]
+    ep = mesh.explicit_pattern(p)
     for c in range(N):
         for k in range(m):
             row = {}
+            if ep is not None:  # a general pattern: row k's entries as listed
+                pi, pj = ep
+                for e in range(pi[k], pi[k + 1]):
+                    row[c * m + int(pj[e])] = p["s_cc"][c, e]
+                for d in (mesh.S, mesh.W, mesh.E, mesh.N):
+                    nb = mesh.neighbour(nx, ny, c, d)
+                    if nb >= 0:
+                        row[nb * m + k] = p["s_nbr"][c, mesh.NBR_SLOT[d], k]
+                for col in sorted(row):
+                    data.append(row[col])
+                    indices.append(col)
+                indptr.append(len(data))
+                continue
             # diagonal block pattern
             row[c * m + k] = p["s_diag"][c, k]
             if k < L:

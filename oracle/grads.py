@@ -29,8 +29,11 @@ def structured_grads(p, nx, ny, L, lam, x):
         lam, x = lam[None], x[None]
     N, m = nx * ny, L + 3
     band, arrow = mesh.pattern(p)
+    ep = mesh.explicit_pattern(p)
     keys = ("s_diag", "s_sub", "s_sup", "s_flow", "s_nbr", "u", "v")
-    if (band, arrow) != (1, 0):
+    if ep is not None:
+        keys = ("s_cc", "s_nbr", "u", "v")
+    elif (band, arrow) != (1, 0):
         keys = keys + ("s_band", "s_lev_flow", "s_flow_lev")
     g = {k: np.zeros_like(p[k]) for k in keys}
     for c in range(N):
@@ -43,7 +46,12 @@ def structured_grads(p, nx, ny, L, lam, x):
             for q in range(a, a + cnt):
                 g["u"][c, q] = G @ p["v"][c, q]
                 g["v"][c, q] = G.T @ p["u"][c, q]
-            if d == mesh.C:
+            if d == mesh.C and ep is not None:  # entry e of row i: G[i, indices[e]]
+                pi, pj = ep
+                for i in range(m):
+                    for e in range(pi[i], pi[i + 1]):
+                        g["s_cc"][c, e] = G[i, pj[e]]
+            elif d == mesh.C:
                 g["s_diag"][c] = np.diag(G)
                 for k in range(L - 1):
                     g["s_sub"][c, k] = G[k + 1, k]

@@ -67,10 +67,21 @@ def pattern(p):
     Jacobian"; arrow = 2 adds the atom density, the last level, coupled to
     every level by the DRa processes).  Default (1, 0): tridiagonal band, no
     coupling."""
+    if "pat_indptr" in p:
+        return 0, 0  # explicit pattern: no structured band (see explicit_pattern)
     if "pattern" not in p:
         return 1, 0
     band, arrow = (int(v) for v in p["pattern"])
     return band, arrow
+
+
+def explicit_pattern(p):
+    """(indptr, indices) of a general pattern of S_cc shared by every cell
+    (values s_cc [N][nnz] in entry order), or None for the structured
+    layouts."""
+    if "pat_indptr" not in p:
+        return None
+    return p["pat_indptr"], p["pat_indices"]
 
 
 def opposite(d: int) -> int:

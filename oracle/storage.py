@@ -43,3 +43,13 @@ def structured_values(nx: int, ny: int, m: int, r_diag: int = 1, r_off: int = 1,
     if arrow == 2:
         diag_block += 2 * max(L - 1 - band, 0)
     return N * diag_block + (B - N) * m + (N * r_diag + (B - N) * r_off) * 2 * m
+
+
+def explicit_pattern_values(nx: int, ny: int, m: int, nnz: int, r_diag: int = 1,
+                            r_off: int = 1) -> int:
+    """Stored values with a general pattern of nnz entries (diagonal
+    included) in every diagonal block: N nnz, plus the neighbour diagonals
+    and the pairs as for the structured layouts."""
+    N = nx * ny
+    B = n_blocks(nx, ny)
+    return N * nnz + (B - N) * m + 2 * m * (N * r_diag + (B - N) * r_off)

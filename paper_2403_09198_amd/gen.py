@@ -229,6 +229,116 @@ def make_vector(nx: int, ny: int, L: int, nrhs: int = 1, seed: int = 0) -> np.nd
     return rng.standard_normal((nrhs, nx * ny, L + 3))
 
 
+# -------------------------------------------------- explicit S_cc pattern --
+# A general sparsity pattern of the diagonal block, shared by every cell
+# (section 4, "Temporal Source Jacobian": the pattern follows from the
+# kinetic processes kept, e.g. a Delta-v band, DRa columns, flow coupling):
+# pat_indptr [m+1], pat_indices [nnz] (int32, CSR; each row lists its
+# diagonal once, columns in any order) and s_cc [N][nnz], the values in the
+# pattern's entry order.  The neighbour blocks and the pairs are as for the
+# structured layouts (s_nbr, u, v, "ranks").
+PATTERN_PROBLEM_FIELDS = ("s_cc", "s_nbr", "u", "v")
+
+
+def layout_pattern(L: int, band: int = 1, arrow: int = 0):
+    """The CSR pattern of S_cc of a structured layout (band, arrow): the
+    diagonal, the level band, the flow corner, the level/flow coupling and,
+    with arrow = 2, the atom's column and row; rows in ascending columns."""
+    m = L + 3
+    rows = [set([i]) for i in range(m)]
+    for k in range(L):
+        for j in range(1, band + 1):
+            if k - j >= 0:
+                rows[k].add(k - j)
+            if k + j < L:
+                rows[k].add(k + j)
+    for i in range(3):
+        for j in range(3):
+            rows[L + i].add(L + j)
+    if arrow:
+        for k in range(L):
+            for i in range(3):
+                rows[k].add(L + i)
+                rows[L + i].add(k)
+    if arrow == 2:
+        a = L - 1
+        for k in range(a):
+            rows[k].add(a)
+            rows[a].add(k)
+    indptr = np.zeros(m + 1, dtype=np.int32)
+    indices = []
+    for i in range(m):
+        cols = sorted(rows[i])
+        indices += cols
+        indptr[i + 1] = indptr[i] + len(cols)
+    return indptr, np.array(indices, dtype=np.int32)
+
+
+def random_pattern(m: int, per_row: int = 3, dense_rows=(), dense_cols=(), seed: int = 0,
+                   shuffle: bool = True):
+    """A random pattern: the diagonal, per_row random off-diagonal columns
+    in every row, full rows `dense_rows` and full columns `dense_cols`; each
+    row's entries in random order when `shuffle`."""
+    rng = np.random.default_rng(seed)
+    rows = [set([i]) for i in range(m)]
+    for i in range(m):
+        others = [j for j in range(m) if j != i]
+        for j in rng.choice(others, size=min(per_row, m - 1), replace=False):
+            rows[i].add(int(j))
+    for i in dense_rows:
+        rows[i] |= set(range(m))
+    for j in dense_cols:
+        for i in range(m):
+            rows[i].add(j)
+    indptr = np.zeros(m + 1, dtype=np.int32)
+    indices = []
+    for i in range(m):
+        cols = sorted(rows[i])
+        if shuffle:
+            cols = list(rng.permutation(cols))
+        indices += [int(c) for c in cols]
+        indptr[i + 1] = indptr[i] + len(cols)
+    return indptr, np.array(indices, dtype=np.int32)
+
+
+def make_pattern_problem(nx: int, ny: int, L: int, indptr, indices, seed: int = 0,
+                         inv_dt: float = 20.0, r_diag: int = 1,
+                         r_off: int = 1) -> Dict[str, np.ndarray]:
+    """Values of a Jacobian whose diagonal blocks share the pattern (indptr,
+    indices): diagonal entries inv_dt + 10 |N(0,1)|, the off-diagonal ones of
+    a row with k of them N(0,1) min(1, 4 / k) (row sums of |S| stay about 3,
+    so the block stays dominant), then s_nbr ~ U(-1, 0), u, v ~ N(0, 0.1^2)
+    as in make_problem."""
+    indptr = np.asarray(indptr, dtype=np.int32)
+    indices = np.asarray(indices, dtype=np.int32)
+    N, m = nx * ny, L + 3
+    if len(indptr) != m + 1:
+        raise ValueError("pattern must have m + 1 = L + 4 row pointers")
+    P = r_diag + 4 * r_off
+    rng = np.random.default_rng(seed)
+    nnz = int(indptr[-1])
+    row = np.repeat(np.arange(m), np.diff(indptr))
+    diag = indices == row
+    off_count = np.diff(indptr) - 1
+    scale = np.minimum(1.0, 4.0 / np.maximum(off_count, 1))[row]
+    z = rng.standard_normal((N, nnz))
+    p = {"pat_indptr": indptr.copy(), "pat_indices": indices.copy()}
+    p["s_cc"] = np.where(diag[None, :], inv_dt + 10.0 * np.abs(z), z * scale[None, :])
+    p["s_nbr"] = rng.uniform(-1.0, 0.0, size=(N, 4, m))
+    p["u"] = 0.1 * rng.standard_normal((N, P, m))
+    p["v"] = 0.1 * rng.standard_normal((N, P, m))
+    ex = block_exists(nx, ny)
+    for j, d in enumerate(NBR_DIRS):
+        p["s_nbr"][~ex[:, d], j, :] = 0.0
+    for d, (a, cnt) in enumerate(pair_slots(r_diag, r_off)):
+        p["u"][~ex[:, d], a:a + cnt, :] = 0.0
+        p["v"][~ex[:, d], a:a + cnt, :] = 0.0
+    for k in PATTERN_PROBLEM_FIELDS:
+        p[k] = np.ascontiguousarray(p[k], dtype=np.float64)
+    p["ranks"] = np.array([r_diag, r_off])
+    return p
+
+
 def workload_problem(w: Workload) -> Dict[str, np.ndarray]:
     return make_problem(w.nx, w.ny, w.L, seed=w.seed, inv_dt=w.inv_dt)
 
