@@ -181,6 +181,25 @@ typedef struct {
   const double* v_off;
 } r1s_graph_inputs;
 
+/* Inputs with a general pattern of S_{c,C} (r1s_mat_init_pattern): s_cc
+ * [N][nnz], the values of the pattern's entries in its entry order; s_nbr,
+ * u, v as in r1s_inputs. */
+typedef struct {
+  const double* s_cc;
+  const double* s_nbr;
+  const double* u;
+  const double* v;
+} r1s_pattern_inputs;
+
+/* Gradient outputs with a general pattern, same shapes as
+ * r1s_pattern_inputs. */
+typedef struct {
+  double* s_cc;
+  double* s_nbr;
+  double* u;
+  double* v;
+} r1s_pattern_grads;
+
 /* Gradient outputs on a general mesh, same shapes as r1s_graph_inputs. */
 typedef struct {
   double* s_diag;
@@ -299,6 +318,38 @@ int r1s_mat_init_graph(int n_cells, int L, const r1s_layout* layout,
                        size_t mem_bytes, void* stream, r1s_mat* out);
 /* New values for a general-mesh matrix (same structure). */
 int r1s_mat_update_graph(r1s_mat A, const r1s_graph_inputs* in, void* stream);
+
+/* General pattern of the diagonal block (section 4, Temporal Source
+ * Jacobian: the nonzeros of S_{c,C} follow from the kinetic processes kept,
+ * e.g. a Delta-v band, the DRa columns of the atom density and T, the flow
+ * coupling, and are the same in every cell).  pattern_indptr [m + 1] and
+ * pattern_indices [nnz] (host int32, CSR over the m = L + 3 unknowns of a
+ * cell; each row lists its diagonal once, columns in any order) describe
+ * S_{c,C} of every cell on the structured nx x ny mesh; its values come in
+ * r1s_pattern_inputs.  layout gives r_diag and r_off; its band must be 1
+ * and arrow 0 (the pattern replaces both).  The library copies what it
+ * needs; the arrays may be freed after the call.
+ *
+ * The host analyses the pattern once: for the products it stores S_{c,C}
+ * as its diagonal, ELL rows (at most 16 entries per row and per column)
+ * and at most 8 dense rows / columns, choosing the split that stores the
+ * fewest rows; for the block-Jacobi it orders the unknowns by minimum degree
+ * and finds the fill of LU without pivoting, which every cell's numeric
+ * factorisation (r1s_prec_setup) then follows, one lane per cell.  Every
+ * other call (matvec, residual, preconditioner, BSR copy, GMRES) takes the
+ * handle like a structured one.  Errors: R1S_ERR_ARG for a malformed
+ * pattern (the message names the row) or band / arrow not 1 / 0,
+ * R1S_ERR_UNSUPPORTED for a pattern that does not fit those limits, as for
+ * r1s_mat_size / r1s_mat_init otherwise. */
+int r1s_mat_size_pattern(int nx, int ny, int L, const r1s_layout* layout,
+                         const int* pattern_indptr, const int* pattern_indices, int flags,
+                         size_t* bytes);
+int r1s_mat_init_pattern(int nx, int ny, int L, const r1s_layout* layout,
+                         const int* pattern_indptr, const int* pattern_indices, int flags,
+                         const r1s_pattern_inputs* in, void* mem, size_t mem_bytes,
+                         void* stream, r1s_mat* out);
+/* New values for a general-pattern matrix (same pattern). */
+int r1s_mat_update_pattern(r1s_mat A, const r1s_pattern_inputs* in, void* stream);
 
 /* Stored-value counts of the structured and dense-block representations
  * (section 3, Jacobian Complexity: N_A = sum m^2 (N_e + 1)). */
@@ -429,6 +480,11 @@ int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double* x,
  * for no block: every listed block exists). */
 int r1s_grad_graph(r1s_mat A, int nrhs, const double* lambda, const double* x,
                    const r1s_graph_grads* out, void* stream);
+
+/* The same gradients for a general-pattern matrix: dLoss/ds_cc[c][e] =
+ * -sum_r lambda_r[c][i] x_r[c][j] for entry e = (i, j) of the pattern. */
+int r1s_grad_pattern(r1s_mat A, int nrhs, const double* lambda, const double* x,
+                     const r1s_pattern_grads* out, void* stream);
 
 #ifdef __cplusplus
 }

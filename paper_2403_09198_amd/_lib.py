@@ -63,6 +63,17 @@ class GraphGrads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in GRAPH_INPUT_FIELDS]
 
 
+PATTERN_INPUT_FIELDS = ("s_cc", "s_nbr", "u", "v")
+
+
+class PatternInputs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in PATTERN_INPUT_FIELDS]
+
+
+class PatternGrads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in PATTERN_INPUT_FIELDS]
+
+
 class Storage(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_cells", "n_blocks", "m", "structured_values", "structured_padded", "bsr_values",
@@ -97,6 +108,10 @@ SIGNATURES = {
     "r1s_mat_init_graph": (_I, [_I, _I, C.POINTER(Layout), _VP, _VP, _I, C.POINTER(GraphInputs),
                                 _VP, _SZ, _VP, C.POINTER(_VP)]),
     "r1s_mat_update_graph": (_I, [_VP, C.POINTER(GraphInputs), _VP]),
+    "r1s_mat_size_pattern": (_I, [_I, _I, _I, C.POINTER(Layout), _VP, _VP, _I, _PSZ]),
+    "r1s_mat_init_pattern": (_I, [_I, _I, _I, C.POINTER(Layout), _VP, _VP, _I,
+                                  C.POINTER(PatternInputs), _VP, _SZ, _VP, C.POINTER(_VP)]),
+    "r1s_mat_update_pattern": (_I, [_VP, C.POINTER(PatternInputs), _VP]),
     "r1s_mat_storage": (_I, [_VP, C.POINTER(Storage)]),
     "r1s_matvec": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP]),
     "r1s_residual": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
@@ -119,6 +134,7 @@ SIGNATURES = {
                                C.POINTER(GmresStats), _VP]),
     "r1s_grad": (_I, [_VP, _I, _VP, _VP, C.POINTER(Grads), _VP]),
     "r1s_grad_graph": (_I, [_VP, _I, _VP, _VP, C.POINTER(GraphGrads), _VP]),
+    "r1s_grad_pattern": (_I, [_VP, _I, _VP, _VP, C.POINTER(PatternGrads), _VP]),
 }
 
 _lib = None

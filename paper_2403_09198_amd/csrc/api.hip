@@ -15,6 +15,9 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <memory>
+
+#include "pattern.hpp"
 #include "r1s.h"
 #include "r1s_kernels.hpp"
 
@@ -120,6 +123,9 @@ struct r1s_mat_s {
   // neighbour tables carved from the matrix buffer
   std::vector<int> indptr, indices;
   int *d_nbr, *d_tslot, *d_offb;
+  // general pattern of S_cc: the host plan and its device tables
+  std::shared_ptr<PatternPlan> plan;
+  int* d_pat;
 };
 
 // Blocks of the Jacobian: 5N - 2nx - 2ny on the structured mesh, the
@@ -209,6 +215,7 @@ extern "C" int r1s_mat_init(int nx, int ny, int L, const r1s_layout* layout, int
 extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
   if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
   if (A->g.graph) return fail(R1S_ERR_ARG, "general-mesh matrix: use r1s_mat_update_graph");
+  if (A->g.pat) return fail(R1S_ERR_ARG, "general-pattern matrix: use r1s_mat_update_pattern");
   if (int e = check_inputs(in, A->g)) return e;
   if (int e = do_pack(A, in, as_stream(stream))) return e;
   HIP_TRY(hipStreamSynchronize(as_stream(stream)));
@@ -217,6 +224,137 @@ extern "C" int r1s_mat_update(r1s_mat A, const r1s_inputs* in, void* stream) {
 
 extern "C" int r1s_mat_destroy(r1s_mat A) {
   delete A;
+  return R1S_OK;
+}
+
+// ---------------------------------------------------- general pattern ----
+// A structured mesh whose diagonal blocks share a general pattern of S_cc.
+static Mesh pattern_mesh(int nx, int ny, int L, const r1s_layout& lay, const PatternPlan& pl) {
+  r1s_layout base = lay;
+  base.band = 1;
+  base.arrow = 0;
+  Mesh g = make_mesh(nx, ny, L, base);
+  g.pat = 1;
+  g.pnnz = pl.nnz;
+  g.ne = pl.ne;
+  g.net = pl.net;
+  g.ns = pl.ns;
+  for (int t = 0; t < PAT_SLOTS_MAX; ++t) g.px[t] = pl.px[t];
+  g.fb = F_BAND;
+  g.fa = g.fb + g.ne;
+  g.fu = g.fa + 2 * g.ns;
+  g.F = g.fu + 2 * g.P;
+  return g;
+}
+
+static int pattern_prepare(int nx, int ny, int L, const r1s_layout* layout,
+                           const int* pattern_indptr, const int* pattern_indices, int flags,
+                           PatternPlan* pl, Mesh* g) {
+  if (int e = check_dims(nx, ny, L)) return e;
+  const r1s_layout lay = layout_or_default(layout);
+  if (int e = check_layout(lay)) return e;
+  if (lay.band != 1 || lay.arrow != 0)
+    return fail(R1S_ERR_ARG, "a general pattern replaces band and arrow (need 1 and 0, got %d, %d)",
+                lay.band, lay.arrow);
+  if (flags & ~R1S_KEEP_F32) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
+  char msg[256] = "";
+  if (int e = build_pattern_plan(L + 3, pattern_indptr, pattern_indices, pl, msg, sizeof msg))
+    return fail(e, "%s", msg);
+  *g = pattern_mesh(nx, ny, L, lay, *pl);
+  return R1S_OK;
+}
+
+static void pattern_layout(Carver& cv, const Mesh& g, const PatternPlan& pl, int flags,
+                           r1s_mat_s* A) {
+  mat_layout(cv, g, flags, &A->rec64, &A->rec32);
+  std::vector<int> tab;
+  Mesh tmp = g;
+  pattern_mat_tables(pl, tab, nullptr, &tmp);
+  A->d_pat = cv.take<int>(tab.size());
+}
+
+extern "C" int r1s_mat_size_pattern(int nx, int ny, int L, const r1s_layout* layout,
+                                    const int* pattern_indptr, const int* pattern_indices,
+                                    int flags, size_t* bytes) {
+  if (!bytes) return fail(R1S_ERR_ARG, "bytes is NULL");
+  PatternPlan pl;
+  Mesh g;
+  if (int e = pattern_prepare(nx, ny, L, layout, pattern_indptr, pattern_indices, flags, &pl, &g))
+    return e;
+  Carver cv(nullptr);
+  r1s_mat_s tmp;
+  pattern_layout(cv, g, pl, flags, &tmp);
+  *bytes = cv.off;
+  return R1S_OK;
+}
+
+static int check_pattern_inputs(const r1s_pattern_inputs* in) {
+  if (!in) return fail(R1S_ERR_ARG, "inputs is NULL");
+  const void* ps[4] = {in->s_cc, in->s_nbr, in->u, in->v};
+  const char* names[4] = {"s_cc", "s_nbr", "u", "v"};
+  for (int i = 0; i < 4; ++i) {
+    if (!ps[i]) return fail(R1S_ERR_ARG, "input %s is NULL", names[i]);
+    if (!aligned(ps[i], 8)) return fail(R1S_ERR_ARG, "input %s is not 8-byte aligned", names[i]);
+  }
+  return R1S_OK;
+}
+
+static int do_pack_pattern(r1s_mat A, const r1s_pattern_inputs* in, hipStream_t s) {
+  PackIn p{};
+  p.s_nbr = in->s_nbr;
+  p.u = in->u;
+  p.v = in->v;
+  p.s_cc = in->s_cc;
+  HIP_TRY(launch_pack(A->g, p, A->rec64, A->rec32, s));
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_init_pattern(int nx, int ny, int L, const r1s_layout* layout,
+                                    const int* pattern_indptr, const int* pattern_indices,
+                                    int flags, const r1s_pattern_inputs* in, void* mem,
+                                    size_t mem_bytes, void* stream, r1s_mat* out) {
+  size_t need;
+  if (int e = r1s_mat_size_pattern(nx, ny, L, layout, pattern_indptr, pattern_indices, flags, &need))
+    return e;
+  if (!out) return fail(R1S_ERR_ARG, "out is NULL");
+  if (int e = check_pattern_inputs(in)) return e;
+  if (!mem || !aligned(mem, 256)) return fail(R1S_ERR_ARG, "mem is NULL or not 256-byte aligned");
+  if (mem_bytes < need) return fail(R1S_ERR_ARG, "mem_bytes %zu < required %zu", mem_bytes, need);
+  auto pl = std::make_shared<PatternPlan>();
+  Mesh g;
+  pattern_prepare(nx, ny, L, layout, pattern_indptr, pattern_indices, flags, pl.get(), &g);
+  r1s_mat A = new (std::nothrow) r1s_mat_s();
+  if (!A) return fail(R1S_ERR_ALLOC, "host allocation failed");
+  A->flags = flags;
+  A->plan = pl;
+  Carver cv(mem);
+  pattern_layout(cv, g, *pl, flags, A);
+  std::vector<int> tab;
+  pattern_mat_tables(*pl, tab, A->d_pat, &g);
+  A->g = g;
+  hipStream_t s = as_stream(stream);
+  int rc = R1S_OK;
+  do {
+    hipError_t e;
+    if ((e = hipMemcpyAsync(A->d_pat, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "copy: %s", hipGetErrorString(e)); break; }
+    if ((rc = do_pack_pattern(A, in, s))) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "pack: %s", hipGetErrorString(e)); break; }
+  } while (0);
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    delete A;
+    return rc;
+  }
+  *out = A;
+  return R1S_OK;
+}
+
+extern "C" int r1s_mat_update_pattern(r1s_mat A, const r1s_pattern_inputs* in, void* stream) {
+  if (!A) return fail(R1S_ERR_ARG, "matrix handle is NULL");
+  if (!A->g.pat) return fail(R1S_ERR_ARG, "not a general-pattern matrix: use r1s_mat_update");
+  if (int e = check_pattern_inputs(in)) return e;
+  if (int e = do_pack_pattern(A, in, as_stream(stream))) return e;
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
   return R1S_OK;
 }
 
@@ -395,6 +533,7 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   if (g.arrow) diag_block += 6 * L;
   // the atom's column and row, less the positions the band already holds
   if (g.arrow == 2) diag_block += 2 * std::max(L - 1 - g.band, 0LL);
+  if (g.pat) diag_block = g.pnnz;  // a general pattern: its entries
   out->structured_values = N * diag_block + (B - N) * m + 2 * pairs * m;
   out->structured_padded = N * (long long)g.F * g.mp;
   out->bsr_values = B * m * m;
@@ -405,7 +544,9 @@ extern "C" int r1s_mat_storage(r1s_mat A, r1s_storage* out) {
   // A0 factors (as many values as S_cc; with the wide pattern the band LU
   // factors, the coupling factors and the 3 x 3 Schur inverse), W and V,
   // C^{-1}; r read, z written
-  const long long a0 = wide_pattern(g) ? (2 * g.band + 1 + (g.arrow ? 6 : 0)) * L + 9 : 3 * m - 2;
+  const long long a0 = g.pat ? (long long)A->plan->nnzF
+                             : wide_pattern(g) ? (2 * g.band + 1 + (g.arrow ? 6 : 0)) * L + 9
+                                               : 3 * m - 2;
   const long long pw = smw_pairs(g);  // with the atom: two more Woodbury terms
   out->smw_apply_bytes = 8 * N * (a0 + 2 * pw * m + pw * pw) + 8 * 2 * N * m;
   return R1S_OK;
@@ -463,15 +604,30 @@ struct r1s_prec_s {
   double *bf, *s3i, *wv, *wvT, *cinv;
   float *bf32, *s3i32, *wv32, *wvT32, *cinv32;
   long long n_bf, n_s3i, n_wv, n_cinv;  // element counts
+  // general pattern: the LU position tables (device, in this buffer); the
+  // band fields above hold its factors (s3i unused)
+  PatLU plu;
+  int* d_lu;
+  long long n_lu;
   // BSR dense LU
   double* lu;
   int* piv;
 };
 
-static void prec_layout(Carver& cv, const Mesh& g, int flags, r1s_prec_s* P) {
+static void prec_layout(Carver& cv, const r1s_mat_s* A, int flags, r1s_prec_s* P) {
+  const Mesh& g = A->g;
   const bool f32 = flags & R1S_KEEP_F32, tr = flags & R1S_WITH_TRANS;
   if (band_walk(g)) {
-    band_prec_counts(g, &P->n_bf, &P->n_s3i, &P->n_wv, &P->n_cinv);
+    if (g.pat) {
+      pattern_prec_counts(g, A->plan->nnzF, &P->n_bf, &P->n_wv, &P->n_cinv);
+      P->n_s3i = 0;
+      std::vector<int> tab;
+      pattern_lu_tables(*A->plan, tab, nullptr, &P->plu);
+      P->n_lu = (long long)tab.size();
+      P->d_lu = cv.take<int>(tab.size());
+    } else {
+      band_prec_counts(g, &P->n_bf, &P->n_s3i, &P->n_wv, &P->n_cinv);
+    }
     P->bf = cv.take<double>(P->n_bf);
     P->s3i = cv.take<double>(P->n_s3i);
     P->wv = cv.take<double>(P->n_wv);
@@ -504,7 +660,7 @@ extern "C" int r1s_prec_size(r1s_mat A, int flags, size_t* bytes) {
   if (flags & ~(R1S_KEEP_F32 | R1S_WITH_TRANS)) return fail(R1S_ERR_ARG, "unknown flags 0x%x", flags);
   Carver cv(nullptr);
   r1s_prec_s tmp = {};
-  prec_layout(cv, A->g, flags, &tmp);
+  prec_layout(cv, A, flags, &tmp);
   *bytes = cv.off;
   return R1S_OK;
 }
@@ -528,21 +684,28 @@ extern "C" int r1s_prec_setup(r1s_mat A, int flags, void* mem, size_t mem_bytes,
   P->flags = flags;
   P->g = A->g;
   Carver cv(mem);
-  prec_layout(cv, A->g, flags, P);
+  prec_layout(cv, A, flags, P);
   hipStream_t s = as_stream(stream);
   int st = 0x7fffffff;
   int rc = R1S_OK;
+  std::vector<int> lu_tab;  // host copy of a general pattern's LU tables, read by an async copy
   do {
     hipError_t e;
     if ((e = launch_fill_int(P->status, 0x7fffffff, 1, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "fill: %s", hipGetErrorString(e)); break; }
     if (band_walk(A->g)) {
-      if ((e = launch_band_setup(A->g, A->rec64, P->bf, P->s3i, P->wv, P->wvT, P->cinv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "band setup: %s", hipGetErrorString(e)); break; }
+      if (A->g.pat) {
+        // the LU tables next to the factors (a copy from pageable memory has
+        // taken the data when it returns)
+        pattern_lu_tables(*A->plan, lu_tab, P->d_lu, &P->plu);
+        if ((e = hipMemcpyAsync(P->d_lu, lu_tab.data(), lu_tab.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "copy: %s", hipGetErrorString(e)); break; }
+        if ((e = launch_pattern_setup(A->g, P->plu, A->rec64, P->bf, P->wv, P->wvT, P->cinv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "pattern setup: %s", hipGetErrorString(e)); break; }
+      } else if ((e = launch_band_setup(A->g, A->rec64, P->bf, P->s3i, P->wv, P->wvT, P->cinv, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "band setup: %s", hipGetErrorString(e)); break; }
       if (P->bf32) {
         const double* src[5] = {P->bf, P->s3i, P->wv, P->wvT, P->cinv};
         float* dst[5] = {P->bf32, P->s3i32, P->wv32, P->wvT32, P->cinv32};
         const long long cnt[5] = {P->n_bf, P->n_s3i, P->n_wv, P->n_wv, P->n_cinv};
         for (int i = 0; i < 5 && e == hipSuccess; ++i)
-          if (dst[i]) e = launch_cast_f32(src[i], dst[i], cnt[i], s);
+          if (dst[i] && cnt[i] > 0) e = launch_cast_f32(src[i], dst[i], cnt[i], s);
         if (e != hipSuccess) { rc = fail(R1S_ERR_HIP, "cast: %s", hipGetErrorString(e)); break; }
       }
     } else if ((e = launch_smw_setup(A->g, A->rec64, P->facF, P->facT, P->invC, P->status, s)) != hipSuccess) { rc = fail(R1S_ERR_HIP, "smw setup: %s", hipGetErrorString(e)); break; }
@@ -588,6 +751,12 @@ extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, co
     if (f32 && !M->bf32) return fail(R1S_ERR_ARG, "float32 apply needs R1S_KEEP_F32 at setup");
     const void* w = f32 ? (trans ? (const void*)M->wvT32 : (const void*)M->wv32)
                         : (trans ? (const void*)M->wvT : (const void*)M->wv);
+    if (M->g.pat) {
+      HIP_TRY(launch_pattern_apply(M->g, M->plu, f32 ? (const void*)M->bf32 : (const void*)M->bf, w,
+                                   f32 ? (const void*)M->cinv32 : (const void*)M->cinv, f32,
+                                   trans != 0, r, z, nrhs, s));
+      return R1S_OK;
+    }
     HIP_TRY(launch_band_apply(M->g, f32 ? (const void*)M->bf32 : (const void*)M->bf,
                               f32 ? (const void*)M->s3i32 : (const void*)M->s3i, w,
                               f32 ? (const void*)M->cinv32 : (const void*)M->cinv, f32, trans != 0,
@@ -608,7 +777,8 @@ extern "C" int r1s_prec_apply(r1s_prec M, int precision, int trans, int nrhs, co
 
 static bool same_layout(const Mesh& a, const Mesh& b) {
   return a.nx == b.nx && a.ny == b.ny && a.N == b.N && a.L == b.L && a.m == b.m && a.rd == b.rd &&
-         a.ro == b.ro && a.band == b.band && a.arrow == b.arrow && a.graph == b.graph;
+         a.ro == b.ro && a.band == b.band && a.arrow == b.arrow && a.graph == b.graph &&
+         a.pat == b.pat && a.pnnz == b.pnnz;
 }
 
 extern "C" int r1s_matvec_prec(r1s_mat A, r1s_prec M, int precision, int nrhs, const double* x,
@@ -1363,7 +1533,7 @@ static int gmres_check(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* o
   if (M->g.nx != A->g.nx || M->g.ny != A->g.ny || M->g.L != A->g.L)
     return fail(R1S_ERR_ARG, "preconditioner does not match the matrix");
   if (M->g.rd != A->g.rd || M->g.ro != A->g.ro || M->g.band != A->g.band ||
-      M->g.arrow != A->g.arrow)
+      M->g.arrow != A->g.arrow || M->g.pat != A->g.pat || M->g.pnnz != A->g.pnnz)
     return fail(R1S_ERR_ARG, "preconditioner was set up for another block layout");
   if (opts->trans && M->kind == PREC_SMW && !smw_has_trans(M))
     return fail(R1S_ERR_ARG, "transposed solve needs a preconditioner set up with R1S_WITH_TRANS");
@@ -1539,6 +1709,7 @@ extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double*
                         const r1s_grads* out, void* stream) {
   if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
   if (A->g.graph) return fail(R1S_ERR_ARG, "general-mesh matrix: use r1s_grad_graph");
+  if (A->g.pat) return fail(R1S_ERR_ARG, "general-pattern matrix: use r1s_grad_pattern");
   if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
   if (int e = check_vec(lambda, "lambda")) return e;
   if (int e = check_vec(x, "x")) return e;
@@ -1553,6 +1724,25 @@ extern "C" int r1s_grad(r1s_mat A, int nrhs, const double* lambda, const double*
   }
   GradOut o{out->s_diag, out->s_sub, out->s_sup, out->s_flow, out->s_nbr, out->u, out->v,
             out->s_band, out->s_lev_flow, out->s_flow_lev};
+  HIP_TRY(launch_grad(A->g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
+  return R1S_OK;
+}
+
+extern "C" int r1s_grad_pattern(r1s_mat A, int nrhs, const double* lambda, const double* x,
+                                const r1s_pattern_grads* out, void* stream) {
+  if (!A || !out) return fail(R1S_ERR_ARG, "NULL argument");
+  if (!A->g.pat) return fail(R1S_ERR_ARG, "not a general-pattern matrix: use r1s_grad");
+  if (nrhs < 1 || nrhs > 64) return fail(R1S_ERR_ARG, "nrhs must be in [1, 64]");
+  if (int e = check_vec(lambda, "lambda")) return e;
+  if (int e = check_vec(x, "x")) return e;
+  const void* ps[4] = {out->s_cc, out->s_nbr, out->u, out->v};
+  for (int i = 0; i < 4; ++i)
+    if (int e = check_vec(ps[i], "gradient output")) return e;
+  GradOut o{};
+  o.s_cc = out->s_cc;
+  o.s_nbr = out->s_nbr;
+  o.u = out->u;
+  o.v = out->v;
   HIP_TRY(launch_grad(A->g, A->rec64, lambda, x, nrhs, o, as_stream(stream)));
   return R1S_OK;
 }

@@ -29,7 +29,10 @@ __global__ __launch_bounds__(256) void k_bsr_assemble(Mesh g, const double* __re
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int j = e / m, i = e - j * m;
     double s = 0.0;
-    if (d == D_C) {
+    if (d == D_C && g.pat) {  // general pattern: the entry at (i, j), if any
+      const int en = g.pdense[i * m + j];
+      s = en >= 0 ? rc[g.peoff[en]] : 0.0;
+    } else if (d == D_C) {
       if (i == j) {
         s = rc[F_DIAG * mp + i];
       } else if (i < L && j < L) {

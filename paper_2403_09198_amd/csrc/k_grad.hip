@@ -86,6 +86,21 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+  // general pattern of S_cc: one gradient per entry (i, j) of the pattern
+  if constexpr (!GRAPH) {
+    if (g.pat) {
+      for (int e = lane; e < g.pnnz; e += WAVE) {
+        const int i = g.perow[e], j = g.pecol[e];
+        double ge = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+          const long long o0 = (long long)r * g.n + (long long)c * m;
+          ge -= lam[o0 + i] * x[o0 + j];
+        }
+        o.s_cc[(long long)c * g.pnnz + e] = ge;
+      }
+    }
+  }
+
   // sparse part
   for (int k = lane; k < m; k += WAVE) {
     double gdiag = 0.0, glo = 0.0, ghi = 0.0;
@@ -99,7 +114,7 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
       pa = L + (i + 2) % 3; va = true;
       pb = L + (i + 1) % 3; vb = true;
     }
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < nrhs && !g.pat; ++r) {
       const double* lr = lam + (long long)r * g.n + (long long)c * m;
       const double* xc = x + (long long)r * g.n + (long long)c * m;
       const double lk = lr[k];
@@ -107,15 +122,17 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
       if (va) glo -= lk * xc[pa];
       if (vb) ghi -= lk * xc[pb];
     }
-    o.s_diag[(long long)c * m + k] = gdiag;
-    if (k < L) {
-      if (k >= 1) o.s_sub[(long long)c * (L - 1) + k - 1] = glo;
-      if (k <= L - 2) o.s_sup[(long long)c * (L - 1) + k] = ghi;
-    } else {
-      const int i = k - L;
-      const int ja = (i + 2) % 3, jb = (i + 1) % 3;
-      o.s_flow[(long long)c * 6 + i * 2 + (ja > i ? ja - 1 : ja)] = glo;
-      o.s_flow[(long long)c * 6 + i * 2 + (jb > i ? jb - 1 : jb)] = ghi;
+    if (!g.pat) {  // (a general pattern's entries are done above)
+      o.s_diag[(long long)c * m + k] = gdiag;
+      if (k < L) {
+        if (k >= 1) o.s_sub[(long long)c * (L - 1) + k - 1] = glo;
+        if (k <= L - 2) o.s_sup[(long long)c * (L - 1) + k] = ghi;
+      } else {
+        const int i = k - L;
+        const int ja = (i + 2) % 3, jb = (i + 1) % 3;
+        o.s_flow[(long long)c * 6 + i * 2 + (ja > i ? ja - 1 : ja)] = glo;
+        o.s_flow[(long long)c * 6 + i * 2 + (jb > i ? jb - 1 : jb)] = ghi;
+      }
     }
     // diagonals of the off-diagonal blocks (zero for blocks outside the mesh)
     for (int bi = 0; bi < rb.n; ++bi) {
@@ -134,7 +151,7 @@ __global__ __launch_bounds__(256) void k_grad(Mesh g, const double* __restrict__
     }
     // wide pattern: further level diagonals and the level/flow coupling
     // (zero in the slots outside the block)
-    if (k < L) {
+    if (k < L && !g.pat) {
       const int nbd = g.band - 1;
       for (int j = 2; j <= g.band; ++j) {
         double glj = 0.0, guj = 0.0;

@@ -43,7 +43,14 @@ __global__ __launch_bounds__(256) void k_pack(Mesh g, PackIn in, TV* __restrict_
       const int iy = c / g.nx, ix = c - iy * g.nx;
       nb[D_S] = iy > 0; nb[D_W] = ix > 0; nb[D_C] = 1;
       nb[D_E] = ix < g.nx - 1; nb[D_N] = iy < g.ny - 1;
-      if (f == F_DIAG) {
+      if (g.pat && (f == F_DIAG || f == F_LO || f == F_HI || (f >= g.fb && f < g.fu))) {
+        // general pattern: diagonal, ELL and dense-index rows from the
+        // entry table (F_LO / F_HI unused, zero)
+        if (f == F_DIAG || f >= g.fb) {
+          const int e = g.ppack[(f == F_DIAG ? 0 : f - g.fb + 1) * g.mp + k];
+          if (e >= 0) val = in.s_cc[(long long)c * g.pnnz + e];
+        }
+      } else if (f == F_DIAG) {
         val = in.s_diag[(long long)c * m + k];
       } else if (f == F_LO || f == F_HI) {
         if (k < L) {
@@ -129,6 +136,10 @@ template <typename TV, bool TRANS, bool RESID>
 static hipError_t launch_mv_t(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   if (!ranks_supported(g.rd, g.ro) || g.band > BAND_MAX) return hipErrorInvalidValue;
+  if (g.pat) {
+    const int kind = (TRANS ? 1 : 0) | (RESID ? 2 : 0) | (std::is_same<TV, float>::value ? 4 : 0);
+    return launch_mv_pattern(g, rec, kind, x, b, y, nrhs, s);
+  }
   if (!wide_pattern(g) && g.rd == 1 && g.ro == 1) {
 #ifndef R1S_NO_PACKED
     if (nrhs == 1 && packed_ok(g))

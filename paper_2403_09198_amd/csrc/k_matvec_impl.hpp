@@ -53,12 +53,14 @@ __device__ inline Mesh kmesh(Mesh g) {
 // cell's own, valid addresses and are masked out of the sums instead of
 // being skipped by a branch.  Lanes past m read element m-1 and are masked.
 // Pair slots past a block's count are skipped by wave-uniform guards.
-// WIDE: the diagonal block has further band diagonals or level/flow coupling.
+// WIDE: the diagonal block has further band diagonals or level/flow coupling
+// (1), or a general pattern (2: ELL rows with a column table and dense
+// indices, see PatLane and the slot helpers).
 // pair2: two neighbouring waves of a workgroup share a cell, the second
 // taking right-hand sides r0 + NR .. r0 + 2 NR - 1 (the cell's rows come
 // from HBM once and from L2 for the second wave; half the registers of one
 // wave holding all 2 NR).
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, int WIDE>
 __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
@@ -114,9 +116,10 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
   // with 6 pairs per neighbour block, 6% slower with 2).  Without coupling
   // the rows read are other rows of the record (distinct, always present)
   // and their values are discarded.
-  constexpr bool PRE_ARROW = WIDE && PRELOAD && ROM > RANK_OFF_SMALL;
+  constexpr bool PRE_ARROW = WIDE == 1 && PRELOAD && ROM > RANK_OFF_SMALL;
   constexpr int NA = PRE_ARROW ? ARROW_SLOTS_MAX : 1;
-  const int nsl = arrow_slots(g);  // coupling slots (wave-uniform)
+  constexpr int NSM = WIDE == 2 ? PAT_SLOTS_MAX : ARROW_SLOTS_MAX;
+  const int nsl = WIDE == 2 ? g.ns : arrow_slots(g);  // coupling slots (wave-uniform)
   TV arw[NA][NCH], alw[NA][NCH], xfl[NR][NA];
   // single chunk: the band / corner partners x[pa], x[pb] of the cell's own
   // block come from the lanes that loaded them (a lane permutation) instead
@@ -199,15 +202,15 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
         acc[r][d][p] = ex[d] ? s : TV(0);
       }
   // coupling sums of the flow unknowns (and the atom) over the cell's levels
-  TV asum[NR][ARROW_SLOTS_MAX];
+  TV asum[NR][NSM];
   if constexpr (WIDE) {
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) asum[r][i] = TV(0);
-    if (g.arrow) {
+      for (int i = 0; i < NSM; ++i) asum[r][i] = TV(0);
+    if (nsl > 0) {
 #pragma unroll
-      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+      for (int i = 0; i < NSM; ++i) {
         if (i >= nsl) break;
         TV ar[NCH];
 #pragma unroll
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
           if constexpr (PRE_ARROW)
             ar[ch] = k < m ? arw[i][ch] : TV(0);
           else
-            ar[ch] = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + (k < m ? k : m - 1)] : TV(0);
+            ar[ch] = k < m ? R.rc[slot_sum_row<WIDE, TRANS>(g, i) * mp + (k < m ? k : m - 1)] : TV(0);
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -237,17 +240,19 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     if (!PRELOAD) load_sparse(ch);
     const int k = ch * WAVE + lane;
     const int kk = k < m ? k : m - 1;
-    BandLane<TV, TRANS> bl;
-    TV al[ARROW_SLOTS_MAX] = {TV(0), TV(0), TV(0), TV(0)};
+    DiagLane<TV, TRANS, WIDE> bl;
+    TV al[NSM];
+#pragma unroll
+    for (int i = 0; i < NSM; ++i) al[i] = TV(0);
     if constexpr (WIDE) {
       bl.load(g, R.rc, kk);
 #pragma unroll
-      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+      for (int i = 0; i < NSM; ++i) {
         if (i >= nsl) break;
         if constexpr (PRE_ARROW)
           al[i] = alw[i][ch];
         else
-          al[i] = R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk];
+          al[i] = R.rc[slot_lane_row<WIDE, TRANS>(g, i) * mp + kk];
       }
     }
 #pragma unroll
@@ -269,22 +274,31 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
           t += bl.apply_lanes(g, xv[r][D_C][ch]);
         else
           t += bl.apply(g, xc);
-        if (g.arrow) {
+        if (nsl > 0) {
           // level lanes: coupling entries times the flow unknowns (and the
-          // atom); flow lane L + i (atom lane L - 1): the coupling sum
+          // atom); flow lane L + i (atom lane L - 1): the coupling sum.  A
+          // general pattern the same with its dense indices px.
 #pragma unroll
-          for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+          for (int i = 0; i < NSM; ++i) {
             if (i >= nsl) break;
             if constexpr (PRE_ARROW)
               t += al[i] * xfl[r][i];
             else if constexpr (SHUFFLE_X)
-              t += al[i] * readlane(xv[r][D_C][ch], arrow_unknown(L, i));
+              t += al[i] * readlane(xv[r][D_C][ch], slot_x<WIDE>(g, i));
             else
-              t += al[i] * (TV)xc[arrow_unknown(L, i)];
+              t += al[i] * (TV)xc[slot_x<WIDE>(g, i)];
           }
-          const int fi = kk - L;
-          t += fi == 0 ? asum[r][0] : fi == 1 ? asum[r][1] : fi == 2 ? asum[r][2] : TV(0);
-          if (nsl > 3 && fi == -1) t += asum[r][3];
+          if constexpr (WIDE == 2) {
+#pragma unroll
+            for (int i = 0; i < NSM; ++i) {
+              if (i >= nsl) break;
+              if (kk == g.px[i]) t += asum[r][i];
+            }
+          } else {
+            const int fi = kk - L;
+            t += fi == 0 ? asum[r][0] : fi == 1 ? asum[r][1] : fi == 2 ? asum[r][2] : TV(0);
+            if (nsl > 3 && fi == -1) t += asum[r][3];
+          }
         }
       }
       const long long o = (long long)(r0 + r) * g.n + (long long)c * m + kk;
@@ -297,7 +311,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
 // 64w .. 64w+63 of one cell, issues all of its loads at once (like the
 // single-chunk kernel), and the pair coefficients are summed over the waves
 // through LDS in a fixed order.
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE,
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, int WIDE,
           bool BAND = false>
 __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __restrict__ rec,
                                                         const double* __restrict__ x,
@@ -306,7 +320,8 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   constexpr bool EXACT = RDM == 1 && ROM == 1;
   constexpr int RM = RDM > ROM ? RDM : ROM;
   __shared__ TV part[NR][5][RM][NCH];
-  __shared__ TV apart[WIDE ? NR : 1][ARROW_SLOTS_MAX][NCH];
+  constexpr int NSM = WIDE == 2 ? PAT_SLOTS_MAX : ARROW_SLOTS_MAX;
+  __shared__ TV apart[WIDE ? NR : 1][NSM][NCH];
   __shared__ TV xs[NR][WAVE * NCH];  // the cell's own x block (band / corner partners)
   const Mesh g = kmesh<EXACT>(g_);
   int c0, qn;
@@ -390,21 +405,23 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
         if (lane == 0) part[r][d][p][wv] = s;
       }
   // wide pattern: this chunk's share of the coupling sums, band terms
-  BandLane<TV, TRANS> bl;
-  TV al[ARROW_SLOTS_MAX] = {TV(0), TV(0), TV(0), TV(0)};
-  const int nsl = arrow_slots(g);
-  if constexpr (WIDE) {
-    if (g.arrow) {
+  DiagLane<TV, TRANS, WIDE> bl;
+  TV al[NSM];
 #pragma unroll
-      for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+  for (int i = 0; i < NSM; ++i) al[i] = TV(0);
+  const int nsl = WIDE == 2 ? g.ns : arrow_slots(g);
+  if constexpr (WIDE) {
+    if (nsl > 0) {
+#pragma unroll
+      for (int i = 0; i < NSM; ++i) {
         if (i >= nsl) break;
-        const TV ar = k < m ? R.rc[arrow_sum_row<TRANS>(g, i) * mp + kk] : TV(0);
+        const TV ar = k < m ? R.rc[slot_sum_row<WIDE, TRANS>(g, i) * mp + kk] : TV(0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const TV s = wave_sum_u(ar * xv[r][D_C]);
           if (lane == 0) apart[r][i][wv] = s;
         }
-        al[i] = R.rc[arrow_lane_row<TRANS>(g, i) * mp + kk];
+        al[i] = R.rc[slot_lane_row<WIDE, TRANS>(g, i) * mp + kk];
       }
     }
     bl.load(g, R.rc, kk);
@@ -427,14 +444,21 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
     if constexpr (WIDE) {
       const double* xc = xr + (long long)r * g.n + (long long)c * m;
       t += bl.apply(g, xc);
-      if (g.arrow) {
+      if (nsl > 0) {
 #pragma unroll
-        for (int i = 0; i < ARROW_SLOTS_MAX; ++i) {
+        for (int i = 0; i < NSM; ++i) {
           if (i >= nsl) break;
-          t += al[i] * (TV)xc[arrow_unknown(L, i)];
+          t += al[i] * (TV)xc[slot_x<WIDE>(g, i)];
         }
-        const int fi = kk - L;
-        const int si = fi >= 0 && fi < 3 ? fi : (nsl > 3 && fi == -1 ? 3 : -1);
+        int si = -1;
+        if constexpr (WIDE == 2) {
+#pragma unroll
+          for (int i = 0; i < NSM; ++i)
+            if (i < nsl && kk == g.px[i]) si = i;
+        } else {
+          const int fi = kk - L;
+          si = fi >= 0 && fi < 3 ? fi : (nsl > 3 && fi == -1 ? 3 : -1);
+        }
         if (si >= 0) {
           TV s = apart[r][si][0];
 #pragma unroll
@@ -448,7 +472,7 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
   }
 }
 
-template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
+template <typename TV, int NCH, bool TRANS, bool RESID, int RDM, int ROM, int WIDE>
 inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const double* b,
                           double* y, int nrhs, hipStream_t s) {
   constexpr bool EXACT = RDM == 1 && ROM == 1;
@@ -511,7 +535,7 @@ inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
   }
 }
 
-template <typename TV, bool TRANS, bool RESID, int RDM, int ROM, bool WIDE>
+template <typename TV, bool TRANS, bool RESID, int RDM, int ROM, int WIDE>
 inline hipError_t launch_mv_r(const Mesh& g, const TV* rec, const double* x, const double* b,
                               double* y, int nrhs, hipStream_t s) {
   switch ((g.m + WAVE - 1) / WAVE) {

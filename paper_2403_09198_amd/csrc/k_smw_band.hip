@@ -121,6 +121,74 @@ __device__ __forceinline__ void band_solve(const T* __restrict__ fb, int L, int 
   for (int i = 0; i < 3; ++i) dst[(L + i) * DS] = (DST)xf[i];
 }
 
+// The Woodbury factors of one cell, one lane per cell: W_i = A0^{-1} u_i and
+// v_i (rows of wc, W first), C^{-1} = (I + V^T W)^{-1} by Gauss-Jordan with
+// partial pivoting (ci, row-major), and when wcT is given the transposed
+// rows A0^{-T} v_i, u_i.  solve(rhs, dst) / solveT(rhs, dst) write A0^{-1}
+// rhs / A0^{-T} rhs into dst[0 .. m) (the cell's own row; rhs(k) gives
+// element k).  Padding elements of the rows are zeroed.
+template <typename PairU, typename PairV, typename Solve, typename SolveT>
+__device__ void woodbury_factors(int m, long long mp, int rd, PairU pair_u, PairV pair_v,
+                                 Solve solve, SolveT solveT, double* wc, double* wcT, double* ci,
+                                 bool& bad) {
+  // SMW-1: W_i = A0^{-1} u_i; V_i = v_i
+  double vv = 0.0, ww = 0.0;
+  for (int i = 0; i < rd; ++i) {
+    double* Wi = wc + (long long)i * mp;
+    double* Vi = wc + (long long)(rd + i) * mp;
+    solve([&](int k) { return pair_u(i, k); }, Wi);
+    for (int k = 0; k < m; ++k) {
+      const double v = pair_v(i, k);
+      Vi[k] = v;
+      vv += v * v;
+      ww += Wi[k] * Wi[k];
+    }
+    for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
+  }
+  // SMW-2: C = I + V^T W, inverted by Gauss-Jordan with partial pivoting
+  double Cm[SMW_PAIRS_MAX][2 * SMW_PAIRS_MAX];
+  for (int i = 0; i < rd; ++i)
+    for (int j = 0; j < rd; ++j) {
+      double s = i == j ? 1.0 : 0.0;
+      const double* Vi = wc + (long long)(rd + i) * mp;
+      const double* Wj = wc + (long long)j * mp;
+      for (int k = 0; k < m; ++k) s += Vi[k] * Wj[k];
+      Cm[i][j] = s;
+      Cm[i][rd + j] = i == j ? 1.0 : 0.0;
+    }
+  const double tol = 1e-12 * (1.0 + sqrt(vv * ww));
+  for (int k = 0; k < rd; ++k) {
+    int p = k;
+    for (int i = k + 1; i < rd; ++i)
+      if (fabs(Cm[i][k]) > fabs(Cm[p][k])) p = i;
+    if (!(fabs(Cm[p][k]) > tol)) bad = true;
+    if (p != k)
+      for (int j = 0; j < 2 * rd; ++j) {
+        const double t = Cm[k][j];
+        Cm[k][j] = Cm[p][j];
+        Cm[p][j] = t;
+      }
+    const double inv = 1.0 / Cm[k][k];
+    for (int j = 0; j < 2 * rd; ++j) Cm[k][j] *= inv;
+    for (int i = 0; i < rd; ++i) {
+      if (i == k) continue;
+      const double f = Cm[i][k];
+      for (int j = 0; j < 2 * rd; ++j) Cm[i][j] -= f * Cm[k][j];
+    }
+  }
+  for (int i = 0; i < rd; ++i)
+    for (int j = 0; j < rd; ++j) ci[i * rd + j] = Cm[i][rd + j];
+  if (wcT) {  // transposed apply: A0^{-T} v_i and u_i
+    for (int i = 0; i < rd; ++i) {
+      double* Wi = wcT + (long long)i * mp;
+      double* Vi = wcT + (long long)(rd + i) * mp;
+      solveT([&](int k) { return pair_v(i, k); }, Wi);
+      for (int k = 0; k < m; ++k) Vi[k] = pair_u(i, k);
+      for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- setup ----
 // One lane per cell (workgroups of 64 = one tile).  Writes the band factors,
 // the Schur inverse (s3i [tile][9][64]), W and V rows for the forward apply
@@ -231,67 +299,16 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
     if (i == rdu) return k == ia ? 1.0 : 0.0;
     return k < ia ? rc[(long long)arrow_row_row(g, 3) * mp + k] : 0.0;
   };
-  double* wc = wv + (long long)c * 2 * rd * mp;  // this cell's W rows, then V rows
-  // SMW-1: W_i = A0^{-1} u_i; V_i = v_i (padding zero)
-  double vv = 0.0, ww = 0.0;
-  for (int i = 0; i < rd; ++i) {
-    double* Wi = wc + (long long)i * mp;
-    double* Vi = wc + (long long)(rd + i) * mp;
-    band_solve<false, 1, double, double>(fb, L, band, g.arrow, s3i,
-                                         [&](int k) { return pair_u(i, k); }, Wi);
-    for (int k = 0; k < m; ++k) {
-      const double v = pair_v(i, k);
-      Vi[k] = v;
-      vv += v * v;
-      ww += Wi[k] * Wi[k];
-    }
-    for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
-  }
-  // SMW-2: C = I + V^T W, inverted by Gauss-Jordan with partial pivoting
-  double Cm[SMW_PAIRS_MAX][2 * SMW_PAIRS_MAX];
-  for (int i = 0; i < rd; ++i)
-    for (int j = 0; j < rd; ++j) {
-      double s = i == j ? 1.0 : 0.0;
-      const double* Vi = wc + (long long)(rd + i) * mp;
-      const double* Wj = wc + (long long)j * mp;
-      for (int k = 0; k < m; ++k) s += Vi[k] * Wj[k];
-      Cm[i][j] = s;
-      Cm[i][rd + j] = i == j ? 1.0 : 0.0;
-    }
-  const double tol = 1e-12 * (1.0 + sqrt(vv * ww));
-  for (int k = 0; k < rd; ++k) {
-    int p = k;
-    for (int i = k + 1; i < rd; ++i)
-      if (fabs(Cm[i][k]) > fabs(Cm[p][k])) p = i;
-    if (!(fabs(Cm[p][k]) > tol)) bad = true;
-    if (p != k)
-      for (int j = 0; j < 2 * rd; ++j) {
-        const double t = Cm[k][j];
-        Cm[k][j] = Cm[p][j];
-        Cm[p][j] = t;
-      }
-    const double inv = 1.0 / Cm[k][k];
-    for (int j = 0; j < 2 * rd; ++j) Cm[k][j] *= inv;
-    for (int i = 0; i < rd; ++i) {
-      if (i == k) continue;
-      const double f = Cm[i][k];
-      for (int j = 0; j < 2 * rd; ++j) Cm[i][j] -= f * Cm[k][j];
-    }
-  }
-  double* ci = cinv + (long long)c * rd * rd;
-  for (int i = 0; i < rd; ++i)
-    for (int j = 0; j < rd; ++j) ci[i * rd + j] = Cm[i][rd + j];
-  if (wvT) {  // transposed apply: A0^{-T} v_i and u_i
-    double* wcT = wvT + (long long)c * 2 * rd * mp;
-    for (int i = 0; i < rd; ++i) {
-      double* Wi = wcT + (long long)i * mp;
-      double* Vi = wcT + (long long)(rd + i) * mp;
-      band_solve<true, 1, double, double>(fb, L, band, g.arrow, s3i,
-                                          [&](int k) { return pair_v(i, k); }, Wi);
-      for (int k = 0; k < m; ++k) Vi[k] = pair_u(i, k);
-      for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
-    }
-  }
+  woodbury_factors(
+      m, mp, rd, pair_u, pair_v,
+      [&](auto rhs, double* dst) {
+        band_solve<false, 1, double, double>(fb, L, band, g.arrow, s3i, rhs, dst);
+      },
+      [&](auto rhs, double* dst) {
+        band_solve<true, 1, double, double>(fb, L, band, g.arrow, s3i, rhs, dst);
+      },
+      wv + (long long)c * 2 * rd * mp, wvT ? wvT + (long long)c * 2 * rd * mp : nullptr,
+      cinv + (long long)c * rd * rd, bad);
   if (bad) atomicMin(status, c);
 }
 
@@ -576,6 +593,190 @@ hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, con
                                                    (const double*)wv, (const double*)cinv, r, z, nrhs, s)
                : launch_band_apply_t<double, false>(g, (const double*)bf, (const double*)s3i,
                                                     (const double*)wv, (const double*)cinv, r, z, nrhs, s);
+}
+
+// ------------------------------------------------------ general pattern ----
+// LU without pivoting of B = P S_cc P^T (P the plan's minimum-degree order)
+// with the fill the host found, one lane per cell: the factor of cell c is
+// nnzF values at positions p of the filled pattern, tile-interleaved
+// [tile][p][TILE] like the band factors, with 1 / U[k][k] at the diagonal
+// positions.  The solves walk the position tables (wave-uniform, the same
+// for every lane) and keep the lane's vector in its original order: the
+// value of new index i lives at perm[i] throughout, so that no permutation
+// pass is needed.
+
+// x = A0^{-1} v (TRANS: A0^{-T} v) in place in v[0 .. m); f(p) is the
+// factor value at position p.  Forward L y = P v, backward U (P x) = y;
+// transposed U^T z = P v, then L^T (P x) = z.
+template <bool TRANS, typename TA, typename FV>
+__device__ __forceinline__ void pattern_solve(const PatLU& lu, int m, FV f, double* v) {
+  if (!TRANS) {
+    for (int i = 0; i < m; ++i) {
+      const int oi = lu.perm[i];
+      TA y = (TA)v[oi];
+      for (int e = lu.lrow_ptr[i]; e < lu.lrow_ptr[i + 1]; ++e)
+        y -= f(lu.lrow_pos[e]) * (TA)v[lu.lrow_oc[e]];
+      v[oi] = (double)y;
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      const int oi = lu.perm[i];
+      TA x = (TA)v[oi];
+      for (int e = lu.urow_ptr[i]; e < lu.urow_ptr[i + 1]; ++e)
+        x -= f(lu.urow_pos[e]) * (TA)v[lu.urow_oc[e]];
+      v[oi] = (double)(x * f(lu.dpos[i]));
+    }
+  } else {
+    for (int i = 0; i < m; ++i) {
+      const int oi = lu.perm[i];
+      TA z = (TA)v[oi];
+      for (int e = lu.ucol_ptr[i]; e < lu.ucol_ptr[i + 1]; ++e)
+        z -= f(lu.ucol_pos[e]) * (TA)v[lu.ucol_or[e]];
+      v[oi] = (double)(z * f(lu.dpos[i]));
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      const int oi = lu.perm[i];
+      TA x = (TA)v[oi];
+      for (int e = lu.lcol_ptr[i]; e < lu.lcol_ptr[i + 1]; ++e)
+        x -= f(lu.lcol_pos[e]) * (TA)v[lu.lcol_or[e]];
+      v[oi] = (double)x;
+    }
+  }
+}
+
+// One lane per cell: the numeric LU (right-looking: for pivot k, scale
+// column k of L, then update the trailing entries (i, j) of row i of L's
+// column k and column j of U's row k), then the Woodbury factors.
+__global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
+                                                        const double* __restrict__ rec,
+                                                        double* __restrict__ bf,
+                                                        double* __restrict__ wv,
+                                                        double* __restrict__ wvT,
+                                                        double* __restrict__ cinv, int* status) {
+  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int c = tile * TILE + lane;
+  if (c >= g.N) return;  // no cross-lane work in this kernel
+  const int m = g.m, rd = smw_pairs(g);
+  const long long mp = g.mp;
+  const double* rc = rec + (long long)c * g.F * mp;
+  double* F = bf + (long long)tile * lu.nnzF * TILE + lane;
+  auto at = [&](int p) -> double& { return F[(long long)p * TILE]; };
+  for (int p = 0; p < lu.nnzF; ++p) {
+    const int o = lu.frec[p];
+    at(p) = o >= 0 ? rc[o] : 0.0;
+  }
+  bool bad = false;
+  for (int k = 0; k < m; ++k) {
+    const double piv = at(lu.dpos[k]);
+    if (!(fabs(piv) > 1e-14 * fabs(rc[F_DIAG * mp + lu.perm[k]]))) bad = true;
+    const double inv = 1.0 / piv;
+    at(lu.dpos[k]) = inv;
+    for (int a = lu.lcol_ptr[k]; a < lu.lcol_ptr[k + 1]; ++a) {
+      const double l = at(lu.lcol_pos[a]) * inv;
+      at(lu.lcol_pos[a]) = l;
+      const int i = lu.lcol_row[a];
+      for (int b = lu.urow_ptr[k]; b < lu.urow_ptr[k + 1]; ++b)
+        at(lu.posF[i * m + lu.urow_col[b]]) -= l * at(lu.urow_pos[b]);
+    }
+  }
+  const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
+  const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
+  auto fv = [&](int p) -> double { return F[(long long)p * TILE]; };
+  woodbury_factors(
+      m, mp, rd, [&](int i, int k) { return uC[i * mp + k]; },
+      [&](int i, int k) { return vC[i * mp + k]; },
+      [&](auto rhs, double* dst) {
+        for (int k = 0; k < m; ++k) dst[k] = rhs(k);
+        pattern_solve<false, double>(lu, m, fv, dst);
+      },
+      [&](auto rhs, double* dst) {
+        for (int k = 0; k < m; ++k) dst[k] = rhs(k);
+        pattern_solve<true, double>(lu, m, fv, dst);
+      },
+      wv + (long long)c * 2 * rd * mp, wvT ? wvT + (long long)c * 2 * rd * mp : nullptr,
+      cinv + (long long)c * rd * rd, bad);
+  if (bad) atomicMin(status, c);
+}
+
+// x0 = A0^{-1} r for every right-hand side, one lane per cell, the tile's
+// right-hand sides staged through LDS as in k_band_solve.
+template <typename TV, bool TRANS>
+__global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
+                                                        const TV* __restrict__ bf,
+                                                        const double* __restrict__ rin,
+                                                        double* __restrict__ zout, int nrhs) {
+  extern __shared__ double sv[];
+  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int m = g.m, ls = (m + 1) | 1;
+  const long long c0 = (long long)tile * TILE;
+  const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
+  const TV* F = bf + (long long)tile * lu.nnzF * TILE + lane;
+  auto fv = [&](int p) -> TV { return F[(long long)p * TILE]; };
+  double* mine = sv + lane * ls;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* rr = rin + (long long)r * g.n + c0 * m;
+    for (int cc = 0; cc < cells; ++cc)
+      for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * m + k];
+    __syncthreads();
+    pattern_solve<TRANS, TV>(lu, m, fv, mine);
+    __syncthreads();
+    double* zz = zout + (long long)r * g.n + c0 * m;
+    for (int cc = 0; cc < cells; ++cc)
+      for (int k = lane; k < m; k += TILE) zz[(long long)cc * m + k] = sv[cc * ls + k];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_pattern_setup(const Mesh& g, const PatLU& lu, const double* rec, double* bf,
+                                double* wv, double* wvT, double* cinv, int* status,
+                                hipStream_t s) {
+  if (!g.pat || g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pattern_setup, dim3((unsigned)tiles(g)), dim3(TILE), 0, s, g, lu, rec, bf,
+                     wv, wvT, cinv, status);
+  return hipGetLastError();
+}
+
+template <typename TV, bool TRANS>
+static void launch_pattern_solve(const Mesh& g, const PatLU& lu, const TV* bf, const double* r,
+                                 double* z, int nrhs, hipStream_t s) {
+  const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_pattern_solve<TV, TRANS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_pattern_solve<TV, TRANS>), dim3((unsigned)tiles(g)), dim3(TILE), lds, s,
+                     g, lu, bf, r, z, nrhs);
+}
+
+template <typename TV, bool TRANS>
+static hipError_t launch_pattern_apply_t(const Mesh& g, const PatLU& lu, const TV* bf,
+                                         const TV* wv, const TV* cinv, const double* r, double* z,
+                                         int nrhs, hipStream_t s) {
+  launch_pattern_solve<TV, TRANS>(g, lu, bf, r, z, nrhs, s);
+  if (g.rd == 1)
+    launch_woodbury_r<TV, TRANS, 1>(g, wv, cinv, z, nrhs, s);
+  else
+    launch_woodbury_r<TV, TRANS, RANK_DIAG_MAX>(g, wv, cinv, z, nrhs, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_apply(const Mesh& g, const PatLU& lu, const void* bf, const void* wv,
+                                const void* cinv, bool f32, bool trans, const double* r,
+                                double* z, int nrhs, hipStream_t s) {
+  if (!g.pat || g.rd > RANK_DIAG_MAX || g.m > WAVE * MAX_CHUNKS) return hipErrorInvalidValue;
+  if (f32)
+    return trans ? launch_pattern_apply_t<float, true>(g, lu, (const float*)bf, (const float*)wv,
+                                                       (const float*)cinv, r, z, nrhs, s)
+                 : launch_pattern_apply_t<float, false>(g, lu, (const float*)bf, (const float*)wv,
+                                                        (const float*)cinv, r, z, nrhs, s);
+  return trans ? launch_pattern_apply_t<double, true>(g, lu, (const double*)bf, (const double*)wv,
+                                                      (const double*)cinv, r, z, nrhs, s)
+               : launch_pattern_apply_t<double, false>(g, lu, (const double*)bf, (const double*)wv,
+                                                       (const double*)cinv, r, z, nrhs, s);
+}
+
+void pattern_prec_counts(const Mesh& g, int nnzF, long long* bf, long long* wv, long long* cinv) {
+  *bf = tiles(g) * (long long)nnzF * TILE;
+  *wv = (long long)g.N * 2 * g.rd * g.mp;
+  *cinv = (long long)g.N * g.rd * g.rd;
 }
 
 // Element counts of the factor arrays (host layout helper): band factors and

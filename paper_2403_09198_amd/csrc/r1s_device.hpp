@@ -53,6 +53,9 @@ constexpr int RANK_DIAG_MAX = 9, RANK_OFF_MAX = 6, RANK_OFF_SMALL = 2;
 // atom's column and row
 constexpr int SMW_PAIRS_MAX = RANK_DIAG_MAX + 2;
 constexpr int BAND_MAX = 8;  // level-band half-width of S_cc
+// General pattern of S_cc: at most PAT_ELL_MAX entries per row (and per
+// column) outside the dense indices, at most PAT_SLOTS_MAX dense indices
+constexpr int PAT_ELL_MAX = 16, PAT_SLOTS_MAX = 8;
 
 // SMW factor records, [N][3 + 2 rd][mp] per direction of application, plus
 // the rd x rd inverse capacitance per cell ([N][rd][rd], row-major).
@@ -85,10 +88,31 @@ struct Mesh {
   const int* nbr;
   const int* tslot;
   const int* offb;
+  // general pattern of S_cc (pat = 1): ne ELL rows from fb, ns dense indices
+  // px[t] (column row fa + t, row row fa + ns + t); shared int tables:
+  // pcol [ne][mp] ELL columns, ptpos / ptcol [net][mp] the transposed ELL
+  // (record offset of the value, -1, and its row), ppack [1 + ne + 2 ns][mp]
+  // entry feeding each record element (-1), perow / pecol / peoff [nnz] the
+  // entries' coordinates and record offsets, pdense [m][m] entry at (i, j)
+  int pat, ne, net, ns, pnnz;
+  int px[PAT_SLOTS_MAX];
+  const int *pcol, *ptpos, *ptcol, *ppack, *perow, *pecol, *peoff, *pdense;
+};
+
+// Tables of the LU of a general pattern (see pattern.hpp): perm (new ->
+// original index), frec (record offset of each factor position, -1 for
+// fill), dpos, posF [m][m], strict L and U by rows and by columns.
+struct PatLU {
+  int nnzF;
+  const int *perm, *frec, *dpos, *posF;
+  const int *lrow_ptr, *lrow_pos, *lrow_oc;
+  const int *urow_ptr, *urow_pos, *urow_col, *urow_oc;
+  const int *lcol_ptr, *lcol_pos, *lcol_row, *lcol_or;
+  const int *ucol_ptr, *ucol_pos, *ucol_or;
 };
 
 // Band or coupling beyond the tridiagonal / uncoupled diagonal block.
-__host__ __device__ inline bool wide_pattern(const Mesh& g) { return g.band > 1 || g.arrow; }
+__host__ __device__ inline bool wide_pattern(const Mesh& g) { return g.band > 1 || g.arrow || g.pat; }
 
 // Coupling slots of the diagonal block: slot i < 3 couples the levels to the
 // flow unknown L + i; with arrow = 2, slot 3 couples the molecule levels to
@@ -121,10 +145,10 @@ __host__ __device__ inline int smw_pairs(const Mesh& g) { return g.rd + (g.arrow
 // columns T^{-1} E and the three coupling rows of the Schur step.
 __host__ __device__ inline int smw_rows(const Mesh& g) { return 3 + 2 * smw_pairs(g) + (g.arrow ? 6 : 0); }
 __host__ __device__ inline int smw_arrow_row(const Mesh& g) { return 3 + 2 * smw_pairs(g); }
-// The block-Jacobi needs the one-lane-per-cell band factorisation when the
-// level band is wider than tridiagonal; the tridiagonal band, with or
-// without level/flow coupling, runs wave-per-cell.
-__host__ __device__ inline bool band_walk(const Mesh& g) { return g.band > 1; }
+// The block-Jacobi needs the one-lane-per-cell factorisation when the level
+// band is wider than tridiagonal or the pattern is a general one; the
+// tridiagonal band, with or without level/flow coupling, runs wave-per-cell.
+__host__ __device__ inline bool band_walk(const Mesh& g) { return g.band > 1 || g.pat; }
 
 // Workgroup id -> logical tile.  With R1S_XCD_REMAP each XCD (which
 // receives every NXCD-th workgroup) works on one contiguous range of tiles;
@@ -618,6 +642,75 @@ __device__ inline int arrow_lane_row(const Mesh& g, int i) {
   return TRANS ? arrow_row_row(g, i) : arrow_col_row(g, i);
 }
 
+// The coupling slots of either kind of wide diagonal block: the structured
+// layouts' (WIDE = 1: flow unknowns, atom) or a general pattern's dense
+// indices (WIDE = 2: column row fa + i, row row fa + ns + i, index px[i]).
+template <int WIDE, bool TRANS>
+__device__ inline int slot_sum_row(const Mesh& g, int i) {
+  if constexpr (WIDE == 2) return TRANS ? g.fa + i : g.fa + g.ns + i;
+  else return arrow_sum_row<TRANS>(g, i);
+}
+template <int WIDE, bool TRANS>
+__device__ inline int slot_lane_row(const Mesh& g, int i) {
+  if constexpr (WIDE == 2) return TRANS ? g.fa + g.ns + i : g.fa + i;
+  else return arrow_lane_row<TRANS>(g, i);
+}
+template <int WIDE>
+__device__ inline int slot_x(const Mesh& g, int i) {
+  if constexpr (WIDE == 2) return g.px[i];
+  else return arrow_unknown(g.L, i);
+}
+
+// The ELL entries of a general pattern at lane kk: forward, row kk's entries
+// (record rows fb + s, columns from the shared table); transposed, column
+// kk's entries (values gathered from the record by offset, their rows from
+// the table).  Absent entries get a zero value and the lane's own index.
+template <typename TV, bool TRANS>
+struct PatLane {
+  TV a[PAT_ELL_MAX];
+  int col[PAT_ELL_MAX];
+
+  __device__ inline void load(const Mesh& g, const TV* rc, int kk) {
+    const long long mp = g.mp;
+    const int n = TRANS ? g.net : g.ne;
+#pragma unroll
+    for (int s = 0; s < PAT_ELL_MAX; ++s) {
+      a[s] = TV(0);
+      col[s] = kk;
+      if (s < n) {
+        if (TRANS) {
+          const int pos = g.ptpos[s * mp + kk];
+          col[s] = g.ptcol[s * mp + kk];
+          a[s] = pos >= 0 ? rc[pos] : TV(0);
+        } else {
+          a[s] = rc[(g.fb + s) * mp + kk];
+          col[s] = g.pcol[s * mp + kk];
+        }
+      }
+    }
+  }
+  __device__ inline TV apply(const Mesh& g, const double* xc) const {
+    const int n = TRANS ? g.net : g.ne;
+    TV s = TV(0);
+#pragma unroll
+    for (int t = 0; t < PAT_ELL_MAX; ++t) {
+      if (t >= n) break;
+      s += a[t] * (TV)xc[col[t]];
+    }
+    return s;
+  }
+  __device__ inline TV apply_lanes(const Mesh& g, TV xk) const {
+    const int n = TRANS ? g.net : g.ne;
+    TV s = TV(0);
+#pragma unroll
+    for (int t = 0; t < PAT_ELL_MAX; ++t) {
+      if (t >= n) break;
+      s += a[t] * __shfl(xk, col[t], WAVE);
+    }
+    return s;
+  }
+};
+
 // Band coefficients of lane kk (clamped lane index) and the x indices they
 // multiply; invalid positions get a zero coefficient and a valid index.
 template <typename TV, bool TRANS>
@@ -668,5 +761,17 @@ struct BandLane {
     return s;
   }
 };
+
+// The lane terms of the wide diagonal block of either kind.
+template <typename TV, bool TRANS, int WIDE>
+struct DiagLaneSel {
+  using type = BandLane<TV, TRANS>;
+};
+template <typename TV, bool TRANS>
+struct DiagLaneSel<TV, TRANS, 2> {
+  using type = PatLane<TV, TRANS>;
+};
+template <typename TV, bool TRANS, int WIDE>
+using DiagLane = typename DiagLaneSel<TV, TRANS, WIDE>::type;
 
 }  // namespace r1s

@@ -9,6 +9,7 @@ namespace r1s {
 struct PackIn {
   const double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
   const double *s_band, *s_lev_flow, *s_flow_lev;  // wide diagonal-block pattern only
+  const double* s_cc;  // general pattern: [N][nnz] (the structured S_cc arrays unused)
 };
 
 // inputs on a general mesh (per cell: diagonal block; per off-diagonal block
@@ -26,6 +27,7 @@ struct GraphGradOut {
 struct GradOut {
   double *s_diag, *s_sub, *s_sup, *s_flow, *s_nbr, *u, *v;
   double *s_band, *s_lev_flow, *s_flow_lev;
+  double* s_cc;  // general pattern: [N][nnz] (the structured S_cc outputs unused)
 };
 
 // pair counts the kernels are built for
@@ -50,6 +52,9 @@ hipError_t launch_mv_general_r2(const Mesh& g, const void* rec, int kind, const 
                                 const double* b, double* y, int nrhs, hipStream_t s);
 hipError_t launch_mv_general_r6(const Mesh& g, const void* rec, int kind, const double* x,
                                 const double* b, double* y, int nrhs, hipStream_t s);
+// the same for a general pattern of the diagonal block
+hipError_t launch_mv_pattern(const Mesh& g, const void* rec, int kind, const double* x,
+                             const double* b, double* y, int nrhs, hipStream_t s);
 
 // structured matvec (rec: packed record, float when f32)
 hipError_t launch_matvec(const Mesh& g, const void* rec, bool f32, bool trans, const double* x,
@@ -93,6 +98,15 @@ hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, doubl
 hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, const void* wv,
                              const void* cinv, bool f32, bool trans, const double* r, double* z,
                              int nrhs, hipStream_t s);
+// The same for a general pattern: LU of the permuted S_cc with the fill of
+// the plan (factor positions lu.nnzF per cell, tile-interleaved), then the
+// Woodbury correction as above.
+void pattern_prec_counts(const Mesh& g, int nnzF, long long* bf, long long* wv, long long* cinv);
+hipError_t launch_pattern_setup(const Mesh& g, const PatLU& lu, const double* rec, double* bf,
+                                double* wv, double* wvT, double* cinv, int* status, hipStream_t s);
+hipError_t launch_pattern_apply(const Mesh& g, const PatLU& lu, const void* bf, const void* wv,
+                                const void* cinv, bool f32, bool trans, const double* r,
+                                double* z, int nrhs, hipStream_t s);
 
 // dense-block BSR baseline
 hipError_t launch_bsr_assemble(const Mesh& g, const double* rec, const int* blk_row,

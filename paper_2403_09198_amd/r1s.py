@@ -185,6 +185,50 @@ def r1s_grad_graph(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
     check(lib().r1s_grad_graph(h, nrhs, _ptr(lam), _ptr(x), C.byref(g), _stream(stream)))
 
 
+def _pattern_inputs(values, N, m, nnz, lay, cls=L.PatternInputs):
+    P = lay.r_diag + 4 * lay.r_off
+    shapes = {"s_cc": (N, nnz), "s_nbr": (N, 4, m), "u": (N, P, m), "v": (N, P, m)}
+    ins = cls()
+    for k in L.PATTERN_INPUT_FIELDS:
+        t = values[k]
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+            raise TypeError(f"{k} must be a float64 CUDA tensor")
+        if tuple(t.shape) != shapes[k] or not t.is_contiguous():
+            raise ValueError(f"{k} must be contiguous with shape {shapes[k]}")
+        setattr(ins, k, _ptr(t).value)
+    return ins
+
+
+def r1s_mat_size_pattern(nx, ny, Lv, lay, indptr, indices, flags=0) -> int:
+    b = C.c_size_t()
+    ip, pip = _host_i32(indptr)
+    ix, pix = _host_i32(indices)
+    check(lib().r1s_mat_size_pattern(nx, ny, Lv, C.byref(lay), pip, pix, flags, C.byref(b)))
+    return b.value
+
+
+def r1s_mat_init_pattern(nx, ny, Lv, lay, indptr, indices, flags, values, mem, stream=None):
+    h = C.c_void_p()
+    ip, pip = _host_i32(indptr)
+    ix, pix = _host_i32(indices)
+    ins = _pattern_inputs(values, nx * ny, Lv + 3, len(ix), lay)
+    check(lib().r1s_mat_init_pattern(nx, ny, Lv, C.byref(lay), pip, pix, flags, C.byref(ins),
+                                     _ptr(mem), mem.numel(), _stream(stream), C.byref(h)))
+    return h
+
+
+def r1s_mat_update_pattern(h, values, nx, ny, Lv, nnz, lay, stream=None):
+    ins = _pattern_inputs(values, nx * ny, Lv + 3, nnz, lay)
+    check(lib().r1s_mat_update_pattern(h, C.byref(ins), _stream(stream)))
+
+
+def r1s_grad_pattern(h, nrhs, lam, x, out: Dict[str, torch.Tensor], stream=None):
+    g = L.PatternGrads()
+    for k in out:
+        setattr(g, k, _ptr(out[k]).value)
+    check(lib().r1s_grad_pattern(h, nrhs, _ptr(lam), _ptr(x), C.byref(g), _stream(stream)))
+
+
 def r1s_mat_storage(h) -> dict:
     s = L.Storage()
     check(lib().r1s_mat_storage(h, C.byref(s)))
@@ -378,6 +422,41 @@ class R1GraphMatrix(R1Matrix):
         r1s_mat_update_graph(self.h, values, self.N, self.n_off, self.L, self.layout, stream)
 
 
+class R1PatternMatrix(R1Matrix):
+    """The block r1-sparse Jacobian on the structured mesh with a general
+    pattern of the diagonal block shared by every cell: pattern = (indptr,
+    indices), a CSR pattern over the m = L + 3 unknowns (host arrays);
+    values s_cc [N, nnz] in the pattern's entry order, s_nbr, u, v as for
+    R1Matrix (see gen.make_pattern_problem)."""
+
+    def __init__(self, nx, ny, L_levels, pattern, values: Dict[str, torch.Tensor], keep_f32=False,
+                 stream=None, ranks=(1, 1)):
+        import numpy as np
+        self.indptr = np.asarray(pattern[0], dtype=np.int32)
+        self.indices = np.asarray(pattern[1], dtype=np.int32)
+        self.nnz = len(self.indices)
+        self.nx, self.ny, self.L = nx, ny, L_levels
+        self.m = L_levels + 3
+        self.N = nx * ny
+        self.n = self.N * self.m
+        self.r_diag, self.r_off = (int(r) for r in ranks)
+        self.n_pairs = self.r_diag + 4 * self.r_off
+        self.band, self.arrow = 1, 0
+        self.layout = layout(self.r_diag, self.r_off, 1, 0)
+        self.flags = L.R1S_KEEP_F32 if keep_f32 else 0
+        dev = values["s_cc"].device
+        self.device = dev
+        self._lib = lib()
+        self.mem = _buffer(r1s_mat_size_pattern(nx, ny, L_levels, self.layout, self.indptr,
+                                                self.indices, self.flags), dev)
+        self.h = r1s_mat_init_pattern(nx, ny, L_levels, self.layout, self.indptr, self.indices,
+                                      self.flags, values, self.mem, stream)
+
+    def update(self, values, stream=None):
+        r1s_mat_update_pattern(self.h, values, self.nx, self.ny, self.L, self.nnz, self.layout,
+                               stream)
+
+
 class SMWPreconditioner:
     """Block-Jacobi through the Sherman-Morrison-Woodbury identity."""
 
@@ -497,6 +576,14 @@ def grad(A: R1Matrix, lam, x, stream=None) -> Dict[str, torch.Tensor]:
     """Gradients w.r.t. the structured arrays given lambda = J^{-T} dLoss/dx."""
     nrhs = _need_vec(lam, "lambda", A.n)
     _need_vec(x, "x", A.n)
+    if isinstance(A, R1PatternMatrix):
+        P = A.r_diag + 4 * A.r_off
+        shapes = {"s_cc": (A.N, A.nnz), "s_nbr": (A.N, 4, A.m), "u": (A.N, P, A.m),
+                  "v": (A.N, P, A.m)}
+        out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device)
+               for k in L.PATTERN_INPUT_FIELDS}
+        r1s_grad_pattern(A.h, nrhs, lam, x, out, stream)
+        return out
     if isinstance(A, R1GraphMatrix):
         shapes = _graph_shapes(A.N, A.n_off, A.L, A.layout)
         out = {k: torch.empty(shapes[k], dtype=torch.float64, device=A.device)
