@@ -272,29 +272,40 @@ def profile_pass(torch, A, M, x, y, z):
 
 
 def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False,
-               physics_values=False, solve=None):
+               physics_values=False, dra=False, explicit=False, solve=None):
     """The float64 pair with several rank-one pairs per block (the paper's
     9 / 2 structure) and optionally the wide diagonal-block pattern;
     algorithmic bytes from the library's storage counts.  physics_values:
     the HLL finite-volume Jacobian of a multi-species gas (8 / 6 pairs,
-    level/flow coupling) in place of random values; solve = (restart, rtol)
-    adds GMRES solves of it."""
+    level/flow coupling; with dra also the DRa source, arrow = 2) in place of
+    random values; explicit: the same Jacobian given as a general pattern of
+    the diagonal block (the layout written out entry by entry); solve =
+    (restart, rtol) adds GMRES solves of it."""
     from paper_2403_09198_amd import gen, physics, r1s
 
     dev = "cuda:0"
     if physics_values:
-        ranks, band, arrow = (physics.R_DIAG, physics.R_OFF), 1, True
+        ranks, band, arrow = (physics.R_DIAG, physics.R_OFF), 1, 2 if dra else 1
     log(f"ranks pair: mesh {nx}x{ny} L={L} ranks {ranks} band {band} arrow {arrow}"
-        + (" (HLL Jacobian)" if physics_values else ""))
+        + (" (HLL Jacobian)" if physics_values else "") + (" as a general pattern" if explicit else ""))
     if physics_values:
-        p = physics.make_problem(nx, ny, L, seed=seed)
-    else:
+        p = physics.make_problem(nx, ny, L, seed=seed, dra=dra)
+    elif not explicit:
         p = gen.make_problem(nx, ny, L, seed=seed, r_diag=ranks[0], r_off=ranks[1], band=band,
                              arrow=arrow)
-    keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
-    vals = {k: torch.from_numpy(p[k]).to(dev) for k in keys}
-    del p
-    A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks, band=band, arrow=arrow)
+    if explicit:
+        # the layout's pattern written out entry by entry, values drawn for it
+        ip, ix = gen.layout_pattern(L, band, arrow)
+        p = gen.make_pattern_problem(nx, ny, L, ip, ix, seed=seed, r_diag=ranks[0],
+                                     r_off=ranks[1])
+        vals = {k: torch.from_numpy(p[k]).to(dev) for k in gen.PATTERN_PROBLEM_FIELDS}
+        del p
+        A = r1s.R1PatternMatrix(nx, ny, L, (ip, ix), vals, keep_f32=True, ranks=ranks)
+    else:
+        keys = gen.FIELDS + tuple(k for k in gen.PATTERN_FIELDS if k in p)
+        vals = {k: torch.from_numpy(p[k]).to(dev) for k in keys}
+        del p
+        A = r1s.R1Matrix(nx, ny, L, vals, keep_f32=True, ranks=ranks, band=band, arrow=arrow)
     del vals
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -305,7 +316,8 @@ def ranks_pair(torch, nx, ny, L, ranks, steps, warm, seed=0, band=1, arrow=False
     x = torch.from_numpy(gen.make_vector(nx, ny, L, seed=0)).to(dev)
     y, z = torch.empty_like(x), torch.empty_like(x)
     N = nx * ny
-    row = {"r_diag": ranks[0], "r_off": ranks[1], "band": band, "arrow": bool(arrow),
+    row = {"r_diag": ranks[0], "r_off": ranks[1], "band": band, "arrow": int(arrow),
+           "explicit_pattern": bool(explicit),
            "stored_values": st["structured_values"],
            "smw_setup_ms": round(t_setup * 1e3, 2)}
     for tag, f1, f2, vb in (
@@ -791,13 +803,22 @@ def c2_block(torch, steps, warm):
     # level/flow coupling (banded-LU block-Jacobi)
     out["wide_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
                                           band=4, arrow=True)
+    # the same pattern given as a general (explicit) pattern of the diagonal
+    # block: host symbolic LU, one lane per cell numeric LU and solves
+    out["explicit_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
+                                              band=4, arrow=True, explicit=True)
+    # the atom density coupled to every level (arrow = 2)
+    out["atom_pattern_pair"] = ranks_pair(torch, nx, ny, L, gen.PAPER_RANKS, steps, warm,
+                                          band=1, arrow=2)
     # physics-shaped values: the HLL finite-volume Jacobian of a multi-species
-    # gas (8 / 6 pairs, level/flow coupling), with GMRES solves of it
-    try:
-        out["physics_pair"] = ranks_pair(torch, nx, ny, L, None, steps, warm,
-                                         physics_values=True, solve=(w.restart, w.rtol))
-    except Exception as e:  # report, never hide
-        out["physics_pair"] = {"error": str(e)}
+    # gas (8 / 6 pairs, level/flow coupling), with GMRES solves of it; and
+    # with the DRa source (atom coupling)
+    for key, dra in (("physics_pair", False), ("physics_dra_pair", True)):
+        try:
+            out[key] = ranks_pair(torch, nx, ny, L, None, steps, warm, physics_values=True,
+                                  dra=dra, solve=(w.restart, w.rtol))
+        except Exception as e:  # report, never hide
+            out[key] = {"error": str(e)}
     # general mesh: about 32 800 triangle cells (Delaunay of 16 400 random
     # points), the same L, one pair per block; shuffled and mesh-ordered
     out["general_mesh_pair"] = mesh_pair(torch, 16400, L, (1, 1), steps, warm)

@@ -605,42 +605,51 @@ hipError_t launch_band_apply(const Mesh& g, const void* bf, const void* s3i, con
 // value of new index i lives at perm[i] throughout, so that no permutation
 // pass is needed.
 
-// x = A0^{-1} v (TRANS: A0^{-T} v) in place in v[0 .. m); f(p) is the
-// factor value at position p.  Forward L y = P v, backward U (P x) = y;
-// transposed U^T z = P v, then L^T (P x) = z.
-template <bool TRANS, typename TA, typename FV>
-__device__ __forceinline__ void pattern_solve(const PatLU& lu, int m, FV f, double* v) {
-  if (!TRANS) {
-    for (int i = 0; i < m; ++i) {
-      const int oi = lu.perm[i];
-      TA y = (TA)v[oi];
-      for (int e = lu.lrow_ptr[i]; e < lu.lrow_ptr[i + 1]; ++e)
-        y -= f(lu.lrow_pos[e]) * (TA)v[lu.lrow_oc[e]];
-      v[oi] = (double)y;
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      const int oi = lu.perm[i];
-      TA x = (TA)v[oi];
-      for (int e = lu.urow_ptr[i]; e < lu.urow_ptr[i + 1]; ++e)
-        x -= f(lu.urow_pos[e]) * (TA)v[lu.urow_oc[e]];
-      v[oi] = (double)(x * f(lu.dpos[i]));
-    }
-  } else {
-    for (int i = 0; i < m; ++i) {
-      const int oi = lu.perm[i];
-      TA z = (TA)v[oi];
-      for (int e = lu.ucol_ptr[i]; e < lu.ucol_ptr[i + 1]; ++e)
-        z -= f(lu.ucol_pos[e]) * (TA)v[lu.ucol_or[e]];
-      v[oi] = (double)(z * f(lu.dpos[i]));
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      const int oi = lu.perm[i];
-      TA x = (TA)v[oi];
-      for (int e = lu.lcol_ptr[i]; e < lu.lcol_ptr[i + 1]; ++e)
-        x -= f(lu.lcol_pos[e]) * (TA)v[lu.lcol_or[e]];
-      v[oi] = (double)x;
-    }
-  }
+// x = A0^{-1} v (A0^{-T} v with the transposed stream) in place in v[0 ..
+// m): the plan's flat operation stream (forward L y = P v, backward U (P x)
+// = y; transposed U^T z = P v, then L^T (P x) = z), each operation one
+// factor value times one element of v.  The factor loads of the next U
+// operations are issued before the current U are computed (the operations
+// themselves are wave-uniform scalar loads); operations past the end are
+// dead.  F points at this lane's factor values (stride TILE).  With SINK
+// every operation reads and writes v (branch-free: a read that is not needed
+// and a write that is not wanted go to the sink element v[m], so the
+// operations of a block are straight-line code); without, v needs only m
+// elements.
+template <int U, bool SINK, typename TA, typename T>
+__device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int nops, int m,
+                                               const T* __restrict__ F, double* v) {
+  struct Op {
+    TA f;
+    int pos, code;
+  };
+  TA acc = TA(0);
+  pipelined_walk<U, Op>(
+      nops,
+      [&](int e, Op& o) {
+        const int ee = e < nops ? e : nops - 1;
+        o.pos = ops[2 * ee];
+        o.code = e < nops ? ops[2 * ee + 1] : -1;
+        o.f = (TA)F[(long long)(o.pos >= 0 ? o.pos : 0) * TILE];
+      },
+      [&](int, const Op& o) {
+        const int kind = o.code >> 16, idx = o.code & 0xffff;
+        if constexpr (SINK) {
+          const bool upd = kind == PAT_OP_UPD, start = kind == PAT_OP_START;
+          const bool end = kind == PAT_OP_END;
+          const TA val = (TA)v[upd || start ? idx : m];
+          acc = start ? val : acc - (upd ? o.f : TA(0)) * val;
+          v[end ? idx : m] = (double)(o.pos >= 0 ? acc * o.f : acc);
+        } else {
+          if (o.code < 0) return;
+          if (kind == PAT_OP_UPD)
+            acc -= o.f * (TA)v[idx];
+          else if (kind == PAT_OP_START)
+            acc = (TA)v[idx];
+          else
+            v[idx] = (double)(o.pos >= 0 ? acc * o.f : acc);
+        }
+      });
 }
 
 // One lane per cell: the numeric LU (right-looking: for pivot k, scale
@@ -680,17 +689,16 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
   }
   const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
   const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
-  auto fv = [&](int p) -> double { return F[(long long)p * TILE]; };
   woodbury_factors(
       m, mp, rd, [&](int i, int k) { return uC[i * mp + k]; },
       [&](int i, int k) { return vC[i * mp + k]; },
       [&](auto rhs, double* dst) {
         for (int k = 0; k < m; ++k) dst[k] = rhs(k);
-        pattern_solve<false, double>(lu, m, fv, dst);
+        pattern_stream<8, false, double>(lu.ops_n, lu.nops_n, m, F, dst);
       },
       [&](auto rhs, double* dst) {
         for (int k = 0; k < m; ++k) dst[k] = rhs(k);
-        pattern_solve<true, double>(lu, m, fv, dst);
+        pattern_stream<8, false, double>(lu.ops_t, lu.nops_t, m, F, dst);
       },
       wv + (long long)c * 2 * rd * mp, wvT ? wvT + (long long)c * 2 * rd * mp : nullptr,
       cinv + (long long)c * rd * rd, bad);
@@ -699,6 +707,9 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
 
 // x0 = A0^{-1} r for every right-hand side, one lane per cell, the tile's
 // right-hand sides staged through LDS as in k_band_solve.
+#ifndef PAT_STREAM_U
+#define PAT_STREAM_U 16  // operations per prefetch block
+#endif
 template <typename TV, bool TRANS>
 __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
                                                         const TV* __restrict__ bf,
@@ -710,14 +721,16 @@ __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
   const long long c0 = (long long)tile * TILE;
   const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
   const TV* F = bf + (long long)tile * lu.nnzF * TILE + lane;
-  auto fv = [&](int p) -> TV { return F[(long long)p * TILE]; };
   double* mine = sv + lane * ls;
   for (int r = 0; r < nrhs; ++r) {
     const double* rr = rin + (long long)r * g.n + c0 * m;
     for (int cc = 0; cc < cells; ++cc)
       for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * m + k];
     __syncthreads();
-    pattern_solve<TRANS, TV>(lu, m, fv, mine);
+    if (TRANS)
+      pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_t, lu.nops_t, m, F, mine);
+    else
+      pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_n, lu.nops_n, m, F, mine);
     __syncthreads();
     double* zz = zout + (long long)r * g.n + c0 * m;
     for (int cc = 0; cc < cells; ++cc)

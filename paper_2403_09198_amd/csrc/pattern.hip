@@ -270,6 +270,27 @@ int build_pattern_plan(int m, const int* indptr, const int* indices, PatternPlan
   csr(false, true, P.urow_ptr, P.urow_pos, &P.urow_col, &P.urow_oc);
   csr(true, false, P.lcol_ptr, P.lcol_pos, &P.lcol_row, &P.lcol_or);
   csr(false, false, P.ucol_ptr, P.ucol_pos, nullptr, &P.ucol_or);
+
+  // flat solve streams
+  auto op = [](std::vector<int>& v, int pos, int kind, int idx) {
+    v.push_back(pos);
+    v.push_back(kind << 16 | idx);
+  };
+  auto sweep = [&](std::vector<int>& v, bool up, const std::vector<int>& ptr,
+                   const std::vector<int>& pos, const std::vector<int>& other, bool scale) {
+    for (int t = 0; t < m; ++t) {
+      const int i = up ? t : m - 1 - t;
+      op(v, -1, PAT_OP_START, P.perm[i]);
+      for (int e = ptr[i]; e < ptr[i + 1]; ++e) op(v, pos[e], PAT_OP_UPD, other[e]);
+      op(v, scale ? P.dpos[i] : -1, PAT_OP_END, P.perm[i]);
+    }
+  };
+  P.ops_n.clear();
+  sweep(P.ops_n, true, P.lrow_ptr, P.lrow_pos, P.lrow_oc, false);
+  sweep(P.ops_n, false, P.urow_ptr, P.urow_pos, P.urow_oc, true);
+  P.ops_t.clear();
+  sweep(P.ops_t, true, P.ucol_ptr, P.ucol_pos, P.ucol_or, true);
+  sweep(P.ops_t, false, P.lcol_ptr, P.lcol_pos, P.lcol_or, false);
   return R1S_OK;
 }
 
@@ -282,6 +303,10 @@ void pattern_lu_tables(const PatternPlan& p, std::vector<int>& out, const int* d
     return dev ? dev + o : nullptr;
   };
   lu->nnzF = p.nnzF;
+  lu->nops_n = (int)p.ops_n.size() / 2;
+  lu->nops_t = (int)p.ops_t.size() / 2;
+  lu->ops_n = add(p.ops_n);
+  lu->ops_t = add(p.ops_t);
   lu->perm = add(p.perm);
   lu->frec = add(p.frec);
   lu->dpos = add(p.dpos);
@@ -302,6 +327,24 @@ void pattern_lu_tables(const PatternPlan& p, std::vector<int>& out, const int* d
   lu->ucol_or = add(p.ucol_or);
 }
 
+void pattern_lane_tables(const PatternPlan& p, std::vector<int>& c8, std::vector<int>& t16) {
+  const int mp = p.mp;
+  c8.assign((size_t)mp * (PAT_ELL_MAX / 4), 0);
+  t16.assign((size_t)mp * (PAT_ELL_MAX / 2), 0);
+  for (int k = 0; k < mp; ++k) {
+    for (int s = 0; s < PAT_ELL_MAX; ++s) {
+      const unsigned col = s < p.ne ? (unsigned)p.pcol[(size_t)s * mp + k] : 0u;
+      c8[(size_t)k * (PAT_ELL_MAX / 4) + s / 4] |= (int)((col & 0xffu) << (8 * (s % 4)));
+      unsigned h = 0xffffu;
+      if (s < p.net && p.ptpos[(size_t)s * mp + k] >= 0) {
+        const int o = p.ptpos[(size_t)s * mp + k];
+        h = (unsigned)((o / mp - F_BAND) << 8 | (o % mp));
+      }
+      t16[(size_t)k * (PAT_ELL_MAX / 2) + s / 2] |= (int)(h << (16 * (s % 2)));
+    }
+  }
+}
+
 void pattern_mat_tables(const PatternPlan& p, std::vector<int>& out, const int* dev, Mesh* g) {
   out.clear();
   auto add = [&](const std::vector<int>& v) -> const int* {
@@ -310,9 +353,11 @@ void pattern_mat_tables(const PatternPlan& p, std::vector<int>& out, const int* 
     while (out.size() % 64) out.push_back(0);
     return dev ? dev + o : nullptr;
   };
-  g->pcol = add(p.pcol);
-  g->ptpos = add(p.ptpos);
-  g->ptcol = add(p.ptcol);
+  std::vector<int> c8, t16;
+  pattern_lane_tables(p, c8, t16);
+  g->pcol = add(c8);
+  g->ptpos = add(t16);
+  g->ptcol = nullptr;
   g->ppack = add(p.pack);
   g->perow = add(p.erow);
   g->pecol = add(p.ecol);

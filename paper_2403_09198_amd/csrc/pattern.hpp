@@ -43,6 +43,12 @@ struct PatternPlan {
   std::vector<int> urow_ptr, urow_pos, urow_col, urow_oc;
   std::vector<int> lcol_ptr, lcol_pos, lcol_row, lcol_or;
   std::vector<int> ucol_ptr, ucol_pos, ucol_or;
+  // The two solves as flat operation streams (forward then backward sweep),
+  // 2 ints per operation: (factor position or -1, kind << 16 | index) with
+  // kind PAT_OP_START (acc = v[index]), PAT_OP_UPD (acc -= F[pos] v[index])
+  // or PAT_OP_END (v[index] = acc, times F[pos] when pos >= 0).  ops_n
+  // solves A0 x = r, ops_t A0^T x = r.
+  std::vector<int> ops_n, ops_t;
 };
 
 // Validates the CSR pattern (m + 1 row pointers from 0, columns in range,
@@ -54,6 +60,12 @@ int build_pattern_plan(int m, const int* indptr, const int* indices, PatternPlan
 // The LU tables in one int array (the order of PatLU's members) and their
 // offsets; `dev` is where the array will live, for the pointers.
 void pattern_lu_tables(const PatternPlan& p, std::vector<int>& out, const int* dev, PatLU* lu);
+
+// The ELL tables as the kernels read them, one lane's slots together: c8
+// [mp][PAT_ELL_MAX / 4] (the column of slot s of lane k in byte s), t16 [mp]
+// [PAT_ELL_MAX / 2] (transposed slot s of lane (column) k in halfword s:
+// the entry's ELL slot << 8 | its row, 0xffff for none).
+void pattern_lane_tables(const PatternPlan& p, std::vector<int>& c8, std::vector<int>& t16);
 
 // The matvec tables in one int array and the Mesh pointers into `dev`.
 void pattern_mat_tables(const PatternPlan& p, std::vector<int>& out, const int* dev, Mesh* g);

@@ -89,11 +89,12 @@ struct Mesh {
   const int* tslot;
   const int* offb;
   // general pattern of S_cc (pat = 1): ne ELL rows from fb, ns dense indices
-  // px[t] (column row fa + t, row row fa + ns + t); shared int tables:
-  // pcol [ne][mp] ELL columns, ptpos / ptcol [net][mp] the transposed ELL
-  // (record offset of the value, -1, and its row), ppack [1 + ne + 2 ns][mp]
-  // entry feeding each record element (-1), perow / pecol / peoff [nnz] the
-  // entries' coordinates and record offsets, pdense [m][m] entry at (i, j)
+  // px[t] (column row fa + t, row row fa + ns + t); shared tables: pcol
+  // [mp][4] the ELL columns of a lane as 16 bytes, ptpos [mp][8] the
+  // transposed ELL of a lane as 16 halfwords (slot << 8 | row, 0xffff for
+  // none), ppack [1 + ne + 2 ns][mp] entry feeding each record element (-1),
+  // perow / pecol / peoff [nnz] the entries' coordinates and record offsets,
+  // pdense [m][m] entry at (i, j); ptcol unused
   int pat, ne, net, ns, pnnz;
   int px[PAT_SLOTS_MAX];
   const int *pcol, *ptpos, *ptcol, *ppack, *perow, *pecol, *peoff, *pdense;
@@ -102,8 +103,10 @@ struct Mesh {
 // Tables of the LU of a general pattern (see pattern.hpp): perm (new ->
 // original index), frec (record offset of each factor position, -1 for
 // fill), dpos, posF [m][m], strict L and U by rows and by columns.
+constexpr int PAT_OP_UPD = 0, PAT_OP_START = 1, PAT_OP_END = 2;
 struct PatLU {
-  int nnzF;
+  int nnzF, nops_n, nops_t;
+  const int *ops_n, *ops_t;  // flat solve streams (see pattern.hpp)
   const int *perm, *frec, *dpos, *posF;
   const int *lrow_ptr, *lrow_pos, *lrow_oc;
   const int *urow_ptr, *urow_pos, *urow_col, *urow_oc;
@@ -673,40 +676,50 @@ struct PatLane {
   __device__ inline void load(const Mesh& g, const TV* rc, int kk) {
     const long long mp = g.mp;
     const int n = TRANS ? g.net : g.ne;
+    // the lane's packed columns (forward) or slot/row halfwords (transposed)
+    unsigned w[PAT_ELL_MAX / 2];
+    if (TRANS) {
+      const uint4* t = reinterpret_cast<const uint4*>(g.ptpos + kk * (PAT_ELL_MAX / 2));
+      const uint4 t0 = t[0], t1 = t[1];
+      w[0] = t0.x; w[1] = t0.y; w[2] = t0.z; w[3] = t0.w;
+      w[4] = t1.x; w[5] = t1.y; w[6] = t1.z; w[7] = t1.w;
+    } else {
+      const uint4 c = *reinterpret_cast<const uint4*>(g.pcol + kk * (PAT_ELL_MAX / 4));
+      w[0] = c.x; w[1] = c.y; w[2] = c.z; w[3] = c.w;
+    }
 #pragma unroll
     for (int s = 0; s < PAT_ELL_MAX; ++s) {
       a[s] = TV(0);
       col[s] = kk;
       if (s < n) {
         if (TRANS) {
-          const int pos = g.ptpos[s * mp + kk];
-          col[s] = g.ptcol[s * mp + kk];
-          a[s] = pos >= 0 ? rc[pos] : TV(0);
+          const unsigned h = (w[s >> 1] >> (16 * (s & 1))) & 0xffffu;
+          const bool on = h != 0xffffu;
+          col[s] = on ? (int)(h & 0xffu) : kk;
+          a[s] = on ? rc[(g.fb + (int)(h >> 8)) * mp + (h & 0xffu)] : TV(0);
         } else {
           a[s] = rc[(g.fb + s) * mp + kk];
-          col[s] = g.pcol[s * mp + kk];
+          col[s] = (int)((w[s >> 2] >> (8 * (s & 3))) & 0xffu);
         }
       }
     }
   }
+  // (guards instead of an early exit, so that the loops unroll and the
+  // slots stay in registers)
   __device__ inline TV apply(const Mesh& g, const double* xc) const {
     const int n = TRANS ? g.net : g.ne;
     TV s = TV(0);
 #pragma unroll
-    for (int t = 0; t < PAT_ELL_MAX; ++t) {
-      if (t >= n) break;
-      s += a[t] * (TV)xc[col[t]];
-    }
+    for (int t = 0; t < PAT_ELL_MAX; ++t)
+      if (t < n) s += a[t] * (TV)xc[col[t]];
     return s;
   }
   __device__ inline TV apply_lanes(const Mesh& g, TV xk) const {
     const int n = TRANS ? g.net : g.ne;
     TV s = TV(0);
 #pragma unroll
-    for (int t = 0; t < PAT_ELL_MAX; ++t) {
-      if (t >= n) break;
-      s += a[t] * __shfl(xk, col[t], WAVE);
-    }
+    for (int t = 0; t < PAT_ELL_MAX; ++t)
+      if (t < n) s += a[t] * __shfl(xk, col[t], WAVE);
     return s;
   }
 };

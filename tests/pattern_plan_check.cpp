@@ -97,6 +97,25 @@ static void check_plan(int m, const std::vector<int>& ip, const std::vector<int>
     const bool ell = f >= fb && f < fa;
     CHECK(tcount[e] == (ell ? 1 : 0), "entry %d in the transposed ELL %d times", e, tcount[e]);
   }
+  // the packed lane tables the kernels read decode to the same slots
+  std::vector<int> c8, t16;
+  pattern_lane_tables(P, c8, t16);
+  for (int k = 0; k < m; ++k)
+    for (int s = 0; s < PAT_ELL_MAX; ++s) {
+      const unsigned cw = (unsigned)c8[(size_t)k * (PAT_ELL_MAX / 4) + s / 4];
+      const int col = (int)((cw >> (8 * (s % 4))) & 0xffu);
+      if (s < P.ne) CHECK(col == P.pcol[(size_t)s * mp + k], "packed column slot %d lane %d", s, k);
+      const unsigned tw = (unsigned)t16[(size_t)k * (PAT_ELL_MAX / 2) + s / 2];
+      const unsigned h = (tw >> (16 * (s % 2))) & 0xffffu;
+      const int o = s < P.net ? P.ptpos[(size_t)s * mp + k] : -1;
+      if (o < 0) {
+        CHECK(h == 0xffffu, "packed transposed slot %d lane %d should be empty", s, k);
+      } else {
+        CHECK((int)((F_BAND + (h >> 8)) * mp + (h & 0xffu)) == o &&
+                  (int)(h & 0xffu) == P.ptcol[(size_t)s * mp + k],
+              "packed transposed slot %d lane %d", s, k);
+      }
+    }
   // LU tables
   const int nF = P.nnzF;
   std::vector<int> isperm(m, 0);
@@ -171,11 +190,34 @@ static void check_plan(int m, const std::vector<int>& ip, const std::vector<int>
       }
     }
   };
+  // the flat operation streams the apply kernel runs
+  auto stream = [&](bool trans, std::vector<double>& v) -> bool {
+    const std::vector<int>& ops = trans ? P.ops_t : P.ops_n;
+    double acc = 0.0;
+    for (size_t e = 0; e + 1 < ops.size(); e += 2) {
+      const int pos = ops[e], kind = ops[e + 1] >> 16, idx = ops[e + 1] & 0xffff;
+      if (idx < 0 || idx >= m || pos < -1 || pos >= nF) return false;
+      if (kind == PAT_OP_UPD) {
+        if (pos < 0) return false;
+        acc -= F[pos] * v[idx];
+      } else if (kind == PAT_OP_START) {
+        acc = v[idx];
+      } else if (kind == PAT_OP_END) {
+        v[idx] = pos >= 0 ? acc * F[pos] : acc;
+      } else {
+        return false;
+      }
+    }
+    return true;
+  };
   for (int trans = 0; trans < 2; ++trans) {
     std::vector<double> b(m), x(m);
     for (int i = 0; i < m; ++i) b[i] = nd(gen);
     x = b;
     solve(trans, x);
+    std::vector<double> xs = b;
+    CHECK(stream(trans, xs), "stream (trans %d) out of range", trans);
+    for (int i = 0; i < m; ++i) CHECK(xs[i] == x[i], "stream (trans %d) differs at %d", trans, i);
     // residual of A x = b (A^T x = b) against |A| |x| + |b|
     double worst = 0.0;
     for (int i = 0; i < m; ++i) {
