@@ -827,6 +827,59 @@ def c2_block(torch, steps, warm):
     return out
 
 
+def solve_timeline(torch, reps=3):
+    """GMRES(50) solves of the 256 x 128, L = 61 system to 1e-10, each
+    between two torch marker kernels (an add before, a multiply after) so
+    that a kernel trace separates them; prints each solve's host wall time."""
+    from paper_2403_09198_amd import gen, r1s
+
+    dev = "cuda:0"
+    w = gen.WORKLOADS["mesh256x128_L61"]
+    p = gen.make_problem(w.nx, w.ny, w.L, seed=w.seed)
+    A = r1s.R1Matrix(w.nx, w.ny, w.L, {k: torch.from_numpy(p[k]).to(dev) for k in gen.FIELDS})
+    M = r1s.SMWPreconditioner(A)
+    b = torch.from_numpy(gen.make_rhs(w.nx, w.ny, w.L, seed=w.seed)).to(dev)
+    for _ in range(3):
+        r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol)
+    mark = torch.zeros(1, device=dev)
+    torch.cuda.synchronize()
+    for rep in range(reps):
+        mark.add_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = r1s.gmres(A, M, b, restart=w.restart, rtol=w.rtol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mark.mul_(2.0)
+        torch.cuda.synchronize()
+        print(json.dumps({"solve": rep, "wall_ms": round((t1 - t0) * 1e3, 3),
+                          "iters": res.stats[0]["iters"]}), flush=True)
+
+
+def summarize_timeline(csv_path):
+    """Per solve of a --solve-timeline trace: the span from its first kernel's
+    start to its last kernel's end, the sum of its kernel durations, and the
+    device idle time in between (host round trips and launch gaps)."""
+    import csv
+    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Start_Timestamp"]))
+    seg, segs = None, []
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "vectorized_elementwise" in name and "add" in name.lower() and seg is None:
+            seg = []
+        elif "vectorized_elementwise" in name and "Mul" in name and seg is not None:
+            segs.append(seg)
+            seg = None
+        elif seg is not None:
+            seg.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    for i, sg in enumerate(segs):
+        span = (sg[-1][1] - sg[0][0]) / 1e3
+        busy = sum(e - b for b, e in sg) / 1e3
+        print(json.dumps({"solve": i, "kernels": len(sg), "span_us": round(span, 1),
+                          "kernel_us": round(busy, 1), "idle_us": round(span - busy, 1),
+                          "idle_pct": round(100 * (span - busy) / span, 2)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -852,7 +905,20 @@ def main():
                     help="512x256 level sweep against the BSR baseline (one JSON line per case)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the fixed kernel sequence used for hardware-counter runs")
+    ap.add_argument("--solve-timeline", action="store_true",
+                    help="three 256x128, L=61 GMRES solves between marker kernels (for a "
+                         "kernel trace) and their unprofiled wall times")
+    ap.add_argument("--summarize-timeline", metavar="KERNEL_TRACE_CSV",
+                    help="device idle time between the kernels of each solve of a "
+                         "--solve-timeline kernel trace")
     args = ap.parse_args()
+    if args.summarize_timeline:
+        summarize_timeline(args.summarize_timeline)
+        return
+    if args.solve_timeline:
+        import torch
+        solve_timeline(torch)
+        return
     if args.summarize_counters:
         summarize_counters(args.workload, *args.summarize_counters)
         return

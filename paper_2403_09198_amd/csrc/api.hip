@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -1150,18 +1151,48 @@ static int op_residual(const OpCtx& c, const double* b, const double* x, double*
   return R1S_OK;
 }
 
+// Waits until flag[0 .. count) all equal val (flags raised by kernels in
+// pinned host memory, see k_dcgs_small / k_stage_flag): a spin instead of an
+// event, which would put a barrier between the kernels of consecutive
+// steps.  After two seconds it synchronises the stream, after which the
+// flags must be set.
+static int spin_flags(const int* f, int count, int val, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned it = 1;; ++it) {
+    bool ok = true;
+    for (int r = 0; r < count && ok; ++r) ok = __atomic_load_n(f + r, __ATOMIC_ACQUIRE) == val;
+    if (ok) return R1S_OK;
+    if ((it & 4095) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int r = 0; r < count; ++r)
+        if (__atomic_load_n(f + r, __ATOMIC_ACQUIRE) != val)
+          return fail(R1S_ERR_HIP, "staging flag %d not raised after the stream drained", r);
+      return R1S_OK;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 // Norms of nrhs contiguous vectors of length n (deterministic, float64).
 // |v_r| per right-hand side (|v_r|^2 stays in W.scal); `pinned` (nrhs
-// doubles of pinned host memory, or null) receives the device copy.
+// doubles of pinned host memory, or null) receives the device copy, and
+// with `flag` (pinned) the host spins on flag[0] == seq instead of
+// synchronising the stream.
 static int norms(const Mesh& g, GmresWork& W, const double* v, int nrhs, hipStream_t s,
-                 std::vector<double>& out, double* pinned = nullptr) {
+                 std::vector<double>& out, double* pinned = nullptr, int* flag = nullptr,
+                 int seq = 0) {
   Basis none{W.V, 0, 0};
   HIP_TRY(launch_multidot(none, 0, v, g.n, g.n, nrhs, W.part, W.nblk, true, s));
-  HIP_TRY(launch_reduce(W.part, nrhs, W.nblk, W.scal, s));
   out.assign(nrhs, 0.0);
   double* dst = pinned ? pinned : out.data();
-  HIP_TRY(hipMemcpyAsync(dst, W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (flag && pinned) {  // one kernel reduces, hands the norms over and raises the flag
+    HIP_TRY(launch_reduce_host(W.part, nrhs, W.nblk, W.scal, pinned, flag, seq, s));
+    if (int e = spin_flags(flag, 1, seq, s)) return e;
+  } else {
+    HIP_TRY(launch_reduce(W.part, nrhs, W.nblk, W.scal, s));
+    HIP_TRY(hipMemcpyAsync(dst, W.scal, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   for (int r = 0; r < nrhs; ++r) out[r] = sqrt(dst[r]);
   return R1S_OK;
 }
@@ -1218,13 +1249,22 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   double* kstage[2];  // written by the kernels
   double* pin_norm = nullptr;
   double* pin_y = nullptr;
+  // ready flags in pinned memory: [2][nrhs] for the step slots (delayed
+  // scheme), one for the norms; zeroed per solve, raised with increasing
+  // sequence numbers
+  int* pin_flag = nullptr;
+  const int nflags = 2 * nrhs + 1;
   if (!sd) {
-    if (int e = staging_acquire((2 * slot_doubles + nrhs + y_doubles) * sizeof(double), &lease.st))
+    const size_t flag_doubles = (size_t)(nflags + 1) / 2;
+    if (int e = staging_acquire((2 * slot_doubles + nrhs + y_doubles + flag_doubles) * sizeof(double),
+                                &lease.st))
       return e;
     stage[0] = kstage[0] = (double*)lease.st->mem;
     stage[1] = kstage[1] = (double*)lease.st->mem + slot_doubles;
     pin_norm = (double*)lease.st->mem + 2 * slot_doubles;
     pin_y = pin_norm + nrhs;
+    pin_flag = (int*)(pin_y + y_doubles);
+    for (int i = 0; i < nflags; ++i) __atomic_store_n(pin_flag + i, 0, __ATOMIC_RELAXED);
   } else {
     host_slots.assign(2 * slot_doubles, 0.0);
     stage[0] = host_slots.data();
@@ -1232,8 +1272,18 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     kstage[0] = sd->dev[0];
     kstage[1] = sd->dev[1];
   }
-  // a step's kernels are queued: mark its slot; the host needs a slot: wait
+  // a step's kernels are queued: mark its slot; the host needs a slot: wait.
+  // The delayed scheme's steps raise ready flags (want[slot] is the sequence
+  // number of the step in the slot); the other schemes record events.
+  const bool flags = pin_flag && delayed;
+  int seq = 0, want[2] = {0, 0};
+  auto step_flag = [&](int slot) -> int* {
+    if (!flags) return nullptr;
+    want[slot] = ++seq;
+    return pin_flag + slot * nrhs;
+  };
   auto mark = [&](int slot) -> int {
+    if (flags) return R1S_OK;
     if (!sd) {
       HIP_TRY(hipEventRecord(lease.st->ev[slot], s));
     } else {
@@ -1243,6 +1293,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     return R1S_OK;
   };
   auto wait = [&](int slot) -> int {
+    if (flags) return spin_flags(pin_flag + slot * nrhs, nrhs, want[slot], s);
     if (!sd) {
       HIP_TRY(hipEventSynchronize(lease.st->ev[slot]));
     } else {
@@ -1250,12 +1301,28 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     }
     return R1S_OK;
   };
-  std::vector<double> bnorm;
-  if (!x0_given) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
-  if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm)) return e;  // leaves |b|^2 in W.scal
+  int* norm_flag = pin_flag ? pin_flag + 2 * nrhs : nullptr;
+  std::vector<double> bnorm(nrhs, 0.0);
   st.assign(nrhs, SolveStat());
-  for (int r = 0; r < nrhs; ++r)
-    if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
+  // |b| (|b|^2 stays in W.scal).  Starting from zero with ready flags, the
+  // first cycle is queued without waiting for it: the host takes |b| from
+  // pinned memory at its first wait (b_pending), so that the device runs
+  // the norm, v_0 and the first steps back to back.
+  // With it, the first cycle always runs and its update writes x (x = M V y
+  // in place of x += M V y), so x needs no clearing.
+  const int b_seq = ++seq;
+  bool b_pending = !x0_given && flags;
+  const bool x_set_by_update = b_pending;
+  if (!x0_given && !b_pending) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
+  if (b_pending) {
+    Basis none{W.V, 0, 0};
+    HIP_TRY(launch_multidot(none, 0, b, g.n, g.n, nrhs, W.part, W.nblk, true, s));
+    HIP_TRY(launch_reduce_host(W.part, nrhs, W.nblk, W.scal, pin_norm, norm_flag, b_seq, s));
+  } else {
+    if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm, norm_flag, b_seq)) return e;
+    for (int r = 0; r < nrhs; ++r)
+      if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
+  }
   // vector-major basis [k + 1][nrhs][n]: v_j of every right-hand side is one
   // contiguous [nrhs][n] block, the layout the operator kernels take
   Basis Vb{W.V, (long long)nrhs * n, n};
@@ -1286,10 +1353,15 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       beta = bnorm;
     } else {
       if (int e = op_residual(c, b, x, W.w, nrhs)) return e;
-      if (int e = norms(g, W, W.w, nrhs, s, beta, pin_norm)) return e;
+      if (int e = norms(g, W, W.w, nrhs, s, beta, pin_norm, norm_flag, ++seq)) return e;
     }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
+      if (b_pending) {  // |b| not known yet: every right-hand side runs (see b_arrived)
+        done[r] = 0;
+        all = false;
+        continue;
+      }
       if (!(beta[r] == beta[r]) || isinf(beta[r])) return fail(R1S_ERR_NONFINITE, "residual of right-hand side %d is not finite", r);
       st[r].rel = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
       st[r].converged = beta[r] <= rtol * bnorm[r];
@@ -1303,6 +1375,29 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       for (int i = 0; i <= k; ++i) gv[(size_t)r * (k + 1) + i] = 0.0;
       gv[(size_t)r * (k + 1)] = beta[r];
     }
+    // the first cycle's |b| has reached the host (called after each wait of
+    // the cycle): fill in what the cycle start left open; a zero right-hand
+    // side is solved by x = 0 and takes no part in the cycle
+    std::vector<char> zero_b(nrhs, 0);
+    auto b_arrived = [&]() -> int {
+      if (!b_pending) return R1S_OK;
+      if (int e = spin_flags(norm_flag, 1, b_seq, s)) return e;
+      b_pending = false;
+      for (int r = 0; r < nrhs; ++r) {
+        bnorm[r] = sqrt(pin_norm[r]);
+        if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
+        beta[r] = bnorm[r];
+        gv[(size_t)r * (k + 1)] = beta[r];
+        st[r].rel = bnorm[r] > 0 ? 1.0 : 0.0;
+        if (bnorm[r] == 0.0) {
+          st[r].converged = true;
+          st[r].cycles = 0;
+          done[r] = 1;
+          zero_b[r] = 1;
+        }
+      }
+      return R1S_OK;
+    };
     // v_0 = r / |r|, the squared norms still in W.scal from the last norms()
     HIP_TRY(launch_scale_unit(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
 
@@ -1402,8 +1497,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         if (int e = prec_apply(c, W.V + (long long)j * Vb.vstride, W.z, nrhs)) return e;
         if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
         HIP_TRY(launch_dcgs_dots(Vb, j, W.w, n, n, nrhs, W.part, W.nblk, s));
+        int* fl = step_flag(j & 1);
         HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, kstage[j & 1], SS,
-                                  false, nrhs, s));
+                                  false, nrhs, s, fl, want[j & 1]));
         HIP_TRY(launch_dcgs_update(Vb, j, k, W.dstate, W.dstride, W.w, n, n, nrhs, s));
         return mark(j & 1);
       };
@@ -1412,11 +1508,21 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
           if (lastcol[r] == -1) return false;
         return true;
       };
+      // after each wait: the first cycle's |b| (a zero right-hand side stops)
+      auto arrived = [&]() -> int {
+        const bool was = b_pending;
+        if (int e = b_arrived()) return e;
+        if (was)
+          for (int r = 0; r < nrhs; ++r)
+            if (zero_b[r]) lastcol[r] = -2;
+        return R1S_OK;
+      };
       bool stopped = false;
       for (int j = 0; j < k && !stopped; ++j) {
         if (int e = launch_step(j)) return e;
         if (j == 0) continue;
         if (int e = wait((j - 1) & 1)) return e;
+        if (int e = arrived()) return e;
         if (j >= 2) final_col(j - 2, stage[(j - 1) & 1]);
         trial(j - 1, stage[(j - 1) & 1]);
         if (all_stopped()) {  // the final column j - 1 comes from step j
@@ -1429,12 +1535,14 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         // the cycle's last step k - 1: its final column needs one more
         // reduction on u_k (slot k), without the operator
         if (int e = wait((k - 1) & 1)) return e;
+        if (int e = arrived()) return e;
         if (k >= 2) final_col(k - 2, stage[(k - 1) & 1]);
         trial(k - 1, stage[(k - 1) & 1]);
         const double* uk = W.V + (long long)k * Vb.vstride;
         HIP_TRY(launch_dcgs_dots(Vb, k, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
+        int* fl = step_flag(k & 1);
         HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, kstage[k & 1], SS,
-                                  true, nrhs, s));
+                                  true, nrhs, s, fl, want[k & 1]));
         if (int e = mark(k & 1)) return e;
         if (int e = wait(k & 1)) return e;
         final_col(k - 1, stage[k & 1]);
@@ -1490,6 +1598,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       if (int e = wait(pending & 1)) return e;
       process(pending);
     }
+    if (int e = b_arrived()) return e;  // (done by the first wait of the cycle)
     // y = R^{-1} g per rhs; x += M (V y)
     std::fill(y.begin(), y.end(), 0.0);
     for (int r = 0; r < nrhs; ++r) {
@@ -1511,8 +1620,12 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, jend[r]);
     HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
-    if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
-    HIP_TRY(launch_axpy(nullptr, W.z, x, n, nrhs, s));
+    if (cycle == 0 && x_set_by_update) {
+      if (int e = prec_apply(c, W.t, x, nrhs)) return e;
+    } else {
+      if (int e = prec_apply(c, W.t, W.z, nrhs)) return e;
+      HIP_TRY(launch_axpy(nullptr, W.z, x, n, nrhs, s));
+    }
   }
   return R1S_OK;
 }

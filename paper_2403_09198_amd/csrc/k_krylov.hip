@@ -108,6 +108,42 @@ __global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, 
   if (lane_id() == 0) out[row] = a;
 }
 
+// k_reduce for a few rows in one workgroup that also hands them to the
+// host: out[row] and host[row] (pinned), then flag[0] = seq once host[] is
+// visible (see stage_ready).
+__global__ __launch_bounds__(KB) void k_reduce_host(const double* __restrict__ part, int rows,
+                                                    int nblk, double* __restrict__ out,
+                                                    double* host, int* flag, int seq) {
+  for (int row = threadIdx.x >> 6; row < rows; row += KB / WAVE) {
+    const double* pr = part + (long long)row * nblk;
+    double v[REDUCE_PER_LANE];
+#pragma unroll
+    for (int t = 0; t < REDUCE_PER_LANE; ++t) {
+      const int b = lane_id() + t * WAVE;
+      v[t] = b < nblk ? pr[b] : 0.0;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < REDUCE_PER_LANE; ++t) a += v[t];
+    a = wave_sum(a);
+    if (lane_id() == 0) {
+      out[row] = a;
+      host[row] = a;
+    }
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_reduce_host(const double* part, int rows, int nblk, double* out, double* host,
+                              int* flag, int seq, hipStream_t s) {
+  if (nblk > REDUCE_PER_LANE * WAVE) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_host, dim3(1), dim3(KB), 0, s, part, rows, nblk, out, host, flag,
+                     seq);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hipStream_t s) {
   if (nblk > REDUCE_PER_LANE * WAVE) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce, dim3((rows + KB / WAVE - 1) / (KB / WAVE)), dim3(KB), 0, s, part,
@@ -459,10 +495,19 @@ __device__ inline void block_sum3(double& x, double& y, double& z, double (*sh)[
   __syncthreads();
 }
 
+// Raises flag[r] = seq once the block's staging writes are visible to the
+// host (each thread fenced at system scope before the barrier); the host
+// spins on the flags instead of waiting for an event.
+__device__ inline void stage_ready(int* flag, int r, int seq) {
+  __syncthreads();
+  if (flag && threadIdx.x == 0)
+    __hip_atomic_store(flag + r, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* __restrict__ part,
                                                    int nblk, double* __restrict__ dstate,
                                                    long long dstride, double* stage, int sstride,
-                                                   int final_only) {
+                                                   int final_only, int* flag, int seq) {
   extern __shared__ double red[];  // the 2j + 3 sums, then t [j + 1]
   __shared__ double bs[3][KB / WAVE];
   const int r = blockIdx.x, rows = 2 * j + 3, tid = threadIdx.x;
@@ -521,6 +566,7 @@ __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* _
       st[2 * K + 5] = brk ? 1.0 : 0.0;
     }
     __threadfence_system();
+    stage_ready(flag, r, seq);
     return;
   }
   __syncthreads();  // column j - 1 of H written before it is read below
@@ -565,14 +611,28 @@ __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* _
     st[2 * K + 5] = brk ? 1.0 : 0.0;
   }
   __threadfence_system();
+  stage_ready(flag, r, seq);
 }
 
 hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double* dstate,
                              long long dstride, double* stage, int sstride, bool final_only,
-                             int nrhs, hipStream_t s) {
+                             int nrhs, hipStream_t s, int* flag, int seq) {
   if (nblk > REDUCE_PER_LANE * WAVE) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_dcgs_small, dim3(nrhs), dim3(KB), (size_t)(3 * j + 4) * sizeof(double), s,
-                     j, K, part, nblk, dstate, dstride, stage, sstride, (int)final_only);
+                     j, K, part, nblk, dstate, dstride, stage, sstride, (int)final_only, flag,
+                     seq);
+  return hipGetLastError();
+}
+
+// flag[0] = seq after everything before it on the stream (a device-to-host
+// copy into pinned memory, say) has completed.
+__global__ void k_stage_flag(int* flag, int seq) {
+  __threadfence_system();
+  __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_stage_flag(int* flag, int seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_flag, dim3(1), dim3(1), 0, s, flag, seq);
   return hipGetLastError();
 }
 

@@ -135,6 +135,10 @@ int dot_blocks(long long n);
 hipError_t launch_multidot(Basis B, int nv, const double* w, long long wstride, long long n,
                            int nrhs, double* part, int nblk, bool with_norm, hipStream_t s);
 hipError_t launch_reduce(const double* part, int rows, int nblk, double* out, hipStream_t s);
+// the same in one workgroup, also writing host[row] (pinned) and then
+// flag[0] = seq (see launch_stage_flag)
+hipError_t launch_reduce_host(const double* part, int rows, int nblk, double* out, double* host,
+                              int* flag, int seq, hipStream_t s);
 int update_multidot_max();
 hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride, double* w,
                                   long long wstride, long long n, int nrhs, double* part, int nblk,
@@ -144,9 +148,13 @@ hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* 
 // Delayed reorthogonalisation (one reduction per Arnoldi step; k_krylov.hip)
 hipError_t launch_dcgs_dots(Basis B, int j, const double* w, long long wstride, long long n,
                             int nrhs, double* part, int nblk, hipStream_t s);
+// flag (pinned host memory, or null): flag[r] = seq once right-hand side r's
+// staging is visible to the host
 hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double* dstate,
                              long long dstride, double* stage, int sstride, bool final_only,
-                             int nrhs, hipStream_t s);
+                             int nrhs, hipStream_t s, int* flag = nullptr, int seq = 0);
+// flag[0] = seq once the stream's earlier work has completed
+hipError_t launch_stage_flag(int* flag, int seq, hipStream_t s);
 hipError_t launch_dcgs_update(Basis B, int j, int K, const double* dstate, long long dstride,
                               const double* w, long long wstride, long long n, int nrhs,
                               hipStream_t s);

@@ -228,6 +228,25 @@ def test_nonfinite_rhs_is_reported():
     assert ei.value.code == R1S_ERR_NONFINITE
 
 
+def test_batch_with_a_zero_rhs_in_float64():
+    # the first cycle starts before |b| reaches the host: a zero right-hand
+    # side must still end with x = 0, converged, no iterations, while the
+    # other one solves
+    nx, ny, L = 6, 5, 9
+    p = gen.make_problem(nx, ny, L, seed=3)
+    A = r1s.R1Matrix(nx, ny, L, to_dev(p))
+    M = r1s.SMWPreconditioner(A)
+    b = gen.make_rhs(nx, ny, L, nrhs=2, seed=3)
+    b[0] = 0.0
+    res = r1s.gmres(A, M, vec(b), rtol=1e-12)
+    x = host(res.x)
+    assert float(np.abs(x[0]).max()) == 0.0
+    assert res.stats[0]["converged"] == 1 and res.stats[0]["iters"] == 0
+    assert res.stats[1]["converged"] == 1 and res.stats[1]["iters"] > 0
+    J = ops.dense_matrix(p, nx, ny, L)
+    assert relnorm(x[1].ravel(), np.linalg.solve(J, b[1].ravel())) <= 1e-10
+
+
 def test_zero_rhs_gives_zero():
     nx, ny, L = 3, 3, 4
     p = gen.make_problem(nx, ny, L, seed=1)
