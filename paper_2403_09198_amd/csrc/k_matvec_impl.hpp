@@ -60,7 +60,8 @@ __device__ inline Mesh kmesh(Mesh g) {
 // taking right-hand sides r0 + NR .. r0 + 2 NR - 1 (the cell's rows come
 // from HBM once and from L2 for the second wave; half the registers of one
 // wave holding all 2 NR).
-template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, int WIDE>
+template <typename TV, int NCH, int NR, bool TRANS, bool RESID, int RDM, int ROM, int WIDE,
+          bool SHARED = false>
 __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restrict__ rec,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     for (int d = 0; d < 5; ++d) {
 #pragma unroll
       for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-        pv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
+        pv[d][p][ch] = p < cnt[d] ? ld_mat<SHARED>(R.base[d] + (R.coef0[d] + p) * mp + kk) : TV(0);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         xv[r][d][ch] = (TV)xr[(long long)r * g.n + (long long)nbc[d] * m + kk];
@@ -139,10 +140,10 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
       pa = L + (i + 2) % 3; va = true;
       pb = L + (i + 1) % 3; vb = true;
     }
-    dg[ch] = ld_stream(R.rc + F_DIAG * mp + kk);
+    dg[ch] = ld_mat<SHARED>(R.rc + F_DIAG * mp + kk);
     if (!TRANS) {  // row k of S_cc: lo at column pa, hi at column pb
-      ca[ch] = ld_stream(R.rc + F_LO * mp + kk);
-      cb[ch] = ld_stream(R.rc + F_HI * mp + kk);
+      ca[ch] = ld_mat<SHARED>(R.rc + F_LO * mp + kk);
+      cb[ch] = ld_mat<SHARED>(R.rc + F_HI * mp + kk);
     } else {       // column k of S_cc: hi of row pa, lo of row pb
       const TV ta = R.rc[F_HI * mp + pa];
       const TV tb = R.rc[F_LO * mp + pb];
@@ -151,10 +152,10 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
     }
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      if (d != D_C) nv[d][ch] = ld_stream(R.base[d] + R.nbr[d] * mp + kk);
+      if (d != D_C) nv[d][ch] = ld_mat<SHARED>(R.base[d] + R.nbr[d] * mp + kk);
 #pragma unroll
       for (int p = 0; p < (d == D_C ? RDM : ROM); ++p)
-        uv[d][p][ch] = p < cnt[d] ? ld_stream(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
+        uv[d][p][ch] = p < cnt[d] ? ld_mat<SHARED>(R.base[d] + (R.out0[d] + p) * mp + kk) : TV(0);
     }
     pa_s[ch] = pa;
     pb_s[ch] = pb;
@@ -170,8 +171,8 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         const bool on = i < nsl;
-        arw[i][ch] = ld_stream(R.rc + (on ? arrow_sum_row<TRANS>(g, i) : F_DIAG + i) * mp + kk);
-        alw[i][ch] = ld_stream(R.rc + (on ? arrow_lane_row<TRANS>(g, i) : F_NBR + i % 3) * mp + kk);
+        arw[i][ch] = ld_mat<SHARED>(R.rc + (on ? arrow_sum_row<TRANS>(g, i) : F_DIAG + i) * mp + kk);
+        alw[i][ch] = ld_mat<SHARED>(R.rc + (on ? arrow_lane_row<TRANS>(g, i) : F_NBR + i % 3) * mp + kk);
 #pragma unroll
         for (int r = 0; r < NR; ++r)
           xfl[r][i] = (TV)xr[(long long)r * g.n + (long long)c * m + arrow_unknown(L, i)];
@@ -510,7 +511,7 @@ inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
       if (rem >= 8) {  // two waves per cell, four right-hand sides each
         // (256 x 128, L = 61: 145 us against 159 us for one wave with all
         // eight at 184 registers, 2 waves per SIMD; four waves of two: 175 us)
-        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>),
+        hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE, true>),
                            dim3((2 * g.N + WPB - 1) / WPB), dim3(64 * WPB), 0, s, g, rec, x, b, y,
                            r0, 1);
         r0 += 8;

@@ -226,6 +226,18 @@ __device__ inline T ld_stream(const T* p) {
 #endif
 }
 
+// Matrix load of a kernel in which two waves of a workgroup read the same
+// record (two halves of a batch of right-hand sides): an ordinary load, so
+// that the second wave's read hits L2 instead of refetching from HBM (a
+// non-temporal line is not kept for it); else ld_stream.
+template <bool SHARED, typename T>
+__device__ inline T ld_mat(const T* p) {
+  if constexpr (SHARED)
+    return *p;
+  else
+    return ld_stream(p);
+}
+
 // Store of a kernel's output vector, non-temporal: an output written back
 // through the caches as ordinary lines competes with the streamed matrix
 // reads for HBM turnarounds.  Measured on MI355X: a streaming read with 1/16
