@@ -440,7 +440,10 @@ int r1s_gmres_work_size(r1s_mat A, const r1s_gmres_opts* opts, int nrhs,
  * estimate meets inner_rtol.
  * `B` is used when opts->op == R1S_OP_BSR (may be NULL otherwise).
  * On R1S_ERR_NOCONV, x holds the last iterate and stats are filled (one
- * r1s_gmres_stats per right-hand side, stats may be NULL). Synchronises. */
+ * r1s_gmres_stats per right-hand side, stats may be NULL).  Returns when the
+ * solve's work on `stream` is complete and x is final: after synchronising
+ * the stream, or after seeing its last kernel raise a ready flag in pinned
+ * memory (that kernel's last write). */
 int r1s_gmres(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opts,
               int nrhs, const double* b, double* x, void* work,
               size_t work_bytes, r1s_gmres_stats* stats, void* stream);

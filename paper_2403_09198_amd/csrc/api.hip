@@ -1076,9 +1076,10 @@ static int staging_acquire(size_t bytes, Staging** out) {
 struct StagingLease {
   Staging* st = nullptr;
   hipStream_t stream = nullptr;
+  bool drained = false;  // the host has seen the stream's last kernel raise its flag
   ~StagingLease() {
     if (st) {
-      (void)hipStreamSynchronize(stream);
+      if (!drained) (void)hipStreamSynchronize(stream);
       std::lock_guard<std::mutex> lk(g_staging_mu);
       g_staging_free.push_back(st);
     }
@@ -1230,7 +1231,7 @@ struct StageDev {
 static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int max_cycles,
                       double rtol, int nrhs, const double* b, double* x, bool x0_given,
                       int ortho, bool trust_estimate, std::vector<SolveStat>& st,
-                      const StageDev* sd) {
+                      const StageDev* sd, bool* drained = nullptr) {
   const bool always_reorth = ortho == R1S_ORTHO_CGS2;
   const bool delayed = ortho == R1S_ORTHO_DELAYED;
   hipStream_t s = c.s;
@@ -1304,21 +1305,17 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
   int* norm_flag = pin_flag ? pin_flag + 2 * nrhs : nullptr;
   std::vector<double> bnorm(nrhs, 0.0);
   st.assign(nrhs, SolveStat());
-  // |b| (|b|^2 stays in W.scal).  Starting from zero with ready flags, the
-  // first cycle is queued without waiting for it: the host takes |b| from
-  // pinned memory at its first wait (b_pending), so that the device runs
-  // the norm, v_0 and the first steps back to back.
+  // |b| (|b|^2 stays in W.scal).  Starting from zero, the delayed scheme
+  // queues the first cycle without it (b_pending): its step 0 normalises b
+  // itself and stages |b|^2, which the host takes at the cycle's first wait,
+  // so that the device starts with the first step.
   // With it, the first cycle always runs and its update writes x (x = M V y
   // in place of x += M V y), so x needs no clearing.
   const int b_seq = ++seq;
-  bool b_pending = !x0_given && flags;
+  bool b_pending = !x0_given && delayed;
   const bool x_set_by_update = b_pending;
   if (!x0_given && !b_pending) HIP_TRY(hipMemsetAsync(x, 0, (size_t)nrhs * n * sizeof(double), s));
-  if (b_pending) {
-    Basis none{W.V, 0, 0};
-    HIP_TRY(launch_multidot(none, 0, b, g.n, g.n, nrhs, W.part, W.nblk, true, s));
-    HIP_TRY(launch_reduce_host(W.part, nrhs, W.nblk, W.scal, pin_norm, norm_flag, b_seq, s));
-  } else {
+  if (!b_pending) {
     if (int e = norms(g, W, b, nrhs, s, bnorm, pin_norm, norm_flag, b_seq)) return e;
     for (int r = 0; r < nrhs; ++r)
       if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
@@ -1347,13 +1344,16 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         break;
       }
     }
-    // true residual of the current iterate (x0 = 0: r = b, whose norms are known)
+    // true residual of the current iterate (x0 = 0: r = b, whose norms are
+    // known); the delayed scheme takes it in basis slot 0, which its step 0
+    // normalises in place (the operator's output w would overwrite it)
     const bool from_b = cycle == 0 && !x0_given;
+    double* rv = delayed ? W.V : W.w;
     if (from_b) {
       beta = bnorm;
     } else {
-      if (int e = op_residual(c, b, x, W.w, nrhs)) return e;
-      if (int e = norms(g, W, W.w, nrhs, s, beta, pin_norm, norm_flag, ++seq)) return e;
+      if (int e = op_residual(c, b, x, rv, nrhs)) return e;
+      if (int e = norms(g, W, rv, nrhs, s, beta, pin_norm, norm_flag, ++seq)) return e;
     }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
@@ -1368,7 +1368,15 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       done[r] = st[r].converged;
       all = all && done[r];
     }
-    if (all || cycle == max_cycles) break;
+    if (all || cycle == max_cycles) {
+      // the norms just read were the last work queued; with a ready flag the
+      // host has seen that kernel's last write, so nothing is left to wait for
+      if (pin_flag) {
+        lease.drained = true;
+        if (drained) *drained = true;
+      }
+      break;
+    }
     for (int r = 0; r < nrhs; ++r) {
       st[r].cycles += done[r] ? 0 : 1;
       jend[r] = 0;
@@ -1379,12 +1387,11 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
     // the cycle): fill in what the cycle start left open; a zero right-hand
     // side is solved by x = 0 and takes no part in the cycle
     std::vector<char> zero_b(nrhs, 0);
-    auto b_arrived = [&]() -> int {
+    auto b_arrived = [&]() -> int {  // (step 0's slot is on the host)
       if (!b_pending) return R1S_OK;
-      if (int e = spin_flags(norm_flag, 1, b_seq, s)) return e;
       b_pending = false;
       for (int r = 0; r < nrhs; ++r) {
-        bnorm[r] = sqrt(pin_norm[r]);
+        bnorm[r] = sqrt(stage[0][(size_t)r * SS]);
         if (!(bnorm[r] == bnorm[r]) || isinf(bnorm[r])) return fail(R1S_ERR_NONFINITE, "right-hand side %d is not finite", r);
         beta[r] = bnorm[r];
         gv[(size_t)r * (k + 1)] = beta[r];
@@ -1399,7 +1406,9 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       return R1S_OK;
     };
     // v_0 = r / |r|, the squared norms still in W.scal from the last norms()
-    HIP_TRY(launch_scale_unit(from_b ? b : W.w, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
+    // (the delayed scheme's step 0 normalises u0 itself)
+    const double* u0 = from_b ? b : rv;
+    if (!delayed) HIP_TRY(launch_scale_unit(u0, n, W.scal, W.V, Vb.rstride, n, nrhs, s));
 
     // Givens update of the least-squares problem with column j of H (rows
     // 0..j+1 in Hat): the previous rotations, then a new one eliminating
@@ -1494,13 +1503,14 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         }
       };
       auto launch_step = [&](int j) -> int {
-        if (int e = prec_apply(c, W.V + (long long)j * Vb.vstride, W.z, nrhs)) return e;
+        if (int e = prec_apply(c, j == 0 ? u0 : W.V + (long long)j * Vb.vstride, W.z, nrhs))
+          return e;
         if (int e = op_apply(c, W.z, W.w, nrhs)) return e;
-        HIP_TRY(launch_dcgs_dots(Vb, j, W.w, n, n, nrhs, W.part, W.nblk, s));
+        HIP_TRY(launch_dcgs_dots(Vb, j, u0, n, W.w, n, n, nrhs, W.part, W.nblk, s));
         int* fl = step_flag(j & 1);
         HIP_TRY(launch_dcgs_small(j, k, W.part, W.nblk, W.dstate, W.dstride, kstage[j & 1], SS,
                                   false, nrhs, s, fl, want[j & 1]));
-        HIP_TRY(launch_dcgs_update(Vb, j, k, W.dstate, W.dstride, W.w, n, n, nrhs, s));
+        HIP_TRY(launch_dcgs_update(Vb, j, k, W.dstate, W.dstride, u0, n, W.w, n, n, nrhs, s));
         return mark(j & 1);
       };
       auto all_stopped = [&]() {
@@ -1539,7 +1549,7 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
         if (k >= 2) final_col(k - 2, stage[(k - 1) & 1]);
         trial(k - 1, stage[(k - 1) & 1]);
         const double* uk = W.V + (long long)k * Vb.vstride;
-        HIP_TRY(launch_dcgs_dots(Vb, k, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
+        HIP_TRY(launch_dcgs_dots(Vb, k, nullptr, 0, uk, Vb.rstride, n, nrhs, W.part, W.nblk, s));
         int* fl = step_flag(k & 1);
         HIP_TRY(launch_dcgs_small(k, k, W.part, W.nblk, W.dstate, W.dstride, kstage[k & 1], SS,
                                   true, nrhs, s, fl, want[k & 1]));
@@ -1612,14 +1622,18 @@ static int gmres_core(const OpCtx& c, const Mesh& g, GmresWork& W, int k, int ma
       }
       if (!st[r].converged) est[r] = fabs(gr[je]);  // |g_je| after the rotations
     }
-    // (the next cycle's norms synchronise before pin_y is written again; a
-    // copy from pageable memory has taken the data when it returns)
-    if (pin_y) std::copy(y.begin(), y.end(), pin_y);
-    HIP_TRY(hipMemcpyAsync(W.ydev, pin_y ? pin_y : y.data(), y.size() * sizeof(double),
-                           hipMemcpyHostToDevice, s));
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, jend[r]);
-    HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
+    if ((long long)nrhs * kmax <= COMBINE_Y_MAX) {  // y passed with the launch
+      HIP_TRY(launch_combine_arg(Vb, kmax, y.data(), k + 1, W.t, n, n, nrhs, s));
+    } else {
+      // (the next cycle's norms synchronise before pin_y is written again; a
+      // copy from pageable memory has taken the data when it returns)
+      if (pin_y) std::copy(y.begin(), y.end(), pin_y);
+      HIP_TRY(hipMemcpyAsync(W.ydev, pin_y ? pin_y : y.data(), y.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(launch_combine(Vb, kmax, W.ydev, k + 1, W.t, n, n, nrhs, s));
+    }
     if (cycle == 0 && x_set_by_update) {
       if (int e = prec_apply(c, W.t, x, nrhs)) return e;
     } else {
@@ -1668,9 +1682,10 @@ static int gmres_run(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opt
   std::vector<SolveStat> st;
   int outer = 0;
   int rc;
+  bool drained = false;
   if (!mixed) {
     rc = gmres_core(c, g, W, opts->restart, opts->max_cycles, opts->rtol, nrhs, b, x,
-                    opts->x0_given != 0, opts->ortho, false, st, sd);
+                    opts->x0_given != 0, opts->ortho, false, st, sd, &drained);
     if (rc) return rc;
   } else {
     // iterative refinement: r = b - J x (float64), inner float32 solve J d = r
@@ -1719,7 +1734,7 @@ static int gmres_run(r1s_mat A, r1s_bsr B, r1s_prec M, const r1s_gmres_opts* opt
     }
     st = tot;
   }
-  HIP_TRY(hipStreamSynchronize(s));
+  if (!drained) HIP_TRY(hipStreamSynchronize(s));
   bool ok = true;
   for (int r = 0; r < nrhs; ++r) {
     ok = ok && st[r].converged;

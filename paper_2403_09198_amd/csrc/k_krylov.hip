@@ -349,7 +349,10 @@ hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const doub
 //   s_j = (V_{j+1}^T w - t) / r with t = H a, and
 //   u_{j+1} = (w - V_{j+1} (t + r s_j)) / (r rho_{j+1}),
 //   rho_{j+1} = sqrt(|B v_j|^2 - |s_j|^2).
-// Step 0 starts from v_0 itself (u_0 = v_0, r = 1).
+// Step 0 starts from the cycle's unnormalised starting vector u_0 (b or a
+// residual, read in place): with no basis yet, r = |u_0| and v_0 = u_0 / r,
+// so the cycle needs no separate norm and scaling before its first step
+// (the host takes |u_0|^2 from the staging of step 0).
 //
 // Device state per right-hand side (doubles, stride dstride): H column-major
 // [K][K + 1], s_{j-1} [K + 1], a [K], t + r s [K + 1], then r, 1 / (r rho),
@@ -388,14 +391,17 @@ __device__ inline void dcgs_pass(const double* Vr, long long vstride, int i, con
 }
 
 // rows of step j's reduction per right-hand side: a_0..a_{j-1}, |u|^2,
-// c_0..c_{j-1}, u . w, |w|^2
-__global__ __launch_bounds__(KB, 4) void k_dcgs_dots(Basis B, int j, const double* __restrict__ w,
+// c_0..c_{j-1}, u . w, |w|^2.  u_0 (j = 0): u0 + r u0stride when u0 is
+// given, else slot 0.
+__global__ __launch_bounds__(KB, 4) void k_dcgs_dots(Basis B, int j, const double* __restrict__ u0,
+                                                  long long u0stride,
+                                                  const double* __restrict__ w,
                                                   long long wstride, long long n,
                                                   double* __restrict__ part, int nblk) {
   __shared__ double sh[2 * DC_GROUP][KB / WAVE];
   const int r = blockIdx.y, wave = threadIdx.x >> 6, tid = threadIdx.x;
   const double* Vr = B.V + (long long)r * B.rstride;
-  const double* u = Vr + (long long)j * B.vstride;
+  const double* u = j == 0 && u0 ? u0 + (long long)r * u0stride : Vr + (long long)j * B.vstride;
   const double* wr = w + (long long)r * wstride;
   const int rows = 2 * j + 3;
   double* pr = part + (long long)r * rows * nblk;
@@ -462,10 +468,11 @@ __global__ __launch_bounds__(KB, 4) void k_dcgs_dots(Basis B, int j, const doubl
   }
 }
 
-hipError_t launch_dcgs_dots(Basis B, int j, const double* w, long long wstride, long long n,
-                            int nrhs, double* part, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblk, nrhs), dim3(KB), 0, s, B, j, w, wstride, n, part,
-                     nblk);
+hipError_t launch_dcgs_dots(Basis B, int j, const double* u0, long long u0stride, const double* w,
+                            long long wstride, long long n, int nrhs, double* part, int nblk,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblk, nrhs), dim3(KB), 0, s, B, j, u0, u0stride, w, wstride,
+                     n, part, nblk);
   return hipGetLastError();
 }
 
@@ -544,12 +551,11 @@ __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* _
     ac += a[i] * c[i];
   }
   block_sum3(aa, ac, dummy, bs);
-  double rr = 1.0;
-  bool brk = false;
+  const double r2 = alpha - aa;
+  const bool brk = !(r2 > 0.0);
+  const double rr = brk ? 1.0 : sqrt(r2);
+  if (j == 0 && tid == 0) st[0] = alpha;  // |u_0|^2 (no final column at step 0)
   if (j > 0) {
-    const double r2 = alpha - aa;
-    brk = !(r2 > 0.0);
-    rr = brk ? 1.0 : sqrt(r2);
     const double rho_prev = sc[2];
     double* col = H + (long long)(j - 1) * (K + 1);
     for (int i = tid; i <= j; i += KB) {
@@ -588,7 +594,7 @@ __global__ __launch_bounds__(KB) void k_dcgs_small(int j, int K, const double* _
   const double inv_r = 1.0 / rr;
   double td = 0.0, tt = 0.0, ss = 0.0;
   for (int i = tid; i <= j; i += KB) {
-    const double di = i < j ? c[i] : (j == 0 ? gam : (gam - ac) * inv_r);
+    const double di = i < j ? c[i] : (gam - ac) * inv_r;
     const double ti = tsh[i];
     const double si = (di - ti) * inv_r;
     td += ti * di;
@@ -636,14 +642,17 @@ hipError_t launch_stage_flag(int* flag, int seq, hipStream_t s) {
   return hipGetLastError();
 }
 
-// v_j = (u_j - V a) / r in slot j (j > 0) and u_{j+1} = (w - V_{j+1} g) / (r rho)
-// in slot j + 1, g = t + r s (device state of k_dcgs_small).
+// v_j = (u_j - V a) / r in slot j and u_{j+1} = (w - V_{j+1} g) / (r rho)
+// in slot j + 1, g = t + r s (device state of k_dcgs_small); u_0 as in
+// k_dcgs_dots.
 __global__ __launch_bounds__(KB) void k_dcgs_update(Basis B, int j, int K,
                                                     const double* __restrict__ dstate,
-                                                    long long dstride, const double* __restrict__ w,
+                                                    long long dstride, const double* u0,
+                                                    long long u0stride, const double* __restrict__ w,
                                                     long long wstride, long long n) {
   const int r = blockIdx.y;
   double* Vr = B.V + (long long)r * B.rstride;
+  const double* ur = j == 0 && u0 ? u0 + (long long)r * u0stride : Vr + (long long)j * B.vstride;
   const double* wr = w + (long long)r * wstride;
   const double* sprev = dstate + (long long)r * dstride + (long long)K * (K + 1);
   const double* aco = sprev + (K + 1);
@@ -652,24 +661,24 @@ __global__ __launch_bounds__(KB) void k_dcgs_update(Basis B, int j, int K,
   const double inv_r = 1.0 / sc[0], inv2 = sc[1], gj = gco[j];
   for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
        e += (long long)gridDim.x * KB) {
-    const double uj = Vr[(long long)j * B.vstride + e];
+    const double uj = ur[e];
     double av = uj, au = wr[e];
     for (int i = 0; i < j; ++i) {
       const double vi = Vr[(long long)i * B.vstride + e];
       av -= aco[i] * vi;
       au -= gco[i] * vi;
     }
-    const double vj = j == 0 ? uj : av * inv_r;
-    if (j > 0) Vr[(long long)j * B.vstride + e] = vj;
+    const double vj = av * inv_r;
+    Vr[(long long)j * B.vstride + e] = vj;
     Vr[(long long)(j + 1) * B.vstride + e] = (au - gj * vj) * inv2;
   }
 }
 
 hipError_t launch_dcgs_update(Basis B, int j, int K, const double* dstate, long long dstride,
-                              const double* w, long long wstride, long long n, int nrhs,
-                              hipStream_t s) {
+                              const double* u0, long long u0stride, const double* w,
+                              long long wstride, long long n, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_dcgs_update, vec_grid(n, nrhs), dim3(KB), 0, s, B, j, K, dstate, dstride,
-                     w, wstride, n);
+                     u0, u0stride, w, wstride, n);
   return hipGetLastError();
 }
 
@@ -729,6 +738,32 @@ __global__ __launch_bounds__(KB) void k_combine(Basis B, int nv, const double* _
 hipError_t launch_combine(Basis B, int nv, const double* y, int ystride, double* out,
                           long long ostride, long long n, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, y, ystride, out, ostride,
+                     n);
+  return hipGetLastError();
+}
+
+// k_combine with the coefficients passed by value (y[r * nv + i]): no copy
+// of y to the device before the launch
+__global__ __launch_bounds__(KB) void k_combine_arg(Basis B, int nv, CombineY y,
+                                                    double* __restrict__ out, long long ostride,
+                                                    long long n) {
+  const int r = blockIdx.y;
+  const double* Vr = B.V + (long long)r * B.rstride;
+  for (long long e = (long long)blockIdx.x * KB + threadIdx.x; e < n;
+       e += (long long)gridDim.x * KB) {
+    double a = 0.0;
+    for (int i = 0; i < nv; ++i) a += y.y[r * nv + i] * Vr[(long long)i * B.vstride + e];
+    out[(long long)r * ostride + e] = a;
+  }
+}
+
+hipError_t launch_combine_arg(Basis B, int nv, const double* y, int ystride, double* out,
+                              long long ostride, long long n, int nrhs, hipStream_t s) {
+  if ((long long)nrhs * nv > COMBINE_Y_MAX) return hipErrorInvalidValue;
+  CombineY ya;
+  for (int r = 0; r < nrhs; ++r)
+    for (int i = 0; i < nv; ++i) ya.y[r * nv + i] = y[(size_t)r * ystride + i];
+  hipLaunchKernelGGL(k_combine_arg, vec_grid(n, nrhs), dim3(KB), 0, s, B, nv, ya, out, ostride,
                      n);
   return hipGetLastError();
 }

@@ -146,8 +146,11 @@ hipError_t launch_update_multidot(Basis B, int nv, const double* h, int hstride,
 hipError_t launch_update(Basis B, int nv, const double* h, int hstride, double* w,
                          long long wstride, long long n, int nrhs, hipStream_t s);
 // Delayed reorthogonalisation (one reduction per Arnoldi step; k_krylov.hip)
-hipError_t launch_dcgs_dots(Basis B, int j, const double* w, long long wstride, long long n,
-                            int nrhs, double* part, int nblk, hipStream_t s);
+// u0 (or null: slot 0): the unnormalised starting vector of step 0, per
+// right-hand side at u0 + r u0stride
+hipError_t launch_dcgs_dots(Basis B, int j, const double* u0, long long u0stride, const double* w,
+                            long long wstride, long long n, int nrhs, double* part, int nblk,
+                            hipStream_t s);
 // flag (pinned host memory, or null): flag[r] = seq once right-hand side r's
 // staging is visible to the host
 hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double* dstate,
@@ -156,8 +159,8 @@ hipError_t launch_dcgs_small(int j, int K, const double* part, int nblk, double*
 // flag[0] = seq once the stream's earlier work has completed
 hipError_t launch_stage_flag(int* flag, int seq, hipStream_t s);
 hipError_t launch_dcgs_update(Basis B, int j, int K, const double* dstate, long long dstride,
-                              const double* w, long long wstride, long long n, int nrhs,
-                              hipStream_t s);
+                              const double* u0, long long u0stride, const double* w,
+                              long long wstride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_update_normalize(Basis B, int nv, const double* h1, const double* h2,
                                    int hstride, const int* need, const double* w,
                                    long long wstride, double* vout, long long n, int nrhs,
@@ -168,6 +171,13 @@ hipError_t launch_scale_unit(const double* w, long long wstride, const double* s
                              long long ostride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_combine(Basis B, int nv, const double* y, int ystride, double* out,
                           long long ostride, long long n, int nrhs, hipStream_t s);
+// the same with y in host memory passed by value (nrhs * nv <= COMBINE_Y_MAX)
+constexpr int COMBINE_Y_MAX = 64;
+struct CombineY {
+  double y[COMBINE_Y_MAX];
+};
+hipError_t launch_combine_arg(Basis B, int nv, const double* y, int ystride, double* out,
+                              long long ostride, long long n, int nrhs, hipStream_t s);
 hipError_t launch_rsub(const double* bv, double* yv, long long n, int nrhs, hipStream_t s);
 hipError_t launch_axpy(const double* alpha, const double* xv, double* yv, long long n, int nrhs,
                        hipStream_t s);
