@@ -98,17 +98,32 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec_prec(Mesh g_, const TV* __r
   if constexpr (EARLY) load_factors();
   __builtin_amdgcn_sched_barrier(0);
 
-  // y_c = (S + sum u v^T) x restricted to block row c
+  // y_c = (S + sum u v^T) x restricted to block row c (the coefficient sums
+  // as the matvec kernel forms them, so that y is bitwise its result)
   TV acc[5][RM];
+  constexpr int NSUM = RDM + 4 * ROM;
 #pragma unroll
-  for (int d = 0; d < 5; ++d)
+  for (int g0 = 0; g0 < NSUM; g0 += 4) {
+    TV s4[4];
 #pragma unroll
-    for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-      TV s = TV(0);
-      if (lane < m) s += pv[d][p] * xv[d];
-      s = wave_sum_u(s);
-      acc[d][p] = ex[d] ? s : TV(0);
+    for (int e = 0; e < 4; ++e) {
+      s4[e] = TV(0);
+      if (g0 + e < NSUM) {
+        int d, p;
+        pair_index<RDM, ROM>(g0 + e, d, p);
+        if (lane < m) s4[e] += pv[d][p] * xv[d];
+      }
     }
+    wave_sums_u(s4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (g0 + e < NSUM) {
+        int d, p;
+        pair_index<RDM, ROM>(g0 + e, d, p);
+        acc[d][p] = ex[d] ? s4[e] : TV(0);
+      }
+    }
+  }
   const TV xa = __shfl(xv[D_C], pa, WAVE), xb = __shfl(xv[D_C], pb, WAVE);
   TV t = dg * xv[D_C] + ca * xa + cb * xb;
 #pragma unroll

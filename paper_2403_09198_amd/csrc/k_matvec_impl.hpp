@@ -188,20 +188,36 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
   }
 
   // pair coefficients: forward v_p . x_nb, transpose u_p(nb, opp d) . x_nb
+  // (multi-value wave sums, four at a time)
   TV acc[NR][5][RM];
+  constexpr int PER_R = RDM + 4 * ROM, NSUM = NR * PER_R;
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
+  for (int g0 = 0; g0 < NSUM; g0 += 4) {
+    TV s4[4];
 #pragma unroll
-    for (int d = 0; d < 5; ++d)
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-        TV s = TV(0);
+    for (int e = 0; e < 4; ++e) {
+      TV s = TV(0);
+      if (g0 + e < NSUM) {
+        const int r = (g0 + e) / PER_R;
+        int d, p;
+        pair_index<RDM, ROM>((g0 + e) % PER_R, d, p);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
           if (ch * WAVE + lane < m) s += pv[d][p][ch] * xv[r][d][ch];
-        s = wave_sum_u(s);
-        acc[r][d][p] = ex[d] ? s : TV(0);
       }
+      s4[e] = s;
+    }
+    wave_sums_u(s4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (g0 + e < NSUM) {
+        const int r = (g0 + e) / PER_R;
+        int d, p;
+        pair_index<RDM, ROM>((g0 + e) % PER_R, d, p);
+        acc[r][d][p] = ex[d] ? s4[e] : TV(0);
+      }
+    }
+  }
   // coupling sums of the flow unknowns (and the atom) over the cell's levels
   TV asum[NR][NSM];
   if constexpr (WIDE) {
@@ -396,15 +412,33 @@ __global__ __launch_bounds__(64 * NCH) void k_matvec_wg(Mesh g_, const TV* __res
 #pragma unroll
   for (int r = 0; r < NR; ++r) xs[r][k] = xv[r][D_C];
 
+  {
+    constexpr int PER_R = RDM + 4 * ROM, NSUM = NR * PER_R;
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
+    for (int g0 = 0; g0 < NSUM; g0 += 4) {
+      TV s4[4];
 #pragma unroll
-    for (int d = 0; d < 5; ++d)
-#pragma unroll
-      for (int p = 0; p < (d == D_C ? RDM : ROM); ++p) {
-        const TV s = wave_sum_u(k < m ? pv[d][p] * xv[r][d] : TV(0));
-        if (lane == 0) part[r][d][p][wv] = s;
+      for (int e = 0; e < 4; ++e) {
+        s4[e] = TV(0);
+        if (g0 + e < NSUM) {
+          const int r = (g0 + e) / PER_R;
+          int d, p;
+          pair_index<RDM, ROM>((g0 + e) % PER_R, d, p);
+          s4[e] = k < m ? pv[d][p] * xv[r][d] : TV(0);
+        }
       }
+      wave_sums_u(s4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (g0 + e < NSUM && lane == 0) {
+          const int r = (g0 + e) / PER_R;
+          int d, p;
+          pair_index<RDM, ROM>((g0 + e) % PER_R, d, p);
+          part[r][d][p][wv] = s4[e];
+        }
+      }
+    }
+  }
   // wide pattern: this chunk's share of the coupling sums, band terms
   DiagLane<TV, TRANS, WIDE> bl;
   TV al[NSM];

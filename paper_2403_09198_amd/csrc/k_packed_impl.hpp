@@ -124,14 +124,18 @@ __global__ __launch_bounds__(64 * NW) void k_matvec_pk(Mesh g_, const TV* __rest
   int q_lo, q_hi;
   pk_wave_cells(wv, m, qn, q_lo, q_hi);
 #pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    const TV pd = act ? pv[d] * xv[d] : TV(0);
+  for (int g0 = 0; g0 < 5 * NS; g0 += 4) {  // multi-value wave sums, four at a time
+    TV s4[4];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      if (q_lo + j <= q_hi) {  // wave-uniform
-        const TV s = wave_sum_u(q == q_lo + j ? pd : TV(0));
-        if (lane == 0) part[d][wv][j] = s;
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int d = (g0 + e) / NS, j = (g0 + e) % NS;
+      s4[e] = g0 + e < 5 * NS && act && q == q_lo + j ? pv[d] * xv[d] : TV(0);
+    }
+    wave_sums_u(s4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int d = (g0 + e) / NS, j = (g0 + e) % NS;
+      if (g0 + e < 5 * NS && q_lo + j <= q_hi && lane == 0) part[d][wv][j] = s4[e];
     }
   }
   __syncthreads();
@@ -221,12 +225,14 @@ __global__ __launch_bounds__(64 * NW) void k_smw_apply_pk(Mesh g, const TV* __re
   int q_lo, q_hi;
   pk_wave_cells(wv, m, qn, q_lo, q_hi);
   const TV p = V * X0;
+  {
+    TV sums[NS];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    if (q_lo + j <= q_hi) {  // wave-uniform
-      const TV s = wave_sum_u(q == q_lo + j ? p : TV(0));
-      if (lane == 0) ss[wv][j] = s;
-    }
+    for (int j = 0; j < NS; ++j) sums[j] = q == q_lo + j ? p : TV(0);
+    wave_sums_u(sums);
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+      if (q_lo + j <= q_hi && lane == 0) ss[wv][j] = sums[j];
   }
   __syncthreads();
   const TV sc = pk_cell_sum<TV, NS>(ss, qq, m);

@@ -469,11 +469,20 @@ __global__ __launch_bounds__(64 * WPB) void k_smw_apply(Mesh g, const TV* __rest
       if constexpr (ARW) arrow_schur<TV, NCH>(L, m, A[j], DI[j], B[j], X[j], E[j], X0);
       TV s[RDM], z[RDM];
 #pragma unroll
-      for (int i = 0; i < RDM; ++i) {
-        TV t = TV(0);
+      for (int g0 = 0; g0 < RDM; g0 += 4) {  // wave sums four at a time
+        TV s4[4];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) t += V[j][i][ch] * X0[ch];
-        s[i] = i < rd ? wave_sum_u(t) : TV(0);
+        for (int e = 0; e < 4; ++e) {
+          s4[e] = TV(0);
+          if (g0 + e < RDM) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) s4[e] += V[j][g0 + e][ch] * X0[ch];
+          }
+        }
+        wave_sums_u(s4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (g0 + e < RDM) s[g0 + e] = g0 + e < rd ? s4[e] : TV(0);
       }
       IC[j].template apply<TRANS>(s, z, rd);
       if (c < g.N) {
@@ -610,13 +619,16 @@ __global__ __launch_bounds__(64 * NCH) void k_smw_apply_wg(Mesh g, const TV* __r
       if (lev) X0[r] -= X[0] * zz[r][0] + X[1] * zz[r][1] + X[2] * zz[r][2];
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
+  for (int g0 = 0; g0 < NR * RDM; g0 += 4) {  // wave sums four at a time
+    TV s4[4];
 #pragma unroll
-    for (int i = 0; i < RDM; ++i) {
-      if (i >= rd) break;
-      const TV sp = wave_sum_u(V[i] * X0[r]);
-      if (lane == 0) ss[r][i][wv] = sp;
-    }
+    for (int e = 0; e < 4; ++e)
+      s4[e] = g0 + e < NR * RDM ? V[(g0 + e) % RDM] * X0[(g0 + e) / RDM] : TV(0);
+    wave_sums_u(s4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (g0 + e < NR * RDM && (g0 + e) % RDM < rd && lane == 0)
+        ss[(g0 + e) / RDM][(g0 + e) % RDM][wv] = s4[e];
   }
   __syncthreads();
 #pragma unroll

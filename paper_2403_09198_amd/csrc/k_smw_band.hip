@@ -526,12 +526,21 @@ __global__ __launch_bounds__(64 * WPB) void k_band_woodbury(Mesh g, const TV* __
     }
     TV s[RDM], zz[RDM];
 #pragma unroll
-    for (int i = 0; i < RDM; ++i) {
-      TV t = TV(0);
+    for (int g0 = 0; g0 < RDM; g0 += 4) {  // wave sums four at a time
+      TV s4[4];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch)
-        if (ch * WAVE + lane < m) t += V[i][ch] * X[ch];
-      s[i] = i < rd ? wave_sum_u(t) : TV(0);
+      for (int e = 0; e < 4; ++e) {
+        s4[e] = TV(0);
+        if (g0 + e < RDM) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            if (ch * WAVE + lane < m) s4[e] += V[g0 + e][ch] * X[ch];
+        }
+      }
+      wave_sums_u(s4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (g0 + e < RDM) s[g0 + e] = g0 + e < rd ? s4[e] : TV(0);
     }
     IC.template apply<TRANS>(s, zz, rd);
     // every lane has read its entries before any lane writes (the reads

@@ -344,6 +344,105 @@ __device__ inline T wave_sum_u(T v) {
   return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
 }
 
+// Sums over the 64 lanes of K values at once, each returned wave-uniform
+// in place.  A reduce-scatter on the gfx950 lane swaps instead of K
+// separate reductions: v_permlane32_swap exchanges the upper 32 lanes of one
+// register with the lower 32 of another, so one swap and one add fold two
+// values over the wave's halves (value 2i in lanes 0-31, 2i+1 in 32-63);
+// v_permlane16_swap (odd rows of one register with even rows of the other)
+// folds the two resulting registers over row pairs, leaving four values per
+// register, one per row; DPP then sums within rows and v_readlane takes each
+// row's total.  About a third of the instructions of K wave_sum_u calls
+// for K >= 4 (groups of four already reach that rate: callers with many
+// sums reduce four at a time, which keeps few partials live).  Every value
+// is summed by the same association tree, whatever its position: bitwise
+// reproducible, and equal between kernels that group their sums
+// differently.
+__device__ inline void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ inline void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ inline void swap32(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ inline void swap16(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+template <typename T, int K>
+__device__ inline void wave_sums_u(T (&v)[K]) {
+  constexpr int K1 = (K + 1) / 2, K2 = (K1 + 1) / 2;
+  T h[2 * K2];  // after the first fold: values 2i (lanes 0-31) and 2i + 1 (32-63)
+#pragma unroll
+  for (int i = 0; i < 2 * K2; ++i) {
+    T a = 2 * i < K ? v[2 * i] : T(0);
+    T b = 2 * i + 1 < K ? v[2 * i + 1] : T(0);
+    if (2 * i < K) {
+      swap32(a, b);
+      h[i] = a + b;
+    } else {
+      h[i] = T(0);
+    }
+  }
+  // second fold: register j holds values 4j, 4j + 2, 4j + 1, 4j + 3 in rows
+  // 0, 1, 2, 3
+  T q[K2];
+#pragma unroll
+  for (int j = 0; j < K2; ++j) {
+    T a = h[2 * j], b = h[2 * j + 1];
+    swap16(a, b);
+    q[j] = a + b;
+  }
+#pragma unroll
+  for (int j = 0; j < K2; ++j) {
+    T x = q[j];
+    x += dpp<DPP_QP_1032>(T(0), x);
+    x += dpp<DPP_QP_2301>(T(0), x);
+    x += dpp<DPP_HALF_MIRROR>(T(0), x);
+    x += dpp<DPP_MIRROR>(T(0), x);
+    if (4 * j < K) v[4 * j] = readlane(x, 0);
+    if (4 * j + 2 < K) v[4 * j + 2] = readlane(x, 16);
+    if (4 * j + 1 < K) v[4 * j + 1] = readlane(x, 32);
+    if (4 * j + 3 < K) v[4 * j + 3] = readlane(x, 48);
+  }
+}
+
+// Block and pair of flat index w of a cell's pair coefficients, ordered by
+// block (S, W, C, E, N) and pair: RDM pairs for the diagonal block, ROM for
+// each neighbour.
+template <int RDM, int ROM>
+__device__ constexpr void pair_index(int w, int& d, int& p) {
+  d = 0;
+  for (int dd = 0; dd < 5; ++dd) {
+    const int cnt = dd == D_C ? RDM : ROM;
+    if (w < cnt) {
+      d = dd;
+      p = w;
+      return;
+    }
+    w -= cnt;
+  }
+  p = 0;
+}
+
 // Inclusive scan of affine maps y -> a*y + b along increasing lane index
 // (lane l ends with the composition of lanes 0..l).  Within rows by DPP
 // shifts with the identity map (1, 0) shifted in; then every row is prefixed
