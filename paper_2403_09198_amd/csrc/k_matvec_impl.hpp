@@ -66,16 +66,25 @@ __global__ __launch_bounds__(64 * WPB) void k_matvec(Mesh g_, const TV* __restri
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
                                                      double* __restrict__ y, int r0_,
-                                                     int pair2) {
+                                                     int pair2, int band) {
   constexpr bool EXACT = RDM == 1 && ROM == 1;
   constexpr int RM = RDM > ROM ? RDM : ROM;
   constexpr bool PRELOAD = NCH == 1;  // hold the sparse rows across the reduction
   const Mesh g = kmesh<EXACT>(g_);
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int wid = __builtin_amdgcn_readfirstlane(tile * WPB + (int)(threadIdx.x >> 6));
-  const int c = pair2 ? wid >> 1 : wid;
-  const int r0 = pair2 ? r0_ + (wid & 1) * NR : r0_;
-  if (c >= g.N) return;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  int c;
+  if (band) {  // column-band tiles of WPB (pair2: WPB / 2) cells
+    int c0, qn;
+    band_tile(g, (int)blockIdx.x, pair2 ? WPB / 2 : WPB, c0, qn);
+    const int q = pair2 ? wv >> 1 : wv;
+    if (q >= qn) return;
+    c = c0 + q;
+  } else {
+    const int wid = xcd_tile(blockIdx.x, gridDim.x) * WPB + wv;
+    c = pair2 ? wid >> 1 : wid;
+    if (c >= g.N) return;
+  }
+  const int r0 = pair2 ? r0_ + (wv & 1) * NR : r0_;
   const int lane = lane_id();
   const int m = g.m, L = g.L;
   const long long mp = g.mp;
@@ -537,7 +546,8 @@ inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
     return;
   }
 #endif
-  const int grid = (g.N + WPB - 1) / WPB;
+  const int band = R1S_MV_BAND;
+  const int grid = band ? band_grid(g, WPB) : (g.N + WPB - 1) / WPB;
   int r0 = 0;
   while (r0 < nrhs) {
     const int rem = nrhs - r0;
@@ -545,26 +555,26 @@ inline void launch_mv_nch(const Mesh& g, const TV* rec, const double* x, const d
       if (rem >= 8) {  // two waves per cell, four right-hand sides each
         // (256 x 128, L = 61: 145 us against 159 us for one wave with all
         // eight at 184 registers, 2 waves per SIMD; four waves of two: 175 us)
+        const int grid2 = band ? band_grid(g, WPB / 2) : (2 * g.N + WPB - 1) / WPB;
         hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE, true>),
-                           dim3((2 * g.N + WPB - 1) / WPB), dim3(64 * WPB), 0, s, g, rec, x, b, y,
-                           r0, 1);
+                           dim3(grid2), dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 1, band);
         r0 += 8;
         continue;
       }
       if (rem >= 4) {
         hipLaunchKernelGGL((k_matvec<TV, NCH, 4, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
+                           dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0, band);
         r0 += 4;
         continue;
       }
     }
     if (rem >= 2) {
       hipLaunchKernelGGL((k_matvec<TV, NCH, 2, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0, band);
       r0 += 2;
     } else {
       hipLaunchKernelGGL((k_matvec<TV, NCH, 1, TRANS, RESID, RDM, ROM, WIDE>), dim3(grid),
-                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0);
+                         dim3(64 * WPB), 0, s, g, rec, x, b, y, r0, 0, band);
       r0 += 1;
     }
   }

@@ -38,7 +38,15 @@ constexpr int WAVE = 64;
 #ifndef R1S_WPB
 #define R1S_WPB 2  // 256 x 128, L = 61: matvec 53.9 us against 54.7 with 4 or 8
 #endif
-constexpr int WPB = R1S_WPB;  // wavefronts (cells) per workgroup of the cell kernels (even)
+constexpr int WPB = R1S_WPB;
+#ifndef R1S_MV_BAND
+// Wave-per-cell matvec on column-band tiles (1) or in cell order (0).  256 x
+// 128, L = 61, eight right-hand sides: the band map cuts the matvec's fetched
+// bytes from 1.64x to 1.02x of its algorithmic reads (the W/E neighbours'
+// x blocks no longer go to three XCDs' L2s) but gains only 1% in time; the
+// waves wait on memory 64% of their cycles at 5 waves per SIMD.
+#define R1S_MV_BAND 1
+#endif  // wavefronts (cells) per workgroup of the cell kernels (even)
 constexpr int NXCD = 8;      // MI355X: 8 XCDs x 32 CUs
 constexpr int F_DIAG = 0, F_LO = 1, F_HI = 2, F_NBR = 3, F_BAND = 7;
 // General mesh: neighbour slot s is addressed as direction GSLOT + s.
