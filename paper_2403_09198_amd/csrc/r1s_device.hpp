@@ -75,7 +75,12 @@ constexpr int PAT_ELL_MAX = 16, PAT_SLOTS_MAX = 8;
 // transpose) in the a / dinv / b rows.
 constexpr int P_A = 0, P_DINV = 1, P_B = 2, P_W = 3;  // V rows at P_W + rd
 
-__host__ __device__ inline int pad_m(int m) { return (m + 7) & ~7; }
+// Record row length: m values, padded to a multiple of 8 from 64 on.  Below
+// 64 the packed kernels read row f of several consecutive cells per load and
+// unpadded rows save lines (512 x 256, L = 32, m = 35: matvec 128.6 against
+// 135.2 us); from 64 on, 64-byte aligned rows are faster (L = 200, m = 203:
+// SMW apply 249.7 against 265.7 us unpadded).
+__host__ __device__ inline int pad_m(int m) { return m < 64 ? m : (m + 7) & ~7; }
 __host__ __device__ inline int nbr_slot(int d) { return d < 2 ? d : d - 1; }
 __host__ __device__ inline int opposite(int d) { return 4 - d; }
 

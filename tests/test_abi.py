@@ -62,8 +62,9 @@ def test_rank_validation():
     assert lib.r1s_mat_size(4, 4, 4, _lay(9, 7), 0, C.byref(b)) == L.R1S_ERR_UNSUPPORTED
     for rd, ro in ((9, 2), (1, 0), (2, 0), (3, 1), (8, 6)):
         assert lib.r1s_mat_size(4, 4, 4, _lay(rd, ro), 0, C.byref(b)) == L.R1S_OK
-        # one record of 7 + 2 (rd + 4 ro) rows of 8 doubles per cell
-        assert b.value >= 16 * (7 + 2 * (rd + 4 * ro)) * 8 * 8
+        # one record of 7 + 2 (rd + 4 ro) rows of m = 7 doubles per cell
+        # (rows shorter than 64 values are not padded)
+        assert b.value >= 16 * (7 + 2 * (rd + 4 * ro)) * 7 * 8
 
 
 def test_layout_validation_and_sizes():
