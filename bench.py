@@ -165,6 +165,37 @@ def time_pair(torch, f1, f2, steps, warmup, flush=None):
     return wall, t1, t2
 
 
+def ceilings(torch, A, M, x, y, z, mv_b, ap_b, reps=20):
+    """Context for the roofline: a device-to-device copy of 1 GiB (torch's
+    copy kernel; read + written bytes per second) and the matvec / SMW apply
+    timed cold, a 512 MiB buffer written before every pair so that neither
+    the L2s nor the 256 MiB Infinity Cache hold any of their inputs."""
+    src = torch.empty(1 << 27, dtype=torch.float64, device=x.device)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    scratch = torch.empty(1 << 26, dtype=torch.float64, device=x.device)
+    _, t1, t2 = time_pair(torch, lambda: A.matvec(x, out=y), lambda: M.apply(y, out=z), reps, 3,
+                          flush=lambda: scratch.fill_(0.0))
+    del scratch
+    mv_ms, ap_ms = float(np.median(t1)), float(np.median(t2))
+    return {"stream_copy_gbs": round(copy_gbs, 1),
+            "cold": {"matvec_us": round(mv_ms * 1e3, 2), "smw_apply_us": round(ap_ms * 1e3, 2),
+                     "matvec_gbs": round(mv_b / (mv_ms / 1e3) / 1e9, 1),
+                     "smw_apply_gbs": round(ap_b / (ap_ms / 1e3) / 1e9, 1),
+                     "note": "median of %d, a 512 MiB buffer written before each pair" % reps}}
+
+
 def capture(torch, fn):
     """Capture fn's launches (on torch's current stream) into a HIP graph."""
     side = torch.cuda.Stream()
@@ -1008,6 +1039,17 @@ def main():
                                "kernel": tra["kernel"] if tra else None,
                                "algorithmic_bytes_per_launch": ap_b},
     }
+    # counted bytes per second (the FETCH_SIZE + WRITE_SIZE traffic of one
+    # launch over its average duration) beside the algorithmic rate
+    if tr:
+        out["roofline"]["traffic_gbs"] = round(tr["traffic_bytes"] / (mv_ms / 1e3) / 1e9, 1)
+    if tra:
+        out["smw_apply_roofline"]["traffic_gbs"] = round(tra["traffic_bytes"] / (ap_ms / 1e3) / 1e9, 1)
+    ce = ceilings(torch, A, M, x, y, z, mv_b, ap_b)
+    out["ceilings"] = ce
+    out["roofline"]["frac_of_copy"] = round(ach / ce["stream_copy_gbs"], 4)
+    log(f"copy {ce['stream_copy_gbs']:.0f} GB/s; cold matvec {ce['cold']['matvec_us']} us, "
+        f"apply {ce['cold']['smw_apply_us']} us")
 
     xs = {}
     b = None
