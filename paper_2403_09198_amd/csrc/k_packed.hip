@@ -5,7 +5,8 @@
 // cache flushed before each launch; algorithmic bytes / kernel time):
 //
 //   m    matvec: packed (waves)   wave per chunk    SMW apply: packed   wave per cell
-//   35   140 us (8) 0.62          164 us 0.53       55.6 us (4) 0.58    64.2 us 0.50
+//   35   127 us (4) 0.68          164 us 0.53       54.7 us (4) 0.58    64.2 us 0.50
+//        (unpadded rows; 8 or 16 waves: 131 us)
 //   64   205 us (4) 0.78          216 us 0.73       78.9 us (4) 0.74    78.3 us 0.75
 //   123  414 us (8) 0.74          430 us 0.71       156 us (2)  0.72    workgroup 147-159 us
 //   203  688 us (16) 0.73         767 us 0.66       318 us (16) 0.59    249 us 0.75
