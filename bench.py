@@ -1045,11 +1045,12 @@ def main():
         out["roofline"]["traffic_gbs"] = round(tr["traffic_bytes"] / (mv_ms / 1e3) / 1e9, 1)
     if tra:
         out["smw_apply_roofline"]["traffic_gbs"] = round(tra["traffic_bytes"] / (ap_ms / 1e3) / 1e9, 1)
-    ce = ceilings(torch, A, M, x, y, z, mv_b, ap_b)
-    out["ceilings"] = ce
-    out["roofline"]["frac_of_copy"] = round(ach / ce["stream_copy_gbs"], 4)
-    log(f"copy {ce['stream_copy_gbs']:.0f} GB/s; cold matvec {ce['cold']['matvec_us']} us, "
-        f"apply {ce['cold']['smw_apply_us']} us")
+    if not args.no_extras:  # (kept out of profiled runs: the cold pairs would enter the averages)
+        ce = ceilings(torch, A, M, x, y, z, mv_b, ap_b)
+        out["ceilings"] = ce
+        out["roofline"]["frac_of_copy"] = round(ach / ce["stream_copy_gbs"], 4)
+        log(f"copy {ce['stream_copy_gbs']:.0f} GB/s; cold matvec {ce['cold']['matvec_us']} us, "
+            f"apply {ce['cold']['smw_apply_us']} us")
 
     xs = {}
     b = None
