@@ -936,6 +936,9 @@ def main():
                     help="512x256 level sweep against the BSR baseline (one JSON line per case)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the fixed kernel sequence used for hardware-counter runs")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides of the --profile-pass vectors (8: the batched "
+                         "operator of the adjoint workload)")
     ap.add_argument("--solve-timeline", action="store_true",
                     help="three 256x128, L=61 GMRES solves between marker kernels (for a "
                          "kernel trace) and their unprofiled wall times")
@@ -993,6 +996,9 @@ def main():
         mv_b, ap_b = st["matvec_bytes"], st["smw_apply_bytes"]
     steps, warm = args.steps, args.warmup
     if args.profile_pass:
+        if args.nrhs > 1:
+            x = torch.from_numpy(gen.make_vector(nx, ny, L, nrhs=args.nrhs, seed=1)).to(dev)
+            y, z = torch.empty_like(x), torch.empty_like(x)
         profile_pass(torch, A, M, x, y, z)
         return
 
