@@ -29,6 +29,8 @@
 // Right-hand sides and results keep the [nrhs][N][m] vector layout.
 #include <math.h>
 
+#include <type_traits>
+
 #include "r1s_device.hpp"
 #include "r1s_kernels.hpp"
 
@@ -121,90 +123,20 @@ __device__ __forceinline__ void band_solve(const T* __restrict__ fb, int L, int 
   for (int i = 0; i < 3; ++i) dst[(L + i) * DS] = (DST)xf[i];
 }
 
-// The Woodbury factors of one cell, one lane per cell: W_i = A0^{-1} u_i and
-// v_i (rows of wc, W first), C^{-1} = (I + V^T W)^{-1} by Gauss-Jordan with
-// partial pivoting (ci, row-major), and when wcT is given the transposed
-// rows A0^{-T} v_i, u_i.  solve(rhs, dst) / solveT(rhs, dst) write A0^{-1}
-// rhs / A0^{-T} rhs into dst[0 .. m) (the cell's own row; rhs(k) gives
-// element k).  Padding elements of the rows are zeroed.
-template <typename PairU, typename PairV, typename Solve, typename SolveT>
-__device__ void woodbury_factors(int m, long long mp, int rd, PairU pair_u, PairV pair_v,
-                                 Solve solve, SolveT solveT, double* wc, double* wcT, double* ci,
-                                 bool& bad) {
-  // SMW-1: W_i = A0^{-1} u_i; V_i = v_i
-  double vv = 0.0, ww = 0.0;
-  for (int i = 0; i < rd; ++i) {
-    double* Wi = wc + (long long)i * mp;
-    double* Vi = wc + (long long)(rd + i) * mp;
-    solve([&](int k) { return pair_u(i, k); }, Wi);
-    for (int k = 0; k < m; ++k) {
-      const double v = pair_v(i, k);
-      Vi[k] = v;
-      vv += v * v;
-      ww += Wi[k] * Wi[k];
-    }
-    for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
-  }
-  // SMW-2: C = I + V^T W, inverted by Gauss-Jordan with partial pivoting
-  double Cm[SMW_PAIRS_MAX][2 * SMW_PAIRS_MAX];
-  for (int i = 0; i < rd; ++i)
-    for (int j = 0; j < rd; ++j) {
-      double s = i == j ? 1.0 : 0.0;
-      const double* Vi = wc + (long long)(rd + i) * mp;
-      const double* Wj = wc + (long long)j * mp;
-      for (int k = 0; k < m; ++k) s += Vi[k] * Wj[k];
-      Cm[i][j] = s;
-      Cm[i][rd + j] = i == j ? 1.0 : 0.0;
-    }
-  const double tol = 1e-12 * (1.0 + sqrt(vv * ww));
-  for (int k = 0; k < rd; ++k) {
-    int p = k;
-    for (int i = k + 1; i < rd; ++i)
-      if (fabs(Cm[i][k]) > fabs(Cm[p][k])) p = i;
-    if (!(fabs(Cm[p][k]) > tol)) bad = true;
-    if (p != k)
-      for (int j = 0; j < 2 * rd; ++j) {
-        const double t = Cm[k][j];
-        Cm[k][j] = Cm[p][j];
-        Cm[p][j] = t;
-      }
-    const double inv = 1.0 / Cm[k][k];
-    for (int j = 0; j < 2 * rd; ++j) Cm[k][j] *= inv;
-    for (int i = 0; i < rd; ++i) {
-      if (i == k) continue;
-      const double f = Cm[i][k];
-      for (int j = 0; j < 2 * rd; ++j) Cm[i][j] -= f * Cm[k][j];
-    }
-  }
-  for (int i = 0; i < rd; ++i)
-    for (int j = 0; j < rd; ++j) ci[i * rd + j] = Cm[i][rd + j];
-  if (wcT) {  // transposed apply: A0^{-T} v_i and u_i
-    for (int i = 0; i < rd; ++i) {
-      double* Wi = wcT + (long long)i * mp;
-      double* Vi = wcT + (long long)(rd + i) * mp;
-      solveT([&](int k) { return pair_v(i, k); }, Wi);
-      for (int k = 0; k < m; ++k) Vi[k] = pair_u(i, k);
-      for (int k = m; k < mp; ++k) Wi[k] = Vi[k] = 0.0;
-    }
-  }
-}
-
 // ---------------------------------------------------------------- setup ----
-// One lane per cell (workgroups of 64 = one tile).  Writes the band factors,
-// the Schur inverse (s3i [tile][9][64]), W and V rows for the forward apply
-// (wv [tile][2 rd][m][64]: W_i = A0^{-1} u_i, then v_i) and, when wvT is
-// given, for the transposed apply (A0^{-T} v_i, then u_i), and C^{-1}
-// ([tile][rd^2][64], row-major per cell).
+// The factorisation, one lane per cell (workgroups of 64 = one tile): the
+// band factors and the Schur inverse (s3i [tile][9][64]).  The Woodbury
+// factors follow in the kernels below launch_band_solve: W and V rows for
+// the forward apply (wv [N][2 rd][mp]: W_i = A0^{-1} u_i, then v_i) and,
+// when wvT is given, for the transposed apply (A0^{-T} v_i, then u_i), and
+// C^{-1} ([N][rd^2], row-major per cell).
 __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __restrict__ rec,
                                                      double* __restrict__ bf,
-                                                     double* __restrict__ s3i_out,
-                                                     double* __restrict__ wv,
-                                                     double* __restrict__ wvT,
-                                                     double* __restrict__ cinv, int* status) {
+                                                     double* __restrict__ s3i_out, int* status) {
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int c = tile * TILE + lane;
   if (c >= g.N) return;  // no cross-lane work in this kernel
-  const int L = g.L, m = g.m, band = g.band, rd = smw_pairs(g), rdu = g.rd;
+  const int L = g.L, m = g.m, band = g.band;
   const long long mp = g.mp;
   const double* rc = rec + (long long)c * g.F * mp;
   const int RB = band_rows(g);
@@ -284,40 +216,158 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
   for (int t = 0; t < 9; ++t) s3i_out[((long long)tile * 9 + t) * TILE + lane] = s3i[t];
   for (int k = 0; k < L; ++k) F(band, k) = 1.0 / F(band, k);
 
-  const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
-  const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
-  // Woodbury term i at element k: the block's pairs, then the atom's column
-  // (u = column, v = e_a) and row (u = e_a, v = row)
-  const int ia = L - 1;
-  auto pair_u = [&](int i, int k) -> double {
-    if (i < rdu) return uC[i * mp + k];
-    if (i == rdu) return k < ia ? rc[(long long)arrow_col_row(g, 3) * mp + k] : 0.0;
-    return k == ia ? 1.0 : 0.0;
-  };
-  auto pair_v = [&](int i, int k) -> double {
-    if (i < rdu) return vC[i * mp + k];
-    if (i == rdu) return k == ia ? 1.0 : 0.0;
-    return k < ia ? rc[(long long)arrow_row_row(g, 3) * mp + k] : 0.0;
-  };
-  woodbury_factors(
-      m, mp, rd, pair_u, pair_v,
-      [&](auto rhs, double* dst) {
-        band_solve<false, 1, double, double>(fb, L, band, g.arrow, s3i, rhs, dst);
-      },
-      [&](auto rhs, double* dst) {
-        band_solve<true, 1, double, double>(fb, L, band, g.arrow, s3i, rhs, dst);
-      },
-      wv + (long long)c * 2 * rd * mp, wvT ? wvT + (long long)c * 2 * rd * mp : nullptr,
-      cinv + (long long)c * rd * rd, bad);
   if (bad) atomicMin(status, c);
 }
 
-hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, double* s3i,
-                             double* wv, double* wvT, double* cinv, int* status, hipStream_t s) {
-  if (g.rd > RANK_DIAG_MAX || g.band > BAND_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_band_setup, dim3((unsigned)tiles(g)), dim3(TILE), 0, s, g, rec, bf, s3i, wv,
-                     wvT, cinv, status);
-  return hipGetLastError();
+// The Woodbury terms of a cell, term i at element k: the block's pairs, then
+// the atom's column (u = column, v = e_a) and row (u = e_a, v = row).
+struct BandPairs {
+  const double *rc, *uC, *vC;
+  long long mp;
+  int rdu, ia, colrow, rowrow;
+  __device__ BandPairs(const Mesh& g, const double* rec, int c) {
+    mp = g.mp;
+    rc = rec + (long long)c * g.F * mp;
+    uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
+    vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
+    rdu = g.rd;
+    ia = g.L - 1;
+    colrow = g.arrow == 2 ? arrow_col_row(g, 3) : 0;
+    rowrow = g.arrow == 2 ? arrow_row_row(g, 3) : 0;
+  }
+  __device__ double u(int i, int k) const {
+    if (i < rdu) return uC[i * mp + k];
+    if (i == rdu) return k < ia ? rc[colrow * mp + k] : 0.0;
+    return k == ia ? 1.0 : 0.0;
+  }
+  __device__ double v(int i, int k) const {
+    if (i < rdu) return vC[i * mp + k];
+    if (i == rdu) return k == ia ? 1.0 : 0.0;
+    return k < ia ? rc[rowrow * mp + k] : 0.0;
+  }
+};
+
+// The rows of wv before the solves, one wavefront per cell: row i = u_i (the
+// right-hand side of W_i = A0^{-1} u_i, solved in place), row rd + i = v_i;
+// wvT: v_i (for A0^{-T} v_i), then u_i.  Padding zeroed.
+__global__ __launch_bounds__(64 * WPB) void k_band_wv_init(Mesh g, const double* __restrict__ rec,
+                                                           double* __restrict__ wv,
+                                                           double* __restrict__ wvT) {
+  const int c = blockIdx.x * WPB + (int)(threadIdx.x >> 6);
+  if (c >= g.N) return;
+  const int lane = lane_id(), m = g.m, rd = smw_pairs(g);
+  const long long mp = g.mp;
+  const BandPairs pr(g, rec, c);
+  double* w = wv + (long long)c * 2 * rd * mp;
+  double* wt = wvT ? wvT + (long long)c * 2 * rd * mp : nullptr;
+  for (int i = 0; i < rd; ++i)
+    for (int k = lane; k < mp; k += WAVE) {
+      const double u = k < m ? pr.u(i, k) : 0.0, v = k < m ? pr.v(i, k) : 0.0;
+      w[i * mp + k] = u;
+      w[(rd + i) * mp + k] = v;
+      if (wt) {
+        wt[i * mp + k] = v;
+        wt[(rd + i) * mp + k] = u;
+      }
+    }
+}
+
+// C = I + V^T W of a cell (the W_i solved in place in wv) and its inverse,
+// one wavefront per cell: the rd^2 dot products as multi-value wave sums,
+// then Gauss-Jordan with partial pivoting on [C | I], lane t holding column t
+// of the augmented matrix (pivots read with v_readlane, every step
+// wave-uniform).  The transposed apply uses (C^{-1})^T.
+template <int NCH>
+__global__ __launch_bounds__(64 * WPB) void k_band_cinv(Mesh g, const double* __restrict__ wv,
+                                                        double* __restrict__ cinv, int* status) {
+  constexpr int RDM = SMW_PAIRS_MAX;
+  const int c = blockIdx.x * WPB + (int)(threadIdx.x >> 6);
+  if (c >= g.N) return;
+  const int lane = lane_id(), m = g.m, rd = smw_pairs(g);
+  const long long mp = g.mp;
+  const double* w = wv + (long long)c * 2 * rd * mp;
+  double V[RDM][NCH], W[RDM][NCH];
+  double vv = 0.0, ww = 0.0;
+#pragma unroll
+  for (int i = 0; i < RDM; ++i)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int k = ch * WAVE + lane;
+      const bool in = i < rd && k < m;
+      V[i][ch] = in ? w[(rd + i) * mp + k] : 0.0;
+      W[i][ch] = in ? w[i * mp + k] : 0.0;
+      vv += V[i][ch] * V[i][ch];
+      ww += W[i][ch] * W[i][ch];
+    }
+  double Mc[RDM];  // row i of [C | I] at column `lane`
+#pragma unroll
+  for (int i = 0; i < RDM; ++i) Mc[i] = lane == rd + i ? 1.0 : 0.0;
+  // C[i][j] = delta_ij + V_i . W_j, the sums of column j four at a time
+  // (fixed trip counts and guards in place of early exits: every index is
+  // a compile-time constant, so Mc stays in registers)
+#pragma unroll
+  for (int j = 0; j < RDM; ++j) {
+    if (j < rd) {
+#pragma unroll
+      for (int g0 = 0; g0 < RDM; g0 += 4) {
+        double s4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          s4[e] = 0.0;
+          if (g0 + e < RDM) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) s4[e] += V[g0 + e][ch] * W[j][ch];
+          }
+        }
+        wave_sums_u(s4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = g0 + e;
+          if (i < RDM && i < rd) Mc[i] = lane == j ? (i == j ? 1.0 : 0.0) + s4[e] : Mc[i];
+        }
+      }
+    }
+  }
+  double t2[2] = {vv, ww};
+  wave_sums_u(t2);
+  // the entries of V^T W carry rounding of order eps |V| |W|
+  const double tol = 1e-12 * (1.0 + sqrt(t2[0] * t2[1]));
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < RDM; ++k) {
+    if (k < rd) {
+      int p = k;
+      double best = fabs(readlane(Mc[k], k));
+#pragma unroll
+      for (int i = k + 1; i < RDM; ++i) {
+        const double a = i < rd ? fabs(readlane(Mc[i], k)) : 0.0;
+        p = a > best ? i : p;
+        best = a > best ? a : best;
+      }
+      if (!(best > tol)) bad = true;
+      double rowp = Mc[k];  // swap rows k and p (p >= k, wave-uniform)
+#pragma unroll
+      for (int i = k + 1; i < RDM; ++i) rowp = i == p ? Mc[i] : rowp;
+#pragma unroll
+      for (int i = k + 1; i < RDM; ++i) Mc[i] = i == p ? Mc[k] : Mc[i];
+      Mc[k] = rowp;
+      Mc[k] *= 1.0 / readlane(Mc[k], k);
+#pragma unroll
+      for (int i = 0; i < RDM; ++i) {
+        if (i != k && i < rd) {
+          const double f = readlane(Mc[i], k);
+          Mc[i] -= f * Mc[k];
+        }
+      }
+    }
+  }
+  if (lane >= rd && lane < 2 * rd) {  // lane rd + j holds column j of C^{-1}
+    double* ic = cinv + (long long)c * rd * rd + (lane - rd);
+#pragma unroll
+    for (int i = 0; i < RDM; ++i)
+      if (i < rd) ic[i * rd] = Mc[i];
+  }
+  if (bad && lane == 0) atomicMin(status, c);
 }
 
 // ---------------------------------------------------------------- apply ----
@@ -454,8 +504,8 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
 template <typename TV, bool TRANS, int BM>
 __global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restrict__ bf,
                                                      const TV* __restrict__ s3i_in,
-                                                     const double* __restrict__ rin,
-                                                     double* __restrict__ zout, int nrhs) {
+                                                     const double* rin, double* zout, int nrhs,
+                                                     long long cs, long long rs) {
   extern __shared__ double sv[];
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int L = g.L, m = g.m, ls = (m + 1) | 1;
@@ -466,29 +516,70 @@ __global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restric
 #pragma unroll
   for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
   double* mine = sv + lane * ls;
-  for (int r = 0; r < nrhs; ++r) {
-    const double* rr = rin + (long long)r * g.n + c0 * m;
-    for (int cc = 0; cc < cells; ++cc)
-      for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * m + k];
-    __syncthreads();
-    band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, s3i, mine);
-    __syncthreads();
-    double* zz = zout + (long long)r * g.n + c0 * m;
-    for (int cc = 0; cc < cells; ++cc)
-      for (int k = lane; k < m; k += TILE) zz[(long long)cc * m + k] = sv[cc * ls + k];
-    __syncthreads();
-  }
+  const int r = blockIdx.y;  // one right-hand side per workgroup
+  const double* rr = rin + (long long)r * rs + c0 * cs;
+  for (int cc = 0; cc < cells; ++cc)
+    for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * cs + k];
+  __syncthreads();
+  band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, s3i, mine);
+  __syncthreads();
+  double* zz = zout + (long long)r * rs + c0 * cs;
+  for (int cc = 0; cc < cells; ++cc)
+    for (int k = lane; k < m; k += TILE) zz[(long long)cc * cs + k] = sv[cc * ls + k];
 }
 
 template <typename TV, bool TRANS, int BM>
 static void launch_band_solve(const Mesh& g, const TV* bf, const TV* s3i, const double* r,
-                              double* z, int nrhs, hipStream_t s) {
+                              double* z, int nrhs, hipStream_t s, long long cs = -1,
+                              long long rs = -1) {
+  if (cs < 0) cs = g.m;  // the [nrhs][N][m] vector layout by default
+  if (rs < 0) rs = g.n;
   const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
   if (lds > 65536)  // up to the 160 KiB of a CU for m > 127
     (void)hipFuncSetAttribute((const void*)k_band_solve<TV, TRANS, BM>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_band_solve<TV, TRANS, BM>), dim3((unsigned)tiles(g)), dim3(TILE), lds, s,
-                     g, bf, s3i, r, z, nrhs);
+  hipLaunchKernelGGL((k_band_solve<TV, TRANS, BM>), dim3((unsigned)tiles(g), nrhs), dim3(TILE), lds,
+                     s, g, bf, s3i, r, z, nrhs, cs, rs);
+}
+
+static void launch_band_cinv(const Mesh& g, const double* wv, double* cinv, int* status,
+                             hipStream_t s) {
+  const dim3 grid((g.N + WPB - 1) / WPB), block(64 * WPB);
+  switch ((g.m + WAVE - 1) / WAVE) {
+    case 1: hipLaunchKernelGGL(k_band_cinv<1>, grid, block, 0, s, g, wv, cinv, status); break;
+    case 2: hipLaunchKernelGGL(k_band_cinv<2>, grid, block, 0, s, g, wv, cinv, status); break;
+    case 3: hipLaunchKernelGGL(k_band_cinv<3>, grid, block, 0, s, g, wv, cinv, status); break;
+    default: hipLaunchKernelGGL(k_band_cinv<4>, grid, block, 0, s, g, wv, cinv, status); break;
+  }
+}
+
+// Setup of the banded block-Jacobi: the factorisation (one lane per cell),
+// then the Woodbury factors with coalesced, wave-per-cell kernels and the
+// apply's pipelined walk: the u / v rows into wv (and wvT), W_i = A0^{-1} u_i
+// (A0^{-T} v_i) solved in place as rd right-hand sides of stride mp in
+// cell-major rows, then C^{-1}.
+hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, double* s3i,
+                             double* wv, double* wvT, double* cinv, int* status, hipStream_t s) {
+  if (g.rd > RANK_DIAG_MAX || g.band > BAND_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_band_setup, dim3((unsigned)tiles(g)), dim3(TILE), 0, s, g, rec, bf, s3i,
+                     status);
+  const int cg = (g.N + WPB - 1) / WPB;
+  hipLaunchKernelGGL(k_band_wv_init, dim3(cg), dim3(64 * WPB), 0, s, g, rec, wv, wvT);
+  const int rd = smw_pairs(g);
+  const long long cs = 2LL * rd * g.mp;
+  auto solve = [&](auto trans_tag, double* w) {
+    constexpr bool TR = decltype(trans_tag)::value;
+    if (g.band <= 2)
+      launch_band_solve<double, TR, 2>(g, bf, s3i, w, w, rd, s, cs, g.mp);
+    else if (g.band <= 4)
+      launch_band_solve<double, TR, 4>(g, bf, s3i, w, w, rd, s, cs, g.mp);
+    else
+      launch_band_solve<double, TR, BAND_MAX>(g, bf, s3i, w, w, rd, s, cs, g.mp);
+  };
+  solve(std::false_type{}, wv);
+  if (wvT) solve(std::true_type{}, wvT);
+  launch_band_cinv(g, wv, cinv, status, s);
+  return hipGetLastError();
 }
 
 // z = x0 - W C^{-1} (V^T x0) in place, one wavefront per cell (NCH chunks of
@@ -666,14 +757,11 @@ __device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int 
 // column k and column j of U's row k), then the Woodbury factors.
 __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
                                                         const double* __restrict__ rec,
-                                                        double* __restrict__ bf,
-                                                        double* __restrict__ wv,
-                                                        double* __restrict__ wvT,
-                                                        double* __restrict__ cinv, int* status) {
+                                                        double* __restrict__ bf, int* status) {
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int c = tile * TILE + lane;
   if (c >= g.N) return;  // no cross-lane work in this kernel
-  const int m = g.m, rd = smw_pairs(g);
+  const int m = g.m;
   const long long mp = g.mp;
   const double* rc = rec + (long long)c * g.F * mp;
   double* F = bf + (long long)tile * lu.nnzF * TILE + lane;
@@ -696,21 +784,6 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
         at(lu.posF[i * m + lu.urow_col[b]]) -= l * at(lu.urow_pos[b]);
     }
   }
-  const double* uC = rc + (long long)(g.fu + pair_start(g, D_C)) * mp;
-  const double* vC = rc + (long long)(g.fu + g.P + pair_start(g, D_C)) * mp;
-  woodbury_factors(
-      m, mp, rd, [&](int i, int k) { return uC[i * mp + k]; },
-      [&](int i, int k) { return vC[i * mp + k]; },
-      [&](auto rhs, double* dst) {
-        for (int k = 0; k < m; ++k) dst[k] = rhs(k);
-        pattern_stream<8, false, double>(lu.ops_n, lu.nops_n, m, F, dst);
-      },
-      [&](auto rhs, double* dst) {
-        for (int k = 0; k < m; ++k) dst[k] = rhs(k);
-        pattern_stream<8, false, double>(lu.ops_t, lu.nops_t, m, F, dst);
-      },
-      wv + (long long)c * 2 * rd * mp, wvT ? wvT + (long long)c * 2 * rd * mp : nullptr,
-      cinv + (long long)c * rd * rd, bad);
   if (bad) atomicMin(status, c);
 }
 
@@ -722,8 +795,8 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
 template <typename TV, bool TRANS>
 __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
                                                         const TV* __restrict__ bf,
-                                                        const double* __restrict__ rin,
-                                                        double* __restrict__ zout, int nrhs) {
+                                                        const double* rin, double* zout,
+                                                        long long cs, long long rs) {
   extern __shared__ double sv[];
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int m = g.m, ls = (m + 1) | 1;
@@ -731,41 +804,52 @@ __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
   const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
   const TV* F = bf + (long long)tile * lu.nnzF * TILE + lane;
   double* mine = sv + lane * ls;
-  for (int r = 0; r < nrhs; ++r) {
-    const double* rr = rin + (long long)r * g.n + c0 * m;
-    for (int cc = 0; cc < cells; ++cc)
-      for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * m + k];
-    __syncthreads();
-    if (TRANS)
-      pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_t, lu.nops_t, m, F, mine);
-    else
-      pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_n, lu.nops_n, m, F, mine);
-    __syncthreads();
-    double* zz = zout + (long long)r * g.n + c0 * m;
-    for (int cc = 0; cc < cells; ++cc)
-      for (int k = lane; k < m; k += TILE) zz[(long long)cc * m + k] = sv[cc * ls + k];
-    __syncthreads();
-  }
+  const int r = blockIdx.y;  // one right-hand side per workgroup
+  const double* rr = rin + (long long)r * rs + c0 * cs;
+  for (int cc = 0; cc < cells; ++cc)
+    for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * cs + k];
+  __syncthreads();
+  if (TRANS)
+    pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_t, lu.nops_t, m, F, mine);
+  else
+    pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_n, lu.nops_n, m, F, mine);
+  __syncthreads();
+  double* zz = zout + (long long)r * rs + c0 * cs;
+  for (int cc = 0; cc < cells; ++cc)
+    for (int k = lane; k < m; k += TILE) zz[(long long)cc * cs + k] = sv[cc * ls + k];
 }
 
+template <typename TV, bool TRANS>
+static void launch_pattern_solve(const Mesh& g, const PatLU& lu, const TV* bf, const double* r,
+                                 double* z, int nrhs, hipStream_t s, long long cs = -1,
+                                 long long rs = -1) {
+  if (cs < 0) cs = g.m;  // the [nrhs][N][m] vector layout by default
+  if (rs < 0) rs = g.n;
+  const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_pattern_solve<TV, TRANS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_pattern_solve<TV, TRANS>), dim3((unsigned)tiles(g), nrhs), dim3(TILE), lds,
+                     s, g, lu, bf, r, z, cs, rs);
+}
+
+// Setup of the general-pattern block-Jacobi: the numeric LU (one lane per
+// cell), then the Woodbury factors as for the band (u / v rows, W solved in
+// place by the apply's stream walk, C^{-1} wave per cell).
 hipError_t launch_pattern_setup(const Mesh& g, const PatLU& lu, const double* rec, double* bf,
                                 double* wv, double* wvT, double* cinv, int* status,
                                 hipStream_t s) {
   if (!g.pat || g.rd > RANK_DIAG_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pattern_setup, dim3((unsigned)tiles(g)), dim3(TILE), 0, s, g, lu, rec, bf,
-                     wv, wvT, cinv, status);
+                     status);
+  const int cg = (g.N + WPB - 1) / WPB;
+  hipLaunchKernelGGL(k_band_wv_init, dim3(cg), dim3(64 * WPB), 0, s, g, rec, wv, wvT);
+  const int rd = smw_pairs(g);
+  const long long cs = 2LL * rd * g.mp;
+  launch_pattern_solve<double, false>(g, lu, bf, wv, wv, rd, s, cs, g.mp);
+  if (wvT) launch_pattern_solve<double, true>(g, lu, bf, wvT, wvT, rd, s, cs, g.mp);
+  launch_band_cinv(g, wv, cinv, status, s);
   return hipGetLastError();
-}
-
-template <typename TV, bool TRANS>
-static void launch_pattern_solve(const Mesh& g, const PatLU& lu, const TV* bf, const double* r,
-                                 double* z, int nrhs, hipStream_t s) {
-  const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_pattern_solve<TV, TRANS>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_pattern_solve<TV, TRANS>), dim3((unsigned)tiles(g)), dim3(TILE), lds, s,
-                     g, lu, bf, r, z, nrhs);
 }
 
 template <typename TV, bool TRANS>
