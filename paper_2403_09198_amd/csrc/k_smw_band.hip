@@ -51,77 +51,6 @@ constexpr int TILE = R1S_BAND_TILE;
 __host__ __device__ inline int band_rows(const Mesh& g) { return 2 * g.band + 1 + (g.arrow ? 6 : 0); }
 __host__ __device__ inline long long tiles(const Mesh& g) { return (g.N + TILE - 1) / TILE; }
 
-// Solve A0 x = r (TRANS: A0^T x = r) for one cell.  r(k) gives the right-hand
-// side; x is written to dst[k * DS] (k < m), which also holds the forward
-// sweep's intermediate.  s3i: the 3 x 3 inverse of the Schur complement (row
-// major).  The last `band` values of each sweep stay in registers (a shift
-// register of BAND_MAX slots), so a step never waits on its own stores, and
-// the factor loads of later steps are independent of the recurrence.
-template <bool TRANS, int DS, typename T, typename TA, typename RHS, typename DST>
-__device__ __forceinline__ void band_solve(const T* __restrict__ fb, int L, int band, int arrow,
-                                           const T (&s3i)[9], RHS r, DST* __restrict__ dst) {
-  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)row * L + k) * TILE]; };
-  TA acc[3] = {TA(0), TA(0), TA(0)};
-  TA h[BAND_MAX];
-#pragma unroll
-  for (int j = 0; j < BAND_MAX; ++j) h[j] = TA(0);
-  // forward sweep: L_B y = r (TRANS: U_B^T y = r), coupling sums on the way;
-  // h[j-1] = y_{k-j} (zero before the first level)
-#pragma unroll 2
-  for (int k = 0; k < L; ++k) {
-    TA y = (TA)r(k);
-#pragma unroll
-    for (int j = 1; j <= BAND_MAX; ++j) {
-      if (j > band) break;
-      // lo(j, k) is stored as zero for k < j; up(j, k - j) needs k >= j
-      const TA a = TRANS ? at(band + j, k >= j ? k - j : 0) : at(j - 1, k);
-      y -= a * h[j - 1];
-    }
-    if (TRANS) y *= at(band, k);
-#pragma unroll
-    for (int j = BAND_MAX - 1; j > 0; --j) h[j] = h[j - 1];
-    h[0] = y;
-    dst[k * DS] = (DST)y;
-    if (arrow) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) acc[i] += at(2 * band + (TRANS ? 1 : 4) + i, k) * y;
-    }
-  }
-  // flow unknowns through the Schur complement (TRANS: its transpose)
-  TA yf[3], xf[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) yf[i] = (TA)r(L + i) - acc[i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-    xf[i] = (TA)s3i[TRANS ? i : 3 * i] * yf[0] + (TA)s3i[TRANS ? 3 + i : 3 * i + 1] * yf[1] +
-            (TA)s3i[TRANS ? 6 + i : 3 * i + 2] * yf[2];
-  // backward sweep: U_B x = y - E_c' x_f (TRANS: L_B^T x = y - E_r'^T x_f);
-  // h[j-1] = x_{k+j}
-#pragma unroll
-  for (int j = 0; j < BAND_MAX; ++j) h[j] = TA(0);
-#pragma unroll 2
-  for (int k = L - 1; k >= 0; --k) {
-    TA x = (TA)dst[k * DS];
-    if (arrow) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) x -= at(2 * band + (TRANS ? 4 : 1) + i, k) * xf[i];
-    }
-#pragma unroll
-    for (int j = 1; j <= BAND_MAX; ++j) {
-      if (j > band) break;
-      // up(j, k) is stored as zero for k + j >= L; lo(j, k + j) needs k + j < L
-      const TA a = TRANS ? at(j - 1, k + j < L ? k + j : k) : at(band + j, k);
-      x -= a * h[j - 1];
-    }
-    if (!TRANS) x *= at(band, k);
-#pragma unroll
-    for (int j = BAND_MAX - 1; j > 0; --j) h[j] = h[j - 1];
-    h[0] = x;
-    dst[k * DS] = (DST)x;
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) dst[(L + i) * DS] = (DST)xf[i];
-}
 
 // ---------------------------------------------------------------- setup ----
 // The factorisation, one lane per cell (workgroups of 64 = one tile): the
@@ -399,9 +328,14 @@ __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp
 }
 
 // x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, in place in the cell's
-// vector v[0..m) (v[m] is the dead steps' scratch slot).  The same
-// arithmetic as band_solve, with the factor loads pipelined; BM >= band, and
-// band >= 2 (the tridiagonal band runs wave-per-cell).  Every load address
+// vector v[0..m) (v[m] is the dead steps' scratch slot): the forward sweep
+// (L_B y = r; TRANS: U_B^T y = r) with the coupling sums on the way, the 3 x 3
+// Schur inverse s3i (row major) on the flow unknowns, then the backward sweep
+// (U_B x = y - E_c' x_f; TRANS: L_B^T x = y - E_r'^T x_f).  The last `band`
+// values of each sweep stay in a register shift register, and the factor
+// loads of the next block of levels are issued before the current block is
+// computed; BM >= band, and band >= 2 (the tridiagonal band runs
+// wave-per-cell).  Every load address
 // is valid and computed without conditions on the step: an absent
 // coefficient (j > band, coupling without `arrow`) reads some other factor
 // entry of the cell and is zeroed by a 0/1 weight in the arithmetic, and a
