@@ -42,7 +42,9 @@ namespace r1s {
 #endif
 constexpr int TILE = R1S_BAND_TILE;
 
-// Row offsets of the band factors inside one tile ([rows][L][64]):
+// Row offsets of the band factors inside one tile, stored level-major
+// ([L][rows][64]: the rows one step of a walk reads are adjacent, and the
+// walk streams through the tile's factors in order):
 //   lo(j) rows 0..band-1       l_{k,j} = L_B[k][k-j]      (k >= j)
 //   ui     row band            1 / U_B[k][k]
 //   up(j) rows band+1..2 band  U_B[k][k+j]                 (k + j < L)
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
   const double* rc = rec + (long long)c * g.F * mp;
   const int RB = band_rows(g);
   double* fb = bf + (long long)tile * RB * L * TILE + lane;
-  auto F = [&](int row, int k) -> double& { return fb[((long long)row * L + k) * TILE]; };
+  auto F = [&](int row, int k) -> double& { return fb[((long long)k * RB + row) * TILE]; };
   bool bad = false;
 
   // level band into the factor rows (lower j, diagonal, upper j)
@@ -327,6 +329,31 @@ __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp
   }
 }
 
+// Ring walk: U steps in flight in U register slots.  Step k is computed from
+// slot k % U, and the slot is refilled at once with the loads of step k + U,
+// so that while one step is computed the loads of the next U - 1 are
+// outstanding (the block walk above keeps only U in flight with 2 U slots).
+// Vector loads return in order, so the wait before each step is for its own
+// slot only; U is chosen so that the U - 1 steps outstanding stay within the
+// 63 vector loads a wave can have in flight.  Steps past the end are dead
+// steps, as in the block walk; the last U steps load nothing more.
+template <int U, typename Step, typename LoadF, typename CompF>
+__device__ __forceinline__ void ring_walk(int count, LoadF load, CompF comp) {
+  Step S[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) load(u, S[u]);
+  const int nb = (count + U - 1) / U;
+  for (int b = 0; b < nb - 1; ++b) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      comp(b * U + u, S[u]);
+      load((b + 1) * U + u, S[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) comp((nb - 1) * U + u, S[u]);
+}
+
 // x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, in place in the cell's
 // vector v[0..m) (v[m] is the dead steps' scratch slot): the forward sweep
 // (L_B y = r; TRANS: U_B^T y = r) with the coupling sums on the way, the 3 x 3
@@ -343,8 +370,10 @@ __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp
 template <bool TRANS, int BM, typename T, typename TA>
 __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L, int m, int band,
                                                 int arrow, const T (&s3i)[9], double* v) {
-  constexpr int U = BM <= 2 ? 8 : BM <= 4 ? 4 : 2;
-  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)row * L + k) * TILE]; };
+  // (U - 1) x (loads per step: BM + 1 + 3) <= 63
+  constexpr int U = BM <= 2 ? 10 : BM <= 4 ? 8 : 5;
+  const int RB = 2 * band + 1 + (arrow ? 6 : 0);  // rows per level
+  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)k * RB + row) * TILE]; };
   struct Step {
     TA a[BM];  // band coefficients of the step
     TA d;      // 1 / u_kk where the sweep divides
@@ -360,7 +389,7 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
 #pragma unroll
   for (int j = 0; j < BM; ++j) h[j] = TA(0);
   // forward: L_B y = r (TRANS: U_B^T y = r); h[j-1] = y_{k-j}
-  pipelined_walk<U, Step>(
+  ring_walk<U, Step>(
       L,
       [&](int k, Step& s) {
         const int kk = min(k, L - 1);
@@ -400,7 +429,7 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
   // h[j-1] = x_{k+j}; step t walks k = L - 1 - t
 #pragma unroll
   for (int j = 0; j < BM; ++j) h[j] = TA(0);
-  pipelined_walk<U, Step>(
+  ring_walk<U, Step>(
       L,
       [&](int t, Step& s) {
         const int kk = max(L - 1 - t, 0);
@@ -429,10 +458,69 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
   for (int i = 0; i < 3; ++i) v[L + i] = (double)xf[i];
 }
 
+// The tile's right-hand sides between HBM (row cc of the tile at cc * cs)
+// and LDS (row cc at cc * ls), both ways as one flat range of cells x m
+// elements: element i is row i / m, column i % m, and each lane takes every
+// TILE-th one.  A batch issues all of its loads before any of its writes, so
+// that the loads of a batch are in flight together (a row at a time, each
+// load would wait for the one before).  i / m comes from a float product
+// and one correction each way: i < 2^24, so the product is within one of
+// the quotient.
+constexpr int STAGE_BATCH = 16;
+
+__device__ __forceinline__ void stage_split(int i, int m, float rm, int& q, int& k) {
+  q = (int)((float)i * rm);
+  q -= q * m > i ? 1 : 0;
+  q += (q + 1) * m <= i ? 1 : 0;
+  k = i - q * m;
+}
+
+__device__ __forceinline__ void stage_in(const double* __restrict__ src, long long cs, int cells,
+                                         int m, double* sv, int ls, int lane) {
+  const int tot = cells * m;
+  const float rm = 1.0f / (float)m;
+  for (int b = 0; b < tot; b += STAGE_BATCH * TILE) {
+    double t[STAGE_BATCH];
+    int o[STAGE_BATCH];
+#pragma unroll
+    for (int u = 0; u < STAGE_BATCH; ++u) {
+      const int i = b + u * TILE + lane;
+      int q, k;
+      stage_split(min(i, tot - 1), m, rm, q, k);
+      t[u] = src[(long long)q * cs + k];
+      o[u] = i < tot ? q * ls + k : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_BATCH; ++u)
+      if (o[u] >= 0) sv[o[u]] = t[u];
+  }
+}
+
+__device__ __forceinline__ void stage_out(const double* sv, int ls, int cells, int m,
+                                          double* __restrict__ dst, long long cs, int lane) {
+  const int tot = cells * m;
+  const float rm = 1.0f / (float)m;
+  for (int b = 0; b < tot; b += STAGE_BATCH * TILE) {
+    double t[STAGE_BATCH];
+    long long o[STAGE_BATCH];
+#pragma unroll
+    for (int u = 0; u < STAGE_BATCH; ++u) {
+      const int i = b + u * TILE + lane;
+      int q, k;
+      stage_split(min(i, tot - 1), m, rm, q, k);
+      t[u] = sv[q * ls + k];
+      o[u] = i < tot ? (long long)q * cs + k : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_BATCH; ++u)
+      if (o[u] >= 0) dst[o[u]] = t[u];
+  }
+}
+
 // x0 = A0^{-1} r for every right-hand side, one lane per cell.  The tile's
 // right-hand sides go through LDS ([TILE][(m + 1) | 1]: an odd row stride, so
 // that the lanes' rows fall in different banks, and a scratch slot at m):
-// loaded and stored row by row with the 64 lanes on consecutive elements,
+// staged in and out as one flat range of elements (stage_in, stage_out),
 // while the walk reads and writes its own row in place.  Lanes past the last
 // cell walk whatever their LDS row holds and store nothing.
 template <typename TV, bool TRANS, int BM>
@@ -446,20 +534,20 @@ __global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restric
   const long long c0 = (long long)tile * TILE;
   const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
   const TV* fb = bf + (long long)tile * band_rows(g) * L * TILE + lane;
-  TV s3i[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
   double* mine = sv + lane * ls;
   const int r = blockIdx.y;  // one right-hand side per workgroup
   const double* rr = rin + (long long)r * rs + c0 * cs;
-  for (int cc = 0; cc < cells; ++cc)
-    for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * cs + k];
+  stage_in(rr, cs, cells, m, sv, ls, lane);
   __syncthreads();
+  // loaded after the barrier (which waits for every load before it), in
+  // flight with the walk's first factor loads; first used between the sweeps
+  TV s3i[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
   band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, s3i, mine);
   __syncthreads();
   double* zz = zout + (long long)r * rs + c0 * cs;
-  for (int cc = 0; cc < cells; ++cc)
-    for (int k = lane; k < m; k += TILE) zz[(long long)cc * cs + k] = sv[cc * ls + k];
+  stage_out(sv, ls, cells, m, zz, cs, lane);
 }
 
 template <typename TV, bool TRANS, int BM>
@@ -740,8 +828,7 @@ __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
   double* mine = sv + lane * ls;
   const int r = blockIdx.y;  // one right-hand side per workgroup
   const double* rr = rin + (long long)r * rs + c0 * cs;
-  for (int cc = 0; cc < cells; ++cc)
-    for (int k = lane; k < m; k += TILE) sv[cc * ls + k] = rr[(long long)cc * cs + k];
+  stage_in(rr, cs, cells, m, sv, ls, lane);
   __syncthreads();
   if (TRANS)
     pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_t, lu.nops_t, m, F, mine);
@@ -749,8 +836,7 @@ __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
     pattern_stream<PAT_STREAM_U, true, TV>(lu.ops_n, lu.nops_n, m, F, mine);
   __syncthreads();
   double* zz = zout + (long long)r * rs + c0 * cs;
-  for (int cc = 0; cc < cells; ++cc)
-    for (int k = lane; k < m; k += TILE) zz[(long long)cc * cs + k] = sv[cc * ls + k];
+  stage_out(sv, ls, cells, m, zz, cs, lane);
 }
 
 template <typename TV, bool TRANS>
