@@ -36,15 +36,18 @@
 
 namespace r1s {
 
-// Cells per band-walk workgroup (one wavefront; lanes past TILE idle).
-#ifndef R1S_BAND_TILE
-#define R1S_BAND_TILE 64
-#endif
-constexpr int TILE = R1S_BAND_TILE;
+// Cells per general-pattern workgroup (one wavefront, one lane per cell).
+constexpr int TILE = WAVE;
+// Cells per band workgroup: the walk runs one wavefront per 32 cells, lanes
+// c and c + 32 both on cell c (each loads half of a step's factor values, and
+// one lane swap gives both lanes all of them), so that twice as many
+// wavefronts stream factors as with one lane per cell.  The setup runs one
+// lane per cell.
+constexpr int BT = WAVE / 2;
 
-// Row offsets of the band factors inside one tile, stored level-major
-// ([L][rows][64]: the rows one step of a walk reads are adjacent, and the
-// walk streams through the tile's factors in order):
+// Row offsets of the band factors inside one tile of BT cells, stored
+// level-major ([L][rows][BT]: the rows one step of a walk reads are adjacent,
+// and the walk streams through the tile's factors in order):
 //   lo(j) rows 0..band-1       l_{k,j} = L_B[k][k-j]      (k >= j)
 //   ui     row band            1 / U_B[k][k]
 //   up(j) rows band+1..2 band  U_B[k][k+j]                 (k + j < L)
@@ -52,27 +55,28 @@ constexpr int TILE = R1S_BAND_TILE;
 //   er(i) rows 2 band+4+i      (E_r U_B^{-1})[i][k]        (coupling only)
 __host__ __device__ inline int band_rows(const Mesh& g) { return 2 * g.band + 1 + (g.arrow ? 6 : 0); }
 __host__ __device__ inline long long tiles(const Mesh& g) { return (g.N + TILE - 1) / TILE; }
+__host__ __device__ inline long long band_tiles(const Mesh& g) { return (g.N + BT - 1) / BT; }
 
 
 // ---------------------------------------------------------------- setup ----
-// The factorisation, one lane per cell (workgroups of 64 = one tile): the
-// band factors and the Schur inverse (s3i [tile][9][64]).  The Woodbury
+// The factorisation, one lane per cell (workgroups of BT = one tile): the
+// band factors and the Schur inverse (s3i [tile][9][BT]).  The Woodbury
 // factors follow in the kernels below launch_band_solve: W and V rows for
 // the forward apply (wv [N][2 rd][mp]: W_i = A0^{-1} u_i, then v_i) and,
 // when wvT is given, for the transposed apply (A0^{-T} v_i, then u_i), and
 // C^{-1} ([N][rd^2], row-major per cell).
-__global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __restrict__ rec,
+__global__ __launch_bounds__(BT) void k_band_setup(Mesh g, const double* __restrict__ rec,
                                                      double* __restrict__ bf,
                                                      double* __restrict__ s3i_out, int* status) {
   const int tile = blockIdx.x, lane = threadIdx.x;
-  const int c = tile * TILE + lane;
+  const int c = tile * BT + lane;
   if (c >= g.N) return;  // no cross-lane work in this kernel
   const int L = g.L, m = g.m, band = g.band;
   const long long mp = g.mp;
   const double* rc = rec + (long long)c * g.F * mp;
   const int RB = band_rows(g);
-  double* fb = bf + (long long)tile * RB * L * TILE + lane;
-  auto F = [&](int row, int k) -> double& { return fb[((long long)k * RB + row) * TILE]; };
+  double* fb = bf + (long long)tile * RB * L * BT + lane;
+  auto F = [&](int row, int k) -> double& { return fb[((long long)k * RB + row) * BT]; };
   bool bad = false;
 
   // level band into the factor rows (lower j, diagonal, upper j)
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(TILE) void k_band_setup(Mesh g, const double* __res
   double s3i[9];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) s3i[3 * i + j] = Fi[i][j] / det;
-  for (int t = 0; t < 9; ++t) s3i_out[((long long)tile * 9 + t) * TILE + lane] = s3i[t];
+  for (int t = 0; t < 9; ++t) s3i_out[((long long)tile * 9 + t) * BT + lane] = s3i[t];
   for (int k = 0; k < L; ++k) F(band, k) = 1.0 / F(band, k);
 
   if (bad) atomicMin(status, c);
@@ -335,8 +339,9 @@ __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp
 // outstanding (the block walk above keeps only U in flight with 2 U slots).
 // Vector loads return in order, so the wait before each step is for its own
 // slot only; U is chosen so that the U - 1 steps outstanding stay within the
-// 63 vector loads a wave can have in flight.  Steps past the end are dead
-// steps, as in the block walk; the last U steps load nothing more.
+// 63 vector loads a wave can have in flight.  The last block's slots past
+// `count` were loaded (dead loads, at addresses the load function keeps
+// valid) but are not computed.
 template <int U, typename Step, typename LoadF, typename CompF>
 __device__ __forceinline__ void ring_walk(int count, LoadF load, CompF comp) {
   Step S[U];
@@ -351,39 +356,83 @@ __device__ __forceinline__ void ring_walk(int count, LoadF load, CompF comp) {
     }
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) comp((nb - 1) * U + u, S[u]);
+  for (int u = 0; u < U; ++u)
+    if ((nb - 1) * U + u < count) comp((nb - 1) * U + u, S[u]);
 }
 
 // x0 = A0^{-1} r (TRANS: A0^{-T} r) for one cell, in place in the cell's
-// vector v[0..m) (v[m] is the dead steps' scratch slot): the forward sweep
-// (L_B y = r; TRANS: U_B^T y = r) with the coupling sums on the way, the 3 x 3
-// Schur inverse s3i (row major) on the flow unknowns, then the backward sweep
+// vector v[0..m) (v[m] is a scratch slot): the forward sweep (L_B y = r;
+// TRANS: U_B^T y = r) with the coupling sums on the way, the 3 x 3 Schur
+// inverse s3i (row major) on the flow unknowns, then the backward sweep
 // (U_B x = y - E_c' x_f; TRANS: L_B^T x = y - E_r'^T x_f).  The last `band`
-// values of each sweep stay in a register shift register, and the factor
-// loads of the next block of levels are issued before the current block is
-// computed; BM >= band, and band >= 2 (the tridiagonal band runs
-// wave-per-cell).  Every load address
-// is valid and computed without conditions on the step: an absent
-// coefficient (j > band, coupling without `arrow`) reads some other factor
-// entry of the cell and is zeroed by a 0/1 weight in the arithmetic, and a
-// dead step reads the last level's entries and writes the scratch slot.
+// values of each sweep stay in a register shift register.  Two lanes walk the
+// cell (half = 0 for lane c, 1 for lane c + 32): of each pair of a step's
+// factor values, half 0 loads the first and half 1 the second, and a lane
+// swap at compute time gives both lanes both values, so both compute the
+// same recurrence and half 0 alone writes the result (half 1 writes the
+// scratch slot).  BM >= band, and band >= 2 (the tridiagonal band runs
+// wave-per-cell).  Every load address is valid and computed without
+// conditions on the step: an absent coefficient (j > band, coupling without
+// `arrow`) reads some other factor entry of the cell and is zeroed by a 0/1
+// weight in the arithmetic, and a step past the last level reads the last
+// level's entries.
 template <bool TRANS, int BM, typename T, typename TA>
 __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L, int m, int band,
-                                                int arrow, const T (&s3i)[9], double* v) {
-  // (U - 1) x (loads per step: BM + 1 + 3) <= 63
-  constexpr int U = BM <= 2 ? 10 : BM <= 4 ? 8 : 5;
-  const int RB = 2 * band + 1 + (arrow ? 6 : 0);  // rows per level
-  auto at = [&](int row, int k) -> TA { return (TA)fb[((long long)k * RB + row) * TILE]; };
+                                                int arrow, int half, const T (&s3i)[9],
+                                                double* v) {
+  // values of a step: the BM band coefficients, the 3 coupling entries and,
+  // in the sweep that divides, 1 / u_kk; NP loads of two values each
+  constexpr int NP = (BM + 5) / 2;
+  constexpr int U = NP <= 3 ? 16 : NP <= 4 ? 15 : 10;  // (U - 1) x NP <= 56
+  const int RB = 2 * band + 1 + (arrow ? 6 : 0);        // rows per level
+  auto ld = [&](int row, int k) -> T { return fb[((long long)k * RB + row) * BT]; };
+  // (row, level) of value q of forward step kk / backward step kk
+  auto fwd_at = [&](int q, int kk, int& row, int& lev) {
+    const int j = q + 1, i = q - BM;
+    if (q < BM) {
+      row = TRANS ? (j <= band ? band + j : j - band) : (j <= band ? j - 1 : j - 1 - band);
+      lev = TRANS ? max(kk - j, 0) : kk;
+    } else if (q < BM + 3) {
+      row = arrow ? 2 * band + (TRANS ? 1 : 4) + i : i;
+      lev = kk;
+    } else {  // 1 / u_kk (TRANS), or an unused value
+      row = band;
+      lev = kk;
+    }
+  };
+  auto bwd_at = [&](int q, int kk, int& row, int& lev) {
+    const int j = q + 1, i = q - BM;
+    if (q < BM) {
+      row = TRANS ? (j <= band ? j - 1 : j - 1 - band) : (j <= band ? band + j : j - band);
+      lev = TRANS ? min(kk + j, L - 1) : kk;
+    } else if (q < BM + 3) {
+      row = arrow ? 2 * band + (TRANS ? 4 : 1) + i : i;
+      lev = kk;
+    } else {  // 1 / u_kk (not TRANS), or an unused value
+      row = band;
+      lev = kk;
+    }
+  };
   struct Step {
-    TA a[BM];  // band coefficients of the step
-    TA d;      // 1 / u_kk where the sweep divides
-    TA e[3];   // coupling entries
-    TA v;      // right-hand side (forward) or the forward result (backward)
+    T raw[NP];  // this lane's half of the step's values
+    TA v;       // right-hand side (forward) or the forward result (backward)
+  };
+  // both lanes of the cell get value 2p (loaded by half 0) in val[2p] and
+  // value 2p + 1 (half 1) in val[2p + 1]
+  auto unpack = [&](const Step& s, TA (&val)[2 * NP]) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      TA x = (TA)s.raw[p], y = x;
+      swap32(x, y);
+      val[2 * p] = x;
+      val[2 * p + 1] = y;
+    }
   };
   TA wj[BM];  // 1 for the band's diagonals, 0 past `band`
 #pragma unroll
   for (int j = 0; j < BM; ++j) wj[j] = j < band ? TA(1) : TA(0);
   const TA we = arrow ? TA(1) : TA(0);
+  const int sink = m;  // half 1's writes
   TA h[BM];
   TA acc[3] = {TA(0), TA(0), TA(0)};
 #pragma unroll
@@ -393,30 +442,28 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
       L,
       [&](int k, Step& s) {
         const int kk = min(k, L - 1);
-        s.v = (TA)v[min(k, m)];
+        s.v = (TA)v[kk];
 #pragma unroll
-        for (int j = 1; j <= BM; ++j) {
-          // lo(j) is row j - 1, up(j) row band + j; past `band`, rows j - band
-          // (TRANS) or j - 1 - band, all below 2 band
-          s.a[j - 1] = TRANS ? at(j <= band ? band + j : j - band, max(kk - j, 0))
-                             : at(j <= band ? j - 1 : j - 1 - band, kk);
+        for (int p = 0; p < NP; ++p) {
+          int ra, la, rb, lb;
+          fwd_at(2 * p, kk, ra, la);
+          fwd_at(2 * p + 1, kk, rb, lb);
+          s.raw[p] = ld(half ? rb : ra, half ? lb : la);
         }
-        s.d = TRANS ? at(band, kk) : TA(1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) s.e[i] = at(arrow ? 2 * band + (TRANS ? 1 : 4) + i : i, kk);
       },
       [&](int k, const Step& s) {
+        TA val[2 * NP];
+        unpack(s, val);
         TA y = s.v;
 #pragma unroll
-        for (int j = BM; j >= 1; --j) y -= (s.a[j - 1] * wj[j - 1]) * h[j - 1];
-        if (TRANS) y *= s.d;
+        for (int j = BM; j >= 1; --j) y -= (val[j - 1] * wj[j - 1]) * h[j - 1];
+        if (TRANS) y *= val[BM + 3];
 #pragma unroll
         for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
         h[0] = y;
-        const bool live = k < L;
-        v[live ? k : m] = (double)y;
+        v[half ? sink : k] = (double)y;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) acc[i] += live ? (s.e[i] * we) * y : TA(0);
+        for (int i = 0; i < 3; ++i) acc[i] += (val[BM + i] * we) * y;
       });
   TA yf[3], xf[3];
 #pragma unroll
@@ -435,33 +482,35 @@ __device__ __forceinline__ void band_solve_pipe(const T* __restrict__ fb, int L,
         const int kk = max(L - 1 - t, 0);
         s.v = (TA)v[kk];
 #pragma unroll
-        for (int j = 1; j <= BM; ++j)
-          s.a[j - 1] = TRANS ? at(j <= band ? j - 1 : j - 1 - band, min(kk + j, L - 1))
-                             : at(j <= band ? band + j : j - band, kk);
-        s.d = TRANS ? TA(1) : at(band, kk);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) s.e[i] = at(arrow ? 2 * band + (TRANS ? 4 : 1) + i : i, kk);
+        for (int p = 0; p < NP; ++p) {
+          int ra, la, rb, lb;
+          bwd_at(2 * p, kk, ra, la);
+          bwd_at(2 * p + 1, kk, rb, lb);
+          s.raw[p] = ld(half ? rb : ra, half ? lb : la);
+        }
       },
       [&](int t, const Step& s) {
+        TA val[2 * NP];
+        unpack(s, val);
         TA x = s.v;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) x -= (s.e[i] * we) * xf[i];
+        for (int i = 0; i < 3; ++i) x -= (val[BM + i] * we) * xf[i];
 #pragma unroll
-        for (int j = BM; j >= 1; --j) x -= (s.a[j - 1] * wj[j - 1]) * h[j - 1];
-        if (!TRANS) x *= s.d;
+        for (int j = BM; j >= 1; --j) x -= (val[j - 1] * wj[j - 1]) * h[j - 1];
+        if (!TRANS) x *= val[BM + 3];
 #pragma unroll
         for (int j = BM - 1; j > 0; --j) h[j] = h[j - 1];
         h[0] = x;
-        v[t < L ? L - 1 - t : m] = (double)x;
+        v[half ? sink : L - 1 - t] = (double)x;
       });
 #pragma unroll
-  for (int i = 0; i < 3; ++i) v[L + i] = (double)xf[i];
+  for (int i = 0; i < 3; ++i) v[half ? sink : L + i] = (double)xf[i];
 }
 
 // The tile's right-hand sides between HBM (row cc of the tile at cc * cs)
 // and LDS (row cc at cc * ls), both ways as one flat range of cells x m
-// elements: element i is row i / m, column i % m, and each lane takes every
-// TILE-th one.  A batch issues all of its loads before any of its writes, so
+// elements: element i is row i / m, column i % m, and each of the
+// workgroup's WAVE threads takes every WAVE-th one.  A batch issues all of its loads before any of its writes, so
 // that the loads of a batch are in flight together (a row at a time, each
 // load would wait for the one before).  i / m comes from a float product
 // and one correction each way: i < 2^24, so the product is within one of
@@ -479,12 +528,12 @@ __device__ __forceinline__ void stage_in(const double* __restrict__ src, long lo
                                          int m, double* sv, int ls, int lane) {
   const int tot = cells * m;
   const float rm = 1.0f / (float)m;
-  for (int b = 0; b < tot; b += STAGE_BATCH * TILE) {
+  for (int b = 0; b < tot; b += STAGE_BATCH * WAVE) {
     double t[STAGE_BATCH];
     int o[STAGE_BATCH];
 #pragma unroll
     for (int u = 0; u < STAGE_BATCH; ++u) {
-      const int i = b + u * TILE + lane;
+      const int i = b + u * WAVE + lane;
       int q, k;
       stage_split(min(i, tot - 1), m, rm, q, k);
       t[u] = src[(long long)q * cs + k];
@@ -500,12 +549,12 @@ __device__ __forceinline__ void stage_out(const double* sv, int ls, int cells, i
                                           double* __restrict__ dst, long long cs, int lane) {
   const int tot = cells * m;
   const float rm = 1.0f / (float)m;
-  for (int b = 0; b < tot; b += STAGE_BATCH * TILE) {
+  for (int b = 0; b < tot; b += STAGE_BATCH * WAVE) {
     double t[STAGE_BATCH];
     long long o[STAGE_BATCH];
 #pragma unroll
     for (int u = 0; u < STAGE_BATCH; ++u) {
-      const int i = b + u * TILE + lane;
+      const int i = b + u * WAVE + lane;
       int q, k;
       stage_split(min(i, tot - 1), m, rm, q, k);
       t[u] = sv[q * ls + k];
@@ -517,37 +566,38 @@ __device__ __forceinline__ void stage_out(const double* sv, int ls, int cells, i
   }
 }
 
-// x0 = A0^{-1} r for every right-hand side, one lane per cell.  The tile's
-// right-hand sides go through LDS ([TILE][(m + 1) | 1]: an odd row stride, so
-// that the lanes' rows fall in different banks, and a scratch slot at m):
-// staged in and out as one flat range of elements (stage_in, stage_out),
-// while the walk reads and writes its own row in place.  Lanes past the last
-// cell walk whatever their LDS row holds and store nothing.
+// x0 = A0^{-1} r for every right-hand side, two lanes per cell (BT cells per
+// wavefront).  The tile's right-hand sides go through LDS ([BT][(m + 1) | 1]:
+// an odd row stride, so that the cells' rows fall in different banks, and a
+// scratch slot at m), staged in and out as one flat range of elements
+// (stage_in, stage_out), while the walk reads and writes its cell's row in
+// place.  Lanes past the last cell walk whatever their LDS row holds and
+// store nothing.
 template <typename TV, bool TRANS, int BM>
-__global__ __launch_bounds__(TILE) void k_band_solve(Mesh g, const TV* __restrict__ bf,
+__global__ __launch_bounds__(WAVE) void k_band_solve(Mesh g, const TV* __restrict__ bf,
                                                      const TV* __restrict__ s3i_in,
                                                      const double* rin, double* zout, int nrhs,
                                                      long long cs, long long rs) {
   extern __shared__ double sv[];
-  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int tile = blockIdx.x, lane = threadIdx.x % BT, half = threadIdx.x / BT;
   const int L = g.L, m = g.m, ls = (m + 1) | 1;
-  const long long c0 = (long long)tile * TILE;
-  const int cells = (int)(g.N - c0 < TILE ? g.N - c0 : TILE);
-  const TV* fb = bf + (long long)tile * band_rows(g) * L * TILE + lane;
+  const long long c0 = (long long)tile * BT;
+  const int cells = (int)(g.N - c0 < BT ? g.N - c0 : BT);
+  const TV* fb = bf + (long long)tile * band_rows(g) * L * BT + lane;
   double* mine = sv + lane * ls;
   const int r = blockIdx.y;  // one right-hand side per workgroup
   const double* rr = rin + (long long)r * rs + c0 * cs;
-  stage_in(rr, cs, cells, m, sv, ls, lane);
+  stage_in(rr, cs, cells, m, sv, ls, threadIdx.x);
   __syncthreads();
   // loaded after the barrier (which waits for every load before it), in
   // flight with the walk's first factor loads; first used between the sweeps
   TV s3i[9];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * TILE + lane];
-  band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, s3i, mine);
+  for (int t = 0; t < 9; ++t) s3i[t] = s3i_in[((long long)tile * 9 + t) * BT + lane];
+  band_solve_pipe<TRANS, BM, TV, TV>(fb, L, m, g.band, g.arrow, half, s3i, mine);
   __syncthreads();
   double* zz = zout + (long long)r * rs + c0 * cs;
-  stage_out(sv, ls, cells, m, zz, cs, lane);
+  stage_out(sv, ls, cells, m, zz, cs, threadIdx.x);
 }
 
 template <typename TV, bool TRANS, int BM>
@@ -556,12 +606,12 @@ static void launch_band_solve(const Mesh& g, const TV* bf, const TV* s3i, const 
                               long long rs = -1) {
   if (cs < 0) cs = g.m;  // the [nrhs][N][m] vector layout by default
   if (rs < 0) rs = g.n;
-  const size_t lds = (size_t)TILE * ((g.m + 1) | 1) * sizeof(double);
-  if (lds > 65536)  // up to the 160 KiB of a CU for m > 127
+  const size_t lds = (size_t)BT * ((g.m + 1) | 1) * sizeof(double);
+  if (lds > 65536)  // up to the 160 KiB of a CU
     (void)hipFuncSetAttribute((const void*)k_band_solve<TV, TRANS, BM>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_band_solve<TV, TRANS, BM>), dim3((unsigned)tiles(g), nrhs), dim3(TILE), lds,
-                     s, g, bf, s3i, r, z, nrhs, cs, rs);
+  hipLaunchKernelGGL((k_band_solve<TV, TRANS, BM>), dim3((unsigned)band_tiles(g), nrhs),
+                     dim3(WAVE), lds, s, g, bf, s3i, r, z, nrhs, cs, rs);
 }
 
 static void launch_band_cinv(const Mesh& g, const double* wv, double* cinv, int* status,
@@ -583,7 +633,7 @@ static void launch_band_cinv(const Mesh& g, const double* wv, double* cinv, int*
 hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, double* s3i,
                              double* wv, double* wvT, double* cinv, int* status, hipStream_t s) {
   if (g.rd > RANK_DIAG_MAX || g.band > BAND_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_band_setup, dim3((unsigned)tiles(g)), dim3(TILE), 0, s, g, rec, bf, s3i,
+  hipLaunchKernelGGL(k_band_setup, dim3((unsigned)band_tiles(g)), dim3(BT), 0, s, g, rec, bf, s3i,
                      status);
   const int cg = (g.N + WPB - 1) / WPB;
   hipLaunchKernelGGL(k_band_wv_init, dim3(cg), dim3(64 * WPB), 0, s, g, rec, wv, wvT);
@@ -909,9 +959,9 @@ void pattern_prec_counts(const Mesh& g, int nnzF, long long* bf, long long* wv, 
 // Schur inverses tile-interleaved, W / V rows and C^{-1} per cell.
 void band_prec_counts(const Mesh& g, long long* bf, long long* s3i, long long* wv,
                       long long* cinv) {
-  const long long T = tiles(g);
-  *bf = T * band_rows(g) * g.L * TILE;
-  *s3i = T * 9 * TILE;
+  const long long T = band_tiles(g);
+  *bf = T * band_rows(g) * g.L * BT;
+  *s3i = T * 9 * BT;
   *wv = (long long)g.N * 2 * smw_pairs(g) * g.mp;
   *cinv = (long long)g.N * smw_pairs(g) * smw_pairs(g);
 }
