@@ -600,7 +600,7 @@ struct r1s_prec_s {
   double *facF, *facT, *invC;
   float *facF32, *facT32, *invC32;
   int* status;
-  // SMW, level band wider than tridiagonal (one lane per cell, tile-interleaved):
+  // SMW, level band wider than tridiagonal (tile-interleaved, 32 cells per tile):
   // band / coupling factors, Schur inverse, W and V rows per direction, C^{-1}
   double *bf, *s3i, *wv, *wvT, *cinv;
   float *bf32, *s3i32, *wv32, *wvT32, *cinv32;

@@ -13,15 +13,15 @@
 // The Woodbury correction with the diagonal block's pairs (section 6, eq.
 // SMW, sign corrected) is then the same as for the tridiagonal pattern.
 //
-// A band solve is a serial recurrence of order `band`, so here one lane owns
-// one cell and walks its levels (64 cells per wavefront) instead of one wave
-// per cell with lane-parallel scans: the scan of an order-h recurrence costs
-// O(h^3 log 64) per lane, the serial walk O(h) per level.  The band factors
-// are stored tile-interleaved, [tile of 64 cells][row][k][lane], so the 64
-// lanes of a wave read one factor entry of 64 consecutive cells as one
-// contiguous 512-byte run, and the walk loads the factors of the next block
-// of levels while it computes the current one (the recurrence itself only
-// touches registers).  The Woodbury correction has no recurrence: a second
+// A band solve is a serial recurrence of order `band`, so here a pair of
+// lanes owns one cell and walks its levels (32 cells per wavefront) instead
+// of one wave per cell with lane-parallel scans: the scan of an order-h
+// recurrence costs O(h^3 log 64) per lane, the serial walk O(h) per level.
+// The band factors are stored tile-interleaved and level-major, [tile of 32
+// cells][k][row][lane], so each half of a wave reads one factor entry of 32
+// consecutive cells as one contiguous 256-byte run, and the walk keeps the
+// factor loads of the next levels in flight while it computes the current
+// one (the recurrence itself only touches registers).  The Woodbury correction has no recurrence: a second
 // kernel does it with one wavefront per cell on per-cell rows ([N][2 rd][mp]
 // for W, V and [N][rd][rd] for C^{-1}), like the tridiagonal path.  With the
 // atom density coupled to every molecule level (arrow = 2) the atom's column

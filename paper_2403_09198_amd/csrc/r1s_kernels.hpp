@@ -90,7 +90,7 @@ hipError_t launch_matvec_prec(const Mesh& g, const void* rec, const void* fac, c
                               bool f32, const double* x, double* y, double* z, hipStream_t s);
 
 // SMW block-Jacobi for the wide diagonal-block pattern (band > 1 or level/flow
-// coupling): tile-interleaved factors, one lane per cell.  wvT may be null.
+// coupling): tile-interleaved factors, 32 cells per tile.  wvT may be null.
 void band_prec_counts(const Mesh& g, long long* bf, long long* s3i, long long* wv,
                       long long* cinv);
 hipError_t launch_band_setup(const Mesh& g, const double* rec, double* bf, double* s3i,
