@@ -339,20 +339,26 @@ __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp
 // outstanding (the block walk above keeps only U in flight with 2 U slots).
 // Vector loads return in order, so the wait before each step is for its own
 // slot only; U is chosen so that the U - 1 steps outstanding stay within the
-// 63 vector loads a wave can have in flight.  The last block's slots past
-// `count` were loaded (dead loads, at addresses the load function keeps
-// valid) but are not computed.
+// 63 vector loads a wave can have in flight.  Steps past `count` are neither
+// loaded nor computed (the last refill and the last block test the step).
 template <int U, typename Step, typename LoadF, typename CompF>
 __device__ __forceinline__ void ring_walk(int count, LoadF load, CompF comp) {
   Step S[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) load(u, S[u]);
   const int nb = (count + U - 1) / U;
-  for (int b = 0; b < nb - 1; ++b) {
+  for (int b = 0; b < nb - 2; ++b) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       comp(b * U + u, S[u]);
       load((b + 1) * U + u, S[u]);
+    }
+  }
+  if (nb >= 2) {  // the last refill loads only the steps that exist
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      comp((nb - 2) * U + u, S[u]);
+      if ((nb - 1) * U + u < count) load((nb - 1) * U + u, S[u]);
     }
   }
 #pragma unroll
