@@ -306,19 +306,17 @@ __global__ __launch_bounds__(64 * WPB) void k_band_cinv(Mesh g, const double* __
 }
 
 // ---------------------------------------------------------------- apply ----
-// Software-pipelined walk: the loads of block b + 1 (U steps) are issued
-// before block b is computed, and the walk runs whole pairs of blocks, so
-// nothing in the loop is conditional: steps past the end are dead steps
-// that the load and compute functions turn into no-ops (zero coefficients,
-// a scratch slot for their result).  With no load or store under a branch,
-// the compiler waits for exactly the loads of the block being computed.
+// Software-pipelined walk: the loads of block b + 1 (U steps, one call of
+// load(b + 1, steps)) are issued before block b is computed, and the walk
+// runs whole pairs of blocks, so nothing in the loop is conditional: steps
+// past the end are dead steps that the load and compute functions turn into
+// no-ops (zero coefficients, a scratch slot for their result).  With no load
+// or store under a branch, the compiler waits for exactly the loads of the
+// block being computed.
 template <int U, typename Step, typename LoadF, typename CompF>
 __device__ __forceinline__ void pipelined_walk(int count, LoadF load, CompF comp) {
   Step A[U], B[U];
-  auto ld = [&](int b, Step(&S)[U]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) load(b * U + u, S[u]);
-  };
+  auto ld = [&](int b, Step(&S)[U]) { load(b, S); };
   auto cp = [&](int b, Step(&S)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) comp(b * U + u, S[u]);
@@ -802,13 +800,26 @@ __device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int 
     int pos, code;
   };
   TA acc = TA(0);
+  // a block's (pos, code) pairs are read as one contiguous run before any of
+  // its factor loads, so that one wait covers the block's scalar loads.  The
+  // tables are padded to 256-byte pieces (32 operations), so a block of U <=
+  // 32 operations that starts before the end lies inside its piece; blocks
+  // past the end reread the last one, and operations past the end are dead.
+  static_assert(32 % U == 0, "a block lies inside one 32-operation piece");
+  const int last = ((nops - 1) / U) * U;
   pipelined_walk<U, Op>(
       nops,
-      [&](int e, Op& o) {
-        const int ee = e < nops ? e : nops - 1;
-        o.pos = ops[2 * ee];
-        o.code = e < nops ? ops[2 * ee + 1] : -1;
-        o.f = (TA)F[(long long)(o.pos >= 0 ? o.pos : 0) * TILE];
+      [&](int b, Op(&S)[U]) {
+        const int2* blk = reinterpret_cast<const int2*>(ops) + min(b * U, last);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int2 pc = blk[u];
+          S[u].pos = pc.x;
+          S[u].code = b * U + u < nops ? pc.y : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          S[u].f = (TA)F[(long long)(S[u].pos >= 0 ? S[u].pos : 0) * TILE];
       },
       [&](int, const Op& o) {
         const int kind = o.code >> 16, idx = o.code & 0xffff;
@@ -868,7 +879,9 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
 // x0 = A0^{-1} r for every right-hand side, one lane per cell, the tile's
 // right-hand sides staged through LDS as in k_band_solve.
 #ifndef PAT_STREAM_U
-#define PAT_STREAM_U 16  // operations per prefetch block
+// operations per prefetch block (16 ran slower: the two blocks' positions and
+// codes no longer fit in scalar registers)
+#define PAT_STREAM_U 8
 #endif
 template <typename TV, bool TRANS>
 __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
