@@ -797,7 +797,7 @@ __device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int 
                                                const T* __restrict__ F, double* v) {
   struct Op {
     TA f;
-    int pos, code;
+    int code;  // kind << 16 | index, bit 20 set where the END scales by f
   };
   TA acc = TA(0);
   // a block's (pos, code) pairs are read as one contiguous run before any of
@@ -811,24 +811,25 @@ __device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int 
       nops,
       [&](int b, Op(&S)[U]) {
         const int2* blk = reinterpret_cast<const int2*>(ops) + min(b * U, last);
+        int pos[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int2 pc = blk[u];
-          S[u].pos = pc.x;
-          S[u].code = b * U + u < nops ? pc.y : -1;
+          pos[u] = pc.x;
+          S[u].code = b * U + u < nops ? pc.y | (pc.x >= 0 ? 1 << 20 : 0) : -1;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          S[u].f = (TA)F[(long long)(S[u].pos >= 0 ? S[u].pos : 0) * TILE];
+        for (int u = 0; u < U; ++u) S[u].f = (TA)F[(long long)(pos[u] >= 0 ? pos[u] : 0) * TILE];
       },
       [&](int, const Op& o) {
-        const int kind = o.code >> 16, idx = o.code & 0xffff;
+        const int kind = (o.code >> 16) & 15, idx = o.code & 0xffff;
+        const bool scale = (o.code >> 20) & 1;
         if constexpr (SINK) {
           const bool upd = kind == PAT_OP_UPD, start = kind == PAT_OP_START;
           const bool end = kind == PAT_OP_END;
           const TA val = (TA)v[upd || start ? idx : m];
           acc = start ? val : acc - (upd ? o.f : TA(0)) * val;
-          v[end ? idx : m] = (double)(o.pos >= 0 ? acc * o.f : acc);
+          v[end ? idx : m] = (double)(scale ? acc * o.f : acc);
         } else {
           if (o.code < 0) return;
           if (kind == PAT_OP_UPD)
@@ -836,7 +837,7 @@ __device__ __forceinline__ void pattern_stream(const int* __restrict__ ops, int 
           else if (kind == PAT_OP_START)
             acc = (TA)v[idx];
           else
-            v[idx] = (double)(o.pos >= 0 ? acc * o.f : acc);
+            v[idx] = (double)(scale ? acc * o.f : acc);
         }
       });
 }
@@ -879,9 +880,9 @@ __global__ __launch_bounds__(TILE) void k_pattern_setup(Mesh g, PatLU lu,
 // x0 = A0^{-1} r for every right-hand side, one lane per cell, the tile's
 // right-hand sides staged through LDS as in k_band_solve.
 #ifndef PAT_STREAM_U
-// operations per prefetch block (16 ran slower: the two blocks' positions and
-// codes no longer fit in scalar registers)
-#define PAT_STREAM_U 8
+// operations per prefetch block (the two blocks' codes fit in scalar
+// registers: 94 SGPRs, no spills)
+#define PAT_STREAM_U 16
 #endif
 template <typename TV, bool TRANS>
 __global__ __launch_bounds__(TILE) void k_pattern_solve(Mesh g, PatLU lu,
